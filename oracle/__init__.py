@@ -1,0 +1,188 @@
+"""ctypes wrapper of the CPU oracle (``oracle/oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by the
+CPU-baseline leg of the benchmark, never by the product package.  It shares no
+code with the HIP implementation.
+"""
+import ctypes as C
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+ST_NAMES = ("a_elig", "t_elig", "in_rc", "excluded", "accepted", "proposals", "bonds",
+            "adj_overflow", "near_rc", "fp64_disagree")
+ST_COUNT = len(ST_NAMES)
+
+OK, EINVAL, ERULE_AMBIGUOUS, ECAP, ENOMEM = 0, -1, -2, -3, -4
+
+
+def _p(a, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+def load(path=None):
+    """Load (building if needed) the oracle library; ``path`` selects a variant."""
+    global _lib
+    if path is not None:
+        return _declare(C.CDLL(path))
+    if _lib is None:
+        _lib = _declare(C.CDLL(_build.ensure_built()))
+    return _lib
+
+
+def _declare(lib):
+    i32, i64, u32, u64, f32, f64 = C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_float, C.c_double
+    P = C.POINTER
+    lib.or_philox_bulk.argtypes = [i64, P(u32), P(u64), P(u32)]
+    lib.or_philox_bulk.restype = None
+    lib.or_threshold.argtypes = [f64]
+    lib.or_threshold.restype = u64
+    rule = [i32, i32, i32, i32, i32, i32, i32, i32, f32, f64, i32]
+    lib.or_react_step.argtypes = [i32, f32, P(f32), P(f32), P(f32), P(i32), P(i32), P(i32), i32,
+                                  *rule, u64, u32, P(i32), i64, P(i64), P(i64)]
+    lib.or_react_step.restype = C.c_int
+    lib.or_run.argtypes = [i32, f32, P(f32), P(f32), P(f32), P(i32), P(i32), P(i32), i32,
+                           *rule, u64, u32, u32, f64, P(i32), i64, P(i64), P(i64)]
+    lib.or_run.restype = C.c_int
+    lib.or_near_cutoff.argtypes = [i32, f32, P(f32), P(f32), P(f32), P(i32), P(i32),
+                                   i32, i32, i32, i32, i32, i32, f32, f64, P(i64), P(i64)]
+    lib.or_near_cutoff.restype = C.c_int
+    lib.or_ih12_offsets.argtypes = [u32, u32, u32, u64, P(i32)]
+    lib.or_ih12_offsets.restype = None
+    lib.or_jitter.argtypes = [i32, f32, P(f32), P(f32), P(f32), u64, u32, f64]
+    lib.or_jitter.restype = None
+    lib.or_num_threads.argtypes = []
+    lib.or_num_threads.restype = C.c_int
+    return lib
+
+
+class Rule:
+    """Reaction rule T^t + A^a -> T^(t+dT)-A^(a+dA) (Sec. II, Eq. (2))."""
+
+    def __init__(self, type_a, a_min, a_max, d_a, type_t, t_min, t_max, d_t, rc, p,
+                 exclude_bonded=1):
+        self.type_a, self.a_min, self.a_max, self.d_a = type_a, a_min, a_max, d_a
+        self.type_t, self.t_min, self.t_max, self.d_t = type_t, t_min, t_max, d_t
+        self.rc, self.p, self.exclude_bonded = float(rc), float(p), int(exclude_bonded)
+
+    def args(self):
+        return (self.type_a, self.a_min, self.a_max, self.d_a, self.type_t, self.t_min,
+                self.t_max, self.d_t, C.c_float(self.rc), self.p, self.exclude_bonded)
+
+    def replace(self, **kw):
+        d = dict(self.__dict__)
+        d.update(kw)
+        return Rule(**d)
+
+
+def philox(ctr, key, lib=None):
+    """Philox4x32-10 of counters ``ctr`` (n x 4 uint32) under keys ``key`` (n uint64)."""
+    lib = lib or load()
+    ctr = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    key = np.ascontiguousarray(np.broadcast_to(np.asarray(key, dtype=np.uint64), (ctr.shape[0],)))
+    out = np.empty_like(ctr)
+    lib.or_philox_bulk(ctr.shape[0], _p(ctr, C.c_uint32), _p(key, C.c_uint64), _p(out, C.c_uint32))
+    return out
+
+
+def threshold(p, lib=None):
+    return int((lib or load()).or_threshold(float(p)))
+
+
+class System:
+    """Host-side particle system: SoA arrays, mutated in place by the oracle."""
+
+    def __init__(self, L, x, y, z, type_, state, adj):
+        self.L = float(np.float32(L))
+        self.x = np.ascontiguousarray(x, dtype=np.float32).copy()
+        self.y = np.ascontiguousarray(y, dtype=np.float32).copy()
+        self.z = np.ascontiguousarray(z, dtype=np.float32).copy()
+        self.type = np.ascontiguousarray(type_, dtype=np.int32).copy()
+        self.state = np.ascontiguousarray(state, dtype=np.int32).copy()
+        self.adj = np.ascontiguousarray(adj, dtype=np.int32).copy()
+        assert self.adj.ndim == 2 and self.adj.shape[0] == self.x.shape[0]
+
+    @property
+    def n(self):
+        return self.x.shape[0]
+
+    @property
+    def B(self):
+        return self.adj.shape[1]
+
+    def copy(self):
+        return System(self.L, self.x, self.y, self.z, self.type, self.state, self.adj)
+
+
+def react_step(sysm, rule, seed, step, lib=None):
+    """One reaction step in place.  Returns (code, bonds[n_b, 2], stats dict)."""
+    lib = lib or load()
+    n = sysm.n
+    cap = n // 2 + 1
+    bonds = np.empty((cap, 2), dtype=np.int32)
+    nb = C.c_int64(0)
+    st = np.zeros(ST_COUNT, dtype=np.int64)
+    code = lib.or_react_step(n, C.c_float(sysm.L), _p(sysm.x, C.c_float), _p(sysm.y, C.c_float),
+                             _p(sysm.z, C.c_float), _p(sysm.type, C.c_int32),
+                             _p(sysm.state, C.c_int32), _p(sysm.adj, C.c_int32), sysm.B,
+                             *rule.args(), C.c_uint64(seed), C.c_uint32(step), _p(bonds, C.c_int32),
+                             cap, C.byref(nb), _p(st, C.c_int64))
+    return code, bonds[: nb.value].copy(), dict(zip(ST_NAMES, st.tolist()))
+
+
+def run(sysm, rule, seed, first_step, n_steps, sigma, log_cap=None, lib=None):
+    """Steps first_step.. in place; each jitters (sigma > 0) then reacts.
+
+    Returns (code, log[n, 3] of (step, id_A, id_T), stats[n_steps, ST_COUNT])."""
+    lib = lib or load()
+    n = sysm.n
+    if log_cap is None:
+        log_cap = max(16, n * 4)
+    log = np.empty((log_cap, 3), dtype=np.int32)
+    nl = C.c_int64(0)
+    st = np.zeros((max(n_steps, 1), ST_COUNT), dtype=np.int64)
+    code = lib.or_run(n, C.c_float(sysm.L), _p(sysm.x, C.c_float), _p(sysm.y, C.c_float),
+                      _p(sysm.z, C.c_float), _p(sysm.type, C.c_int32), _p(sysm.state, C.c_int32),
+                      _p(sysm.adj, C.c_int32), sysm.B, *rule.args(), C.c_uint64(seed),
+                      C.c_uint32(first_step), C.c_uint32(n_steps), float(sigma),
+                      _p(log, C.c_int32), log_cap, C.byref(nl), _p(st, C.c_int64))
+    return code, log[: min(nl.value, log_cap)].copy(), st[:n_steps]
+
+
+def jitter(sysm, seed, step, sigma, lib=None):
+    lib = lib or load()
+    lib.or_jitter(sysm.n, C.c_float(sysm.L), _p(sysm.x, C.c_float), _p(sysm.y, C.c_float),
+                  _p(sysm.z, C.c_float), C.c_uint64(seed), C.c_uint32(step), float(sigma))
+
+
+def ih12_offsets(step, ids, tag, seed, lib=None):
+    """Integer Irwin-Hall offsets S (n x 3) of the jitter for particle ``ids``."""
+    lib = lib or load()
+    out = np.empty((len(ids), 3), dtype=np.int32)
+    buf = (C.c_int32 * 3)()
+    for k, i in enumerate(ids):
+        lib.or_ih12_offsets(C.c_uint32(step), C.c_uint32(int(i)), C.c_uint32(tag), C.c_uint64(seed), buf)
+        out[k] = list(buf)
+    return out
+
+
+def near_cutoff(sysm, rule, tol=1e-6, lib=None):
+    """(count of eligible pairs with |r64 - rc| < tol, count of FP32/FP64 disagreements)."""
+    lib = lib or load()
+    near, dis = C.c_int64(0), C.c_int64(0)
+    lib.or_near_cutoff(sysm.n, C.c_float(sysm.L), _p(sysm.x, C.c_float), _p(sysm.y, C.c_float),
+                       _p(sysm.z, C.c_float), _p(sysm.type, C.c_int32), _p(sysm.state, C.c_int32),
+                       rule.type_a, rule.a_min, rule.a_max, rule.type_t, rule.t_min, rule.t_max,
+                       C.c_float(rule.rc), float(tol), C.byref(near), C.byref(dis))
+    return near.value, dis.value
+
+
+def num_threads(lib=None):
+    return int((lib or load()).or_num_threads())
+
+
+__all__ = ["Rule", "System", "react_step", "run", "jitter", "philox", "threshold", "near_cutoff",
+           "ih12_offsets", "ST_NAMES", "load", "num_threads"]

@@ -1,0 +1,446 @@
+/*
+ * oracle.c -- plain, slow CPU reference of the polymerization reaction step of
+ * de Buyl & Nies, "A parallel algorithm for step- and chain-growth
+ * polymerization in Molecular Dynamics" (arXiv:1409.7498).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library may include, link
+ * or call this file; only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark use it.  It shares no code, header, table or constant
+ * generator with the HIP implementation: both are written independently from
+ * the paper and from the arithmetic contract stated in the design notes.
+ *
+ * What it computes, in the paper's order (Sec. III, Table I, steps 1-9):
+ *   1. candidates: every (A, T) pair whose type and state match the rule and
+ *      whose distance is below the reaction cutoff (Sec. II, Eq. (2) and the
+ *      text after it), found by brute force over all pairs -- no cell list;
+ *   2. acceptance of each candidate with probability p = k*dt*Theta
+ *      (Sec. II, Eqs. (3)-(4): u < k dt Theta, u uniform in [0,1));
+ *   3-5. for each active particle A, one accepted target T chosen at random;
+ *   6-7. for each target T, one of the A's that chose it, chosen at random;
+ *   9. bond creation and state update of both partners (Eq. (2): t -> t+dt,
+ *      a -> a+da), simultaneously after all selections.
+ * The communication steps (4, 6, 8) have no counterpart in a shared-memory run.
+ *
+ * Randomness.  The paper only asks for uniform u and "random" selection.  To
+ * make one outcome the correct one, each (step, id_A, id_T) pair draws one
+ * Philox4x32-10 block (Salmon, Moraes, Dror, Shaw, SC'11, "Parallel random
+ * numbers: as easy as 1, 2, 3"); word 0 decides acceptance, word 1 ranks the
+ * A-side choice, word 2 ranks the T-side choice.  The minimum of i.i.d.
+ * uniform keys is a uniform choice, ties (impossible within one A or one T,
+ * since the low 32 bits carry the partner id) go to the lower id.
+ *
+ * Floating point: positions are FP32; the squared minimum-image distance is
+ * evaluated as ((dx*dx + dy*dy) + dz*dz) with every operation rounded to
+ * FP32 and no fused multiply-add (this file must be built with
+ * -ffp-contract=off and without -ffast-math).  The pair is in range iff
+ * r2 < rc2 with rc2 = fl32(rc*rc) (strict).
+ *
+ * Parity pins of each function are listed in the tests; functions with no
+ * pin say so here.  All functions are pinned (see tests/test_oracle_*.py).
+ */
+#include <math.h>
+#include <stdint.h>
+/* OR_MUTANT (default 0) plants one known mistake per value; only the mutation
+ * tests build such variants, to show that the pins catch each mistake. */
+#ifndef OR_MUTANT
+#define OR_MUTANT 0
+#endif
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* error codes, same numeric meaning as the library's */
+#define OR_OK 0
+#define OR_EINVAL (-1)
+#define OR_ERULE_AMBIGUOUS (-2)
+#define OR_ECAP (-3)
+#define OR_ENOMEM (-4)
+
+/* ----------------------------------------------------------------------- */
+/* Philox4x32-10 (Salmon et al. 2011): 10 rounds of the Philox S-P network  */
+/* on a 128-bit counter with a 64-bit key; between rounds the key is       */
+/* bumped by the Weyl constants (golden ratio, sqrt(3)-1).                 */
+/* ----------------------------------------------------------------------- */
+#define PHILOX_M0 0xD2511F53u
+#define PHILOX_M1 0xCD9E8D57u
+#define PHILOX_W0 0x9E3779B9u
+#define PHILOX_W1 0xBB67AE85u
+
+void or_philox4x32_10(const uint32_t ctr[4], uint64_t key, uint32_t out[4]) {
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += PHILOX_W0;
+      k1 += PHILOX_W1;
+    }
+    uint64_t prod0 = (uint64_t)PHILOX_M0 * (uint64_t)c0;
+    uint64_t prod1 = (uint64_t)PHILOX_M1 * (uint64_t)c2;
+    uint32_t n0 = (uint32_t)(prod1 >> 32) ^ c1 ^ k0;
+    uint32_t n1 = (uint32_t)prod1;
+    uint32_t n2 = (uint32_t)(prod0 >> 32) ^ c3 ^ k1;
+    uint32_t n3 = (uint32_t)prod0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* bulk form for the tests: n counters (4 words each) -> n outputs */
+void or_philox_bulk(int64_t n, const uint32_t* ctr, const uint64_t* key, uint32_t* out) {
+  for (int64_t i = 0; i < n; ++i) or_philox4x32_10(ctr + 4 * i, key[i], out + 4 * i);
+}
+
+/* ----------------------------------------------------------------------- */
+/* Rule and helpers                                                          */
+/* ----------------------------------------------------------------------- */
+typedef struct {
+  int32_t type_a, a_min, a_max, d_a;  /* active role A: type, state window, delta */
+  int32_t type_t, t_min, t_max, d_t;  /* target role T */
+  float rc;                           /* reaction cutoff */
+  double p;                           /* acceptance probability k*dt*Theta */
+  int32_t exclude_bonded;             /* 1: already bonded pairs are not candidates */
+} or_rule;
+
+static int is_active(const or_rule* r, int32_t type, int32_t state) {
+  return type == r->type_a && state >= r->a_min && state <= r->a_max;
+}
+static int is_target(const or_rule* r, int32_t type, int32_t state) {
+  return type == r->type_t && state >= r->t_min && state <= r->t_max;
+}
+
+/* acceptance threshold: w0 < ceil(p * 2^32)  <=>  w0 * 2^-32 < p */
+uint64_t or_threshold(double p) {
+  double t = ceil(p * 4294967296.0);
+  if (t < 0.0) t = 0.0;
+  if (t > 4294967296.0) t = 4294967296.0;
+  return (uint64_t)t;
+}
+
+/* minimum-image component: one conditional wrap, as fixed by the contract */
+static float min_image(float d, float L, float halfL) {
+#if OR_MUTANT == 2 /* mutant: no periodic wrap */
+  return d;
+#endif
+  if (d > halfL) d = d - L;
+  else if (d < -halfL) d = d + L;
+  return d;
+}
+
+/* squared distance of T=j relative to A=i, every op rounded to FP32 */
+static float dist2(const float* x, const float* y, const float* z, int64_t i, int64_t j,
+                   float L, float halfL) {
+  float dx = min_image(x[j] - x[i], L, halfL);
+  float dy = min_image(y[j] - y[i], L, halfL);
+  float dz = min_image(z[j] - z[i], L, halfL);
+  float sx = dx * dx;
+  float sy = dy * dy;
+  float sz = dz * dz;
+  float sxy = sx + sy;
+#if OR_MUTANT == 1 /* mutant: dropped z term */
+  return sxy + 0.0f * sz;
+#endif
+  return sxy + sz;
+}
+
+static int bonded(const int32_t* adj, int32_t B, int64_t i, int64_t j) {
+  for (int32_t k = 0; k < B; ++k)
+    if (adj[i * B + k] == (int32_t)j) return 1;
+  return 0;
+}
+
+static int validate(int32_t n, float L, const float* x, const float* y, const float* z,
+                    int32_t B, const or_rule* r) {
+  if (n < 0 || B < 1) return OR_EINVAL;
+  if (!(r->rc > 0.0f) || !(L > 2.0f * r->rc) || !isfinite(L)) return OR_EINVAL;
+  if (!(r->p >= 0.0 && r->p <= 1.0)) return OR_EINVAL;
+  if (r->type_a == r->type_t && r->a_min <= r->t_max && r->t_min <= r->a_max)
+    return OR_ERULE_AMBIGUOUS;
+  for (int64_t i = 0; i < n; ++i) {
+    if (!(x[i] >= 0.0f && x[i] < L) || !(y[i] >= 0.0f && y[i] < L) ||
+        !(z[i] >= 0.0f && z[i] < L))
+      return OR_EINVAL;
+  }
+  return OR_OK;
+}
+
+/* stats layout (int64 x 10) */
+enum {
+  ST_A_ELIG = 0, ST_T_ELIG, ST_IN_RC, ST_EXCLUDED, ST_ACCEPTED,
+  ST_PROPOSALS, ST_BONDS, ST_ADJ_OVERFLOW, ST_NEAR_RC, ST_FP64_DISAGREE, ST_COUNT
+};
+
+/* ----------------------------------------------------------------------- */
+/* One reaction step (Table I, steps 1-9).                                   */
+/* bonds: 2*cap int32 (id_A, id_T), written in increasing id_A order.        */
+/* ----------------------------------------------------------------------- */
+int or_react_step(int32_t n, float L, const float* x, const float* y, const float* z,
+                  const int32_t* type, int32_t* state, int32_t* adj, int32_t B,
+                  int32_t type_a, int32_t a_min, int32_t a_max, int32_t d_a,
+                  int32_t type_t, int32_t t_min, int32_t t_max, int32_t d_t,
+                  float rc, double p, int32_t exclude_bonded,
+                  uint64_t seed, uint32_t step,
+                  int32_t* bonds, int64_t cap, int64_t* n_bonds, int64_t* stats) {
+  or_rule R = {type_a, a_min, a_max, d_a, type_t, t_min, t_max, d_t, rc, p, exclude_bonded};
+  int err = validate(n, L, x, y, z, B, &R);
+  if (err) return err;
+  if (cap < (int64_t)n / 2) return OR_ECAP;
+
+  const float halfL = 0.5f * L;
+  const float rc2 = rc * rc;
+#if OR_MUTANT == 7 /* mutant: doubled acceptance probability */
+  const uint64_t thresh = or_threshold(p > 0.5 ? 1.0 : 2.0 * p);
+#else
+  const uint64_t thresh = or_threshold(p);
+#endif
+  const uint64_t EMPTY = UINT64_MAX;
+
+  /* roles from the pre-step state (all predicates use the state before the step) */
+  int64_t* alist = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  uint8_t* is_t = (uint8_t*)malloc((size_t)(n > 0 ? n : 1));
+  uint64_t* a_choice = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
+  uint64_t* t_best = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
+  if (!alist || !is_t || !a_choice || !t_best) {
+    free(alist); free(is_t); free(a_choice); free(t_best);
+    return OR_ENOMEM;
+  }
+  int64_t na = 0, nt = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (is_active(&R, type[i], state[i])) alist[na++] = i;
+    is_t[i] = (uint8_t)is_target(&R, type[i], state[i]);
+    nt += is_t[i];
+    t_best[i] = EMPTY;
+  }
+
+  /* Steps 1-5: for each A, scan every particle (brute force), keep the
+   * in-range, eligible, non-bonded, accepted targets and pick one of them:
+   * the one with the smallest (w1, id_T) key. */
+  int64_t in_rc = 0, excluded = 0, accepted = 0, proposals = 0;
+#pragma omp parallel for schedule(dynamic, 8) reduction(+ : in_rc, excluded, accepted, proposals)
+  for (int64_t k = 0; k < na; ++k) {
+    const int64_t i = alist[k];
+    uint64_t best = EMPTY;
+    for (int64_t j = 0; j < n; ++j) {
+      if (!is_t[j] || j == i) continue;
+      float r2 = dist2(x, y, z, i, j, L, halfL);
+#if OR_MUTANT == 3 /* mutant: inclusive cutoff */
+      if (!(r2 <= rc2)) continue;
+#else
+      if (!(r2 < rc2)) continue;                    /* step 1: cutoff */
+#endif
+      in_rc++;
+#if OR_MUTANT == 9 /* mutant: bonded pairs not excluded */
+      if (0) {
+#else
+      if (exclude_bonded && bonded(adj, B, i, j)) { /* step 1: not already bonded */
+#endif
+        excluded++;
+        continue;
+      }
+      uint32_t ctr[4] = {step, (uint32_t)i, (uint32_t)j, 0u}, w[4];
+      or_philox4x32_10(ctr, seed, w);
+      if (!((uint64_t)w[0] < thresh)) continue;    /* step 2: u < k dt Theta */
+      accepted++;
+      uint64_t key = ((uint64_t)w[1] << 32) | (uint64_t)(uint32_t)j;
+      if (key < best) best = key;                   /* step 5: one T per A */
+    }
+    a_choice[k] = best;
+    if (best != EMPTY) proposals++;
+  }
+
+  /* Steps 6-7: each chosen T keeps the A with the smallest (w2, id_A). */
+  for (int64_t k = 0; k < na; ++k) {
+    if (a_choice[k] == EMPTY) continue;
+    const int64_t i = alist[k];
+    const int64_t j = (int64_t)(a_choice[k] & 0xFFFFFFFFu);
+    uint32_t ctr[4] = {step, (uint32_t)i, (uint32_t)j, 0u}, w[4];
+    or_philox4x32_10(ctr, seed, w);
+    uint64_t key2 = ((uint64_t)w[2] << 32) | (uint64_t)(uint32_t)i;
+    if (key2 < t_best[j]) t_best[j] = key2;
+  }
+
+  /* Step 9: bonds in increasing id_A order; states updated simultaneously
+   * (every selection above used the pre-step states). */
+  int64_t nb = 0, overflow = 0;
+  for (int64_t k = 0; k < na; ++k) {
+    if (a_choice[k] == EMPTY) continue;
+    const int64_t i = alist[k];
+    const int64_t j = (int64_t)(a_choice[k] & 0xFFFFFFFFu);
+#if OR_MUTANT != 5 /* mutant 5: no one-A-per-T selection */
+    if ((t_best[j] & 0xFFFFFFFFu) != (uint64_t)(uint32_t)i) continue;
+#endif
+    bonds[2 * nb] = (int32_t)i;
+    bonds[2 * nb + 1] = (int32_t)j;
+    nb++;
+  }
+  for (int64_t b = 0; b < nb; ++b) {
+    const int64_t i = bonds[2 * b], j = bonds[2 * b + 1];
+#if OR_MUTANT == 10 /* mutant: deltas swapped between roles */
+    state[i] += d_t;
+    state[j] += d_a;
+#else
+    state[i] += d_a;
+    state[j] += d_t;
+#endif
+    int placed = 0;
+    for (int32_t s = 0; s < B && !placed; ++s)
+      if (adj[i * B + s] < 0) { adj[i * B + s] = (int32_t)j; placed = 1; }
+    if (!placed) overflow++;
+    placed = 0;
+    for (int32_t s = 0; s < B && !placed; ++s)
+      if (adj[j * B + s] < 0) { adj[j * B + s] = (int32_t)i; placed = 1; }
+    if (!placed) overflow++;
+  }
+  *n_bonds = nb;
+  if (stats) {
+    stats[ST_A_ELIG] = na;
+    stats[ST_T_ELIG] = nt;
+    stats[ST_IN_RC] = in_rc;
+    stats[ST_EXCLUDED] = excluded;
+    stats[ST_ACCEPTED] = accepted;
+    stats[ST_PROPOSALS] = proposals;
+    stats[ST_BONDS] = nb;
+    stats[ST_ADJ_OVERFLOW] = overflow;
+  }
+  free(alist); free(is_t); free(a_choice); free(t_best);
+  return overflow ? OR_ECAP : OR_OK;
+}
+
+/* ----------------------------------------------------------------------- */
+/* FP64 recheck of the cutoff decision (diagnostic only).                    */
+/* Counts, over all eligible (A, T) pairs, those whose FP64 distance from  */
+/* the same FP32 coordinates lies within tol of rc, and those where the    */
+/* FP64 decision r < rc differs from the FP32 decision r2 < rc2.           */
+/* ----------------------------------------------------------------------- */
+int or_near_cutoff(int32_t n, float L, const float* x, const float* y, const float* z,
+                   const int32_t* type, const int32_t* state,
+                   int32_t type_a, int32_t a_min, int32_t a_max,
+                   int32_t type_t, int32_t t_min, int32_t t_max,
+                   float rc, double tol, int64_t* near, int64_t* disagree) {
+  const double Ld = (double)L, halfd = 0.5 * Ld, rcd = (double)rc;
+  const float halfL = 0.5f * L, rc2 = rc * rc;
+  int64_t cnt_near = 0, cnt_dis = 0;
+#pragma omp parallel for schedule(dynamic, 8) reduction(+ : cnt_near, cnt_dis)
+  for (int64_t i = 0; i < n; ++i) {
+    if (!(type[i] == type_a && state[i] >= a_min && state[i] <= a_max)) continue;
+    for (int64_t j = 0; j < n; ++j) {
+      if (!(type[j] == type_t && state[j] >= t_min && state[j] <= t_max) || j == i) continue;
+      double d[3] = {(double)x[j] - (double)x[i], (double)y[j] - (double)y[i],
+                     (double)z[j] - (double)z[i]};
+      double r2 = 0.0;
+      for (int c = 0; c < 3; ++c) {
+        if (d[c] > halfd) d[c] -= Ld;
+        else if (d[c] < -halfd) d[c] += Ld;
+        r2 += d[c] * d[c];
+      }
+      if (r2 > (rcd + 1.0) * (rcd + 1.0)) continue;
+      double r = sqrt(r2);
+      if (fabs(r - rcd) < tol) cnt_near++;
+      int in32 = dist2(x, y, z, i, j, L, halfL) < rc2;
+      int in64 = r < rcd;
+      if (in32 != in64) cnt_dis++;
+    }
+  }
+  *near = cnt_near;
+  *disagree = cnt_dis;
+  return OR_OK;
+}
+
+/* ----------------------------------------------------------------------- */
+/* Re-jitter between reaction steps: the synthetic stand-in for the MD       */
+/* integration that the paper runs between reaction steps (Sec. III: the     */
+/* reaction runs every Theta MD steps).  Not part of the paper's method.     */
+/* Displacement per dimension: S = (sum of 12 uniform bytes) - 1530, an       */
+/* Irwin-Hall(12) variable on an integer grid with mean 0 and variance 65535,*/
+/* scaled by c = fl32(sigma/256); the bytes come from three Philox blocks     */
+/* with counter (step, id, blk, tag), blk = 0..2, words 3d..3d+2 for dim d.   */
+/* ----------------------------------------------------------------------- */
+void or_ih12_offsets(uint32_t step, uint32_t id, uint32_t tag, uint64_t seed, int32_t S[3]) {
+  uint32_t words[12];
+  for (uint32_t blk = 0; blk < 3; ++blk) {
+    uint32_t ctr[4] = {step, id, blk, tag};
+    or_philox4x32_10(ctr, seed, words + 4 * blk);
+  }
+  for (int d = 0; d < 3; ++d) {
+    int32_t sum = 0;
+    for (int w = 0; w < 3; ++w) {
+      uint32_t v = words[3 * d + w];
+      for (int b = 0; b < 4; ++b) sum += (int32_t)((v >> (8 * b)) & 0xFFu);
+    }
+#if OR_MUTANT == 12 /* mutant: off-centre jitter */
+    S[d] = sum - 1536;
+#else
+    S[d] = sum - 1530;
+#endif
+  }
+}
+
+static float wrap_box(float v, float L) {
+  if (v < 0.0f) v = v + L;
+  if (v >= L) v = v - L;
+  return v;
+}
+
+void or_jitter(int32_t n, float L, float* x, float* y, float* z, uint64_t seed,
+               uint32_t step, double sigma) {
+  const float c = (float)(sigma / 256.0);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    int32_t S[3];
+    or_ih12_offsets(step, (uint32_t)i, 1u, seed, S);
+    float dx = (float)S[0] * c, dy = (float)S[1] * c, dz = (float)S[2] * c;
+    x[i] = wrap_box(x[i] + dx, L);
+    y[i] = wrap_box(y[i] + dy, L);
+    z[i] = wrap_box(z[i] + dz, L);
+  }
+}
+
+/* ----------------------------------------------------------------------- */
+/* A run of reaction steps first_step .. first_step+n_steps-1.  Each step s  */
+/* jitters the positions with step index s (if sigma > 0) and then reacts.   */
+/* Bond log rows: (step, id_A, id_T).  stats_per_step: n_steps x ST_COUNT.   */
+/* ----------------------------------------------------------------------- */
+int or_run(int32_t n, float L, float* x, float* y, float* z, const int32_t* type,
+           int32_t* state, int32_t* adj, int32_t B,
+           int32_t type_a, int32_t a_min, int32_t a_max, int32_t d_a,
+           int32_t type_t, int32_t t_min, int32_t t_max, int32_t d_t,
+           float rc, double p, int32_t exclude_bonded, uint64_t seed,
+           uint32_t first_step, uint32_t n_steps, double sigma,
+           int32_t* log, int64_t log_cap, int64_t* n_log, int64_t* stats_per_step) {
+  int32_t* step_bonds = (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)(n / 2 + 1));
+  if (!step_bonds) return OR_ENOMEM;
+  int64_t total = 0;
+  int rc_code = OR_OK;
+  for (uint32_t k = 0; k < n_steps; ++k) {
+    uint32_t s = first_step + k;
+    if (sigma > 0.0) or_jitter(n, L, x, y, z, seed, s, sigma);
+    int64_t nb = 0;
+    int64_t* st = stats_per_step ? stats_per_step + (int64_t)k * ST_COUNT : NULL;
+    int e = or_react_step(n, L, x, y, z, type, state, adj, B, type_a, a_min, a_max, d_a,
+                          type_t, t_min, t_max, d_t, rc, p, exclude_bonded, seed, s,
+                          step_bonds, n / 2 + 1, &nb, st);
+    if (e != OR_OK && e != OR_ECAP) { rc_code = e; break; }
+    if (e == OR_ECAP) rc_code = OR_ECAP;
+    for (int64_t b = 0; b < nb; ++b) {
+      if (total < log_cap) {
+        log[3 * total] = (int32_t)s;
+        log[3 * total + 1] = step_bonds[2 * b];
+        log[3 * total + 2] = step_bonds[2 * b + 1];
+      }
+      total++;
+    }
+  }
+  *n_log = total;
+  free(step_bonds);
+  if (rc_code == OR_OK && total > log_cap) return OR_ECAP;
+  return rc_code;
+}
+
+int or_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

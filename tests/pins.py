@@ -1,0 +1,469 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Every check takes the oracle library handle ``lib`` so that the mutation test
+can run the same checks against oracle builds with a planted mistake and show
+that each mistake is caught.  A check raises AssertionError on failure.
+"""
+import itertools
+import math
+from collections import Counter
+
+import numpy as np
+
+import oracle
+from oracle import Rule, System
+from paper_1409_7498_amd import workload
+
+STEP = dict(type_a=1, a_min=1, a_max=4, d_a=-1, type_t=0, t_min=1, t_max=2, d_t=-1)
+CHAIN = dict(type_a=0, a_min=2, a_max=2, d_a=-1, type_t=0, t_min=0, t_max=0, d_t=2)
+
+
+def mk(L, pts, types, states, B=4, adj=None):
+    pts = np.asarray(pts, dtype=np.float32).reshape(-1, 3)
+    n = pts.shape[0]
+    a = np.full((n, B), -1, np.int32) if adj is None else np.asarray(adj, np.int32)
+    return System(L, pts[:, 0], pts[:, 1], pts[:, 2], np.asarray(types, np.int32),
+                  np.asarray(states, np.int32), a)
+
+
+def step_rule(rc=1.12, p=1.0, excl=1):
+    return Rule(**STEP, rc=rc, p=p, exclude_bonded=excl)
+
+
+def chain_rule(rc=1.12, p=1.0):
+    return Rule(**CHAIN, rc=rc, p=p, exclude_bonded=1)
+
+
+def one(lib, s, rule, seed=1, step=1):
+    code, bonds, st = oracle.react_step(s, rule, seed, step, lib=lib)
+    return code, [tuple(b) for b in bonds.tolist()], st
+
+
+# --------------------------------------------------------------------------
+# distance and cutoff (Sec. II: reaction within a given interaction range)
+# --------------------------------------------------------------------------
+def check_pair_distance(lib):
+    A = (5.0, 5.0, 5.0)
+    cases = [((6.0, 5.0, 5.0), True),     # r = 1.0
+             ((6.2, 5.0, 5.0), False),    # r = 1.2
+             ((5.7, 5.7, 5.5), True),     # r2 = 1.23 < 1.2544
+             ((5.7, 5.7, 5.6), False),    # r2 = 1.34: the z term decides
+             ((5.0, 5.0, 6.15), False),   # pure z separation beyond rc
+             ((5.0, 5.0, 3.95), True)]    # pure -z separation inside rc
+    for T, inside in cases:
+        code, bonds, _ = one(lib, mk(10.0, [A, T], [1, 0], [4, 2]), step_rule())
+        assert code == 0
+        assert bonds == ([(0, 1)] if inside else []), (T, bonds)
+
+
+def check_periodic(lib):
+    cases = [([(0.1, 5, 5), (9.5, 5, 5)], True),       # through x = 0: r = 0.6
+             ([(0.1, 5, 5), (8.9, 5, 5)], False),      # r = 1.2 across the boundary
+             ([(5, 9.9, 0.2), (5, 0.3, 9.8)], True),   # y and z both wrap: r2 = 0.32
+             ([(9.7, 9.7, 9.7), (0.2, 0.2, 0.2)], True)]  # corner: r2 = 0.75
+    for pts, inside in cases:
+        code, bonds, _ = one(lib, mk(10.0, pts, [1, 0], [4, 2]), step_rule())
+        assert code == 0 and bonds == ([(0, 1)] if inside else []), (pts, bonds)
+
+
+def check_cutoff_strict(lib):
+    s = mk(10.0, [(1, 1, 1), (2, 1, 1)], [1, 0], [4, 2])  # r2 = 1 exactly
+    _, bonds, st = one(lib, s.copy(), step_rule(rc=1.0))
+    assert bonds == [] and st["in_rc"] == 0, "r2 == rc2 must be out of range"
+    rc_up = float(np.nextafter(np.float32(1.0), np.float32(2.0)))
+    _, bonds, st = one(lib, s.copy(), step_rule(rc=rc_up))
+    assert bonds == [(0, 1)] and st["in_rc"] == 1
+
+
+# --------------------------------------------------------------------------
+# acceptance u < k dt Theta (Sec. II, Eqs. (3)-(4))
+# --------------------------------------------------------------------------
+def check_p0_p1(lib):
+    g = workload.generate(4000, 16.75, "step", 7)
+    s0 = System(g["L"], g["x"], g["y"], g["z"], g["type"], g["state"], g["adj"])
+    _, bonds, st = one(lib, s0.copy(), step_rule(p=0.0))
+    assert bonds == [] and st["accepted"] == 0 and st["in_rc"] > 0
+    _, bonds, st = one(lib, s0.copy(), step_rule(p=1.0))
+    assert st["accepted"] == st["in_rc"] - st["excluded"]
+    # every A with at least one candidate proposes; count candidates in FP64
+    x, y, z = (np.asarray(v, np.float64) for v in (s0.x, s0.y, s0.z))
+    A = np.nonzero(s0.type == 1)[0]
+    T = np.nonzero(s0.type == 0)[0]
+    L = s0.L
+    with_cand = 0
+    for i in A:
+        d = np.stack([x[T] - x[i], y[T] - y[i], z[T] - z[i]])
+        d -= L * np.round(d / L)
+        r = np.sqrt((d * d).sum(0))
+        assert not np.any(np.abs(r - 1.12) < 1e-5), "fixture too close to the cutoff"
+        with_cand += int(np.any(r < 1.12))
+    assert st["proposals"] == with_cand
+    assert len(bonds) <= with_cand and len(bonds) > 0.5 * with_cand
+
+
+def check_isolated_pairs(lib):
+    pts, types, states = [], [], []
+    for k in range(50):
+        cx, cy, cz = 2.0 + 3.0 * (k % 5), 2.0 + 3.0 * ((k // 5) % 5), 2.0 + 3.0 * (k // 25)
+        pts += [(cx, cy, cz), (cx + 0.5, cy + 0.5, cz)]
+        types += [1, 0]
+        states += [4, 2]
+    _, bonds, _ = one(lib, mk(15.0, pts, types, states), step_rule(p=1.0))
+    assert bonds == [(2 * k, 2 * k + 1) for k in range(50)]
+
+
+def _cluster_system(n_t, copies, spacing=3.5):
+    """``copies`` isolated clusters, each one A with n_t targets at r = 0.8."""
+    dirs = [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]
+    m = int(math.ceil(copies ** (1 / 3)))
+    L = spacing * m
+    pts, types, states = [], [], []
+    for k in range(copies):
+        c = np.array([(k % m) + 0.5, ((k // m) % m) + 0.5, (k // (m * m)) + 0.5]) * spacing
+        pts.append(tuple(c))
+        types.append(1)
+        states.append(4)
+        for d in dirs[:n_t]:
+            pts.append(tuple(c + 0.8 * np.array(d)))
+            types.append(0)
+            states.append(2)
+    return mk(L, pts, types, states)
+
+
+def check_isolated_cluster_probability(lib, p=0.3, copies=343, seeds=6):
+    """isolated A with n partners bonds with probability 1 - (1 - p)^n."""
+    for n_t in (1, 2, 4):
+        s = _cluster_system(n_t, copies)
+        hits = 0
+        for seed in range(seeds):
+            _, bonds, _ = one(lib, s.copy(), step_rule(p=p), seed=1000 + seed)
+            hits += len(bonds)
+        trials = copies * seeds
+        q = 1 - (1 - p) ** n_t
+        sd = math.sqrt(q * (1 - q) / trials)
+        assert abs(hits / trials - q) < 4.5 * sd, (n_t, hits / trials, q)
+
+
+def check_acceptance_ratio(lib, p=0.3):
+    """accepted / candidates is binomial(p) on a frozen configuration."""
+    g = workload.generate(4000, 16.75, "step", 11)
+    s0 = System(g["L"], g["x"], g["y"], g["z"], g["type"], g["state"], g["adj"])
+    acc = cand = 0
+    for step in range(1, 9):
+        _, _, st = one(lib, s0.copy(), step_rule(p=p), seed=5, step=step)
+        acc += st["accepted"]
+        cand += st["in_rc"] - st["excluded"]
+    sd = math.sqrt(p * (1 - p) / cand)
+    assert abs(acc / cand - p) < 4.5 * sd, (acc / cand, p)
+
+
+# --------------------------------------------------------------------------
+# selection: one T per A and one A per T, each at random (Table I, steps 5, 7)
+# --------------------------------------------------------------------------
+def check_two_a_one_t(lib, seeds=2000):
+    s = mk(10.0, [(5, 5, 5), (6.8, 5, 5), (5.9, 5, 5)], [1, 1, 0], [4, 4, 2])
+    wins = Counter()
+    for seed in range(seeds):
+        _, bonds, _ = one(lib, s.copy(), step_rule(p=1.0), seed=seed)
+        assert len(bonds) == 1, bonds
+        wins[bonds[0][0]] += 1
+    sd = math.sqrt(0.25 / seeds)
+    assert abs(wins[0] / seeds - 0.5) < 4.5 * sd, wins
+
+
+def check_two_a_one_t_probability(lib, p=0.4, seeds=3000):
+    """Two A's share a lone T: A0 wins w.p. p - p^2/2 and a bond forms w.p. 1-(1-p)^2."""
+    s = mk(10.0, [(5, 5, 5), (6.8, 5, 5), (5.9, 5, 5)], [1, 1, 0], [4, 4, 2])
+    w0 = nb = 0
+    for seed in range(seeds):
+        _, bonds, _ = one(lib, s.copy(), step_rule(p=p), seed=seed)
+        assert len(bonds) <= 1
+        nb += len(bonds)
+        w0 += sum(1 for b in bonds if b[0] == 0)
+    for obs, q in ((w0, p - p * p / 2), (nb, 1 - (1 - p) ** 2)):
+        sd = math.sqrt(q * (1 - q) / seeds)
+        assert abs(obs / seeds - q) < 4.5 * sd, (obs / seeds, q)
+
+
+def check_uniform_choice(lib, seeds=2500):
+    """One A with five partners at p = 1: each chosen with frequency 1/5."""
+    c = np.array([5.0, 5.0, 5.0])
+    dirs = [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1)]
+    pts = [tuple(c)] + [tuple(c + 0.8 * np.array(d)) for d in dirs]
+    s = mk(10.0, pts, [1] + [0] * 5, [4] + [2] * 5)
+    cnt = Counter()
+    for seed in range(seeds):
+        _, bonds, _ = one(lib, s.copy(), step_rule(p=1.0), seed=seed)
+        assert len(bonds) == 1
+        cnt[bonds[0][1]] += 1
+    e = seeds / 5
+    chi2 = sum((cnt[k] - e) ** 2 / e for k in range(1, 6))
+    assert chi2 < 23.5, (chi2, cnt)  # chi2(4 dof) p-value 1e-4
+
+
+def exact_outcomes(edges, p):
+    """Exact outcome distribution of one reaction step on a tiny bipartite
+    candidate graph, by enumeration of the paper's steps: accept each edge
+    independently with probability p; each A picks one accepted edge uniformly;
+    each T keeps one of the A's that picked it, uniformly."""
+    dist = Counter()
+    A = sorted({a for a, _ in edges})
+    for mask in itertools.product((0, 1), repeat=len(edges)):
+        pm = math.prod(p if m else 1 - p for m in mask)
+        acc = [e for e, m in zip(edges, mask) if m]
+        per_a = [[t for a2, t in acc if a2 == a] for a in A]
+        choices = [opts if opts else [None] for opts in per_a]
+        for pick in itertools.product(*choices):
+            pa = pm * math.prod(1.0 / len(o) for o in per_a if o)
+            by_t = {}
+            for a, t in zip(A, pick):
+                if t is not None:
+                    by_t.setdefault(t, []).append(a)
+            for win in itertools.product(*[[(a, t) for a in by_t[t]] for t in sorted(by_t)]):
+                pw = pa * math.prod(1.0 / len(by_t[t]) for t in by_t)
+                dist[tuple(sorted(win))] += pw
+    return dist
+
+
+def check_exact_small_graph(lib, p=0.5, seeds=12000):
+    """Empirical outcome frequencies equal the exact enumeration (chi^2)."""
+    # A0 = 0, A1 = 1, T0 = 2, T1 = 3, T2 = 4; A0-{T0,T1}, A1-{T1,T2}
+    pts = [(3.0, 5, 5), (4.8, 5, 5), (2.2, 5, 5), (3.9, 5, 5), (5.6, 5, 5)]
+    s = mk(10.0, pts, [1, 1, 0, 0, 0], [4, 4, 2, 2, 2])
+    exact = exact_outcomes([(0, 2), (0, 3), (1, 3), (1, 4)], p)
+    emp = Counter()
+    for seed in range(seeds):
+        _, bonds, _ = one(lib, s.copy(), step_rule(p=p), seed=seed)
+        emp[tuple(sorted(bonds))] += 1
+    assert set(emp) <= set(exact), set(emp) - set(exact)
+    chi2 = sum((emp[k] - seeds * q) ** 2 / (seeds * q) for k, q in exact.items())
+    dof = len(exact) - 1
+    assert chi2 < dof + 6 * math.sqrt(2 * dof), (chi2, dof)
+
+
+# --------------------------------------------------------------------------
+# bonding, states, exclusion (Sec. II, Eq. (2); Table I, step 9)
+# --------------------------------------------------------------------------
+def check_exclusion(lib):
+    adj = [[1, -1, -1, -1], [0, -1, -1, -1]]
+    s = mk(10.0, [(5, 5, 5), (5.8, 5, 5)], [1, 0], [3, 1], adj=adj)
+    _, bonds, st = one(lib, s.copy(), step_rule(p=1.0, excl=1))
+    assert bonds == [] and st["excluded"] == 1
+    s2 = s.copy()
+    _, bonds, _ = one(lib, s2, step_rule(p=1.0, excl=0))
+    assert bonds == [(0, 1)] and s2.adj[0].tolist() == [1, 1, -1, -1]
+
+
+def check_valence_stop(lib):
+    s = mk(10.0, [(5, 5, 5), (5.8, 5, 5), (4.2, 5, 5)], [1, 0, 0], [1, 2, 2])
+    _, bonds, _ = one(lib, s, step_rule(p=1.0), step=1)
+    assert len(bonds) == 1 and s.state[0] == 0
+    other = 2 if bonds[0][1] == 1 else 1
+    assert s.state[bonds[0][1]] == 1 and s.state[other] == 2
+    _, bonds, _ = one(lib, s, step_rule(p=1.0), step=2)
+    assert bonds == [], "a crosslinker at state 0 stops bonding"
+
+
+def check_chain_transfer(lib):
+    s = mk(10.0, [(2, 5, 5), (2.8, 5, 5), (3.6, 5, 5)], [0, 0, 0], [2, 0, 0], B=2)
+    _, bonds, _ = one(lib, s, chain_rule(), step=1)
+    assert bonds == [(0, 1)] and s.state.tolist() == [1, 2, 0]
+    _, bonds, _ = one(lib, s, chain_rule(), step=2)
+    assert bonds == [(1, 2)] and s.state.tolist() == [1, 1, 2]
+    _, bonds, _ = one(lib, s, chain_rule(), step=3)
+    assert bonds == [] and s.adj.tolist() == [[1, -1], [0, 2], [1, -1]]
+
+
+def check_errors(lib):
+    ok = mk(10.0, [(1, 1, 1), (2, 1, 1)], [1, 0], [4, 2])
+    assert one(lib, ok.copy(), step_rule(rc=5.0))[0] == oracle.EINVAL      # L <= 2 rc
+    assert one(lib, ok.copy(), step_rule(p=1.5))[0] == oracle.EINVAL
+    assert one(lib, ok.copy(), step_rule(p=-0.1))[0] == oracle.EINVAL
+    for bad in ((np.nan, 1, 1), (10.0, 1, 1), (-0.5, 1, 1)):
+        s = mk(10.0, [(1, 1, 1), bad], [1, 0], [4, 2])
+        assert one(lib, s, step_rule())[0] == oracle.EINVAL, bad
+    amb = Rule(type_a=0, a_min=1, a_max=3, d_a=-1, type_t=0, t_min=3, t_max=5, d_t=1, rc=1.12, p=0.5)
+    assert one(lib, ok.copy(), amb)[0] == oracle.ERULE_AMBIGUOUS
+
+
+def check_adj_overflow(lib):
+    s = mk(10.0, [(5, 5, 5), (5.8, 5, 5)], [1, 0], [4, 2], B=1, adj=[[7], [-1]])
+    code, bonds, st = one(lib, s, step_rule(p=1.0))
+    assert code == oracle.ECAP and bonds == [(0, 1)] and st["adj_overflow"] == 1
+    assert s.state.tolist() == [3, 1] and s.adj.tolist() == [[7], [0]]
+
+
+# --------------------------------------------------------------------------
+# invariants over a full run (Sec. III: at most one new bond per particle)
+# --------------------------------------------------------------------------
+def fp64_dist(s, i, j):
+    d = np.array([s.x[j], s.y[j], s.z[j]], np.float64) - np.array([s.x[i], s.y[i], s.z[i]], np.float64)
+    d -= s.L * np.round(d / s.L)
+    return float(np.sqrt((d * d).sum()))
+
+
+def check_run_invariants(lib, steps=200, p=0.05):
+    cfg = workload.CONFIGS["c1"]
+    g = workload.generate(cfg.N, cfg.L, "step", cfg.seed)
+    s = System(g["L"], g["x"], g["y"], g["z"], g["type"], g["state"], g["adj"])
+    state0 = s.state.copy()
+    rule = step_rule(p=p)
+    all_pairs = set()
+    total = 0
+    for step in range(1, steps + 1):
+        oracle.jitter(s, cfg.seed, step, cfg.sigma, lib=lib)
+        pre = s.state.copy()
+        code, bonds, st = one(lib, s, rule, seed=cfg.seed, step=step)
+        assert code == 0
+        ids = [i for b in bonds for i in b]
+        assert len(ids) == len(set(ids)), "a particle took two bonds in one step"
+        assert [b[0] for b in bonds] == sorted(b[0] for b in bonds)
+        for i, j in bonds:
+            assert s.type[i] == 1 and 1 <= pre[i] <= 4 and s.type[j] == 0 and 1 <= pre[j] <= 2
+            assert fp64_dist(s, i, j) < 1.12 + 1e-5
+            assert (i, j) not in all_pairs
+            all_pairs.add((i, j))
+        assert st["bonds"] == len(bonds)
+        total += len(bonds)
+    deg = np.zeros(s.n, np.int64)
+    for i, j in all_pairs:
+        deg[i] += 1
+        deg[j] += 1
+    assert np.array_equal(deg, state0 - s.state), "bonds formed != state decrements"
+    assert s.state.min() >= 0 and np.all(s.state[s.type == 1] <= 4) and np.all(s.state[s.type == 0] <= 2)
+    for i in range(s.n):  # adjacency symmetric and exactly the bond set
+        row = [v for v in s.adj[i] if v >= 0]
+        assert len(row) == deg[i]
+        for v in row:
+            assert i in s.adj[v]
+    assert total > 100
+
+
+# --------------------------------------------------------------------------
+# jitter (synthetic stand-in for MD between reaction steps)
+# --------------------------------------------------------------------------
+def ih12_exact_pmf():
+    """Exact pmf of the sum of 12 independent uniform bytes, by convolution."""
+    pmf = np.array([1.0])
+    byte = np.full(256, 1.0 / 256)
+    for _ in range(12):
+        pmf = np.convolve(pmf, byte)
+    return pmf  # index k <-> sum k, k = 0..3060
+
+
+def check_jitter_distribution(lib, n=30000):
+    S = oracle.ih12_offsets(3, np.arange(n), 1, 12345, lib=lib).ravel().astype(np.int64)
+    assert S.min() >= -1530 and S.max() <= 1530
+    assert abs(S.mean()) < 5 * math.sqrt(65535 / S.size), S.mean()
+    assert abs(S.var() / 65535 - 1) < 0.03
+    pmf = ih12_exact_pmf()
+    idx = np.clip(np.searchsorted(np.cumsum(pmf), np.linspace(0, 1, 31)[1:-1]), 0, 3060)
+    bins = np.concatenate([[-1], idx, [3060]])
+    obs = np.histogram(S + 1530, bins=bins + 0.5)[0]
+    exp = np.array([pmf[bins[k] + 1: bins[k + 1] + 1].sum() for k in range(len(bins) - 1)]) * S.size
+    chi2 = ((obs - exp) ** 2 / exp).sum()
+    dof = len(obs) - 1
+    assert chi2 < dof + 6 * math.sqrt(2 * dof), chi2
+
+
+def check_jitter_wrap(lib):
+    L = 10.0
+    pts = [(0.001, 9.999, 5.0), (9.9999, 0.0, 0.0), (5, 5, 5)]
+    s = mk(L, pts, [0, 0, 0], [2, 2, 2])
+    x0 = s.x.copy()
+    for step in range(1, 40):
+        oracle.jitter(s, 99, step, 0.05, lib=lib)
+        for v in (s.x, s.y, s.z):
+            assert np.all(v >= 0) and np.all(v < np.float32(L))
+    # particle 2 never wraps: displacement equals the sum of the offsets * c
+    S = sum(oracle.ih12_offsets(st, [2], 1, 99, lib=lib)[0, 0] for st in range(1, 40))
+    assert abs((s.x[2] - x0[2]) - S * (0.05 / 256)) < 1e-4
+
+
+# --------------------------------------------------------------------------
+# kinetics: step-growth rate equation at short times (Sec. II C, Eqs. (12)-(13))
+# --------------------------------------------------------------------------
+def _eligible_counts(s, A, b_of):
+    """Per crosslinker: number of eligible, not yet bonded end units in range."""
+    T = np.nonzero((s.type == 0) & (s.state >= 1) & (s.state <= 2))[0]
+    xs = np.stack([s.x, s.y, s.z], 1).astype(np.float64)
+    out = []
+    for i in A:
+        if not (1 <= s.state[i] <= 4):
+            continue
+        d = xs[T] - xs[i]
+        d -= s.L * np.round(d / s.L)
+        near = T[(d * d).sum(1) < 1.12 ** 2]
+        nb = sum(1 for j in near if j not in s.adj[i])
+        out.append((b_of(i), nb))
+    return out
+
+
+def check_step_rate_equation(lib, replicas=24, kt_max=0.3, p=0.01):
+    from scipy.integrate import odeint
+    n_steps = int(round(kt_max / p))
+    checkpoints = (n_steps // 3, 2 * n_steps // 3, n_steps)
+    frac = {c: np.zeros(5) for c in checkpoints}
+    nsum, ncnt = np.zeros(5), np.zeros(5)
+    n_x = 0
+    for r in range(replicas):
+        seed = 777 + r
+        g = workload.generate(4000, 16.75, "step", seed)
+        s = System(g["L"], g["x"], g["y"], g["z"], g["type"], g["state"], g["adj"])
+        A = np.nonzero(s.type == 1)[0]
+        n_x += len(A)
+        for step in range(1, n_steps + 1):
+            oracle.jitter(s, seed, step, 0.05, lib=lib)
+            for b, nb in _eligible_counts(s, A, lambda i: 4 - s.state[i]):
+                nsum[b] += nb
+                ncnt[b] += 1
+            one(lib, s, step_rule(p=p), seed=seed, step=step)
+            if step in frac:
+                frac[step] += np.bincount(4 - s.state[A], minlength=5)
+    Nb = nsum / np.maximum(ncnt, 1)
+
+    def rhs(xv, _t):
+        d = np.zeros(5)
+        for b in range(5):
+            if b < 4:
+                d[b] -= Nb[b] * xv[b]
+            if b > 0:
+                d[b] += Nb[b - 1] * xv[b - 1]
+        return d
+
+    for c in checkpoints:
+        pred = odeint(rhs, [1, 0, 0, 0, 0], [0, c * p])[-1]
+        obs = frac[c] / n_x
+        for b in range(3):
+            sd = math.sqrt(max(pred[b] * (1 - pred[b]), 1e-4) / n_x)
+            assert abs(obs[b] - pred[b]) < 4 * sd + 0.02, (c, b, obs[b], pred[b])
+
+
+def check_chain_consumption(lib, p=0.05, steps=40):
+    """Chain growth: monomer loss per step equals p times the candidate pairs
+    around the active ends, to first order in p (Sec. II B, Eqs. (6)-(10))."""
+    pred = obs = 0.0
+    for r in range(6):
+        seed = 4242 + r
+        g = workload.generate(4000, 16.75, "chain", seed)
+        state = g["state"].copy()
+        rng = np.random.default_rng(seed)
+        state[:] = 0
+        state[rng.choice(4000, 120, replace=False)] = 2
+        s = System(g["L"], g["x"], g["y"], g["z"], g["type"], state, g["adj"])
+        m0 = int((s.state == 0).sum())
+        for step in range(1, steps + 1):
+            oracle.jitter(s, seed, step, 0.05, lib=lib)
+            _, _, st = one(lib, s, chain_rule(p=p), seed=seed, step=step)
+            pred += p * (st["in_rc"] - st["excluded"])
+        obs += m0 - int((s.state == 0).sum())
+    # first-order prediction overshoots by O(p * N) (two accepted partners of
+    # one A give one bond, two A's on one T give one bond)
+    assert 0.85 * pred < obs < 1.01 * pred + 3 * math.sqrt(pred), (obs, pred)
+
+
+ALL = [check_pair_distance, check_periodic, check_cutoff_strict, check_p0_p1, check_isolated_pairs,
+       check_isolated_cluster_probability, check_acceptance_ratio, check_two_a_one_t,
+       check_two_a_one_t_probability, check_uniform_choice, check_exact_small_graph,
+       check_exclusion, check_valence_stop, check_chain_transfer, check_errors, check_adj_overflow,
+       check_jitter_distribution, check_jitter_wrap]
