@@ -1,0 +1,169 @@
+/*
+ * polyreact.h -- C ABI of the MI355X (gfx950) reaction-step library.
+ *
+ * The library implements the bond-creation step of de Buyl & Nies, "A
+ * parallel algorithm for step- and chain-growth polymerization in Molecular
+ * Dynamics" (arXiv:1409.7498): particles of given type and state that are
+ * closer than a cutoff react pairwise with probability p = k*dt*Theta per
+ * reaction step; every particle takes at most one new bond per step; bonded
+ * partners update their states.  All compute runs in HIP kernels built for
+ * gfx950; there is no CPU fallback.
+ *
+ * Conventions (every entry point):
+ *   - returns PR_OK (0) or a negative PR_E* code and never aborts; the text of
+ *     the last error of the calling thread is available from pr_last_error();
+ *   - argument validation that needs no device data happens before any launch
+ *     and leaves every buffer untouched;
+ *   - "device" pointers are HIP device allocations (e.g. torch tensors'
+ *     data_ptr()), "host" pointers ordinary host memory; sizes are in elements;
+ *   - stream arguments are hipStream_t passed as void*; NULL is the default
+ *     stream.  Calls that return host-visible results synchronise that stream.
+ *
+ * Arithmetic contract (identical on every path; the CPU oracle in the test
+ * suite implements the same contract independently):
+ *   - min-image component: d = p_T - p_A; if (d > L/2) d -= L; else if
+ *     (d < -L/2) d += L;  r2 = (dx*dx + dy*dy) + dz*dz, each operation rounded
+ *     to FP32, no fused multiply-add; in range iff r2 < fl32(rc*rc);
+ *   - draw: Philox4x32-10 (Salmon et al., SC'11) with counter
+ *     (step, id_A, id_T, 0) and key seed -> words (w0, w1, w2, w3); accepted
+ *     iff w0 < ceil(p * 2^32), i.e. u = w0 * 2^-32 < p (Sec. II, Eq. (4));
+ *   - one T per A: the smallest (w1, id_T) among A's retained candidates
+ *     (Table I, steps 3-5); one A per T: the smallest (w2, id_A) among the A's
+ *     that chose it (Table I, steps 6-7); states updated simultaneously after
+ *     all choices (Table I, step 9; Eq. (2));
+ *   - bonds of one step are reported in increasing id_A order.
+ */
+#ifndef POLYREACT_H
+#define POLYREACT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PR_OK 0
+#define PR_EINVAL (-1)          /* bad size, box, cutoff, probability or position */
+#define PR_ERULE_AMBIGUOUS (-2) /* type_a == type_t and the two state windows overlap */
+#define PR_ECAP (-3)            /* an output or adjacency capacity was too small */
+#define PR_ENOMEM (-4)          /* device allocation failed */
+#define PR_EHIP (-5)            /* a HIP runtime call failed (the handle is unusable) */
+#define PR_EBUSY (-6)           /* serving: request does not fit the memory budget now */
+#define PR_ENOTFOUND (-7)       /* serving: unknown ticket */
+
+/* One reaction rule, T^t + A^a -> T^(t+d_t)-A^(a+d_a) (Sec. II, Eq. (2)).
+ * A particle is eligible for the A role iff type == type_a and
+ * a_min <= state <= a_max (the paper's s_min^A, Sec. III); for the T role iff
+ * type == type_t and t_min <= state <= t_max.  Roles are decided on the state
+ * before the step.  rc: reaction cutoff (strict, r < rc).  p = k*dt*Theta in
+ * [0, 1] (Sec. II, Eqs. (3)-(4)).  exclude_bonded = 1: a pair that is already
+ * bonded (id_T present in the A's adjacency row) is never a candidate. */
+typedef struct pr_rule {
+  int32_t type_a, a_min, a_max, d_a;
+  int32_t type_t, t_min, t_max, d_t;
+  float rc;
+  int32_t exclude_bonded;
+  double p;
+} pr_rule;
+
+/* Per-step counters.  in_rc: eligible (A, T) pairs with r2 < rc2; drawn: of
+ * those, pairs whose draw passed; excluded: drawn pairs already bonded;
+ * accepted = drawn - excluded (the retained candidates); proposals: A's with a
+ * retained candidate; bonds: bonds created; adj_overflow: adjacency appends
+ * that found the row full (the bond and the states are still applied). */
+typedef struct pr_stats {
+  int64_t a_elig, t_elig, in_rc, drawn, excluded, accepted, proposals, bonds, adj_overflow;
+} pr_stats;
+
+/* Text of the calling thread's last error (static storage, never NULL). */
+const char* pr_last_error(void);
+
+/* Library version string. */
+const char* pr_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* One reaction step on caller-owned device arrays (Table I, steps 1-9).     */
+/*                                                                          */
+/* n particles in the periodic cube [0, L)^3.  Device arrays, indexed by     */
+/* particle id 0..n-1: x, y, z (FP32, each in [0, L)), type, state (in/out),  */
+/* adj (in/out, n x B row-major, -1 = empty slot; new partners are written   */
+/* into the first empty slot of each row).  step and seed key the draws.     */
+/* bonds (device, 2*cap int32): (id_A, id_T) pairs in increasing id_A order; */
+/* cap >= n/2 is required (at most one bond per particle).  n_bonds (host)   */
+/* receives the count; st (host, may be NULL) the counters.                  */
+/* Errors: PR_EINVAL (n < 0, B < 1, rc <= 0, L <= 2 rc, p outside [0,1], or a */
+/* position that is NaN or outside [0, L) -- detected on the device before   */
+/* any write), PR_ERULE_AMBIGUOUS, PR_ECAP (cap < n/2: nothing written; or    */
+/* an adjacency row was full: the step is complete except for the missing     */
+/* adjacency entries, counted in st->adj_overflow).  Synchronises stream.    */
+/* ------------------------------------------------------------------------ */
+int pr_react_step(int32_t n, float L, const float* x, const float* y, const float* z,
+                  const int32_t* type, int32_t* state, int32_t* adj, int32_t B,
+                  const pr_rule* rule, uint64_t seed, uint32_t step, int32_t* bonds,
+                  int32_t cap, int32_t* n_bonds, pr_stats* st, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Resident system: particle state kept in device memory across steps.      */
+/* ------------------------------------------------------------------------ */
+typedef struct pr_sys pr_sys;
+
+/* Creates a system of n particles in the cube [0, L)^3 with adjacency width
+ * B, reaction rule and draw seed.  log_cap: capacity of the device bond log
+ * in bonds (0 = n).  The handle owns all its device memory; stream (may be
+ * NULL) is the stream every later call on the handle uses. */
+int pr_sys_create(pr_sys** out, int32_t n, float L, int32_t B, const pr_rule* rule,
+                  uint64_t seed, int64_t log_cap, void* stream);
+void pr_sys_destroy(pr_sys* s);
+
+/* Loads a configuration indexed by particle id: x, y, z, type, state and adj
+ * (n x B).  on_device = 1: the pointers are device memory, 0: host memory.
+ * Clears the bond log and the counters.  PR_EINVAL on a position outside
+ * [0, L) or NaN (detected on the device, nothing loaded).  Synchronises. */
+int pr_sys_load(pr_sys* s, const float* x, const float* y, const float* z, const int32_t* type,
+                const int32_t* state, const int32_t* adj, int32_t on_device);
+
+/* Generates the synthetic jittered-lattice configuration on the device:
+ * kind 0 = step growth (5% crosslinkers type 1 state 4, else type 0 state 2),
+ * kind 1 = chain growth (0.1% active ends state 2, else free monomers state 0);
+ * lattice displacement sigma0; gen_seed keys the draws.  Same recipe as the
+ * host generator of the package.  Clears the bond log and counters. */
+int pr_sys_generate(pr_sys* s, int32_t kind, uint64_t gen_seed, double sigma0);
+
+/* Runs reaction steps first_step .. first_step + n_steps - 1.  Each step
+ * first moves every particle by the re-jitter (when sigma > 0) -- the
+ * stand-in for the MD integration between reaction steps -- and then reacts.
+ * Bonds are appended to the device bond log as (step, id_A, id_T) rows and
+ * counters to the per-step counter log.  Asynchronous on the handle's stream;
+ * errors found on the device are reported by the next synchronising call. */
+int pr_sys_run(pr_sys* s, uint32_t first_step, uint32_t n_steps, double sigma);
+
+/* Phase timing: like pr_sys_run, but synchronises and returns in ms[0..2]
+ * the summed GPU time of the jitter, the reaction step (every reaction
+ * kernel) and the dominant pair-sweep kernel alone, measured with HIP events
+ * on the handle's stream around each phase. */
+int pr_sys_run_timed(pr_sys* s, uint32_t first_step, uint32_t n_steps, double sigma, float* ms);
+
+/* Copies the current configuration out in particle-id order (host or device
+ * pointers per on_device; any pointer may be NULL to skip).  Synchronises;
+ * returns a pending device error, if any. */
+int pr_sys_read(pr_sys* s, float* x, float* y, float* z, int32_t* state, int32_t* adj,
+                int32_t on_device);
+
+/* Copies the bond log out: up to cap rows of (step, id_A, id_T) int32 into
+ * host memory; *n receives the total logged (PR_ECAP if it exceeded the log
+ * capacity; rows beyond it were dropped).  Synchronises. */
+int pr_sys_bonds(pr_sys* s, int32_t* out, int64_t cap, int64_t* n);
+
+/* Copies the per-step counters of the steps run since the last load (at most
+ * cap records) into host memory; *n receives their number.  Synchronises. */
+int pr_sys_stats(pr_sys* s, pr_stats* out, int64_t cap, int64_t* n);
+
+/* Dense-pass tuning of a handle: sort_period = steps between spatial re-sorts
+ * of the particle storage (0 = never sort; the results do not depend on it). */
+int pr_sys_set_sort_period(pr_sys* s, int32_t sort_period);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* POLYREACT_H */

@@ -12,8 +12,8 @@ from . import build as _build
 
 _lib = None
 
-ST_NAMES = ("a_elig", "t_elig", "in_rc", "excluded", "accepted", "proposals", "bonds",
-            "adj_overflow", "near_rc", "fp64_disagree")
+ST_NAMES = ("a_elig", "t_elig", "in_rc", "drawn", "excluded", "accepted", "proposals", "bonds",
+            "adj_overflow")
 ST_COUNT = len(ST_NAMES)
 
 OK, EINVAL, ERULE_AMBIGUOUS, ECAP, ENOMEM = 0, -1, -2, -3, -4
@@ -47,6 +47,9 @@ def _declare(lib):
     lib.or_run.argtypes = [i32, f32, P(f32), P(f32), P(f32), P(i32), P(i32), P(i32), i32,
                            *rule, u64, u32, u32, f64, P(i32), i64, P(i64), P(i64)]
     lib.or_run.restype = C.c_int
+    lib.or_sample_bonds.argtypes = [i32, f32, P(f32), P(f32), P(f32), P(i32), P(i32), P(i32), i32,
+                                    *rule, u64, u32, P(i64), i64, P(i32)]
+    lib.or_sample_bonds.restype = C.c_int
     lib.or_near_cutoff.argtypes = [i32, f32, P(f32), P(f32), P(f32), P(i32), P(i32),
                                    i32, i32, i32, i32, i32, i32, f32, f64, P(i64), P(i64)]
     lib.or_near_cutoff.restype = C.c_int
@@ -152,6 +155,21 @@ def run(sysm, rule, seed, first_step, n_steps, sigma, log_cap=None, lib=None):
     return code, log[: min(nl.value, log_cap)].copy(), st[:n_steps]
 
 
+def sample_bonds(sysm, rule, seed, step, ids, lib=None):
+    """Partner id of each sampled particle in this step's bonds (-1: none)."""
+    lib = lib or load()
+    ids = np.ascontiguousarray(ids, dtype=np.int64)
+    out = np.empty(ids.shape[0], np.int32)
+    code = lib.or_sample_bonds(sysm.n, C.c_float(sysm.L), _p(sysm.x, C.c_float),
+                               _p(sysm.y, C.c_float), _p(sysm.z, C.c_float),
+                               _p(sysm.type, C.c_int32), _p(sysm.state, C.c_int32),
+                               _p(sysm.adj, C.c_int32), sysm.B, *rule.args(), C.c_uint64(seed),
+                               C.c_uint32(step), _p(ids, C.c_int64), ids.shape[0],
+                               _p(out, C.c_int32))
+    assert code == 0, code
+    return out
+
+
 def jitter(sysm, seed, step, sigma, lib=None):
     lib = lib or load()
     lib.or_jitter(sysm.n, C.c_float(sysm.L), _p(sysm.x, C.c_float), _p(sysm.y, C.c_float),
@@ -185,4 +203,5 @@ def num_threads(lib=None):
 
 
 __all__ = ["Rule", "System", "react_step", "run", "jitter", "philox", "threshold", "near_cutoff",
+           "sample_bonds",
            "ih12_offsets", "ST_NAMES", "load", "num_threads"]

@@ -165,11 +165,59 @@ static int validate(int32_t n, float L, const float* x, const float* y, const fl
   return OR_OK;
 }
 
-/* stats layout (int64 x 10) */
+/* per-step counters (int64 x 9):
+ *   a_elig, t_elig  particles eligible for the A and T roles
+ *   in_rc           eligible (A, T) pairs with r2 < rc2
+ *   drawn           in-range pairs whose draw passes u < p
+ *   excluded        drawn pairs that are already bonded (not candidates)
+ *   accepted        drawn and not bonded: the retained candidates
+ *   proposals       A's with at least one retained candidate
+ *   bonds           bonds created
+ *   adj_overflow    adjacency appends that found the row full */
 enum {
-  ST_A_ELIG = 0, ST_T_ELIG, ST_IN_RC, ST_EXCLUDED, ST_ACCEPTED,
-  ST_PROPOSALS, ST_BONDS, ST_ADJ_OVERFLOW, ST_NEAR_RC, ST_FP64_DISAGREE, ST_COUNT
+  ST_A_ELIG = 0, ST_T_ELIG, ST_IN_RC, ST_DRAWN, ST_EXCLUDED, ST_ACCEPTED,
+  ST_PROPOSALS, ST_BONDS, ST_ADJ_OVERFLOW, ST_COUNT
 };
+
+/* Steps 1-5 for one active particle i: brute force over all particles, keep
+ * the in-range, target-eligible, not yet bonded, accepted ones (Table I, steps
+ * 1-2) and return the smallest (w1, id_T) key among them, or UINT64_MAX when
+ * there is none (steps 3-5).  cnt += {in range, drawn, excluded, accepted}. */
+static uint64_t choose_target(int32_t n, float L, const float* x, const float* y,
+                              const float* z, const uint8_t* is_t, const int32_t* adj,
+                              int32_t B, const or_rule* R, uint64_t thresh, uint64_t seed,
+                              uint32_t step, int64_t i, int64_t cnt[4]) {
+  const float halfL = 0.5f * L;
+  const float rc2 = R->rc * R->rc;
+  uint64_t best = UINT64_MAX;
+  for (int64_t j = 0; j < n; ++j) {
+    if (!is_t[j] || j == i) continue;
+    float r2 = dist2(x, y, z, i, j, L, halfL);
+#if OR_MUTANT == 3 /* mutant: inclusive cutoff */
+    if (!(r2 <= rc2)) continue;
+#else
+    if (!(r2 < rc2)) continue;                    /* step 1: cutoff */
+#endif
+    cnt[0]++;
+#if OR_MUTANT == 9 /* mutant: bonded pairs not excluded */
+    const int already = 0;
+#else
+    const int already = R->exclude_bonded && bonded(adj, B, i, j); /* step 1: not yet bonded */
+#endif
+    uint32_t ctr[4] = {step, (uint32_t)i, (uint32_t)j, 0u}, w[4];
+    or_philox4x32_10(ctr, seed, w);
+    if (!((uint64_t)w[0] < thresh)) continue;    /* step 2: u < k dt Theta */
+    cnt[1]++;
+    if (already) {
+      cnt[2]++;
+      continue;
+    }
+    cnt[3]++;
+    uint64_t key = ((uint64_t)w[1] << 32) | (uint64_t)(uint32_t)j;
+    if (key < best) best = key;                   /* step 5: one T per A */
+  }
+  return best;
+}
 
 /* ----------------------------------------------------------------------- */
 /* One reaction step (Table I, steps 1-9).                                   */
@@ -187,8 +235,6 @@ int or_react_step(int32_t n, float L, const float* x, const float* y, const floa
   if (err) return err;
   if (cap < (int64_t)n / 2) return OR_ECAP;
 
-  const float halfL = 0.5f * L;
-  const float rc2 = rc * rc;
 #if OR_MUTANT == 7 /* mutant: doubled acceptance probability */
   const uint64_t thresh = or_threshold(p > 0.5 ? 1.0 : 2.0 * p);
 #else
@@ -216,37 +262,16 @@ int or_react_step(int32_t n, float L, const float* x, const float* y, const floa
   /* Steps 1-5: for each A, scan every particle (brute force), keep the
    * in-range, eligible, non-bonded, accepted targets and pick one of them:
    * the one with the smallest (w1, id_T) key. */
-  int64_t in_rc = 0, excluded = 0, accepted = 0, proposals = 0;
-#pragma omp parallel for schedule(dynamic, 8) reduction(+ : in_rc, excluded, accepted, proposals)
+  int64_t in_rc = 0, drawn = 0, excluded = 0, accepted = 0, proposals = 0;
+#pragma omp parallel for schedule(dynamic, 8) reduction(+ : in_rc, drawn, excluded, accepted, proposals)
   for (int64_t k = 0; k < na; ++k) {
-    const int64_t i = alist[k];
-    uint64_t best = EMPTY;
-    for (int64_t j = 0; j < n; ++j) {
-      if (!is_t[j] || j == i) continue;
-      float r2 = dist2(x, y, z, i, j, L, halfL);
-#if OR_MUTANT == 3 /* mutant: inclusive cutoff */
-      if (!(r2 <= rc2)) continue;
-#else
-      if (!(r2 < rc2)) continue;                    /* step 1: cutoff */
-#endif
-      in_rc++;
-#if OR_MUTANT == 9 /* mutant: bonded pairs not excluded */
-      if (0) {
-#else
-      if (exclude_bonded && bonded(adj, B, i, j)) { /* step 1: not already bonded */
-#endif
-        excluded++;
-        continue;
-      }
-      uint32_t ctr[4] = {step, (uint32_t)i, (uint32_t)j, 0u}, w[4];
-      or_philox4x32_10(ctr, seed, w);
-      if (!((uint64_t)w[0] < thresh)) continue;    /* step 2: u < k dt Theta */
-      accepted++;
-      uint64_t key = ((uint64_t)w[1] << 32) | (uint64_t)(uint32_t)j;
-      if (key < best) best = key;                   /* step 5: one T per A */
-    }
-    a_choice[k] = best;
-    if (best != EMPTY) proposals++;
+    int64_t cnt[4] = {0, 0, 0, 0};
+    a_choice[k] = choose_target(n, L, x, y, z, is_t, adj, B, &R, thresh, seed, step, alist[k], cnt);
+    in_rc += cnt[0];
+    drawn += cnt[1];
+    excluded += cnt[2];
+    accepted += cnt[3];
+    if (a_choice[k] != EMPTY) proposals++;
   }
 
   /* Steps 6-7: each chosen T keeps the A with the smallest (w2, id_A). */
@@ -297,6 +322,7 @@ int or_react_step(int32_t n, float L, const float* x, const float* y, const floa
     stats[ST_A_ELIG] = na;
     stats[ST_T_ELIG] = nt;
     stats[ST_IN_RC] = in_rc;
+    stats[ST_DRAWN] = drawn;
     stats[ST_EXCLUDED] = excluded;
     stats[ST_ACCEPTED] = accepted;
     stats[ST_PROPOSALS] = proposals;
@@ -305,6 +331,53 @@ int or_react_step(int32_t n, float L, const float* x, const float* y, const floa
   }
   free(alist); free(is_t); free(a_choice); free(t_best);
   return overflow ? OR_ECAP : OR_OK;
+}
+
+/* ----------------------------------------------------------------------- */
+/* Sampled form of steps 1-7, for checks at sizes where a whole step is too  */
+/* slow: for each sampled particle ids[k], out[k] = the id of the target it  */
+/* bonds with in this step, or -1.  Its choice (steps 1-5) is computed by    */
+/* brute force; the T side (steps 6-7) by computing the choice of every      */
+/* active particle within the cutoff of that target.                          */
+/* ----------------------------------------------------------------------- */
+int or_sample_bonds(int32_t n, float L, const float* x, const float* y, const float* z,
+                    const int32_t* type, const int32_t* state, const int32_t* adj, int32_t B,
+                    int32_t type_a, int32_t a_min, int32_t a_max, int32_t d_a,
+                    int32_t type_t, int32_t t_min, int32_t t_max, int32_t d_t,
+                    float rc, double p, int32_t exclude_bonded, uint64_t seed, uint32_t step,
+                    const int64_t* ids, int64_t m, int32_t* out) {
+  or_rule R = {type_a, a_min, a_max, d_a, type_t, t_min, t_max, d_t, rc, p, exclude_bonded};
+  int err = validate(n, L, x, y, z, B, &R);
+  if (err) return err;
+  const uint64_t thresh = or_threshold(p);
+  const float halfL = 0.5f * L, rc2 = rc * rc;
+  uint8_t* is_t = (uint8_t*)malloc((size_t)(n > 0 ? n : 1));
+  if (!is_t) return OR_ENOMEM;
+  for (int64_t i = 0; i < n; ++i) is_t[i] = (uint8_t)is_target(&R, type[i], state[i]);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t k = 0; k < m; ++k) {
+    const int64_t i = ids[k];
+    int64_t cnt[4] = {0, 0, 0, 0};
+    out[k] = -1;
+    if (!is_active(&R, type[i], state[i])) continue;
+    const uint64_t key = choose_target(n, L, x, y, z, is_t, adj, B, &R, thresh, seed, step, i, cnt);
+    if (key == UINT64_MAX) continue;
+    const int64_t j = (int64_t)(key & 0xFFFFFFFFu);
+    uint64_t best = UINT64_MAX;
+    for (int64_t i2 = 0; i2 < n; ++i2) {
+      if (!is_active(&R, type[i2], state[i2])) continue;
+      if (!(dist2(x, y, z, i2, j, L, halfL) < rc2)) continue;
+      const uint64_t k2 = choose_target(n, L, x, y, z, is_t, adj, B, &R, thresh, seed, step, i2, cnt);
+      if (k2 == UINT64_MAX || (int64_t)(k2 & 0xFFFFFFFFu) != j) continue;
+      uint32_t ctr[4] = {step, (uint32_t)i2, (uint32_t)j, 0u}, w[4];
+      or_philox4x32_10(ctr, seed, w);
+      const uint64_t bid = ((uint64_t)w[2] << 32) | (uint64_t)(uint32_t)i2;
+      if (bid < best) best = bid;
+    }
+    if ((best & 0xFFFFFFFFu) == (uint64_t)(uint32_t)i) out[k] = (int32_t)j;
+  }
+  free(is_t);
+  return OR_OK;
 }
 
 /* ----------------------------------------------------------------------- */

@@ -1,0 +1,198 @@
+"""ctypes binding of ``libpolyreact.so`` (C ABI in include/polyreact.h).
+
+Argument marshalling only: every step of the reaction path runs in the HIP
+kernels of the library.  Device arrays are torch CUDA (HIP) tensors; streams
+are torch streams.  Importing this module fails loudly when the library has
+not been built -- there is no CPU fallback.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpolyreact.so")
+
+PR_OK, PR_EINVAL, PR_ERULE_AMBIGUOUS, PR_ECAP, PR_ENOMEM, PR_EHIP, PR_EBUSY, PR_ENOTFOUND = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+STATS_FIELDS = ("a_elig", "t_elig", "in_rc", "drawn", "excluded", "accepted", "proposals", "bonds",
+                "adj_overflow")
+
+
+class PrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("polyreact error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Rule(C.Structure):
+    _fields_ = [("type_a", C.c_int32), ("a_min", C.c_int32), ("a_max", C.c_int32),
+                ("d_a", C.c_int32), ("type_t", C.c_int32), ("t_min", C.c_int32),
+                ("t_max", C.c_int32), ("d_t", C.c_int32), ("rc", C.c_float),
+                ("exclude_bonded", C.c_int32), ("p", C.c_double)]
+
+    @classmethod
+    def make(cls, d=None, **kw):
+        v = dict(d or {})
+        v.update(kw)
+        return cls(**{k: v[k] for k, _ in cls._fields_})
+
+
+class Stats(C.Structure):
+    _fields_ = [(f, C.c_int64) for f in STATS_FIELDS]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f in STATS_FIELDS}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libpolyreact.so is not built (run __graft_entry__.build() or "
+                          "python paper_1409_7498_amd/csrc/build.py)")
+    lib = C.CDLL(LIB_PATH)
+    P, i32, i64, u32, u64, f32, f64, vp = (C.POINTER, C.c_int32, C.c_int64, C.c_uint32,
+                                           C.c_uint64, C.c_float, C.c_double, C.c_void_p)
+    sig = {
+        "pr_last_error": ([], C.c_char_p),
+        "pr_version": ([], C.c_char_p),
+        "pr_react_step": ([i32, f32, vp, vp, vp, vp, vp, vp, i32, P(Rule), u64, u32, vp, i32,
+                           P(i32), P(Stats), vp], C.c_int),
+        "pr_sys_create": ([P(vp), i32, f32, i32, P(Rule), u64, i64, vp], C.c_int),
+        "pr_sys_destroy": ([vp], None),
+        "pr_sys_load": ([vp, vp, vp, vp, vp, vp, vp, i32], C.c_int),
+        "pr_sys_generate": ([vp, i32, u64, f64], C.c_int),
+        "pr_sys_run": ([vp, u32, u32, f64], C.c_int),
+        "pr_sys_run_timed": ([vp, u32, u32, f64, P(f32)], C.c_int),
+        "pr_sys_read": ([vp, vp, vp, vp, vp, vp, i32], C.c_int),
+        "pr_sys_bonds": ([vp, vp, i64, P(i64)], C.c_int),
+        "pr_sys_stats": ([vp, P(Stats), i64, P(i64)], C.c_int),
+        "pr_sys_set_sort_period": ([vp, i32], C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+lib = _load()
+
+
+def exported_symbols():
+    return [n for n in ("pr_last_error", "pr_version", "pr_react_step", "pr_sys_create",
+                        "pr_sys_destroy", "pr_sys_load", "pr_sys_generate", "pr_sys_run",
+                        "pr_sys_run_timed", "pr_sys_read", "pr_sys_bonds", "pr_sys_stats",
+                        "pr_sys_set_sort_period")]
+
+
+def _check(code):
+    if code != PR_OK:
+        raise PrError(code, lib.pr_last_error().decode())
+    return code
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def react_step(x, y, z, type_, state, adj, L, rule, seed, step, bonds=None, stream=None,
+               raise_on_error=True):
+    """One reaction step on device tensors (state and adj updated in place).
+
+    Returns (code, bonds[n_b, 2] device tensor view, stats dict)."""
+    import torch
+    n = x.numel()
+    B = adj.shape[1] if adj.dim() == 2 else 1
+    for t, dt in ((x, torch.float32), (y, torch.float32), (z, torch.float32), (type_, torch.int32),
+                  (state, torch.int32), (adj, torch.int32)):
+        assert t.is_cuda and t.dtype == dt and t.is_contiguous() and t.shape[0] == n
+    cap = n // 2 + 1
+    if bonds is None:
+        bonds = torch.empty((cap, 2), dtype=torch.int32, device=x.device)
+    nb = C.c_int32(0)
+    st = Stats()
+    r = rule if isinstance(rule, Rule) else Rule.make(rule)
+    code = lib.pr_react_step(n, C.c_float(L), _ptr(x), _ptr(y), _ptr(z), _ptr(type_), _ptr(state),
+                             _ptr(adj), B, C.byref(r), C.c_uint64(seed), C.c_uint32(step),
+                             _ptr(bonds), bonds.shape[0], C.byref(nb), C.byref(st), _stream(stream))
+    if raise_on_error and code not in (PR_OK,):
+        _check(code)
+    return code, bonds[: nb.value], st.as_dict()
+
+
+class System:
+    """Resident particle system (pr_sys_* entry points)."""
+
+    def __init__(self, n, L, B, rule, seed, log_cap=0, stream=None):
+        self._h = C.c_void_p()
+        r = rule if isinstance(rule, Rule) else Rule.make(rule)
+        self.n, self.L, self.B = int(n), float(np.float32(L)), int(B)
+        _check(lib.pr_sys_create(C.byref(self._h), self.n, C.c_float(L), self.B, C.byref(r),
+                                 C.c_uint64(seed), int(log_cap), _stream(stream)))
+
+    def close(self):
+        if self._h:
+            lib.pr_sys_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load(self, cfg):
+        """Load a host configuration dict (x, y, z, type, state, adj numpy arrays)."""
+        arr = [np.ascontiguousarray(cfg[k], dtype=np.float32) for k in ("x", "y", "z")]
+        arr += [np.ascontiguousarray(cfg[k], dtype=np.int32) for k in ("type", "state", "adj")]
+        assert all(a.shape[0] == self.n for a in arr) and arr[5].shape[1] == self.B
+        ptrs = [a.ctypes.data_as(C.c_void_p) for a in arr]
+        _check(lib.pr_sys_load(self._h, *ptrs, 0))
+
+    def load_device(self, x, y, z, type_, state, adj):
+        _check(lib.pr_sys_load(self._h, _ptr(x), _ptr(y), _ptr(z), _ptr(type_), _ptr(state),
+                               _ptr(adj), 1))
+
+    def generate(self, kind, gen_seed, sigma0=0.1):
+        _check(lib.pr_sys_generate(self._h, 0 if kind == "step" else 1, C.c_uint64(gen_seed),
+                                   float(sigma0)))
+
+    def run(self, first_step, n_steps, sigma):
+        _check(lib.pr_sys_run(self._h, int(first_step), int(n_steps), float(sigma)))
+
+    def run_timed(self, first_step, n_steps, sigma):
+        ms = (C.c_float * 3)()
+        _check(lib.pr_sys_run_timed(self._h, int(first_step), int(n_steps), float(sigma), ms))
+        return {"jitter_ms": ms[0], "react_ms": ms[1], "sweep_ms": ms[2]}
+
+    def set_sort_period(self, k):
+        _check(lib.pr_sys_set_sort_period(self._h, int(k)))
+
+    def read(self):
+        n, B = self.n, self.B
+        out = dict(x=np.empty(n, np.float32), y=np.empty(n, np.float32), z=np.empty(n, np.float32),
+                   state=np.empty(n, np.int32), adj=np.empty((n, B), np.int32))
+        _check(lib.pr_sys_read(self._h, *[out[k].ctypes.data_as(C.c_void_p)
+                                           for k in ("x", "y", "z", "state", "adj")], 0))
+        return out
+
+    def bonds(self):
+        n = C.c_int64(0)
+        lib.pr_sys_bonds(self._h, None, 0, C.byref(n))
+        total = n.value
+        out = np.empty((max(total, 1), 3), np.int32)
+        _check(lib.pr_sys_bonds(self._h, out.ctypes.data_as(C.c_void_p), total, C.byref(n)))
+        return out[:total]
+
+    def stats(self):
+        n = C.c_int64(0)
+        _check(lib.pr_sys_stats(self._h, None, 0, C.byref(n)))
+        arr = (Stats * max(n.value, 1))()
+        _check(lib.pr_sys_stats(self._h, arr, n.value, C.byref(n)))
+        return [arr[k].as_dict() for k in range(n.value)]

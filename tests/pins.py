@@ -151,8 +151,8 @@ def check_acceptance_ratio(lib, p=0.3):
     acc = cand = 0
     for step in range(1, 9):
         _, _, st = one(lib, s0.copy(), step_rule(p=p), seed=5, step=step)
-        acc += st["accepted"]
-        cand += st["in_rc"] - st["excluded"]
+        acc += st["drawn"]
+        cand += st["in_rc"]
     sd = math.sqrt(p * (1 - p) / cand)
     assert abs(acc / cand - p) < 4.5 * sd, (acc / cand, p)
 
@@ -455,7 +455,8 @@ def check_chain_consumption(lib, p=0.05, steps=40):
         for step in range(1, steps + 1):
             oracle.jitter(s, seed, step, 0.05, lib=lib)
             _, _, st = one(lib, s, chain_rule(p=p), seed=seed, step=step)
-            pred += p * (st["in_rc"] - st["excluded"])
+            pred += p * st["in_rc"]
+            assert st["excluded"] == 0
         obs += m0 - int((s.state == 0).sum())
     # first-order prediction overshoots by O(p * N) (two accepted partners of
     # one A give one bond, two A's on one T give one bond)

@@ -1,0 +1,68 @@
+"""The C-ABI library loads and exports every symbol the header declares (CPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "polyreact.h")
+LIB = os.path.join(ROOT, "paper_1409_7498_amd", "libpolyreact.so")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pr_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_1409_7498_amd.csrc import build
+        build.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_entry_points():
+    names = declared()
+    for n in ("pr_react_step", "pr_sys_create", "pr_sys_run", "pr_sys_bonds", "pr_last_error"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_names_match_header():
+    from paper_1409_7498_amd import binding
+    assert set(binding.exported_symbols()) <= set(declared())
+
+
+def test_host_validation_without_gpu():
+    """Argument errors are reported before any device call."""
+    from paper_1409_7498_amd import binding as b
+    r = b.Rule.make(type_a=1, a_min=1, a_max=4, d_a=-1, type_t=0, t_min=1, t_max=2, d_t=-1,
+                    rc=1.12, exclude_bonded=1, p=0.5)
+    nb = ctypes.c_int32(0)
+    st = b.Stats()
+    L = ctypes.c_float(2.0)  # L <= 2 rc
+    code = b.lib.pr_react_step(10, L, None, None, None, None, None, None, 4, ctypes.byref(r), 1, 1,
+                               None, 5, ctypes.byref(nb), ctypes.byref(st), None)
+    assert code == b.PR_EINVAL and b"2*rc" in b.lib.pr_last_error()
+    code = b.lib.pr_react_step(10, ctypes.c_float(10.0), None, None, None, None, None, None, 4,
+                               ctypes.byref(r), 1, 1, None, 4, ctypes.byref(nb), ctypes.byref(st), None)
+    assert code == b.PR_ECAP
+    amb = b.Rule.make(type_a=0, a_min=1, a_max=3, d_a=-1, type_t=0, t_min=3, t_max=5, d_t=1,
+                      rc=1.12, exclude_bonded=1, p=0.5)
+    code = b.lib.pr_react_step(10, ctypes.c_float(10.0), None, None, None, None, None, None, 4,
+                               ctypes.byref(amb), 1, 1, None, 5, ctypes.byref(nb), ctypes.byref(st), None)
+    assert code == b.PR_ERULE_AMBIGUOUS
+    bad_p = b.Rule.make({f: getattr(r, f) for f, _ in r._fields_}, p=1.5)
+    code = b.lib.pr_react_step(10, ctypes.c_float(10.0), None, None, None, None, None, None, 4,
+                               ctypes.byref(bad_p), 1, 1, None, 5, ctypes.byref(nb), ctypes.byref(st), None)
+    assert code == b.PR_EINVAL
+    h = ctypes.c_void_p()
+    assert b.lib.pr_sys_create(ctypes.byref(h), 0, ctypes.c_float(10.0), 4, ctypes.byref(r), 1, 0,
+                               None) == b.PR_EINVAL
