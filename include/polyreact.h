@@ -138,10 +138,11 @@ int pr_sys_generate(pr_sys* s, int32_t kind, uint64_t gen_seed, double sigma0);
  * errors found on the device are reported by the next synchronising call. */
 int pr_sys_run(pr_sys* s, uint32_t first_step, uint32_t n_steps, double sigma);
 
-/* Phase timing: like pr_sys_run, but synchronises and returns in ms[0..2]
- * the summed GPU time of the jitter, the reaction step (every reaction
- * kernel) and the dominant pair-sweep kernel alone, measured with HIP events
- * on the handle's stream around each phase. */
+/* Phase timing: like pr_sys_run, but every step is launched directly (no
+ * graph) and the call synchronises; ms[0..2] receive the summed GPU time of
+ * the prep kernel (re-jitter fused with the binning of the A particles), of
+ * whole steps, and of the pair-sweep kernel alone, measured with HIP events
+ * on the handle's stream. */
 int pr_sys_run_timed(pr_sys* s, uint32_t first_step, uint32_t n_steps, double sigma, float* ms);
 
 /* Copies the current configuration out in particle-id order (host or device
@@ -151,8 +152,9 @@ int pr_sys_read(pr_sys* s, float* x, float* y, float* z, int32_t* state, int32_t
                 int32_t on_device);
 
 /* Copies the bond log out: up to cap rows of (step, id_A, id_T) int32 into
- * host memory; *n receives the total logged (PR_ECAP if it exceeded the log
- * capacity; rows beyond it were dropped).  Synchronises. */
+ * host memory, ordered by step and, within a step, by id_A; *n receives the
+ * total logged (PR_ECAP if it exceeded the log capacity; rows beyond it were
+ * dropped).  Synchronises. */
 int pr_sys_bonds(pr_sys* s, int32_t* out, int64_t cap, int64_t* n);
 
 /* Copies the per-step counters of the steps run since the last load (at most
@@ -160,8 +162,14 @@ int pr_sys_bonds(pr_sys* s, int32_t* out, int64_t cap, int64_t* n);
 int pr_sys_stats(pr_sys* s, pr_stats* out, int64_t cap, int64_t* n);
 
 /* Dense-pass tuning of a handle: sort_period = steps between spatial re-sorts
- * of the particle storage (0 = never sort; the results do not depend on it). */
+ * of the particle storage (default 64; 0 = never sort).  Results never depend
+ * on it: every selection is a minimum over keys, whatever the storage order. */
 int pr_sys_set_sort_period(pr_sys* s, int32_t sort_period);
+
+/* on = 1 (default): pr_sys_run replays blocks of steps (one sort and
+ * sort_period steps, or 32 steps without sorting) from a captured HIP graph;
+ * on = 0: every kernel is launched directly.  Results are identical. */
+int pr_sys_set_graphs(pr_sys* s, int32_t on);
 
 #ifdef __cplusplus
 }

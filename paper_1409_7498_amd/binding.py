@@ -46,6 +46,9 @@ class Stats(C.Structure):
 
 
 def _load():
+    # torch first: its HIP runtime (SONAME libamdhip64.so.7) then also serves
+    # this library, so the process holds one runtime, whatever the import order
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError("libpolyreact.so is not built (run __graft_entry__.build() or "
                           "python paper_1409_7498_amd/csrc/build.py)")
@@ -67,6 +70,7 @@ def _load():
         "pr_sys_bonds": ([vp, vp, i64, P(i64)], C.c_int),
         "pr_sys_stats": ([vp, P(Stats), i64, P(i64)], C.c_int),
         "pr_sys_set_sort_period": ([vp, i32], C.c_int),
+        "pr_sys_set_graphs": ([vp, i32], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -82,7 +86,7 @@ def exported_symbols():
     return [n for n in ("pr_last_error", "pr_version", "pr_react_step", "pr_sys_create",
                         "pr_sys_destroy", "pr_sys_load", "pr_sys_generate", "pr_sys_run",
                         "pr_sys_run_timed", "pr_sys_read", "pr_sys_bonds", "pr_sys_stats",
-                        "pr_sys_set_sort_period")]
+                        "pr_sys_set_sort_period", "pr_sys_set_graphs")]
 
 
 def _check(code):
@@ -169,10 +173,13 @@ class System:
     def run_timed(self, first_step, n_steps, sigma):
         ms = (C.c_float * 3)()
         _check(lib.pr_sys_run_timed(self._h, int(first_step), int(n_steps), float(sigma), ms))
-        return {"jitter_ms": ms[0], "react_ms": ms[1], "sweep_ms": ms[2]}
+        return {"prep_ms": ms[0], "step_ms": ms[1], "sweep_ms": ms[2]}
 
     def set_sort_period(self, k):
         _check(lib.pr_sys_set_sort_period(self._h, int(k)))
+
+    def set_graphs(self, on):
+        _check(lib.pr_sys_set_graphs(self._h, 1 if on else 0))
 
     def read(self):
         n, B = self.n, self.B

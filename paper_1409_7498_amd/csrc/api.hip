@@ -2,7 +2,9 @@
 //
 // Owns device memory (resident systems and the per-device workspace of the
 // stateless single step), validates arguments before any launch, sizes the
-// coarse A grid, and drives the per-step kernel sequence of kernels.hip.
+// coarse A grid and the bricks, and drives the per-step kernel sequence of
+// kernels.hip -- directly, or replayed from a captured HIP graph that holds a
+// whole block of steps (one spatial sort followed by sort_period steps).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -20,17 +22,17 @@
 namespace pr {
 hipError_t launch_ctl_reset(Ctl* c, uint32_t step, int full, hipStream_t s);
 hipError_t launch_classify(const Dev& d, hipStream_t s);
-hipError_t launch_jitter(const Dev& d, hipStream_t s);
+hipError_t launch_identity(const Dev& d, hipStream_t s);
 hipError_t launch_generate(const Dev& d, int kind, unsigned long long gseed, float c0, float a,
                            int nl, unsigned long long thr, hipStream_t s);
-hipError_t launch_step(const Dev& d, int abin_grid, hipStream_t s, hipEvent_t ev_sweep0,
+hipError_t launch_step(const Dev& d, int k, hipStream_t s, hipEvent_t ev_sweep0,
                        hipEvent_t ev_sweep1);
+hipError_t launch_block_end(const Dev& d, int K, hipStream_t s);
+hipError_t launch_single_end(const Dev& d, hipStream_t s);
 hipError_t launch_sort(const Dev& d, hipStream_t s);
-hipError_t launch_alist_rebuild(const Dev& d, hipStream_t s);
-hipError_t launch_identity(const Dev& d, hipStream_t s);
 hipError_t launch_gather_out(const Dev& d, float* ox, float* oy, float* oz, int32_t* ost,
                              int32_t* oadj, hipStream_t s);
-int abin_blocks(const Dev& d, long long na_hint);
+int abin_blocks(long long work);
 }  // namespace pr
 
 using namespace pr;
@@ -73,9 +75,14 @@ unsigned long long threshold(double p) {
   return (unsigned long long)t;
 }
 
+int sweep_blocks(int32_t n) { return std::max(1, (n + kThreads - 1) / kThreads); }
+
 // Coarse A grid: nc cells per side of width L/nc >= 2 rc (1 + 2^-10); the
 // margin keeps the 2x2x2 block exact under FP32 rounding of the cell index.
-void set_geometry(Dev& d, int32_t n, float L, int32_t B, const pr_rule* r, uint64_t seed) {
+// Bricks of bs^3 cells; the staged region (bs + 2 cells per side) must not
+// wrap onto itself, so bs <= nc - 2, else one brick covers the whole grid.
+void set_geometry(Dev& d, int32_t n, float L, int32_t B, const pr_rule* r, uint64_t seed,
+                  int brick_pref) {
   d.n = n;
   d.B = B;
   d.L = L;
@@ -92,11 +99,12 @@ void set_geometry(Dev& d, int32_t n, float L, int32_t B, const pr_rule* r, uint6
   d.seed = seed;
   d.rule = RuleD{r->type_a, r->a_min, r->a_max, r->d_a, r->type_t, r->t_min, r->t_max, r->d_t,
                  r->exclude_bonded};
-  d.nwg_sweep = std::max(1, (n + kSweepThreads - 1) / kSweepThreads);
+  d.nwg_sweep = sweep_blocks(n);
+  d.nwg_abin = abin_blocks(n);
   d.jit_c = 0.0f;
-  // bricks of bs^3 cells; the staged region (bs + 2 cells per side) must not
-  // wrap onto itself, so bs <= nc - 2, else one brick covers the whole grid
-  int bs = std::min<int>(kMaxBrick, (int)nc - 2);
+  d.part = nullptr;
+  d.part_cap = 0;
+  const int bs = std::min<int>(std::max(1, std::min(brick_pref, kMaxBrick)), (int)nc - 2);
   if (bs >= 1) {
     d.bs = bs;
     d.nb = (int32_t)((nc + bs - 1) / bs);
@@ -106,6 +114,8 @@ void set_geometry(Dev& d, int32_t n, float L, int32_t B, const pr_rule* r, uint6
   }
   d.nbricks = d.nb * d.nb * d.nb;
   d.sorted = 0;
+  // closing groups cover the larger of the two sweep grids (dense, bricks)
+  d.ngroups = (std::max(d.nwg_sweep, d.nbricks) + kGroup - 1) / kGroup;
 }
 
 struct Arena {
@@ -128,21 +138,26 @@ struct Arena {
 };
 
 // Scratch of one step (everything but the particle arrays and the logs).
-int alloc_scratch(Arena& a, Dev& d, int32_t n, hipStream_t s) {
+// nwg: sweep workgroups to provide for (the larger of the two sweep grids).
+int alloc_scratch(Arena& a, Dev& d, int32_t n, int32_t nwg, hipStream_t s) {
   int e;
-  if ((e = a.alloc(&d.alist[0], n)) || (e = a.alloc(&d.alist[1], n))) return e;
-  if ((e = a.alloc(&d.cnt[0], d.ncell)) || (e = a.alloc(&d.cnt[1], d.ncell))) return e;
-  if ((e = a.alloc(&d.rec, (size_t)d.ncell * kCellCap)) || (e = a.alloc(&d.ovf, n))) return e;
-  if ((e = a.alloc(&d.slotA, n)) || (e = a.alloc(&d.slotT, n))) return e;
-  if ((e = a.alloc(&d.propA, n)) || (e = a.alloc(&d.wgst, (size_t)d.nwg_sweep * kWgStats)))
+  if ((e = a.alloc(&d.alist, n)) || (e = a.alloc(&d.inlist, n)) || (e = a.alloc(&d.tflag, n)))
     return e;
-  size_t n2 = 1;
-  while (n2 < (size_t)n / 2 + 1) n2 <<= 1;
-  if ((e = a.alloc(&d.sortbuf, n2)) || (e = a.alloc(&d.ctl, 1))) return e;
+  if ((e = a.alloc(&d.cnt[0], d.ncell)) || (e = a.alloc(&d.cnt[1], d.ncell))) return e;
+  if ((e = a.alloc(&d.rec, (size_t)d.ncell * kCellCap))) return e;
+  if ((e = a.alloc(&d.slotA, n))) return e;
+  for (int p = 0; p < 2; ++p) {
+    if ((e = a.alloc(&d.ovf[p], n)) || (e = a.alloc(&d.wgp[p], (size_t)nwg * kPropCap)) ||
+        (e = a.alloc(&d.wgo[p], (size_t)nwg * kWgOut)) || (e = a.alloc(&d.povf[p], n)) ||
+        (e = a.alloc(&d.wgw[p], (size_t)nwg * kWinCap)) || (e = a.alloc(&d.wov[p], n / 2 + 1)) ||
+        (e = a.alloc(&d.abst[p], kAbinMax)))
+      return e;
+  }
+  if ((e = a.alloc(&d.ctl, 1))) return e;
   HIP_TRY(hipMemsetAsync(d.cnt[0], 0, sizeof(uint32_t) * std::max(1, d.ncell), s));
   HIP_TRY(hipMemsetAsync(d.cnt[1], 0, sizeof(uint32_t) * std::max(1, d.ncell), s));
   HIP_TRY(hipMemsetAsync(d.slotA, 0xFF, sizeof(unsigned long long) * std::max(1, n), s));
-  HIP_TRY(hipMemsetAsync(d.slotT, 0xFF, sizeof(unsigned long long) * std::max(1, n), s));
+  HIP_TRY(hipMemsetAsync(d.tflag, 0, std::max(1, n), s));
   HIP_TRY(hipMemsetAsync(d.ctl, 0, sizeof(Ctl), s));
   return PR_OK;
 }
@@ -152,12 +167,15 @@ struct Workspace {
   Arena arena;
   Dev d{};
   int32_t n = -1, ncell = -1;
-  long long* slog = nullptr;
-  Ctl* hctl = nullptr;           // pinned host copies
-  long long* hstats = nullptr;
+  int32_t* part = nullptr;
+  int32_t ngroups = 0;
+  int32_t* log = nullptr;
+  unsigned long long* sortbuf = nullptr;
+  Ctl* hctl = nullptr;  // pinned host copies
+  int32_t* hpart = nullptr;
   ~Workspace() {
     if (hctl) (void)hipHostFree(hctl);
-    if (hstats) (void)hipHostFree(hstats);
+    if (hpart) (void)hipHostFree(hpart);
   }
 };
 
@@ -173,7 +191,7 @@ extern "C" {
 
 const char* pr_last_error(void) { return g_err.c_str(); }
 
-const char* pr_version(void) { return "polyreact 0.1 (gfx950)"; }
+const char* pr_version(void) { return "polyreact 0.2 (gfx950)"; }
 
 int pr_react_step(int32_t n, float L, const float* x, const float* y, const float* z,
                   const int32_t* type, int32_t* state, int32_t* adj, int32_t B,
@@ -196,26 +214,31 @@ int pr_react_step(int32_t n, float L, const float* x, const float* y, const floa
   if ((int)g_ws.size() <= dev) g_ws.resize(dev + 1, nullptr);
   Workspace*& ws = g_ws[dev];
   Dev geo{};
-  set_geometry(geo, n, L, B, rule, seed);
+  set_geometry(geo, n, L, B, rule, seed, kMaxBrick);
   if (!ws || ws->n < n || ws->ncell < geo.ncell) {
     delete ws;
     ws = new Workspace();
     ws->d = geo;
     const int32_t n_alloc = std::max(n, 1024);
-    ws->d.nwg_sweep = (n_alloc + kSweepThreads - 1) / kSweepThreads;
-    if ((e = alloc_scratch(ws->arena, ws->d, n_alloc, s))) {
+    if ((e = alloc_scratch(ws->arena, ws->d, n_alloc, sweep_blocks(n_alloc), s))) {
       delete ws;
       ws = nullptr;
       return e;
     }
-    if ((e = ws->arena.alloc(&ws->slog, kStatsPerStep))) return e;
+    size_t n2 = 1;
+    while (n2 < (size_t)n_alloc / 2 + 1) n2 <<= 1;
+    ws->ngroups = (sweep_blocks(n_alloc) + kGroup - 1) / kGroup;
+    if ((e = ws->arena.alloc(&ws->part, (size_t)ws->ngroups * kPart)) ||
+        (e = ws->arena.alloc(&ws->log, 3 * ((size_t)n_alloc / 2 + 1))) ||
+        (e = ws->arena.alloc(&ws->sortbuf, n2)))
+      return e;
     HIP_TRY(hipHostMalloc((void**)&ws->hctl, sizeof(Ctl)));
-    HIP_TRY(hipHostMalloc((void**)&ws->hstats, sizeof(long long) * kStatsPerStep));
-    ws->n = std::max(n, 1024);
+    HIP_TRY(hipHostMalloc((void**)&ws->hpart, sizeof(int32_t) * ws->ngroups * kPart));
+    ws->n = n_alloc;
     ws->ncell = geo.ncell;
   }
   Dev d = ws->d;  // scratch pointers
-  // geometry of this call (the A grid may be smaller than the allocation)
+  // geometry of this call (the allocation may be larger)
   d.n = geo.n;
   d.B = geo.B;
   d.L = geo.L;
@@ -228,19 +251,24 @@ int pr_react_step(int32_t n, float L, const float* x, const float* y, const floa
   d.seed = geo.seed;
   d.rule = geo.rule;
   d.nwg_sweep = geo.nwg_sweep;
-  d.x = const_cast<float*>(x);
-  d.y = const_cast<float*>(y);
-  d.z = const_cast<float*>(z);
-  d.typ = const_cast<int32_t*>(type);
-  d.st = state;
-  d.adj = adj;
-  d.id = d.slot_of = nullptr;
+  d.nwg_abin = geo.nwg_abin;
+  d.nwg_jit = 0;
+  d.jitter = 0;
+  d.sorted = 0;
+  float* cx = const_cast<float*>(x);
+  float* cy = const_cast<float*>(y);
+  float* cz = const_cast<float*>(z);
+  const Arr caller{{cx, cx}, {cy, cy}, {cz, cz}, const_cast<int32_t*>(type), state, adj, nullptr};
+  d.set[0] = d.set[1] = caller;
+  d.slot_of = nullptr;
   d.bonds = bonds;
   d.bonds_cap = cap;
-  d.log = nullptr;
-  d.log_cap = 0;
-  d.slog = ws->slog;
-  d.slog_cap = 1;
+  d.log = ws->log;
+  d.log_cap = (int64_t)ws->n / 2 + 1;
+  d.sortbuf = ws->sortbuf;
+  d.part = ws->part;
+  d.part_cap = 1;
+  d.ngroups = (d.nwg_sweep + kGroup - 1) / kGroup;
   // The workspace serves calls of any box size: a previous call may have left
   // counts in cells beyond this call's grid, so both count buffers are cleared
   // over their whole allocation (each step only clears the cells it uses).
@@ -248,17 +276,21 @@ int pr_react_step(int32_t n, float L, const float* x, const float* y, const floa
   HIP_TRY(hipMemsetAsync(d.cnt[1], 0, sizeof(uint32_t) * (size_t)ws->ncell, s));
   HIP_TRY(launch_ctl_reset(d.ctl, step, 1, s));
   HIP_TRY(launch_classify(d, s));
-  HIP_TRY(launch_step(d, abin_blocks(d, n / 8), s, nullptr, nullptr));
+  HIP_TRY(launch_step(d, 0, s, nullptr, nullptr));
+  HIP_TRY(launch_single_end(d, s));
   HIP_TRY(hipMemcpyAsync(ws->hctl, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(ws->hstats, ws->slog, sizeof(long long) * kStatsPerStep,
+  HIP_TRY(hipMemcpyAsync(ws->hpart, ws->part, sizeof(int32_t) * d.ngroups * kPart,
                          hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   const Ctl c = *ws->hctl;
   if (c.err) return fail(c.err, "invalid particle position (NaN or outside [0, L))");
-  *n_bonds = (int32_t)c.nwin;
-  const long long* h = ws->hstats;
-  if (st) *st = pr_stats{h[0], h[1], h[2], h[3], h[4], h[5], h[6], h[7], h[8]};
-  if (h[8] > 0) return fail(PR_ECAP, "%lld adjacency appends found a full row", h[8]);
+  *n_bonds = (int32_t)c.log_n;
+  long long h[kPart] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int g = 0; g < d.ngroups; ++g)
+    for (int q = 0; q < kPart; ++q) h[q] += ws->hpart[g * kPart + q];
+  // partial layout: a_elig, t_elig, in_rc, drawn, excluded, proposals, bonds, lost
+  if (st) *st = pr_stats{h[0], h[1], h[2], h[3], h[4], h[3] - h[4], h[5], h[6], h[7]};
+  if (h[7] > 0) return fail(PR_ECAP, "%lld adjacency appends found a full row", h[7]);
   return PR_OK;
 }
 
@@ -269,22 +301,30 @@ int pr_react_step(int32_t n, float L, const float* x, const float* y, const floa
 // ===========================================================================
 struct pr_sys {
   int dev = 0;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;   // the caller's stream: every launch goes here
+  hipStream_t cap = nullptr;      // private stream, used only to capture graphs
   Arena arena;
   Dev d{};
   pr_rule rule{};
   int64_t log_cap = 0;
-  int64_t slog_cap = 0;
+  int64_t part_cap = 0;
   int64_t steps_since_load = 0;
-  long long na_hint = 0;
+  int64_t steps_since_sort = 0;
   bool loaded = false;
   bool poisoned = false;
   int32_t sort_period = 0;
-  int64_t steps_since_sort = 0;
+  int32_t use_graphs = 1;
+  // captured block: one sort (when sort_period > 0) and block_steps steps
+  hipGraphExec_t gexec = nullptr;
+  int32_t g_steps = 0;
+  float g_jit = -1.0f;
+  long long g_part = 0;
   float *rx = nullptr, *ry = nullptr, *rz = nullptr;  // id-order read buffers
   int32_t *rst = nullptr, *radj = nullptr;
   Ctl* hctl = nullptr;
   ~pr_sys() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (cap) (void)hipStreamDestroy(cap);
     if (hctl) (void)hipHostFree(hctl);
   }
 };
@@ -304,28 +344,47 @@ int sync_ctl(pr_sys* s) {
   return PR_OK;
 }
 
-int grow_slog(pr_sys* s, int64_t need) {
-  if (need <= s->slog_cap) return PR_OK;
-  int64_t cap = std::max<int64_t>(need, 2 * s->slog_cap);
-  long long* nb = nullptr;
-  int e = s->arena.alloc(&nb, (size_t)cap * kStatsPerStep);
+void drop_graph(pr_sys* s) {
+  if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+  s->gexec = nullptr;
+}
+
+// The partial-counter log holds `need` steps (grown by doubling; a copy keeps
+// the steps already logged).
+int grow_part(pr_sys* s, int64_t need) {
+  if (need <= s->part_cap) return PR_OK;
+  const int64_t cap = std::max<int64_t>(need, 2 * s->part_cap);
+  const size_t row = (size_t)s->d.ngroups * kPart;
+  int32_t* nb = nullptr;
+  int e = s->arena.alloc(&nb, (size_t)cap * row);
   if (e) return e;
-  if (s->d.slog && s->slog_cap > 0)
-    HIP_TRY(hipMemcpyAsync(nb, s->d.slog, sizeof(long long) * kStatsPerStep * s->slog_cap,
+  if (s->d.part && s->part_cap > 0)
+    HIP_TRY(hipMemcpyAsync(nb, s->d.part, sizeof(int32_t) * row * s->part_cap,
                            hipMemcpyDeviceToDevice, s->stream));
-  s->d.slog = nb;  // the old block stays in the arena until destroy
-  s->slog_cap = cap;
-  s->d.slog_cap = cap;
+  s->d.part = nb;  // the old block stays in the arena until destroy
+  s->part_cap = cap;
+  s->d.part_cap = cap;
+  drop_graph(s);  // the captured kernels hold the old pointer
   return PR_OK;
+}
+
+// Dense mode until the first sort: every particle is an A candidate of k_abin.
+void set_dense(pr_sys* s) {
+  s->d.sorted = 0;
+  s->d.nwg_sweep = sweep_blocks(s->d.n);
+  s->d.nwg_abin = abin_blocks(s->d.n);
 }
 
 int after_load(pr_sys* s) {
   hipStream_t st = s->stream;
-  s->d.sorted = 0;
-  s->d.nwg_sweep = std::max(1, (s->d.n + kSweepThreads - 1) / kSweepThreads);
+  set_dense(s);
+  drop_graph(s);
   s->steps_since_sort = 0;
-  HIP_TRY(launch_identity(s->d, st));
+  // parity 0 after the reset: both cell-count buffers start cleared
+  HIP_TRY(hipMemsetAsync(s->d.cnt[0], 0, sizeof(uint32_t) * (size_t)s->d.ncell, st));
+  HIP_TRY(hipMemsetAsync(s->d.cnt[1], 0, sizeof(uint32_t) * (size_t)s->d.ncell, st));
   HIP_TRY(launch_ctl_reset(s->d.ctl, 0, 1, st));
+  HIP_TRY(launch_identity(s->d, st));
   HIP_TRY(launch_classify(s->d, st));
   int e = sync_ctl(s);
   if (e) return e;
@@ -334,8 +393,64 @@ int after_load(pr_sys* s) {
     s->loaded = false;
     return fail(s->hctl->err, "invalid particle position (NaN or outside [0, L))");
   }
-  s->na_hint = s->hctl->na[0];
   s->loaded = true;
+  return PR_OK;
+}
+
+int list_abin_blocks(const Dev& d) { return abin_blocks(std::max<long long>(4096, d.n / 8)); }
+
+// Counting sort of the storage by brick (writes the other storage set and
+// rebuilds the A list); afterwards the sweep runs per brick.
+int sort_storage(pr_sys* s, hipStream_t st) {
+  HIP_TRY(launch_sort(s->d, st));
+  s->d.sorted = 1;
+  s->d.nwg_sweep = s->d.nbricks;
+  s->d.nwg_abin = list_abin_blocks(s->d);  // list mode: the grid covers the A list
+  s->steps_since_sort = 0;
+  return PR_OK;
+}
+
+// A block of K steps on st: a sort first when due, K steps, the block end.
+// ev (timed runs, K == 1): events before the prep, before and after the sweep.
+int run_block(pr_sys* s, hipStream_t st, int32_t K, hipEvent_t* ev) {
+  int e;
+  if (s->sort_period > 0 && (!s->d.sorted || s->steps_since_sort >= s->sort_period))
+    if ((e = sort_storage(s, st))) return e;
+  if (ev) HIP_TRY(hipEventRecord(ev[0], st));
+  for (int32_t k = 0; k < K; ++k)
+    HIP_TRY(launch_step(s->d, k, st, ev ? ev[1] : nullptr, ev ? ev[2] : nullptr));
+  HIP_TRY(launch_block_end(s->d, K, st));
+  s->steps_since_sort += K;
+  return PR_OK;
+}
+
+// Captures one block into a graph on the private stream.
+int capture_block(pr_sys* s, int32_t K) {
+  drop_graph(s);
+  hipGraph_t g = nullptr;
+  HIP_TRY(hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal));
+  const Dev saved_d = s->d;
+  const int64_t saved_since = s->steps_since_sort;
+  const int e = run_block(s, s->cap, K, nullptr);
+  const hipError_t ce = hipStreamEndCapture(s->cap, &g);
+  // capturing executes nothing: the host-side state moves only when the
+  // graph is launched (see run_impl)
+  s->d = saved_d;
+  s->steps_since_sort = saved_since;
+  if (e) {
+    if (g) (void)hipGraphDestroy(g);
+    return e;
+  }
+  if (ce != hipSuccess) return fail(PR_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(ce));
+  const hipError_t ie = hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ie != hipSuccess) {
+    s->gexec = nullptr;
+    return fail(PR_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+  }
+  s->g_steps = K;
+  s->g_jit = s->d.jit_c;
+  s->g_part = (long long)(size_t)s->d.part;
   return PR_OK;
 }
 
@@ -353,41 +468,40 @@ int pr_sys_create(pr_sys** out, int32_t n, float L, int32_t B, const pr_rule* ru
   pr_sys* s = new pr_sys();
   s->stream = (hipStream_t)stream;
   s->rule = *rule;
-  if (hipGetDevice(&s->dev) != hipSuccess) {
+  if (hipGetDevice(&s->dev) != hipSuccess || hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking) != hipSuccess) {
     delete s;
-    return fail(PR_EHIP, "hipGetDevice failed");
+    return fail(PR_EHIP, "hipGetDevice/hipStreamCreate failed");
   }
   Dev& d = s->d;
-  set_geometry(d, n, L, B, rule, seed);
+  set_geometry(d, n, L, B, rule, seed, kMaxBrick);
   s->log_cap = log_cap > 0 ? log_cap : n;
-  e = alloc_scratch(s->arena, d, n, s->stream);
-  if (!e) e = s->arena.alloc(&d.x, n);
-  if (!e) e = s->arena.alloc(&d.y, n);
-  if (!e) e = s->arena.alloc(&d.z, n);
-  if (!e) e = s->arena.alloc(&d.typ, n);
-  if (!e) e = s->arena.alloc(&d.st, n);
-  if (!e) e = s->arena.alloc(&d.adj, (size_t)n * B);
-  if (!e) e = s->arena.alloc(&d.log, (size_t)s->log_cap * 3);
-  if (!e) e = s->arena.alloc(&d.id, n);
-  if (!e) e = s->arena.alloc(&d.slot_of, n);
-  if (!e) e = s->arena.alloc(&d.bstart, (size_t)d.nbricks + 1);
-  if (!e) e = s->arena.alloc(&d.bcnt, (size_t)d.nbricks);
-  if (!e) e = s->arena.alloc(&d.rank, n);
-  if (!e) e = s->arena.alloc(&d.x2, n);
-  if (!e) e = s->arena.alloc(&d.y2, n);
-  if (!e) e = s->arena.alloc(&d.z2, n);
-  if (!e) e = s->arena.alloc(&d.typ2, n);
-  if (!e) e = s->arena.alloc(&d.st2, n);
-  if (!e) e = s->arena.alloc(&d.id2, n);
-  if (!e) e = s->arena.alloc(&d.adj2, (size_t)n * B);
-  if (!e && d.nbricks > d.nwg_sweep) {
-    // sweep counters for the brick grid as well
-    e = s->arena.alloc(&d.wgst, (size_t)d.nbricks * kWgStats);
+  e = alloc_scratch(s->arena, d, n, std::max(sweep_blocks(n), d.nbricks), s->stream);
+  for (int q = 0; q < 2 && !e; ++q) {
+    Arr& a = d.set[q];
+    for (int p = 0; p < 2 && !e; ++p) {
+      if (!e) e = s->arena.alloc(&a.x[p], n);
+      if (!e) e = s->arena.alloc(&a.y[p], n);
+      if (!e) e = s->arena.alloc(&a.z[p], n);
+    }
+    if (!e) e = s->arena.alloc(&a.typ, n);
+    if (!e) e = s->arena.alloc(&a.st, n);
+    if (!e) e = s->arena.alloc(&a.id, n);
+    if (!e) e = s->arena.alloc(&a.adj, (size_t)n * B);
   }
-  if (!e && hipMemsetAsync(d.bcnt, 0, sizeof(uint32_t) * d.nbricks, s->stream) != hipSuccess)
+  if (!e) e = s->arena.alloc(&d.slot_of, n);
+  if (!e) e = s->arena.alloc(&d.log, (size_t)s->log_cap * 3);
+  if (!e) e = s->arena.alloc(&d.bstart, (size_t)d.nbricks + 1);
+  if (!e) e = s->arena.alloc(&d.astart, (size_t)d.nbricks + 1);
+  if (!e) e = s->arena.alloc(&d.bcnt, (size_t)d.nbricks);
+  if (!e) e = s->arena.alloc(&d.bacnt, (size_t)d.nbricks);
+  if (!e) e = s->arena.alloc(&d.rank, n);
+  if (!e) e = s->arena.alloc(&d.arank, n);
+  if (!e && (hipMemsetAsync(d.bcnt, 0, sizeof(uint32_t) * d.nbricks, s->stream) != hipSuccess ||
+             hipMemsetAsync(d.bacnt, 0, sizeof(uint32_t) * d.nbricks, s->stream) != hipSuccess))
     e = fail(PR_EHIP, "hipMemsetAsync failed");
   if (!e && hipHostMalloc((void**)&s->hctl, sizeof(Ctl)) != hipSuccess)
     e = fail(PR_ENOMEM, "hipHostMalloc failed");
+  if (!e) e = grow_part(s, 1024);
   if (e) {
     delete s;
     return e;
@@ -395,11 +509,11 @@ int pr_sys_create(pr_sys** out, int32_t n, float L, int32_t B, const pr_rule* ru
   d.bonds = nullptr;
   d.bonds_cap = 0;
   d.log_cap = s->log_cap;
+  d.sortbuf = nullptr;
+  d.jitter = 1;
+  d.nwg_jit = sweep_blocks(n);
   s->sort_period = 64;
-  if ((e = grow_slog(s, 1024))) {
-    delete s;
-    return e;
-  }
+  set_dense(s);
   *out = s;
   return PR_OK;
 }
@@ -415,15 +529,15 @@ int pr_sys_load(pr_sys* s, const float* x, const float* y, const float* z, const
   int e = check_sys(s, false);
   if (e) return e;
   if (!x || !y || !z || !type || !state || !adj) return fail(PR_EINVAL, "NULL array");
-  const Dev& d = s->d;
+  const Arr& a = s->d.set[0];
   const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-  const size_t n = (size_t)d.n;
-  HIP_TRY(hipMemcpyAsync(d.x, x, n * 4, k, s->stream));
-  HIP_TRY(hipMemcpyAsync(d.y, y, n * 4, k, s->stream));
-  HIP_TRY(hipMemcpyAsync(d.z, z, n * 4, k, s->stream));
-  HIP_TRY(hipMemcpyAsync(d.typ, type, n * 4, k, s->stream));
-  HIP_TRY(hipMemcpyAsync(d.st, state, n * 4, k, s->stream));
-  HIP_TRY(hipMemcpyAsync(d.adj, adj, n * 4 * d.B, k, s->stream));
+  const size_t n = (size_t)s->d.n;
+  HIP_TRY(hipMemcpyAsync(a.x[0], x, n * 4, k, s->stream));
+  HIP_TRY(hipMemcpyAsync(a.y[0], y, n * 4, k, s->stream));
+  HIP_TRY(hipMemcpyAsync(a.z[0], z, n * 4, k, s->stream));
+  HIP_TRY(hipMemcpyAsync(a.typ, type, n * 4, k, s->stream));
+  HIP_TRY(hipMemcpyAsync(a.st, state, n * 4, k, s->stream));
+  HIP_TRY(hipMemcpyAsync(a.adj, adj, n * 4 * s->d.B, k, s->stream));
   return after_load(s);
 }
 
@@ -448,24 +562,7 @@ int pr_sys_set_sort_period(pr_sys* s, int32_t sort_period) {
   if (e) return e;
   if (sort_period < 0) return fail(PR_EINVAL, "sort_period < 0");
   s->sort_period = sort_period;
-  return PR_OK;
-}
-
-// Counting sort of the storage by brick, then the A list in the new order.
-static int sort_storage(pr_sys* s) {
-  Dev& d = s->d;
-  HIP_TRY(launch_sort(d, s->stream));
-  std::swap(d.x, d.x2);
-  std::swap(d.y, d.y2);
-  std::swap(d.z, d.z2);
-  std::swap(d.typ, d.typ2);
-  std::swap(d.st, d.st2);
-  std::swap(d.adj, d.adj2);
-  std::swap(d.id, d.id2);
-  d.sorted = 1;
-  d.nwg_sweep = d.nbricks;
-  HIP_TRY(launch_alist_rebuild(d, s->stream));
-  s->steps_since_sort = 0;
+  drop_graph(s);
   return PR_OK;
 }
 
@@ -474,50 +571,62 @@ static int run_impl(pr_sys* s, uint32_t first_step, uint32_t n_steps, double sig
   if (e) return e;
   if (!(sigma >= 0.0) || sigma * 6.0 >= (double)s->d.L * 0.5)
     return fail(PR_EINVAL, "sigma=%g", sigma);
-  if ((e = grow_slog(s, s->steps_since_load + n_steps))) return e;
+  if ((e = grow_part(s, s->steps_since_load + n_steps))) return e;
   s->d.jit_c = (float)(sigma / 256.0);
-  const int abin_grid = abin_blocks(s->d, s->na_hint);
   hipStream_t st = s->stream;
   HIP_TRY(launch_ctl_reset(s->d.ctl, first_step, 0, st));
-  std::vector<hipEvent_t> ev;
   if (ms) {
-    ev.resize((size_t)n_steps * 4);
+    // phase timing: one-step blocks launched directly, HIP events around the
+    // prep (jitter + A binning), the sweep and the whole step
+    std::vector<hipEvent_t> ev((size_t)n_steps * 3 + 1);
     for (auto& v : ev) HIP_TRY(hipEventCreate(&v));
-  }
-  for (uint32_t k = 0; k < n_steps; ++k) {
-    if (s->sort_period > 0 && (!s->d.sorted || s->steps_since_sort >= s->sort_period))
-      if ((e = sort_storage(s))) return e;
-    s->steps_since_sort++;
-    const Dev& d = s->d;
-    if (ms) HIP_TRY(hipEventRecord(ev[4 * k], st));
-    if (sigma > 0.0) HIP_TRY(launch_jitter(d, st));
-    if (ms) HIP_TRY(hipEventRecord(ev[4 * k + 1], st));
-    HIP_TRY(launch_step(d, abin_grid, st, ms ? ev[4 * k + 2] : nullptr,
-                        ms ? ev[4 * k + 3] : nullptr));
-  }
-  s->steps_since_load += n_steps;
-  if (ms) {
-    hipEvent_t end;
-    HIP_TRY(hipEventCreate(&end));
-    HIP_TRY(hipEventRecord(end, st));
-    HIP_TRY(hipEventSynchronize(end));
-    float tj = 0, tr = 0, tsw = 0;
+    for (uint32_t k = 0; k < n_steps; ++k)
+      if ((e = run_block(s, st, 1, &ev[3 * k]))) return e;
+    HIP_TRY(hipEventRecord(ev[3 * n_steps], st));
+    HIP_TRY(hipEventSynchronize(ev[3 * n_steps]));
+    float tp = 0, tstep = 0, tsw = 0;
     for (uint32_t k = 0; k < n_steps; ++k) {
       float a = 0, b = 0, c = 0;
-      hipEvent_t stop = (k + 1 < n_steps) ? ev[4 * (k + 1)] : end;
-      HIP_TRY(hipEventElapsedTime(&a, ev[4 * k], ev[4 * k + 1]));
-      HIP_TRY(hipEventElapsedTime(&b, ev[4 * k + 1], stop));
-      HIP_TRY(hipEventElapsedTime(&c, ev[4 * k + 2], ev[4 * k + 3]));
-      tj += a;
-      tr += b;
-      tsw += c;
+      HIP_TRY(hipEventElapsedTime(&a, ev[3 * k], ev[3 * k + 1]));
+      HIP_TRY(hipEventElapsedTime(&b, ev[3 * k + 1], ev[3 * k + 2]));
+      HIP_TRY(hipEventElapsedTime(&c, ev[3 * k], ev[3 * (k + 1)]));
+      tp += a;
+      tsw += b;
+      tstep += c;
     }
-    ms[0] = tj;
-    ms[1] = tr;
+    ms[0] = tp;
+    ms[1] = tstep;
     ms[2] = tsw;
     for (auto& v : ev) (void)hipEventDestroy(v);
-    (void)hipEventDestroy(end);
+    s->steps_since_load += n_steps;
+    return PR_OK;
   }
+  const int32_t block = s->sort_period > 0 ? s->sort_period : 32;
+  uint32_t left = n_steps;
+  while (left > 0) {
+    const bool aligned =
+        s->sort_period == 0 || !s->d.sorted || s->steps_since_sort >= s->sort_period;
+    if (s->use_graphs && aligned && left >= (uint32_t)block) {
+      if (!s->gexec || s->g_steps != block || s->g_jit != s->d.jit_c ||
+          s->g_part != (long long)(size_t)s->d.part)
+        if ((e = capture_block(s, block))) return e;
+      HIP_TRY(hipGraphLaunch(s->gexec, st));
+      // the host-side state the block leaves behind
+      if (s->sort_period > 0) {
+        s->d.sorted = 1;
+        s->d.nwg_sweep = s->d.nbricks;
+        s->d.nwg_abin = list_abin_blocks(s->d);
+        s->steps_since_sort = block;
+      } else {
+        s->steps_since_sort += block;
+      }
+      left -= (uint32_t)block;
+    } else {
+      if ((e = run_block(s, st, 1, nullptr))) return e;
+      left -= 1;
+    }
+  }
+  s->steps_since_load += n_steps;
   return PR_OK;
 }
 
@@ -567,10 +676,23 @@ int pr_sys_bonds(pr_sys* s, int32_t* out, int64_t cap, int64_t* n) {
   const int64_t total = (int64_t)s->hctl->log_n;
   const int64_t have = std::min<int64_t>(total, s->log_cap);
   const int64_t m = std::min<int64_t>(have, cap);
-  if (m > 0) HIP_TRY(hipMemcpy(out, s->d.log, (size_t)m * 12, hipMemcpyDeviceToHost));
+  if (m > 0) {
+    // rows of one step were appended in workgroup order: order them by
+    // (step, id_A) -- steps are already in order, id_A is unique in a step
+    struct Row {
+      int32_t step, a, t;
+    };
+    std::vector<Row> rows((size_t)have);
+    HIP_TRY(hipMemcpy(rows.data(), s->d.log, (size_t)have * sizeof(Row), hipMemcpyDeviceToHost));
+    std::sort(rows.begin(), rows.end(), [](const Row& u, const Row& v) {
+      return u.step != v.step ? u.step < v.step : u.a < v.a;
+    });
+    std::memcpy(out, rows.data(), (size_t)m * sizeof(Row));
+  }
   *n = total;
-  if (total > s->log_cap) return fail(PR_ECAP, "bond log overflowed: %lld > %lld", (long long)total,
-                                      (long long)s->log_cap);
+  if (total > s->log_cap)
+    return fail(PR_ECAP, "bond log overflowed: %lld > %lld", (long long)total,
+                (long long)s->log_cap);
   return PR_OK;
 }
 
@@ -579,11 +701,29 @@ int pr_sys_stats(pr_sys* s, pr_stats* out, int64_t cap, int64_t* n) {
   if (e) return e;
   if (!n || (cap > 0 && !out)) return fail(PR_EINVAL, "NULL output");
   if ((e = sync_ctl(s))) return e;
-  const int64_t have = std::min<int64_t>((int64_t)s->hctl->stats_n, s->slog_cap);
+  const int64_t have = std::min<int64_t>((int64_t)s->hctl->stats_n0, s->part_cap);
   const int64_t m = std::min<int64_t>(have, cap);
-  if (m > 0)
-    HIP_TRY(hipMemcpy(out, s->d.slog, (size_t)m * sizeof(pr_stats), hipMemcpyDeviceToHost));
+  if (m > 0) {
+    const size_t row = (size_t)s->d.ngroups * kPart;
+    std::vector<int32_t> p((size_t)m * row);
+    HIP_TRY(hipMemcpy(p.data(), s->d.part, p.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    for (int64_t k = 0; k < m; ++k) {
+      long long h[kPart] = {0, 0, 0, 0, 0, 0, 0, 0};
+      for (int g = 0; g < s->d.ngroups; ++g)
+        for (int q = 0; q < kPart; ++q) h[q] += p[(size_t)k * row + (size_t)g * kPart + q];
+      // partial layout: a_elig, t_elig, in_rc, drawn, excluded, proposals, bonds, lost
+      out[k] = pr_stats{h[0], h[1], h[2], h[3], h[4], h[3] - h[4], h[5], h[6], h[7]};
+    }
+  }
   *n = have;
+  return PR_OK;
+}
+
+int pr_sys_set_graphs(pr_sys* s, int32_t on) {
+  int e = check_sys(s, false);
+  if (e) return e;
+  s->use_graphs = on ? 1 : 0;
+  drop_graph(s);
   return PR_OK;
 }
 

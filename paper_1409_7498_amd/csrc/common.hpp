@@ -13,31 +13,40 @@ namespace pr {
 // bucket; records beyond that go to an overflow list every sweep also scans.
 constexpr int kCellCap = 8;
 constexpr unsigned long long kEmpty = ~0ull;
-constexpr int kTailThreads = 1024;  // one workgroup resolves and applies
-constexpr int kSortLds = 4096;      // bonds per step sorted in LDS (else in HBM)
-constexpr int kSweepThreads = 256;
+constexpr int kThreads = 256;       // workgroup size of the per-particle kernels
+constexpr int kFinThreads = 1024;   // the single-workgroup finishing kernels
+constexpr int kSortLds = 4096;      // bonds of a stateless step sorted in LDS up to this
 constexpr int kStatsPerStep = 9;    // pr_stats fields
-constexpr int kWgStats = 4;         // per sweep workgroup: t_elig, in_rc, drawn, excluded
+constexpr int kGroup = 256;         // sweep workgroups closed by one closing workgroup
+constexpr int kPart = 8;            // partial counters per closing workgroup and step
+constexpr int kWgOut = 8;           // per sweep workgroup counters (see WgOut)
+constexpr int kPropCap = 32;        // first-touched A's a sweep workgroup keeps in place
+constexpr int kWinCap = 16;         // bonds a resolve workgroup stages in place
+constexpr int kAbinMax = 2048;      // A-bin workgroups at most (grid-stride beyond)
 // Spatially sorted storage: particles are kept ordered by "brick" (a block of
 // bs^3 coarse cells); one sweep workgroup owns a brick and stages the A
 // records of the brick plus one halo cell layer in LDS.
 constexpr int kMaxBrick = 4;
 constexpr int kStageCells = (kMaxBrick + 2) * (kMaxBrick + 2) * (kMaxBrick + 2);
-constexpr int kStageRecs = 1024;
+constexpr int kStageRecs = 512;
+constexpr int kQueue = 1024;        // in-range pairs queued per chunk of kThreads particles
 
-// Device control block: every count whose value is data dependent lives here,
-// so a step needs no host round trip and a captured graph can replay it.
+enum WgOut { kOutTElig = 0, kOutInRc, kOutDrawn, kOutExcl, kOutProp, kOutBonds, kOutLost };
+
+// Device control block.  Steps are launched in blocks of K steps; the kernels
+// of step k of a block use step0 + k and parity (par0 + k) & 1, so a captured
+// graph of a block can be replayed: its last kernel advances step0 and par0.
 struct Ctl {
-  uint32_t step;      // current reaction step (draw counter word 0)
-  int32_t err;        // first device-detected error (0 = none)
-  uint32_t par;       // buffer parity of this step (flips every step)
-  uint32_t pad0;
-  uint32_t na[2];     // A-list lengths, indexed by parity
-  uint32_t ovf_n;     // A records beyond their cell bucket this step
-  uint32_t nprop;     // A's with a retained candidate this step
-  uint32_t nwin;      // bonds created by the last step
-  uint32_t stats_n;   // records in the per-step counter log
-  uint64_t log_n;     // rows appended to the bond log (may exceed capacity)
+  uint32_t step0;      // reaction step of the block's first step (draw counter word 0)
+  uint32_t par0;       // parity of the block's first step (buffers used per step)
+  int32_t err;         // first device-detected error (0 = none)
+  uint32_t set;        // which of the two storage sets holds the particles
+  uint32_t na;         // A-list length (entries may have left the A window)
+  uint32_t ovf_n[2];   // A records beyond their cell bucket, by parity
+  uint32_t nprop_ovf[2];  // first-touched A's beyond kPropCap, by parity
+  uint32_t nwin_ovf[2];   // bonds beyond kWinCap, by parity
+  uint32_t stats_n0;   // counter-log index of the block's first step
+  uint64_t log_n;      // rows appended to the bond log (may exceed capacity)
 };
 
 struct RuleD {
@@ -46,39 +55,49 @@ struct RuleD {
   int32_t exclude;
 };
 
+// Particle arrays of one storage set, slot order.  Positions have two
+// buffers: a step reads parity p and writes the jittered positions to p ^ 1.
+struct Arr {
+  float *x[2], *y[2], *z[2];
+  int32_t *typ, *st, *adj, *id;  // id == nullptr: slot == id
+};
+
 // Everything a kernel needs, passed by value as the kernel argument.
 struct Dev {
-  // particle storage, slot order (slot == id unless id/slot_of are set)
-  float *x, *y, *z;
-  int32_t *typ, *st, *adj;
-  int32_t *id, *slot_of;
-  // A list (slots), by parity
-  int32_t* alist[2];
+  Arr set[2];           // storage sets (the sort writes the other one)
+  int32_t* slot_of;     // id -> slot (nullptr: identity)
+  int32_t* alist;       // slots of particles in the A window (capacity n)
+  uint8_t* inlist;      // per slot: has an entry in the A list (live or not)
   // A grid: per-cell counts by parity, bucket records, overflow records
   uint32_t* cnt[2];
-  float4 *rec, *ovf;
-  // selection: per-id minimum keys of the A side and the T side
-  unsigned long long *slotA, *slotT;
-  int32_t* propA;       // ids of A's with a retained candidate
-  // spatial sort: brick offsets of the storage, counters, ranks, second buffers
-  int32_t* bstart;      // nbricks + 1 slot offsets (valid when sorted)
-  uint32_t* bcnt;
-  int32_t* rank;
-  float *x2, *y2, *z2;
-  int32_t *typ2, *st2, *adj2, *id2;
-  int32_t* wgst;        // sweep workgroup counters
-  unsigned long long* sortbuf;  // bonds of one step when they exceed LDS
+  float4 *rec, *ovf[2];
+  // selection: per-id minimum key (w1, id_T) of the A side
+  unsigned long long* slotA;
+  // per sweep workgroup, by parity: first-touched A's and counters
+  int32_t* wgp[2];
+  int32_t* wgo[2];
+  int32_t* povf[2];     // first-touched A's beyond kPropCap (capacity n each)
+  uint8_t* tflag;       // per slot: this T has a retained pair in the current step
+  int2* wgw[2];         // staged bonds (id_A, id_T), kWinCap per workgroup, by parity
+  int2* wov[2];         // staged bonds beyond kWinCap (capacity n/2 + 1 each)
+  int32_t* abst[2];     // A-bin workgroup counts of eligible A's, by parity
+  // spatial sort
+  int32_t *bstart, *astart;  // nbricks + 1 slot offsets, A-list offsets
+  uint32_t *bcnt, *bacnt;
+  int32_t *rank, *arank;
   // outputs
-  int32_t* bonds;       // per-step (id_A, id_T), may be null
+  int32_t* bonds;       // stateless step: (id_A, id_T) in id_A order
   int64_t bonds_cap;
-  int32_t* log;         // (step, id_A, id_T) rows, may be null
+  int32_t* log;         // (step, id_A, id_T) rows
   int64_t log_cap;
-  long long* slog;      // kStatsPerStep counters per step, may be null
-  int64_t slog_cap;
+  int32_t* part;        // per step and closing group: kPart partial counters
+  int64_t part_cap;     // steps the partial-counter log holds
+  unsigned long long* sortbuf;  // stateless step: bonds beyond LDS
   Ctl* ctl;
   // geometry, rule, draws
-  int32_t n, B, nc, ncell, nwg_sweep;
+  int32_t n, B, nc, ncell, nwg_sweep, nwg_abin, nwg_jit, ngroups;
   int32_t bs, nb, nbricks, sorted;  // brick edge (cells), bricks per side, total, storage sorted
+  int32_t jitter;       // 1: resident system (positions ping-pong, re-jitter by jit_c)
   float L, halfL, rc2, inv_w, jit_c;
   unsigned long long thresh, seed;
   RuleD rule;

@@ -1,20 +1,30 @@
 // kernels.hip -- HIP kernels of the reaction step for gfx950 (CDNA4, wave64).
 //
-// One reaction step (Table I of the paper, steps 1-9, on one GPU; the
-// communication steps 4, 6 and 8 have nothing to exchange):
-//   k_abin    A-role particles (a sparse list) -> coarse cell buckets
-//   k_sweep   every particle streams once (coalesced SoA loads); each
-//             T-eligible one tests the A records of its 2x2x2 cell block:
-//             cutoff (step 1), keyed Philox draw (step 2), bonded exclusion,
-//             A-side choice by 64-bit atomicMin of (w1, id_T) (steps 3-5)
-//   k_tail    one workgroup: T-side choice by atomicMin of (w2, id_A) (steps
-//             6-7), bonds sorted by id_A, states and adjacency (step 9)
-// plus k_jitter (the MD stand-in between steps), k_generate (synthetic
-// initial configuration) and k_classify (A list from scratch, validation).
+// One reaction step is three kernels (Table I of the paper, steps 1-9, on one
+// GPU; the communication steps 4, 6 and 8 have nothing to exchange):
+//   k_prep     re-jitter of every particle (the MD stand-in between steps;
+//              positions ping-pong between two buffers) fused with the binning
+//              of the A-role particles into coarse cells of width >= 2 rc (each
+//              A's jittered position is recomputed from the same draws); one
+//              extra workgroup closes the previous step (counters, bond rows,
+//              reset of the touched selection keys)
+//   k_sweep    every particle streams once with coalesced SoA loads (in brick
+//              order once the storage is sorted, the brick's A records staged in
+//              LDS); in-range pairs (step 1) go to an LDS queue so that the keyed
+//              Philox draws (step 2) run on full wavefronts; each retained pair
+//              lowers its A's key (w1, id_T) by a 64-bit atomicMin (steps 3-5)
+//              and flags its T
+//   k_resolve  each flagged T enumerates its retained pairs again, keeps those
+//              whose A chose it and takes the smallest (w2, id_A) (steps 6-7):
+//              that pair is bonded, states and adjacency updated (step 9)
+// plus the counting sort of the storage by brick, the synthetic generator and
+// the helpers of the runtime.
 //
 // Arithmetic follows the contract of include/polyreact.h: FP32 min-image
 // distance with explicitly rounded operations (no contraction), Philox4x32-10
-// per pair keyed by (step, id_A, id_T), integer threshold on word 0.
+// per pair keyed by (step, id_A, id_T), integer threshold on word 0.  Every
+// selection is a minimum over 64-bit keys, so no result depends on thread or
+// atomic order, nor on the storage order of the particles.
 #include <hip/hip_runtime.h>
 
 #include "common.hpp"
@@ -83,22 +93,68 @@ __device__ __forceinline__ bool in_window(int32_t t, int32_t s, int32_t type, in
   return t == type && s >= lo && s <= hi;
 }
 
+__device__ __forceinline__ bool is_a(const Dev& d, int32_t t, int32_t s) {
+  return in_window(t, s, d.rule.type_a, d.rule.a_min, d.rule.a_max);
+}
+
+__device__ __forceinline__ bool is_t(const Dev& d, int32_t t, int32_t s) {
+  return in_window(t, s, d.rule.type_t, d.rule.t_min, d.rule.t_max);
+}
+
 __device__ __forceinline__ int cell1(float u, int nc) {
   int c = (int)floorf(u);
   return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
 }
 
-// Wave-aggregated append: one atomic per wavefront, lane order inside it.
-__device__ __forceinline__ void wave_append(bool pred, int32_t value, int32_t* list,
-                                            uint32_t* counter) {
-  const unsigned long long mask = __ballot(pred);
-  if (mask == 0ull) return;
-  const int lane = __lane_id();
-  const int leader = __ffsll((long long)mask) - 1;
-  uint32_t base = 0;
-  if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
-  base = __shfl(base, leader);
-  if (pred) list[base + __popcll(mask & ((1ull << lane) - 1ull))] = value;
+__device__ __forceinline__ int cell_of(const Dev& d, float x, float y, float z) {
+  const int nc = d.nc;
+  const int cx = cell1(__fmul_rn(x, d.inv_w), nc);
+  const int cy = cell1(__fmul_rn(y, d.inv_w), nc);
+  const int cz = cell1(__fmul_rn(z, d.inv_w), nc);
+  return (cz * nc + cy) * nc + cx;
+}
+
+__device__ __forceinline__ void set_err(Ctl* c, int code) { atomicCAS(&c->err, 0, code); }
+
+__device__ __forceinline__ int32_t read_err(const Ctl* c) {
+  return __hip_atomic_load(&c->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Element p (0 or 1) of a two-element array held in the kernel argument,
+// chosen without dynamic indexing (which would copy the argument to scratch).
+// Both pointers are read and combined with a mask, so that no address select
+// (and no copy of the aggregate to scratch) is formed.
+template <typename T>
+__device__ __forceinline__ T* pick(T* const (&v)[2], uint32_t p) {
+  const unsigned long long a = (unsigned long long)v[0], b = (unsigned long long)v[1];
+  const unsigned long long m = 0ull - (unsigned long long)(p & 1u);
+  return (T*)((a & ~m) | (b & m));
+}
+
+// Storage set s, member by member (a select of the whole aggregate would be
+// built in scratch memory).
+__device__ __forceinline__ Arr pick_set(const Dev& d, uint32_t s) {
+  const Arr &u = d.set[0], &v = d.set[1];
+  Arr r;
+  for (int q = 0; q < 2; ++q) {
+    r.x[q] = pick({u.x[q], v.x[q]}, s);
+    r.y[q] = pick({u.y[q], v.y[q]}, s);
+    r.z[q] = pick({u.z[q], v.z[q]}, s);
+  }
+  r.typ = pick({u.typ, v.typ}, s);
+  r.st = pick({u.st, v.st}, s);
+  r.adj = pick({u.adj, v.adj}, s);
+  r.id = pick({u.id, v.id}, s);
+  return r;
+}
+
+// Step k of the current block: reaction step number and buffer parity.
+struct StepInfo {
+  uint32_t step, par;
+};
+
+__device__ __forceinline__ StepInfo step_info(const Ctl* c, int k) {
+  return StepInfo{c->step0 + (uint32_t)k, (c->par0 + (uint32_t)k) & 1u};
 }
 
 // Exclusive prefix sum over the workgroup (wave64 shuffles, then wave
@@ -130,440 +186,601 @@ __device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t* s_wave
   return r;
 }
 
-__device__ __forceinline__ void set_err(Ctl* c, int code) { atomicCAS(&c->err, 0, code); }
-
-__device__ __forceinline__ int32_t read_err(const Ctl* c) {
-  return __hip_atomic_load(&c->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // ---------------------------------------------------------------------------
 // Control block set-up (a kernel rather than a memset/memcpy so that a
-// captured graph may hold it).
+// captured graph may hold it).  A full reset selects storage set 0 and
+// parity 0 (the caller clears both cell-count buffers with it).
 // ---------------------------------------------------------------------------
 __global__ void k_ctl_reset(Ctl* c, uint32_t step, int full) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    c->step = step;
-    if (full) {  // par is kept: the cell counts of parity par are the cleared ones
+    c->step0 = step;
+    if (full) {
+      c->par0 = 0;
       c->err = 0;
-      c->na[0] = c->na[1] = 0;
-      c->ovf_n = 0;
-      c->nprop = 0;
-      c->nwin = 0;
-      c->stats_n = 0;
+      c->set = 0;
+      c->na = 0;
+      for (int p = 0; p < 2; ++p) {
+        c->ovf_n[p] = 0;
+        c->nprop_ovf[p] = 0;
+        c->nwin_ovf[p] = 0;
+      }
+      c->stats_n0 = 0;
       c->log_n = 0;
     }
   }
 }
 
-// ---------------------------------------------------------------------------
-// Validation and A list from scratch (after a load, and for the stateless
-// single step).
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_classify(Dev d) {
+// Position validation (after a load, and for the stateless single step).
+__global__ __launch_bounds__(kThreads) void k_classify(Dev d) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t cur = d.ctl->par;
-  bool isA = false;
-  if (k < d.n) {
-    const float x = d.x[k], y = d.y[k], z = d.z[k];
-    const bool ok = (x >= 0.0f && x < d.L) && (y >= 0.0f && y < d.L) && (z >= 0.0f && z < d.L);
-    if (!ok) set_err(d.ctl, PR_EINVAL);
-    isA = in_window(d.typ[k], d.st[k], d.rule.type_a, d.rule.a_min, d.rule.a_max);
-  }
-  wave_append(isA, k, d.alist[cur], &d.ctl->na[cur]);
+  if (k >= d.n) return;
+  const Arr a = pick_set(d, 0);
+  const float x = pick(a.x, 0)[k], y = pick(a.y, 0)[k], z = pick(a.z, 0)[k];
+  const bool ok = (x >= 0.0f && x < d.L) && (y >= 0.0f && y < d.L) && (z >= 0.0f && z < d.L);
+  if (!ok) set_err(d.ctl, PR_EINVAL);
+}
+
+// Identity storage order after a load (slot == id), cleared T flags.
+__global__ __launch_bounds__(kThreads) void k_identity(Dev d) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= d.n) return;
+  if (pick_set(d, 0).id) pick_set(d, 0).id[k] = k;
+  if (d.slot_of) d.slot_of[k] = k;
+  d.tflag[k] = 0;
 }
 
 // ---------------------------------------------------------------------------
-// Re-jitter (stand-in for MD between reaction steps).
+// Synthetic jittered-lattice initial configuration (storage set 0, parity 0,
+// slot == id).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_jitter(Dev d) {
+__global__ __launch_bounds__(kThreads) void k_generate(Dev d, int kind, unsigned long long gseed,
+                                                       float c0, float a, int nl,
+                                                       unsigned long long thr_x) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= d.n) return;
-  if (read_err(d.ctl)) return;
-  const uint32_t step = d.ctl->step;
-  const uint32_t id = d.id ? (uint32_t)d.id[k] : (uint32_t)k;
-  int32_t S[3];
-  ih12(step, id, 1u, d.seed, S);
-  d.x[k] = wrap_box(__fadd_rn(d.x[k], __fmul_rn((float)S[0], d.jit_c)), d.L);
-  d.y[k] = wrap_box(__fadd_rn(d.y[k], __fmul_rn((float)S[1], d.jit_c)), d.L);
-  d.z[k] = wrap_box(__fadd_rn(d.z[k], __fmul_rn((float)S[2], d.jit_c)), d.L);
-}
-
-// ---------------------------------------------------------------------------
-// Synthetic jittered-lattice initial configuration (slot == id).
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_generate(Dev d, int kind, unsigned long long gseed,
-                                                  float c0, float a, int nl,
-                                                  unsigned long long thr_x) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= d.n) return;
+  const Arr o = pick_set(d, 0);
   const unsigned long long n3 = (unsigned long long)nl * nl * nl;
   const unsigned long long s = ((unsigned long long)k * 2147483647ull) % n3;
-  const int ix = (int)(s % nl), iy = (int)((s / nl) % nl), iz = (int)(s / ((unsigned long long)nl * nl));
+  const int ix = (int)(s % nl), iy = (int)((s / nl) % nl),
+            iz = (int)(s / ((unsigned long long)nl * nl));
   int32_t S[3];
   ih12(0u, (uint32_t)k, 2u, gseed, S);
   const float px = __fmul_rn(__fadd_rn((float)ix, 0.5f), a);
   const float py = __fmul_rn(__fadd_rn((float)iy, 0.5f), a);
   const float pz = __fmul_rn(__fadd_rn((float)iz, 0.5f), a);
-  d.x[k] = wrap_box(__fadd_rn(px, __fmul_rn((float)S[0], c0)), d.L);
-  d.y[k] = wrap_box(__fadd_rn(py, __fmul_rn((float)S[1], c0)), d.L);
-  d.z[k] = wrap_box(__fadd_rn(pz, __fmul_rn((float)S[2], c0)), d.L);
+  pick(o.x, 0)[k] = wrap_box(__fadd_rn(px, __fmul_rn((float)S[0], c0)), d.L);
+  pick(o.y, 0)[k] = wrap_box(__fadd_rn(py, __fmul_rn((float)S[1], c0)), d.L);
+  pick(o.z, 0)[k] = wrap_box(__fadd_rn(pz, __fmul_rn((float)S[2], c0)), d.L);
   const W4 w = philox(0u, (uint32_t)k, 0u, 3u, gseed);
   const bool pick = (unsigned long long)w.w0 < thr_x;
   if (kind == 0) {
-    d.typ[k] = pick ? 1 : 0;
-    d.st[k] = pick ? 4 : 2;
+    o.typ[k] = pick ? 1 : 0;
+    o.st[k] = pick ? 4 : 2;
   } else {
-    d.typ[k] = 0;
-    d.st[k] = pick ? 2 : 0;
+    o.typ[k] = 0;
+    o.st[k] = pick ? 2 : 0;
   }
-  for (int b = 0; b < d.B; ++b) d.adj[(size_t)k * d.B + b] = -1;
+  for (int b = 0; b < d.B; ++b) o.adj[(size_t)k * d.B + b] = -1;
 }
 
 // ---------------------------------------------------------------------------
-// A list -> cell buckets.  Drops A's whose state left the A window, keeps the
-// rest in the list of the next parity, and records (x, y, z, id) per cell.
+// Closing a step, group g (one workgroup of kThreads): the counters of sweep
+// workgroups g*kGroup .. +kGroup summed into the step's partial record, their
+// staged bonds appended to the bond log (one reservation per group; rows of a
+// step end up in group order and readers order them by id_A), and the A-side
+// keys they touched reset.  Group 0 also takes the overflow lists and resets
+// the step's per-parity counters.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_abin(Dev d) {
-  if (read_err(d.ctl)) return;
-  const uint32_t cur = d.ctl->par, nxt = cur ^ 1u;
-  const uint32_t na = d.ctl->na[cur];
-  const int nc = d.nc;
-  for (uint32_t base = blockIdx.x * blockDim.x; base < na; base += gridDim.x * blockDim.x) {
-    const uint32_t k = base + threadIdx.x;
-    int slot = -1;
-    bool keep = false;
-    if (k < na) {
-      slot = d.alist[cur][k];
-      keep = in_window(d.typ[slot], d.st[slot], d.rule.type_a, d.rule.a_min, d.rule.a_max);
+__device__ void close_group(const Dev& d, uint32_t par, uint32_t step, uint32_t sidx, int g,
+                            uint32_t* s_wave) {
+  __shared__ int s_sum[kPart];
+  __shared__ uint64_t s_row;
+  Ctl* c = d.ctl;
+  const int tid = threadIdx.x;
+  if (tid < kPart) s_sum[tid] = 0;
+  const int w = g * kGroup + tid;
+  int o[7] = {0, 0, 0, 0, 0, 0, 0};
+  if (w < d.nwg_sweep) {
+    const int32_t* src = pick(d.wgo, par) + w * kWgOut;
+    for (int q = 0; q < 7; ++q) o[q] = src[q];
+    const int np = o[kOutProp] < kPropCap ? o[kOutProp] : kPropCap;
+    const int32_t* props = pick(d.wgp, par) + w * kPropCap;
+    for (int e = 0; e < np; ++e) d.slotA[props[e]] = kEmpty;
+  }
+  int a_elig = 0;  // the A-bin workgroup counts, strided over the groups
+  for (int q = w; q < d.nwg_abin; q += d.ngroups * kGroup) a_elig += pick(d.abst, par)[q];
+  const uint32_t nw = (uint32_t)min(o[kOutBonds], kWinCap);
+  uint32_t tot = 0;
+  const uint32_t off = block_scan_excl(nw, s_wave, tot);
+  const uint32_t nwov = g == 0 ? c->nwin_ovf[par] : 0u;
+  if (tid == 0 && tot + nwov > 0) s_row = atomicAdd((unsigned long long*)&c->log_n,
+                                                    (unsigned long long)(tot + nwov));
+  if (a_elig) atomicAdd(&s_sum[0], a_elig);
+  for (int q = 0; q < 7; ++q)
+    if (o[q]) atomicAdd(&s_sum[q + 1], o[q]);
+  __syncthreads();
+  const uint64_t row0 = s_row;
+  const int2* staged = pick(d.wgw, par) + w * kWinCap;
+  for (uint32_t e = 0; e < nw; ++e) {
+    const uint64_t row = row0 + off + e;
+    const int2 b = staged[e];
+    if ((int64_t)row < d.log_cap) {
+      d.log[3 * row] = (int32_t)step;
+      d.log[3 * row + 1] = b.x;
+      d.log[3 * row + 2] = b.y;
     }
-    wave_append(keep, slot, d.alist[nxt], &d.ctl->na[nxt]);
-    if (keep) {
-      const float x = d.x[slot], y = d.y[slot], z = d.z[slot];
-      const int id = d.id ? d.id[slot] : slot;
-      const int cx = cell1(__fmul_rn(x, d.inv_w), nc);
-      const int cy = cell1(__fmul_rn(y, d.inv_w), nc);
-      const int cz = cell1(__fmul_rn(z, d.inv_w), nc);
-      const int c = (cz * nc + cy) * nc + cx;
-      const uint32_t r = atomicAdd(&d.cnt[cur][c], 1u);
-      const float4 rec = make_float4(x, y, z, __int_as_float(id));
-      if (r < (uint32_t)kCellCap) {
-        d.rec[(size_t)c * kCellCap + r] = rec;
-      } else {
-        const uint32_t o = atomicAdd(&d.ctl->ovf_n, 1u);
-        d.ovf[o] = rec;
+  }
+  if (g == 0) {
+    for (uint32_t e = tid; e < nwov; e += blockDim.x) {
+      const uint64_t row = row0 + tot + e;
+      const int2 b = pick(d.wov, par)[e];
+      if ((int64_t)row < d.log_cap) {
+        d.log[3 * row] = (int32_t)step;
+        d.log[3 * row + 1] = b.x;
+        d.log[3 * row + 2] = b.y;
       }
     }
+    const uint32_t novf = c->nprop_ovf[par];
+    for (uint32_t e = tid; e < novf; e += blockDim.x) d.slotA[pick(d.povf, par)[e]] = kEmpty;
+  }
+  __syncthreads();
+  if (tid < kPart && (int64_t)sidx < d.part_cap)
+    d.part[((size_t)sidx * d.ngroups + g) * kPart + tid] = s_sum[tid];
+  if (g == 0 && tid == 0) {
+    c->ovf_n[par] = 0;
+    c->nprop_ovf[par] = 0;
+    c->nwin_ovf[par] = 0;
   }
 }
 
 // ---------------------------------------------------------------------------
-// Dense sweep: every particle once.  T-eligible particles test the A records
-// of the 2x2x2 cells around them (cell width >= 2 rc) and the overflow list.
+// k_prep: [jitter blocks][A-bin blocks][closing groups of step k - 1 when k > 0].
 // ---------------------------------------------------------------------------
-struct SweepCtx {
-  float xj, yj, zj;
-  uint32_t idj, step;
-  int in_rc, drawn, excl;
-};
+__device__ __forceinline__ void jittered(const Dev& d, const Arr& a, uint32_t par, uint32_t step,
+                                         int slot, float& x, float& y, float& z) {
+  x = pick(a.x, par)[slot];
+  y = pick(a.y, par)[slot];
+  z = pick(a.z, par)[slot];
+  if (d.jitter && d.jit_c != 0.0f) {
+    const uint32_t id = a.id ? (uint32_t)a.id[slot] : (uint32_t)slot;
+    int32_t S[3];
+    ih12(step, id, 1u, d.seed, S);
+    x = wrap_box(__fadd_rn(x, __fmul_rn((float)S[0], d.jit_c)), d.L);
+    y = wrap_box(__fadd_rn(y, __fmul_rn((float)S[1], d.jit_c)), d.L);
+    z = wrap_box(__fadd_rn(z, __fmul_rn((float)S[2], d.jit_c)), d.L);
+  }
+}
 
-__device__ __forceinline__ void test_pair(const Dev& d, SweepCtx& t, float4 a) {
-  const int ida = __float_as_int(a.w);
-  const float dx = min_image(__fsub_rn(t.xj, a.x), d.L, d.halfL);
-  const float dy = min_image(__fsub_rn(t.yj, a.y), d.L, d.halfL);
-  const float dz = min_image(__fsub_rn(t.zj, a.z), d.L, d.halfL);
-  const float r2 = __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz));
-  if (!(r2 < d.rc2)) return;
-  t.in_rc++;
-  const W4 w = philox(t.step, (uint32_t)ida, t.idj, 0u, d.seed);
-  if (!((unsigned long long)w.w0 < d.thresh)) return;
-  t.drawn++;
-  if (d.rule.exclude) {
-    const int sa = d.slot_of ? d.slot_of[ida] : ida;
-    const int32_t* row = d.adj + (size_t)sa * d.B;
-    for (int b = 0; b < d.B; ++b)
-      if (row[b] == (int32_t)t.idj) {
-        t.excl++;
-        return;
+__global__ __launch_bounds__(kThreads) void k_prep(Dev d, int k) {
+  __shared__ int s_na;
+  __shared__ uint32_t s_wave[kThreads / 64 + 1];
+  const StepInfo si = step_info(d.ctl, k);
+  const Arr a = pick_set(d, d.ctl->set & 1u);
+  const int b = blockIdx.x;
+  if (b < d.nwg_jit) {  // re-jitter: positions of parity par -> par ^ 1
+    const int i = b * kThreads + threadIdx.x;
+    if (i >= d.n || read_err(d.ctl)) return;
+    float x, y, z;
+    jittered(d, a, si.par, si.step, i, x, y, z);
+    pick(a.x, si.par ^ 1u)[i] = x;
+    pick(a.y, si.par ^ 1u)[i] = y;
+    pick(a.z, si.par ^ 1u)[i] = z;
+    return;
+  }
+  if (b < d.nwg_jit + d.nwg_abin) {  // A particles -> cell buckets
+    const int g = b - d.nwg_jit;
+    if (threadIdx.x == 0) s_na = 0;
+    __syncthreads();
+    if (read_err(d.ctl) == 0) {
+      const uint32_t total = d.sorted ? d.ctl->na : (uint32_t)d.n;
+      int mine = 0;
+      for (uint32_t q = g * kThreads + threadIdx.x; q < total; q += d.nwg_abin * kThreads) {
+        const int slot = d.sorted ? d.alist[q] : (int)q;
+        if (!is_a(d, a.typ[slot], a.st[slot])) continue;
+        mine++;
+        float x, y, z;
+        jittered(d, a, si.par, si.step, slot, x, y, z);
+        const int id = a.id ? a.id[slot] : slot;
+        const int c = cell_of(d, x, y, z);
+        const uint32_t r = atomicAdd(&pick(d.cnt, si.par)[c], 1u);
+        const float4 rec = make_float4(x, y, z, __int_as_float(id));
+        if (r < (uint32_t)kCellCap) {
+          d.rec[(size_t)c * kCellCap + r] = rec;
+        } else {
+          const uint32_t o = atomicAdd(&d.ctl->ovf_n[si.par], 1u);
+          pick(d.ovf, si.par)[o] = rec;
+        }
       }
+      if (mine) atomicAdd(&s_na, mine);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) pick(d.abst, si.par)[g] = s_na;
+    return;
   }
-  const unsigned long long key = ((unsigned long long)w.w1 << 32) | (unsigned long long)t.idj;
-  const unsigned long long old = atomicMin(&d.slotA[ida], key);
-  if (old == kEmpty) {
-    const uint32_t p = atomicAdd(&d.ctl->nprop, 1u);
-    d.propA[p] = ida;
+  // closing groups of the previous step of the block
+  close_group(d, si.par ^ 1u, si.step - 1u, d.ctl->stats_n0 + (uint32_t)k - 1u,
+              b - d.nwg_jit - d.nwg_abin, s_wave);
+}
+
+// Closes step k of the block (one workgroup per closing group).
+__global__ __launch_bounds__(kThreads) void k_close(Dev d, int k) {
+  __shared__ uint32_t s_wave[kThreads / 64 + 1];
+  const StepInfo si = step_info(d.ctl, k);
+  close_group(d, si.par, si.step, d.ctl->stats_n0 + (uint32_t)k, blockIdx.x, s_wave);
+}
+
+// Advances the block origin by K steps (after the block's last step closed).
+__global__ void k_advance(Ctl* c, int K) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    c->step0 += (uint32_t)K;
+    c->par0 = (c->par0 + (uint32_t)K) & 1u;
+    c->stats_n0 += (uint32_t)K;
   }
 }
 
+// ---------------------------------------------------------------------------
+// Pair tests shared by the sweep and the resolution.
+// ---------------------------------------------------------------------------
 // The 2x2x2 block of coarse cells around a particle: per dimension the cells
 // floor(u - 1/2) and floor(u - 1/2) + 1 (periodic), u = x / cell width.
-// Cell width >= 2 rc (1 + 2^-10) puts every partner within rc in this block.
-struct Block2 {
-  int cx[2], cy[2], cz[2], m;
-};
-
-__device__ __forceinline__ void lo_hi(float v, float inv_w, int nc, int out[2]) {
+__device__ __forceinline__ void lo_hi(float v, float inv_w, int nc, int& c0, int& c1) {
   const int l = (int)floorf(__fsub_rn(__fmul_rn(v, inv_w), 0.5f));
-  out[0] = l < 0 ? l + nc : l;
-  out[1] = l + 1 >= nc ? l + 1 - nc : l + 1;
-  if (nc == 1) out[0] = out[1] = 0;
+  c0 = l < 0 ? l + nc : l;
+  c1 = l + 1 >= nc ? l + 1 - nc : l + 1;
+  if (nc == 1) c0 = c1 = 0;
 }
 
-__device__ __forceinline__ Block2 block_of(const Dev& d, float x, float y, float z) {
-  Block2 b;
-  lo_hi(x, d.inv_w, d.nc, b.cx);
-  lo_hi(y, d.inv_w, d.nc, b.cy);
-  lo_hi(z, d.inv_w, d.nc, b.cz);
-  b.m = d.nc > 1 ? 2 : 1;
-  return b;
+__device__ __forceinline__ float dist2(const Dev& d, float xj, float yj, float zj, float4 a) {
+  const float dx = min_image(__fsub_rn(xj, a.x), d.L, d.halfL);
+  const float dy = min_image(__fsub_rn(yj, a.y), d.L, d.halfL);
+  const float dz = min_image(__fsub_rn(zj, a.z), d.L, d.halfL);
+  return __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz));
 }
 
-// One T particle against the global cell buckets.
-__device__ __forceinline__ void sweep_global(const Dev& d, SweepCtx& t, const Block2& bk,
-                                             uint32_t cur) {
+__device__ __forceinline__ bool bonded(const Dev& d, const Arr& a, int ida, uint32_t idj) {
+  const int sa = d.slot_of ? d.slot_of[ida] : ida;
+  const int32_t* row = a.adj + (size_t)sa * d.B;
+  for (int b = 0; b < d.B; ++b)
+    if (row[b] == (int32_t)idj) return true;
+  return false;
+}
+
+// Visits the A records of the 2x2x2 cell block around (x, y, z) in the global
+// buckets, then the overflow list.
+template <typename F>
+__device__ __forceinline__ void for_global_records(const Dev& d, uint32_t par, uint32_t novf,
+                                                   float x, float y, float z, F f) {
   const int nc = d.nc;
-  for (int a = 0; a < bk.m; ++a)
-    for (int b = 0; b < bk.m; ++b)
-      for (int e = 0; e < bk.m; ++e) {
-        const int c = (bk.cz[a] * nc + bk.cy[b]) * nc + bk.cx[e];
-        uint32_t nr = d.cnt[cur][c];
-        nr = nr < (uint32_t)kCellCap ? nr : (uint32_t)kCellCap;
-        const float4* rec = d.rec + (size_t)c * kCellCap;
-        for (uint32_t r = 0; r < nr; ++r) test_pair(d, t, rec[r]);
-      }
-}
-
-__device__ __forceinline__ void wg_stats_out(const Dev& d, int* s_cnt, int t_elig,
-                                             const SweepCtx& t) {
-  if (t_elig) atomicAdd(&s_cnt[0], t_elig);
-  if (t.in_rc) atomicAdd(&s_cnt[1], t.in_rc);
-  if (t.drawn) atomicAdd(&s_cnt[2], t.drawn);
-  if (t.excl) atomicAdd(&s_cnt[3], t.excl);
-  __syncthreads();
-  if (threadIdx.x < kWgStats) d.wgst[blockIdx.x * kWgStats + threadIdx.x] = s_cnt[threadIdx.x];
-}
-
-// Unsorted storage (and the stateless step): one thread per particle.
-__global__ __launch_bounds__(kSweepThreads) void k_sweep(Dev d) {
-  __shared__ int s_cnt[kWgStats];
-  if (threadIdx.x < kWgStats) s_cnt[threadIdx.x] = 0;
-  const bool dead = read_err(d.ctl) != 0;
-  const uint32_t step = d.ctl->step, cur = d.ctl->par, nxt = cur ^ 1u;
-  const uint32_t novf = d.ctl->ovf_n;
-  // clear the bucket counts of the next step's parity
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < d.ncell; c += gridDim.x * blockDim.x)
-    d.cnt[nxt][c] = 0u;
-  __syncthreads();
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  int t_elig = 0;
-  SweepCtx t;
-  t.in_rc = t.drawn = t.excl = 0;
-  if (!dead && k < d.n &&
-      in_window(d.typ[k], d.st[k], d.rule.type_t, d.rule.t_min, d.rule.t_max)) {
-    t_elig = 1;
-    t.xj = d.x[k];
-    t.yj = d.y[k];
-    t.zj = d.z[k];
-    t.idj = d.id ? (uint32_t)d.id[k] : (uint32_t)k;
-    t.step = step;
-    sweep_global(d, t, block_of(d, t.xj, t.yj, t.zj), cur);
-    for (uint32_t r = 0; r < novf; ++r) test_pair(d, t, d.ovf[r]);
+  int cx0, cx1, cy0, cy1, cz0, cz1;
+  lo_hi(x, d.inv_w, nc, cx0, cx1);
+  lo_hi(y, d.inv_w, nc, cy0, cy1);
+  lo_hi(z, d.inv_w, nc, cz0, cz1);
+  const int m = nc > 1 ? 2 : 1;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int ia = q >> 2, ib = (q >> 1) & 1, ie = q & 1;
+    if (ia >= m || ib >= m || ie >= m) continue;
+    const int c = ((ia ? cz1 : cz0) * nc + (ib ? cy1 : cy0)) * nc + (ie ? cx1 : cx0);
+    uint32_t nr = pick(d.cnt, par)[c];
+    nr = nr < (uint32_t)kCellCap ? nr : (uint32_t)kCellCap;
+    const float4* rec = d.rec + (size_t)c * kCellCap;
+    for (uint32_t r = 0; r < nr; ++r) f(rec[r]);
   }
-  wg_stats_out(d, s_cnt, t_elig, t);
+  const float4* ovf = pick(d.ovf, par);
+  for (uint32_t r = 0; r < novf; ++r) f(ovf[r]);
 }
 
-// Brick geometry: staged region = brick cells plus one halo layer per side
-// (or the whole grid in single-brick mode, bs == nc).
-struct Region {
-  int base[3], ext[3];
-};
-
-__device__ __forceinline__ Region region_of(const Dev& d, int b) {
-  Region g;
-  const int nb = d.nb;
-  const int bc[3] = {b % nb, (b / nb) % nb, b / (nb * nb)};
-  for (int q = 0; q < 3; ++q) {
-    if (d.nbricks == 1) {
-      g.base[q] = 0;
-      g.ext[q] = d.nc;
-    } else {
-      const int lo = bc[q] * d.bs;
-      const int sz = min(d.bs, d.nc - lo);
-      g.base[q] = lo == 0 ? d.nc - 1 : lo - 1;
-      g.ext[q] = sz + 2;
-    }
+// Staged region of a brick along one dimension: the brick's cells plus one
+// halo cell per side (the whole grid in single-brick mode).
+__device__ __forceinline__ void region_dim(const Dev& d, int bc, int& base, int& ext) {
+  if (d.nbricks == 1) {
+    base = 0;
+    ext = d.nc;
+  } else {
+    const int lo = bc * d.bs;
+    const int sz = min(d.bs, d.nc - lo);
+    base = lo == 0 ? d.nc - 1 : lo - 1;
+    ext = sz + 2;
   }
-  return g;
 }
 
 __device__ __forceinline__ int local_of(int c, int base, int nc) {
-  int l = c - base;
+  const int l = c - base;
   return l < 0 ? l + nc : l;
 }
 
-// Sorted storage: one workgroup per brick; A records of the staged region
-// in LDS; particles that drifted out of reach of the region since the last
-// sort (and bricks whose region holds too many records) use the global path.
-__global__ __launch_bounds__(kSweepThreads) void k_sweep_brick(Dev d) {
-  __shared__ int s_cnt[kWgStats];
-  __shared__ uint32_t s_off[kStageCells + 1];
-  __shared__ uint32_t s_wave[kSweepThreads / 64 + 1];
-  __shared__ float4 s_rec[kStageRecs];
-  if (threadIdx.x < kWgStats) s_cnt[threadIdx.x] = 0;
-  const bool dead = read_err(d.ctl) != 0;
-  const uint32_t step = d.ctl->step, cur = d.ctl->par, nxt = cur ^ 1u;
-  const uint32_t novf = d.ctl->ovf_n;
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < d.ncell; c += gridDim.x * blockDim.x)
-    d.cnt[nxt][c] = 0u;
-  const Region g = region_of(d, blockIdx.x);
-  const int ncs = g.ext[0] * g.ext[1] * g.ext[2];
-  const int nc = d.nc;
-  // counts of the staged cells -> exclusive offsets
-  uint32_t mine = 0;
-  int myc = 0;
-  if ((int)threadIdx.x < ncs) {
-    const int l = threadIdx.x;
-    const int lx = l % g.ext[0], ly = (l / g.ext[0]) % g.ext[1], lz = l / (g.ext[0] * g.ext[1]);
-    int cx = g.base[0] + lx, cy = g.base[1] + ly, cz = g.base[2] + lz;
-    cx -= cx >= nc ? nc : 0;
-    cy -= cy >= nc ? nc : 0;
-    cz -= cz >= nc ? nc : 0;
-    myc = (cz * nc + cy) * nc + cx;
-    mine = dead ? 0u : d.cnt[cur][myc];
-    mine = mine < (uint32_t)kCellCap ? mine : (uint32_t)kCellCap;
+// Slot range of sweep/resolve workgroup w.
+template <bool kBrick>
+__device__ __forceinline__ void range_of(const Dev& d, int w, int& s0, int& s1) {
+  if (kBrick) {
+    s0 = d.bstart[w];
+    s1 = d.bstart[w + 1];
+  } else {
+    s0 = w * kThreads;
+    s1 = min(d.n, s0 + kThreads);
   }
-  uint32_t total = 0;
-  const uint32_t off = block_scan_excl(mine, s_wave, total);
-  if ((int)threadIdx.x < ncs) s_off[threadIdx.x] = off;
-  if (threadIdx.x == 0) s_off[ncs] = total;
-  const bool staged = total <= (uint32_t)kStageRecs;
-  if (staged && (int)threadIdx.x < ncs)
-    for (uint32_t r = 0; r < mine; ++r) s_rec[off + r] = d.rec[(size_t)myc * kCellCap + r];
-  __syncthreads();
-  int t_elig = 0;
-  SweepCtx t;
-  t.in_rc = t.drawn = t.excl = 0;
-  t.step = step;
-  const int s0 = d.bstart[blockIdx.x], s1 = d.bstart[blockIdx.x + 1];
-  for (int k = s0 + threadIdx.x; !dead && k < s1; k += blockDim.x) {
-    if (!in_window(d.typ[k], d.st[k], d.rule.type_t, d.rule.t_min, d.rule.t_max)) continue;
-    t_elig++;
-    t.xj = d.x[k];
-    t.yj = d.y[k];
-    t.zj = d.z[k];
-    t.idj = (uint32_t)d.id[k];
-    const Block2 bk = block_of(d, t.xj, t.yj, t.zj);
-    int lx[2], ly[2], lz[2];
-    bool inside = staged;
-    for (int q = 0; q < bk.m; ++q) {
-      lx[q] = local_of(bk.cx[q], g.base[0], nc);
-      ly[q] = local_of(bk.cy[q], g.base[1], nc);
-      lz[q] = local_of(bk.cz[q], g.base[2], nc);
-      inside = inside && lx[q] < g.ext[0] && ly[q] < g.ext[1] && lz[q] < g.ext[2];
-    }
-    if (inside) {
-      for (int a = 0; a < bk.m; ++a)
-        for (int b = 0; b < bk.m; ++b)
-          for (int e = 0; e < bk.m; ++e) {
-            const int l = (lz[a] * g.ext[1] + ly[b]) * g.ext[0] + lx[e];
-            const uint32_t q1 = s_off[l + 1];
-            for (uint32_t q = s_off[l]; q < q1; ++q) test_pair(d, t, s_rec[q]);
-          }
+}
+
+// Draw, exclusion and A-side choice of an in-range pair (steps 2-5); the first
+// T to touch an A records it for the reset of its key.
+struct SweepAcc {
+  int t_elig, in_rc, drawn, excl;
+};
+
+__device__ __forceinline__ void retain(const Dev& d, const Arr& a, uint32_t step, uint32_t par,
+                                       int ida, uint32_t idj, int sj, SweepAcc& n, int* s_np) {
+  const W4 r = philox(step, (uint32_t)ida, idj, 0u, d.seed);
+  if (!((unsigned long long)r.w0 < d.thresh)) return;
+  n.drawn++;
+  if (d.rule.exclude && bonded(d, a, ida, idj)) {
+    n.excl++;
+    return;
+  }
+  d.tflag[sj] = 1;
+  const unsigned long long key = ((unsigned long long)r.w1 << 32) | (unsigned long long)idj;
+  if (atomicMin(&d.slotA[ida], key) == kEmpty) {
+    const int p = atomicAdd(s_np, 1);
+    if (p < kPropCap) {
+      pick(d.wgp, par)[blockIdx.x * kPropCap + p] = ida;
     } else {
-      sweep_global(d, t, bk, cur);
+      const uint32_t o = atomicAdd(&d.ctl->nprop_ovf[par], 1u);
+      pick(d.povf, par)[o] = ida;
     }
-    for (uint32_t r = 0; r < novf; ++r) test_pair(d, t, d.ovf[r]);
   }
-  wg_stats_out(d, s_cnt, t_elig, t);
 }
 
 // ---------------------------------------------------------------------------
-// Spatial sort of the storage by brick (counting sort: count, scan, scatter).
-// Results never depend on the storage order; the sort only gives each sweep
-// workgroup a compact region of space.
+// k_sweep: kBrick = sorted storage, one workgroup per brick with the brick's A
+// records in LDS (particles that drifted out of the staged region since the
+// last sort, and bricks whose region holds more than kStageRecs records, use
+// the global buckets); otherwise a workgroup takes kThreads consecutive slots.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int brick_of(const Dev& d, float x, float y, float z) {
-  if (d.nbricks == 1) return 0;
-  const int cx = cell1(__fmul_rn(x, d.inv_w), d.nc) / d.bs;
-  const int cy = cell1(__fmul_rn(y, d.inv_w), d.nc) / d.bs;
-  const int cz = cell1(__fmul_rn(z, d.inv_w), d.nc) / d.bs;
-  return (cz * d.nb + cy) * d.nb + cx;
-}
-
-__global__ __launch_bounds__(256) void k_sort_count(Dev d) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= d.n) return;
-  const int b = brick_of(d, d.x[k], d.y[k], d.z[k]);
-  d.rank[k] = (int32_t)atomicAdd(&d.bcnt[b], 1u);
-}
-
-__global__ __launch_bounds__(1024) void k_sort_scan(Dev d) {
-  __shared__ uint32_t s_wave[1024 / 64 + 1];
-  uint32_t carry = 0;
-  for (int base = 0; base < d.nbricks; base += blockDim.x) {
-    const int b = base + threadIdx.x;
-    const uint32_t v = b < d.nbricks ? d.bcnt[b] : 0u;
+template <bool kBrick>
+__global__ __launch_bounds__(kThreads) void k_sweep(Dev d, int k) {
+  __shared__ int s_cnt[5];
+  __shared__ int s_qn;
+  __shared__ uint32_t s_off[kBrick ? kStageCells + 1 : 1];
+  __shared__ uint32_t s_wave[kThreads / 64 + 1];
+  __shared__ float4 s_rec[kBrick ? kStageRecs : 1];
+  __shared__ int32_t s_qa[kQueue];
+  __shared__ uint16_t s_qt[kQueue];
+  __shared__ uint32_t s_tj[kThreads];
+  __shared__ int32_t s_ts[kThreads];
+  const int tid = threadIdx.x, w = blockIdx.x;
+  if (tid < 5) s_cnt[tid] = 0;
+  if (tid == 0) s_qn = 0;
+  const Ctl* c = d.ctl;
+  const bool dead = read_err(c) != 0;
+  const StepInfo si = step_info(c, k);
+  const uint32_t par = si.par, step = si.step;
+  const Arr a = pick_set(d, c->set & 1u);
+  const float *X = pick(a.x, par ^ 1u), *Y = pick(a.y, par ^ 1u), *Z = pick(a.z, par ^ 1u);
+  const uint32_t novf = c->ovf_n[par];
+  int s0, s1;
+  range_of<kBrick>(d, w, s0, s1);
+  // the first chunk's particle data, issued before the staging round trips
+  int slot = s0 + tid;
+  int typ = -1, stt = 0, idv = 0;
+  float xj = 0.0f, yj = 0.0f, zj = 0.0f;
+  if (slot < s1) {
+    typ = a.typ[slot];
+    stt = a.st[slot];
+    xj = X[slot];
+    yj = Y[slot];
+    zj = Z[slot];
+    idv = a.id ? a.id[slot] : slot;
+  }
+  // clear the bucket counts of the next step's parity
+  for (int q = w * kThreads + tid; q < d.ncell; q += gridDim.x * kThreads) pick(d.cnt, par ^ 1u)[q] = 0u;
+  int bx = 0, ex = 0, by = 0, ey = 0, bz = 0, ez = 0;
+  bool staged = false;
+  const int nc = d.nc;
+  if (kBrick) {
+    const int nb = d.nb;
+    region_dim(d, w % nb, bx, ex);
+    region_dim(d, (w / nb) % nb, by, ey);
+    region_dim(d, w / (nb * nb), bz, ez);
+    const int ncs = ex * ey * ez;
+    uint32_t mine = 0;
+    int myc = 0;
+    if (tid < ncs) {
+      const int lx = tid % ex, ly = (tid / ex) % ey, lz = tid / (ex * ey);
+      int cx = bx + lx, cy = by + ly, cz = bz + lz;
+      cx -= cx >= nc ? nc : 0;
+      cy -= cy >= nc ? nc : 0;
+      cz -= cz >= nc ? nc : 0;
+      myc = (cz * nc + cy) * nc + cx;
+      mine = dead ? 0u : pick(d.cnt, par)[myc];
+      mine = mine < (uint32_t)kCellCap ? mine : (uint32_t)kCellCap;
+    }
     uint32_t total = 0;
-    const uint32_t ex = block_scan_excl(v, s_wave, total);
-    if (b < d.nbricks) {
-      d.bstart[b] = (int32_t)(carry + ex);
-      d.bcnt[b] = 0u;
+    const uint32_t off = block_scan_excl(mine, s_wave, total);
+    if (tid < ncs) s_off[tid] = off;
+    if (tid == 0) s_off[ncs] = total;
+    staged = total <= (uint32_t)kStageRecs;
+    if (staged && tid < ncs)
+      for (uint32_t r = 0; r < mine; ++r) s_rec[off + r] = d.rec[(size_t)myc * kCellCap + r];
+  }
+  __syncthreads();
+  SweepAcc n = {0, 0, 0, 0};
+  for (int base = s0; base < s1 && !dead; base += kThreads) {
+    if (base != s0) {
+      slot = base + tid;
+      typ = -1;
+      if (slot < s1) {
+        typ = a.typ[slot];
+        stt = a.st[slot];
+        xj = X[slot];
+        yj = Y[slot];
+        zj = Z[slot];
+        idv = a.id ? a.id[slot] : slot;
+      }
     }
-    carry += total;
+    if (slot < s1 && is_t(d, typ, stt)) {
+      n.t_elig++;
+      s_tj[tid] = (uint32_t)idv;
+      s_ts[tid] = slot;
+      // an in-range pair is queued; a full queue sends it straight to the draw
+      auto push = [&](float4 A) {
+        if (dist2(d, xj, yj, zj, A) < d.rc2) {
+          n.in_rc++;
+          const int p = atomicAdd(&s_qn, 1);
+          if (p < kQueue) {
+            s_qa[p] = __float_as_int(A.w);
+            s_qt[p] = (uint16_t)tid;
+          } else {
+            retain(d, a, step, par, __float_as_int(A.w), (uint32_t)idv, slot, n, &s_cnt[kOutProp]);
+          }
+        }
+      };
+      bool inside = false;
+      int lx0 = 0, lx1 = 0, ly0 = 0, ly1 = 0, lz0 = 0, lz1 = 0;
+      if (kBrick && staged) {
+        int cx0, cx1, cy0, cy1, cz0, cz1;
+        lo_hi(xj, d.inv_w, nc, cx0, cx1);
+        lo_hi(yj, d.inv_w, nc, cy0, cy1);
+        lo_hi(zj, d.inv_w, nc, cz0, cz1);
+        lx0 = local_of(cx0, bx, nc);
+        lx1 = local_of(cx1, bx, nc);
+        ly0 = local_of(cy0, by, nc);
+        ly1 = local_of(cy1, by, nc);
+        lz0 = local_of(cz0, bz, nc);
+        lz1 = local_of(cz1, bz, nc);
+        inside = lx0 < ex && lx1 < ex && ly0 < ey && ly1 < ey && lz0 < ez && lz1 < ez;
+      }
+      if (inside) {
+        const int m = nc > 1 ? 2 : 1;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int ia = q >> 2, ib = (q >> 1) & 1, ie = q & 1;
+          if (ia >= m || ib >= m || ie >= m) continue;
+          const int l = ((ia ? lz1 : lz0) * ey + (ib ? ly1 : ly0)) * ex + (ie ? lx1 : lx0);
+          const uint32_t r1 = s_off[l + 1];
+          for (uint32_t r = s_off[l]; r < r1; ++r) push(s_rec[r]);
+        }
+        const float4* ovf = pick(d.ovf, par);
+        for (uint32_t r = 0; r < novf; ++r) push(ovf[r]);
+      } else {
+        for_global_records(d, par, novf, xj, yj, zj, push);
+      }
+    }
+    __syncthreads();
+    // the queued pairs of this chunk: draws on full wavefronts
+    const int qn = min(s_qn, kQueue);
+    for (int e = tid; e < qn; e += kThreads) {
+      const int t = s_qt[e];
+      retain(d, a, step, par, s_qa[e], s_tj[t], s_ts[t], n, &s_cnt[kOutProp]);
+    }
+    __syncthreads();
+    if (tid == 0) s_qn = 0;
+    __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    d.bstart[d.nbricks] = (int32_t)carry;
-    d.ctl->na[d.ctl->par] = 0;  // the A list is rebuilt in the new order
-  }
-}
-
-__global__ __launch_bounds__(256) void k_sort_scatter(Dev d) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= d.n) return;
-  const float x = d.x[k], y = d.y[k], z = d.z[k];
-  const int ns = d.bstart[brick_of(d, x, y, z)] + d.rank[k];
-  d.x2[ns] = x;
-  d.y2[ns] = y;
-  d.z2[ns] = z;
-  d.typ2[ns] = d.typ[k];
-  d.st2[ns] = d.st[k];
-  const int id = d.id[k];
-  d.id2[ns] = id;
-  d.slot_of[id] = ns;
-  for (int b = 0; b < d.B; ++b) d.adj2[(size_t)ns * d.B + b] = d.adj[(size_t)k * d.B + b];
-}
-
-// A list from scratch in storage order (after a sort), no validation.
-__global__ __launch_bounds__(256) void k_alist_rebuild(Dev d) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t cur = d.ctl->par;
-  const bool isA =
-      k < d.n && in_window(d.typ[k], d.st[k], d.rule.type_a, d.rule.a_min, d.rule.a_max);
-  wave_append(isA, k, d.alist[cur], &d.ctl->na[cur]);
-}
-
-__global__ __launch_bounds__(256) void k_identity(Dev d) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= d.n) return;
-  d.id[k] = k;
-  d.slot_of[k] = k;
-}
-
-// Storage order -> particle-id order.
-__global__ __launch_bounds__(256) void k_gather_out(Dev d, float* ox, float* oy, float* oz,
-                                                    int32_t* ost, int32_t* oadj) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= d.n) return;
-  const int id = d.id[k];
-  if (ox) ox[id] = d.x[k];
-  if (oy) oy[id] = d.y[k];
-  if (oz) oz[id] = d.z[k];
-  if (ost) ost[id] = d.st[k];
-  if (oadj)
-    for (int b = 0; b < d.B; ++b) oadj[(size_t)id * d.B + b] = d.adj[(size_t)k * d.B + b];
+  if (n.t_elig) atomicAdd(&s_cnt[kOutTElig], n.t_elig);
+  if (n.in_rc) atomicAdd(&s_cnt[kOutInRc], n.in_rc);
+  if (n.drawn) atomicAdd(&s_cnt[kOutDrawn], n.drawn);
+  if (n.excl) atomicAdd(&s_cnt[kOutExcl], n.excl);
+  __syncthreads();
+  if (tid < 5) pick(d.wgo, par)[w * kWgOut + tid] = s_cnt[tid];
 }
 
 // ---------------------------------------------------------------------------
-// Resolution and application, one workgroup.
+// k_resolve: the T side (steps 6-7) and the bonds (step 9).  A flagged T is
+// handled by the workgroup that owns its slot; it enumerates its retained
+// pairs again (same cells, same draws), keeps those whose A's final key names
+// it, and bonds the smallest (w2, id_A).  An A chose exactly one T and a T
+// bonds at most one A, so every state and adjacency row has one writer.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool adj_append(int32_t* row, int B, int32_t v) {
+  for (int b = 0; b < B; ++b)
+    if (row[b] < 0) {
+      row[b] = v;
+      return true;
+    }
+  return false;
+}
+
+template <bool kBrick>
+__global__ __launch_bounds__(kThreads) void k_resolve(Dev d, int k) {
+  __shared__ int s_nw, s_lost, s_nadd, s_abase;
+  __shared__ int32_t s_add[kThreads];
+  const int tid = threadIdx.x, w = blockIdx.x;
+  if (tid == 0) {
+    s_nw = 0;
+    s_lost = 0;
+  }
+  const Ctl* c0 = d.ctl;
+  Ctl* c = d.ctl;
+  const bool dead = read_err(c0) != 0;
+  const StepInfo si = step_info(c0, k);
+  const uint32_t par = si.par, step = si.step;
+  const Arr a = pick_set(d, c0->set & 1u);
+  const float *X = pick(a.x, par ^ 1u), *Y = pick(a.y, par ^ 1u), *Z = pick(a.z, par ^ 1u);
+  const uint32_t novf = c0->ovf_n[par];
+  int s0, s1;
+  range_of<kBrick>(d, w, s0, s1);
+  __syncthreads();
+  for (int base = s0; base < s1 && !dead; base += kThreads) {
+    if (tid == 0) s_nadd = 0;
+    __syncthreads();
+    const int slot = base + tid;
+    if (slot < s1 && d.tflag[slot]) {
+      d.tflag[slot] = 0;
+      const float xj = X[slot], yj = Y[slot], zj = Z[slot];
+      const uint32_t idj = a.id ? (uint32_t)a.id[slot] : (uint32_t)slot;
+      unsigned long long best = kEmpty;
+      for_global_records(d, par, novf, xj, yj, zj, [&](float4 A) {
+        if (!(dist2(d, xj, yj, zj, A) < d.rc2)) return;
+        const int ida = __float_as_int(A.w);
+        const W4 r = philox(step, (uint32_t)ida, idj, 0u, d.seed);
+        if (!((unsigned long long)r.w0 < d.thresh)) return;
+        if ((uint32_t)d.slotA[ida] != idj) return;  // the A chose another T
+        if (d.rule.exclude && bonded(d, a, ida, idj)) return;
+        const unsigned long long bid = ((unsigned long long)r.w2 << 32) | (uint32_t)ida;
+        best = bid < best ? bid : best;
+      });
+      if (best != kEmpty) {
+        const int i = (int)(uint32_t)best;
+        const int sa = d.slot_of ? d.slot_of[i] : i;
+        a.st[sa] += d.rule.d_a;
+        const int32_t nt = a.st[slot] + d.rule.d_t;
+        a.st[slot] = nt;
+        int lost = 0;
+        if (!adj_append(a.adj + (size_t)sa * d.B, d.B, (int32_t)idj)) lost++;
+        if (!adj_append(a.adj + (size_t)slot * d.B, d.B, i)) lost++;
+        if (lost) atomicAdd(&s_lost, lost);
+        const int p = atomicAdd(&s_nw, 1);
+        if (p < kWinCap) {
+          pick(d.wgw, par)[w * kWinCap + p] = make_int2(i, (int)idj);
+        } else {
+          const uint32_t o = atomicAdd(&c->nwin_ovf[par], 1u);
+          pick(d.wov, par)[o] = make_int2(i, (int)idj);
+        }
+        // a T entering the A window joins the A list, unless an entry of an
+        // earlier stay in the window is still there (it is live again now)
+        if (d.sorted && is_a(d, a.typ[slot], nt) && !d.inlist[slot]) {
+          d.inlist[slot] = 1;
+          s_add[atomicAdd(&s_nadd, 1)] = slot;
+        }
+      }
+    }
+    __syncthreads();
+    const int nadd = s_nadd;
+    if (nadd) {
+      if (tid == 0) s_abase = (int)atomicAdd(&c->na, (uint32_t)nadd);
+      __syncthreads();
+      if (tid < nadd) d.alist[s_abase + tid] = s_add[tid];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    pick(d.wgo, par)[w * kWgOut + kOutBonds] = s_nw;
+    pick(d.wgo, par)[w * kWgOut + kOutLost] = s_lost;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Stateless single step: close it and sort its bonds by id_A into the
+// caller's buffer (one workgroup).
 // ---------------------------------------------------------------------------
 __device__ void bitonic_sort(unsigned long long* buf, int n2) {
   for (int k = 2; k <= n2; k <<= 1)
@@ -584,137 +801,144 @@ __device__ void bitonic_sort(unsigned long long* buf, int n2) {
     }
 }
 
-__device__ __forceinline__ bool adj_append(int32_t* row, int B, int32_t v) {
-  for (int b = 0; b < B; ++b)
-    if (row[b] < 0) {
-      row[b] = v;
-      return true;
-    }
-  return false;
-}
-
-__global__ __launch_bounds__(kTailThreads) void k_tail(Dev d) {
-  __shared__ unsigned long long wins[kSortLds];
-  __shared__ uint32_t s_nwin, s_ovf;
-  __shared__ long long s_sum[kWgStats];
-  Ctl* c = d.ctl;
+// After k_close and k_advance of the single step: its bonds (the whole log)
+// sorted by id_A into the caller's buffer.
+__global__ __launch_bounds__(kFinThreads) void k_single_sort(Dev d) {
+  __shared__ unsigned long long s_b[kSortLds];
+  const Ctl* c = d.ctl;
   if (read_err(c)) return;
-  const int tid = threadIdx.x, bs = blockDim.x;
-  const uint32_t step = c->step, cur = c->par, nxt = cur ^ 1u;
-  const uint32_t nprop = c->nprop;
-  const uint32_t a_elig = c->na[nxt];
-  if (tid == 0) {
-    s_nwin = 0;
-    s_ovf = 0;
-  }
-  if (tid < kWgStats) s_sum[tid] = 0;
-  __syncthreads();
-  // steps 6-7: every proposal bids for its T with (w2, id_A)
-  for (uint32_t k = tid; k < nprop; k += bs) {
-    const int i = d.propA[k];
-    const unsigned long long key =
-        __hip_atomic_load(&d.slotA[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t j = (uint32_t)key;
-    const W4 w = philox(step, (uint32_t)i, j, 0u, d.seed);
-    atomicMin(&d.slotT[j], ((unsigned long long)w.w2 << 32) | (uint32_t)i);
-  }
-  __threadfence();
-  __syncthreads();
-  for (uint32_t k = tid; k < nprop; k += bs) {
-    const int i = d.propA[k];
-    const unsigned long long key =
-        __hip_atomic_load(&d.slotA[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t j = (uint32_t)key;
-    const W4 w = philox(step, (uint32_t)i, j, 0u, d.seed);
-    const unsigned long long bid = ((unsigned long long)w.w2 << 32) | (uint32_t)i;
-    const unsigned long long best =
-        __hip_atomic_load(&d.slotT[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (best == bid) {
-      const uint32_t pos = atomicAdd(&s_nwin, 1u);
-      const unsigned long long v = ((unsigned long long)(uint32_t)i << 32) | j;
-      if (pos < (uint32_t)kSortLds) wins[pos] = v;
-      d.sortbuf[pos] = v;
-    }
-  }
-  __threadfence();
-  __syncthreads();
-  const uint32_t nwin = s_nwin;
+  const int64_t nb = (int64_t)c->log_n;
+  const int64_t m = nb < d.log_cap ? nb : d.log_cap;
   int n2 = 1;
-  while (n2 < (int)nwin) n2 <<= 1;
-  unsigned long long* buf = (n2 <= kSortLds) ? wins : d.sortbuf;
-  for (int t = (int)nwin + tid; t < n2; t += bs) buf[t] = kEmpty;
+  while (n2 < m) n2 <<= 1;
+  unsigned long long* buf = n2 <= kSortLds ? s_b : d.sortbuf;
+  for (int t = threadIdx.x; t < n2; t += blockDim.x)
+    buf[t] = t < m ? (((unsigned long long)(uint32_t)d.log[3 * t + 1] << 32) |
+                      (uint32_t)d.log[3 * t + 2])
+                   : kEmpty;
   __threadfence_block();
   __syncthreads();
-  if (nwin > 1) bitonic_sort(buf, n2);
-  // step 9: bonds in id_A order, states, adjacency, A-list additions
-  const uint64_t log0 = c->log_n;
-  for (uint32_t k = tid; k < nwin; k += bs) {
-    const unsigned long long v = buf[k];
-    const int i = (int)(v >> 32), j = (int)(uint32_t)v;
-    const int si = d.slot_of ? d.slot_of[i] : i;
-    const int sj = d.slot_of ? d.slot_of[j] : j;
-    d.st[si] += d.rule.d_a;
-    const int32_t nt = d.st[sj] + d.rule.d_t;
-    d.st[sj] = nt;
-    uint32_t lost = 0;
-    if (!adj_append(d.adj + (size_t)si * d.B, d.B, j)) lost++;
-    if (!adj_append(d.adj + (size_t)sj * d.B, d.B, i)) lost++;
-    if (lost) atomicAdd(&s_ovf, lost);
-    if (in_window(d.typ[sj], nt, d.rule.type_a, d.rule.a_min, d.rule.a_max)) {
-      const uint32_t p = atomicAdd(&c->na[nxt], 1u);
-      d.alist[nxt][p] = sj;
-    }
-    if (d.bonds && (int64_t)k < d.bonds_cap) {
-      d.bonds[2 * (size_t)k] = i;
-      d.bonds[2 * (size_t)k + 1] = j;
-    }
-    if (d.log) {
-      const uint64_t row = log0 + k;
-      if ((int64_t)row < d.log_cap) {
-        d.log[3 * row] = (int32_t)step;
-        d.log[3 * row + 1] = i;
-        d.log[3 * row + 2] = j;
-      }
-    }
+  if (m > 1) bitonic_sort(buf, n2);
+  for (int t = threadIdx.x; t < m && t < d.bonds_cap; t += blockDim.x) {
+    d.bonds[2 * t] = (int32_t)(buf[t] >> 32);
+    d.bonds[2 * t + 1] = (int32_t)(uint32_t)buf[t];
   }
-  // reset every touched selection slot
-  for (uint32_t k = tid; k < nprop; k += bs) {
-    const int i = d.propA[k];
-    const unsigned long long key = d.slotA[i];
-    d.slotT[(uint32_t)key] = kEmpty;
-    d.slotA[i] = kEmpty;
+}
+
+// ---------------------------------------------------------------------------
+// Spatial sort of the storage by brick (counting sort: count, scan, scatter),
+// which also rebuilds the A list in brick order.  Results never depend on the
+// storage order; the sort only gives each sweep workgroup a compact region.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int brick_of(const Dev& d, float x, float y, float z) {
+  if (d.nbricks == 1) return 0;
+  const int cx = cell1(__fmul_rn(x, d.inv_w), d.nc) / d.bs;
+  const int cy = cell1(__fmul_rn(y, d.inv_w), d.nc) / d.bs;
+  const int cz = cell1(__fmul_rn(z, d.inv_w), d.nc) / d.bs;
+  return (cz * d.nb + cy) * d.nb + cx;
+}
+
+// Ranks within bricks; lanes of a wavefront that share a brick take one
+// atomic together (storage is nearly sorted, so a wave spans few bricks).
+__global__ __launch_bounds__(kThreads) void k_sort_count(Dev d) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const Arr a = pick_set(d, d.ctl->set & 1u);
+  const uint32_t par = d.ctl->par0;
+  const bool active = k < d.n;
+  int b = -1;
+  bool isA = false;
+  if (active) {
+    b = brick_of(d, pick(a.x, par)[k], pick(a.y, par)[k], pick(a.z, par)[k]);
+    isA = is_a(d, a.typ[k], a.st[k]);
   }
-  // counters of the sweep workgroups
-  long long acc[kWgStats] = {0, 0, 0, 0};
-  for (int g = tid; g < d.nwg_sweep; g += bs)
-    for (int q = 0; q < kWgStats; ++q) acc[q] += d.wgst[g * kWgStats + q];
-  for (int q = 0; q < kWgStats; ++q)
-    if (acc[q]) atomicAdd((unsigned long long*)&s_sum[q], (unsigned long long)acc[q]);
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) {
-    const uint32_t sn = c->stats_n;
-    if (d.slog && (int64_t)sn < d.slog_cap) {
-      long long* r = d.slog + (size_t)sn * kStatsPerStep;
-      r[0] = a_elig;
-      r[1] = s_sum[0];
-      r[2] = s_sum[1];
-      r[3] = s_sum[2];
-      r[4] = s_sum[3];
-      r[5] = s_sum[2] - s_sum[3];
-      r[6] = nprop;
-      r[7] = nwin;
-      r[8] = s_ovf;
+  unsigned long long rem = __ballot(active);
+  while (rem) {
+    const int leader = __ffsll((long long)rem) - 1;
+    const int bl = __shfl(b, leader);
+    const unsigned long long same = __ballot(active && b == bl);
+    const unsigned long long sameA = __ballot(active && b == bl && isA);
+    uint32_t base = 0, abase = 0;
+    if (__lane_id() == leader) {
+      base = atomicAdd(&d.bcnt[bl], (uint32_t)__popcll(same));
+      if (sameA) abase = atomicAdd(&d.bacnt[bl], (uint32_t)__popcll(sameA));
     }
-    c->stats_n = sn + 1;
-    c->log_n = log0 + nwin;
-    c->nwin = nwin;
-    c->na[cur] = 0;
-    c->nprop = 0;
-    c->ovf_n = 0;
-    c->par = nxt;
-    c->step = step + 1;
+    base = __shfl(base, leader);
+    abase = __shfl(abase, leader);
+    if (active && b == bl) {
+      const unsigned long long lt = (1ull << __lane_id()) - 1ull;
+      d.rank[k] = (int32_t)(base + __popcll(same & lt));
+      d.arank[k] = isA ? (int32_t)(abase + __popcll(sameA & lt)) : -1;
+    }
+    rem &= ~same;
   }
+}
+
+__global__ __launch_bounds__(kFinThreads) void k_sort_scan(Dev d) {
+  __shared__ uint32_t s_wave[kFinThreads / 64 + 1];
+  uint32_t carry = 0, acarry = 0;
+  for (int base = 0; base < d.nbricks; base += blockDim.x) {
+    const int b = base + threadIdx.x;
+    const uint32_t v = b < d.nbricks ? d.bcnt[b] : 0u;
+    const uint32_t va = b < d.nbricks ? d.bacnt[b] : 0u;
+    uint32_t total = 0, atotal = 0;
+    const uint32_t ex = block_scan_excl(v, s_wave, total);
+    const uint32_t exa = block_scan_excl(va, s_wave, atotal);
+    if (b < d.nbricks) {
+      d.bstart[b] = (int32_t)(carry + ex);
+      d.astart[b] = (int32_t)(acarry + exa);
+      d.bcnt[b] = 0u;
+      d.bacnt[b] = 0u;
+    }
+    carry += total;
+    acarry += atotal;
+  }
+  if (threadIdx.x == 0) {
+    d.bstart[d.nbricks] = (int32_t)carry;
+    d.astart[d.nbricks] = (int32_t)acarry;
+    d.ctl->na = acarry;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_sort_scatter(Dev d) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= d.n) return;
+  const uint32_t s = d.ctl->set & 1u, par = d.ctl->par0;
+  const Arr a = pick_set(d, s), o = pick_set(d, s ^ 1u);
+  const float x = pick(a.x, par)[k], y = pick(a.y, par)[k], z = pick(a.z, par)[k];
+  const int b = brick_of(d, x, y, z);
+  const int ns = d.bstart[b] + d.rank[k];
+  pick(o.x, par)[ns] = x;
+  pick(o.y, par)[ns] = y;
+  pick(o.z, par)[ns] = z;
+  o.typ[ns] = a.typ[k];
+  o.st[ns] = a.st[k];
+  const int id = a.id[k];
+  o.id[ns] = id;
+  d.slot_of[id] = ns;
+  for (int q = 0; q < d.B; ++q) o.adj[(size_t)ns * d.B + q] = a.adj[(size_t)k * d.B + q];
+  const int ar = d.arank[k];
+  d.inlist[ns] = ar >= 0 ? 1 : 0;
+  if (ar >= 0) d.alist[d.astart[b] + ar] = ns;
+}
+
+__global__ void k_sort_flip(Ctl* c) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) c->set ^= 1u;
+}
+
+// Storage order -> particle-id order (positions of the current parity).
+__global__ __launch_bounds__(kThreads) void k_gather_out(Dev d, float* ox, float* oy, float* oz,
+                                                         int32_t* ost, int32_t* oadj) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= d.n) return;
+  const Arr a = pick_set(d, d.ctl->set & 1u);
+  const uint32_t par = d.ctl->par0;
+  const int id = a.id[k];
+  if (ox) ox[id] = pick(a.x, par)[k];
+  if (oy) oy[id] = pick(a.y, par)[k];
+  if (oz) oz[id] = pick(a.z, par)[k];
+  if (ost) ost[id] = a.st[k];
+  if (oadj)
+    for (int b = 0; b < d.B; ++b) oadj[(size_t)id * d.B + b] = a.adj[(size_t)k * d.B + b];
 }
 
 // ---------------------------------------------------------------------------
@@ -728,63 +952,73 @@ hipError_t launch_ctl_reset(Ctl* c, uint32_t step, int full, hipStream_t s) {
 }
 
 hipError_t launch_classify(const Dev& d, hipStream_t s) {
-  if (d.n > 0) k_classify<<<blocks_for(d.n, 256), 256, 0, s>>>(d);
+  if (d.n > 0) k_classify<<<blocks_for(d.n, kThreads), kThreads, 0, s>>>(d);
   return hipGetLastError();
 }
 
-hipError_t launch_jitter(const Dev& d, hipStream_t s) {
-  if (d.n > 0) k_jitter<<<blocks_for(d.n, 256), 256, 0, s>>>(d);
+hipError_t launch_identity(const Dev& d, hipStream_t s) {
+  if (d.n > 0) k_identity<<<blocks_for(d.n, kThreads), kThreads, 0, s>>>(d);
   return hipGetLastError();
 }
 
 hipError_t launch_generate(const Dev& d, int kind, unsigned long long gseed, float c0, float a,
                            int nl, unsigned long long thr, hipStream_t s) {
-  if (d.n > 0) k_generate<<<blocks_for(d.n, 256), 256, 0, s>>>(d, kind, gseed, c0, a, nl, thr);
+  if (d.n > 0)
+    k_generate<<<blocks_for(d.n, kThreads), kThreads, 0, s>>>(d, kind, gseed, c0, a, nl, thr);
   return hipGetLastError();
 }
 
-int abin_blocks(const Dev& d, long long na_hint) {
-  long long b = blocks_for(na_hint > 0 ? na_hint : 1, 256);
-  if (b < 64) b = 64;
-  if (b > 4096) b = 4096;
-  (void)d;
+// A-bin grid: fixed (it is captured into graphs); sized for the expected
+// work, grid-stride beyond.
+int abin_blocks(long long work) {
+  long long b = blocks_for(work > 0 ? work : 1, kThreads);
+  if (b < 16) b = 16;
+  if (b > kAbinMax) b = kAbinMax;
   return (int)b;
 }
 
-hipError_t launch_step(const Dev& d, int abin_grid, hipStream_t s, hipEvent_t ev_sweep0,
+// Step k of a block: prep (with the closing of step k - 1), sweep, resolve.
+hipError_t launch_step(const Dev& d, int k, hipStream_t s, hipEvent_t ev_sweep0,
                        hipEvent_t ev_sweep1) {
-  k_abin<<<abin_grid, 256, 0, s>>>(d);
+  const int prep_blocks = d.nwg_jit + d.nwg_abin + (k > 0 ? d.ngroups : 0);
+  k_prep<<<prep_blocks, kThreads, 0, s>>>(d, k);
   if (ev_sweep0) (void)hipEventRecord(ev_sweep0, s);
   if (d.sorted)
-    k_sweep_brick<<<d.nbricks, kSweepThreads, 0, s>>>(d);
+    k_sweep<true><<<d.nwg_sweep, kThreads, 0, s>>>(d, k);
   else
-    k_sweep<<<blocks_for(d.n, kSweepThreads), kSweepThreads, 0, s>>>(d);
+    k_sweep<false><<<d.nwg_sweep, kThreads, 0, s>>>(d, k);
   if (ev_sweep1) (void)hipEventRecord(ev_sweep1, s);
-  k_tail<<<1, kTailThreads, 0, s>>>(d);
+  if (d.sorted)
+    k_resolve<true><<<d.nwg_sweep, kThreads, 0, s>>>(d, k);
+  else
+    k_resolve<false><<<d.nwg_sweep, kThreads, 0, s>>>(d, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_end(const Dev& d, int K, hipStream_t s) {
+  k_close<<<d.ngroups, kThreads, 0, s>>>(d, K - 1);
+  k_advance<<<1, 64, 0, s>>>(d.ctl, K);
+  return hipGetLastError();
+}
+
+hipError_t launch_single_end(const Dev& d, hipStream_t s) {
+  k_close<<<d.ngroups, kThreads, 0, s>>>(d, 0);
+  k_advance<<<1, 64, 0, s>>>(d.ctl, 1);
+  k_single_sort<<<1, kFinThreads, 0, s>>>(d);
   return hipGetLastError();
 }
 
 hipError_t launch_sort(const Dev& d, hipStream_t s) {
-  k_sort_count<<<blocks_for(d.n, 256), 256, 0, s>>>(d);
-  k_sort_scan<<<1, 1024, 0, s>>>(d);
-  k_sort_scatter<<<blocks_for(d.n, 256), 256, 0, s>>>(d);
-  return hipGetLastError();
-}
-
-// after the caller swapped the primary and secondary buffers
-hipError_t launch_alist_rebuild(const Dev& d, hipStream_t s) {
-  k_alist_rebuild<<<blocks_for(d.n, 256), 256, 0, s>>>(d);
-  return hipGetLastError();
-}
-
-hipError_t launch_identity(const Dev& d, hipStream_t s) {
-  k_identity<<<blocks_for(d.n, 256), 256, 0, s>>>(d);
+  k_sort_count<<<blocks_for(d.n, kThreads), kThreads, 0, s>>>(d);
+  k_sort_scan<<<1, kFinThreads, 0, s>>>(d);
+  k_sort_scatter<<<blocks_for(d.n, kThreads), kThreads, 0, s>>>(d);
+  k_sort_flip<<<1, 64, 0, s>>>(d.ctl);
   return hipGetLastError();
 }
 
 hipError_t launch_gather_out(const Dev& d, float* ox, float* oy, float* oz, int32_t* ost,
                              int32_t* oadj, hipStream_t s) {
-  k_gather_out<<<blocks_for(d.n, 256), 256, 0, s>>>(d, ox, oy, oz, ost, oadj);
+  k_gather_out<<<blocks_for(d.n, kThreads), kThreads, 0, s>>>(d, ox, oy, oz, ost, oadj);
   return hipGetLastError();
 }
 

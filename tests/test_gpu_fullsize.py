@@ -79,9 +79,14 @@ def test_many_steps_invariants(name, steps):
         assert np.array_equal(host["state"] - out["state"], deg)
         assert np.all(host["type"][log[:, 1]] == 1) and np.all(host["type"][log[:, 2]] == 0)
     else:
-        # chain growth: every monomer bonds first as T (0 -> 2) then as A (2 -> 1)
-        assert np.all(np.isin(out["state"], [0, 1, 2]))
-        assert np.array_equal(out["state"] == 0, deg == 0)
+        # chain growth: a free monomer bonds first as T (0 -> 2, one bond) then
+        # as A (2 -> 1, two bonds); an initiator bonds once, as A (2 -> 1)
+        st0, st1 = host["state"], out["state"]
+        assert np.all(np.isin(st1, [0, 1, 2]))
+        expect = np.where(st0 == 0, np.select([st1 == 0, st1 == 2, st1 == 1], [0, 1, 2]),
+                          np.where(st1 == 1, 1, 0))
+        assert np.all((st0 == 0) | (st1 != 0))
+        assert np.array_equal(deg, expect)
     adj = out["adj"]
     assert np.array_equal((adj >= 0).sum(1), deg)
     rows = np.repeat(np.arange(c.N), adj.shape[1])

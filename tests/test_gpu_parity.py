@@ -161,12 +161,13 @@ def test_device_generator_matches_host(B):
         s.close()
 
 
-def _run_both(cfg, rule, seed, first, steps, sigma, sort_period=0):
+def _run_both(cfg, rule, seed, first, steps, sigma, sort_period=0, graphs=True):
     from paper_1409_7498_amd import binding
     n, Bw = len(cfg["x"]), cfg["adj"].shape[1]
-    say("run_both", "n=%d steps=%d sort=%d" % (n, steps, sort_period))
-    s = binding.System(n, cfg["L"], Bw, rule, seed, log_cap=4 * n)
+    say("run_both", "n=%d steps=%d sort=%d graphs=%d" % (n, steps, sort_period, graphs))
+    s = binding.System(n, cfg["L"], Bw, rule, seed, log_cap=8 * n)
     s.set_sort_period(sort_period)
+    s.set_graphs(graphs)
     s.load(cfg)
     s.run(first, steps, sigma)
     out, log, st = s.read(), s.bonds(), s.stats()
@@ -184,12 +185,37 @@ def _run_both(cfg, rule, seed, first, steps, sigma, sort_period=0):
     return log
 
 
-@pytest.mark.parametrize("sort_period", [0, 1, 16])
-def test_c1_full_run(B, sort_period):
+@pytest.mark.parametrize("sort_period,graphs", [(0, False), (1, True), (16, True), (16, False),
+                                               (0, True), (64, True)])
+def test_c1_full_run(B, sort_period, graphs):
     c = workload.CONFIGS["c1"]
     cfg = gen(c.N, c.L, c.kind, c.seed)
-    log = _run_both(cfg, c.rule(), c.seed, 1, c.steps, c.sigma, sort_period)
+    log = _run_both(cfg, c.rule(), c.seed, 1, c.steps, c.sigma, sort_period, graphs)
     assert len(log) > 200
+
+
+@pytest.mark.parametrize("sort_period", [1000, 5])
+def test_a_list_growth_and_compaction(B, sort_period):
+    """Chain growth with half the particles active and p = 1: the A list gains
+    an entry per bond; with rare sorts it must be compacted in place."""
+    N = 4000
+    cfg = gen(N, workload.box_for(N), "chain", 61)
+    cfg["state"][np.random.default_rng(61).choice(N, N // 2, replace=False)] = 2
+    _run_both(cfg, _rule("chain", 1.0), 61, 1, 30, 0.05, sort_period)
+
+
+@pytest.mark.parametrize("sort_period", [1000, 3, 0])
+def test_window_reentry_rule(B, sort_period):
+    """A rule under which particles leave and re-enter the A window between
+    sorts (A: state 2 -> 1, T: state 0/1 -> +1): no duplicate A entries."""
+    N = 4000
+    rng = np.random.default_rng(71)
+    cfg = gen(N, workload.box_for(N), "chain", 71)
+    cfg["state"] = rng.integers(0, 3, N).astype(np.int32)
+    cfg["adj"] = np.full((N, 32), -1, np.int32)
+    rule = dict(type_a=0, a_min=2, a_max=2, d_a=-1, type_t=0, t_min=0, t_max=1, d_t=1,
+                rc=1.12, p=0.5, exclude_bonded=1)
+    _run_both(cfg, rule, 71, 1, 25, 0.05, sort_period)
 
 
 @pytest.mark.parametrize("sort_period", [0, 10])
