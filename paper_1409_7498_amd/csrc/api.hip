@@ -101,6 +101,7 @@ void set_geometry(Dev& d, int32_t n, float L, int32_t B, const pr_rule* r, uint6
                  r->exclude_bonded};
   d.nwg_sweep = sweep_blocks(n);
   d.nwg_abin = abin_blocks(n);
+  d.adj_staged = B <= kAdjStage ? 1 : 0;
   d.jit_c = 0.0f;
   d.part = nullptr;
   d.part_cap = 0;
@@ -144,11 +145,16 @@ int alloc_scratch(Arena& a, Dev& d, int32_t n, int32_t nwg, hipStream_t s) {
   if ((e = a.alloc(&d.alist, n)) || (e = a.alloc(&d.inlist, n)) || (e = a.alloc(&d.tflag, n)))
     return e;
   if ((e = a.alloc(&d.cnt[0], d.ncell)) || (e = a.alloc(&d.cnt[1], d.ncell))) return e;
-  if ((e = a.alloc(&d.rec, (size_t)d.ncell * kCellCap))) return e;
+  const size_t nrec = (size_t)d.ncell * kCellCap;
+  if ((e = a.alloc(&d.rec, nrec)) || (e = a.alloc(&d.rsa, nrec)) ||
+      (e = a.alloc(&d.radj, nrec)))
+    return e;
   if ((e = a.alloc(&d.slotA, n))) return e;
   for (int p = 0; p < 2; ++p) {
-    if ((e = a.alloc(&d.ovf[p], n)) || (e = a.alloc(&d.wgp[p], (size_t)nwg * kPropCap)) ||
-        (e = a.alloc(&d.wgo[p], (size_t)nwg * kWgOut)) || (e = a.alloc(&d.povf[p], n)) ||
+    if ((e = a.alloc(&d.ovf[p], n)) || (e = a.alloc(&d.ovf_sa[p], n)) ||
+        (e = a.alloc(&d.wgo[p], (size_t)nwg * kWgOut)) ||
+        (e = a.alloc(&d.wge[p], (size_t)nwg * kRetCap)) ||
+        (e = a.alloc(&d.wgk[p], (size_t)nwg * kRetCap)) ||
         (e = a.alloc(&d.wgw[p], (size_t)nwg * kWinCap)) || (e = a.alloc(&d.wov[p], n / 2 + 1)) ||
         (e = a.alloc(&d.abst[p], kAbinMax)))
       return e;
@@ -250,6 +256,7 @@ int pr_react_step(int32_t n, float L, const float* x, const float* y, const floa
   d.thresh = geo.thresh;
   d.seed = geo.seed;
   d.rule = geo.rule;
+  d.adj_staged = geo.adj_staged;
   d.nwg_sweep = geo.nwg_sweep;
   d.nwg_abin = geo.nwg_abin;
   d.nwg_jit = 0;

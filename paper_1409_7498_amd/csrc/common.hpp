@@ -20,18 +20,20 @@ constexpr int kStatsPerStep = 9;    // pr_stats fields
 constexpr int kGroup = 256;         // sweep workgroups closed by one closing workgroup
 constexpr int kPart = 8;            // partial counters per closing workgroup and step
 constexpr int kWgOut = 8;           // per sweep workgroup counters (see WgOut)
-constexpr int kPropCap = 32;        // first-touched A's a sweep workgroup keeps in place
+constexpr int kRetCap = 32;         // retained pairs a sweep workgroup hands to the resolve
 constexpr int kWinCap = 16;         // bonds a resolve workgroup stages in place
+constexpr int kAdjStage = 4;        // adjacency rows up to this width travel with A records
 constexpr int kAbinMax = 2048;      // A-bin workgroups at most (grid-stride beyond)
 // Spatially sorted storage: particles are kept ordered by "brick" (a block of
 // bs^3 coarse cells); one sweep workgroup owns a brick and stages the A
 // records of the brick plus one halo cell layer in LDS.
 constexpr int kMaxBrick = 4;
 constexpr int kStageCells = (kMaxBrick + 2) * (kMaxBrick + 2) * (kMaxBrick + 2);
-constexpr int kStageRecs = 512;
-constexpr int kQueue = 1024;        // in-range pairs queued per chunk of kThreads particles
+constexpr int kStageRecs = 256;
+constexpr int kTPass = 768;         // particles a sweep workgroup holds per pass (3 per thread)
+constexpr int kQueue = 512;         // in-range pairs queued per pass
 
-enum WgOut { kOutTElig = 0, kOutInRc, kOutDrawn, kOutExcl, kOutProp, kOutBonds, kOutLost };
+enum WgOut { kOutTElig = 0, kOutInRc, kOutDrawn, kOutExcl, kOutRet, kOutProp, kOutBonds, kOutLost };
 
 // Device control block.  Steps are launched in blocks of K steps; the kernels
 // of step k of a block use step0 + k and parity (par0 + k) & 1, so a captured
@@ -43,7 +45,7 @@ struct Ctl {
   uint32_t set;        // which of the two storage sets holds the particles
   uint32_t na;         // A-list length (entries may have left the A window)
   uint32_t ovf_n[2];   // A records beyond their cell bucket, by parity
-  uint32_t nprop_ovf[2];  // first-touched A's beyond kPropCap, by parity
+  uint32_t ret_ovf[2];    // retained pairs beyond kRetCap (the resolve then re-enumerates)
   uint32_t nwin_ovf[2];   // bonds beyond kWinCap, by parity
   uint32_t stats_n0;   // counter-log index of the block's first step
   uint64_t log_n;      // rows appended to the bond log (may exceed capacity)
@@ -68,15 +70,21 @@ struct Dev {
   int32_t* slot_of;     // id -> slot (nullptr: identity)
   int32_t* alist;       // slots of particles in the A window (capacity n)
   uint8_t* inlist;      // per slot: has an entry in the A list (live or not)
-  // A grid: per-cell counts by parity, bucket records, overflow records
+  // A grid: per-cell counts by parity; bucket records (x, y, z, id), the
+  // A's slot and (rows of width <= kAdjStage) its adjacency row; overflow
+  // records and slots
   uint32_t* cnt[2];
   float4 *rec, *ovf[2];
-  // selection: per-id minimum key (w1, id_T) of the A side
+  int32_t *rsa, *ovf_sa[2];
+  int4* radj;
+  // selection: per-id minimum key (w1, id_T) of the A side; the resolve
+  // empties the key it reads back as its own
   unsigned long long* slotA;
-  // per sweep workgroup, by parity: first-touched A's and counters
-  int32_t* wgp[2];
+  // per sweep workgroup, by parity: counters and retained pairs
+  // (id_A, slot_A, slot_T, id_T) with their w2 words
   int32_t* wgo[2];
-  int32_t* povf[2];     // first-touched A's beyond kPropCap (capacity n each)
+  int4* wge[2];
+  uint32_t* wgk[2];
   uint8_t* tflag;       // per slot: this T has a retained pair in the current step
   int2* wgw[2];         // staged bonds (id_A, id_T), kWinCap per workgroup, by parity
   int2* wov[2];         // staged bonds beyond kWinCap (capacity n/2 + 1 each)
@@ -98,6 +106,7 @@ struct Dev {
   int32_t n, B, nc, ncell, nwg_sweep, nwg_abin, nwg_jit, ngroups;
   int32_t bs, nb, nbricks, sorted;  // brick edge (cells), bricks per side, total, storage sorted
   int32_t jitter;       // 1: resident system (positions ping-pong, re-jitter by jit_c)
+  int32_t adj_staged;   // B <= kAdjStage: records carry the adjacency row
   float L, halfL, rc2, inv_w, jit_c;
   unsigned long long thresh, seed;
   RuleD rule;

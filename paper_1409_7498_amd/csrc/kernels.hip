@@ -2,21 +2,20 @@
 //
 // One reaction step is three kernels (Table I of the paper, steps 1-9, on one
 // GPU; the communication steps 4, 6 and 8 have nothing to exchange):
-//   k_prep     re-jitter of every particle (the MD stand-in between steps;
-//              positions ping-pong between two buffers) fused with the binning
-//              of the A-role particles into coarse cells of width >= 2 rc (each
-//              A's jittered position is recomputed from the same draws); one
-//              extra workgroup closes the previous step (counters, bond rows,
-//              reset of the touched selection keys)
+//   k_prep     closes the previous step (counters, bond rows), bins the
+//              A-role particles into coarse cells of width >= 2 rc (record:
+//              jittered position, id, slot, adjacency row) and re-jitters every
+//              particle (the MD stand-in between steps; positions ping-pong
+//              between two buffers)
 //   k_sweep    every particle streams once with coalesced SoA loads (in brick
-//              order once the storage is sorted, the brick's A records staged in
-//              LDS); in-range pairs (step 1) go to an LDS queue so that the keyed
-//              Philox draws (step 2) run on full wavefronts; each retained pair
-//              lowers its A's key (w1, id_T) by a 64-bit atomicMin (steps 3-5)
-//              and flags its T
-//   k_resolve  each flagged T enumerates its retained pairs again, keeps those
-//              whose A chose it and takes the smallest (w2, id_A) (steps 6-7):
-//              that pair is bonded, states and adjacency updated (step 9)
+//              order once the storage is sorted, the A records of the brick and
+//              its halo staged in LDS); in-range pairs (step 1) go to an LDS
+//              queue so that the keyed Philox draws (step 2) run on full
+//              wavefronts; each retained pair lowers its A's key (w1, id_T) by
+//              a 64-bit atomicMin (steps 3-5) and joins the workgroup's list
+//   k_resolve  per workgroup, the listed pairs whose A chose their T; of those
+//              the smallest (w2, id_A) per T is bonded, states and adjacency
+//              updated (steps 6-9)
 // plus the counting sort of the storage by brick, the synthetic generator and
 // the helpers of the runtime.
 //
@@ -82,10 +81,10 @@ __device__ __forceinline__ float wrap_box(float v, float L) {
   return v;
 }
 
+// Single conditional wrap of a difference (selects, no branches).
 __device__ __forceinline__ float min_image(float d, float L, float halfL) {
-  if (d > halfL) d = __fsub_rn(d, L);
-  else if (d < -halfL) d = __fadd_rn(d, L);
-  return d;
+  const float dn = __fsub_rn(d, L), up = __fadd_rn(d, L);
+  return d > halfL ? dn : (d < -halfL ? up : d);
 }
 
 __device__ __forceinline__ bool in_window(int32_t t, int32_t s, int32_t type, int32_t lo,
@@ -120,15 +119,15 @@ __device__ __forceinline__ int32_t read_err(const Ctl* c) {
   return __hip_atomic_load(&c->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Element p (0 or 1) of a two-element array held in the kernel argument,
-// chosen without dynamic indexing (which would copy the argument to scratch).
-// Both pointers are read and combined with a mask, so that no address select
-// (and no copy of the aggregate to scratch) is formed.
+// Element p (0 or 1) of a two-element array held in the kernel argument:
+// both pointers are read and one selected, without dynamic indexing (which
+// would copy the argument to scratch); the select keeps the pointers in the
+// global address space.
 template <typename T>
 __device__ __forceinline__ T* pick(T* const (&v)[2], uint32_t p) {
-  const unsigned long long a = (unsigned long long)v[0], b = (unsigned long long)v[1];
-  const unsigned long long m = 0ull - (unsigned long long)(p & 1u);
-  return (T*)((a & ~m) | (b & m));
+  T* const a = v[0];
+  T* const b = v[1];
+  return (p & 1u) ? b : a;
 }
 
 // Storage set s, member by member (a select of the whole aggregate would be
@@ -201,7 +200,7 @@ __global__ void k_ctl_reset(Ctl* c, uint32_t step, int full) {
       c->na = 0;
       for (int p = 0; p < 2; ++p) {
         c->ovf_n[p] = 0;
-        c->nprop_ovf[p] = 0;
+        c->ret_ovf[p] = 0;
         c->nwin_ovf[p] = 0;
       }
       c->stats_n0 = 0;
@@ -265,11 +264,11 @@ __global__ __launch_bounds__(kThreads) void k_generate(Dev d, int kind, unsigned
 
 // ---------------------------------------------------------------------------
 // Closing a step, group g (one workgroup of kThreads): the counters of sweep
-// workgroups g*kGroup .. +kGroup summed into the step's partial record, their
-// staged bonds appended to the bond log (one reservation per group; rows of a
-// step end up in group order and readers order them by id_A), and the A-side
-// keys they touched reset.  Group 0 also takes the overflow lists and resets
-// the step's per-parity counters.
+// workgroups g*kGroup .. +kGroup summed into the step's partial record and
+// their staged bonds appended to the bond log (one reservation per group; rows
+// of a step end up in group order and readers order them by id_A).  Group 0
+// also takes the bonds beyond the staging windows and resets the step's
+// per-parity counters.
 // ---------------------------------------------------------------------------
 __device__ void close_group(const Dev& d, uint32_t par, uint32_t step, uint32_t sidx, int g,
                             uint32_t* s_wave) {
@@ -279,13 +278,11 @@ __device__ void close_group(const Dev& d, uint32_t par, uint32_t step, uint32_t 
   const int tid = threadIdx.x;
   if (tid < kPart) s_sum[tid] = 0;
   const int w = g * kGroup + tid;
-  int o[7] = {0, 0, 0, 0, 0, 0, 0};
+  int o[kWgOut] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (w < d.nwg_sweep) {
     const int32_t* src = pick(d.wgo, par) + w * kWgOut;
-    for (int q = 0; q < 7; ++q) o[q] = src[q];
-    const int np = o[kOutProp] < kPropCap ? o[kOutProp] : kPropCap;
-    const int32_t* props = pick(d.wgp, par) + w * kPropCap;
-    for (int e = 0; e < np; ++e) d.slotA[props[e]] = kEmpty;
+#pragma unroll
+    for (int q = 0; q < kWgOut; ++q) o[q] = src[q];
   }
   int a_elig = 0;  // the A-bin workgroup counts, strided over the groups
   for (int q = w; q < d.nwg_abin; q += d.ngroups * kGroup) a_elig += pick(d.abst, par)[q];
@@ -295,9 +292,12 @@ __device__ void close_group(const Dev& d, uint32_t par, uint32_t step, uint32_t 
   const uint32_t nwov = g == 0 ? c->nwin_ovf[par] : 0u;
   if (tid == 0 && tot + nwov > 0) s_row = atomicAdd((unsigned long long*)&c->log_n,
                                                     (unsigned long long)(tot + nwov));
-  if (a_elig) atomicAdd(&s_sum[0], a_elig);
-  for (int q = 0; q < 7; ++q)
-    if (o[q]) atomicAdd(&s_sum[q + 1], o[q]);
+  // partial layout: a_elig, t_elig, in_rc, drawn, excluded, proposals, bonds, lost
+  const int v[kPart] = {a_elig,         o[kOutTElig], o[kOutInRc], o[kOutDrawn],
+                        o[kOutExcl],    o[kOutProp],  o[kOutBonds], o[kOutLost]};
+#pragma unroll
+  for (int q = 0; q < kPart; ++q)
+    if (v[q]) atomicAdd(&s_sum[q], v[q]);
   __syncthreads();
   const uint64_t row0 = s_row;
   const int2* staged = pick(d.wgw, par) + w * kWinCap;
@@ -320,21 +320,21 @@ __device__ void close_group(const Dev& d, uint32_t par, uint32_t step, uint32_t 
         d.log[3 * row + 2] = b.y;
       }
     }
-    const uint32_t novf = c->nprop_ovf[par];
-    for (uint32_t e = tid; e < novf; e += blockDim.x) d.slotA[pick(d.povf, par)[e]] = kEmpty;
   }
   __syncthreads();
   if (tid < kPart && (int64_t)sidx < d.part_cap)
     d.part[((size_t)sidx * d.ngroups + g) * kPart + tid] = s_sum[tid];
   if (g == 0 && tid == 0) {
     c->ovf_n[par] = 0;
-    c->nprop_ovf[par] = 0;
+    c->ret_ovf[par] = 0;
     c->nwin_ovf[par] = 0;
   }
 }
 
 // ---------------------------------------------------------------------------
-// k_prep: [jitter blocks][A-bin blocks][closing groups of step k - 1 when k > 0].
+// k_prep: [closing groups of step k - 1 when k > 0][A-bin blocks][jitter
+// blocks].  The latency-bound closing and binning blocks come first so that
+// they are dispatched before the streaming jitter blocks.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void jittered(const Dev& d, const Arr& a, uint32_t par, uint32_t step,
                                          int slot, float& x, float& y, float& z) {
@@ -356,25 +356,20 @@ __global__ __launch_bounds__(kThreads) void k_prep(Dev d, int k) {
   __shared__ uint32_t s_wave[kThreads / 64 + 1];
   const StepInfo si = step_info(d.ctl, k);
   const Arr a = pick_set(d, d.ctl->set & 1u);
-  const int b = blockIdx.x;
-  if (b < d.nwg_jit) {  // re-jitter: positions of parity par -> par ^ 1
-    const int i = b * kThreads + threadIdx.x;
-    if (i >= d.n || read_err(d.ctl)) return;
-    float x, y, z;
-    jittered(d, a, si.par, si.step, i, x, y, z);
-    pick(a.x, si.par ^ 1u)[i] = x;
-    pick(a.y, si.par ^ 1u)[i] = y;
-    pick(a.z, si.par ^ 1u)[i] = z;
+  const int ncl = k > 0 ? d.ngroups : 0;
+  int b = blockIdx.x;
+  if (b < ncl) {  // closing groups of the previous step of the block
+    close_group(d, si.par ^ 1u, si.step - 1u, d.ctl->stats_n0 + (uint32_t)k - 1u, b, s_wave);
     return;
   }
-  if (b < d.nwg_jit + d.nwg_abin) {  // A particles -> cell buckets
-    const int g = b - d.nwg_jit;
+  b -= ncl;
+  if (b < d.nwg_abin) {  // A particles -> cell buckets
     if (threadIdx.x == 0) s_na = 0;
     __syncthreads();
     if (read_err(d.ctl) == 0) {
       const uint32_t total = d.sorted ? d.ctl->na : (uint32_t)d.n;
       int mine = 0;
-      for (uint32_t q = g * kThreads + threadIdx.x; q < total; q += d.nwg_abin * kThreads) {
+      for (uint32_t q = b * kThreads + threadIdx.x; q < total; q += d.nwg_abin * kThreads) {
         const int slot = d.sorted ? d.alist[q] : (int)q;
         if (!is_a(d, a.typ[slot], a.st[slot])) continue;
         mine++;
@@ -385,21 +380,38 @@ __global__ __launch_bounds__(kThreads) void k_prep(Dev d, int k) {
         const uint32_t r = atomicAdd(&pick(d.cnt, si.par)[c], 1u);
         const float4 rec = make_float4(x, y, z, __int_as_float(id));
         if (r < (uint32_t)kCellCap) {
-          d.rec[(size_t)c * kCellCap + r] = rec;
+          const size_t ri = (size_t)c * kCellCap + r;
+          d.rec[ri] = rec;
+          d.rsa[ri] = slot;
+          if (d.adj_staged) {
+            const int32_t* row = a.adj + (size_t)slot * d.B;
+            int4 q4 = make_int4(row[0], -1, -1, -1);
+            if (d.B > 1) q4.y = row[1];
+            if (d.B > 2) q4.z = row[2];
+            if (d.B > 3) q4.w = row[3];
+            d.radj[ri] = q4;
+          }
         } else {
           const uint32_t o = atomicAdd(&d.ctl->ovf_n[si.par], 1u);
           pick(d.ovf, si.par)[o] = rec;
+          pick(d.ovf_sa, si.par)[o] = slot;
         }
       }
       if (mine) atomicAdd(&s_na, mine);
     }
     __syncthreads();
-    if (threadIdx.x == 0) pick(d.abst, si.par)[g] = s_na;
+    if (threadIdx.x == 0) pick(d.abst, si.par)[b] = s_na;
     return;
   }
-  // closing groups of the previous step of the block
-  close_group(d, si.par ^ 1u, si.step - 1u, d.ctl->stats_n0 + (uint32_t)k - 1u,
-              b - d.nwg_jit - d.nwg_abin, s_wave);
+  b -= d.nwg_abin;
+  // re-jitter: positions of parity par -> par ^ 1
+  const int i = b * kThreads + threadIdx.x;
+  if (i >= d.n || read_err(d.ctl)) return;
+  float x, y, z;
+  jittered(d, a, si.par, si.step, i, x, y, z);
+  pick(a.x, si.par ^ 1u)[i] = x;
+  pick(a.y, si.par ^ 1u)[i] = y;
+  pick(a.z, si.par ^ 1u)[i] = z;
 }
 
 // Closes step k of the block (one workgroup per closing group).
@@ -437,16 +449,14 @@ __device__ __forceinline__ float dist2(const Dev& d, float xj, float yj, float z
   return __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz));
 }
 
-__device__ __forceinline__ bool bonded(const Dev& d, const Arr& a, int ida, uint32_t idj) {
-  const int sa = d.slot_of ? d.slot_of[ida] : ida;
-  const int32_t* row = a.adj + (size_t)sa * d.B;
-  for (int b = 0; b < d.B; ++b)
-    if (row[b] == (int32_t)idj) return true;
+__device__ __forceinline__ bool row_has(const int32_t* row, int B, int32_t v) {
+  for (int b = 0; b < B; ++b)
+    if (row[b] == v) return true;
   return false;
 }
 
-// Visits the A records of the 2x2x2 cell block around (x, y, z) in the global
-// buckets, then the overflow list.
+// Visits the A records (record, slot of the A) of the 2x2x2 cell block around
+// (x, y, z) in the global buckets, then the overflow list.
 template <typename F>
 __device__ __forceinline__ void for_global_records(const Dev& d, uint32_t par, uint32_t novf,
                                                    float x, float y, float z, F f) {
@@ -463,11 +473,12 @@ __device__ __forceinline__ void for_global_records(const Dev& d, uint32_t par, u
     const int c = ((ia ? cz1 : cz0) * nc + (ib ? cy1 : cy0)) * nc + (ie ? cx1 : cx0);
     uint32_t nr = pick(d.cnt, par)[c];
     nr = nr < (uint32_t)kCellCap ? nr : (uint32_t)kCellCap;
-    const float4* rec = d.rec + (size_t)c * kCellCap;
-    for (uint32_t r = 0; r < nr; ++r) f(rec[r]);
+    const size_t r0 = (size_t)c * kCellCap;
+    for (uint32_t r = 0; r < nr; ++r) f(d.rec[r0 + r], d.rsa[r0 + r]);
   }
   const float4* ovf = pick(d.ovf, par);
-  for (uint32_t r = 0; r < novf; ++r) f(ovf[r]);
+  const int32_t* osa = pick(d.ovf_sa, par);
+  for (uint32_t r = 0; r < novf; ++r) f(ovf[r], osa[r]);
 }
 
 // Staged region of a brick along one dimension: the brick's cells plus one
@@ -501,77 +512,119 @@ __device__ __forceinline__ void range_of(const Dev& d, int w, int& s0, int& s1) 
   }
 }
 
-// Draw, exclusion and A-side choice of an in-range pair (steps 2-5); the first
-// T to touch an A records it for the reset of its key.
+// Draw, exclusion and A-side choice of an in-range pair (steps 2-5).  A
+// retained pair lowers the A's key (w1, id_T) with a 64-bit atomicMin whose
+// result is not needed, flags its T and is handed to the resolve in the
+// workgroup's list.  arow: the A's adjacency row staged with its record
+// (nullptr: the row is read from the particle arrays).
 struct SweepAcc {
   int t_elig, in_rc, drawn, excl;
 };
 
-__device__ __forceinline__ void retain(const Dev& d, const Arr& a, uint32_t step, uint32_t par,
-                                       int ida, uint32_t idj, int sj, SweepAcc& n, int* s_np) {
+struct RetList {
+  int* n;
+  int4* ent;
+  uint32_t* w2;
+};
+
+__device__ __forceinline__ void retain(const Dev& d, const Arr& a, uint32_t step, int ida,
+                                       int sa, uint32_t idj, int sj, const int4* arow,
+                                       SweepAcc& n, const RetList& l) {
   const W4 r = philox(step, (uint32_t)ida, idj, 0u, d.seed);
   if (!((unsigned long long)r.w0 < d.thresh)) return;
   n.drawn++;
-  if (d.rule.exclude && bonded(d, a, ida, idj)) {
-    n.excl++;
-    return;
+  if (d.rule.exclude) {
+    bool b;
+    if (arow) {
+      const int4 q = *arow;
+      const int v = (int)idj;
+      b = q.x == v || q.y == v || q.z == v || q.w == v;
+    } else {
+      b = row_has(a.adj + (size_t)sa * d.B, d.B, (int32_t)idj);
+    }
+    if (b) {
+      n.excl++;
+      return;
+    }
   }
   d.tflag[sj] = 1;
-  const unsigned long long key = ((unsigned long long)r.w1 << 32) | (unsigned long long)idj;
-  if (atomicMin(&d.slotA[ida], key) == kEmpty) {
-    const int p = atomicAdd(s_np, 1);
-    if (p < kPropCap) {
-      pick(d.wgp, par)[blockIdx.x * kPropCap + p] = ida;
-    } else {
-      const uint32_t o = atomicAdd(&d.ctl->nprop_ovf[par], 1u);
-      pick(d.povf, par)[o] = ida;
-    }
+  atomicMin(&d.slotA[ida], ((unsigned long long)r.w1 << 32) | (unsigned long long)idj);
+  const int p = atomicAdd(l.n, 1);
+  if (p < kRetCap) {
+    l.ent[p] = make_int4(ida, sa, sj, (int)idj);
+    l.w2[p] = r.w2;
   }
 }
 
 // ---------------------------------------------------------------------------
-// k_sweep: kBrick = sorted storage, one workgroup per brick with the brick's A
-// records in LDS (particles that drifted out of the staged region since the
-// last sort, and bricks whose region holds more than kStageRecs records, use
-// the global buckets); otherwise a workgroup takes kThreads consecutive slots.
+// k_sweep: kBrick = sorted storage, one workgroup per brick with the A records
+// of the brick and its halo (positions, ids, slots, adjacency rows) staged in
+// LDS, one record per thread.  The brick's particles are loaded a pass of
+// kTPass at a time.  A T whose 2x2x2 cell block lies in the staged region
+// scans it as four runs of two x-adjacent cells (contiguous in LDS); its
+// in-range pairs are kept in registers and enter the LDS queue with one
+// reservation per wavefront, and the queue is drawn on full wavefronts after
+// the pass.  Other T's (particles that drifted out of the staged region since
+// the last sort, bricks whose region holds more than kStageRecs records, any
+// step with bucket overflow, kBrick = false where a workgroup takes kThreads
+// consecutive slots) read the global buckets and draw at once.
 // ---------------------------------------------------------------------------
+// One particle of a sweep pass, loaded with coalesced SoA reads.
+struct Part {
+  int typ, st, id;
+  float x, y, z;
+};
+
+__device__ __forceinline__ Part load_part(const Arr& a, const float* X, const float* Y,
+                                          const float* Z, int slot, int s1) {
+  Part q{-1, 0, 0, 0.0f, 0.0f, 0.0f};
+  if (slot < s1) {
+    q.typ = a.typ[slot];
+    q.st = a.st[slot];
+    q.x = X[slot];
+    q.y = Y[slot];
+    q.z = Z[slot];
+    q.id = a.id ? a.id[slot] : slot;
+  }
+  return q;
+}
+
 template <bool kBrick>
 __global__ __launch_bounds__(kThreads) void k_sweep(Dev d, int k) {
-  __shared__ int s_cnt[5];
-  __shared__ int s_qn;
-  __shared__ uint32_t s_off[kBrick ? kStageCells + 1 : 1];
-  __shared__ uint32_t s_wave[kThreads / 64 + 1];
+  constexpr int kPer = kBrick ? kTPass / kThreads : 1;
+  constexpr uint32_t kNoRec = 0xFFFFu;
   __shared__ float4 s_rec[kBrick ? kStageRecs : 1];
-  __shared__ int32_t s_qa[kQueue];
-  __shared__ uint16_t s_qt[kQueue];
-  __shared__ uint32_t s_tj[kThreads];
-  __shared__ int32_t s_ts[kThreads];
-  const int tid = threadIdx.x, w = blockIdx.x;
-  if (tid < 5) s_cnt[tid] = 0;
-  if (tid == 0) s_qn = 0;
+  __shared__ int4 s_radj[kBrick ? kStageRecs : 1];
+  __shared__ int32_t s_rsa[kBrick ? kStageRecs : 1];
+  __shared__ uint32_t s_off[kBrick ? kStageCells + 1 : 1];
+  __shared__ int32_t s_cid[kBrick ? kStageCells : 1];
+  __shared__ int4 s_q[kBrick ? kQueue : 1];  // (id_A, slot_A, id_T, local T | record << 16)
+  __shared__ int4 s_ent[kRetCap];
+  __shared__ uint32_t s_ew2[kRetCap];
+  __shared__ uint32_t s_wave[kThreads / 64 + 1];
+  __shared__ int s_cnt[4];
+  __shared__ int s_qn, s_ne, s_dead;
+  const int tid = threadIdx.x, w = blockIdx.x, lane = __lane_id();
+  if (tid < 4) s_cnt[tid] = 0;
+  if (tid == 0) {
+    s_qn = 0;
+    s_ne = 0;
+    s_dead = read_err(d.ctl) != 0;
+  }
   const Ctl* c = d.ctl;
-  const bool dead = read_err(c) != 0;
   const StepInfo si = step_info(c, k);
   const uint32_t par = si.par, step = si.step;
   const Arr a = pick_set(d, c->set & 1u);
   const float *X = pick(a.x, par ^ 1u), *Y = pick(a.y, par ^ 1u), *Z = pick(a.z, par ^ 1u);
   const uint32_t novf = c->ovf_n[par];
+  const RetList rl{&s_ne, s_ent, s_ew2};
   int s0, s1;
   range_of<kBrick>(d, w, s0, s1);
-  // the first chunk's particle data, issued before the staging round trips
-  int slot = s0 + tid;
-  int typ = -1, stt = 0, idv = 0;
-  float xj = 0.0f, yj = 0.0f, zj = 0.0f;
-  if (slot < s1) {
-    typ = a.typ[slot];
-    stt = a.st[slot];
-    xj = X[slot];
-    yj = Y[slot];
-    zj = Z[slot];
-    idv = a.id ? a.id[slot] : slot;
-  }
+  // the first particle of the first pass, issued before the staging round trips
+  Part cur = load_part(a, X, Y, Z, s0 + tid, s1);
   // clear the bucket counts of the next step's parity
-  for (int q = w * kThreads + tid; q < d.ncell; q += gridDim.x * kThreads) pick(d.cnt, par ^ 1u)[q] = 0u;
+  for (int q = w * kThreads + tid; q < d.ncell; q += gridDim.x * kThreads)
+    pick(d.cnt, par ^ 1u)[q] = 0u;
   int bx = 0, ex = 0, by = 0, ey = 0, bz = 0, ez = 0;
   bool staged = false;
   const int nc = d.nc;
@@ -582,113 +635,205 @@ __global__ __launch_bounds__(kThreads) void k_sweep(Dev d, int k) {
     region_dim(d, w / (nb * nb), bz, ez);
     const int ncs = ex * ey * ez;
     uint32_t mine = 0;
-    int myc = 0;
     if (tid < ncs) {
       const int lx = tid % ex, ly = (tid / ex) % ey, lz = tid / (ex * ey);
       int cx = bx + lx, cy = by + ly, cz = bz + lz;
       cx -= cx >= nc ? nc : 0;
       cy -= cy >= nc ? nc : 0;
       cz -= cz >= nc ? nc : 0;
-      myc = (cz * nc + cy) * nc + cx;
-      mine = dead ? 0u : pick(d.cnt, par)[myc];
+      const int myc = (cz * nc + cy) * nc + cx;
+      s_cid[tid] = myc;
+      mine = pick(d.cnt, par)[myc];
       mine = mine < (uint32_t)kCellCap ? mine : (uint32_t)kCellCap;
     }
     uint32_t total = 0;
     const uint32_t off = block_scan_excl(mine, s_wave, total);
     if (tid < ncs) s_off[tid] = off;
     if (tid == 0) s_off[ncs] = total;
-    staged = total <= (uint32_t)kStageRecs;
-    if (staged && tid < ncs)
-      for (uint32_t r = 0; r < mine; ++r) s_rec[off + r] = d.rec[(size_t)myc * kCellCap + r];
+    staged = total <= (uint32_t)kStageRecs && novf == 0;
+    __syncthreads();
+    if (staged && tid < (int)total) {
+      // the cell of record tid: s_off[lo] <= tid < s_off[lo + 1]
+      int lo = 0, hi = ncs;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (s_off[mid] <= (uint32_t)tid) lo = mid;
+        else hi = mid;
+      }
+      const size_t ri = (size_t)s_cid[lo] * kCellCap + (tid - (int)s_off[lo]);
+      s_rec[tid] = d.rec[ri];
+      s_rsa[tid] = d.rsa[ri];
+      if (d.adj_staged) s_radj[tid] = d.radj[ri];
+    }
   }
   __syncthreads();
+  const bool dead = s_dead != 0;
   SweepAcc n = {0, 0, 0, 0};
-  for (int base = s0; base < s1 && !dead; base += kThreads) {
-    if (base != s0) {
-      slot = base + tid;
-      typ = -1;
-      if (slot < s1) {
-        typ = a.typ[slot];
-        stt = a.st[slot];
-        xj = X[slot];
-        yj = Y[slot];
-        zj = Z[slot];
-        idv = a.id ? a.id[slot] : slot;
-      }
-    }
-    if (slot < s1 && is_t(d, typ, stt)) {
-      n.t_elig++;
-      s_tj[tid] = (uint32_t)idv;
-      s_ts[tid] = slot;
-      // an in-range pair is queued; a full queue sends it straight to the draw
-      auto push = [&](float4 A) {
-        if (dist2(d, xj, yj, zj, A) < d.rc2) {
-          n.in_rc++;
-          const int p = atomicAdd(&s_qn, 1);
-          if (p < kQueue) {
-            s_qa[p] = __float_as_int(A.w);
-            s_qt[p] = (uint16_t)tid;
-          } else {
-            retain(d, a, step, par, __float_as_int(A.w), (uint32_t)idv, slot, n, &s_cnt[kOutProp]);
+  for (int base = s0; base < s1 && !dead; base += kPer * kThreads) {
+    if (base != s0) cur = load_part(a, X, Y, Z, base + tid, s1);
+#pragma unroll 1
+    for (int u = 0; u < kPer; ++u) {
+      const int lt = u * kThreads + tid;
+      const int slot = base + lt;
+      // the next particle's loads are in flight while this one is handled
+      Part nxt = cur;
+      if (u + 1 < kPer) nxt = load_part(a, X, Y, Z, slot + kThreads, s1);
+      // in-range pairs with staged A's: up to three held in registers as
+      // (local T | record << 16), more go to the queue one by one
+      int nh = 0;
+      uint32_t h0 = 0, h1 = 0, h2 = 0;
+      const uint32_t idj = (uint32_t)cur.id;
+      if (slot < s1 && is_t(d, cur.typ, cur.st)) {
+        n.t_elig++;
+        const float px = cur.x, py = cur.y, pz = cur.z;
+        int cx0, cx1, cy0, cy1, cz0, cz1;
+        lo_hi(px, d.inv_w, nc, cx0, cx1);
+        lo_hi(py, d.inv_w, nc, cy0, cy1);
+        lo_hi(pz, d.inv_w, nc, cz0, cz1);
+        bool inside = false;
+        int lx0 = 0, ly0 = 0, lz0 = 0;
+        if (kBrick && staged) {
+          lx0 = local_of(cx0, bx, nc);
+          ly0 = local_of(cy0, by, nc);
+          lz0 = local_of(cz0, bz, nc);
+          const int lx1 = local_of(cx1, bx, nc), ly1 = local_of(cy1, by, nc),
+                    lz1 = local_of(cz1, bz, nc);
+          inside = lx1 == lx0 + 1 && ly1 == ly0 + 1 && lz1 == lz0 + 1 && lx1 < ex &&
+                   ly1 < ey && lz1 < ez;
+        }
+        if (inside) {
+          // runs (dy, dz) = (0,0), (1,0), (0,1), (1,1): cells lx0 and lx0 + 1
+          const int l0 = (lz0 * ey + ly0) * ex + lx0;
+          const int l1 = l0 + ex, l2 = l0 + ex * ey, l3 = l2 + ex;
+          const int b0 = (int)s_off[l0], b1 = (int)s_off[l1], b2 = (int)s_off[l2],
+                    b3 = (int)s_off[l3];
+          const int p1 = (int)s_off[l0 + 2] - b0;
+          const int p2 = p1 + (int)s_off[l1 + 2] - b1;
+          const int p3 = p2 + (int)s_off[l2 + 2] - b2;
+          const int tot = p3 + (int)s_off[l3 + 2] - b3;
+          const int o1 = b1 - p1, o2 = b2 - p2, o3 = b3 - p3;
+          for (int q = 0; q < tot; ++q) {
+            const int r = q + (q < p1 ? b0 : (q < p2 ? o1 : (q < p3 ? o2 : o3)));
+            const float4 A = s_rec[r];
+            if (!(dist2(d, px, py, pz, A) < d.rc2)) continue;
+            n.in_rc++;
+            const uint32_t hw = (uint32_t)lt | ((uint32_t)r << 16);
+            if (nh < 3) {
+              h2 = h1;
+              h1 = h0;
+              h0 = hw;
+              nh++;
+            } else {
+              const int p = atomicAdd(&s_qn, 1);
+              if (p < kQueue)
+                s_q[p] = make_int4(__float_as_int(A.w), s_rsa[r], (int)idj, (int)hw);
+              else
+                retain(d, a, step, __float_as_int(A.w), s_rsa[r], idj, slot,
+                       d.adj_staged ? &s_radj[r] : nullptr, n, rl);
+            }
+          }
+        } else {
+          // global buckets (cells 0-7 of the block), then the overflow list
+          const int m = nc > 1 ? 2 : 1;
+          const float4* ovf = pick(d.ovf, par);
+          const int32_t* osa = pick(d.ovf_sa, par);
+          for (int q = 0; q < 9; ++q) {
+            const float4* rp;
+            const int32_t* sp;
+            uint32_t nr;
+            if (q < 8) {
+              const int ia = q >> 2, ib = (q >> 1) & 1, ie = q & 1;
+              if (ia >= m || ib >= m || ie >= m) continue;
+              const int cc = ((ia ? cz1 : cz0) * nc + (ib ? cy1 : cy0)) * nc + (ie ? cx1 : cx0);
+              nr = pick(d.cnt, par)[cc];
+              nr = nr < (uint32_t)kCellCap ? nr : (uint32_t)kCellCap;
+              rp = d.rec + (size_t)cc * kCellCap;
+              sp = d.rsa + (size_t)cc * kCellCap;
+            } else {
+              nr = novf;
+              rp = ovf;
+              sp = osa;
+            }
+            for (uint32_t r = 0; r < nr; ++r) {
+              const float4 A = rp[r];
+              if (!(dist2(d, px, py, pz, A) < d.rc2)) continue;
+              n.in_rc++;
+              retain(d, a, step, __float_as_int(A.w), sp[r], idj, slot, nullptr, n, rl);
+            }
           }
         }
-      };
-      bool inside = false;
-      int lx0 = 0, lx1 = 0, ly0 = 0, ly1 = 0, lz0 = 0, lz1 = 0;
-      if (kBrick && staged) {
-        int cx0, cx1, cy0, cy1, cz0, cz1;
-        lo_hi(xj, d.inv_w, nc, cx0, cx1);
-        lo_hi(yj, d.inv_w, nc, cy0, cy1);
-        lo_hi(zj, d.inv_w, nc, cz0, cz1);
-        lx0 = local_of(cx0, bx, nc);
-        lx1 = local_of(cx1, bx, nc);
-        ly0 = local_of(cy0, by, nc);
-        ly1 = local_of(cy1, by, nc);
-        lz0 = local_of(cz0, bz, nc);
-        lz1 = local_of(cz1, bz, nc);
-        inside = lx0 < ex && lx1 < ex && ly0 < ey && ly1 < ey && lz0 < ez && lz1 < ez;
       }
-      if (inside) {
-        const int m = nc > 1 ? 2 : 1;
+      if (kBrick) {
+        // one queue reservation per wavefront for the pairs held in registers
+        uint32_t incl = (uint32_t)nh;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int ia = q >> 2, ib = (q >> 1) & 1, ie = q & 1;
-          if (ia >= m || ib >= m || ie >= m) continue;
-          const int l = ((ia ? lz1 : lz0) * ey + (ib ? ly1 : ly0)) * ex + (ie ? lx1 : lx0);
-          const uint32_t r1 = s_off[l + 1];
-          for (uint32_t r = s_off[l]; r < r1; ++r) push(s_rec[r]);
+        for (int o = 1; o < 64; o <<= 1) {
+          const uint32_t y = __shfl_up(incl, o);
+          if (lane >= o) incl += y;
         }
-        const float4* ovf = pick(d.ovf, par);
-        for (uint32_t r = 0; r < novf; ++r) push(ovf[r]);
-      } else {
-        for_global_records(d, par, novf, xj, yj, zj, push);
+        const uint32_t wtot = __shfl(incl, 63);
+        if (wtot) {
+          uint32_t qb = 0;
+          if (lane == 0) qb = (uint32_t)atomicAdd(&s_qn, (int)wtot);
+          qb = __shfl(qb, 0) + incl - (uint32_t)nh;
+          for (int j = 0; j < nh; ++j) {
+            const uint32_t hw = j == 0 ? h0 : (j == 1 ? h1 : h2);
+            const uint32_t r = hw >> 16;
+            const int ida = __float_as_int(s_rec[r].w), sa = s_rsa[r];
+            const uint32_t p = qb + (uint32_t)j;
+            if (p < (uint32_t)kQueue)
+              s_q[p] = make_int4(ida, sa, (int)idj, (int)hw);
+            else
+              retain(d, a, step, ida, sa, idj, slot, d.adj_staged ? &s_radj[r] : nullptr, n,
+                     rl);
+          }
+        }
       }
+      cur = nxt;
     }
-    __syncthreads();
-    // the queued pairs of this chunk: draws on full wavefronts
-    const int qn = min(s_qn, kQueue);
-    for (int e = tid; e < qn; e += kThreads) {
-      const int t = s_qt[e];
-      retain(d, a, step, par, s_qa[e], s_tj[t], s_ts[t], n, &s_cnt[kOutProp]);
+    if (kBrick) {
+      __syncthreads();
+      // the pass's queued pairs: draws on full wavefronts
+      const int qn = min(s_qn, kQueue);
+      for (int e = tid; e < qn; e += kThreads) {
+        const int4 q = s_q[e];
+        const uint32_t lt = (uint32_t)q.w & 0xFFFFu, r = (uint32_t)q.w >> 16;
+        retain(d, a, step, q.x, q.y, (uint32_t)q.z, base + (int)lt,
+               r != kNoRec && d.adj_staged ? &s_radj[r] : nullptr, n, rl);
+      }
+      __syncthreads();
+      if (tid == 0) s_qn = 0;
+      __syncthreads();
     }
-    __syncthreads();
-    if (tid == 0) s_qn = 0;
-    __syncthreads();
   }
   if (n.t_elig) atomicAdd(&s_cnt[kOutTElig], n.t_elig);
   if (n.in_rc) atomicAdd(&s_cnt[kOutInRc], n.in_rc);
   if (n.drawn) atomicAdd(&s_cnt[kOutDrawn], n.drawn);
   if (n.excl) atomicAdd(&s_cnt[kOutExcl], n.excl);
   __syncthreads();
-  if (tid < 5) pick(d.wgo, par)[w * kWgOut + tid] = s_cnt[tid];
+  const int ne = s_ne;
+  const int nk = ne < kRetCap ? ne : kRetCap;
+  if (tid < nk) {
+    pick(d.wge, par)[w * kRetCap + tid] = s_ent[tid];
+    pick(d.wgk, par)[w * kRetCap + tid] = s_ew2[tid];
+  }
+  int32_t* out = pick(d.wgo, par) + w * kWgOut;
+  if (tid < 4) out[tid] = s_cnt[tid];
+  if (tid == 0) {
+    out[kOutRet] = nk;
+    if (ne > kRetCap) atomicAdd(&d.ctl->ret_ovf[par], (uint32_t)(ne - kRetCap));
+  }
 }
 
 // ---------------------------------------------------------------------------
-// k_resolve: the T side (steps 6-7) and the bonds (step 9).  A flagged T is
-// handled by the workgroup that owns its slot; it enumerates its retained
-// pairs again (same cells, same draws), keeps those whose A's final key names
-// it, and bonds the smallest (w2, id_A).  An A chose exactly one T and a T
-// bonds at most one A, so every state and adjacency row has one writer.
+// k_resolve: the T side (steps 6-7) and the bonds (step 9).  Every retained
+// pair belongs to the workgroup that owns its T's slot.  Normally the pairs
+// come from the sweep workgroup's list: a pair whose A's final key names its
+// T is a proposal (the A's key is emptied for the next step), and of the
+// proposals to one T the smallest (w2, id_A) is bonded.  If any list
+// overflowed in this step, every flagged T enumerates its pairs again (same
+// cells, same draws) instead.  An A chose exactly one T and a T bonds at most
+// one A, so every state and adjacency row has one writer.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool adj_append(int32_t* row, int B, int32_t v) {
   for (int b = 0; b < B; ++b)
@@ -699,82 +844,136 @@ __device__ __forceinline__ bool adj_append(int32_t* row, int B, int32_t v) {
   return false;
 }
 
+struct BondCtx {
+  int* nw;
+  int* lost;
+  int* add;
+  int* nadd;
+};
+
+__device__ __forceinline__ void make_bond(const Dev& d, const Arr& a, uint32_t par, int w,
+                                          int ida, int sa, int sj, int idj, const BondCtx& b) {
+  a.st[sa] += d.rule.d_a;
+  const int32_t nt = a.st[sj] + d.rule.d_t;
+  a.st[sj] = nt;
+  int lost = 0;
+  if (!adj_append(a.adj + (size_t)sa * d.B, d.B, (int32_t)idj)) lost++;
+  if (!adj_append(a.adj + (size_t)sj * d.B, d.B, (int32_t)ida)) lost++;
+  if (lost) atomicAdd(b.lost, lost);
+  const int p = atomicAdd(b.nw, 1);
+  if (p < kWinCap) {
+    pick(d.wgw, par)[w * kWinCap + p] = make_int2(ida, idj);
+  } else {
+    const uint32_t o = atomicAdd(&d.ctl->nwin_ovf[par], 1u);
+    pick(d.wov, par)[o] = make_int2(ida, idj);
+  }
+  // a T entering the A window joins the A list, unless an entry of an
+  // earlier stay in the window is still there (it is live again now)
+  if (d.sorted && is_a(d, a.typ[sj], nt) && !d.inlist[sj]) {
+    d.inlist[sj] = 1;
+    b.add[atomicAdd(b.nadd, 1)] = sj;
+  }
+}
+
 template <bool kBrick>
 __global__ __launch_bounds__(kThreads) void k_resolve(Dev d, int k) {
-  __shared__ int s_nw, s_lost, s_nadd, s_abase;
+  __shared__ int s_nw, s_lost, s_nadd, s_abase, s_prop, s_mode;
   __shared__ int32_t s_add[kThreads];
+  __shared__ unsigned long long s_key[kRetCap];
+  __shared__ int32_t s_sj[kRetCap];
   const int tid = threadIdx.x, w = blockIdx.x;
+  const Ctl* c = d.ctl;
+  const StepInfo si = step_info(c, k);
+  const uint32_t par = si.par, step = si.step;
   if (tid == 0) {
     s_nw = 0;
     s_lost = 0;
+    s_nadd = 0;
+    s_prop = 0;
+    s_mode = read_err(c) ? 0 : (c->ret_ovf[par] ? 2 : 1);
   }
-  const Ctl* c0 = d.ctl;
-  Ctl* c = d.ctl;
-  const bool dead = read_err(c0) != 0;
-  const StepInfo si = step_info(c0, k);
-  const uint32_t par = si.par, step = si.step;
-  const Arr a = pick_set(d, c0->set & 1u);
-  const float *X = pick(a.x, par ^ 1u), *Y = pick(a.y, par ^ 1u), *Z = pick(a.z, par ^ 1u);
-  const uint32_t novf = c0->ovf_n[par];
-  int s0, s1;
-  range_of<kBrick>(d, w, s0, s1);
   __syncthreads();
-  for (int base = s0; base < s1 && !dead; base += kThreads) {
-    if (tid == 0) s_nadd = 0;
-    __syncthreads();
-    const int slot = base + tid;
-    if (slot < s1 && d.tflag[slot]) {
-      d.tflag[slot] = 0;
-      const float xj = X[slot], yj = Y[slot], zj = Z[slot];
-      const uint32_t idj = a.id ? (uint32_t)a.id[slot] : (uint32_t)slot;
-      unsigned long long best = kEmpty;
-      for_global_records(d, par, novf, xj, yj, zj, [&](float4 A) {
-        if (!(dist2(d, xj, yj, zj, A) < d.rc2)) return;
-        const int ida = __float_as_int(A.w);
-        const W4 r = philox(step, (uint32_t)ida, idj, 0u, d.seed);
-        if (!((unsigned long long)r.w0 < d.thresh)) return;
-        if ((uint32_t)d.slotA[ida] != idj) return;  // the A chose another T
-        if (d.rule.exclude && bonded(d, a, ida, idj)) return;
-        const unsigned long long bid = ((unsigned long long)r.w2 << 32) | (uint32_t)ida;
-        best = bid < best ? bid : best;
-      });
-      if (best != kEmpty) {
-        const int i = (int)(uint32_t)best;
-        const int sa = d.slot_of ? d.slot_of[i] : i;
-        a.st[sa] += d.rule.d_a;
-        const int32_t nt = a.st[slot] + d.rule.d_t;
-        a.st[slot] = nt;
-        int lost = 0;
-        if (!adj_append(a.adj + (size_t)sa * d.B, d.B, (int32_t)idj)) lost++;
-        if (!adj_append(a.adj + (size_t)slot * d.B, d.B, i)) lost++;
-        if (lost) atomicAdd(&s_lost, lost);
-        const int p = atomicAdd(&s_nw, 1);
-        if (p < kWinCap) {
-          pick(d.wgw, par)[w * kWinCap + p] = make_int2(i, (int)idj);
-        } else {
-          const uint32_t o = atomicAdd(&c->nwin_ovf[par], 1u);
-          pick(d.wov, par)[o] = make_int2(i, (int)idj);
-        }
-        // a T entering the A window joins the A list, unless an entry of an
-        // earlier stay in the window is still there (it is live again now)
-        if (d.sorted && is_a(d, a.typ[slot], nt) && !d.inlist[slot]) {
-          d.inlist[slot] = 1;
-          s_add[atomicAdd(&s_nadd, 1)] = slot;
-        }
-      }
-    }
-    __syncthreads();
+  const int mode = s_mode;
+  const Arr a = pick_set(d, c->set & 1u);
+  const BondCtx bc{&s_nw, &s_lost, s_add, &s_nadd};
+  auto flush_adds = [&]() {  // every thread; after a barrier
     const int nadd = s_nadd;
     if (nadd) {
-      if (tid == 0) s_abase = (int)atomicAdd(&c->na, (uint32_t)nadd);
+      if (tid == 0) s_abase = (int)atomicAdd(&d.ctl->na, (uint32_t)nadd);
       __syncthreads();
       if (tid < nadd) d.alist[s_abase + tid] = s_add[tid];
+      __syncthreads();
+      if (tid == 0) s_nadd = 0;
     }
     __syncthreads();
+  };
+  if (mode == 1) {
+    const int ne = pick(d.wgo, par)[w * kWgOut + kOutRet];
+    if (ne > 0) {
+      bool chosen = false;
+      int4 e = make_int4(0, 0, 0, 0);
+      unsigned long long key = kEmpty;
+      if (tid < ne) {
+        e = pick(d.wge, par)[w * kRetCap + tid];
+        const uint32_t w2 = pick(d.wgk, par)[w * kRetCap + tid];
+        d.tflag[e.z] = 0;
+        chosen = (uint32_t)d.slotA[e.x] == (uint32_t)e.w;
+        if (chosen) {
+          d.slotA[e.x] = kEmpty;
+          key = ((unsigned long long)w2 << 32) | (uint32_t)e.x;
+          atomicAdd(&s_prop, 1);
+        }
+        s_key[tid] = key;
+        s_sj[tid] = e.z;
+      }
+      __syncthreads();
+      if (chosen) {
+        bool win = true;
+        for (int f = 0; f < ne; ++f)
+          if (s_sj[f] == e.z && s_key[f] < key) win = false;
+        if (win) make_bond(d, a, par, w, e.x, e.y, e.z, e.w, bc);
+      }
+      __syncthreads();
+      flush_adds();
+    }
+  } else if (mode == 2) {
+    const float *X = pick(a.x, par ^ 1u), *Y = pick(a.y, par ^ 1u), *Z = pick(a.z, par ^ 1u);
+    const uint32_t novf = c->ovf_n[par];
+    int s0, s1;
+    range_of<kBrick>(d, w, s0, s1);
+    for (int base = s0; base < s1; base += kThreads) {
+      const int slot = base + tid;
+      if (slot < s1 && d.tflag[slot]) {
+        d.tflag[slot] = 0;
+        const float xj = X[slot], yj = Y[slot], zj = Z[slot];
+        const uint32_t idj = a.id ? (uint32_t)a.id[slot] : (uint32_t)slot;
+        unsigned long long best = kEmpty;
+        int best_sa = 0, np = 0;
+        for_global_records(d, par, novf, xj, yj, zj, [&](float4 A, int sa) {
+          if (!(dist2(d, xj, yj, zj, A) < d.rc2)) return;
+          const int ida = __float_as_int(A.w);
+          if ((uint32_t)d.slotA[ida] != idj) return;  // not retained, or the A chose another T
+          const W4 r = philox(step, (uint32_t)ida, idj, 0u, d.seed);
+          d.slotA[ida] = kEmpty;
+          np++;
+          const unsigned long long bid = ((unsigned long long)r.w2 << 32) | (uint32_t)ida;
+          if (bid < best) {
+            best = bid;
+            best_sa = sa;
+          }
+        });
+        if (np) atomicAdd(&s_prop, np);
+        if (best != kEmpty) make_bond(d, a, par, w, (int)(uint32_t)best, best_sa, slot, (int)idj, bc);
+      }
+      __syncthreads();
+      flush_adds();
+    }
   }
   if (tid == 0) {
-    pick(d.wgo, par)[w * kWgOut + kOutBonds] = s_nw;
-    pick(d.wgo, par)[w * kWgOut + kOutLost] = s_lost;
+    int32_t* out = pick(d.wgo, par) + w * kWgOut;
+    out[kOutProp] = s_prop;
+    out[kOutBonds] = s_nw;
+    out[kOutLost] = s_lost;
   }
 }
 
