@@ -185,6 +185,21 @@ __device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t* s_wave
   return r;
 }
 
+// Sum over the wavefront (every lane of the wave must call it); the result
+// is valid in every lane.
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Adds v of every lane to *dst with one LDS atomic per wavefront (every lane
+// of the wave must call it).
+__device__ __forceinline__ void wave_add(int* dst, int v) {
+  const int t = wave_sum(v);
+  if (__lane_id() == 0 && t) atomicAdd(dst, t);
+}
+
 // ---------------------------------------------------------------------------
 // Control block set-up (a kernel rather than a memset/memcpy so that a
 // captured graph may hold it).  A full reset selects storage set 0 and
@@ -296,8 +311,7 @@ __device__ void close_group(const Dev& d, uint32_t par, uint32_t step, uint32_t 
   const int v[kPart] = {a_elig,         o[kOutTElig], o[kOutInRc], o[kOutDrawn],
                         o[kOutExcl],    o[kOutProp],  o[kOutBonds], o[kOutLost]};
 #pragma unroll
-  for (int q = 0; q < kPart; ++q)
-    if (v[q]) atomicAdd(&s_sum[q], v[q]);
+  for (int q = 0; q < kPart; ++q) wave_add(&s_sum[q], v[q]);
   __syncthreads();
   const uint64_t row0 = s_row;
   const int2* staged = pick(d.wgw, par) + w * kWinCap;
@@ -366,9 +380,9 @@ __global__ __launch_bounds__(kThreads) void k_prep(Dev d, int k) {
   if (b < d.nwg_abin) {  // A particles -> cell buckets
     if (threadIdx.x == 0) s_na = 0;
     __syncthreads();
+    int mine = 0;
     if (read_err(d.ctl) == 0) {
       const uint32_t total = d.sorted ? d.ctl->na : (uint32_t)d.n;
-      int mine = 0;
       for (uint32_t q = b * kThreads + threadIdx.x; q < total; q += d.nwg_abin * kThreads) {
         const int slot = d.sorted ? d.alist[q] : (int)q;
         if (!is_a(d, a.typ[slot], a.st[slot])) continue;
@@ -397,8 +411,8 @@ __global__ __launch_bounds__(kThreads) void k_prep(Dev d, int k) {
           pick(d.ovf_sa, si.par)[o] = slot;
         }
       }
-      if (mine) atomicAdd(&s_na, mine);
     }
+    wave_add(&s_na, mine);
     __syncthreads();
     if (threadIdx.x == 0) pick(d.abst, si.par)[b] = s_na;
     return;
@@ -446,6 +460,13 @@ __device__ __forceinline__ float dist2(const Dev& d, float xj, float yj, float z
   const float dx = min_image(__fsub_rn(xj, a.x), d.L, d.halfL);
   const float dy = min_image(__fsub_rn(yj, a.y), d.L, d.halfL);
   const float dz = min_image(__fsub_rn(zj, a.z), d.L, d.halfL);
+  return __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz));
+}
+
+// dist2 of two positions whose difference is known to lie within
+// (-L/2, L/2) in every component (the minimum image is the identity there).
+__device__ __forceinline__ float dist2_plain(float xj, float yj, float zj, float4 a) {
+  const float dx = __fsub_rn(xj, a.x), dy = __fsub_rn(yj, a.y), dz = __fsub_rn(zj, a.z);
   return __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz));
 }
 
@@ -569,6 +590,22 @@ __device__ __forceinline__ void retain(const Dev& d, const Arr& a, uint32_t step
 // step with bucket overflow, kBrick = false where a workgroup takes kThreads
 // consecutive slots) read the global buckets and draw at once.
 // ---------------------------------------------------------------------------
+// An in-range pair (local T, staged record r) into the three register slots;
+// false (and spill = q) when they are full.
+__device__ __forceinline__ bool hold_hit(int q, int r, int lt, int& nh, uint32_t& h0,
+                                         uint32_t& h1, uint32_t& h2, int& spill, int& in_rc) {
+  if (nh == 3) {
+    spill = q;
+    return false;
+  }
+  in_rc++;
+  h2 = h1;
+  h1 = h0;
+  h0 = (uint32_t)lt | ((uint32_t)r << 16);
+  nh++;
+  return true;
+}
+
 // One particle of a sweep pass, loaded with coalesced SoA reads.
 struct Part {
   int typ, st, id;
@@ -590,7 +627,7 @@ __device__ __forceinline__ Part load_part(const Arr& a, const float* X, const fl
 }
 
 template <bool kBrick>
-__global__ __launch_bounds__(kThreads) void k_sweep(Dev d, int k) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) void k_sweep(Dev d, int k) {
   constexpr int kPer = kBrick ? kTPass / kThreads : 1;
   constexpr uint32_t kNoRec = 0xFFFFu;
   __shared__ float4 s_rec[kBrick ? kStageRecs : 1];
@@ -626,13 +663,18 @@ __global__ __launch_bounds__(kThreads) void k_sweep(Dev d, int k) {
   for (int q = w * kThreads + tid; q < d.ncell; q += gridDim.x * kThreads)
     pick(d.cnt, par ^ 1u)[q] = 0u;
   int bx = 0, ex = 0, by = 0, ey = 0, bz = 0, ez = 0;
-  bool staged = false;
+  bool staged = false, nowrap = false;
   const int nc = d.nc;
   if (kBrick) {
     const int nb = d.nb;
     region_dim(d, w % nb, bx, ex);
     region_dim(d, (w / nb) % nb, by, ey);
     region_dim(d, w / (nb * nb), bz, ez);
+    // a region that does not wrap around the box and spans less than half of
+    // it: a difference of two positions in it is below L/2 in magnitude, and
+    // the minimum image leaves it unchanged
+    nowrap = d.nbricks > 1 && bx + ex <= nc && by + ey <= nc && bz + ez <= nc &&
+             2 * ex + 1 <= nc && 2 * ey + 1 <= nc && 2 * ez + 1 <= nc;
     const int ncs = ex * ey * ez;
     uint32_t mine = 0;
     if (tid < ncs) {
@@ -712,25 +754,34 @@ __global__ __launch_bounds__(kThreads) void k_sweep(Dev d, int k) {
           const int p3 = p2 + (int)s_off[l2 + 2] - b2;
           const int tot = p3 + (int)s_off[l3 + 2] - b3;
           const int o1 = b1 - p1, o2 = b2 - p2, o3 = b3 - p3;
-          for (int q = 0; q < tot; ++q) {
+          // the first three in-range records go to registers; from a fourth
+          // on (rare) the rest of the runs is scanned again below
+          int spill = -1;
+          if (nowrap) {  // no difference can reach L/2 in this region
+            for (int q = 0; q < tot; ++q) {
+              const int r = q + (q < p1 ? b0 : (q < p2 ? o1 : (q < p3 ? o2 : o3)));
+              if (!(dist2_plain(px, py, pz, s_rec[r]) < d.rc2)) continue;
+              if (!hold_hit(q, r, lt, nh, h0, h1, h2, spill, n.in_rc)) break;
+            }
+          } else {
+            for (int q = 0; q < tot; ++q) {
+              const int r = q + (q < p1 ? b0 : (q < p2 ? o1 : (q < p3 ? o2 : o3)));
+              if (!(dist2(d, px, py, pz, s_rec[r]) < d.rc2)) continue;
+              if (!hold_hit(q, r, lt, nh, h0, h1, h2, spill, n.in_rc)) break;
+            }
+          }
+          for (int q = spill; q >= 0 && q < tot; ++q) {
             const int r = q + (q < p1 ? b0 : (q < p2 ? o1 : (q < p3 ? o2 : o3)));
             const float4 A = s_rec[r];
             if (!(dist2(d, px, py, pz, A) < d.rc2)) continue;
             n.in_rc++;
-            const uint32_t hw = (uint32_t)lt | ((uint32_t)r << 16);
-            if (nh < 3) {
-              h2 = h1;
-              h1 = h0;
-              h0 = hw;
-              nh++;
-            } else {
-              const int p = atomicAdd(&s_qn, 1);
-              if (p < kQueue)
-                s_q[p] = make_int4(__float_as_int(A.w), s_rsa[r], (int)idj, (int)hw);
-              else
-                retain(d, a, step, __float_as_int(A.w), s_rsa[r], idj, slot,
-                       d.adj_staged ? &s_radj[r] : nullptr, n, rl);
-            }
+            const int p = atomicAdd(&s_qn, 1);
+            if (p < kQueue)
+              s_q[p] = make_int4(__float_as_int(A.w), s_rsa[r], (int)idj,
+                                 (int)((uint32_t)lt | ((uint32_t)r << 16)));
+            else
+              retain(d, a, step, __float_as_int(A.w), s_rsa[r], idj, slot,
+                     d.adj_staged ? &s_radj[r] : nullptr, n, rl);
           }
         } else {
           // global buckets (cells 0-7 of the block), then the overflow list
@@ -806,10 +857,10 @@ __global__ __launch_bounds__(kThreads) void k_sweep(Dev d, int k) {
       __syncthreads();
     }
   }
-  if (n.t_elig) atomicAdd(&s_cnt[kOutTElig], n.t_elig);
-  if (n.in_rc) atomicAdd(&s_cnt[kOutInRc], n.in_rc);
-  if (n.drawn) atomicAdd(&s_cnt[kOutDrawn], n.drawn);
-  if (n.excl) atomicAdd(&s_cnt[kOutExcl], n.excl);
+  wave_add(&s_cnt[kOutTElig], n.t_elig);
+  wave_add(&s_cnt[kOutInRc], n.in_rc);
+  wave_add(&s_cnt[kOutDrawn], n.drawn);
+  wave_add(&s_cnt[kOutExcl], n.excl);
   __syncthreads();
   const int ne = s_ne;
   const int nk = ne < kRetCap ? ne : kRetCap;
