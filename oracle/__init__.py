@@ -55,6 +55,10 @@ def _declare(lib):
     lib.or_near_cutoff.restype = C.c_int
     lib.or_ih12_offsets.argtypes = [u32, u32, u32, u64, P(i32)]
     lib.or_ih12_offsets.restype = None
+    lib.or_ih4_offsets.argtypes = [u32, u32, u32, u64, P(i32)]
+    lib.or_ih4_offsets.restype = None
+    lib.or_jitter_scale.argtypes = [f64]
+    lib.or_jitter_scale.restype = C.c_float
     lib.or_jitter.argtypes = [i32, f32, P(f32), P(f32), P(f32), u64, u32, f64]
     lib.or_jitter.restype = None
     lib.or_num_threads.argtypes = []
@@ -177,7 +181,7 @@ def jitter(sysm, seed, step, sigma, lib=None):
 
 
 def ih12_offsets(step, ids, tag, seed, lib=None):
-    """Integer Irwin-Hall offsets S (n x 3) of the jitter for particle ``ids``."""
+    """Integer Irwin-Hall(12) offsets S (n x 3) of the initial configuration."""
     lib = lib or load()
     out = np.empty((len(ids), 3), dtype=np.int32)
     buf = (C.c_int32 * 3)()
@@ -185,6 +189,23 @@ def ih12_offsets(step, ids, tag, seed, lib=None):
         lib.or_ih12_offsets(C.c_uint32(step), C.c_uint32(int(i)), C.c_uint32(tag), C.c_uint64(seed), buf)
         out[k] = list(buf)
     return out
+
+
+def ih4_offsets(step, ids, tag, seed, lib=None):
+    """Integer Irwin-Hall(4) offsets S (n x 3) of the re-jitter for particle ``ids``."""
+    lib = lib or load()
+    out = np.empty((len(ids), 3), dtype=np.int32)
+    buf = (C.c_int32 * 3)()
+    for k, i in enumerate(ids):
+        lib.or_ih4_offsets(C.c_uint32(step), C.c_uint32(int(i)), C.c_uint32(tag), C.c_uint64(seed), buf)
+        out[k] = list(buf)
+    return out
+
+
+def jitter_scale(sigma, lib=None):
+    """The FP32 displacement per unit offset of the re-jitter."""
+    lib = lib or load()
+    return float(lib.or_jitter_scale(float(sigma)))
 
 
 def near_cutoff(sysm, rule, tol=1e-6, lib=None):
@@ -204,4 +225,4 @@ def num_threads(lib=None):
 
 __all__ = ["Rule", "System", "react_step", "run", "jitter", "philox", "threshold", "near_cutoff",
            "sample_bonds",
-           "ih12_offsets", "ST_NAMES", "load", "num_threads"]
+           "ih12_offsets", "ih4_offsets", "jitter_scale", "ST_NAMES", "load", "num_threads"]

@@ -421,13 +421,10 @@ int or_near_cutoff(int32_t n, float L, const float* x, const float* y, const flo
 }
 
 /* ----------------------------------------------------------------------- */
-/* Re-jitter between reaction steps: the synthetic stand-in for the MD       */
-/* integration that the paper runs between reaction steps (Sec. III: the     */
-/* reaction runs every Theta MD steps).  Not part of the paper's method.     */
-/* Displacement per dimension: S = (sum of 12 uniform bytes) - 1530, an       */
-/* Irwin-Hall(12) variable on an integer grid with mean 0 and variance 65535,*/
-/* scaled by c = fl32(sigma/256); the bytes come from three Philox blocks     */
-/* with counter (step, id, blk, tag), blk = 0..2, words 3d..3d+2 for dim d.   */
+/* Integer Irwin-Hall(12) offsets of the synthetic initial configuration:    */
+/* per dimension S = (sum of 12 uniform bytes) - 1530 (mean 0, variance     */
+/* 65535); the bytes come from three Philox blocks with counter              */
+/* (step, id, blk, tag), blk = 0..2, words 3d..3d+2 for dimension d.         */
 /* ----------------------------------------------------------------------- */
 void or_ih12_offsets(uint32_t step, uint32_t id, uint32_t tag, uint64_t seed, int32_t S[3]) {
   uint32_t words[12];
@@ -441,13 +438,36 @@ void or_ih12_offsets(uint32_t step, uint32_t id, uint32_t tag, uint64_t seed, in
       uint32_t v = words[3 * d + w];
       for (int b = 0; b < 4; ++b) sum += (int32_t)((v >> (8 * b)) & 0xFFu);
     }
-#if OR_MUTANT == 12 /* mutant: off-centre jitter */
-    S[d] = sum - 1536;
-#else
     S[d] = sum - 1530;
+  }
+}
+
+/* ----------------------------------------------------------------------- */
+/* Re-jitter between reaction steps: the synthetic stand-in for the MD       */
+/* integration that the paper runs between reaction steps (Sec. III: the     */
+/* reaction runs every Theta MD steps).  Not part of the paper's method.     */
+/* Displacement per dimension d: S = (sum of the 4 bytes of word d) - 510,   */
+/* an Irwin-Hall(4) variable on an integer grid with mean 0 and variance     */
+/* 21845, scaled by c = fl32(sigma / sqrt(21845)); the words come from one   */
+/* Philox block with counter (step, id, 0, tag).                             */
+/* ----------------------------------------------------------------------- */
+void or_ih4_offsets(uint32_t step, uint32_t id, uint32_t tag, uint64_t seed, int32_t S[3]) {
+  uint32_t words[4];
+  uint32_t ctr[4] = {step, id, 0u, tag};
+  or_philox4x32_10(ctr, seed, words);
+  for (int d = 0; d < 3; ++d) {
+    int32_t sum = 0;
+    for (int b = 0; b < 4; ++b) sum += (int32_t)((words[d] >> (8 * b)) & 0xFFu);
+#if OR_MUTANT == 12 /* mutant: off-centre jitter */
+    S[d] = sum - 512;
+#else
+    S[d] = sum - 510;
 #endif
   }
 }
+
+/* The displacement scale of the re-jitter for a given sigma. */
+float or_jitter_scale(double sigma) { return (float)(sigma / sqrt(21845.0)); }
 
 static float wrap_box(float v, float L) {
   if (v < 0.0f) v = v + L;
@@ -457,11 +477,11 @@ static float wrap_box(float v, float L) {
 
 void or_jitter(int32_t n, float L, float* x, float* y, float* z, uint64_t seed,
                uint32_t step, double sigma) {
-  const float c = (float)(sigma / 256.0);
+  const float c = or_jitter_scale(sigma);
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
     int32_t S[3];
-    or_ih12_offsets(step, (uint32_t)i, 1u, seed, S);
+    or_ih4_offsets(step, (uint32_t)i, 1u, seed, S);
     float dx = (float)S[0] * c, dy = (float)S[1] * c, dz = (float)S[2] * c;
     x[i] = wrap_box(x[i] + dx, L);
     y[i] = wrap_box(y[i] + dy, L);

@@ -32,7 +32,6 @@ hipError_t launch_single_end(const Dev& d, hipStream_t s);
 hipError_t launch_sort(const Dev& d, hipStream_t s);
 hipError_t launch_gather_out(const Dev& d, float* ox, float* oy, float* oz, int32_t* ost,
                              int32_t* oadj, hipStream_t s);
-int abin_blocks(long long work);
 }  // namespace pr
 
 using namespace pr;
@@ -76,6 +75,9 @@ unsigned long long threshold(double p) {
 }
 
 int sweep_blocks(int32_t n) { return std::max(1, (n + kThreads - 1) / kThreads); }
+int prep_blocks(int32_t n) {
+  return std::max(1, (int)(((int64_t)n + kThreads * kPrepRoles - 1) / (kThreads * kPrepRoles)));
+}
 
 // Coarse A grid: nc cells per side of width L/nc >= 2 rc (1 + 2^-10); the
 // margin keeps the 2x2x2 block exact under FP32 rounding of the cell index.
@@ -100,7 +102,7 @@ void set_geometry(Dev& d, int32_t n, float L, int32_t B, const pr_rule* r, uint6
   d.rule = RuleD{r->type_a, r->a_min, r->a_max, r->d_a, r->type_t, r->t_min, r->t_max, r->d_t,
                  r->exclude_bonded};
   d.nwg_sweep = sweep_blocks(n);
-  d.nwg_abin = abin_blocks(n);
+  d.nwg_prep = prep_blocks(n);
   d.adj_staged = B <= kAdjStage ? 1 : 0;
   d.jit_c = 0.0f;
   d.part = nullptr;
@@ -142,7 +144,7 @@ struct Arena {
 // nwg: sweep workgroups to provide for (the larger of the two sweep grids).
 int alloc_scratch(Arena& a, Dev& d, int32_t n, int32_t nwg, hipStream_t s) {
   int e;
-  if ((e = a.alloc(&d.alist, n)) || (e = a.alloc(&d.inlist, n)) || (e = a.alloc(&d.tflag, n)))
+  if ((e = a.alloc(&d.tflag, n)))
     return e;
   if ((e = a.alloc(&d.cnt[0], d.ncell)) || (e = a.alloc(&d.cnt[1], d.ncell))) return e;
   const size_t nrec = (size_t)d.ncell * kCellCap;
@@ -156,7 +158,7 @@ int alloc_scratch(Arena& a, Dev& d, int32_t n, int32_t nwg, hipStream_t s) {
         (e = a.alloc(&d.wge[p], (size_t)nwg * kRetCap)) ||
         (e = a.alloc(&d.wgk[p], (size_t)nwg * kRetCap)) ||
         (e = a.alloc(&d.wgw[p], (size_t)nwg * kWinCap)) || (e = a.alloc(&d.wov[p], n / 2 + 1)) ||
-        (e = a.alloc(&d.abst[p], kAbinMax)))
+        (e = a.alloc(&d.abst[p], (size_t)sweep_blocks(n))))
       return e;
   }
   if ((e = a.alloc(&d.ctl, 1))) return e;
@@ -176,6 +178,7 @@ struct Workspace {
   int32_t* part = nullptr;
   int32_t ngroups = 0;
   int32_t* log = nullptr;
+  uint8_t* role = nullptr;
   unsigned long long* sortbuf = nullptr;
   Ctl* hctl = nullptr;  // pinned host copies
   int32_t* hpart = nullptr;
@@ -236,6 +239,7 @@ int pr_react_step(int32_t n, float L, const float* x, const float* y, const floa
     ws->ngroups = (sweep_blocks(n_alloc) + kGroup - 1) / kGroup;
     if ((e = ws->arena.alloc(&ws->part, (size_t)ws->ngroups * kPart)) ||
         (e = ws->arena.alloc(&ws->log, 3 * ((size_t)n_alloc / 2 + 1))) ||
+        (e = ws->arena.alloc(&ws->role, (size_t)n_alloc)) ||
         (e = ws->arena.alloc(&ws->sortbuf, n2)))
       return e;
     HIP_TRY(hipHostMalloc((void**)&ws->hctl, sizeof(Ctl)));
@@ -258,14 +262,14 @@ int pr_react_step(int32_t n, float L, const float* x, const float* y, const floa
   d.rule = geo.rule;
   d.adj_staged = geo.adj_staged;
   d.nwg_sweep = geo.nwg_sweep;
-  d.nwg_abin = geo.nwg_abin;
-  d.nwg_jit = 0;
+  d.nwg_prep = geo.nwg_prep;
   d.jitter = 0;
   d.sorted = 0;
   float* cx = const_cast<float*>(x);
   float* cy = const_cast<float*>(y);
   float* cz = const_cast<float*>(z);
-  const Arr caller{{cx, cx}, {cy, cy}, {cz, cz}, const_cast<int32_t*>(type), state, adj, nullptr};
+  const Arr caller{{cx, cx}, {cy, cy}, {cz, cz}, const_cast<int32_t*>(type), state, adj, nullptr,
+                   ws->role};
   d.set[0] = d.set[1] = caller;
   d.slot_of = nullptr;
   d.bonds = bonds;
@@ -375,11 +379,10 @@ int grow_part(pr_sys* s, int64_t need) {
   return PR_OK;
 }
 
-// Dense mode until the first sort: every particle is an A candidate of k_abin.
+// Unsorted storage until the first sort: sweep workgroups take consecutive slots.
 void set_dense(pr_sys* s) {
   s->d.sorted = 0;
   s->d.nwg_sweep = sweep_blocks(s->d.n);
-  s->d.nwg_abin = abin_blocks(s->d.n);
 }
 
 int after_load(pr_sys* s) {
@@ -404,15 +407,12 @@ int after_load(pr_sys* s) {
   return PR_OK;
 }
 
-int list_abin_blocks(const Dev& d) { return abin_blocks(std::max<long long>(4096, d.n / 8)); }
-
-// Counting sort of the storage by brick (writes the other storage set and
-// rebuilds the A list); afterwards the sweep runs per brick.
+// Counting sort of the storage by brick (writes the other storage set);
+// afterwards the sweep runs per brick.
 int sort_storage(pr_sys* s, hipStream_t st) {
   HIP_TRY(launch_sort(s->d, st));
   s->d.sorted = 1;
   s->d.nwg_sweep = s->d.nbricks;
-  s->d.nwg_abin = list_abin_blocks(s->d);  // list mode: the grid covers the A list
   s->steps_since_sort = 0;
   return PR_OK;
 }
@@ -493,18 +493,15 @@ int pr_sys_create(pr_sys** out, int32_t n, float L, int32_t B, const pr_rule* ru
     if (!e) e = s->arena.alloc(&a.typ, n);
     if (!e) e = s->arena.alloc(&a.st, n);
     if (!e) e = s->arena.alloc(&a.id, n);
+    if (!e) e = s->arena.alloc(&a.role, n);
     if (!e) e = s->arena.alloc(&a.adj, (size_t)n * B);
   }
   if (!e) e = s->arena.alloc(&d.slot_of, n);
   if (!e) e = s->arena.alloc(&d.log, (size_t)s->log_cap * 3);
   if (!e) e = s->arena.alloc(&d.bstart, (size_t)d.nbricks + 1);
-  if (!e) e = s->arena.alloc(&d.astart, (size_t)d.nbricks + 1);
   if (!e) e = s->arena.alloc(&d.bcnt, (size_t)d.nbricks);
-  if (!e) e = s->arena.alloc(&d.bacnt, (size_t)d.nbricks);
   if (!e) e = s->arena.alloc(&d.rank, n);
-  if (!e) e = s->arena.alloc(&d.arank, n);
-  if (!e && (hipMemsetAsync(d.bcnt, 0, sizeof(uint32_t) * d.nbricks, s->stream) != hipSuccess ||
-             hipMemsetAsync(d.bacnt, 0, sizeof(uint32_t) * d.nbricks, s->stream) != hipSuccess))
+  if (!e && hipMemsetAsync(d.bcnt, 0, sizeof(uint32_t) * d.nbricks, s->stream) != hipSuccess)
     e = fail(PR_EHIP, "hipMemsetAsync failed");
   if (!e && hipHostMalloc((void**)&s->hctl, sizeof(Ctl)) != hipSuccess)
     e = fail(PR_ENOMEM, "hipHostMalloc failed");
@@ -518,7 +515,6 @@ int pr_sys_create(pr_sys** out, int32_t n, float L, int32_t B, const pr_rule* ru
   d.log_cap = s->log_cap;
   d.sortbuf = nullptr;
   d.jitter = 1;
-  d.nwg_jit = sweep_blocks(n);
   s->sort_period = 64;
   set_dense(s);
   *out = s;
@@ -579,7 +575,7 @@ static int run_impl(pr_sys* s, uint32_t first_step, uint32_t n_steps, double sig
   if (!(sigma >= 0.0) || sigma * 6.0 >= (double)s->d.L * 0.5)
     return fail(PR_EINVAL, "sigma=%g", sigma);
   if ((e = grow_part(s, s->steps_since_load + n_steps))) return e;
-  s->d.jit_c = (float)(sigma / 256.0);
+  s->d.jit_c = (float)(sigma / std::sqrt(21845.0));  // unit-variance offsets
   hipStream_t st = s->stream;
   HIP_TRY(launch_ctl_reset(s->d.ctl, first_step, 0, st));
   if (ms) {
@@ -622,7 +618,6 @@ static int run_impl(pr_sys* s, uint32_t first_step, uint32_t n_steps, double sig
       if (s->sort_period > 0) {
         s->d.sorted = 1;
         s->d.nwg_sweep = s->d.nbricks;
-        s->d.nwg_abin = list_abin_blocks(s->d);
         s->steps_since_sort = block;
       } else {
         s->steps_since_sort += block;

@@ -14,6 +14,7 @@ namespace pr {
 constexpr int kCellCap = 8;
 constexpr unsigned long long kEmpty = ~0ull;
 constexpr int kThreads = 256;       // workgroup size of the per-particle kernels
+constexpr int kPrepRoles = 16;      // role bytes a prep thread scans for A's
 constexpr int kFinThreads = 1024;   // the single-workgroup finishing kernels
 constexpr int kSortLds = 4096;      // bonds of a stateless step sorted in LDS up to this
 constexpr int kStatsPerStep = 9;    // pr_stats fields
@@ -23,7 +24,6 @@ constexpr int kWgOut = 8;           // per sweep workgroup counters (see WgOut)
 constexpr int kRetCap = 32;         // retained pairs a sweep workgroup hands to the resolve
 constexpr int kWinCap = 16;         // bonds a resolve workgroup stages in place
 constexpr int kAdjStage = 4;        // adjacency rows up to this width travel with A records
-constexpr int kAbinMax = 2048;      // A-bin workgroups at most (grid-stride beyond)
 // Spatially sorted storage: particles are kept ordered by "brick" (a block of
 // bs^3 coarse cells); one sweep workgroup owns a brick and stages the A
 // records of the brick plus one halo cell layer in LDS.
@@ -43,7 +43,6 @@ struct Ctl {
   uint32_t par0;       // parity of the block's first step (buffers used per step)
   int32_t err;         // first device-detected error (0 = none)
   uint32_t set;        // which of the two storage sets holds the particles
-  uint32_t na;         // A-list length (entries may have left the A window)
   uint32_t ovf_n[2];   // A records beyond their cell bucket, by parity
   uint32_t ret_ovf[2];    // retained pairs beyond kRetCap (the resolve then re-enumerates)
   uint32_t nwin_ovf[2];   // bonds beyond kWinCap, by parity
@@ -62,14 +61,15 @@ struct RuleD {
 struct Arr {
   float *x[2], *y[2], *z[2];
   int32_t *typ, *st, *adj, *id;  // id == nullptr: slot == id
+  uint8_t* role;                 // kRoleT / kRoleA / 0 from (type, state) and the rule
 };
+
+enum Role : uint8_t { kRoleNone = 0, kRoleT = 1, kRoleA = 2 };
 
 // Everything a kernel needs, passed by value as the kernel argument.
 struct Dev {
   Arr set[2];           // storage sets (the sort writes the other one)
   int32_t* slot_of;     // id -> slot (nullptr: identity)
-  int32_t* alist;       // slots of particles in the A window (capacity n)
-  uint8_t* inlist;      // per slot: has an entry in the A list (live or not)
   // A grid: per-cell counts by parity; bucket records (x, y, z, id), the
   // A's slot and (rows of width <= kAdjStage) its adjacency row; overflow
   // records and slots
@@ -88,11 +88,11 @@ struct Dev {
   uint8_t* tflag;       // per slot: this T has a retained pair in the current step
   int2* wgw[2];         // staged bonds (id_A, id_T), kWinCap per workgroup, by parity
   int2* wov[2];         // staged bonds beyond kWinCap (capacity n/2 + 1 each)
-  int32_t* abst[2];     // A-bin workgroup counts of eligible A's, by parity
+  int32_t* abst[2];     // per prep workgroup: A's binned, by parity
   // spatial sort
-  int32_t *bstart, *astart;  // nbricks + 1 slot offsets, A-list offsets
-  uint32_t *bcnt, *bacnt;
-  int32_t *rank, *arank;
+  int32_t* bstart;      // nbricks + 1 slot offsets
+  uint32_t* bcnt;
+  int32_t* rank;
   // outputs
   int32_t* bonds;       // stateless step: (id_A, id_T) in id_A order
   int64_t bonds_cap;
@@ -103,9 +103,10 @@ struct Dev {
   unsigned long long* sortbuf;  // stateless step: bonds beyond LDS
   Ctl* ctl;
   // geometry, rule, draws
-  int32_t n, B, nc, ncell, nwg_sweep, nwg_abin, nwg_jit, ngroups;
+  int32_t n, B, nc, ncell, nwg_sweep, nwg_prep, ngroups;
   int32_t bs, nb, nbricks, sorted;  // brick edge (cells), bricks per side, total, storage sorted
   int32_t jitter;       // 1: resident system (positions ping-pong, re-jitter by jit_c)
+                        // 0: caller's arrays, read only
   int32_t adj_staged;   // B <= kAdjStage: records carry the adjacency row
   float L, halfL, rc2, inv_w, jit_c;
   unsigned long long thresh, seed;

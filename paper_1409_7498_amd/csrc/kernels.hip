@@ -45,8 +45,10 @@ __device__ __forceinline__ W4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
   uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    // one 32x32 -> 64-bit product each (a single v_mad_u64_u32)
+    const unsigned long long p0 = 0xD2511F53ull * c0, p1 = 0xCD9E8D57ull * c2;
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
     const uint32_t n0 = hi1 ^ c1 ^ k0;
     const uint32_t n2 = hi0 ^ c3 ^ k1;
     c0 = n0;
@@ -63,8 +65,9 @@ __device__ __forceinline__ uint32_t byte_sum(uint32_t v, uint32_t acc) {
   return __builtin_amdgcn_sad_u8(v, 0u, acc);  // |bytes - 0| summed, plus acc
 }
 
-// Irwin-Hall(12) offsets of the jitter: S_d = (12 bytes) - 1530, bytes of
-// words 3d..3d+2 of the blocks (step, id, 0..2, tag).
+// Irwin-Hall(12) offsets of the synthetic initial configuration:
+// S_d = (12 bytes) - 1530, bytes of words 3d..3d+2 of the blocks
+// (step, id, 0..2, tag).
 __device__ __forceinline__ void ih12(uint32_t step, uint32_t id, uint32_t tag,
                                      unsigned long long key, int32_t S[3]) {
   const W4 a = philox(step, id, 0u, tag, key);
@@ -73,6 +76,16 @@ __device__ __forceinline__ void ih12(uint32_t step, uint32_t id, uint32_t tag,
   S[0] = (int32_t)byte_sum(a.w2, byte_sum(a.w1, byte_sum(a.w0, 0u))) - 1530;
   S[1] = (int32_t)byte_sum(b.w1, byte_sum(b.w0, byte_sum(a.w3, 0u))) - 1530;
   S[2] = (int32_t)byte_sum(c.w0, byte_sum(b.w3, byte_sum(b.w2, 0u))) - 1530;
+}
+
+// Irwin-Hall(4) offsets of the re-jitter between reaction steps (the stand-in
+// for the MD): S_d = (the 4 bytes of word d) - 510, block (step, id, 0, tag).
+__device__ __forceinline__ void ih4(uint32_t step, uint32_t id, uint32_t tag,
+                                    unsigned long long key, int32_t S[3]) {
+  const W4 a = philox(step, id, 0u, tag, key);
+  S[0] = (int32_t)byte_sum(a.w0, 0u) - 510;
+  S[1] = (int32_t)byte_sum(a.w1, 0u) - 510;
+  S[2] = (int32_t)byte_sum(a.w2, 0u) - 510;
 }
 
 __device__ __forceinline__ float wrap_box(float v, float L) {
@@ -98,6 +111,10 @@ __device__ __forceinline__ bool is_a(const Dev& d, int32_t t, int32_t s) {
 
 __device__ __forceinline__ bool is_t(const Dev& d, int32_t t, int32_t s) {
   return in_window(t, s, d.rule.type_t, d.rule.t_min, d.rule.t_max);
+}
+
+__device__ __forceinline__ uint8_t role_of(const Dev& d, int32_t t, int32_t s) {
+  return is_t(d, t, s) ? kRoleT : (is_a(d, t, s) ? kRoleA : kRoleNone);
 }
 
 __device__ __forceinline__ int cell1(float u, int nc) {
@@ -144,6 +161,7 @@ __device__ __forceinline__ Arr pick_set(const Dev& d, uint32_t s) {
   r.st = pick({u.st, v.st}, s);
   r.adj = pick({u.adj, v.adj}, s);
   r.id = pick({u.id, v.id}, s);
+  r.role = pick({u.role, v.role}, s);
   return r;
 }
 
@@ -212,7 +230,6 @@ __global__ void k_ctl_reset(Ctl* c, uint32_t step, int full) {
       c->par0 = 0;
       c->err = 0;
       c->set = 0;
-      c->na = 0;
       for (int p = 0; p < 2; ++p) {
         c->ovf_n[p] = 0;
         c->ret_ovf[p] = 0;
@@ -224,7 +241,8 @@ __global__ void k_ctl_reset(Ctl* c, uint32_t step, int full) {
   }
 }
 
-// Position validation (after a load, and for the stateless single step).
+// Position validation and the roles (after a load, and for the stateless
+// single step).
 __global__ __launch_bounds__(kThreads) void k_classify(Dev d) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= d.n) return;
@@ -232,6 +250,7 @@ __global__ __launch_bounds__(kThreads) void k_classify(Dev d) {
   const float x = pick(a.x, 0)[k], y = pick(a.y, 0)[k], z = pick(a.z, 0)[k];
   const bool ok = (x >= 0.0f && x < d.L) && (y >= 0.0f && y < d.L) && (z >= 0.0f && z < d.L);
   if (!ok) set_err(d.ctl, PR_EINVAL);
+  a.role[k] = role_of(d, a.typ[k], a.st[k]);
 }
 
 // Identity storage order after a load (slot == id), cleared T flags.
@@ -300,7 +319,7 @@ __device__ void close_group(const Dev& d, uint32_t par, uint32_t step, uint32_t 
     for (int q = 0; q < kWgOut; ++q) o[q] = src[q];
   }
   int a_elig = 0;  // the A-bin workgroup counts, strided over the groups
-  for (int q = w; q < d.nwg_abin; q += d.ngroups * kGroup) a_elig += pick(d.abst, par)[q];
+  for (int q = w; q < d.nwg_prep; q += d.ngroups * kGroup) a_elig += pick(d.abst, par)[q];
   const uint32_t nw = (uint32_t)min(o[kOutBonds], kWinCap);
   uint32_t tot = 0;
   const uint32_t off = block_scan_excl(nw, s_wave, tot);
@@ -346,25 +365,9 @@ __device__ void close_group(const Dev& d, uint32_t par, uint32_t step, uint32_t 
 }
 
 // ---------------------------------------------------------------------------
-// k_prep: [closing groups of step k - 1 when k > 0][A-bin blocks][jitter
-// blocks].  The latency-bound closing and binning blocks come first so that
-// they are dispatched before the streaming jitter blocks.
+// k_prep: [closing groups of step k - 1 when k > 0][binning of the A-role
+// particles, kThreads * kPrepRoles slots per block].
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void jittered(const Dev& d, const Arr& a, uint32_t par, uint32_t step,
-                                         int slot, float& x, float& y, float& z) {
-  x = pick(a.x, par)[slot];
-  y = pick(a.y, par)[slot];
-  z = pick(a.z, par)[slot];
-  if (d.jitter && d.jit_c != 0.0f) {
-    const uint32_t id = a.id ? (uint32_t)a.id[slot] : (uint32_t)slot;
-    int32_t S[3];
-    ih12(step, id, 1u, d.seed, S);
-    x = wrap_box(__fadd_rn(x, __fmul_rn((float)S[0], d.jit_c)), d.L);
-    y = wrap_box(__fadd_rn(y, __fmul_rn((float)S[1], d.jit_c)), d.L);
-    z = wrap_box(__fadd_rn(z, __fmul_rn((float)S[2], d.jit_c)), d.L);
-  }
-}
-
 __global__ __launch_bounds__(kThreads) void k_prep(Dev d, int k) {
   __shared__ int s_na;
   __shared__ uint32_t s_wave[kThreads / 64 + 1];
@@ -377,55 +380,86 @@ __global__ __launch_bounds__(kThreads) void k_prep(Dev d, int k) {
     return;
   }
   b -= ncl;
-  if (b < d.nwg_abin) {  // A particles -> cell buckets
-    if (threadIdx.x == 0) s_na = 0;
-    __syncthreads();
-    int mine = 0;
-    if (read_err(d.ctl) == 0) {
-      const uint32_t total = d.sorted ? d.ctl->na : (uint32_t)d.n;
-      for (uint32_t q = b * kThreads + threadIdx.x; q < total; q += d.nwg_abin * kThreads) {
-        const int slot = d.sorted ? d.alist[q] : (int)q;
-        if (!is_a(d, a.typ[slot], a.st[slot])) continue;
-        mine++;
-        float x, y, z;
-        jittered(d, a, si.par, si.step, slot, x, y, z);
-        const int id = a.id ? a.id[slot] : slot;
-        const int c = cell_of(d, x, y, z);
-        const uint32_t r = atomicAdd(&pick(d.cnt, si.par)[c], 1u);
-        const float4 rec = make_float4(x, y, z, __int_as_float(id));
-        if (r < (uint32_t)kCellCap) {
-          const size_t ri = (size_t)c * kCellCap + r;
-          d.rec[ri] = rec;
-          d.rsa[ri] = slot;
-          if (d.adj_staged) {
-            const int32_t* row = a.adj + (size_t)slot * d.B;
-            int4 q4 = make_int4(row[0], -1, -1, -1);
-            if (d.B > 1) q4.y = row[1];
-            if (d.B > 2) q4.z = row[2];
-            if (d.B > 3) q4.w = row[3];
-            d.radj[ri] = q4;
-          }
-        } else {
-          const uint32_t o = atomicAdd(&d.ctl->ovf_n[si.par], 1u);
-          pick(d.ovf, si.par)[o] = rec;
-          pick(d.ovf_sa, si.par)[o] = slot;
-        }
+  // binning of the A's: each lane scans kPrepRoles role bytes, the slots of
+  // the wavefront's A's are compacted into LDS (ballot-free: a wave prefix
+  // sum of the per-lane counts) and handled one per lane.  An A's record
+  // holds its re-jittered position (the same draws as the sweep's), id, slot
+  // and adjacency row.
+  __shared__ int32_t s_list[kThreads / 64][kPrepRoles * 64];
+  if (threadIdx.x == 0) s_na = 0;
+  const int lane = __lane_id(), wv = threadIdx.x >> 6;
+  const int i0 = (b * kThreads + threadIdx.x) * kPrepRoles;
+  const bool ok = read_err(d.ctl) == 0;
+  uint32_t rw[kPrepRoles / 4] = {0u, 0u, 0u, 0u};
+  if (ok && i0 + kPrepRoles <= d.n) {
+    const uint4 v = *(const uint4*)(a.role + i0);
+    rw[0] = v.x;
+    rw[1] = v.y;
+    rw[2] = v.z;
+    rw[3] = v.w;
+  } else if (ok && i0 < d.n) {
+#pragma unroll
+    for (int q = 0; q < kPrepRoles / 4; ++q)
+      for (int e = 0; e < 4; ++e) {
+        const int i = i0 + 4 * q + e;
+        if (i < d.n) rw[q] |= (uint32_t)a.role[i] << (8 * e);
       }
-    }
-    wave_add(&s_na, mine);
-    __syncthreads();
-    if (threadIdx.x == 0) pick(d.abst, si.par)[b] = s_na;
-    return;
   }
-  b -= d.nwg_abin;
-  // re-jitter: positions of parity par -> par ^ 1
-  const int i = b * kThreads + threadIdx.x;
-  if (i >= d.n || read_err(d.ctl)) return;
-  float x, y, z;
-  jittered(d, a, si.par, si.step, i, x, y, z);
-  pick(a.x, si.par ^ 1u)[i] = x;
-  pick(a.y, si.par ^ 1u)[i] = y;
-  pick(a.z, si.par ^ 1u)[i] = z;
+  int na = 0;
+#pragma unroll
+  for (int q = 0; q < kPrepRoles / 4; ++q)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) na += ((rw[q] >> (8 * e)) & 0xFFu) == kRoleA;
+  uint32_t incl = (uint32_t)na;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(incl, o);
+    if (lane >= o) incl += y;
+  }
+  const int wtot = (int)__shfl(incl, 63);
+  int at = (int)incl - na;
+#pragma unroll
+  for (int q = 0; q < kPrepRoles / 4; ++q)
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (((rw[q] >> (8 * e)) & 0xFFu) == kRoleA) s_list[wv][at++] = i0 + 4 * q + e;
+  __syncthreads();
+  for (int e = lane; e < wtot; e += 64) {
+    const int i = s_list[wv][e];
+    float x = pick(a.x, si.par)[i], y = pick(a.y, si.par)[i], z = pick(a.z, si.par)[i];
+    const int id = a.id ? a.id[i] : i;
+    int4 q4 = make_int4(-1, -1, -1, -1);
+    if (d.adj_staged) {
+      const int32_t* row = a.adj + (size_t)i * d.B;
+      q4.x = row[0];
+      if (d.B > 1) q4.y = row[1];
+      if (d.B > 2) q4.z = row[2];
+      if (d.B > 3) q4.w = row[3];
+    }
+    if (d.jitter && d.jit_c != 0.0f) {
+      int32_t S[3];
+      ih4(si.step, (uint32_t)id, 1u, d.seed, S);
+      x = wrap_box(__fadd_rn(x, __fmul_rn((float)S[0], d.jit_c)), d.L);
+      y = wrap_box(__fadd_rn(y, __fmul_rn((float)S[1], d.jit_c)), d.L);
+      z = wrap_box(__fadd_rn(z, __fmul_rn((float)S[2], d.jit_c)), d.L);
+    }
+    const int c = cell_of(d, x, y, z);
+    const uint32_t r = atomicAdd(&pick(d.cnt, si.par)[c], 1u);
+    const float4 rec = make_float4(x, y, z, __int_as_float(id));
+    if (r < (uint32_t)kCellCap) {
+      const size_t ri = (size_t)c * kCellCap + r;
+      d.rec[ri] = rec;
+      d.rsa[ri] = i;
+      if (d.adj_staged) d.radj[ri] = q4;
+    } else {
+      const uint32_t o = atomicAdd(&d.ctl->ovf_n[si.par], 1u);
+      pick(d.ovf, si.par)[o] = rec;
+      pick(d.ovf_sa, si.par)[o] = i;
+    }
+  }
+  if (lane == 0 && wtot) atomicAdd(&s_na, wtot);
+  __syncthreads();
+  if (threadIdx.x == 0) pick(d.abst, si.par)[b] = s_na;
 }
 
 // Closes step k of the block (one workgroup per closing group).
@@ -578,46 +612,35 @@ __device__ __forceinline__ void retain(const Dev& d, const Arr& a, uint32_t step
 }
 
 // ---------------------------------------------------------------------------
-// k_sweep: kBrick = sorted storage, one workgroup per brick with the A records
+// k_sweep: every particle is re-jittered (resident systems) and written to
+// the other position buffer; T's test the step's A records at their new
+// positions.  kBrick = sorted storage: one workgroup per brick, the A records
 // of the brick and its halo (positions, ids, slots, adjacency rows) staged in
-// LDS, one record per thread.  The brick's particles are loaded a pass of
-// kTPass at a time.  A T whose 2x2x2 cell block lies in the staged region
-// scans it as four runs of two x-adjacent cells (contiguous in LDS); its
-// in-range pairs are kept in registers and enter the LDS queue with one
-// reservation per wavefront, and the queue is drawn on full wavefronts after
-// the pass.  Other T's (particles that drifted out of the staged region since
-// the last sort, bricks whose region holds more than kStageRecs records, any
-// step with bucket overflow, kBrick = false where a workgroup takes kThreads
-// consecutive slots) read the global buckets and draw at once.
+// LDS, one record per thread, and the brick's particles handled kTPass at a
+// time.  A T whose 2x2x2 cell block lies in the staged region scans it as four
+// runs of two x-adjacent cells (contiguous in LDS) and keeps up to three
+// in-range pairs in registers; the wavefront then reserves queue slots for all
+// of them at once (ballot and mbcnt over the per-lane counts) and the queue is
+// drawn on full wavefronts after the pass.  Every other T is deferred to a
+// list and scanned again, after the queue, in the global buckets: T's with
+// more than three in-range pairs or whose pairs find the queue full,
+// particles that drifted out of the staged region since the last sort,
+// bricks whose region holds more than kStageRecs records, steps with bucket
+// overflow, and all T's of kBrick = false (kThreads consecutive slots per
+// workgroup).  A deferred T enters the queue with none of its pairs, so every
+// pair is drawn exactly once.
 // ---------------------------------------------------------------------------
-// An in-range pair (local T, staged record r) into the three register slots;
-// false (and spill = q) when they are full.
-__device__ __forceinline__ bool hold_hit(int q, int r, int lt, int& nh, uint32_t& h0,
-                                         uint32_t& h1, uint32_t& h2, int& spill, int& in_rc) {
-  if (nh == 3) {
-    spill = q;
-    return false;
-  }
-  in_rc++;
-  h2 = h1;
-  h1 = h0;
-  h0 = (uint32_t)lt | ((uint32_t)r << 16);
-  nh++;
-  return true;
-}
-
 // One particle of a sweep pass, loaded with coalesced SoA reads.
 struct Part {
-  int typ, st, id;
+  int role, id;
   float x, y, z;
 };
 
 __device__ __forceinline__ Part load_part(const Arr& a, const float* X, const float* Y,
                                           const float* Z, int slot, int s1) {
-  Part q{-1, 0, 0, 0.0f, 0.0f, 0.0f};
+  Part q{kRoleNone, 0, 0.0f, 0.0f, 0.0f};
   if (slot < s1) {
-    q.typ = a.typ[slot];
-    q.st = a.st[slot];
+    q.role = a.role[slot];
     q.x = X[slot];
     q.y = Y[slot];
     q.z = Z[slot];
@@ -626,9 +649,36 @@ __device__ __forceinline__ Part load_part(const Arr& a, const float* X, const fl
   return q;
 }
 
+// The re-jittered position (identical arithmetic in k_prep and k_sweep).
+__device__ __forceinline__ void rejitter(const Dev& d, uint32_t step, uint32_t id, float& x,
+                                         float& y, float& z) {
+  int32_t S[3];
+  ih4(step, id, 1u, d.seed, S);
+  x = wrap_box(__fadd_rn(x, __fmul_rn((float)S[0], d.jit_c)), d.L);
+  y = wrap_box(__fadd_rn(y, __fmul_rn((float)S[1], d.jit_c)), d.L);
+  z = wrap_box(__fadd_rn(z, __fmul_rn((float)S[2], d.jit_c)), d.L);
+}
+
+// An in-range pair (local T, staged record r) into the three register slots;
+// false when they are full (the T is then deferred).
+__device__ __forceinline__ bool hold_hit(int r, int lt, int& nh, uint32_t& h0, uint32_t& h1,
+                                         uint32_t& h2) {
+  if (nh == 3) return false;
+  h2 = h1;
+  h1 = h0;
+  h0 = (uint32_t)lt | ((uint32_t)r << 16);
+  nh++;
+  return true;
+}
+
+__device__ __forceinline__ uint32_t lanes_below(unsigned long long b) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+}
+
 template <bool kBrick>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) void k_sweep(Dev d, int k) {
   constexpr int kPer = kBrick ? kTPass / kThreads : 1;
+  constexpr int kTP = kPer * kThreads;
   constexpr uint32_t kNoRec = 0xFFFFu;
   __shared__ float4 s_rec[kBrick ? kStageRecs : 1];
   __shared__ int4 s_radj[kBrick ? kStageRecs : 1];
@@ -636,15 +686,17 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
   __shared__ uint32_t s_off[kBrick ? kStageCells + 1 : 1];
   __shared__ int32_t s_cid[kBrick ? kStageCells : 1];
   __shared__ int4 s_q[kBrick ? kQueue : 1];  // (id_A, slot_A, id_T, local T | record << 16)
+  __shared__ uint16_t s_def[kTP];            // deferred T's (local index in the pass)
   __shared__ int4 s_ent[kRetCap];
   __shared__ uint32_t s_ew2[kRetCap];
   __shared__ uint32_t s_wave[kThreads / 64 + 1];
   __shared__ int s_cnt[4];
-  __shared__ int s_qn, s_ne, s_dead;
-  const int tid = threadIdx.x, w = blockIdx.x, lane = __lane_id();
+  __shared__ int s_qn, s_ndef, s_ne, s_dead;
+  const int tid = threadIdx.x, w = blockIdx.x;
   if (tid < 4) s_cnt[tid] = 0;
   if (tid == 0) {
     s_qn = 0;
+    s_ndef = 0;
     s_ne = 0;
     s_dead = read_err(d.ctl) != 0;
   }
@@ -652,7 +704,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
   const StepInfo si = step_info(c, k);
   const uint32_t par = si.par, step = si.step;
   const Arr a = pick_set(d, c->set & 1u);
-  const float *X = pick(a.x, par ^ 1u), *Y = pick(a.y, par ^ 1u), *Z = pick(a.z, par ^ 1u);
+  // positions of the previous step (parity par); the re-jittered ones are
+  // written to parity par ^ 1
+  const float *X = pick(a.x, par), *Y = pick(a.y, par), *Z = pick(a.z, par);
+  float *XW = pick(a.x, par ^ 1u), *YW = pick(a.y, par ^ 1u), *ZW = pick(a.z, par ^ 1u);
+  const bool jit = d.jitter && d.jit_c != 0.0f;
   const uint32_t novf = c->ovf_n[par];
   const RetList rl{&s_ne, s_ent, s_ew2};
   int s0, s1;
@@ -711,7 +767,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
   __syncthreads();
   const bool dead = s_dead != 0;
   SweepAcc n = {0, 0, 0, 0};
-  for (int base = s0; base < s1 && !dead; base += kPer * kThreads) {
+  for (int base = s0; base < s1 && !dead; base += kTP) {
     if (base != s0) cur = load_part(a, X, Y, Z, base + tid, s1);
 #pragma unroll 1
     for (int u = 0; u < kPer; ++u) {
@@ -720,142 +776,150 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
       // the next particle's loads are in flight while this one is handled
       Part nxt = cur;
       if (u + 1 < kPer) nxt = load_part(a, X, Y, Z, slot + kThreads, s1);
-      // in-range pairs with staged A's: up to three held in registers as
-      // (local T | record << 16), more go to the queue one by one
+      const uint32_t idj = (uint32_t)cur.id;
+      if (slot < s1 && d.jitter) {  // the re-jitter (stand-in for the MD between steps)
+        if (jit) rejitter(d, step, idj, cur.x, cur.y, cur.z);
+        XW[slot] = cur.x;
+        YW[slot] = cur.y;
+        ZW[slot] = cur.z;
+      }
       int nh = 0;
       uint32_t h0 = 0, h1 = 0, h2 = 0;
-      const uint32_t idj = (uint32_t)cur.id;
-      if (slot < s1 && is_t(d, cur.typ, cur.st)) {
+      bool defer = false;
+      if (slot < s1 && cur.role == kRoleT) {
         n.t_elig++;
-        const float px = cur.x, py = cur.y, pz = cur.z;
-        int cx0, cx1, cy0, cy1, cz0, cz1;
-        lo_hi(px, d.inv_w, nc, cx0, cx1);
-        lo_hi(py, d.inv_w, nc, cy0, cy1);
-        lo_hi(pz, d.inv_w, nc, cz0, cz1);
-        bool inside = false;
-        int lx0 = 0, ly0 = 0, lz0 = 0;
+        defer = true;
         if (kBrick && staged) {
-          lx0 = local_of(cx0, bx, nc);
-          ly0 = local_of(cy0, by, nc);
-          lz0 = local_of(cz0, bz, nc);
+          const float px = cur.x, py = cur.y, pz = cur.z;
+          int cx0, cx1, cy0, cy1, cz0, cz1;
+          lo_hi(px, d.inv_w, nc, cx0, cx1);
+          lo_hi(py, d.inv_w, nc, cy0, cy1);
+          lo_hi(pz, d.inv_w, nc, cz0, cz1);
+          const int lx0 = local_of(cx0, bx, nc), ly0 = local_of(cy0, by, nc),
+                    lz0 = local_of(cz0, bz, nc);
           const int lx1 = local_of(cx1, bx, nc), ly1 = local_of(cy1, by, nc),
                     lz1 = local_of(cz1, bz, nc);
-          inside = lx1 == lx0 + 1 && ly1 == ly0 + 1 && lz1 == lz0 + 1 && lx1 < ex &&
-                   ly1 < ey && lz1 < ez;
-        }
-        if (inside) {
-          // runs (dy, dz) = (0,0), (1,0), (0,1), (1,1): cells lx0 and lx0 + 1
-          const int l0 = (lz0 * ey + ly0) * ex + lx0;
-          const int l1 = l0 + ex, l2 = l0 + ex * ey, l3 = l2 + ex;
-          const int b0 = (int)s_off[l0], b1 = (int)s_off[l1], b2 = (int)s_off[l2],
-                    b3 = (int)s_off[l3];
-          const int p1 = (int)s_off[l0 + 2] - b0;
-          const int p2 = p1 + (int)s_off[l1 + 2] - b1;
-          const int p3 = p2 + (int)s_off[l2 + 2] - b2;
-          const int tot = p3 + (int)s_off[l3 + 2] - b3;
-          const int o1 = b1 - p1, o2 = b2 - p2, o3 = b3 - p3;
-          // the first three in-range records go to registers; from a fourth
-          // on (rare) the rest of the runs is scanned again below
-          int spill = -1;
-          if (nowrap) {  // no difference can reach L/2 in this region
-            for (int q = 0; q < tot; ++q) {
-              const int r = q + (q < p1 ? b0 : (q < p2 ? o1 : (q < p3 ? o2 : o3)));
-              if (!(dist2_plain(px, py, pz, s_rec[r]) < d.rc2)) continue;
-              if (!hold_hit(q, r, lt, nh, h0, h1, h2, spill, n.in_rc)) break;
-            }
-          } else {
-            for (int q = 0; q < tot; ++q) {
-              const int r = q + (q < p1 ? b0 : (q < p2 ? o1 : (q < p3 ? o2 : o3)));
-              if (!(dist2(d, px, py, pz, s_rec[r]) < d.rc2)) continue;
-              if (!hold_hit(q, r, lt, nh, h0, h1, h2, spill, n.in_rc)) break;
-            }
-          }
-          for (int q = spill; q >= 0 && q < tot; ++q) {
-            const int r = q + (q < p1 ? b0 : (q < p2 ? o1 : (q < p3 ? o2 : o3)));
-            const float4 A = s_rec[r];
-            if (!(dist2(d, px, py, pz, A) < d.rc2)) continue;
-            n.in_rc++;
-            const int p = atomicAdd(&s_qn, 1);
-            if (p < kQueue)
-              s_q[p] = make_int4(__float_as_int(A.w), s_rsa[r], (int)idj,
-                                 (int)((uint32_t)lt | ((uint32_t)r << 16)));
-            else
-              retain(d, a, step, __float_as_int(A.w), s_rsa[r], idj, slot,
-                     d.adj_staged ? &s_radj[r] : nullptr, n, rl);
-          }
-        } else {
-          // global buckets (cells 0-7 of the block), then the overflow list
-          const int m = nc > 1 ? 2 : 1;
-          const float4* ovf = pick(d.ovf, par);
-          const int32_t* osa = pick(d.ovf_sa, par);
-          for (int q = 0; q < 9; ++q) {
-            const float4* rp;
-            const int32_t* sp;
-            uint32_t nr;
-            if (q < 8) {
-              const int ia = q >> 2, ib = (q >> 1) & 1, ie = q & 1;
-              if (ia >= m || ib >= m || ie >= m) continue;
-              const int cc = ((ia ? cz1 : cz0) * nc + (ib ? cy1 : cy0)) * nc + (ie ? cx1 : cx0);
-              nr = pick(d.cnt, par)[cc];
-              nr = nr < (uint32_t)kCellCap ? nr : (uint32_t)kCellCap;
-              rp = d.rec + (size_t)cc * kCellCap;
-              sp = d.rsa + (size_t)cc * kCellCap;
+          if (lx1 == lx0 + 1 && ly1 == ly0 + 1 && lz1 == lz0 + 1 && lx1 < ex && ly1 < ey &&
+              lz1 < ez) {
+            // runs (dy, dz) = (0,0), (1,0), (0,1), (1,1): cells lx0 and lx0 + 1
+            const int l0 = (lz0 * ey + ly0) * ex + lx0;
+            const int l1 = l0 + ex, l2 = l0 + ex * ey, l3 = l2 + ex;
+            const int b0 = (int)s_off[l0], b1 = (int)s_off[l1], b2 = (int)s_off[l2],
+                      b3 = (int)s_off[l3];
+            const int p1 = (int)s_off[l0 + 2] - b0;
+            const int p2 = p1 + (int)s_off[l1 + 2] - b1;
+            const int p3 = p2 + (int)s_off[l2 + 2] - b2;
+            const int tot = p3 + (int)s_off[l3 + 2] - b3;
+            const int o1 = b1 - p1, o2 = b2 - p2, o3 = b3 - p3;
+            bool full = false;
+            if (nowrap) {  // no difference can reach L/2 in this region
+              for (int q = 0; q < tot && !full; ++q) {
+                const int r = q + (q < p1 ? b0 : (q < p2 ? o1 : (q < p3 ? o2 : o3)));
+                if (dist2_plain(px, py, pz, s_rec[r]) < d.rc2)
+                  full = !hold_hit(r, lt, nh, h0, h1, h2);
+              }
             } else {
-              nr = novf;
-              rp = ovf;
-              sp = osa;
+              for (int q = 0; q < tot && !full; ++q) {
+                const int r = q + (q < p1 ? b0 : (q < p2 ? o1 : (q < p3 ? o2 : o3)));
+                if (dist2(d, px, py, pz, s_rec[r]) < d.rc2)
+                  full = !hold_hit(r, lt, nh, h0, h1, h2);
+              }
             }
-            for (uint32_t r = 0; r < nr; ++r) {
-              const float4 A = rp[r];
-              if (!(dist2(d, px, py, pz, A) < d.rc2)) continue;
-              n.in_rc++;
-              retain(d, a, step, __float_as_int(A.w), sp[r], idj, slot, nullptr, n, rl);
-            }
+            defer = full;
           }
         }
       }
+      if (defer) nh = 0;
       if (kBrick) {
-        // one queue reservation per wavefront for the pairs held in registers
-        uint32_t incl = (uint32_t)nh;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-          const uint32_t y = __shfl_up(incl, o);
-          if (lane >= o) incl += y;
-        }
-        const uint32_t wtot = __shfl(incl, 63);
+        // queue slots for the wavefront's held pairs: lane j's pairs go after
+        // those of the lower lanes (counts from three ballots)
+        const unsigned long long g1 = __ballot(nh >= 1), g2 = __ballot(nh >= 2),
+                                 g3 = __ballot(nh >= 3);
+        const uint32_t wtot = (uint32_t)(__popcll(g1) + __popcll(g2) + __popcll(g3));
         if (wtot) {
           uint32_t qb = 0;
-          if (lane == 0) qb = (uint32_t)atomicAdd(&s_qn, (int)wtot);
-          qb = __shfl(qb, 0) + incl - (uint32_t)nh;
-          for (int j = 0; j < nh; ++j) {
-            const uint32_t hw = j == 0 ? h0 : (j == 1 ? h1 : h2);
-            const uint32_t r = hw >> 16;
-            const int ida = __float_as_int(s_rec[r].w), sa = s_rsa[r];
-            const uint32_t p = qb + (uint32_t)j;
-            if (p < (uint32_t)kQueue)
-              s_q[p] = make_int4(ida, sa, (int)idj, (int)hw);
-            else
-              retain(d, a, step, ida, sa, idj, slot, d.adj_staged ? &s_radj[r] : nullptr, n,
-                     rl);
+          if (__lane_id() == 0) qb = (uint32_t)atomicAdd(&s_qn, (int)wtot);
+          qb = (uint32_t)__builtin_amdgcn_readlane((int)qb, 0);
+          const uint32_t p = qb + lanes_below(g1) + lanes_below(g2) + lanes_below(g3);
+          if (nh > 0) {
+            if (p + (uint32_t)nh <= (uint32_t)kQueue) {
+              n.in_rc += nh;
+              for (int j = 0; j < nh; ++j) {
+                const uint32_t hw = j == 0 ? h0 : (j == 1 ? h1 : h2);
+                const uint32_t r = hw >> 16;
+                s_q[p + j] = make_int4(__float_as_int(s_rec[r].w), s_rsa[r], (int)idj, (int)hw);
+              }
+            } else {
+              // the pairs do not all fit: the T is deferred and the slots it
+              // reserved below kQueue are marked empty
+              for (int j = 0; j < nh; ++j)
+                if (p + j < (uint32_t)kQueue) s_q[p + j] = make_int4(-1, 0, 0, 0);
+              defer = true;
+            }
           }
         }
       }
+      if (defer) s_def[atomicAdd(&s_ndef, 1)] = (uint16_t)lt;
       cur = nxt;
     }
+    __syncthreads();
     if (kBrick) {
-      __syncthreads();
       // the pass's queued pairs: draws on full wavefronts
       const int qn = min(s_qn, kQueue);
       for (int e = tid; e < qn; e += kThreads) {
         const int4 q = s_q[e];
+        if (q.x < 0) continue;
         const uint32_t lt = (uint32_t)q.w & 0xFFFFu, r = (uint32_t)q.w >> 16;
         retain(d, a, step, q.x, q.y, (uint32_t)q.z, base + (int)lt,
                r != kNoRec && d.adj_staged ? &s_radj[r] : nullptr, n, rl);
       }
-      __syncthreads();
-      if (tid == 0) s_qn = 0;
-      __syncthreads();
     }
+    // the deferred T's, in the global buckets (cells 0-7 of the block, then
+    // the overflow list), re-jittered again from the previous positions
+    const int ndef = s_ndef;
+    for (int e = tid; e < ndef; e += kThreads) {
+      const int slot = base + (int)s_def[e];
+      float px = X[slot], py = Y[slot], pz = Z[slot];
+      const uint32_t idj = a.id ? (uint32_t)a.id[slot] : (uint32_t)slot;
+      if (jit) rejitter(d, step, idj, px, py, pz);
+      int cx0, cx1, cy0, cy1, cz0, cz1;
+      lo_hi(px, d.inv_w, nc, cx0, cx1);
+      lo_hi(py, d.inv_w, nc, cy0, cy1);
+      lo_hi(pz, d.inv_w, nc, cz0, cz1);
+      const int m = nc > 1 ? 2 : 1;
+      const float4* ovf = pick(d.ovf, par);
+      const int32_t* osa = pick(d.ovf_sa, par);
+      for (int q = 0; q < 9; ++q) {
+        const float4* rp;
+        const int32_t* sp;
+        uint32_t nr;
+        if (q < 8) {
+          const int ia = q >> 2, ib = (q >> 1) & 1, ie = q & 1;
+          if (ia >= m || ib >= m || ie >= m) continue;
+          const int cc = ((ia ? cz1 : cz0) * nc + (ib ? cy1 : cy0)) * nc + (ie ? cx1 : cx0);
+          nr = pick(d.cnt, par)[cc];
+          nr = nr < (uint32_t)kCellCap ? nr : (uint32_t)kCellCap;
+          rp = d.rec + (size_t)cc * kCellCap;
+          sp = d.rsa + (size_t)cc * kCellCap;
+        } else {
+          nr = novf;
+          rp = ovf;
+          sp = osa;
+        }
+        for (uint32_t r = 0; r < nr; ++r) {
+          const float4 A = rp[r];
+          if (!(dist2(d, px, py, pz, A) < d.rc2)) continue;
+          n.in_rc++;
+          retain(d, a, step, __float_as_int(A.w), sp[r], idj, slot, nullptr, n, rl);
+        }
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      s_qn = 0;
+      s_ndef = 0;
+    }
+    __syncthreads();
   }
   wave_add(&s_cnt[kOutTElig], n.t_elig);
   wave_add(&s_cnt[kOutInRc], n.in_rc);
@@ -898,15 +962,15 @@ __device__ __forceinline__ bool adj_append(int32_t* row, int B, int32_t v) {
 struct BondCtx {
   int* nw;
   int* lost;
-  int* add;
-  int* nadd;
 };
 
 __device__ __forceinline__ void make_bond(const Dev& d, const Arr& a, uint32_t par, int w,
                                           int ida, int sa, int sj, int idj, const BondCtx& b) {
-  a.st[sa] += d.rule.d_a;
-  const int32_t nt = a.st[sj] + d.rule.d_t;
+  const int32_t na = a.st[sa] + d.rule.d_a, nt = a.st[sj] + d.rule.d_t;
+  a.st[sa] = na;
   a.st[sj] = nt;
+  a.role[sa] = role_of(d, a.typ[sa], na);
+  a.role[sj] = role_of(d, a.typ[sj], nt);
   int lost = 0;
   if (!adj_append(a.adj + (size_t)sa * d.B, d.B, (int32_t)idj)) lost++;
   if (!adj_append(a.adj + (size_t)sj * d.B, d.B, (int32_t)ida)) lost++;
@@ -918,18 +982,11 @@ __device__ __forceinline__ void make_bond(const Dev& d, const Arr& a, uint32_t p
     const uint32_t o = atomicAdd(&d.ctl->nwin_ovf[par], 1u);
     pick(d.wov, par)[o] = make_int2(ida, idj);
   }
-  // a T entering the A window joins the A list, unless an entry of an
-  // earlier stay in the window is still there (it is live again now)
-  if (d.sorted && is_a(d, a.typ[sj], nt) && !d.inlist[sj]) {
-    d.inlist[sj] = 1;
-    b.add[atomicAdd(b.nadd, 1)] = sj;
-  }
 }
 
 template <bool kBrick>
 __global__ __launch_bounds__(kThreads) void k_resolve(Dev d, int k) {
-  __shared__ int s_nw, s_lost, s_nadd, s_abase, s_prop, s_mode;
-  __shared__ int32_t s_add[kThreads];
+  __shared__ int s_nw, s_lost, s_prop, s_mode;
   __shared__ unsigned long long s_key[kRetCap];
   __shared__ int32_t s_sj[kRetCap];
   const int tid = threadIdx.x, w = blockIdx.x;
@@ -939,25 +996,13 @@ __global__ __launch_bounds__(kThreads) void k_resolve(Dev d, int k) {
   if (tid == 0) {
     s_nw = 0;
     s_lost = 0;
-    s_nadd = 0;
     s_prop = 0;
     s_mode = read_err(c) ? 0 : (c->ret_ovf[par] ? 2 : 1);
   }
   __syncthreads();
   const int mode = s_mode;
   const Arr a = pick_set(d, c->set & 1u);
-  const BondCtx bc{&s_nw, &s_lost, s_add, &s_nadd};
-  auto flush_adds = [&]() {  // every thread; after a barrier
-    const int nadd = s_nadd;
-    if (nadd) {
-      if (tid == 0) s_abase = (int)atomicAdd(&d.ctl->na, (uint32_t)nadd);
-      __syncthreads();
-      if (tid < nadd) d.alist[s_abase + tid] = s_add[tid];
-      __syncthreads();
-      if (tid == 0) s_nadd = 0;
-    }
-    __syncthreads();
-  };
+  const BondCtx bc{&s_nw, &s_lost};
   if (mode == 1) {
     const int ne = pick(d.wgo, par)[w * kWgOut + kOutRet];
     if (ne > 0) {
@@ -984,8 +1029,6 @@ __global__ __launch_bounds__(kThreads) void k_resolve(Dev d, int k) {
           if (s_sj[f] == e.z && s_key[f] < key) win = false;
         if (win) make_bond(d, a, par, w, e.x, e.y, e.z, e.w, bc);
       }
-      __syncthreads();
-      flush_adds();
     }
   } else if (mode == 2) {
     const float *X = pick(a.x, par ^ 1u), *Y = pick(a.y, par ^ 1u), *Z = pick(a.z, par ^ 1u);
@@ -1016,10 +1059,9 @@ __global__ __launch_bounds__(kThreads) void k_resolve(Dev d, int k) {
         if (np) atomicAdd(&s_prop, np);
         if (best != kEmpty) make_bond(d, a, par, w, (int)(uint32_t)best, best_sa, slot, (int)idj, bc);
       }
-      __syncthreads();
-      flush_adds();
     }
   }
+  __syncthreads();
   if (tid == 0) {
     int32_t* out = pick(d.wgo, par) + w * kWgOut;
     out[kOutProp] = s_prop;
@@ -1096,28 +1138,18 @@ __global__ __launch_bounds__(kThreads) void k_sort_count(Dev d) {
   const uint32_t par = d.ctl->par0;
   const bool active = k < d.n;
   int b = -1;
-  bool isA = false;
-  if (active) {
-    b = brick_of(d, pick(a.x, par)[k], pick(a.y, par)[k], pick(a.z, par)[k]);
-    isA = is_a(d, a.typ[k], a.st[k]);
-  }
+  if (active) b = brick_of(d, pick(a.x, par)[k], pick(a.y, par)[k], pick(a.z, par)[k]);
   unsigned long long rem = __ballot(active);
   while (rem) {
     const int leader = __ffsll((long long)rem) - 1;
     const int bl = __shfl(b, leader);
     const unsigned long long same = __ballot(active && b == bl);
-    const unsigned long long sameA = __ballot(active && b == bl && isA);
-    uint32_t base = 0, abase = 0;
-    if (__lane_id() == leader) {
-      base = atomicAdd(&d.bcnt[bl], (uint32_t)__popcll(same));
-      if (sameA) abase = atomicAdd(&d.bacnt[bl], (uint32_t)__popcll(sameA));
-    }
+    uint32_t base = 0;
+    if (__lane_id() == leader) base = atomicAdd(&d.bcnt[bl], (uint32_t)__popcll(same));
     base = __shfl(base, leader);
-    abase = __shfl(abase, leader);
     if (active && b == bl) {
       const unsigned long long lt = (1ull << __lane_id()) - 1ull;
       d.rank[k] = (int32_t)(base + __popcll(same & lt));
-      d.arank[k] = isA ? (int32_t)(abase + __popcll(sameA & lt)) : -1;
     }
     rem &= ~same;
   }
@@ -1125,28 +1157,19 @@ __global__ __launch_bounds__(kThreads) void k_sort_count(Dev d) {
 
 __global__ __launch_bounds__(kFinThreads) void k_sort_scan(Dev d) {
   __shared__ uint32_t s_wave[kFinThreads / 64 + 1];
-  uint32_t carry = 0, acarry = 0;
+  uint32_t carry = 0;
   for (int base = 0; base < d.nbricks; base += blockDim.x) {
     const int b = base + threadIdx.x;
     const uint32_t v = b < d.nbricks ? d.bcnt[b] : 0u;
-    const uint32_t va = b < d.nbricks ? d.bacnt[b] : 0u;
-    uint32_t total = 0, atotal = 0;
+    uint32_t total = 0;
     const uint32_t ex = block_scan_excl(v, s_wave, total);
-    const uint32_t exa = block_scan_excl(va, s_wave, atotal);
     if (b < d.nbricks) {
       d.bstart[b] = (int32_t)(carry + ex);
-      d.astart[b] = (int32_t)(acarry + exa);
       d.bcnt[b] = 0u;
-      d.bacnt[b] = 0u;
     }
     carry += total;
-    acarry += atotal;
   }
-  if (threadIdx.x == 0) {
-    d.bstart[d.nbricks] = (int32_t)carry;
-    d.astart[d.nbricks] = (int32_t)acarry;
-    d.ctl->na = acarry;
-  }
+  if (threadIdx.x == 0) d.bstart[d.nbricks] = (int32_t)carry;
 }
 
 __global__ __launch_bounds__(kThreads) void k_sort_scatter(Dev d) {
@@ -1162,13 +1185,11 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(Dev d) {
   pick(o.z, par)[ns] = z;
   o.typ[ns] = a.typ[k];
   o.st[ns] = a.st[k];
+  o.role[ns] = a.role[k];
   const int id = a.id[k];
   o.id[ns] = id;
   d.slot_of[id] = ns;
   for (int q = 0; q < d.B; ++q) o.adj[(size_t)ns * d.B + q] = a.adj[(size_t)k * d.B + q];
-  const int ar = d.arank[k];
-  d.inlist[ns] = ar >= 0 ? 1 : 0;
-  if (ar >= 0) d.alist[d.astart[b] + ar] = ns;
 }
 
 __global__ void k_sort_flip(Ctl* c) {
@@ -1218,19 +1239,10 @@ hipError_t launch_generate(const Dev& d, int kind, unsigned long long gseed, flo
   return hipGetLastError();
 }
 
-// A-bin grid: fixed (it is captured into graphs); sized for the expected
-// work, grid-stride beyond.
-int abin_blocks(long long work) {
-  long long b = blocks_for(work > 0 ? work : 1, kThreads);
-  if (b < 16) b = 16;
-  if (b > kAbinMax) b = kAbinMax;
-  return (int)b;
-}
-
 // Step k of a block: prep (with the closing of step k - 1), sweep, resolve.
 hipError_t launch_step(const Dev& d, int k, hipStream_t s, hipEvent_t ev_sweep0,
                        hipEvent_t ev_sweep1) {
-  const int prep_blocks = d.nwg_jit + d.nwg_abin + (k > 0 ? d.ngroups : 0);
+  const int prep_blocks = d.nwg_prep + (k > 0 ? d.ngroups : 0);
   k_prep<<<prep_blocks, kThreads, 0, s>>>(d, k);
   if (ev_sweep0) (void)hipEventRecord(ev_sweep0, s);
   if (d.sorted)

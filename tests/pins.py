@@ -342,28 +342,43 @@ def check_run_invariants(lib, steps=200, p=0.05):
 # --------------------------------------------------------------------------
 # jitter (synthetic stand-in for MD between reaction steps)
 # --------------------------------------------------------------------------
-def ih12_exact_pmf():
-    """Exact pmf of the sum of 12 independent uniform bytes, by convolution."""
+def ih_exact_pmf(nbytes):
+    """Exact pmf of the sum of ``nbytes`` independent uniform bytes, by convolution."""
     pmf = np.array([1.0])
     byte = np.full(256, 1.0 / 256)
-    for _ in range(12):
+    for _ in range(nbytes):
         pmf = np.convolve(pmf, byte)
-    return pmf  # index k <-> sum k, k = 0..3060
+    return pmf  # index k <-> sum k, k = 0..255*nbytes
 
 
-def check_jitter_distribution(lib, n=30000):
-    S = oracle.ih12_offsets(3, np.arange(n), 1, 12345, lib=lib).ravel().astype(np.int64)
-    assert S.min() >= -1530 and S.max() <= 1530
-    assert abs(S.mean()) < 5 * math.sqrt(65535 / S.size), S.mean()
-    assert abs(S.var() / 65535 - 1) < 0.03
-    pmf = ih12_exact_pmf()
-    idx = np.clip(np.searchsorted(np.cumsum(pmf), np.linspace(0, 1, 31)[1:-1]), 0, 3060)
-    bins = np.concatenate([[-1], idx, [3060]])
-    obs = np.histogram(S + 1530, bins=bins + 0.5)[0]
+def _check_ih(S, nbytes):
+    """S (integer offsets, flattened) against Irwin-Hall(nbytes) on bytes:
+    range, mean, variance nbytes*65535/12 and a chi-square over 30 equiprobable
+    bins of the exact pmf."""
+    half = 255 * nbytes // 2
+    var = nbytes * 65535 / 12
+    assert S.min() >= -half and S.max() <= half
+    assert abs(S.mean()) < 5 * math.sqrt(var / S.size), S.mean()
+    assert abs(S.var() / var - 1) < 0.03
+    pmf = ih_exact_pmf(nbytes)
+    top = 255 * nbytes
+    idx = np.clip(np.searchsorted(np.cumsum(pmf), np.linspace(0, 1, 31)[1:-1]), 0, top)
+    bins = np.concatenate([[-1], idx, [top]])
+    obs = np.histogram(S + half, bins=bins + 0.5)[0]
     exp = np.array([pmf[bins[k] + 1: bins[k + 1] + 1].sum() for k in range(len(bins) - 1)]) * S.size
     chi2 = ((obs - exp) ** 2 / exp).sum()
     dof = len(obs) - 1
     assert chi2 < dof + 6 * math.sqrt(2 * dof), chi2
+
+
+def check_jitter_distribution(lib, n=300000):
+    """Re-jitter offsets: Irwin-Hall(4) of bytes, centred."""
+    _check_ih(oracle.ih4_offsets(3, np.arange(n), 1, 12345, lib=lib).ravel().astype(np.int64), 4)
+
+
+def check_generator_offsets(lib, n=20000):
+    """Initial-configuration offsets: Irwin-Hall(12) of bytes, centred."""
+    _check_ih(oracle.ih12_offsets(0, np.arange(n), 2, 12345, lib=lib).ravel().astype(np.int64), 12)
 
 
 def check_jitter_wrap(lib):
@@ -375,9 +390,11 @@ def check_jitter_wrap(lib):
         oracle.jitter(s, 99, step, 0.05, lib=lib)
         for v in (s.x, s.y, s.z):
             assert np.all(v >= 0) and np.all(v < np.float32(L))
-    # particle 2 never wraps: displacement equals the sum of the offsets * c
-    S = sum(oracle.ih12_offsets(st, [2], 1, 99, lib=lib)[0, 0] for st in range(1, 40))
-    assert abs((s.x[2] - x0[2]) - S * (0.05 / 256)) < 1e-4
+    # particle 2 never wraps: displacement equals the sum of the offsets * c,
+    # c = sigma / sqrt(21845) (unit variance per offset)
+    assert abs(oracle.jitter_scale(0.05, lib=lib) - 0.05 / math.sqrt(21845)) < 1e-9
+    S = sum(oracle.ih4_offsets(st, [2], 1, 99, lib=lib)[0, 0] for st in range(1, 40))
+    assert abs((s.x[2] - x0[2]) - S * (0.05 / math.sqrt(21845))) < 1e-4
 
 
 # --------------------------------------------------------------------------
@@ -467,4 +484,4 @@ ALL = [check_pair_distance, check_periodic, check_cutoff_strict, check_p0_p1, ch
        check_isolated_cluster_probability, check_acceptance_ratio, check_two_a_one_t,
        check_two_a_one_t_probability, check_uniform_choice, check_exact_small_graph,
        check_exclusion, check_valence_stop, check_chain_transfer, check_errors, check_adj_overflow,
-       check_jitter_distribution, check_jitter_wrap]
+       check_jitter_distribution, check_generator_offsets, check_jitter_wrap]
