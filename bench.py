@@ -2,16 +2,27 @@
 
 Workload: step growth, N = 1,048,576 particles in L = 105.6 (jittered lattice,
 5% crosslinkers, r_c = 1.12, p = 0.005), generated on the device.  One step =
-the re-jitter (stand-in for MD between reaction steps, timed apart) followed
-by one reaction step.  ``value`` is reaction-step throughput in particles/s
-(N / reaction time per step), measured with HIP events around every reaction
-kernel on the system's stream; the whole-loop rate is reported beside it.
+the re-jitter of every particle (the stand-in for the MD between reaction
+steps, fused into the pair sweep) followed by the reaction step.  ``value``
+is whole-job throughput in particles/s: N x steps / wall time of the timed
+steps, replayed from captured HIP graphs with the state resident in HBM.
+
+``roofline`` covers the dominant kernel, the pair sweep: its algorithmic
+bytes per launch (positions read and written, type and state) over its mean
+duration, measured with HIP events around every sweep launch on the
+system's stream in a second, directly launched run of the same steps.
+``traffic`` is the sweep's HBM traffic per launch from the profiler
+counters recorded under profiles/ (null when the kernel source changed
+since).  ``cpu_baseline`` times the CPU oracle on one full step of the same
+workload.
 
 Prints ONE JSON line.  ``--gpus N`` with N > 1 exits: this build runs on one GPU.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -19,31 +30,50 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+SWEEP_B_PER_PARTICLE = 32.0   # x, y, z read (12) + type, state (8) + re-jittered x, y, z written (12)
+BOND_B = 24.0                 # per new bond: the pair, two states, two adjacency entries
+COUNTERS = os.path.join(ROOT, "profiles", "k_sweep_step_growth_1M_counters.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_1409_7498_amd", "csrc", "kernels.hip")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(cfg, max_steps=1):
-    """The CPU oracle on a bounded sample of the same workload (first step(s))."""
+def kernel_digest():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def recorded_traffic():
+    """HBM bytes per sweep launch from the committed counter summary, if it was
+    taken on the current kernel source."""
+    if not os.path.exists(COUNTERS):
+        return None
+    text = open(COUNTERS).read()
+    m_d = re.search(r"kernels\.hip digest:\s*([0-9a-f]+)", text)
+    m_t = re.search(r"traffic bytes per launch:\s*([0-9.eE+]+)", text)
+    if not (m_d and m_t) or m_d.group(1) != kernel_digest():
+        return None
+    return float(m_t.group(1))
+
+
+def cpu_baseline(cfg):
+    """The CPU oracle, as it is, on one full step (re-jitter + brute-force
+    reaction step) of the same workload."""
     import oracle
     from paper_1409_7498_amd import workload
     g = workload.generate(cfg.N, cfg.L, cfg.kind, cfg.seed)
     s = oracle.System(g["L"], g["x"], g["y"], g["z"], g["type"], g["state"], g["adj"])
     rule = oracle.Rule(**cfg.rule())
     t0 = time.perf_counter()
-    code, _, _ = oracle.run(s, rule, cfg.seed, 1, max_steps, cfg.sigma)
+    code, _, _ = oracle.run(s, rule, cfg.seed, 1, 1, cfg.sigma)
     dt = time.perf_counter() - t0
     assert code == 0
-    return {"value": cfg.N * max_steps / dt, "unit": "particles/s", "cores": oracle.num_threads(),
+    return {"value": cfg.N / dt, "unit": "particles/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": "%d reaction step(s) (jitter + brute-force O(N_A N) step) of the full "
-                      "%d-particle workload, %.1f s wall" % (max_steps, cfg.N, dt)}
-
-
-def sysm_sort_period(args):
-    return 64 if args.sort_period < 0 else args.sort_period
+            "sample": "one full step (re-jitter + O(N_A N) brute-force reaction step, Table I "
+                      "steps 1-9) of the %d-particle workload: %.1f s wall" % (cfg.N, dt)}
 
 
 def main():
@@ -83,14 +113,15 @@ def main():
                           log_cap=cfg.N * 2, stream=stream)
     if args.sort_period >= 0:
         sysm.set_sort_period(args.sort_period)
+    sort_period = 64 if args.sort_period < 0 else args.sort_period
     sysm.generate(cfg.kind, cfg.seed, workload.SIGMA_LATTICE)
     first = 1
     sysm.run(first, args.warmup, cfg.sigma)
     first += args.warmup
     torch.cuda.synchronize()
 
-    # timed loop: K steps, each the re-jitter fused with the reaction step,
-    # replayed from captured HIP graphs; events on the system's stream
+    # timed region: K steps replayed from captured HIP graphs (blocks of one
+    # spatial sort + sort_period steps), events on the system's stream
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(stream)
@@ -102,7 +133,7 @@ def main():
     K = args.steps
     st = sysm.stats()[-K:]
 
-    # kernel timing: the same steps launched directly, HIP events around the
+    # kernel timing: the next steps launched directly, HIP events around the
     # prep kernel, the sweep kernel and whole steps
     KT = min(K, 64)
     ph = sysm.run_timed(first, KT, cfg.sigma)
@@ -111,9 +142,10 @@ def main():
     n_t = sum(r["t_elig"] for r in st) / len(st)
     bonds = sum(r["bonds"] for r in st) / len(st)
     step_ms = loop_ms / K
-    sweep_bytes = 20.0 * cfg.N                     # type, state, x, y, z of every particle
-    step_bytes = 32.0 * cfg.N + 24.0 * bonds       # B_alg with the re-jitter fused (+12 B)
+    sweep_bytes = SWEEP_B_PER_PARTICLE * cfg.N
+    step_bytes = SWEEP_B_PER_PARTICLE * cfg.N + BOND_B * bonds
     achieved = sweep_bytes / (sweep_ms * 1e-3) / 1e9
+    traffic = recorded_traffic()
     out = {
         "metric": "reaction-step particles/s at 1M + % HBM roofline",
         "value": cfg.N / (step_ms * 1e-3),
@@ -128,8 +160,8 @@ def main():
         "dtype": "f32+u32",
         "data": "synthetic (jittered lattice, generated on device)",
         "config": {"workload": "step growth N=1,048,576 L=105.6 rc=1.12 p=0.005, 5% crosslinkers; "
-                               "a step = re-jitter (sigma=0.05) + reaction step",
-                   "steps_timed": K, "sort_period": sysm_sort_period(args)},
+                               "a step = re-jitter (sigma=0.05, fused) + reaction step",
+                   "steps_timed": K, "sort_period": sort_period},
         "step_roofline_frac": step_bytes / (step_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
         "prep_ms_direct": prep_ms,
         "sweep_ms_direct": sweep_ms,
@@ -137,13 +169,13 @@ def main():
         "bonds_per_step": bonds,
         "t_elig_per_step": n_t,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_sweep", "bytes_per_launch": sweep_bytes},
         "cpu_baseline": None,
     }
     sysm.close()
     if not args.no_cpu:
-        log("timing the CPU oracle on a bounded sample ...")
+        log("timing the CPU oracle on one full step of the workload ...")
         out["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(out), flush=True)
 

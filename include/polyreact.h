@@ -132,17 +132,21 @@ int pr_sys_generate(pr_sys* s, int32_t kind, uint64_t gen_seed, double sigma0);
 
 /* Runs reaction steps first_step .. first_step + n_steps - 1.  Each step
  * first moves every particle by the re-jitter (when sigma > 0) -- the
- * stand-in for the MD integration between reaction steps -- and then reacts.
+ * stand-in for the MD integration between reaction steps: per dimension an
+ * Irwin-Hall(4) offset (the four bytes of one Philox4x32-10 word of the block
+ * (step, id, 0, 1), summed, minus 510) times fl32(sigma / sqrt(21845)), then
+ * a single periodic wrap -- and then reacts.
  * Bonds are appended to the device bond log as (step, id_A, id_T) rows and
  * counters to the per-step counter log.  Asynchronous on the handle's stream;
  * errors found on the device are reported by the next synchronising call. */
 int pr_sys_run(pr_sys* s, uint32_t first_step, uint32_t n_steps, double sigma);
 
 /* Phase timing: like pr_sys_run, but every step is launched directly (no
- * graph) and the call synchronises; ms[0..2] receive the summed GPU time of
- * the prep kernel (re-jitter fused with the binning of the A particles), of
- * whole steps, and of the pair-sweep kernel alone, measured with HIP events
- * on the handle's stream. */
+ * graph) and the call synchronises; ms[0..2] receive the summed GPU time from
+ * the start of each step to the start of its pair sweep (the binning of the
+ * A particles), of whole steps, and of the pair-sweep kernels alone (their
+ * own start and end, stamped by hipExtLaunchKernel), measured with HIP
+ * events on the handle's stream. */
 int pr_sys_run_timed(pr_sys* s, uint32_t first_step, uint32_t n_steps, double sigma, float* ms);
 
 /* Copies the current configuration out in particle-id order (host or device

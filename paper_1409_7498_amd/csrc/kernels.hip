@@ -24,6 +24,7 @@
 // per pair keyed by (step, id_A, id_T), integer threshold on word 0.  Every
 // selection is a minimum over 64-bit keys, so no result depends on thread or
 // atomic order, nor on the storage order of the particles.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "common.hpp"
@@ -1240,16 +1241,24 @@ hipError_t launch_generate(const Dev& d, int kind, unsigned long long gseed, flo
 }
 
 // Step k of a block: prep (with the closing of step k - 1), sweep, resolve.
+// ev_sweep0/1 (timed runs): the sweep is launched with hipExtLaunchKernel,
+// which stamps the two events at the kernel's own start and end.
 hipError_t launch_step(const Dev& d, int k, hipStream_t s, hipEvent_t ev_sweep0,
                        hipEvent_t ev_sweep1) {
   const int prep_blocks = d.nwg_prep + (k > 0 ? d.ngroups : 0);
   k_prep<<<prep_blocks, kThreads, 0, s>>>(d, k);
-  if (ev_sweep0) (void)hipEventRecord(ev_sweep0, s);
-  if (d.sorted)
-    k_sweep<true><<<d.nwg_sweep, kThreads, 0, s>>>(d, k);
-  else
-    k_sweep<false><<<d.nwg_sweep, kThreads, 0, s>>>(d, k);
-  if (ev_sweep1) (void)hipEventRecord(ev_sweep1, s);
+  const dim3 g(d.nwg_sweep), b(kThreads);
+  if (d.sorted) {
+    if (ev_sweep0)
+      hipExtLaunchKernelGGL(k_sweep<true>, g, b, 0, s, ev_sweep0, ev_sweep1, 0, d, k);
+    else
+      k_sweep<true><<<g, b, 0, s>>>(d, k);
+  } else {
+    if (ev_sweep0)
+      hipExtLaunchKernelGGL(k_sweep<false>, g, b, 0, s, ev_sweep0, ev_sweep1, 0, d, k);
+    else
+      k_sweep<false><<<g, b, 0, s>>>(d, k);
+  }
   if (d.sorted)
     k_resolve<true><<<d.nwg_sweep, kThreads, 0, s>>>(d, k);
   else
