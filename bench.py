@@ -9,8 +9,9 @@ steps, replayed from captured HIP graphs with the state resident in HBM.
 
 ``roofline`` covers the dominant kernel, the pair sweep: its algorithmic
 bytes per launch (positions read and written, type and state) over its mean
-duration, measured with HIP events around every sweep launch on the
-system's stream in a second, directly launched run of the same steps.
+duration, measured with events stamped at each sweep's own start and end
+(hipExtLaunchKernel) on the system's stream, in a second, directly launched
+run of the next steps.
 ``traffic`` is the sweep's HBM traffic per launch from the profiler
 counters recorded under profiles/ (null when the kernel source changed
 since).  ``cpu_baseline`` times the CPU oracle on one full step of the same
@@ -76,6 +77,66 @@ def cpu_baseline(cfg):
                       "steps 1-9) of the %d-particle workload: %.1f s wall" % (cfg.N, dt)}
 
 
+def bench_batch(args):
+    """Batched ensemble (256 replicas of uneven size, 500 steps): replicas/s of
+    the batched launch against the plain per-replica launch loop, at identical
+    results (bond-log and state digests compared).  Each timed region is the
+    whole run of a freshly generated ensemble (graph capture included)."""
+    import numpy as np
+    import torch
+    from paper_1409_7498_amd import binding, workload
+    reps = workload.replica_configs()
+    steps = args.batch_steps
+    descs = [dict(n=c.N, L=c.L, B=c.B, rule=c.rule(), seed=c.seed, kind=c.kind,
+                  gen_seed=c.seed ^ 0x5A5A, sigma0=workload.SIGMA_LATTICE, log_cap=2 * c.N)
+             for c in reps]
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+
+    def digest(bt):
+        h = hashlib.sha256()
+        for r in range(len(descs)):
+            h.update(bt.bonds(r).tobytes())
+            h.update(bt.read(r)["state"].tobytes())
+        return h.hexdigest()[:16]
+
+    out = {}
+    for mode in ("batched", "loop"):
+        bt = binding.Batch(descs, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        (bt.run if mode == "batched" else bt.run_loop)(1, steps, workload.SIGMA_JITTER)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[mode] = (dt, digest(bt))
+        log("%s: %.3f s" % (mode, dt))
+        bt.close()
+    assert out["batched"][1] == out["loop"][1], "batched and loop results differ"
+    n_tot = sum(c.N for c in reps)
+    res = {
+        "metric": "replicas/s (batched ensemble: 256 uneven replicas)",
+        "value": len(reps) / out["batched"][0],
+        "unit": "replicas/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": 0,
+        "ms_per_step": out["batched"][0] * 1e3 / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+u32",
+        "data": "synthetic (jittered lattices, generated on device)",
+        "config": {"workload": "256 replicas, N log-uniform in [2000, 65536] (total %d), "
+                               "alternating step/chain growth, p in [0.001, 0.02], %d steps each"
+                               % (n_tot, steps)},
+        "loop_replicas_per_s": len(reps) / out["loop"][0],
+        "speedup_vs_loop": out["loop"][0] / out["batched"][0],
+        "particle_steps_per_s": n_tot * steps / out["batched"][0],
+        "results_digest": out["batched"][1],
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +145,7 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--sort-period", type=int, default=-1)
+    ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--probe-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates the HBM "
                          "byte counters of the profiler) and exit")
@@ -106,6 +168,8 @@ def main():
         return
     from paper_1409_7498_amd import binding, workload
 
+    if args.config == "c4":
+        return bench_batch(args)
     cfg = workload.CONFIGS[args.config]
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()

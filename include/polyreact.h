@@ -175,6 +175,54 @@ int pr_sys_set_sort_period(pr_sys* s, int32_t sort_period);
  * on = 0: every kernel is launched directly.  Results are identical. */
 int pr_sys_set_graphs(pr_sys* s, int32_t on);
 
+
+/* ------------------------------------------------------------------------ */
+/* Batched ensemble: many independent replicas (uneven sizes, step or chain  */
+/* growth, each with its own rule, seed and rate) stepped in lockstep.  Each */
+/* kernel launch covers every replica (a map spreads one grid over them) and */
+/* blocks of steps -- one spatial sort and then sort_period steps -- replay  */
+/* from one captured HIP graph.  Every replica's bonds, states, positions    */
+/* and counters equal those of a pr_sys run of that replica alone (the same  */
+/* arithmetic contract; results never depend on launch grouping).            */
+/* ------------------------------------------------------------------------ */
+typedef struct pr_replica_desc {
+  int32_t n;          /* particles (>= 1) */
+  float L;            /* periodic cube [0, L)^3 */
+  int32_t B;          /* adjacency width */
+  pr_rule rule;       /* reaction rule */
+  uint64_t seed;      /* draw seed of the reaction steps and the re-jitter */
+  int32_t gen_kind;   /* synthetic start: 0 step growth, 1 chain growth (as pr_sys_generate) */
+  uint64_t gen_seed;  /* generator seed */
+  double gen_sigma0;  /* lattice displacement of the generator */
+  int64_t log_cap;    /* bond-log capacity in bonds (0 = n) */
+} pr_replica_desc;
+
+typedef struct pr_batch pr_batch;
+
+/* Creates n_rep replicas (each validated like pr_sys_create) and generates
+ * their configurations on the device.  The handle owns all device memory;
+ * stream (may be NULL) is used by every later call.  Synchronises. */
+int pr_batch_create(pr_batch** out, const pr_replica_desc* reps, int32_t n_rep, void* stream);
+void pr_batch_destroy(pr_batch* b);
+
+/* Runs steps first_step .. first_step + n_steps - 1 of every replica (each
+ * step: re-jitter with sigma, then the reaction step), all replicas in the
+ * same launches, blocks of sort_period (64) steps replayed from one graph.
+ * Asynchronous on the handle's stream. */
+int pr_batch_run(pr_batch* b, uint32_t first_step, uint32_t n_steps, double sigma);
+
+/* The same steps as a plain per-replica launch loop: replica after replica,
+ * every kernel launched directly from the host (no graph, no batching).
+ * The reference point for the batched run; results are identical. */
+int pr_batch_run_loop(pr_batch* b, uint32_t first_step, uint32_t n_steps, double sigma);
+
+/* Per-replica results, as pr_sys_bonds, pr_sys_read and pr_sys_stats
+ * (rep in [0, n_rep), else PR_EINVAL).  Synchronise. */
+int pr_batch_bonds(pr_batch* b, int32_t rep, int32_t* out, int64_t cap, int64_t* n);
+int pr_batch_read(pr_batch* b, int32_t rep, float* x, float* y, float* z, int32_t* state,
+                  int32_t* adj, int32_t on_device);
+int pr_batch_stats(pr_batch* b, int32_t rep, pr_stats* out, int64_t cap, int64_t* n);
+
 #ifdef __cplusplus
 }
 #endif

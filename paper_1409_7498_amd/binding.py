@@ -38,6 +38,12 @@ class Rule(C.Structure):
         return cls(**{k: v[k] for k, _ in cls._fields_})
 
 
+class ReplicaDesc(C.Structure):
+    _fields_ = [("n", C.c_int32), ("L", C.c_float), ("B", C.c_int32), ("rule", Rule),
+                ("seed", C.c_uint64), ("gen_kind", C.c_int32), ("gen_seed", C.c_uint64),
+                ("gen_sigma0", C.c_double), ("log_cap", C.c_int64)]
+
+
 class Stats(C.Structure):
     _fields_ = [(f, C.c_int64) for f in STATS_FIELDS]
 
@@ -71,6 +77,13 @@ def _load():
         "pr_sys_stats": ([vp, P(Stats), i64, P(i64)], C.c_int),
         "pr_sys_set_sort_period": ([vp, i32], C.c_int),
         "pr_sys_set_graphs": ([vp, i32], C.c_int),
+        "pr_batch_create": ([P(vp), P(ReplicaDesc), i32, vp], C.c_int),
+        "pr_batch_destroy": ([vp], None),
+        "pr_batch_run": ([vp, u32, u32, f64], C.c_int),
+        "pr_batch_run_loop": ([vp, u32, u32, f64], C.c_int),
+        "pr_batch_bonds": ([vp, i32, vp, i64, P(i64)], C.c_int),
+        "pr_batch_read": ([vp, i32, vp, vp, vp, vp, vp, i32], C.c_int),
+        "pr_batch_stats": ([vp, i32, P(Stats), i64, P(i64)], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -86,7 +99,9 @@ def exported_symbols():
     return [n for n in ("pr_last_error", "pr_version", "pr_react_step", "pr_sys_create",
                         "pr_sys_destroy", "pr_sys_load", "pr_sys_generate", "pr_sys_run",
                         "pr_sys_run_timed", "pr_sys_read", "pr_sys_bonds", "pr_sys_stats",
-                        "pr_sys_set_sort_period", "pr_sys_set_graphs")]
+                        "pr_sys_set_sort_period", "pr_sys_set_graphs", "pr_batch_create",
+                        "pr_batch_destroy", "pr_batch_run", "pr_batch_run_loop", "pr_batch_bonds",
+                        "pr_batch_read", "pr_batch_stats")]
 
 
 def _check(code):
@@ -202,4 +217,64 @@ class System:
         _check(lib.pr_sys_stats(self._h, None, 0, C.byref(n)))
         arr = (Stats * max(n.value, 1))()
         _check(lib.pr_sys_stats(self._h, arr, n.value, C.byref(n)))
+        return [arr[k].as_dict() for k in range(n.value)]
+
+
+class Batch:
+    """Batched ensemble of independent replicas (pr_batch_* entry points).
+
+    ``reps``: list of dicts with n, L, B, rule (dict or Rule), seed, kind
+    ('step' or 'chain', the synthetic start), gen_seed, sigma0 and log_cap."""
+
+    def __init__(self, reps, stream=None):
+        arr = (ReplicaDesc * len(reps))()
+        for k, r in enumerate(reps):
+            rule = r["rule"] if isinstance(r["rule"], Rule) else Rule.make(r["rule"])
+            arr[k] = ReplicaDesc(int(r["n"]), float(np.float32(r["L"])), int(r["B"]), rule,
+                                 int(r["seed"]), 0 if r["kind"] == "step" else 1,
+                                 int(r["gen_seed"]), float(r.get("sigma0", 0.1)),
+                                 int(r.get("log_cap", 0)))
+        self.reps = [dict(r) for r in reps]
+        self._h = C.c_void_p()
+        _check(lib.pr_batch_create(C.byref(self._h), arr, len(reps), _stream(stream)))
+
+    def close(self):
+        if self._h:
+            lib.pr_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, first_step, n_steps, sigma):
+        _check(lib.pr_batch_run(self._h, int(first_step), int(n_steps), float(sigma)))
+
+    def run_loop(self, first_step, n_steps, sigma):
+        _check(lib.pr_batch_run_loop(self._h, int(first_step), int(n_steps), float(sigma)))
+
+    def read(self, rep):
+        n, B = int(self.reps[rep]["n"]), int(self.reps[rep]["B"])
+        out = dict(x=np.empty(n, np.float32), y=np.empty(n, np.float32), z=np.empty(n, np.float32),
+                   state=np.empty(n, np.int32), adj=np.empty((n, B), np.int32))
+        _check(lib.pr_batch_read(self._h, int(rep), *[out[k].ctypes.data_as(C.c_void_p)
+                                                      for k in ("x", "y", "z", "state", "adj")], 0))
+        return out
+
+    def bonds(self, rep):
+        n = C.c_int64(0)
+        lib.pr_batch_bonds(self._h, int(rep), None, 0, C.byref(n))
+        total = n.value
+        out = np.empty((max(total, 1), 3), np.int32)
+        _check(lib.pr_batch_bonds(self._h, int(rep), out.ctypes.data_as(C.c_void_p), total,
+                                  C.byref(n)))
+        return out[:total]
+
+    def stats(self, rep):
+        n = C.c_int64(0)
+        _check(lib.pr_batch_stats(self._h, int(rep), None, 0, C.byref(n)))
+        arr = (Stats * max(n.value, 1))()
+        _check(lib.pr_batch_stats(self._h, int(rep), arr, n.value, C.byref(n)))
         return [arr[k].as_dict() for k in range(n.value)]

@@ -730,3 +730,237 @@ int pr_sys_set_graphs(pr_sys* s, int32_t on) {
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// Batched ensembles
+// ===========================================================================
+namespace pr {
+hipError_t launch_ctl_b(const BatchLaunch& b, int op, uint32_t arg, hipStream_t s);
+hipError_t launch_step_b(const BatchLaunch& b, int k, hipStream_t s);
+hipError_t launch_block_end_b(const BatchLaunch& b, int K, hipStream_t s);
+hipError_t launch_sort_b(const BatchLaunch& b, hipStream_t s);
+}  // namespace pr
+
+struct pr_batch {
+  hipStream_t stream = nullptr;
+  hipStream_t cap = nullptr;
+  std::vector<pr_sys*> sys;
+  Arena arena;
+  BatchLaunch bl{};
+  Dev* ds = nullptr;              // device copies of the replicas' Devs
+  std::vector<Dev> hds;           // host staging of the same
+  hipEvent_t copied = nullptr;    // the last upload of hds has completed
+  int32_t sort_period = 64;
+  hipGraphExec_t gexec = nullptr;
+  int32_t g_steps = 0;
+  ~pr_batch() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (copied) (void)hipEventDestroy(copied);
+    if (cap) (void)hipStreamDestroy(cap);
+    for (pr_sys* s : sys) pr_sys_destroy(s);
+  }
+};
+
+namespace {
+
+int check_batch(pr_batch* b, int32_t rep) {
+  if (!b) return fail(PR_EINVAL, "NULL batch handle");
+  if (rep < 0 || rep >= (int32_t)b->sys.size())
+    return fail(PR_EINVAL, "replica %d outside [0, %zu)", rep, b->sys.size());
+  return PR_OK;
+}
+
+// Maps of grid blocks to (replica, local block, blocks of the replica) for
+// the sorted-storage kernels of the batch.
+int build_maps(pr_batch* b) {
+  std::vector<int4> prep0, prepk, sweep, close, part;
+  for (int r = 0; r < (int)b->sys.size(); ++r) {
+    const Dev& d = b->sys[r]->d;
+    for (int q = 0; q < d.nwg_prep; ++q) prep0.push_back(make_int4(r, q, d.nwg_prep, 0));
+    for (int q = 0; q < d.ngroups + d.nwg_prep; ++q)
+      prepk.push_back(make_int4(r, q, d.ngroups + d.nwg_prep, 0));
+    for (int q = 0; q < d.nbricks; ++q) sweep.push_back(make_int4(r, q, d.nbricks, 0));
+    for (int q = 0; q < d.ngroups; ++q) close.push_back(make_int4(r, q, d.ngroups, 0));
+    const int np = (d.n + kThreads - 1) / kThreads;
+    for (int q = 0; q < np; ++q) part.push_back(make_int4(r, q, np, 0));
+  }
+  int4 *m0, *mk, *ms, *mc, *mp;
+  int e;
+  if ((e = b->arena.alloc(&m0, prep0.size())) || (e = b->arena.alloc(&mk, prepk.size())) ||
+      (e = b->arena.alloc(&ms, sweep.size())) || (e = b->arena.alloc(&mc, close.size())) ||
+      (e = b->arena.alloc(&mp, part.size())))
+    return e;
+  HIP_TRY(hipMemcpy(m0, prep0.data(), prep0.size() * sizeof(int4), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(mk, prepk.data(), prepk.size() * sizeof(int4), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(ms, sweep.data(), sweep.size() * sizeof(int4), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(mc, close.data(), close.size() * sizeof(int4), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(mp, part.data(), part.size() * sizeof(int4), hipMemcpyHostToDevice));
+  b->bl.prep0 = m0;
+  b->bl.prepk = mk;
+  b->bl.sweep = ms;
+  b->bl.close = mc;
+  b->bl.part = mp;
+  b->bl.n_prep0 = (int)prep0.size();
+  b->bl.n_prepk = (int)prepk.size();
+  b->bl.n_sweep = (int)sweep.size();
+  b->bl.n_close = (int)close.size();
+  b->bl.n_part = (int)part.size();
+  return PR_OK;
+}
+
+// One block of K steps for every replica: a sort, the steps, the block end.
+int run_block_b(pr_batch* b, hipStream_t st, int32_t K) {
+  HIP_TRY(launch_sort_b(b->bl, st));
+  for (int32_t k = 0; k < K; ++k) HIP_TRY(launch_step_b(b->bl, k, st));
+  HIP_TRY(launch_block_end_b(b->bl, K, st));
+  return PR_OK;
+}
+
+int capture_block_b(pr_batch* b, int32_t K) {
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  b->gexec = nullptr;
+  hipGraph_t g = nullptr;
+  HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+  const int e = run_block_b(b, b->cap, K);
+  const hipError_t ce = hipStreamEndCapture(b->cap, &g);
+  if (e) {
+    if (g) (void)hipGraphDestroy(g);
+    return e;
+  }
+  if (ce != hipSuccess) return fail(PR_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(ce));
+  const hipError_t ie = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ie != hipSuccess) {
+    b->gexec = nullptr;
+    return fail(PR_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+  }
+  b->g_steps = K;
+  return PR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pr_batch_create(pr_batch** out, const pr_replica_desc* reps, int32_t n_rep, void* stream) {
+  if (!out) return fail(PR_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n_rep < 1 || !reps) return fail(PR_EINVAL, "n_rep=%d", n_rep);
+  pr_batch* b = new pr_batch();
+  b->stream = (hipStream_t)stream;
+  if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->copied, hipEventDisableTiming) != hipSuccess) {
+    delete b;
+    return fail(PR_EHIP, "hipStreamCreate/hipEventCreate failed");
+  }
+  int e = PR_OK;
+  for (int32_t r = 0; r < n_rep && !e; ++r) {
+    const pr_replica_desc& q = reps[r];
+    pr_sys* s = nullptr;
+    e = pr_sys_create(&s, q.n, q.L, q.B, &q.rule, q.seed, q.log_cap, stream);
+    if (!e) {
+      b->sys.push_back(s);
+      e = pr_sys_generate(s, q.gen_kind, q.gen_seed, q.gen_sigma0);
+    }
+    if (e) {
+      const std::string msg = g_err;
+      fail(e, "replica %d: %s", r, msg.c_str());
+    }
+  }
+  if (!e) e = build_maps(b);
+  if (!e) e = b->arena.alloc(&b->ds, (size_t)n_rep);
+  if (e) {
+    delete b;
+    return e;
+  }
+  b->bl.ds = b->ds;
+  b->bl.nrep = n_rep;
+  b->hds.resize((size_t)n_rep);
+  *out = b;
+  return PR_OK;
+}
+
+void pr_batch_destroy(pr_batch* b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->stream);
+  delete b;
+}
+
+int pr_batch_run(pr_batch* b, uint32_t first_step, uint32_t n_steps, double sigma) {
+  int e = check_batch(b, 0);
+  if (e) return e;
+  for (pr_sys* s : b->sys) {
+    if ((e = check_sys(s, true))) return e;
+    if (!(sigma >= 0.0) || sigma * 6.0 >= (double)s->d.L * 0.5)
+      return fail(PR_EINVAL, "sigma=%g", sigma);
+  }
+  if (n_steps == 0) return PR_OK;
+  hipStream_t st = b->stream;
+  HIP_TRY(hipEventSynchronize(b->copied));  // the staging copy of a previous run is done
+  // the replicas' Devs as the batch's blocks leave them: storage sorted at
+  // the start of every block, logs sized for the whole run
+  for (size_t r = 0; r < b->sys.size(); ++r) {
+    pr_sys* s = b->sys[r];
+    if ((e = grow_part(s, s->steps_since_load + n_steps))) return e;
+    s->d.jit_c = (float)(sigma / std::sqrt(21845.0));
+    s->d.sorted = 1;
+    s->d.nwg_sweep = s->d.nbricks;
+    b->hds[r] = s->d;
+  }
+  HIP_TRY(hipMemcpyAsync(b->ds, b->hds.data(), sizeof(Dev) * b->hds.size(),
+                         hipMemcpyHostToDevice, st));
+  HIP_TRY(hipEventRecord(b->copied, st));
+  HIP_TRY(launch_ctl_b(b->bl, 0, first_step, st));
+  const int32_t K = b->sort_period;
+  uint32_t left = n_steps;
+  while (left > 0) {
+    if (left >= (uint32_t)K) {
+      if (!b->gexec || b->g_steps != K)
+        if ((e = capture_block_b(b, K))) return e;
+      HIP_TRY(hipGraphLaunch(b->gexec, st));
+      left -= (uint32_t)K;
+    } else {
+      if ((e = run_block_b(b, st, (int32_t)left))) return e;
+      left = 0;
+    }
+  }
+  // host-side state of every replica after the run
+  for (pr_sys* s : b->sys) {
+    drop_graph(s);
+    s->steps_since_sort = n_steps % (uint32_t)K == 0 ? K : (int32_t)(n_steps % (uint32_t)K);
+    s->steps_since_load += n_steps;
+  }
+  return PR_OK;
+}
+
+int pr_batch_run_loop(pr_batch* b, uint32_t first_step, uint32_t n_steps, double sigma) {
+  int e = check_batch(b, 0);
+  if (e) return e;
+  for (pr_sys* s : b->sys) {
+    const int32_t g = s->use_graphs;
+    s->use_graphs = 0;
+    drop_graph(s);
+    e = pr_sys_run(s, first_step, n_steps, sigma);
+    s->use_graphs = g;
+    if (e) return e;
+  }
+  return PR_OK;
+}
+
+int pr_batch_bonds(pr_batch* b, int32_t rep, int32_t* out, int64_t cap, int64_t* n) {
+  int e = check_batch(b, rep);
+  return e ? e : pr_sys_bonds(b->sys[rep], out, cap, n);
+}
+
+int pr_batch_read(pr_batch* b, int32_t rep, float* x, float* y, float* z, int32_t* state,
+                  int32_t* adj, int32_t on_device) {
+  int e = check_batch(b, rep);
+  return e ? e : pr_sys_read(b->sys[rep], x, y, z, state, adj, on_device);
+}
+
+int pr_batch_stats(pr_batch* b, int32_t rep, pr_stats* out, int64_t cap, int64_t* n) {
+  int e = check_batch(b, rep);
+  return e ? e : pr_sys_stats(b->sys[rep], out, cap, n);
+}
+
+}  // extern "C"

@@ -113,4 +113,14 @@ struct Dev {
   RuleD rule;
 };
 
+// A batch of independent systems stepped in lockstep: their Devs in device
+// memory and, per kernel, the map of grid blocks to (replica, local block,
+// blocks of that replica).
+struct BatchLaunch {
+  const Dev* ds;
+  int nrep;
+  const int4 *prep0, *prepk, *sweep, *close, *part;  // prep at k == 0 / k > 0, sweep and
+  int n_prep0, n_prepk, n_sweep, n_close, n_part;     // resolve, closing, particle blocks
+};
+
 }  // namespace pr

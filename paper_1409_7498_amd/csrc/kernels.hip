@@ -369,13 +369,13 @@ __device__ void close_group(const Dev& d, uint32_t par, uint32_t step, uint32_t 
 // k_prep: [closing groups of step k - 1 when k > 0][binning of the A-role
 // particles, kThreads * kPrepRoles slots per block].
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_prep(Dev d, int k) {
+__device__ __forceinline__ void prep_body(const Dev& d, int k, int blk) {
   __shared__ int s_na;
   __shared__ uint32_t s_wave[kThreads / 64 + 1];
   const StepInfo si = step_info(d.ctl, k);
   const Arr a = pick_set(d, d.ctl->set & 1u);
   const int ncl = k > 0 ? d.ngroups : 0;
-  int b = blockIdx.x;
+  int b = blk;
   if (b < ncl) {  // closing groups of the previous step of the block
     close_group(d, si.par ^ 1u, si.step - 1u, d.ctl->stats_n0 + (uint32_t)k - 1u, b, s_wave);
     return;
@@ -464,19 +464,17 @@ __global__ __launch_bounds__(kThreads) void k_prep(Dev d, int k) {
 }
 
 // Closes step k of the block (one workgroup per closing group).
-__global__ __launch_bounds__(kThreads) void k_close(Dev d, int k) {
+__device__ __forceinline__ void close_body(const Dev& d, int k, int g) {
   __shared__ uint32_t s_wave[kThreads / 64 + 1];
   const StepInfo si = step_info(d.ctl, k);
-  close_group(d, si.par, si.step, d.ctl->stats_n0 + (uint32_t)k, blockIdx.x, s_wave);
+  close_group(d, si.par, si.step, d.ctl->stats_n0 + (uint32_t)k, g, s_wave);
 }
 
 // Advances the block origin by K steps (after the block's last step closed).
-__global__ void k_advance(Ctl* c, int K) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    c->step0 += (uint32_t)K;
-    c->par0 = (c->par0 + (uint32_t)K) & 1u;
-    c->stats_n0 += (uint32_t)K;
-  }
+__device__ __forceinline__ void advance_ctl(Ctl* c, int K) {
+  c->step0 += (uint32_t)K;
+  c->par0 = (c->par0 + (uint32_t)K) & 1u;
+  c->stats_n0 += (uint32_t)K;
 }
 
 // ---------------------------------------------------------------------------
@@ -677,7 +675,7 @@ __device__ __forceinline__ uint32_t lanes_below(unsigned long long b) {
 }
 
 template <bool kBrick>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) void k_sweep(Dev d, int k) {
+__device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) {
   constexpr int kPer = kBrick ? kTPass / kThreads : 1;
   constexpr int kTP = kPer * kThreads;
   constexpr uint32_t kNoRec = 0xFFFFu;
@@ -693,7 +691,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
   __shared__ uint32_t s_wave[kThreads / 64 + 1];
   __shared__ int s_cnt[4];
   __shared__ int s_qn, s_ndef, s_ne, s_dead;
-  const int tid = threadIdx.x, w = blockIdx.x;
+  const int tid = threadIdx.x;
   if (tid < 4) s_cnt[tid] = 0;
   if (tid == 0) {
     s_qn = 0;
@@ -717,7 +715,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
   // the first particle of the first pass, issued before the staging round trips
   Part cur = load_part(a, X, Y, Z, s0 + tid, s1);
   // clear the bucket counts of the next step's parity
-  for (int q = w * kThreads + tid; q < d.ncell; q += gridDim.x * kThreads)
+  for (int q = w * kThreads + tid; q < d.ncell; q += nwg * kThreads)
     pick(d.cnt, par ^ 1u)[q] = 0u;
   int bx = 0, ex = 0, by = 0, ey = 0, bz = 0, ez = 0;
   bool staged = false, nowrap = false;
@@ -986,11 +984,11 @@ __device__ __forceinline__ void make_bond(const Dev& d, const Arr& a, uint32_t p
 }
 
 template <bool kBrick>
-__global__ __launch_bounds__(kThreads) void k_resolve(Dev d, int k) {
+__device__ __forceinline__ void resolve_body(const Dev& d, int k, int w) {
   __shared__ int s_nw, s_lost, s_prop, s_mode;
   __shared__ unsigned long long s_key[kRetCap];
   __shared__ int32_t s_sj[kRetCap];
-  const int tid = threadIdx.x, w = blockIdx.x;
+  const int tid = threadIdx.x;
   const Ctl* c = d.ctl;
   const StepInfo si = step_info(c, k);
   const uint32_t par = si.par, step = si.step;
@@ -1133,8 +1131,7 @@ __device__ __forceinline__ int brick_of(const Dev& d, float x, float y, float z)
 
 // Ranks within bricks; lanes of a wavefront that share a brick take one
 // atomic together (storage is nearly sorted, so a wave spans few bricks).
-__global__ __launch_bounds__(kThreads) void k_sort_count(Dev d) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void sort_count_body(const Dev& d, int k) {
   const Arr a = pick_set(d, d.ctl->set & 1u);
   const uint32_t par = d.ctl->par0;
   const bool active = k < d.n;
@@ -1156,7 +1153,7 @@ __global__ __launch_bounds__(kThreads) void k_sort_count(Dev d) {
   }
 }
 
-__global__ __launch_bounds__(kFinThreads) void k_sort_scan(Dev d) {
+__device__ __forceinline__ void sort_scan_body(const Dev& d) {
   __shared__ uint32_t s_wave[kFinThreads / 64 + 1];
   uint32_t carry = 0;
   for (int base = 0; base < d.nbricks; base += blockDim.x) {
@@ -1173,8 +1170,7 @@ __global__ __launch_bounds__(kFinThreads) void k_sort_scan(Dev d) {
   if (threadIdx.x == 0) d.bstart[d.nbricks] = (int32_t)carry;
 }
 
-__global__ __launch_bounds__(kThreads) void k_sort_scatter(Dev d) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void sort_scatter_body(const Dev& d, int k) {
   if (k >= d.n) return;
   const uint32_t s = d.ctl->set & 1u, par = d.ctl->par0;
   const Arr a = pick_set(d, s), o = pick_set(d, s ^ 1u);
@@ -1193,8 +1189,92 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(Dev d) {
   for (int q = 0; q < d.B; ++q) o.adj[(size_t)ns * d.B + q] = a.adj[(size_t)k * d.B + q];
 }
 
+// ---------------------------------------------------------------------------
+// Entry points.  One system: the kernel argument is its Dev and the grid is
+// its own.  A batch of systems (independent replicas stepping in lockstep):
+// the Devs live in device memory and map[blockIdx.x] = (replica, local block,
+// blocks of that replica) spreads one grid over all of them.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_prep(Dev d, int k) { prep_body(d, k, blockIdx.x); }
+__global__ __launch_bounds__(kThreads) void k_close(Dev d, int k) { close_body(d, k, blockIdx.x); }
+__global__ void k_advance(Ctl* c, int K) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) advance_ctl(c, K);
+}
+template <bool kBrick>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) void k_sweep(Dev d, int k) {
+  sweep_body<kBrick>(d, k, blockIdx.x, gridDim.x);
+}
+template <bool kBrick>
+__global__ __launch_bounds__(kThreads) void k_resolve(Dev d, int k) {
+  resolve_body<kBrick>(d, k, blockIdx.x);
+}
+__global__ __launch_bounds__(kThreads) void k_sort_count(Dev d) {
+  sort_count_body(d, blockIdx.x * blockDim.x + threadIdx.x);
+}
+__global__ __launch_bounds__(kFinThreads) void k_sort_scan(Dev d) { sort_scan_body(d); }
+__global__ __launch_bounds__(kThreads) void k_sort_scatter(Dev d) {
+  sort_scatter_body(d, blockIdx.x * blockDim.x + threadIdx.x);
+}
 __global__ void k_sort_flip(Ctl* c) {
   if (threadIdx.x == 0 && blockIdx.x == 0) c->set ^= 1u;
+}
+
+// The block's map entry, made wavefront-uniform (scalar registers) so that
+// the replica's Dev is read with scalar loads.
+__device__ __forceinline__ int4 uniform_map(const int4* __restrict__ map) {
+  const int4 m = map[blockIdx.x];
+  return make_int4(__builtin_amdgcn_readfirstlane(m.x), __builtin_amdgcn_readfirstlane(m.y),
+                   __builtin_amdgcn_readfirstlane(m.z), 0);
+}
+
+__global__ __launch_bounds__(kThreads) void k_prep_b(const Dev* __restrict__ ds,
+                                                     const int4* __restrict__ map, int k) {
+  const int4 m = uniform_map(map);
+  const Dev& d = ds[m.x];
+  prep_body(d, k, m.y);
+}
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) void k_sweep_b(
+    const Dev* __restrict__ ds, const int4* __restrict__ map, int k) {
+  const int4 m = uniform_map(map);
+  const Dev& d = ds[m.x];
+  sweep_body<true>(d, k, m.y, m.z);
+}
+__global__ __launch_bounds__(kThreads) void k_resolve_b(const Dev* __restrict__ ds,
+                                                        const int4* __restrict__ map, int k) {
+  const int4 m = uniform_map(map);
+  const Dev& d = ds[m.x];
+  resolve_body<true>(d, k, m.y);
+}
+__global__ __launch_bounds__(kThreads) void k_close_b(const Dev* __restrict__ ds,
+                                                      const int4* __restrict__ map, int k) {
+  const int4 m = uniform_map(map);
+  const Dev& d = ds[m.x];
+  close_body(d, k, m.y);
+}
+// one thread per replica
+__global__ void k_ctl_b(const Dev* __restrict__ ds, int nrep, int op, uint32_t arg) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrep) return;
+  Ctl* c = ds[r].ctl;
+  if (op == 0) c->step0 = arg;               // start of a run
+  else if (op == 1) advance_ctl(c, (int)arg);  // end of a block of arg steps
+  else c->set ^= 1u;                         // after a sort
+}
+__global__ __launch_bounds__(kThreads) void k_sort_count_b(const Dev* __restrict__ ds,
+                                                           const int4* __restrict__ map) {
+  const int4 m = uniform_map(map);
+  const Dev& d = ds[m.x];
+  sort_count_body(d, m.y * kThreads + threadIdx.x);
+}
+__global__ __launch_bounds__(kFinThreads) void k_sort_scan_b(const Dev* __restrict__ ds) {
+  const Dev& d = ds[__builtin_amdgcn_readfirstlane((int)blockIdx.x)];
+  sort_scan_body(d);
+}
+__global__ __launch_bounds__(kThreads) void k_sort_scatter_b(const Dev* __restrict__ ds,
+                                                             const int4* __restrict__ map) {
+  const int4 m = uniform_map(map);
+  const Dev& d = ds[m.x];
+  sort_scatter_body(d, m.y * kThreads + threadIdx.x);
 }
 
 // Storage order -> particle-id order (positions of the current parity).
@@ -1285,6 +1365,36 @@ hipError_t launch_sort(const Dev& d, hipStream_t s) {
   k_sort_scatter<<<blocks_for(d.n, kThreads), kThreads, 0, s>>>(d);
   k_sort_flip<<<1, 64, 0, s>>>(d.ctl);
   return hipGetLastError();
+}
+
+// Batched launches (every replica in one grid per kernel).
+static inline int ctl_blocks(int nrep) { return (nrep + 63) / 64; }
+
+hipError_t launch_ctl_b(const BatchLaunch& b, int op, uint32_t arg, hipStream_t s) {
+  k_ctl_b<<<ctl_blocks(b.nrep), 64, 0, s>>>(b.ds, b.nrep, op, arg);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_b(const BatchLaunch& b, int k, hipStream_t s) {
+  if (k > 0)
+    k_prep_b<<<b.n_prepk, kThreads, 0, s>>>(b.ds, b.prepk, k);
+  else
+    k_prep_b<<<b.n_prep0, kThreads, 0, s>>>(b.ds, b.prep0, k);
+  k_sweep_b<<<b.n_sweep, kThreads, 0, s>>>(b.ds, b.sweep, k);
+  k_resolve_b<<<b.n_sweep, kThreads, 0, s>>>(b.ds, b.sweep, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_end_b(const BatchLaunch& b, int K, hipStream_t s) {
+  k_close_b<<<b.n_close, kThreads, 0, s>>>(b.ds, b.close, K - 1);
+  return launch_ctl_b(b, 1, (uint32_t)K, s);
+}
+
+hipError_t launch_sort_b(const BatchLaunch& b, hipStream_t s) {
+  k_sort_count_b<<<b.n_part, kThreads, 0, s>>>(b.ds, b.part);
+  k_sort_scan_b<<<b.nrep, kFinThreads, 0, s>>>(b.ds);
+  k_sort_scatter_b<<<b.n_part, kThreads, 0, s>>>(b.ds, b.part);
+  return launch_ctl_b(b, 2, 0u, s);
 }
 
 hipError_t launch_gather_out(const Dev& d, float* ox, float* oy, float* oz, int32_t* ost,
