@@ -137,6 +137,98 @@ def bench_batch(args):
     print(json.dumps(res), flush=True)
 
 
+def bench_serve(args):
+    """Served stream: requests arrive as a Poisson process (200/s), each a
+    replica of N log-uniform in [1000, 1,048,576] particles, step or chain
+    growth, 1000 steps; a request loop with continuous batching admits them by
+    HBM footprint.  Reports p50/p99 of completion minus arrival and replicas/s
+    (completed requests over the time from the first arrival to the last
+    completion), beside the plain per-replica launch loop on the first
+    requests of the same stream (same results, digest compared)."""
+    import threading
+    import numpy as np
+    import torch
+    from paper_1409_7498_amd import binding, workload
+    arrivals, cfgs = workload.request_stream(n_req=args.requests)
+    descs = [dict(n=c.N, L=c.L, B=c.B, rule=c.rule(), seed=c.seed, kind=c.kind,
+                  gen_seed=c.seed ^ 0x5A5A, sigma0=workload.SIGMA_LATTICE, log_cap=2 * c.N)
+             for c in cfgs]
+    steps = cfgs[0].steps
+    torch.cuda.set_device(0)
+    srv = binding.Server(int(args.budget_gb * (1 << 30)), args.slots)
+    tickets = [None] * len(descs)
+    t_start = time.perf_counter()
+
+    def feed():
+        for i, d in enumerate(descs):
+            wait = t_start + arrivals[i] - time.perf_counter()
+            if wait > 0:
+                time.sleep(wait)
+            tickets[i] = srv.submit(d, steps, workload.SIGMA_JITTER)
+
+    th = threading.Thread(target=feed)
+    th.start()
+    lat = []
+    last = 0.0
+    for i in range(len(descs)):
+        while tickets[i] is None:
+            time.sleep(0.0005)
+        st, code, l = srv.wait(tickets[i], 3600.0)
+        assert st == binding.Server.DONE, (i, st, code)
+        lat.append(l)
+        last = max(last, arrivals[i] + l)
+    th.join()
+    info = srv.info()
+    nb = min(args.baseline_requests, len(descs))
+    h_srv = hashlib.sha256()
+    for i in range(nb):
+        h_srv.update(srv.bonds(tickets[i]).tobytes())
+    srv.close()
+    # the plain per-replica launch loop on the first nb requests (back to back)
+    h_loop = hashlib.sha256()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(nb):
+        d = descs[i]
+        s = binding.System(d["n"], d["L"], d["B"], d["rule"], d["seed"], log_cap=d["log_cap"])
+        s.generate(d["kind"], d["gen_seed"], d["sigma0"])
+        s.set_graphs(False)
+        s.run(1, steps, workload.SIGMA_JITTER)
+        h_loop.update(s.bonds().tobytes())
+        s.close()
+    torch.cuda.synchronize()
+    t_loop = time.perf_counter() - t0
+    assert h_srv.hexdigest() == h_loop.hexdigest(), "served and loop results differ"
+    lat = np.array(lat)
+    n_part = float(sum(c.N for c in cfgs))
+    res = {
+        "metric": "served stream: replicas/s, p50/p99 completion latency",
+        "value": len(descs) / last,
+        "unit": "replicas/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": 0,
+        "ms_per_step": None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+u32",
+        "data": "synthetic (jittered lattices, generated on device per request)",
+        "config": {"workload": "%d requests, Poisson arrivals at 200/s, N log-uniform in "
+                               "[1000, 1048576] (mean %.0f), step/chain 50/50, p in [0.001, 0.02], "
+                               "%d steps each" % (len(descs), n_part / len(descs), steps),
+                   "hbm_budget_gb": args.budget_gb, "slots": args.slots},
+        "p50_latency_s": float(np.percentile(lat, 50)),
+        "p99_latency_s": float(np.percentile(lat, 99)),
+        "particle_steps_per_s": n_part * steps / last,
+        "gpu_busy_fraction": info["busy_s"] / last,
+        "rounds": info["rounds"],
+        "loop_replicas_per_s": nb / t_loop,
+        "loop_requests": nb,
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -146,6 +238,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--sort-period", type=int, default=-1)
     ap.add_argument("--batch-steps", type=int, default=500)
+    ap.add_argument("--requests", type=int, default=1000, help="c5: requests of the stream")
+    ap.add_argument("--budget-gb", type=float, default=64.0, help="c5: HBM admission budget")
+    ap.add_argument("--slots", type=int, default=64, help="c5: replicas resident at once")
+    ap.add_argument("--baseline-requests", type=int, default=100,
+                    help="c5: requests run through the plain per-replica loop")
     ap.add_argument("--probe-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates the HBM "
                          "byte counters of the profiler) and exit")
@@ -170,6 +267,8 @@ def main():
 
     if args.config == "c4":
         return bench_batch(args)
+    if args.config == "c5":
+        return bench_serve(args)
     cfg = workload.CONFIGS[args.config]
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()

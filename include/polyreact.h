@@ -223,6 +223,63 @@ int pr_batch_read(pr_batch* b, int32_t rep, float* x, float* y, float* z, int32_
                   int32_t* adj, int32_t on_device);
 int pr_batch_stats(pr_batch* b, int32_t rep, pr_stats* out, int64_t cap, int64_t* n);
 
+
+/* Device bytes a resident system of this description allocates for a run of
+ * n_steps steps (the admission measure of the server).  PR_EINVAL as
+ * pr_sys_create. */
+int pr_footprint(const pr_replica_desc* r, uint32_t n_steps, int64_t* bytes);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: a request loop with continuous batching.  Requests (a replica   */
+/* description, a number of steps and the re-jitter sigma) queue in arrival */
+/* order; a worker thread admits the head of the queue as soon as a slot and */
+/* its HBM footprint (pr_footprint) are free, keeps the admitted replicas    */
+/* resident, and advances all of them together, rounds of up to 64 steps in */
+/* the batched launches (each replica takes part in the steps it has left). */
+/* A finished replica's results move to host memory and its device memory  */
+/* is freed at once, so later requests are admitted while others still run.*/
+/* Each result equals the replica run alone (pr_sys_run).                    */
+/* ------------------------------------------------------------------------ */
+typedef struct pr_server pr_server;
+
+typedef struct pr_server_info {
+  int64_t budget, used;            /* HBM budget and bytes held by admitted replicas */
+  int64_t queued, active, done, failed;
+  int64_t rounds;                  /* batched rounds launched */
+  double busy_s;                   /* GPU time of those rounds (HIP events) */
+} pr_server_info;
+
+/* hbm_budget: bytes the admitted replicas may hold together; max_slots:
+ * replicas resident at once.  stream: NULL = the server creates its own.
+ * Starts the worker thread (on the calling thread's current device). */
+int pr_server_create(pr_server** out, int64_t hbm_budget, int32_t max_slots, void* stream);
+/* Stops admitting, lets the worker finish its current round, cancels what
+ * is queued, frees everything. */
+void pr_server_destroy(pr_server* s);
+
+/* Queues a request and returns its ticket.  PR_EINVAL on an invalid
+ * description; PR_EBUSY if its footprint exceeds the whole budget (it could
+ * never be admitted).  Thread-safe. */
+int pr_server_submit(pr_server* s, const pr_replica_desc* r, uint32_t n_steps, double sigma,
+                     uint64_t* ticket);
+
+/* Request status: 0 queued, 1 running, 2 done, 3 failed (*code: its error);
+ * latency_s: completion minus submission time (seconds, steady clock; valid
+ * when done).  timeout_s > 0 waits up to that long for completion, 0 does
+ * not wait.  PR_ENOTFOUND for an unknown or released ticket. */
+int pr_server_wait(pr_server* s, uint64_t ticket, double timeout_s, int32_t* status,
+                   int32_t* code, double* latency_s);
+
+/* Results of a finished request (host memory), as pr_sys_bonds, pr_sys_read
+ * (on_device = 0) and pr_sys_stats; PR_EBUSY while it is not done. */
+int pr_server_bonds(pr_server* s, uint64_t ticket, int32_t* out, int64_t cap, int64_t* n);
+int pr_server_read(pr_server* s, uint64_t ticket, float* x, float* y, float* z, int32_t* state,
+                   int32_t* adj);
+int pr_server_stats(pr_server* s, uint64_t ticket, pr_stats* out, int64_t cap, int64_t* n);
+/* Forgets a finished request (frees its host results). */
+int pr_server_release(pr_server* s, uint64_t ticket);
+int pr_server_info_get(pr_server* s, pr_server_info* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -44,6 +44,15 @@ class ReplicaDesc(C.Structure):
                 ("gen_sigma0", C.c_double), ("log_cap", C.c_int64)]
 
 
+class ServerInfo(C.Structure):
+    _fields_ = [("budget", C.c_int64), ("used", C.c_int64), ("queued", C.c_int64),
+                ("active", C.c_int64), ("done", C.c_int64), ("failed", C.c_int64),
+                ("rounds", C.c_int64), ("busy_s", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class Stats(C.Structure):
     _fields_ = [(f, C.c_int64) for f in STATS_FIELDS]
 
@@ -84,6 +93,16 @@ def _load():
         "pr_batch_bonds": ([vp, i32, vp, i64, P(i64)], C.c_int),
         "pr_batch_read": ([vp, i32, vp, vp, vp, vp, vp, i32], C.c_int),
         "pr_batch_stats": ([vp, i32, P(Stats), i64, P(i64)], C.c_int),
+        "pr_footprint": ([P(ReplicaDesc), u32, P(i64)], C.c_int),
+        "pr_server_create": ([P(vp), i64, i32, vp], C.c_int),
+        "pr_server_destroy": ([vp], None),
+        "pr_server_submit": ([vp, P(ReplicaDesc), u32, f64, P(u64)], C.c_int),
+        "pr_server_wait": ([vp, u64, f64, P(i32), P(i32), P(f64)], C.c_int),
+        "pr_server_bonds": ([vp, u64, vp, i64, P(i64)], C.c_int),
+        "pr_server_read": ([vp, u64, vp, vp, vp, vp, vp], C.c_int),
+        "pr_server_stats": ([vp, u64, P(Stats), i64, P(i64)], C.c_int),
+        "pr_server_release": ([vp, u64], C.c_int),
+        "pr_server_info_get": ([vp, P(ServerInfo)], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -101,7 +120,10 @@ def exported_symbols():
                         "pr_sys_run_timed", "pr_sys_read", "pr_sys_bonds", "pr_sys_stats",
                         "pr_sys_set_sort_period", "pr_sys_set_graphs", "pr_batch_create",
                         "pr_batch_destroy", "pr_batch_run", "pr_batch_run_loop", "pr_batch_bonds",
-                        "pr_batch_read", "pr_batch_stats")]
+                        "pr_batch_read", "pr_batch_stats", "pr_footprint", "pr_server_create",
+                        "pr_server_destroy", "pr_server_submit", "pr_server_wait",
+                        "pr_server_bonds", "pr_server_read", "pr_server_stats",
+                        "pr_server_release", "pr_server_info_get")]
 
 
 def _check(code):
@@ -220,6 +242,21 @@ class System:
         return [arr[k].as_dict() for k in range(n.value)]
 
 
+def replica_desc(r):
+    """ReplicaDesc from a dict: n, L, B, rule, seed, kind, gen_seed, sigma0, log_cap."""
+    rule = r["rule"] if isinstance(r["rule"], Rule) else Rule.make(r["rule"])
+    return ReplicaDesc(int(r["n"]), float(np.float32(r["L"])), int(r["B"]), rule, int(r["seed"]),
+                       0 if r["kind"] == "step" else 1, int(r["gen_seed"]),
+                       float(r.get("sigma0", 0.1)), int(r.get("log_cap", 0)))
+
+
+def footprint(r, n_steps):
+    b = C.c_int64(0)
+    d = replica_desc(r)
+    _check(lib.pr_footprint(C.byref(d), int(n_steps), C.byref(b)))
+    return b.value
+
+
 class Batch:
     """Batched ensemble of independent replicas (pr_batch_* entry points).
 
@@ -229,11 +266,7 @@ class Batch:
     def __init__(self, reps, stream=None):
         arr = (ReplicaDesc * len(reps))()
         for k, r in enumerate(reps):
-            rule = r["rule"] if isinstance(r["rule"], Rule) else Rule.make(r["rule"])
-            arr[k] = ReplicaDesc(int(r["n"]), float(np.float32(r["L"])), int(r["B"]), rule,
-                                 int(r["seed"]), 0 if r["kind"] == "step" else 1,
-                                 int(r["gen_seed"]), float(r.get("sigma0", 0.1)),
-                                 int(r.get("log_cap", 0)))
+            arr[k] = replica_desc(r)
         self.reps = [dict(r) for r in reps]
         self._h = C.c_void_p()
         _check(lib.pr_batch_create(C.byref(self._h), arr, len(reps), _stream(stream)))
@@ -278,3 +311,72 @@ class Batch:
         arr = (Stats * max(n.value, 1))()
         _check(lib.pr_batch_stats(self._h, int(rep), arr, n.value, C.byref(n)))
         return [arr[k].as_dict() for k in range(n.value)]
+
+
+class Server:
+    """Request loop with continuous batching (pr_server_* entry points)."""
+
+    QUEUED, RUNNING, DONE, FAILED = 0, 1, 2, 3
+
+    def __init__(self, hbm_budget, max_slots, stream=None):
+        self._h = C.c_void_p()
+        s = C.c_void_p(stream.cuda_stream) if stream is not None else None
+        _check(lib.pr_server_create(C.byref(self._h), int(hbm_budget), int(max_slots), s))
+        self._n = {}
+
+    def close(self):
+        if self._h:
+            lib.pr_server_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, r, n_steps, sigma):
+        d = replica_desc(r)
+        t = C.c_uint64(0)
+        _check(lib.pr_server_submit(self._h, C.byref(d), int(n_steps), float(sigma), C.byref(t)))
+        self._n[t.value] = (int(r["n"]), int(r["B"]))
+        return t.value
+
+    def wait(self, ticket, timeout_s=0.0):
+        st, code, lat = C.c_int32(0), C.c_int32(0), C.c_double(0)
+        _check(lib.pr_server_wait(self._h, C.c_uint64(ticket), float(timeout_s), C.byref(st),
+                                  C.byref(code), C.byref(lat)))
+        return st.value, code.value, lat.value
+
+    def bonds(self, ticket):
+        n = C.c_int64(0)
+        _check(lib.pr_server_bonds(self._h, C.c_uint64(ticket), None, 0, C.byref(n)))
+        out = np.empty((max(n.value, 1), 3), np.int32)
+        _check(lib.pr_server_bonds(self._h, C.c_uint64(ticket), out.ctypes.data_as(C.c_void_p),
+                                   n.value, C.byref(n)))
+        return out[: n.value]
+
+    def read(self, ticket):
+        n, B = self._n[ticket]
+        out = dict(x=np.empty(n, np.float32), y=np.empty(n, np.float32), z=np.empty(n, np.float32),
+                   state=np.empty(n, np.int32), adj=np.empty((n, B), np.int32))
+        _check(lib.pr_server_read(self._h, C.c_uint64(ticket),
+                                  *[out[k].ctypes.data_as(C.c_void_p)
+                                    for k in ("x", "y", "z", "state", "adj")]))
+        return out
+
+    def stats(self, ticket):
+        n = C.c_int64(0)
+        _check(lib.pr_server_stats(self._h, C.c_uint64(ticket), None, 0, C.byref(n)))
+        arr = (Stats * max(n.value, 1))()
+        _check(lib.pr_server_stats(self._h, C.c_uint64(ticket), arr, n.value, C.byref(n)))
+        return [arr[k].as_dict() for k in range(n.value)]
+
+    def release(self, ticket):
+        _check(lib.pr_server_release(self._h, C.c_uint64(ticket)))
+        self._n.pop(ticket, None)
+
+    def info(self):
+        i = ServerInfo()
+        _check(lib.pr_server_info_get(self._h, C.byref(i)))
+        return i.as_dict()

@@ -8,6 +8,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <thread>
+#include <unordered_map>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -104,6 +110,8 @@ void set_geometry(Dev& d, int32_t n, float L, int32_t B, const pr_rule* r, uint6
   d.nwg_sweep = sweep_blocks(n);
   d.nwg_prep = prep_blocks(n);
   d.adj_staged = B <= kAdjStage ? 1 : 0;
+  d.k_limit = INT32_MAX;
+  d.first_step = 0;
   d.jit_c = 0.0f;
   d.part = nullptr;
   d.part_cap = 0;
@@ -121,8 +129,12 @@ void set_geometry(Dev& d, int32_t n, float L, int32_t B, const pr_rule* r, uint6
   d.ngroups = (std::max(d.nwg_sweep, d.nbricks) + kGroup - 1) / kGroup;
 }
 
+// Device allocations of one handle.  dry = true only adds up the bytes (the
+// footprint of a system before it is created: the same allocation code runs).
 struct Arena {
   std::vector<void*> ptrs;
+  bool dry = false;
+  size_t bytes = 0;
   ~Arena() { release(); }
   void release() {
     for (void* p : ptrs) (void)hipFree(p);
@@ -130,10 +142,15 @@ struct Arena {
   }
   template <typename T>
   int alloc(T** out, size_t count) {
-    void* p = nullptr;
     if (count == 0) count = 1;
-    if (hipMalloc(&p, count * sizeof(T)) != hipSuccess)
-      return fail(PR_ENOMEM, "hipMalloc of %zu bytes failed", count * sizeof(T));
+    const size_t nb = count * sizeof(T);
+    bytes += (nb + 255) & ~(size_t)255;
+    if (dry) {
+      *out = nullptr;
+      return PR_OK;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, nb) != hipSuccess) return fail(PR_ENOMEM, "hipMalloc of %zu bytes failed", nb);
     ptrs.push_back(p);
     *out = (T*)p;
     return PR_OK;
@@ -162,6 +179,7 @@ int alloc_scratch(Arena& a, Dev& d, int32_t n, int32_t nwg, hipStream_t s) {
       return e;
   }
   if ((e = a.alloc(&d.ctl, 1))) return e;
+  if (a.dry) return PR_OK;
   HIP_TRY(hipMemsetAsync(d.cnt[0], 0, sizeof(uint32_t) * std::max(1, d.ncell), s));
   HIP_TRY(hipMemsetAsync(d.cnt[1], 0, sizeof(uint32_t) * std::max(1, d.ncell), s));
   HIP_TRY(hipMemsetAsync(d.slotA, 0xFF, sizeof(unsigned long long) * std::max(1, n), s));
@@ -463,7 +481,56 @@ int capture_block(pr_sys* s, int32_t K) {
 
 }  // namespace
 
+namespace {
+
+// Every device allocation of a resident system but the partial-counter log
+// (grown on demand) and the host-read staging buffers (on first read).
+int alloc_system(Arena& A, Dev& d, int32_t n, int32_t B, int64_t log_cap, hipStream_t st) {
+  int e = alloc_scratch(A, d, n, std::max(sweep_blocks(n), d.nbricks), st);
+  for (int q = 0; q < 2 && !e; ++q) {
+    Arr& a = d.set[q];
+    for (int p = 0; p < 2 && !e; ++p) {
+      if (!e) e = A.alloc(&a.x[p], n);
+      if (!e) e = A.alloc(&a.y[p], n);
+      if (!e) e = A.alloc(&a.z[p], n);
+    }
+    if (!e) e = A.alloc(&a.typ, n);
+    if (!e) e = A.alloc(&a.st, n);
+    if (!e) e = A.alloc(&a.id, n);
+    if (!e) e = A.alloc(&a.role, n);
+    if (!e) e = A.alloc(&a.adj, (size_t)n * B);
+  }
+  if (!e) e = A.alloc(&d.slot_of, n);
+  if (!e) e = A.alloc(&d.log, (size_t)log_cap * 3);
+  if (!e) e = A.alloc(&d.bstart, (size_t)d.nbricks + 1);
+  if (!e) e = A.alloc(&d.bcnt, (size_t)d.nbricks);
+  if (!e) e = A.alloc(&d.rank, n);
+  if (!e && !A.dry && hipMemsetAsync(d.bcnt, 0, sizeof(uint32_t) * d.nbricks, st) != hipSuccess)
+    e = fail(PR_EHIP, "hipMemsetAsync failed");
+  return e;
+}
+
+}  // namespace
+
 extern "C" {
+
+int pr_footprint(const pr_replica_desc* r, uint32_t n_steps, int64_t* bytes) {
+  if (!r || !bytes) return fail(PR_EINVAL, "NULL argument");
+  if (r->n < 1 || r->B < 1) return fail(PR_EINVAL, "n=%d B=%d", r->n, r->B);
+  int e = validate_rule(&r->rule, r->L);
+  if (e) return e;
+  Dev d{};
+  set_geometry(d, r->n, r->L, r->B, &r->rule, r->seed, kMaxBrick);
+  Arena A;
+  A.dry = true;
+  const int64_t log_cap = r->log_cap > 0 ? r->log_cap : r->n;
+  if ((e = alloc_system(A, d, r->n, r->B, log_cap, nullptr))) return e;
+  // partial counters for max(1024, n_steps) steps; host-read staging buffers
+  const size_t part = (size_t)std::max<uint32_t>(1024u, n_steps) * d.ngroups * kPart * 4;
+  const size_t rd = (size_t)r->n * (3 * 4 + 4 + 4 * (size_t)r->B);
+  *bytes = (int64_t)(A.bytes + ((part + 255) & ~(size_t)255) + rd);
+  return PR_OK;
+}
 
 int pr_sys_create(pr_sys** out, int32_t n, float L, int32_t B, const pr_rule* rule, uint64_t seed,
                   int64_t log_cap, void* stream) {
@@ -482,27 +549,7 @@ int pr_sys_create(pr_sys** out, int32_t n, float L, int32_t B, const pr_rule* ru
   Dev& d = s->d;
   set_geometry(d, n, L, B, rule, seed, kMaxBrick);
   s->log_cap = log_cap > 0 ? log_cap : n;
-  e = alloc_scratch(s->arena, d, n, std::max(sweep_blocks(n), d.nbricks), s->stream);
-  for (int q = 0; q < 2 && !e; ++q) {
-    Arr& a = d.set[q];
-    for (int p = 0; p < 2 && !e; ++p) {
-      if (!e) e = s->arena.alloc(&a.x[p], n);
-      if (!e) e = s->arena.alloc(&a.y[p], n);
-      if (!e) e = s->arena.alloc(&a.z[p], n);
-    }
-    if (!e) e = s->arena.alloc(&a.typ, n);
-    if (!e) e = s->arena.alloc(&a.st, n);
-    if (!e) e = s->arena.alloc(&a.id, n);
-    if (!e) e = s->arena.alloc(&a.role, n);
-    if (!e) e = s->arena.alloc(&a.adj, (size_t)n * B);
-  }
-  if (!e) e = s->arena.alloc(&d.slot_of, n);
-  if (!e) e = s->arena.alloc(&d.log, (size_t)s->log_cap * 3);
-  if (!e) e = s->arena.alloc(&d.bstart, (size_t)d.nbricks + 1);
-  if (!e) e = s->arena.alloc(&d.bcnt, (size_t)d.nbricks);
-  if (!e) e = s->arena.alloc(&d.rank, n);
-  if (!e && hipMemsetAsync(d.bcnt, 0, sizeof(uint32_t) * d.nbricks, s->stream) != hipSuccess)
-    e = fail(PR_EHIP, "hipMemsetAsync failed");
+  e = alloc_system(s->arena, d, n, B, s->log_cap, s->stream);
   if (!e && hipHostMalloc((void**)&s->hctl, sizeof(Ctl)) != hipSuccess)
     e = fail(PR_ENOMEM, "hipHostMalloc failed");
   if (!e) e = grow_part(s, 1024);
@@ -772,10 +819,10 @@ int check_batch(pr_batch* b, int32_t rep) {
 
 // Maps of grid blocks to (replica, local block, blocks of the replica) for
 // the sorted-storage kernels of the batch.
-int build_maps(pr_batch* b) {
+int fill_maps(const std::vector<pr_sys*>& sys, Arena& arena, BatchLaunch& bl) {
   std::vector<int4> prep0, prepk, sweep, close, part;
-  for (int r = 0; r < (int)b->sys.size(); ++r) {
-    const Dev& d = b->sys[r]->d;
+  for (int r = 0; r < (int)sys.size(); ++r) {
+    const Dev& d = sys[r]->d;
     for (int q = 0; q < d.nwg_prep; ++q) prep0.push_back(make_int4(r, q, d.nwg_prep, 0));
     for (int q = 0; q < d.ngroups + d.nwg_prep; ++q)
       prepk.push_back(make_int4(r, q, d.ngroups + d.nwg_prep, 0));
@@ -786,33 +833,34 @@ int build_maps(pr_batch* b) {
   }
   int4 *m0, *mk, *ms, *mc, *mp;
   int e;
-  if ((e = b->arena.alloc(&m0, prep0.size())) || (e = b->arena.alloc(&mk, prepk.size())) ||
-      (e = b->arena.alloc(&ms, sweep.size())) || (e = b->arena.alloc(&mc, close.size())) ||
-      (e = b->arena.alloc(&mp, part.size())))
+  if ((e = arena.alloc(&m0, prep0.size())) || (e = arena.alloc(&mk, prepk.size())) ||
+      (e = arena.alloc(&ms, sweep.size())) || (e = arena.alloc(&mc, close.size())) ||
+      (e = arena.alloc(&mp, part.size())))
     return e;
   HIP_TRY(hipMemcpy(m0, prep0.data(), prep0.size() * sizeof(int4), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(mk, prepk.data(), prepk.size() * sizeof(int4), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(ms, sweep.data(), sweep.size() * sizeof(int4), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(mc, close.data(), close.size() * sizeof(int4), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(mp, part.data(), part.size() * sizeof(int4), hipMemcpyHostToDevice));
-  b->bl.prep0 = m0;
-  b->bl.prepk = mk;
-  b->bl.sweep = ms;
-  b->bl.close = mc;
-  b->bl.part = mp;
-  b->bl.n_prep0 = (int)prep0.size();
-  b->bl.n_prepk = (int)prepk.size();
-  b->bl.n_sweep = (int)sweep.size();
-  b->bl.n_close = (int)close.size();
-  b->bl.n_part = (int)part.size();
+  bl.prep0 = m0;
+  bl.prepk = mk;
+  bl.sweep = ms;
+  bl.close = mc;
+  bl.part = mp;
+  bl.n_prep0 = (int)prep0.size();
+  bl.n_prepk = (int)prepk.size();
+  bl.n_sweep = (int)sweep.size();
+  bl.n_close = (int)close.size();
+  bl.n_part = (int)part.size();
+  bl.nrep = (int)sys.size();
   return PR_OK;
 }
 
 // One block of K steps for every replica: a sort, the steps, the block end.
-int run_block_b(pr_batch* b, hipStream_t st, int32_t K) {
-  HIP_TRY(launch_sort_b(b->bl, st));
-  for (int32_t k = 0; k < K; ++k) HIP_TRY(launch_step_b(b->bl, k, st));
-  HIP_TRY(launch_block_end_b(b->bl, K, st));
+int run_block_b(const BatchLaunch& bl, hipStream_t st, int32_t K) {
+  HIP_TRY(launch_sort_b(bl, st));
+  for (int32_t k = 0; k < K; ++k) HIP_TRY(launch_step_b(bl, k, st));
+  HIP_TRY(launch_block_end_b(bl, K, st));
   return PR_OK;
 }
 
@@ -821,7 +869,7 @@ int capture_block_b(pr_batch* b, int32_t K) {
   b->gexec = nullptr;
   hipGraph_t g = nullptr;
   HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-  const int e = run_block_b(b, b->cap, K);
+  const int e = run_block_b(b->bl, b->cap, K);
   const hipError_t ce = hipStreamEndCapture(b->cap, &g);
   if (e) {
     if (g) (void)hipGraphDestroy(g);
@@ -867,7 +915,7 @@ int pr_batch_create(pr_batch** out, const pr_replica_desc* reps, int32_t n_rep, 
       fail(e, "replica %d: %s", r, msg.c_str());
     }
   }
-  if (!e) e = build_maps(b);
+  if (!e) e = fill_maps(b->sys, b->arena, b->bl);
   if (!e) e = b->arena.alloc(&b->ds, (size_t)n_rep);
   if (e) {
     delete b;
@@ -906,11 +954,13 @@ int pr_batch_run(pr_batch* b, uint32_t first_step, uint32_t n_steps, double sigm
     s->d.sorted = 1;
     s->d.nwg_sweep = s->d.nbricks;
     b->hds[r] = s->d;
+    b->hds[r].k_limit = INT32_MAX;
+    b->hds[r].first_step = first_step;
   }
   HIP_TRY(hipMemcpyAsync(b->ds, b->hds.data(), sizeof(Dev) * b->hds.size(),
                          hipMemcpyHostToDevice, st));
   HIP_TRY(hipEventRecord(b->copied, st));
-  HIP_TRY(launch_ctl_b(b->bl, 0, first_step, st));
+  HIP_TRY(launch_ctl_b(b->bl, 0, 0u, st));
   const int32_t K = b->sort_period;
   uint32_t left = n_steps;
   while (left > 0) {
@@ -920,7 +970,7 @@ int pr_batch_run(pr_batch* b, uint32_t first_step, uint32_t n_steps, double sigm
       HIP_TRY(hipGraphLaunch(b->gexec, st));
       left -= (uint32_t)K;
     } else {
-      if ((e = run_block_b(b, st, (int32_t)left))) return e;
+      if ((e = run_block_b(b->bl, st, (int32_t)left))) return e;
       left = 0;
     }
   }
@@ -961,6 +1011,409 @@ int pr_batch_read(pr_batch* b, int32_t rep, float* x, float* y, float* z, int32_
 int pr_batch_stats(pr_batch* b, int32_t rep, pr_stats* out, int64_t cap, int64_t* n) {
   int e = check_batch(b, rep);
   return e ? e : pr_sys_stats(b->sys[rep], out, cap, n);
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Serving
+// ===========================================================================
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct SrvReq {
+  uint64_t ticket = 0;
+  pr_replica_desc desc{};
+  uint32_t n_steps = 0, done_steps = 0;
+  double sigma = 0.0;
+  int64_t bytes = 0;
+  Clock::time_point t_submit, t_done;
+  int32_t status = 0;  // 0 queued, 1 running, 2 done, 3 failed
+  int32_t code = 0;
+  pr_sys* sys = nullptr;
+  // results, host memory
+  std::vector<int32_t> bonds;
+  int64_t n_bonds = 0;
+  std::vector<float> x, y, z;
+  std::vector<int32_t> state, adj;
+  std::vector<pr_stats> stats;
+};
+
+}  // namespace
+
+struct pr_server {
+  int dev = 0;
+  int64_t budget = 0, used = 0;
+  int32_t max_slots = 1;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<SrvReq*> queue;
+  std::vector<SrvReq*> active;  // worker thread only (under mu when changed)
+  std::unordered_map<uint64_t, SrvReq*> all;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  int64_t rounds = 0, n_done = 0, n_failed = 0;
+  double busy_s = 0.0;
+  std::thread worker;
+  // batched launch state of the active set
+  Arena maps;
+  BatchLaunch bl{};
+  Arena dsa;
+  Dev* ds = nullptr;
+  size_t ds_cap = 0;
+  std::vector<Dev> hds;
+  bool set_changed = true;
+};
+
+namespace {
+
+// The worker's results copy of a finished replica, then its device memory
+// freed.  Returns the error code (0 = done).
+int srv_finish(SrvReq* r) {
+  pr_sys* s = r->sys;
+  const size_t n = (size_t)r->desc.n, B = (size_t)r->desc.B;
+  int64_t nb = 0;
+  int e = pr_sys_bonds(s, nullptr, 0, &nb);
+  if (!e) {
+    r->bonds.resize((size_t)std::max<int64_t>(nb, 1) * 3);
+    e = pr_sys_bonds(s, r->bonds.data(), nb, &nb);
+    r->n_bonds = nb;
+  }
+  if (!e) {
+    r->x.resize(n);
+    r->y.resize(n);
+    r->z.resize(n);
+    r->state.resize(n);
+    r->adj.resize(n * B);
+    e = pr_sys_read(s, r->x.data(), r->y.data(), r->z.data(), r->state.data(), r->adj.data(), 0);
+  }
+  if (!e) {
+    int64_t ns = 0;
+    e = pr_sys_stats(s, nullptr, 0, &ns);
+    if (!e) {
+      r->stats.resize((size_t)std::max<int64_t>(ns, 1));
+      e = pr_sys_stats(s, r->stats.data(), ns, &ns);
+      r->stats.resize((size_t)ns);
+    }
+  }
+  pr_sys_destroy(s);
+  r->sys = nullptr;
+  return e;
+}
+
+// Creates and generates an admitted replica (worker thread).
+int srv_admit(pr_server* S, SrvReq* r) {
+  const pr_replica_desc& q = r->desc;
+  pr_sys* s = nullptr;
+  int e = pr_sys_create(&s, q.n, q.L, q.B, &q.rule, q.seed, q.log_cap, S->stream);
+  if (!e) e = pr_sys_generate(s, q.gen_kind, q.gen_seed, q.gen_sigma0);
+  if (!e) e = grow_part(s, std::max<int64_t>(1024, r->n_steps));
+  if (e) {
+    if (s) pr_sys_destroy(s);
+    return e;
+  }
+  s->d.jit_c = (float)(r->sigma / std::sqrt(21845.0));
+  r->sys = s;
+  return PR_OK;
+}
+
+// One round: every active replica takes min(64, steps left) steps in the
+// batched launches.  Returns an error code (the round's replicas fail).
+int srv_round(pr_server* S) {
+  const int32_t Kmax = 64;
+  std::vector<pr_sys*> sys;
+  for (SrvReq* r : S->active) sys.push_back(r->sys);
+  int e;
+  if (S->set_changed) {
+    S->maps.release();
+    S->maps.bytes = 0;
+    if ((e = fill_maps(sys, S->maps, S->bl))) return e;
+    if (S->ds_cap < sys.size()) {
+      S->dsa.release();
+      S->ds_cap = std::max<size_t>(sys.size(), 2 * S->ds_cap);
+      if ((e = S->dsa.alloc(&S->ds, S->ds_cap))) return e;
+    }
+    S->bl.ds = S->ds;
+    S->set_changed = false;
+  }
+  S->hds.resize(sys.size());
+  int32_t K = 0;
+  for (size_t i = 0; i < sys.size(); ++i) {
+    SrvReq* r = S->active[i];
+    pr_sys* s = r->sys;
+    const int32_t kl = (int32_t)std::min<uint32_t>((uint32_t)Kmax, r->n_steps - r->done_steps);
+    s->d.sorted = 1;
+    s->d.nwg_sweep = s->d.nbricks;
+    S->hds[i] = s->d;
+    S->hds[i].k_limit = kl;
+    S->hds[i].first_step = 1u + r->done_steps;
+    K = std::max(K, kl);
+  }
+  hipStream_t st = S->stream;
+  HIP_TRY(hipMemcpyAsync(S->ds, S->hds.data(), sizeof(Dev) * S->hds.size(), hipMemcpyHostToDevice,
+                         st));
+  HIP_TRY(hipEventRecord(S->ev0, st));
+  HIP_TRY(launch_ctl_b(S->bl, 0, 0u, st));
+  if ((e = run_block_b(S->bl, st, K))) return e;
+  HIP_TRY(hipEventRecord(S->ev1, st));
+  HIP_TRY(hipEventSynchronize(S->ev1));
+  float ms = 0.0f;
+  HIP_TRY(hipEventElapsedTime(&ms, S->ev0, S->ev1));
+  S->busy_s += ms * 1e-3;
+  S->rounds++;
+  for (size_t i = 0; i < sys.size(); ++i) {
+    SrvReq* r = S->active[i];
+    const uint32_t kl = (uint32_t)S->hds[i].k_limit;
+    r->done_steps += kl;
+    drop_graph(r->sys);
+    r->sys->steps_since_sort = (int64_t)kl;
+    r->sys->steps_since_load += kl;
+  }
+  return PR_OK;
+}
+
+void srv_loop(pr_server* S) {
+  (void)hipSetDevice(S->dev);
+  for (;;) {
+    std::vector<SrvReq*> adm;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv_work.wait(lk, [&] { return S->stop || !S->queue.empty() || !S->active.empty(); });
+      if (S->stop) break;
+      // admission in arrival order: the head waits until it fits
+      while (!S->queue.empty()) {
+        SrvReq* r = S->queue.front();
+        if ((int32_t)(S->active.size() + adm.size()) >= S->max_slots ||
+            S->used + r->bytes > S->budget)
+          break;
+        S->queue.pop_front();
+        S->used += r->bytes;
+        r->status = 1;
+        adm.push_back(r);
+      }
+    }
+    for (SrvReq* r : adm) {
+      const int e = srv_admit(S, r);
+      std::lock_guard<std::mutex> lk(S->mu);
+      if (e) {
+        r->status = 3;
+        r->code = e;
+        r->t_done = Clock::now();
+        S->used -= r->bytes;
+        S->n_failed++;
+        S->cv_done.notify_all();
+      } else {
+        S->active.push_back(r);
+        S->set_changed = true;
+      }
+    }
+    if (S->active.empty()) continue;
+    const int e = srv_round(S);
+    std::vector<SrvReq*> fin, keep;
+    for (SrvReq* r : S->active) {
+      if (e || r->done_steps >= r->n_steps) fin.push_back(r);
+      else keep.push_back(r);
+    }
+    for (SrvReq* r : fin) {
+      const int fe = e ? e : srv_finish(r);
+      if (e && r->sys) {
+        pr_sys_destroy(r->sys);
+        r->sys = nullptr;
+      }
+      std::lock_guard<std::mutex> lk(S->mu);
+      r->t_done = Clock::now();
+      r->status = fe ? 3 : 2;
+      r->code = fe;
+      S->used -= r->bytes;
+      if (fe) S->n_failed++;
+      else S->n_done++;
+    }
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      if (!fin.empty()) S->set_changed = true;
+      S->active.swap(keep);
+    }
+    if (!fin.empty()) S->cv_done.notify_all();
+  }
+}
+
+SrvReq* srv_find(pr_server* S, uint64_t t) {
+  auto it = S->all.find(t);
+  return it == S->all.end() ? nullptr : it->second;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pr_server_create(pr_server** out, int64_t hbm_budget, int32_t max_slots, void* stream) {
+  if (!out) return fail(PR_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (hbm_budget <= 0 || max_slots < 1)
+    return fail(PR_EINVAL, "budget=%lld max_slots=%d", (long long)hbm_budget, max_slots);
+  pr_server* S = new pr_server();
+  S->budget = hbm_budget;
+  S->max_slots = max_slots;
+  S->stream = (hipStream_t)stream;
+  if (hipGetDevice(&S->dev) != hipSuccess ||
+      (!S->stream && hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess) ||
+      hipEventCreate(&S->ev0) != hipSuccess || hipEventCreate(&S->ev1) != hipSuccess) {
+    delete S;
+    return fail(PR_EHIP, "hipGetDevice/hipStreamCreate/hipEventCreate failed");
+  }
+  S->own_stream = stream == nullptr;
+  S->worker = std::thread(srv_loop, S);
+  *out = S;
+  return PR_OK;
+}
+
+void pr_server_destroy(pr_server* S) {
+  if (!S) return;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+  }
+  S->cv_work.notify_all();
+  if (S->worker.joinable()) S->worker.join();
+  for (SrvReq* r : S->active)
+    if (r->sys) pr_sys_destroy(r->sys);
+  for (auto& kv : S->all) delete kv.second;
+  (void)hipStreamSynchronize(S->stream);
+  if (S->ev0) (void)hipEventDestroy(S->ev0);
+  if (S->ev1) (void)hipEventDestroy(S->ev1);
+  if (S->own_stream) (void)hipStreamDestroy(S->stream);
+  delete S;
+}
+
+int pr_server_submit(pr_server* S, const pr_replica_desc* r, uint32_t n_steps, double sigma,
+                     uint64_t* ticket) {
+  if (!S || !r || !ticket) return fail(PR_EINVAL, "NULL argument");
+  if (n_steps < 1) return fail(PR_EINVAL, "n_steps=0");
+  if (!(sigma >= 0.0) || sigma * 6.0 >= (double)r->L * 0.5) return fail(PR_EINVAL, "sigma=%g", sigma);
+  if (r->gen_kind != 0 && r->gen_kind != 1) return fail(PR_EINVAL, "gen_kind=%d", r->gen_kind);
+  if (!(r->gen_sigma0 >= 0.0) || r->gen_sigma0 * 6.0 >= (double)r->L * 0.5)
+    return fail(PR_EINVAL, "gen_sigma0=%g", r->gen_sigma0);
+  int64_t bytes = 0;
+  int e = pr_footprint(r, n_steps, &bytes);
+  if (e) return e;
+  if (bytes > S->budget)
+    return fail(PR_EBUSY, "footprint %lld B exceeds the budget %lld B", (long long)bytes,
+                (long long)S->budget);
+  SrvReq* q = new SrvReq();
+  q->desc = *r;
+  q->n_steps = n_steps;
+  q->sigma = sigma;
+  q->bytes = bytes;
+  q->t_submit = Clock::now();
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    q->ticket = S->next_ticket++;
+    S->all[q->ticket] = q;
+    S->queue.push_back(q);
+  }
+  S->cv_work.notify_all();
+  *ticket = q->ticket;
+  return PR_OK;
+}
+
+int pr_server_wait(pr_server* S, uint64_t ticket, double timeout_s, int32_t* status, int32_t* code,
+                   double* latency_s) {
+  if (!S) return fail(PR_EINVAL, "NULL server");
+  std::unique_lock<std::mutex> lk(S->mu);
+  SrvReq* q = srv_find(S, ticket);
+  if (!q) return fail(PR_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+  if (timeout_s > 0.0)
+    S->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s),
+                        [&] { return q->status >= 2; });
+  if (status) *status = q->status;
+  if (code) *code = q->code;
+  if (latency_s)
+    *latency_s = q->status >= 2 ? std::chrono::duration<double>(q->t_done - q->t_submit).count() : -1.0;
+  return PR_OK;
+}
+
+static SrvReq* srv_done(pr_server* S, uint64_t ticket, int* e) {
+  SrvReq* q = srv_find(S, ticket);
+  if (!q) {
+    *e = fail(PR_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+    return nullptr;
+  }
+  if (q->status != 2) {
+    *e = fail(q->status == 3 ? q->code : PR_EBUSY, "request %llu is not done",
+              (unsigned long long)ticket);
+    return nullptr;
+  }
+  *e = PR_OK;
+  return q;
+}
+
+int pr_server_bonds(pr_server* S, uint64_t ticket, int32_t* out, int64_t cap, int64_t* n) {
+  if (!S || !n || (cap > 0 && !out)) return fail(PR_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  int e;
+  SrvReq* q = srv_done(S, ticket, &e);
+  if (!q) return e;
+  const int64_t m = std::min<int64_t>(cap, q->n_bonds);
+  if (m > 0) std::memcpy(out, q->bonds.data(), (size_t)m * 3 * sizeof(int32_t));
+  *n = q->n_bonds;
+  return PR_OK;
+}
+
+int pr_server_read(pr_server* S, uint64_t ticket, float* x, float* y, float* z, int32_t* state,
+                   int32_t* adj) {
+  if (!S) return fail(PR_EINVAL, "NULL server");
+  std::lock_guard<std::mutex> lk(S->mu);
+  int e;
+  SrvReq* q = srv_done(S, ticket, &e);
+  if (!q) return e;
+  const size_t n = (size_t)q->desc.n;
+  if (x) std::memcpy(x, q->x.data(), n * 4);
+  if (y) std::memcpy(y, q->y.data(), n * 4);
+  if (z) std::memcpy(z, q->z.data(), n * 4);
+  if (state) std::memcpy(state, q->state.data(), n * 4);
+  if (adj) std::memcpy(adj, q->adj.data(), n * 4 * (size_t)q->desc.B);
+  return PR_OK;
+}
+
+int pr_server_stats(pr_server* S, uint64_t ticket, pr_stats* out, int64_t cap, int64_t* n) {
+  if (!S || !n || (cap > 0 && !out)) return fail(PR_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  int e;
+  SrvReq* q = srv_done(S, ticket, &e);
+  if (!q) return e;
+  const int64_t m = std::min<int64_t>(cap, (int64_t)q->stats.size());
+  if (m > 0) std::memcpy(out, q->stats.data(), (size_t)m * sizeof(pr_stats));
+  *n = (int64_t)q->stats.size();
+  return PR_OK;
+}
+
+int pr_server_release(pr_server* S, uint64_t ticket) {
+  if (!S) return fail(PR_EINVAL, "NULL server");
+  std::lock_guard<std::mutex> lk(S->mu);
+  SrvReq* q = srv_find(S, ticket);
+  if (!q) return fail(PR_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+  if (q->status < 2) return fail(PR_EBUSY, "request %llu is not finished", (unsigned long long)ticket);
+  S->all.erase(ticket);
+  delete q;
+  return PR_OK;
+}
+
+int pr_server_info_get(pr_server* S, pr_server_info* out) {
+  if (!S || !out) return fail(PR_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  out->budget = S->budget;
+  out->used = S->used;
+  out->queued = (int64_t)S->queue.size();
+  out->active = (int64_t)S->active.size();
+  out->done = S->n_done;
+  out->failed = S->n_failed;
+  out->rounds = S->rounds;
+  out->busy_s = S->busy_s;
+  return PR_OK;
 }
 
 }  // extern "C"

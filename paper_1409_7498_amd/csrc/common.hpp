@@ -108,6 +108,10 @@ struct Dev {
   int32_t jitter;       // 1: resident system (positions ping-pong, re-jitter by jit_c)
                         // 0: caller's arrays, read only
   int32_t adj_staged;   // B <= kAdjStage: records carry the adjacency row
+  // batched launches only: steps of the current block this system takes part
+  // in (0 .. k_limit - 1) and the reaction step of the block's first step
+  int32_t k_limit;
+  uint32_t first_step;
   float L, halfL, rc2, inv_w, jit_c;
   unsigned long long thresh, seed;
   RuleD rule;

@@ -1227,38 +1227,50 @@ __device__ __forceinline__ int4 uniform_map(const int4* __restrict__ map) {
                    __builtin_amdgcn_readfirstlane(m.z), 0);
 }
 
+// A replica takes part in steps k < k_limit of a block; its workgroups of
+// later steps return at once (uniformly: the whole block belongs to it).
 __global__ __launch_bounds__(kThreads) void k_prep_b(const Dev* __restrict__ ds,
                                                      const int4* __restrict__ map, int k) {
   const int4 m = uniform_map(map);
   const Dev& d = ds[m.x];
+  if (k >= d.k_limit) return;
   prep_body(d, k, m.y);
 }
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) void k_sweep_b(
     const Dev* __restrict__ ds, const int4* __restrict__ map, int k) {
   const int4 m = uniform_map(map);
   const Dev& d = ds[m.x];
+  if (k >= d.k_limit) return;
   sweep_body<true>(d, k, m.y, m.z);
 }
 __global__ __launch_bounds__(kThreads) void k_resolve_b(const Dev* __restrict__ ds,
                                                         const int4* __restrict__ map, int k) {
   const int4 m = uniform_map(map);
   const Dev& d = ds[m.x];
+  if (k >= d.k_limit) return;
   resolve_body<true>(d, k, m.y);
 }
 __global__ __launch_bounds__(kThreads) void k_close_b(const Dev* __restrict__ ds,
                                                       const int4* __restrict__ map, int k) {
   const int4 m = uniform_map(map);
   const Dev& d = ds[m.x];
-  close_body(d, k, m.y);
+  if (d.k_limit < 1) return;
+  close_body(d, k < d.k_limit - 1 ? k : d.k_limit - 1, m.y);  // the replica's last step
 }
 // one thread per replica
 __global__ void k_ctl_b(const Dev* __restrict__ ds, int nrep, int op, uint32_t arg) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrep) return;
-  Ctl* c = ds[r].ctl;
-  if (op == 0) c->step0 = arg;               // start of a run
-  else if (op == 1) advance_ctl(c, (int)arg);  // end of a block of arg steps
-  else c->set ^= 1u;                         // after a sort
+  const Dev& d = ds[r];
+  Ctl* c = d.ctl;
+  if (op == 0) {
+    c->step0 = d.first_step;                 // start of a block
+  } else if (op == 1) {                      // end of a block of arg steps
+    const int kk = d.k_limit < (int)arg ? d.k_limit : (int)arg;
+    if (kk > 0) advance_ctl(c, kk);
+  } else {
+    c->set ^= 1u;                            // after a sort
+  }
 }
 __global__ __launch_bounds__(kThreads) void k_sort_count_b(const Dev* __restrict__ ds,
                                                            const int4* __restrict__ map) {
