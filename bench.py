@@ -223,6 +223,7 @@ def bench_serve(args):
         "particle_steps_per_s": n_part * steps / last,
         "gpu_busy_fraction": info["busy_s"] / last,
         "rounds": info["rounds"],
+        "worker_s": {k: round(info[k], 3) for k in ("admit_s", "finish_s", "launch_s", "wait_s")},
         "loop_replicas_per_s": nb / t_loop,
         "loop_requests": nb,
     }

@@ -247,6 +247,8 @@ typedef struct pr_server_info {
   int64_t queued, active, done, failed;
   int64_t rounds;                  /* batched rounds launched */
   double busy_s;                   /* GPU time of those rounds (HIP events) */
+  double admit_s, finish_s;        /* worker time creating replicas / moving results out */
+  double launch_s, wait_s;         /* worker time launching rounds / waiting for their end */
 } pr_server_info;
 
 /* hbm_budget: bytes the admitted replicas may hold together; max_slots:

@@ -47,7 +47,8 @@ class ReplicaDesc(C.Structure):
 class ServerInfo(C.Structure):
     _fields_ = [("budget", C.c_int64), ("used", C.c_int64), ("queued", C.c_int64),
                 ("active", C.c_int64), ("done", C.c_int64), ("failed", C.c_int64),
-                ("rounds", C.c_int64), ("busy_s", C.c_double)]
+                ("rounds", C.c_int64), ("busy_s", C.c_double), ("admit_s", C.c_double),
+                ("finish_s", C.c_double), ("launch_s", C.c_double), ("wait_s", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

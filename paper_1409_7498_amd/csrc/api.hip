@@ -131,13 +131,17 @@ void set_geometry(Dev& d, int32_t n, float L, int32_t B, const pr_rule* r, uint6
 
 // Device allocations of one handle.  dry = true only adds up the bytes (the
 // footprint of a system before it is created: the same allocation code runs).
+// async = true: stream-ordered allocation on astream (hipMallocAsync /
+// hipFreeAsync), so that freeing does not wait for unrelated device work.
 struct Arena {
   std::vector<void*> ptrs;
-  bool dry = false;
+  bool dry = false, async = false;
+  hipStream_t astream = nullptr;
+  hipMemPool_t pool = nullptr;  // async: the pool to draw from (null: the device's default)
   size_t bytes = 0;
   ~Arena() { release(); }
   void release() {
-    for (void* p : ptrs) (void)hipFree(p);
+    for (void* p : ptrs) (void)(async ? hipFreeAsync(p, astream) : hipFree(p));
     ptrs.clear();
   }
   template <typename T>
@@ -150,7 +154,10 @@ struct Arena {
       return PR_OK;
     }
     void* p = nullptr;
-    if (hipMalloc(&p, nb) != hipSuccess) return fail(PR_ENOMEM, "hipMalloc of %zu bytes failed", nb);
+    const hipError_t he = !async ? hipMalloc(&p, nb)
+                          : pool ? hipMallocFromPoolAsync(&p, nb, pool, astream)
+                                 : hipMallocAsync(&p, nb, astream);
+    if (he != hipSuccess) return fail(PR_ENOMEM, "hipMalloc of %zu bytes failed", nb);
     ptrs.push_back(p);
     *out = (T*)p;
     return PR_OK;
@@ -351,10 +358,11 @@ struct pr_sys {
   float *rx = nullptr, *ry = nullptr, *rz = nullptr;  // id-order read buffers
   int32_t *rst = nullptr, *radj = nullptr;
   Ctl* hctl = nullptr;
+  bool own_hctl = true;  // false: the pinned word belongs to a server's pool
   ~pr_sys() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (cap) (void)hipStreamDestroy(cap);
-    if (hctl) (void)hipHostFree(hctl);
+    if (hctl && own_hctl) (void)hipHostFree(hctl);
   }
 };
 
@@ -453,6 +461,7 @@ int run_block(pr_sys* s, hipStream_t st, int32_t K, hipEvent_t* ev) {
 int capture_block(pr_sys* s, int32_t K) {
   drop_graph(s);
   hipGraph_t g = nullptr;
+  if (!s->cap) HIP_TRY(hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking));
   HIP_TRY(hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal));
   const Dev saved_d = s->d;
   const int64_t saved_since = s->steps_since_sort;
@@ -532,8 +541,21 @@ int pr_footprint(const pr_replica_desc* r, uint32_t n_steps, int64_t* bytes) {
   return PR_OK;
 }
 
-int pr_sys_create(pr_sys** out, int32_t n, float L, int32_t B, const pr_rule* rule, uint64_t seed,
-                  int64_t log_cap, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Resources a server lends to the systems it creates: device memory drawn in
+// stream order from its pool (systems are created and retired while other
+// work runs, and a plain hipFree would wait for that work) and a pinned
+// control word from its own pool (hipHostFree waits for the device too).
+struct SysLease {
+  hipMemPool_t pool = nullptr;
+  Ctl* hctl = nullptr;
+};
+
+int sys_create(pr_sys** out, int32_t n, float L, int32_t B, const pr_rule* rule, uint64_t seed,
+               int64_t log_cap, void* stream, const SysLease* lease) {
   if (!out) return fail(PR_EINVAL, "out is NULL");
   *out = nullptr;
   if (n < 1 || B < 1) return fail(PR_EINVAL, "n=%d B=%d", n, B);
@@ -541,16 +563,23 @@ int pr_sys_create(pr_sys** out, int32_t n, float L, int32_t B, const pr_rule* ru
   if (e) return e;
   pr_sys* s = new pr_sys();
   s->stream = (hipStream_t)stream;
+  s->arena.async = lease != nullptr;
+  s->arena.astream = s->stream;
+  s->arena.pool = lease ? lease->pool : nullptr;
   s->rule = *rule;
-  if (hipGetDevice(&s->dev) != hipSuccess || hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking) != hipSuccess) {
+  if (lease) {
+    s->hctl = lease->hctl;
+    s->own_hctl = false;
+  }
+  if (hipGetDevice(&s->dev) != hipSuccess) {
     delete s;
-    return fail(PR_EHIP, "hipGetDevice/hipStreamCreate failed");
+    return fail(PR_EHIP, "hipGetDevice failed");
   }
   Dev& d = s->d;
   set_geometry(d, n, L, B, rule, seed, kMaxBrick);
   s->log_cap = log_cap > 0 ? log_cap : n;
   e = alloc_system(s->arena, d, n, B, s->log_cap, s->stream);
-  if (!e && hipHostMalloc((void**)&s->hctl, sizeof(Ctl)) != hipSuccess)
+  if (!e && !s->hctl && hipHostMalloc((void**)&s->hctl, sizeof(Ctl)) != hipSuccess)
     e = fail(PR_ENOMEM, "hipHostMalloc failed");
   if (!e) e = grow_part(s, 1024);
   if (e) {
@@ -566,6 +595,15 @@ int pr_sys_create(pr_sys** out, int32_t n, float L, int32_t B, const pr_rule* ru
   set_dense(s);
   *out = s;
   return PR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pr_sys_create(pr_sys** out, int32_t n, float L, int32_t B, const pr_rule* rule, uint64_t seed,
+                  int64_t log_cap, void* stream) {
+  return sys_create(out, n, L, B, rule, seed, log_cap, stream, nullptr);
 }
 
 void pr_sys_destroy(pr_sys* s) {
@@ -732,10 +770,26 @@ int pr_sys_bonds(pr_sys* s, int32_t* out, int64_t cap, int64_t* n) {
       int32_t step, a, t;
     };
     std::vector<Row> rows((size_t)have);
-    HIP_TRY(hipMemcpy(rows.data(), s->d.log, (size_t)have * sizeof(Row), hipMemcpyDeviceToHost));
-    std::sort(rows.begin(), rows.end(), [](const Row& u, const Row& v) {
-      return u.step != v.step ? u.step < v.step : u.a < v.a;
-    });
+    HIP_TRY(hipMemcpyAsync(rows.data(), s->d.log, (size_t)have * sizeof(Row),
+                           hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    // the rows of one step are appended together, steps in order: sorting
+    // each step's run by id_A is enough (else everything is sorted)
+    bool runs = true;
+    for (size_t i = 1; i < rows.size() && runs; ++i) runs = rows[i - 1].step <= rows[i].step;
+    if (runs) {
+      for (size_t i = 0; i < rows.size();) {
+        size_t j = i + 1;
+        while (j < rows.size() && rows[j].step == rows[i].step) ++j;
+        std::sort(rows.begin() + i, rows.begin() + j,
+                  [](const Row& u, const Row& v) { return u.a < v.a; });
+        i = j;
+      }
+    } else {
+      std::sort(rows.begin(), rows.end(), [](const Row& u, const Row& v) {
+        return u.step != v.step ? u.step < v.step : u.a < v.a;
+      });
+    }
     std::memcpy(out, rows.data(), (size_t)m * sizeof(Row));
   }
   *n = total;
@@ -755,7 +809,9 @@ int pr_sys_stats(pr_sys* s, pr_stats* out, int64_t cap, int64_t* n) {
   if (m > 0) {
     const size_t row = (size_t)s->d.ngroups * kPart;
     std::vector<int32_t> p((size_t)m * row);
-    HIP_TRY(hipMemcpy(p.data(), s->d.part, p.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpyAsync(p.data(), s->d.part, p.size() * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
     for (int64_t k = 0; k < m; ++k) {
       long long h[kPart] = {0, 0, 0, 0, 0, 0, 0, 0};
       for (int g = 0; g < s->d.ngroups; ++g)
@@ -1025,7 +1081,7 @@ using Clock = std::chrono::steady_clock;
 struct SrvReq {
   uint64_t ticket = 0;
   pr_replica_desc desc{};
-  uint32_t n_steps = 0, done_steps = 0;
+  uint32_t n_steps = 0, done_steps = 0, round_steps = 0;
   double sigma = 0.0;
   int64_t bytes = 0;
   Clock::time_point t_submit, t_done;
@@ -1046,7 +1102,8 @@ struct pr_server {
   int dev = 0;
   int64_t budget = 0, used = 0;
   int32_t max_slots = 1;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;    // rounds
+  hipStream_t iostream = nullptr;  // admission (generation) and result copies
   bool own_stream = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::mutex mu;
@@ -1057,7 +1114,7 @@ struct pr_server {
   uint64_t next_ticket = 1;
   bool stop = false;
   int64_t rounds = 0, n_done = 0, n_failed = 0;
-  double busy_s = 0.0;
+  double busy_s = 0.0, admit_s = 0.0, finish_s = 0.0, launch_s = 0.0, wait_s = 0.0;
   std::thread worker;
   // batched launch state of the active set
   Arena maps;
@@ -1067,13 +1124,32 @@ struct pr_server {
   size_t ds_cap = 0;
   std::vector<Dev> hds;
   bool set_changed = true;
+  // what the server lends its systems: a stream-ordered device pool that
+  // keeps up to the budget mapped, and pinned control words (never freed
+  // while the server lives: freeing pinned memory waits for the device)
+  hipMemPool_t pool = nullptr;
+  std::vector<Ctl*> ctl_chunks, ctl_free;
 };
 
 namespace {
 
 // The worker's results copy of a finished replica, then its device memory
 // freed.  Returns the error code (0 = done).
-int srv_finish(SrvReq* r) {
+// A pinned control word from the server's pool (worker thread).
+Ctl* srv_ctl(pr_server* S) {
+  if (S->ctl_free.empty()) {
+    const int chunk = 64;
+    Ctl* c = nullptr;
+    if (hipHostMalloc((void**)&c, sizeof(Ctl) * chunk) != hipSuccess) return nullptr;
+    S->ctl_chunks.push_back(c);
+    for (int i = chunk - 1; i >= 0; --i) S->ctl_free.push_back(c + i);
+  }
+  Ctl* c = S->ctl_free.back();
+  S->ctl_free.pop_back();
+  return c;
+}
+
+int srv_finish(pr_server* S, SrvReq* r) {
   pr_sys* s = r->sys;
   const size_t n = (size_t)r->desc.n, B = (size_t)r->desc.B;
   int64_t nb = 0;
@@ -1100,7 +1176,9 @@ int srv_finish(SrvReq* r) {
       r->stats.resize((size_t)ns);
     }
   }
+  Ctl* c = s->hctl;
   pr_sys_destroy(s);
+  S->ctl_free.push_back(c);
   r->sys = nullptr;
   return e;
 }
@@ -1109,11 +1187,15 @@ int srv_finish(SrvReq* r) {
 int srv_admit(pr_server* S, SrvReq* r) {
   const pr_replica_desc& q = r->desc;
   pr_sys* s = nullptr;
-  int e = pr_sys_create(&s, q.n, q.L, q.B, &q.rule, q.seed, q.log_cap, S->stream);
+  SysLease lease;
+  lease.pool = S->pool;
+  if (!(lease.hctl = srv_ctl(S))) return fail(PR_ENOMEM, "hipHostMalloc failed");
+  int e = sys_create(&s, q.n, q.L, q.B, &q.rule, q.seed, q.log_cap, S->iostream, &lease);
   if (!e) e = pr_sys_generate(s, q.gen_kind, q.gen_seed, q.gen_sigma0);
   if (!e) e = grow_part(s, std::max<int64_t>(1024, r->n_steps));
   if (e) {
     if (s) pr_sys_destroy(s);
+    S->ctl_free.push_back(lease.hctl);
     return e;
   }
   s->d.jit_c = (float)(r->sigma / std::sqrt(21845.0));
@@ -1121,14 +1203,15 @@ int srv_admit(pr_server* S, SrvReq* r) {
   return PR_OK;
 }
 
-// One round: every active replica takes min(64, steps left) steps in the
-// batched launches.  Returns an error code (the round's replicas fail).
-int srv_round(pr_server* S) {
+// Launches one round on the server's stream: every active replica takes
+// min(64, steps left) steps in the batched launches.  Asynchronous; the
+// round's end is S->ev1.
+int srv_launch_round(pr_server* S) {
   const int32_t Kmax = 64;
-  std::vector<pr_sys*> sys;
-  for (SrvReq* r : S->active) sys.push_back(r->sys);
   int e;
   if (S->set_changed) {
+    std::vector<pr_sys*> sys;
+    for (SrvReq* r : S->active) sys.push_back(r->sys);
     S->maps.release();
     S->maps.bytes = 0;
     if ((e = fill_maps(sys, S->maps, S->bl))) return e;
@@ -1140,9 +1223,9 @@ int srv_round(pr_server* S) {
     S->bl.ds = S->ds;
     S->set_changed = false;
   }
-  S->hds.resize(sys.size());
+  S->hds.resize(S->active.size());
   int32_t K = 0;
-  for (size_t i = 0; i < sys.size(); ++i) {
+  for (size_t i = 0; i < S->active.size(); ++i) {
     SrvReq* r = S->active[i];
     pr_sys* s = r->sys;
     const int32_t kl = (int32_t)std::min<uint32_t>((uint32_t)Kmax, r->n_steps - r->done_steps);
@@ -1151,6 +1234,7 @@ int srv_round(pr_server* S) {
     S->hds[i] = s->d;
     S->hds[i].k_limit = kl;
     S->hds[i].first_step = 1u + r->done_steps;
+    r->round_steps = (uint32_t)kl;
     K = std::max(K, kl);
   }
   hipStream_t st = S->stream;
@@ -1160,85 +1244,138 @@ int srv_round(pr_server* S) {
   HIP_TRY(launch_ctl_b(S->bl, 0, 0u, st));
   if ((e = run_block_b(S->bl, st, K))) return e;
   HIP_TRY(hipEventRecord(S->ev1, st));
+  return PR_OK;
+}
+
+// Waits for the launched round and books its steps.
+int srv_end_round(pr_server* S) {
   HIP_TRY(hipEventSynchronize(S->ev1));
   float ms = 0.0f;
   HIP_TRY(hipEventElapsedTime(&ms, S->ev0, S->ev1));
   S->busy_s += ms * 1e-3;
   S->rounds++;
-  for (size_t i = 0; i < sys.size(); ++i) {
-    SrvReq* r = S->active[i];
-    const uint32_t kl = (uint32_t)S->hds[i].k_limit;
-    r->done_steps += kl;
+  for (SrvReq* r : S->active) {
+    r->done_steps += r->round_steps;
     drop_graph(r->sys);
-    r->sys->steps_since_sort = (int64_t)kl;
-    r->sys->steps_since_load += kl;
+    r->sys->steps_since_sort = (int64_t)r->round_steps;
+    r->sys->steps_since_load += r->round_steps;
   }
   return PR_OK;
 }
 
+// Takes requests off the queue while a slot and their footprint are free.
+std::vector<SrvReq*> srv_take(pr_server* S, size_t resident) {
+  std::vector<SrvReq*> adm;
+  std::lock_guard<std::mutex> lk(S->mu);
+  while (!S->queue.empty()) {  // arrival order: the head waits until it fits
+    SrvReq* r = S->queue.front();
+    if ((int32_t)(resident + adm.size()) >= S->max_slots || S->used + r->bytes > S->budget) break;
+    S->queue.pop_front();
+    S->used += r->bytes;
+    r->status = 1;
+    adm.push_back(r);
+  }
+  return adm;
+}
+
+void srv_fail(pr_server* S, SrvReq* r, int e) {
+  if (r->sys) {
+    pr_sys_destroy(r->sys);
+    r->sys = nullptr;
+  }
+  std::lock_guard<std::mutex> lk(S->mu);
+  r->t_done = Clock::now();
+  r->status = 3;
+  r->code = e;
+  S->used -= r->bytes;
+  S->n_failed++;
+}
+
+// The worker: round r + 1 is launched as soon as round r has ended; while it
+// runs, the requests that finished in round r are copied out and freed and
+// new requests are admitted (their generation runs on the I/O stream), to
+// join round r + 2.
 void srv_loop(pr_server* S) {
   (void)hipSetDevice(S->dev);
+  std::vector<SrvReq*> incoming, finished;
+  bool in_flight = false;
   for (;;) {
-    std::vector<SrvReq*> adm;
     {
       std::unique_lock<std::mutex> lk(S->mu);
-      S->cv_work.wait(lk, [&] { return S->stop || !S->queue.empty() || !S->active.empty(); });
+      S->cv_work.wait(lk, [&] {
+        return S->stop || !S->queue.empty() || !S->active.empty() || !incoming.empty() ||
+               !finished.empty() || in_flight;
+      });
       if (S->stop) break;
-      // admission in arrival order: the head waits until it fits
-      while (!S->queue.empty()) {
-        SrvReq* r = S->queue.front();
-        if ((int32_t)(S->active.size() + adm.size()) >= S->max_slots ||
-            S->used + r->bytes > S->budget)
-          break;
-        S->queue.pop_front();
-        S->used += r->bytes;
-        r->status = 1;
-        adm.push_back(r);
-      }
     }
-    for (SrvReq* r : adm) {
-      const int e = srv_admit(S, r);
-      std::lock_guard<std::mutex> lk(S->mu);
-      if (e) {
-        r->status = 3;
-        r->code = e;
-        r->t_done = Clock::now();
-        S->used -= r->bytes;
-        S->n_failed++;
-        S->cv_done.notify_all();
-      } else {
-        S->active.push_back(r);
-        S->set_changed = true;
-      }
-    }
-    if (S->active.empty()) continue;
-    const int e = srv_round(S);
-    std::vector<SrvReq*> fin, keep;
-    for (SrvReq* r : S->active) {
-      if (e || r->done_steps >= r->n_steps) fin.push_back(r);
-      else keep.push_back(r);
-    }
-    for (SrvReq* r : fin) {
-      const int fe = e ? e : srv_finish(r);
-      if (e && r->sys) {
-        pr_sys_destroy(r->sys);
-        r->sys = nullptr;
+    // the round in flight ends; finished replicas leave, admitted ones join
+    if (in_flight) {
+      const auto t0 = Clock::now();
+      const int e = srv_end_round(S);
+      S->wait_s += std::chrono::duration<double>(Clock::now() - t0).count();
+      in_flight = false;
+      std::vector<SrvReq*> keep;
+      for (SrvReq* r : S->active) {
+        if (e) srv_fail(S, r, e);
+        else if (r->done_steps >= r->n_steps) finished.push_back(r);
+        else keep.push_back(r);
       }
       std::lock_guard<std::mutex> lk(S->mu);
-      r->t_done = Clock::now();
-      r->status = fe ? 3 : 2;
-      r->code = fe;
-      S->used -= r->bytes;
-      if (fe) S->n_failed++;
-      else S->n_done++;
-    }
-    {
-      std::lock_guard<std::mutex> lk(S->mu);
-      if (!fin.empty()) S->set_changed = true;
+      if (keep.size() != S->active.size()) S->set_changed = true;
       S->active.swap(keep);
     }
-    if (!fin.empty()) S->cv_done.notify_all();
+    if (!incoming.empty()) {
+      std::lock_guard<std::mutex> lk(S->mu);
+      for (SrvReq* r : incoming) S->active.push_back(r);
+      incoming.clear();
+      S->set_changed = true;
+    }
+    if (!S->active.empty()) {
+      const auto t0 = Clock::now();
+      const int e = srv_launch_round(S);
+      S->launch_s += std::chrono::duration<double>(Clock::now() - t0).count();
+      if (e) {
+        for (SrvReq* r : S->active) srv_fail(S, r, e);
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->active.clear();
+        S->set_changed = true;
+      } else {
+        in_flight = true;
+      }
+    }
+    // while the round runs: results out, memory back, new requests in
+    if (!finished.empty()) {
+      const auto t0 = Clock::now();
+      for (SrvReq* r : finished) {
+        const int fe = srv_finish(S, r);
+        std::lock_guard<std::mutex> lk(S->mu);
+        r->t_done = Clock::now();
+        r->status = fe ? 3 : 2;
+        r->code = fe;
+        S->used -= r->bytes;
+        if (fe) S->n_failed++;
+        else S->n_done++;
+      }
+      finished.clear();
+      S->finish_s += std::chrono::duration<double>(Clock::now() - t0).count();
+      S->cv_done.notify_all();
+    }
+    for (SrvReq* r : srv_take(S, S->active.size() + incoming.size())) {
+      const auto t0 = Clock::now();
+      const int e = srv_admit(S, r);
+      S->admit_s += std::chrono::duration<double>(Clock::now() - t0).count();
+      if (e) {
+        srv_fail(S, r, e);
+        S->cv_done.notify_all();
+      } else {
+        incoming.push_back(r);
+      }
+    }
   }
+  if (in_flight) (void)hipEventSynchronize(S->ev1);
+  std::lock_guard<std::mutex> lk(S->mu);  // the destroyer frees what is still resident
+  for (SrvReq* r : incoming) S->active.push_back(r);
+  for (SrvReq* r : finished) S->active.push_back(r);
 }
 
 SrvReq* srv_find(pr_server* S, uint64_t t) {
@@ -1261,11 +1398,23 @@ int pr_server_create(pr_server** out, int64_t hbm_budget, int32_t max_slots, voi
   S->stream = (hipStream_t)stream;
   if (hipGetDevice(&S->dev) != hipSuccess ||
       (!S->stream && hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess) ||
+      hipStreamCreateWithFlags(&S->iostream, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreate(&S->ev0) != hipSuccess || hipEventCreate(&S->ev1) != hipSuccess) {
     delete S;
     return fail(PR_EHIP, "hipGetDevice/hipStreamCreate/hipEventCreate failed");
   }
   S->own_stream = stream == nullptr;
+  hipMemPoolProps props{};
+  props.allocType = hipMemAllocationTypePinned;
+  props.location.type = hipMemLocationTypeDevice;
+  props.location.id = S->dev;
+  if (hipMemPoolCreate(&S->pool, &props) != hipSuccess) {
+    S->pool = nullptr;
+    pr_server_destroy(S);
+    return fail(PR_EHIP, "hipMemPoolCreate failed");
+  }
+  uint64_t keep = (uint64_t)hbm_budget;
+  (void)hipMemPoolSetAttribute(S->pool, hipMemPoolAttrReleaseThreshold, &keep);
   S->worker = std::thread(srv_loop, S);
   *out = S;
   return PR_OK;
@@ -1283,9 +1432,15 @@ void pr_server_destroy(pr_server* S) {
     if (r->sys) pr_sys_destroy(r->sys);
   for (auto& kv : S->all) delete kv.second;
   (void)hipStreamSynchronize(S->stream);
+  S->maps.release();
+  S->dsa.release();
+  if (S->iostream) (void)hipStreamSynchronize(S->iostream);
+  if (S->pool) (void)hipMemPoolDestroy(S->pool);
+  for (Ctl* c : S->ctl_chunks) (void)hipHostFree(c);
   if (S->ev0) (void)hipEventDestroy(S->ev0);
   if (S->ev1) (void)hipEventDestroy(S->ev1);
   if (S->own_stream) (void)hipStreamDestroy(S->stream);
+  if (S->iostream) (void)hipStreamDestroy(S->iostream);
   delete S;
 }
 
@@ -1413,6 +1568,10 @@ int pr_server_info_get(pr_server* S, pr_server_info* out) {
   out->failed = S->n_failed;
   out->rounds = S->rounds;
   out->busy_s = S->busy_s;
+  out->admit_s = S->admit_s;
+  out->finish_s = S->finish_s;
+  out->launch_s = S->launch_s;
+  out->wait_s = S->wait_s;
   return PR_OK;
 }
 
