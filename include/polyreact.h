@@ -92,7 +92,8 @@ const char* pr_version(void);
 /* bonds (device, 2*cap int32): (id_A, id_T) pairs in increasing id_A order; */
 /* cap >= n/2 is required (at most one bond per particle).  n_bonds (host)   */
 /* receives the count; st (host, may be NULL) the counters.                  */
-/* Errors: PR_EINVAL (n < 0, B < 1, rc <= 0, L <= 2 rc, p outside [0,1], or a */
+/* Errors: PR_EINVAL (n < 0 or n > 2^30, B < 1, rc <= 0, L <= 2 rc, p outside */
+/* [0,1], or a                                                              */
 /* position that is NaN or outside [0, L) -- detected on the device before   */
 /* any write), PR_ERULE_AMBIGUOUS, PR_ECAP (cap < n/2: nothing written; or    */
 /* an adjacency row was full: the step is complete except for the missing     */
@@ -108,8 +109,8 @@ int pr_react_step(int32_t n, float L, const float* x, const float* y, const floa
 /* ------------------------------------------------------------------------ */
 typedef struct pr_sys pr_sys;
 
-/* Creates a system of n particles in the cube [0, L)^3 with adjacency width
- * B, reaction rule and draw seed.  log_cap: capacity of the device bond log
+/* Creates a system of n particles (1 <= n <= 2^30) in the cube [0, L)^3 with
+ * adjacency width B, reaction rule and draw seed.  log_cap: capacity of the device bond log
  * in bonds (0 = n).  The handle owns all its device memory; stream (may be
  * NULL) is the stream every later call on the handle uses. */
 int pr_sys_create(pr_sys** out, int32_t n, float L, int32_t B, const pr_rule* rule,

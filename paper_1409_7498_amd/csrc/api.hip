@@ -231,7 +231,7 @@ int pr_react_step(int32_t n, float L, const float* x, const float* y, const floa
                   const int32_t* type, int32_t* state, int32_t* adj, int32_t B,
                   const pr_rule* rule, uint64_t seed, uint32_t step, int32_t* bonds,
                   int32_t cap, int32_t* n_bonds, pr_stats* st, void* stream) {
-  if (n < 0 || B < 1) return fail(PR_EINVAL, "n=%d B=%d", n, B);
+  if (n < 0 || n > kMaxParticles || B < 1) return fail(PR_EINVAL, "n=%d B=%d", n, B);
   int e = validate_rule(rule, L);
   if (e) return e;
   if (!n_bonds) return fail(PR_EINVAL, "n_bonds is NULL");
@@ -525,7 +525,8 @@ extern "C" {
 
 int pr_footprint(const pr_replica_desc* r, uint32_t n_steps, int64_t* bytes) {
   if (!r || !bytes) return fail(PR_EINVAL, "NULL argument");
-  if (r->n < 1 || r->B < 1) return fail(PR_EINVAL, "n=%d B=%d", r->n, r->B);
+  if (r->n < 1 || r->n > kMaxParticles || r->B < 1)
+    return fail(PR_EINVAL, "n=%d B=%d", r->n, r->B);
   int e = validate_rule(&r->rule, r->L);
   if (e) return e;
   Dev d{};
@@ -558,7 +559,7 @@ int sys_create(pr_sys** out, int32_t n, float L, int32_t B, const pr_rule* rule,
                int64_t log_cap, void* stream, const SysLease* lease) {
   if (!out) return fail(PR_EINVAL, "out is NULL");
   *out = nullptr;
-  if (n < 1 || B < 1) return fail(PR_EINVAL, "n=%d B=%d", n, B);
+  if (n < 1 || n > kMaxParticles || B < 1) return fail(PR_EINVAL, "n=%d B=%d", n, B);
   int e = validate_rule(rule, L);
   if (e) return e;
   pr_sys* s = new pr_sys();

@@ -58,6 +58,9 @@ __device__ __forceinline__ W4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
     c3 = lo0;
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
+    // the round keys are bumped on the scalar unit each round rather than
+    // precomputed: twenty live key registers would spill to vector lanes
+    asm volatile("" : "+s"(k0), "+s"(k1));
   }
   return W4{c0, c1, c2, c3};
 }
@@ -489,6 +492,22 @@ __device__ __forceinline__ void lo_hi(float v, float inv_w, int nc, int& c0, int
   if (nc == 1) c0 = c1 = 0;
 }
 
+// floor(v) as an integer in one instruction (v is a finite coordinate in
+// cell units, far inside the int range): identical to (int)floorf(v)
+__device__ __forceinline__ int floor_int(float v) {
+  int r;
+  asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(v));
+  return r;
+}
+
+// Local coordinate, in a staged region whose first cell is `base`, of the
+// lower cell floor(u - 1/2) of a particle's 2x2x2 block (u = v / width; the
+// cell index, in [-1, nc - 1], is taken mod nc): in [0, nc - 1].
+__device__ __forceinline__ int local_lo(float v, float inv_w, int base, int nc) {
+  const int l = floor_int(__fsub_rn(__fmul_rn(v, inv_w), 0.5f)) - base;
+  return l < 0 ? l + nc : l;
+}
+
 __device__ __forceinline__ float dist2(const Dev& d, float xj, float yj, float zj, float4 a) {
   const float dx = min_image(__fsub_rn(xj, a.x), d.L, d.halfL);
   const float dy = min_image(__fsub_rn(yj, a.y), d.L, d.halfL);
@@ -635,15 +654,21 @@ struct Part {
   float x, y, z;
 };
 
+// Sorted storage always carries the id array; the unsorted mode may run on
+// caller arrays without one (the slot is the id).
+template <bool kBrick>
 __device__ __forceinline__ Part load_part(const Arr& a, const float* X, const float* Y,
                                           const float* Z, int slot, int s1) {
   Part q{kRoleNone, 0, 0.0f, 0.0f, 0.0f};
   if (slot < s1) {
-    q.role = a.role[slot];
-    q.x = X[slot];
-    q.y = Y[slot];
-    q.z = Z[slot];
-    q.id = a.id ? a.id[slot] : slot;
+    // 32-bit byte offsets (n < 2^30): the loads take the array base from
+    // scalar registers and need no 64-bit address arithmetic
+    const uint32_t bo = (uint32_t)slot * 4u;
+    q.role = a.role[(uint32_t)slot];
+    q.x = *(const float*)((const char*)X + bo);
+    q.y = *(const float*)((const char*)Y + bo);
+    q.z = *(const float*)((const char*)Z + bo);
+    q.id = kBrick || a.id ? *(const int32_t*)((const char*)a.id + bo) : slot;
   }
   return q;
 }
@@ -678,13 +703,14 @@ template <bool kBrick>
 __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) {
   constexpr int kPer = kBrick ? kTPass / kThreads : 1;
   constexpr int kTP = kPer * kThreads;
-  constexpr uint32_t kNoRec = 0xFFFFu;
+  constexpr uint32_t kQEmpty = 0xFFFFFFFFu;
   __shared__ float4 s_rec[kBrick ? kStageRecs : 1];
   __shared__ int4 s_radj[kBrick ? kStageRecs : 1];
   __shared__ int32_t s_rsa[kBrick ? kStageRecs : 1];
   __shared__ uint32_t s_off[kBrick ? kStageCells + 1 : 1];
   __shared__ int32_t s_cid[kBrick ? kStageCells : 1];
-  __shared__ int4 s_q[kBrick ? kQueue : 1];  // (id_A, slot_A, id_T, local T | record << 16)
+  __shared__ uint32_t s_q[kBrick ? kQueue : 1];  // queued pair: local T | staged record << 16
+  __shared__ int32_t s_tid[kBrick ? kTP : 1];    // ids of the pass's T's
   __shared__ uint16_t s_def[kTP];            // deferred T's (local index in the pass)
   __shared__ int4 s_ent[kRetCap];
   __shared__ uint32_t s_ew2[kRetCap];
@@ -713,7 +739,7 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
   int s0, s1;
   range_of<kBrick>(d, w, s0, s1);
   // the first particle of the first pass, issued before the staging round trips
-  Part cur = load_part(a, X, Y, Z, s0 + tid, s1);
+  Part cur = load_part<kBrick>(a, X, Y, Z, s0 + tid, s1);
   // clear the bucket counts of the next step's parity
   for (int q = w * kThreads + tid; q < d.ncell; q += nwg * kThreads)
     pick(d.cnt, par ^ 1u)[q] = 0u;
@@ -765,41 +791,49 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
   }
   __syncthreads();
   const bool dead = s_dead != 0;
+  // the workgroup-uniform switches of the pass loop, one scalar register
+  // whose bits are tested where they are used (kept as separate booleans
+  // they would each occupy a 64-bit lane mask)
+  constexpr uint32_t kFJit = 1u, kFMove = 2u, kFStaged = 4u, kFNowrap = 8u;
+  const uint32_t flags0 = (uint32_t)__builtin_amdgcn_readfirstlane(
+      (jit ? kFJit : 0u) | (d.jitter ? kFMove : 0u) | (staged ? kFStaged : 0u) |
+      (nowrap ? kFNowrap : 0u));
   SweepAcc n = {0, 0, 0, 0};
   for (int base = s0; base < s1 && !dead; base += kTP) {
-    if (base != s0) cur = load_part(a, X, Y, Z, base + tid, s1);
+    if (base != s0) cur = load_part<kBrick>(a, X, Y, Z, base + tid, s1);
 #pragma unroll 1
     for (int u = 0; u < kPer; ++u) {
       const int lt = u * kThreads + tid;
       const int slot = base + lt;
+      uint32_t fl = flags0;
+      asm volatile("" : "+s"(fl));
       // the next particle's loads are in flight while this one is handled
       Part nxt = cur;
-      if (u + 1 < kPer) nxt = load_part(a, X, Y, Z, slot + kThreads, s1);
+      if (u + 1 < kPer) nxt = load_part<kBrick>(a, X, Y, Z, slot + kThreads, s1);
       const uint32_t idj = (uint32_t)cur.id;
-      if (slot < s1 && d.jitter) {  // the re-jitter (stand-in for the MD between steps)
-        if (jit) rejitter(d, step, idj, cur.x, cur.y, cur.z);
-        XW[slot] = cur.x;
-        YW[slot] = cur.y;
-        ZW[slot] = cur.z;
+      if (slot < s1 && (fl & kFMove)) {  // the re-jitter (stand-in for the MD between steps)
+        if (fl & kFJit) rejitter(d, step, idj, cur.x, cur.y, cur.z);
+        const uint32_t bo = (uint32_t)slot * 4u;  // 32-bit byte offsets: scalar-base stores
+        *(float*)((char*)XW + bo) = cur.x;
+        *(float*)((char*)YW + bo) = cur.y;
+        *(float*)((char*)ZW + bo) = cur.z;
       }
+      // in-range staged records of this T: up to four, one byte each
       int nh = 0;
-      uint32_t h0 = 0, h1 = 0, h2 = 0;
+      uint32_t hits = 0;
       bool defer = false;
       if (slot < s1 && cur.role == kRoleT) {
         n.t_elig++;
         defer = true;
-        if (kBrick && staged) {
+        if (kBrick && (fl & kFStaged)) {
+          if (kBrick) s_tid[lt] = (int)idj;
           const float px = cur.x, py = cur.y, pz = cur.z;
-          int cx0, cx1, cy0, cy1, cz0, cz1;
-          lo_hi(px, d.inv_w, nc, cx0, cx1);
-          lo_hi(py, d.inv_w, nc, cy0, cy1);
-          lo_hi(pz, d.inv_w, nc, cz0, cz1);
-          const int lx0 = local_of(cx0, bx, nc), ly0 = local_of(cy0, by, nc),
-                    lz0 = local_of(cz0, bz, nc);
-          const int lx1 = local_of(cx1, bx, nc), ly1 = local_of(cy1, by, nc),
-                    lz1 = local_of(cz1, bz, nc);
-          if (lx1 == lx0 + 1 && ly1 == ly0 + 1 && lz1 == lz0 + 1 && lx1 < ex && ly1 < ey &&
-              lz1 < ez) {
+          // local coordinates (in the staged region) of the lower corner of
+          // the T's 2x2x2 cell block: floor(u - 1/2) - base, taken mod nc
+          const int lx0 = local_lo(px, d.inv_w, bx, nc), ly0 = local_lo(py, d.inv_w, by, nc),
+                    lz0 = local_lo(pz, d.inv_w, bz, nc);
+          if ((uint32_t)lx0 < (uint32_t)(ex - 1) && (uint32_t)ly0 < (uint32_t)(ey - 1) &&
+              (uint32_t)lz0 < (uint32_t)(ez - 1)) {
             // runs (dy, dz) = (0,0), (1,0), (0,1), (1,1): cells lx0 and lx0 + 1
             const int l0 = (lz0 * ey + ly0) * ex + lx0;
             const int l1 = l0 + ex, l2 = l0 + ex * ey, l3 = l2 + ex;
@@ -810,49 +844,54 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
             const int p3 = p2 + (int)s_off[l2 + 2] - b2;
             const int tot = p3 + (int)s_off[l3 + 2] - b3;
             const int o1 = b1 - p1, o2 = b2 - p2, o3 = b3 - p3;
-            bool full = false;
-            if (nowrap) {  // no difference can reach L/2 in this region
-              for (int q = 0; q < tot && !full; ++q) {
+            bool over = false;
+            if (fl & kFNowrap) {  // no difference can reach L/2 in this region
+              for (int q = 0; q < tot; ++q) {
                 const int r = q + (q < p1 ? b0 : (q < p2 ? o1 : (q < p3 ? o2 : o3)));
-                if (dist2_plain(px, py, pz, s_rec[r]) < d.rc2)
-                  full = !hold_hit(r, lt, nh, h0, h1, h2);
+                if (dist2_plain(px, py, pz, s_rec[r]) < d.rc2) {
+                  over |= nh == 4;
+                  hits |= (uint32_t)r << (8 * (nh & 3));
+                  nh++;
+                }
               }
             } else {
-              for (int q = 0; q < tot && !full; ++q) {
+              for (int q = 0; q < tot; ++q) {
                 const int r = q + (q < p1 ? b0 : (q < p2 ? o1 : (q < p3 ? o2 : o3)));
-                if (dist2(d, px, py, pz, s_rec[r]) < d.rc2)
-                  full = !hold_hit(r, lt, nh, h0, h1, h2);
+                if (dist2(d, px, py, pz, s_rec[r]) < d.rc2) {
+                  over |= nh == 4;
+                  hits |= (uint32_t)r << (8 * (nh & 3));
+                  nh++;
+                }
               }
             }
-            defer = full;
+            defer = over;
           }
         }
       }
       if (defer) nh = 0;
       if (kBrick) {
         // queue slots for the wavefront's held pairs: lane j's pairs go after
-        // those of the lower lanes (counts from three ballots)
+        // those of the lower lanes (counts from four ballots)
         const unsigned long long g1 = __ballot(nh >= 1), g2 = __ballot(nh >= 2),
-                                 g3 = __ballot(nh >= 3);
-        const uint32_t wtot = (uint32_t)(__popcll(g1) + __popcll(g2) + __popcll(g3));
+                                 g3 = __ballot(nh >= 3), g4 = __ballot(nh >= 4);
+        const uint32_t wtot =
+            (uint32_t)(__popcll(g1) + __popcll(g2) + __popcll(g3) + __popcll(g4));
         if (wtot) {
           uint32_t qb = 0;
           if (__lane_id() == 0) qb = (uint32_t)atomicAdd(&s_qn, (int)wtot);
           qb = (uint32_t)__builtin_amdgcn_readlane((int)qb, 0);
-          const uint32_t p = qb + lanes_below(g1) + lanes_below(g2) + lanes_below(g3);
+          const uint32_t p =
+              qb + lanes_below(g1) + lanes_below(g2) + lanes_below(g3) + lanes_below(g4);
           if (nh > 0) {
             if (p + (uint32_t)nh <= (uint32_t)kQueue) {
               n.in_rc += nh;
-              for (int j = 0; j < nh; ++j) {
-                const uint32_t hw = j == 0 ? h0 : (j == 1 ? h1 : h2);
-                const uint32_t r = hw >> 16;
-                s_q[p + j] = make_int4(__float_as_int(s_rec[r].w), s_rsa[r], (int)idj, (int)hw);
-              }
+              for (int j = 0; j < nh; ++j)
+                s_q[p + j] = (uint32_t)lt | (((hits >> (8 * j)) & 0xFFu) << 16);
             } else {
               // the pairs do not all fit: the T is deferred and the slots it
               // reserved below kQueue are marked empty
               for (int j = 0; j < nh; ++j)
-                if (p + j < (uint32_t)kQueue) s_q[p + j] = make_int4(-1, 0, 0, 0);
+                if (p + j < (uint32_t)kQueue) s_q[p + j] = kQEmpty;
               defer = true;
             }
           }
@@ -866,11 +905,11 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
       // the pass's queued pairs: draws on full wavefronts
       const int qn = min(s_qn, kQueue);
       for (int e = tid; e < qn; e += kThreads) {
-        const int4 q = s_q[e];
-        if (q.x < 0) continue;
-        const uint32_t lt = (uint32_t)q.w & 0xFFFFu, r = (uint32_t)q.w >> 16;
-        retain(d, a, step, q.x, q.y, (uint32_t)q.z, base + (int)lt,
-               r != kNoRec && d.adj_staged ? &s_radj[r] : nullptr, n, rl);
+        const uint32_t q = s_q[e];
+        if (q == kQEmpty) continue;
+        const uint32_t lt = q & 0xFFFFu, r = q >> 16;
+        retain(d, a, step, __float_as_int(s_rec[r].w), s_rsa[r], (uint32_t)s_tid[lt],
+               base + (int)lt, d.adj_staged ? &s_radj[r] : nullptr, n, rl);
       }
     }
     // the deferred T's, in the global buckets (cells 0-7 of the block, then
