@@ -29,6 +29,7 @@ constexpr int kAdjStage = 4;        // adjacency rows up to this width travel wi
 // records of the brick plus one halo cell layer in LDS.
 constexpr int kMaxBrick = 4;
 constexpr int kStageCells = (kMaxBrick + 2) * (kMaxBrick + 2) * (kMaxBrick + 2);
+static_assert(kStageCells <= kThreads, "the sweep stages one region cell per thread");
 constexpr int kStageRecs = 256;
 constexpr int kTPass = 768;         // particles a sweep workgroup holds per pass (3 per thread)
 constexpr int kQueue = 512;
@@ -106,6 +107,7 @@ struct Dev {
   // geometry, rule, draws
   int32_t n, B, nc, ncell, nwg_sweep, nwg_prep, ngroups;
   int32_t bs, nb, nbricks, sorted;  // brick edge (cells), bricks per side, total, storage sorted
+  uint32_t nb_m;                     // floor(2^32 / nb): brick coordinates by multiplication
   int32_t jitter;       // 1: resident system (positions ping-pong, re-jitter by jit_c)
                         // 0: caller's arrays, read only
   int32_t adj_staged;   // B <= kAdjStage: records carry the adjacency row

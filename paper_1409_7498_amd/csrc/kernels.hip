@@ -568,6 +568,25 @@ __device__ __forceinline__ void region_dim(const Dev& d, int bc, int& base, int&
   }
 }
 
+// q = w / nb and r = w mod nb for a brick index: a high multiply by
+// floor(2^32 / nb) is below the quotient by at most one.
+__device__ __forceinline__ int div_nb(const Dev& d, int w, int& r) {
+  uint32_t q = __umulhi((uint32_t)w, d.nb_m);
+  int rr = w - (int)q * d.nb;
+  if (rr >= d.nb) {
+    q++;
+    rr -= d.nb;
+  }
+  r = rr;
+  return (int)q;
+}
+
+// x / d for the small operands of a staged region (x < 1024, d <= 64) as
+// (x * m) >> 16 with m = ceil(2^16 / d): exact there, and two instructions
+// instead of an integer division.
+__device__ __forceinline__ uint32_t recip16(uint32_t d) { return (65536u + d - 1u) / d; }
+__device__ __forceinline__ int div_small(int x, uint32_t m) { return (int)(((uint32_t)x * m) >> 16); }
+
 __device__ __forceinline__ int local_of(int c, int base, int nc) {
   const int l = c - base;
   return l < 0 ? l + nc : l;
@@ -709,6 +728,7 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
   __shared__ int32_t s_rsa[kBrick ? kStageRecs : 1];
   __shared__ uint32_t s_off[kBrick ? kStageCells + 1 : 1];
   __shared__ int32_t s_cid[kBrick ? kStageCells : 1];
+  __shared__ uint8_t s_rcell[kBrick ? kStageRecs : 1];  // staged record -> region cell
   __shared__ uint32_t s_q[kBrick ? kQueue : 1];  // queued pair: local T | staged record << 16
   __shared__ int32_t s_tid[kBrick ? kTP : 1];    // ids of the pass's T's
   __shared__ uint16_t s_def[kTP];            // deferred T's (local index in the pass)
@@ -738,28 +758,26 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
   const RetList rl{&s_ne, s_ent, s_ew2};
   int s0, s1;
   range_of<kBrick>(d, w, s0, s1);
-  // the first particle of the first pass, issued before the staging round trips
-  Part cur = load_part<kBrick>(a, X, Y, Z, s0 + tid, s1);
-  // clear the bucket counts of the next step's parity
-  for (int q = w * kThreads + tid; q < d.ncell; q += nwg * kThreads)
-    pick(d.cnt, par ^ 1u)[q] = 0u;
   int bx = 0, ex = 0, by = 0, ey = 0, bz = 0, ez = 0;
   bool staged = false, nowrap = false;
   const int nc = d.nc;
+  int ncs = 0;
+  uint32_t mine = 0;
   if (kBrick) {
-    const int nb = d.nb;
-    region_dim(d, w % nb, bx, ex);
-    region_dim(d, (w / nb) % nb, by, ey);
-    region_dim(d, w / (nb * nb), bz, ez);
+    int bxc, byc;
+    const int bzc = div_nb(d, div_nb(d, w, bxc), byc);
+    region_dim(d, bxc, bx, ex);
+    region_dim(d, byc, by, ey);
+    region_dim(d, bzc, bz, ez);
     // a region that does not wrap around the box and spans less than half of
     // it: a difference of two positions in it is below L/2 in magnitude, and
     // the minimum image leaves it unchanged
     nowrap = d.nbricks > 1 && bx + ex <= nc && by + ey <= nc && bz + ez <= nc &&
              2 * ex + 1 <= nc && 2 * ey + 1 <= nc && 2 * ez + 1 <= nc;
-    const int ncs = ex * ey * ez;
-    uint32_t mine = 0;
-    if (tid < ncs) {
-      const int lx = tid % ex, ly = (tid / ex) % ey, lz = tid / (ex * ey);
+    ncs = ex * ey * ez;
+    if (tid < ncs) {  // the record count of this thread's region cell, issued first
+      const int lz = div_small(tid, recip16((uint32_t)(ex * ey))), rem = tid - lz * ex * ey;
+      const int ly = div_small(rem, recip16((uint32_t)ex)), lx = rem - ly * ex;
       int cx = bx + lx, cy = by + ly, cz = bz + lz;
       cx -= cx >= nc ? nc : 0;
       cy -= cy >= nc ? nc : 0;
@@ -767,22 +785,25 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
       const int myc = (cz * nc + cy) * nc + cx;
       s_cid[tid] = myc;
       mine = pick(d.cnt, par)[myc];
-      mine = mine < (uint32_t)kCellCap ? mine : (uint32_t)kCellCap;
     }
+  }
+  // the first particle of the first pass, issued behind the record counts
+  // (memory operations complete in issue order)
+  Part cur = load_part<kBrick>(a, X, Y, Z, s0 + tid, s1);
+  if (kBrick) {
+    mine = mine < (uint32_t)kCellCap ? mine : (uint32_t)kCellCap;
     uint32_t total = 0;
     const uint32_t off = block_scan_excl(mine, s_wave, total);
-    if (tid < ncs) s_off[tid] = off;
+    if (tid < ncs) {
+      s_off[tid] = off;
+      for (uint32_t j = 0; j < mine && off + j < (uint32_t)kStageRecs; ++j)
+        s_rcell[off + j] = (uint8_t)tid;
+    }
     if (tid == 0) s_off[ncs] = total;
     staged = total <= (uint32_t)kStageRecs && novf == 0;
     __syncthreads();
     if (staged && tid < (int)total) {
-      // the cell of record tid: s_off[lo] <= tid < s_off[lo + 1]
-      int lo = 0, hi = ncs;
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (s_off[mid] <= (uint32_t)tid) lo = mid;
-        else hi = mid;
-      }
+      const int lo = s_rcell[tid];  // the region cell of record tid
       const size_t ri = (size_t)s_cid[lo] * kCellCap + (tid - (int)s_off[lo]);
       s_rec[tid] = d.rec[ri];
       s_rsa[tid] = d.rsa[ri];
@@ -959,6 +980,10 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
     }
     __syncthreads();
   }
+  // clear the bucket counts of the next step's parity (no workgroup of this
+  // step reads them)
+  for (int q = w * kThreads + tid; q < d.ncell; q += nwg * kThreads)
+    pick(d.cnt, par ^ 1u)[q] = 0u;
   wave_add(&s_cnt[kOutTElig], n.t_elig);
   wave_add(&s_cnt[kOutInRc], n.in_rc);
   wave_add(&s_cnt[kOutDrawn], n.drawn);
