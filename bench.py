@@ -77,11 +77,39 @@ def cpu_baseline(cfg):
                       "steps 1-9) of the %d-particle workload: %.1f s wall" % (cfg.N, dt)}
 
 
+def tune_bricks(binding, descs, steps, sigma, target_wgs=4096, max_copies=256):
+    """Brick edge per replica from the device autotuner, one tuning per class
+    of equal coarse grids (the edges a box allows depend on its cells per
+    side).  Each class is timed as one of enough identical replicas of a
+    batch to fill the GPU (about target_wgs sweep workgroups at the default
+    edge), the context of a replica in a full ensemble."""
+    import math
+    from paper_1409_7498_amd import workload
+    by_nc = {}
+    for k, d in enumerate(descs):
+        nc = int(math.floor(float(d["L"]) / (2.0 * workload.RC * (1.0 + 1.0 / 1024.0))))
+        by_nc.setdefault(nc, []).append(k)
+    choice, table = {}, {}
+    for nc, ks in sorted(by_nc.items()):
+        rep = descs[ks[len(ks) // 2]]
+        bs = max(1, min(4, nc - 2))
+        nb = -(-nc // bs) if nc > 2 else 1
+        copies = int(min(max_copies, max(1, -(-target_wgs // nb ** 3))))
+        best, us = binding.autotune(rep, steps, sigma, copies=copies)
+        table[nc] = {"brick": best, "us_per_replica_step": {b: round(t, 3) for b, t in us.items()},
+                     "replicas": len(ks), "copies": copies}
+        for k in ks:
+            choice[k] = best
+    return [dict(d, brick=choice[k]) for k, d in enumerate(descs)], table
+
+
 def bench_batch(args):
     """Batched ensemble (256 replicas of uneven size, 500 steps): replicas/s of
     the batched launch against the plain per-replica launch loop, at identical
     results (bond-log and state digests compared).  Each timed region is the
-    whole run of a freshly generated ensemble (graph capture included)."""
+    whole run of a freshly generated ensemble (graph capture included).  The
+    brick edge of each replica comes from the device autotuner (untimed set-up,
+    reported as autotune_s); the batch at the default edge is timed too."""
     import numpy as np
     import torch
     from paper_1409_7498_amd import binding, workload
@@ -100,18 +128,24 @@ def bench_batch(args):
             h.update(bt.read(r)["state"].tobytes())
         return h.hexdigest()[:16]
 
+    t0 = time.perf_counter()
+    tuned, table = tune_bricks(binding, descs, 64, workload.SIGMA_JITTER)
+    torch.cuda.synchronize()
+    tune_s = time.perf_counter() - t0
+    log("autotune: %.2f s, %s" % (tune_s, {nc: v["brick"] for nc, v in table.items()}))
     out = {}
-    for mode in ("batched", "loop"):
-        bt = binding.Batch(descs, stream=stream)
+    for mode, reps_ in (("batched", tuned), ("batched_default", descs), ("loop", descs)):
+        bt = binding.Batch(reps_, stream=stream)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        (bt.run if mode == "batched" else bt.run_loop)(1, steps, workload.SIGMA_JITTER)
+        (bt.run_loop if mode == "loop" else bt.run)(1, steps, workload.SIGMA_JITTER)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         out[mode] = (dt, digest(bt))
         log("%s: %.3f s" % (mode, dt))
         bt.close()
-    assert out["batched"][1] == out["loop"][1], "batched and loop results differ"
+    assert out["batched"][1] == out["loop"][1] == out["batched_default"][1], \
+        "batched, default-brick and loop results differ"
     n_tot = sum(c.N for c in reps)
     res = {
         "metric": "replicas/s (batched ensemble: 256 uneven replicas)",
@@ -130,6 +164,9 @@ def bench_batch(args):
                                "alternating step/chain growth, p in [0.001, 0.02], %d steps each"
                                % (n_tot, steps)},
         "loop_replicas_per_s": len(reps) / out["loop"][0],
+        "default_brick_replicas_per_s": len(reps) / out["batched_default"][0],
+        "autotune_s": tune_s,
+        "autotune": {str(nc): v for nc, v in table.items()},
         "speedup_vs_loop": out["loop"][0] / out["batched"][0],
         "particle_steps_per_s": n_tot * steps / out["batched"][0],
         "results_digest": out["batched"][1],

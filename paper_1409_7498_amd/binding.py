@@ -41,7 +41,7 @@ class Rule(C.Structure):
 class ReplicaDesc(C.Structure):
     _fields_ = [("n", C.c_int32), ("L", C.c_float), ("B", C.c_int32), ("rule", Rule),
                 ("seed", C.c_uint64), ("gen_kind", C.c_int32), ("gen_seed", C.c_uint64),
-                ("gen_sigma0", C.c_double), ("log_cap", C.c_int64)]
+                ("gen_sigma0", C.c_double), ("log_cap", C.c_int64), ("brick", C.c_int32)]
 
 
 class ServerInfo(C.Structure):
@@ -77,6 +77,8 @@ def _load():
         "pr_react_step": ([i32, f32, vp, vp, vp, vp, vp, vp, i32, P(Rule), u64, u32, vp, i32,
                            P(i32), P(Stats), vp], C.c_int),
         "pr_sys_create": ([P(vp), i32, f32, i32, P(Rule), u64, i64, vp], C.c_int),
+        "pr_sys_create_ex": ([P(vp), i32, f32, i32, P(Rule), u64, i64, vp, i32], C.c_int),
+        "pr_sys_geometry": ([vp, P(i32), P(i32), P(i32)], C.c_int),
         "pr_sys_destroy": ([vp], None),
         "pr_sys_load": ([vp, vp, vp, vp, vp, vp, vp, i32], C.c_int),
         "pr_sys_generate": ([vp, i32, u64, f64], C.c_int),
@@ -95,6 +97,7 @@ def _load():
         "pr_batch_read": ([vp, i32, vp, vp, vp, vp, vp, i32], C.c_int),
         "pr_batch_stats": ([vp, i32, P(Stats), i64, P(i64)], C.c_int),
         "pr_footprint": ([P(ReplicaDesc), u32, P(i64)], C.c_int),
+        "pr_autotune": ([P(ReplicaDesc), u32, f64, i32, vp, P(i32), P(f32)], C.c_int),
         "pr_server_create": ([P(vp), i64, i32, vp], C.c_int),
         "pr_server_destroy": ([vp], None),
         "pr_server_submit": ([vp, P(ReplicaDesc), u32, f64, P(u64)], C.c_int),
@@ -117,6 +120,7 @@ lib = _load()
 
 def exported_symbols():
     return [n for n in ("pr_last_error", "pr_version", "pr_react_step", "pr_sys_create",
+                        "pr_sys_create_ex", "pr_sys_geometry", "pr_autotune",
                         "pr_sys_destroy", "pr_sys_load", "pr_sys_generate", "pr_sys_run",
                         "pr_sys_run_timed", "pr_sys_read", "pr_sys_bonds", "pr_sys_stats",
                         "pr_sys_set_sort_period", "pr_sys_set_graphs", "pr_batch_create",
@@ -171,12 +175,19 @@ def react_step(x, y, z, type_, state, adj, L, rule, seed, step, bonds=None, stre
 class System:
     """Resident particle system (pr_sys_* entry points)."""
 
-    def __init__(self, n, L, B, rule, seed, log_cap=0, stream=None):
+    def __init__(self, n, L, B, rule, seed, log_cap=0, stream=None, brick=0):
+        """brick: brick edge in coarse cells (1..4, 0 = 4), a tuning choice only."""
         self._h = C.c_void_p()
         r = rule if isinstance(rule, Rule) else Rule.make(rule)
         self.n, self.L, self.B = int(n), float(np.float32(L)), int(B)
-        _check(lib.pr_sys_create(C.byref(self._h), self.n, C.c_float(L), self.B, C.byref(r),
-                                 C.c_uint64(seed), int(log_cap), _stream(stream)))
+        _check(lib.pr_sys_create_ex(C.byref(self._h), self.n, C.c_float(L), self.B, C.byref(r),
+                                    C.c_uint64(seed), int(log_cap), _stream(stream), int(brick)))
+
+    def geometry(self):
+        """(coarse cells per side, effective brick edge, bricks)."""
+        v = [C.c_int32(0) for _ in range(3)]
+        _check(lib.pr_sys_geometry(self._h, *[C.byref(x) for x in v]))
+        return tuple(x.value for x in v)
 
     def close(self):
         if self._h:
@@ -244,11 +255,25 @@ class System:
 
 
 def replica_desc(r):
-    """ReplicaDesc from a dict: n, L, B, rule, seed, kind, gen_seed, sigma0, log_cap."""
+    """ReplicaDesc from a dict: n, L, B, rule, seed, kind, gen_seed, sigma0, log_cap
+    and optionally brick (0 = 4)."""
     rule = r["rule"] if isinstance(r["rule"], Rule) else Rule.make(r["rule"])
     return ReplicaDesc(int(r["n"]), float(np.float32(r["L"])), int(r["B"]), rule, int(r["seed"]),
                        0 if r["kind"] == "step" else 1, int(r["gen_seed"]),
-                       float(r.get("sigma0", 0.1)), int(r.get("log_cap", 0)))
+                       float(r.get("sigma0", 0.1)), int(r.get("log_cap", 0)),
+                       int(r.get("brick", 0)))
+
+
+def autotune(r, n_steps=128, sigma=0.05, copies=1, stream=None):
+    """Times the replica at every distinct brick edge on the device (pr_autotune),
+    alone (copies = 1) or as one of `copies` identical replicas of a batch.
+    Returns (best edge, {edge: microseconds per replica-step})."""
+    d = replica_desc(r)
+    best = C.c_int32(0)
+    us = (C.c_float * 4)()
+    _check(lib.pr_autotune(C.byref(d), int(n_steps), float(sigma), int(copies), _stream(stream),
+                           C.byref(best), us))
+    return best.value, {b + 1: float(us[b]) for b in range(4) if us[b] >= 0.0}
 
 
 def footprint(r, n_steps):

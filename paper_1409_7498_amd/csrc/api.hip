@@ -528,10 +528,11 @@ int pr_footprint(const pr_replica_desc* r, uint32_t n_steps, int64_t* bytes) {
   if (!r || !bytes) return fail(PR_EINVAL, "NULL argument");
   if (r->n < 1 || r->n > kMaxParticles || r->B < 1)
     return fail(PR_EINVAL, "n=%d B=%d", r->n, r->B);
+  if (r->brick < 0 || r->brick > kMaxBrick) return fail(PR_EINVAL, "brick=%d", r->brick);
   int e = validate_rule(&r->rule, r->L);
   if (e) return e;
   Dev d{};
-  set_geometry(d, r->n, r->L, r->B, &r->rule, r->seed, kMaxBrick);
+  set_geometry(d, r->n, r->L, r->B, &r->rule, r->seed, r->brick > 0 ? r->brick : kMaxBrick);
   Arena A;
   A.dry = true;
   const int64_t log_cap = r->log_cap > 0 ? r->log_cap : r->n;
@@ -557,10 +558,11 @@ struct SysLease {
 };
 
 int sys_create(pr_sys** out, int32_t n, float L, int32_t B, const pr_rule* rule, uint64_t seed,
-               int64_t log_cap, void* stream, const SysLease* lease) {
+               int64_t log_cap, void* stream, int32_t brick, const SysLease* lease) {
   if (!out) return fail(PR_EINVAL, "out is NULL");
   *out = nullptr;
   if (n < 1 || n > kMaxParticles || B < 1) return fail(PR_EINVAL, "n=%d B=%d", n, B);
+  if (brick < 0 || brick > kMaxBrick) return fail(PR_EINVAL, "brick=%d", brick);
   int e = validate_rule(rule, L);
   if (e) return e;
   pr_sys* s = new pr_sys();
@@ -578,7 +580,7 @@ int sys_create(pr_sys** out, int32_t n, float L, int32_t B, const pr_rule* rule,
     return fail(PR_EHIP, "hipGetDevice failed");
   }
   Dev& d = s->d;
-  set_geometry(d, n, L, B, rule, seed, kMaxBrick);
+  set_geometry(d, n, L, B, rule, seed, brick > 0 ? brick : kMaxBrick);
   s->log_cap = log_cap > 0 ? log_cap : n;
   e = alloc_system(s->arena, d, n, B, s->log_cap, s->stream);
   if (!e && !s->hctl && hipHostMalloc((void**)&s->hctl, sizeof(Ctl)) != hipSuccess)
@@ -605,7 +607,21 @@ extern "C" {
 
 int pr_sys_create(pr_sys** out, int32_t n, float L, int32_t B, const pr_rule* rule, uint64_t seed,
                   int64_t log_cap, void* stream) {
-  return sys_create(out, n, L, B, rule, seed, log_cap, stream, nullptr);
+  return sys_create(out, n, L, B, rule, seed, log_cap, stream, 0, nullptr);
+}
+
+int pr_sys_create_ex(pr_sys** out, int32_t n, float L, int32_t B, const pr_rule* rule,
+                     uint64_t seed, int64_t log_cap, void* stream, int32_t brick) {
+  return sys_create(out, n, L, B, rule, seed, log_cap, stream, brick, nullptr);
+}
+
+int pr_sys_geometry(pr_sys* s, int32_t* nc, int32_t* brick, int32_t* nbricks) {
+  int e = check_sys(s, false);
+  if (e) return e;
+  if (nc) *nc = s->d.nc;
+  if (brick) *brick = s->d.bs;
+  if (nbricks) *nbricks = s->d.nbricks;
+  return PR_OK;
 }
 
 void pr_sys_destroy(pr_sys* s) {
@@ -826,6 +842,67 @@ int pr_sys_stats(pr_sys* s, pr_stats* out, int64_t cap, int64_t* n) {
   return PR_OK;
 }
 
+int pr_autotune(const pr_replica_desc* r, uint32_t n_steps, double sigma, int32_t copies,
+                void* stream, int32_t* best, float* us) {
+  if (!r || !best) return fail(PR_EINVAL, "NULL argument");
+  if (n_steps < 1 || copies < 1) return fail(PR_EINVAL, "n_steps=%u copies=%d", n_steps, copies);
+  *best = 0;
+  if (us)
+    for (int b = 0; b < kMaxBrick; ++b) us[b] = -1.0f;
+  int64_t bytes = 0;
+  int e = pr_footprint(r, n_steps + 64, &bytes);  // validates the description
+  if (e) return e;
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess) {
+    for (hipEvent_t v : ev)
+      if (v) (void)hipEventDestroy(v);
+    return fail(PR_EHIP, "hipEventCreate failed");
+  }
+  float best_us = 0.0f;
+  std::vector<int32_t> tried;  // brick counts already timed (clamped requests repeat one)
+  for (int b = 1; b <= kMaxBrick && !e; ++b) {
+    Dev g{};
+    set_geometry(g, r->n, r->L, r->B, &r->rule, r->seed, b);
+    if (std::find(tried.begin(), tried.end(), g.nbricks) != tried.end()) continue;
+    tried.push_back(g.nbricks);
+    // one system, or `copies` identical replicas stepped as one batch; one
+    // untimed block (first sort, graph capture), then n_steps timed
+    pr_replica_desc q = *r;
+    q.brick = b;
+    pr_sys* s = nullptr;
+    pr_batch* bt = nullptr;
+    if (copies == 1) {
+      e = sys_create(&s, q.n, q.L, q.B, &q.rule, q.seed, q.log_cap, stream, b, nullptr);
+      if (!e) e = pr_sys_generate(s, q.gen_kind, q.gen_seed, q.gen_sigma0);
+      if (!e) e = pr_sys_run(s, 1, 64, sigma);
+    } else {
+      std::vector<pr_replica_desc> qs((size_t)copies, q);
+      e = pr_batch_create(&bt, qs.data(), copies, stream);
+      if (!e) e = pr_batch_run(bt, 1, 64, sigma);
+    }
+    float ms = 0.0f;
+    if (!e) {
+      if (hipEventRecord(ev[0], st) != hipSuccess) e = fail(PR_EHIP, "hipEventRecord failed");
+      if (!e) e = s ? pr_sys_run(s, 65, n_steps, sigma) : pr_batch_run(bt, 65, n_steps, sigma);
+      if (!e && (hipEventRecord(ev[1], st) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess ||
+                 hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess))
+        e = fail(PR_EHIP, "timing events failed");
+    }
+    if (s) pr_sys_destroy(s);
+    if (bt) pr_batch_destroy(bt);
+    if (e) break;
+    const float t = ms * 1000.0f / ((float)n_steps * (float)copies);
+    if (us) us[g.bs - 1] = t;
+    if (*best == 0 || t < best_us) {
+      *best = g.bs;
+      best_us = t;
+    }
+  }
+  for (hipEvent_t v : ev) (void)hipEventDestroy(v);
+  return e;
+}
+
 int pr_sys_set_graphs(pr_sys* s, int32_t on) {
   int e = check_sys(s, false);
   if (e) return e;
@@ -963,7 +1040,7 @@ int pr_batch_create(pr_batch** out, const pr_replica_desc* reps, int32_t n_rep, 
   for (int32_t r = 0; r < n_rep && !e; ++r) {
     const pr_replica_desc& q = reps[r];
     pr_sys* s = nullptr;
-    e = pr_sys_create(&s, q.n, q.L, q.B, &q.rule, q.seed, q.log_cap, stream);
+    e = pr_sys_create_ex(&s, q.n, q.L, q.B, &q.rule, q.seed, q.log_cap, stream, q.brick);
     if (!e) {
       b->sys.push_back(s);
       e = pr_sys_generate(s, q.gen_kind, q.gen_seed, q.gen_sigma0);
@@ -1192,7 +1269,7 @@ int srv_admit(pr_server* S, SrvReq* r) {
   SysLease lease;
   lease.pool = S->pool;
   if (!(lease.hctl = srv_ctl(S))) return fail(PR_ENOMEM, "hipHostMalloc failed");
-  int e = sys_create(&s, q.n, q.L, q.B, &q.rule, q.seed, q.log_cap, S->iostream, &lease);
+  int e = sys_create(&s, q.n, q.L, q.B, &q.rule, q.seed, q.log_cap, S->iostream, q.brick, &lease);
   if (!e) e = pr_sys_generate(s, q.gen_kind, q.gen_seed, q.gen_sigma0);
   if (!e) e = grow_part(s, std::max<int64_t>(1024, r->n_steps));
   if (e) {
