@@ -263,8 +263,10 @@ int pr_autotune(const pr_replica_desc* r, uint32_t n_steps, double sigma, int32_
 /* its HBM footprint (pr_footprint) are free, keeps the admitted replicas    */
 /* resident, and advances all of them together, rounds of up to 64 steps in */
 /* the batched launches (each replica takes part in the steps it has left). */
-/* A finished replica's results move to host memory and its device memory  */
-/* is freed at once, so later requests are admitted while others still run.*/
+/* A finished replica is retired by a second thread on its own stream (its  */
+/* results moved to host memory through pinned staging, its device memory  */
+/* freed) while the worker launches the next round, so later requests are  */
+/* admitted while others still run.                                         */
 /* Each result equals the replica run alone (pr_sys_run).                    */
 /* ------------------------------------------------------------------------ */
 typedef struct pr_server pr_server;
@@ -274,13 +276,14 @@ typedef struct pr_server_info {
   int64_t queued, active, done, failed;
   int64_t rounds;                  /* batched rounds launched */
   double busy_s;                   /* GPU time of those rounds (HIP events) */
-  double admit_s, finish_s;        /* worker time creating replicas / moving results out */
+  double admit_s, finish_s;        /* time creating replicas (worker) / retiring them (finisher) */
   double launch_s, wait_s;         /* worker time launching rounds / waiting for their end */
 } pr_server_info;
 
 /* hbm_budget: bytes the admitted replicas may hold together; max_slots:
  * replicas resident at once.  stream: NULL = the server creates its own.
- * Starts the worker thread (on the calling thread's current device). */
+ * Starts the worker and finisher threads (on the calling thread's current
+ * device). */
 int pr_server_create(pr_server** out, int64_t hbm_budget, int32_t max_slots, void* stream);
 /* Stops admitting, lets the worker finish its current round, cancels what
  * is queued, frees everything. */

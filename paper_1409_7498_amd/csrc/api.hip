@@ -773,7 +773,13 @@ int pr_sys_read(pr_sys* s, float* x, float* y, float* z, int32_t* state, int32_t
   return PR_OK;
 }
 
-int pr_sys_bonds(pr_sys* s, int32_t* out, int64_t cap, int64_t* n) {
+}  // extern "C"
+
+namespace {
+
+// The bond log in (step, id_A) order.  pin (may be NULL): pinned host memory
+// of pin_bytes for the device copy (the rows are ordered in place there).
+int sys_bonds(pr_sys* s, int32_t* out, int64_t cap, int64_t* n, void* pin, size_t pin_bytes) {
   int e = check_sys(s, false);
   if (e) return e;
   if (!n || (cap > 0 && !out)) return fail(PR_EINVAL, "NULL output");
@@ -787,34 +793,49 @@ int pr_sys_bonds(pr_sys* s, int32_t* out, int64_t cap, int64_t* n) {
     struct Row {
       int32_t step, a, t;
     };
-    std::vector<Row> rows((size_t)have);
-    HIP_TRY(hipMemcpyAsync(rows.data(), s->d.log, (size_t)have * sizeof(Row),
-                           hipMemcpyDeviceToHost, s->stream));
+    std::vector<Row> vrows;
+    Row* rows = nullptr;
+    if (pin && pin_bytes >= (size_t)have * sizeof(Row)) {
+      rows = (Row*)pin;
+    } else {
+      vrows.resize((size_t)have);
+      rows = vrows.data();
+    }
+    HIP_TRY(hipMemcpyAsync(rows, s->d.log, (size_t)have * sizeof(Row), hipMemcpyDeviceToHost,
+                           s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
     // the rows of one step are appended together, steps in order: sorting
     // each step's run by id_A is enough (else everything is sorted)
+    const size_t nr = (size_t)have;
     bool runs = true;
-    for (size_t i = 1; i < rows.size() && runs; ++i) runs = rows[i - 1].step <= rows[i].step;
+    for (size_t i = 1; i < nr && runs; ++i) runs = rows[i - 1].step <= rows[i].step;
     if (runs) {
-      for (size_t i = 0; i < rows.size();) {
+      for (size_t i = 0; i < nr;) {
         size_t j = i + 1;
-        while (j < rows.size() && rows[j].step == rows[i].step) ++j;
-        std::sort(rows.begin() + i, rows.begin() + j,
-                  [](const Row& u, const Row& v) { return u.a < v.a; });
+        while (j < nr && rows[j].step == rows[i].step) ++j;
+        std::sort(rows + i, rows + j, [](const Row& u, const Row& v) { return u.a < v.a; });
         i = j;
       }
     } else {
-      std::sort(rows.begin(), rows.end(), [](const Row& u, const Row& v) {
+      std::sort(rows, rows + nr, [](const Row& u, const Row& v) {
         return u.step != v.step ? u.step < v.step : u.a < v.a;
       });
     }
-    std::memcpy(out, rows.data(), (size_t)m * sizeof(Row));
+    std::memcpy(out, rows, (size_t)m * sizeof(Row));
   }
   *n = total;
   if (total > s->log_cap)
     return fail(PR_ECAP, "bond log overflowed: %lld > %lld", (long long)total,
                 (long long)s->log_cap);
   return PR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pr_sys_bonds(pr_sys* s, int32_t* out, int64_t cap, int64_t* n) {
+  return sys_bonds(s, out, cap, n, nullptr, 0);
 }
 
 int pr_sys_stats(pr_sys* s, pr_stats* out, int64_t cap, int64_t* n) {
@@ -1208,6 +1229,18 @@ struct pr_server {
   // while the server lives: freeing pinned memory waits for the device)
   hipMemPool_t pool = nullptr;
   std::vector<Ctl*> ctl_chunks, ctl_free;
+  // retirement runs on its own thread and stream: results copied out (into
+  // pinned staging, grown and never shrunk: freeing pinned memory waits for
+  // the device), systems destroyed, memory handed back; the worker meanwhile
+  // launches the next round
+  std::thread finisher;
+  std::deque<SrvReq*> fin_q;
+  std::condition_variable cv_fin;
+  bool fin_stop = false;
+  uint64_t freed = 0;  // retirements so far (the worker waits on it when memory is short)
+  hipStream_t fstream = nullptr;
+  void* stage = nullptr;
+  size_t stage_bytes = 0;
 };
 
 namespace {
@@ -1231,11 +1264,22 @@ Ctl* srv_ctl(pr_server* S) {
 int srv_finish(pr_server* S, SrvReq* r) {
   pr_sys* s = r->sys;
   const size_t n = (size_t)r->desc.n, B = (size_t)r->desc.B;
+  // the device copies land in the pinned staging (DMA at full speed), then
+  // in the request's host arrays
   int64_t nb = 0;
   int e = pr_sys_bonds(s, nullptr, 0, &nb);
+  const size_t need = std::max((size_t)n * (16 + 4 * B), (size_t)std::max<int64_t>(nb, 1) * 12);
+  if (!e && S->stage_bytes < need) {
+    const size_t grow = std::max(need, 2 * S->stage_bytes);
+    if (S->stage) (void)hipHostFree(S->stage);
+    S->stage = nullptr;
+    S->stage_bytes = 0;
+    if (hipHostMalloc(&S->stage, grow) == hipSuccess) S->stage_bytes = grow;
+    else S->stage = nullptr;  // the copies then go to pageable memory
+  }
   if (!e) {
     r->bonds.resize((size_t)std::max<int64_t>(nb, 1) * 3);
-    e = pr_sys_bonds(s, r->bonds.data(), nb, &nb);
+    e = sys_bonds(s, r->bonds.data(), nb, &nb, S->stage, S->stage_bytes);
     r->n_bonds = nb;
   }
   if (!e) {
@@ -1244,7 +1288,21 @@ int srv_finish(pr_server* S, SrvReq* r) {
     r->z.resize(n);
     r->state.resize(n);
     r->adj.resize(n * B);
-    e = pr_sys_read(s, r->x.data(), r->y.data(), r->z.data(), r->state.data(), r->adj.data(), 0);
+    if (S->stage) {
+      float* sx = (float*)S->stage;
+      int32_t* ss = (int32_t*)(sx + 3 * n);
+      int32_t* sa = ss + n;
+      e = pr_sys_read(s, sx, sx + n, sx + 2 * n, ss, sa, 0);
+      if (!e) {
+        std::memcpy(r->x.data(), sx, n * 4);
+        std::memcpy(r->y.data(), sx + n, n * 4);
+        std::memcpy(r->z.data(), sx + 2 * n, n * 4);
+        std::memcpy(r->state.data(), ss, n * 4);
+        std::memcpy(r->adj.data(), sa, n * B * 4);
+      }
+    } else {
+      e = pr_sys_read(s, r->x.data(), r->y.data(), r->z.data(), r->state.data(), r->adj.data(), 0);
+    }
   }
   if (!e) {
     int64_t ns = 0;
@@ -1374,18 +1432,53 @@ void srv_fail(pr_server* S, SrvReq* r, int e) {
 // runs, the requests that finished in round r are copied out and freed and
 // new requests are admitted (their generation runs on the I/O stream), to
 // join round r + 2.
+// The finisher: retires finished replicas in arrival order of completion.
+void fin_loop(pr_server* S) {
+  (void)hipSetDevice(S->dev);
+  for (;;) {
+    SrvReq* r = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv_fin.wait(lk, [&] { return S->fin_stop || !S->fin_q.empty(); });
+      if (S->fin_q.empty()) break;  // stopping, nothing left
+      r = S->fin_q.front();
+      S->fin_q.pop_front();
+    }
+    const auto t0 = Clock::now();
+    r->sys->stream = S->fstream;  // its last round has ended: the copies and frees go here
+    r->sys->arena.astream = S->fstream;
+    const int fe = srv_finish(S, r);
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      r->t_done = Clock::now();
+      r->status = fe ? 3 : 2;
+      r->code = fe;
+      S->used -= r->bytes;
+      S->freed++;
+      if (fe) S->n_failed++;
+      else S->n_done++;
+      S->finish_s += std::chrono::duration<double>(Clock::now() - t0).count();
+    }
+    S->cv_done.notify_all();
+    S->cv_work.notify_all();
+  }
+}
+
 void srv_loop(pr_server* S) {
   (void)hipSetDevice(S->dev);
   std::vector<SrvReq*> incoming, finished;
   bool in_flight = false;
+  bool short_of_memory = false;  // requests wait for memory the finisher returns
+  uint64_t freed_seen = 0;
   for (;;) {
     {
       std::unique_lock<std::mutex> lk(S->mu);
       S->cv_work.wait(lk, [&] {
-        return S->stop || !S->queue.empty() || !S->active.empty() || !incoming.empty() ||
-               !finished.empty() || in_flight;
+        return S->stop || !S->active.empty() || !incoming.empty() || in_flight ||
+               (!S->queue.empty() && (!short_of_memory || S->freed != freed_seen));
       });
       if (S->stop) break;
+      freed_seen = S->freed;
     }
     // the round in flight ends; finished replicas leave, admitted ones join
     if (in_flight) {
@@ -1422,24 +1515,19 @@ void srv_loop(pr_server* S) {
         in_flight = true;
       }
     }
-    // while the round runs: results out, memory back, new requests in
+    // while the round runs: finished replicas to the finisher, new requests in
     if (!finished.empty()) {
-      const auto t0 = Clock::now();
-      for (SrvReq* r : finished) {
-        const int fe = srv_finish(S, r);
-        std::lock_guard<std::mutex> lk(S->mu);
-        r->t_done = Clock::now();
-        r->status = fe ? 3 : 2;
-        r->code = fe;
-        S->used -= r->bytes;
-        if (fe) S->n_failed++;
-        else S->n_done++;
-      }
+      std::lock_guard<std::mutex> lk(S->mu);
+      for (SrvReq* r : finished) S->fin_q.push_back(r);
       finished.clear();
-      S->finish_s += std::chrono::duration<double>(Clock::now() - t0).count();
-      S->cv_done.notify_all();
+      S->cv_fin.notify_one();
     }
-    for (SrvReq* r : srv_take(S, S->active.size() + incoming.size())) {
+    const std::vector<SrvReq*> taken = srv_take(S, S->active.size() + incoming.size());
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      short_of_memory = taken.empty() && !S->queue.empty();
+    }
+    for (SrvReq* r : taken) {
       const auto t0 = Clock::now();
       const int e = srv_admit(S, r);
       S->admit_s += std::chrono::duration<double>(Clock::now() - t0).count();
@@ -1478,6 +1566,7 @@ int pr_server_create(pr_server** out, int64_t hbm_budget, int32_t max_slots, voi
   if (hipGetDevice(&S->dev) != hipSuccess ||
       (!S->stream && hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess) ||
       hipStreamCreateWithFlags(&S->iostream, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&S->fstream, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreate(&S->ev0) != hipSuccess || hipEventCreate(&S->ev1) != hipSuccess) {
     delete S;
     return fail(PR_EHIP, "hipGetDevice/hipStreamCreate/hipEventCreate failed");
@@ -1494,6 +1583,7 @@ int pr_server_create(pr_server** out, int64_t hbm_budget, int32_t max_slots, voi
   }
   uint64_t keep = (uint64_t)hbm_budget;
   (void)hipMemPoolSetAttribute(S->pool, hipMemPoolAttrReleaseThreshold, &keep);
+  S->finisher = std::thread(fin_loop, S);
   S->worker = std::thread(srv_loop, S);
   *out = S;
   return PR_OK;
@@ -1507,6 +1597,12 @@ void pr_server_destroy(pr_server* S) {
   }
   S->cv_work.notify_all();
   if (S->worker.joinable()) S->worker.join();
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->fin_stop = true;  // the finisher drains its queue first
+  }
+  S->cv_fin.notify_all();
+  if (S->finisher.joinable()) S->finisher.join();
   for (SrvReq* r : S->active)
     if (r->sys) pr_sys_destroy(r->sys);
   for (auto& kv : S->all) delete kv.second;
@@ -1514,12 +1610,15 @@ void pr_server_destroy(pr_server* S) {
   S->maps.release();
   S->dsa.release();
   if (S->iostream) (void)hipStreamSynchronize(S->iostream);
+  if (S->fstream) (void)hipStreamSynchronize(S->fstream);
   if (S->pool) (void)hipMemPoolDestroy(S->pool);
   for (Ctl* c : S->ctl_chunks) (void)hipHostFree(c);
+  if (S->stage) (void)hipHostFree(S->stage);
   if (S->ev0) (void)hipEventDestroy(S->ev0);
   if (S->ev1) (void)hipEventDestroy(S->ev1);
   if (S->own_stream) (void)hipStreamDestroy(S->stream);
   if (S->iostream) (void)hipStreamDestroy(S->iostream);
+  if (S->fstream) (void)hipStreamDestroy(S->fstream);
   delete S;
 }
 
