@@ -32,8 +32,8 @@ constexpr int kStageCells = (kMaxBrick + 2) * (kMaxBrick + 2) * (kMaxBrick + 2);
 static_assert(kStageCells <= kThreads, "the sweep stages one region cell per thread");
 constexpr int kStageRecs = 256;
 constexpr int kTPass = 768;         // particles a sweep workgroup holds per pass (3 per thread)
-constexpr int kQueue = 512;
-constexpr int32_t kMaxParticles = 1 << 30;  // byte offsets of 4-byte fields fit in 32 bits         // in-range pairs queued per pass
+constexpr int kQueue = 512;         // in-range pairs queued per pass
+constexpr int32_t kMaxParticles = 1 << 30;  // byte offsets of 4-byte fields fit in 32 bits
 
 enum WgOut { kOutTElig = 0, kOutInRc, kOutDrawn, kOutExcl, kOutRet, kOutProp, kOutBonds, kOutLost };
 
