@@ -124,6 +124,7 @@ void set_geometry(Dev& d, int32_t n, float L, int32_t B, const pr_rule* r, uint6
     d.nb = 1;
   }
   d.nbricks = d.nb * d.nb * d.nb;
+  d.nd = (d.bs + 1) * (d.bs + 1) * (d.bs + 1);
   d.nb_m = (uint32_t)((1ull << 32) / (unsigned long long)d.nb);  // nb >= 1; nb = 1 gives 0
   d.sorted = 0;
   // closing groups cover the larger of the two sweep grids (dense, bricks)
@@ -514,8 +515,12 @@ int alloc_system(Arena& A, Dev& d, int32_t n, int32_t B, int64_t log_cap, hipStr
   if (!e) e = A.alloc(&d.log, (size_t)log_cap * 3);
   if (!e) e = A.alloc(&d.bstart, (size_t)d.nbricks + 1);
   if (!e) e = A.alloc(&d.bcnt, (size_t)d.nbricks);
+  if (!e) e = A.alloc(&d.dcnt, (size_t)d.nbricks * d.nd);
+  if (!e) e = A.alloc(&d.dloc, (size_t)d.nbricks * d.nd);
   if (!e) e = A.alloc(&d.rank, n);
-  if (!e && !A.dry && hipMemsetAsync(d.bcnt, 0, sizeof(uint32_t) * d.nbricks, st) != hipSuccess)
+  if (!e && !A.dry &&
+      (hipMemsetAsync(d.bcnt, 0, sizeof(uint32_t) * d.nbricks, st) != hipSuccess ||
+       hipMemsetAsync(d.dcnt, 0, sizeof(uint32_t) * d.nbricks * d.nd, st) != hipSuccess))
     e = fail(PR_EHIP, "hipMemsetAsync failed");
   return e;
 }
@@ -977,8 +982,10 @@ int check_batch(pr_batch* b, int32_t rep) {
 // the sorted-storage kernels of the batch.
 int fill_maps(const std::vector<pr_sys*>& sys, Arena& arena, BatchLaunch& bl) {
   std::vector<int4> prep0, prepk, sweep, close, part;
+  int n_sortl = 1;
   for (int r = 0; r < (int)sys.size(); ++r) {
     const Dev& d = sys[r]->d;
+    n_sortl = std::max(n_sortl, (d.nbricks + kThreads / 64 - 1) / (kThreads / 64));
     for (int q = 0; q < d.nwg_prep; ++q) prep0.push_back(make_int4(r, q, d.nwg_prep, 0));
     for (int q = 0; q < d.ngroups + d.nwg_prep; ++q)
       prepk.push_back(make_int4(r, q, d.ngroups + d.nwg_prep, 0));
@@ -1008,6 +1015,7 @@ int fill_maps(const std::vector<pr_sys*>& sys, Arena& arena, BatchLaunch& bl) {
   bl.n_sweep = (int)sweep.size();
   bl.n_close = (int)close.size();
   bl.n_part = (int)part.size();
+  bl.n_sortl = n_sortl;
   bl.nrep = (int)sys.size();
   return PR_OK;
 }

@@ -91,9 +91,12 @@ struct Dev {
   int2* wgw[2];         // staged bonds (id_A, id_T), kWinCap per workgroup, by parity
   int2* wov[2];         // staged bonds beyond kWinCap (capacity n/2 + 1 each)
   int32_t* abst[2];     // per prep workgroup: A's binned, by parity
-  // spatial sort
+  // spatial sort: bricks, and within a brick its (bs + 1)^3 "dual cells"
+  // (nd bins per brick): per-bin counts, offsets within the brick, and the
+  // rank of every particle within its bin
   int32_t* bstart;      // nbricks + 1 slot offsets
   uint32_t* bcnt;
+  uint32_t *dcnt, *dloc;
   int32_t* rank;
   // outputs
   int32_t* bonds;       // stateless step: (id_A, id_T) in id_A order
@@ -107,6 +110,7 @@ struct Dev {
   // geometry, rule, draws
   int32_t n, B, nc, ncell, nwg_sweep, nwg_prep, ngroups;
   int32_t bs, nb, nbricks, sorted;  // brick edge (cells), bricks per side, total, storage sorted
+  int32_t nd;                        // sort bins per brick, (bs + 1)^3
   uint32_t nb_m;                     // floor(2^32 / nb): brick coordinates by multiplication
   int32_t jitter;       // 1: resident system (positions ping-pong, re-jitter by jit_c)
                         // 0: caller's arrays, read only
@@ -128,6 +132,7 @@ struct BatchLaunch {
   int nrep;
   const int4 *prep0, *prepk, *sweep, *close, *part;  // prep at k == 0 / k > 0, sweep and
   int n_prep0, n_prepk, n_sweep, n_close, n_part;     // resolve, closing, particle blocks
+  int n_sortl;          // blocks of the per-brick sort scan of the largest replica
 };
 
 }  // namespace pr

@@ -1185,36 +1185,63 @@ __global__ __launch_bounds__(kFinThreads) void k_single_sort(Dev d) {
 // which also rebuilds the A list in brick order.  Results never depend on the
 // storage order; the sort only gives each sweep workgroup a compact region.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int brick_of(const Dev& d, float x, float y, float z) {
-  if (d.nbricks == 1) return 0;
-  const int cx = cell1(__fmul_rn(x, d.inv_w), d.nc) / d.bs;
-  const int cy = cell1(__fmul_rn(y, d.inv_w), d.nc) / d.bs;
-  const int cz = cell1(__fmul_rn(z, d.inv_w), d.nc) / d.bs;
-  return (cz * d.nb + cy) * d.nb + cx;
+// The sort bin of a particle: its brick b and, within it, its dual cell
+// floor(u - 1/2) (u = position / cell width; bs + 1 values per dimension from
+// the brick's first cell - 1).  All T's of one dual cell have the same 2x2x2
+// partner block, so a wavefront of them scans runs of equal length.
+__device__ __forceinline__ int sort_bin(const Dev& d, float x, float y, float z, int& b) {
+  const float ux = __fmul_rn(x, d.inv_w), uy = __fmul_rn(y, d.inv_w), uz = __fmul_rn(z, d.inv_w);
+  const int nc = d.nc, bs = d.bs, e = bs + 1;
+  int bx = 0, by = 0, bz = 0;
+  if (d.nbricks > 1) {
+    bx = cell1(ux, nc) / bs;
+    by = cell1(uy, nc) / bs;
+    bz = cell1(uz, nc) / bs;
+  }
+  b = (bz * d.nb + by) * d.nb + bx;
+  const int lx = min(max((int)floorf(__fsub_rn(ux, 0.5f)) - (bx * bs - 1), 0), bs);
+  const int ly = min(max((int)floorf(__fsub_rn(uy, 0.5f)) - (by * bs - 1), 0), bs);
+  const int lz = min(max((int)floorf(__fsub_rn(uz, 0.5f)) - (bz * bs - 1), 0), bs);
+  return b * d.nd + (lz * e + ly) * e + lx;
 }
 
-// Ranks within bricks; lanes of a wavefront that share a brick take one
-// atomic together (storage is nearly sorted, so a wave spans few bricks).
+// Ranks within sort bins.
 __device__ __forceinline__ void sort_count_body(const Dev& d, int k) {
+  if (k >= d.n) return;
   const Arr a = pick_set(d, d.ctl->set & 1u);
   const uint32_t par = d.ctl->par0;
-  const bool active = k < d.n;
-  int b = -1;
-  if (active) b = brick_of(d, pick(a.x, par)[k], pick(a.y, par)[k], pick(a.z, par)[k]);
-  unsigned long long rem = __ballot(active);
-  while (rem) {
-    const int leader = __ffsll((long long)rem) - 1;
-    const int bl = __shfl(b, leader);
-    const unsigned long long same = __ballot(active && b == bl);
-    uint32_t base = 0;
-    if (__lane_id() == leader) base = atomicAdd(&d.bcnt[bl], (uint32_t)__popcll(same));
-    base = __shfl(base, leader);
-    if (active && b == bl) {
-      const unsigned long long lt = (1ull << __lane_id()) - 1ull;
-      d.rank[k] = (int32_t)(base + __popcll(same & lt));
-    }
-    rem &= ~same;
+  int b;
+  const int bin = sort_bin(d, pick(a.x, par)[k], pick(a.y, par)[k], pick(a.z, par)[k], b);
+  d.rank[k] = (int32_t)atomicAdd(&d.dcnt[bin], 1u);
+}
+
+// Offsets of the bins within brick b (one wavefront, two bins per lane;
+// nd <= 125), the brick's total for the scan over bricks; the counts are
+// cleared for the next sort.
+__device__ __forceinline__ void sort_local_body(const Dev& d, int b) {
+  if (b >= d.nbricks) return;
+  const int lane = __lane_id(), nd = d.nd;
+  uint32_t* c = d.dcnt + (size_t)b * nd;
+  uint32_t* o = d.dloc + (size_t)b * nd;
+  const int j0 = 2 * lane, j1 = j0 + 1;
+  const uint32_t v0 = j0 < nd ? c[j0] : 0u, v1 = j1 < nd ? c[j1] : 0u;
+  uint32_t x = v0 + v1;
+#pragma unroll
+  for (int q = 1; q < 64; q <<= 1) {
+    const uint32_t y = __shfl_up(x, q);
+    if (lane >= q) x += y;
   }
+  const uint32_t ex = x - v0 - v1;
+  if (j0 < nd) {
+    o[j0] = ex;
+    c[j0] = 0u;
+  }
+  if (j1 < nd) {
+    o[j1] = ex + v0;
+    c[j1] = 0u;
+  }
+  const uint32_t total = __shfl(x, 63);
+  if (lane == 0) d.bcnt[b] = total;
 }
 
 __device__ __forceinline__ void sort_scan_body(const Dev& d) {
@@ -1239,8 +1266,9 @@ __device__ __forceinline__ void sort_scatter_body(const Dev& d, int k) {
   const uint32_t s = d.ctl->set & 1u, par = d.ctl->par0;
   const Arr a = pick_set(d, s), o = pick_set(d, s ^ 1u);
   const float x = pick(a.x, par)[k], y = pick(a.y, par)[k], z = pick(a.z, par)[k];
-  const int b = brick_of(d, x, y, z);
-  const int ns = d.bstart[b] + d.rank[k];
+  int b;
+  const int bin = sort_bin(d, x, y, z, b);
+  const int ns = d.bstart[b] + (int)d.dloc[bin] + d.rank[k];
   pick(o.x, par)[ns] = x;
   pick(o.y, par)[ns] = y;
   pick(o.z, par)[ns] = z;
@@ -1274,6 +1302,9 @@ __global__ __launch_bounds__(kThreads) void k_resolve(Dev d, int k) {
 }
 __global__ __launch_bounds__(kThreads) void k_sort_count(Dev d) {
   sort_count_body(d, blockIdx.x * blockDim.x + threadIdx.x);
+}
+__global__ __launch_bounds__(kThreads) void k_sort_local(Dev d) {
+  sort_local_body(d, blockIdx.x * (kThreads / 64) + (int)(threadIdx.x / 64));
 }
 __global__ __launch_bounds__(kFinThreads) void k_sort_scan(Dev d) { sort_scan_body(d); }
 __global__ __launch_bounds__(kThreads) void k_sort_scatter(Dev d) {
@@ -1341,6 +1372,12 @@ __global__ __launch_bounds__(kThreads) void k_sort_count_b(const Dev* __restrict
   const int4 m = uniform_map(map);
   const Dev& d = ds[m.x];
   sort_count_body(d, m.y * kThreads + threadIdx.x);
+}
+// ngrp blocks per replica (the brick groups of the largest one)
+__global__ __launch_bounds__(kThreads) void k_sort_local_b(const Dev* __restrict__ ds, int ngrp) {
+  const int r = __builtin_amdgcn_readfirstlane((int)(blockIdx.x / (unsigned)ngrp));
+  const int g = (int)blockIdx.x - r * ngrp;
+  sort_local_body(ds[r], g * (kThreads / 64) + (int)(threadIdx.x / 64));
 }
 __global__ __launch_bounds__(kFinThreads) void k_sort_scan_b(const Dev* __restrict__ ds) {
   const Dev& d = ds[__builtin_amdgcn_readfirstlane((int)blockIdx.x)];
@@ -1437,6 +1474,7 @@ hipError_t launch_single_end(const Dev& d, hipStream_t s) {
 
 hipError_t launch_sort(const Dev& d, hipStream_t s) {
   k_sort_count<<<blocks_for(d.n, kThreads), kThreads, 0, s>>>(d);
+  k_sort_local<<<blocks_for(d.nbricks, kThreads / 64), kThreads, 0, s>>>(d);
   k_sort_scan<<<1, kFinThreads, 0, s>>>(d);
   k_sort_scatter<<<blocks_for(d.n, kThreads), kThreads, 0, s>>>(d);
   k_sort_flip<<<1, 64, 0, s>>>(d.ctl);
@@ -1468,6 +1506,7 @@ hipError_t launch_block_end_b(const BatchLaunch& b, int K, hipStream_t s) {
 
 hipError_t launch_sort_b(const BatchLaunch& b, hipStream_t s) {
   k_sort_count_b<<<b.n_part, kThreads, 0, s>>>(b.ds, b.part);
+  k_sort_local_b<<<b.n_sortl * b.nrep, kThreads, 0, s>>>(b.ds, b.n_sortl);
   k_sort_scan_b<<<b.nrep, kFinThreads, 0, s>>>(b.ds);
   k_sort_scatter_b<<<b.n_part, kThreads, 0, s>>>(b.ds, b.part);
   return launch_ctl_b(b, 2, 0u, s);
