@@ -51,6 +51,7 @@ extern "C" {
 #define PR_EHIP (-5)            /* a HIP runtime call failed (the handle is unusable) */
 #define PR_EBUSY (-6)           /* serving: request does not fit the memory budget now */
 #define PR_ENOTFOUND (-7)       /* serving: unknown ticket */
+#define PR_ECANCELED (-8)       /* serving: the request was cancelled */
 
 /* One reaction rule, T^t + A^a -> T^(t+d_t)-A^(a+d_a) (Sec. II, Eq. (2)).
  * A particle is eligible for the A role iff type == type_a and
@@ -81,6 +82,23 @@ const char* pr_last_error(void);
 
 /* Library version string. */
 const char* pr_version(void);
+
+/* The per-pair, per-step acceptance probability p = k * dt * Theta of a rate
+ * constant k, an MD time step dt and a reaction interval of Theta MD steps
+ * (Sec. II, Eqs. (3)-(4)); the method assumes p << 1.  *warn (may be NULL)
+ * receives 1 when p > 0.1 (then the single draw per pair and interval is a
+ * coarse stand-in for the rate: two reactive events in one interval are no
+ * longer rare), else 0.  Negative or non-finite inputs return -1.  Host
+ * only. */
+double pr_p_from_rate(double k, double dt, double theta, int32_t* warn);
+
+/* The library's draws: Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11)
+ * of n counters under one key, computed on the device by the same code as
+ * the acceptance test of Eq. (4) (counter (step, id_A, id_T, 0), key = the
+ * system's seed) and the re-jitter.  ctr, out: device arrays of 4 n uint32
+ * (counter words 0-3, output words 0-3; out may equal ctr).  0 <= n <= 2^30
+ * (else PR_EINVAL).  Asynchronous on stream. */
+int pr_draws(const uint32_t* ctr, int64_t n, uint64_t key, uint32_t* out, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* One reaction step on caller-owned device arrays (Table I, steps 1-9).     */
@@ -177,6 +195,24 @@ int pr_sys_bonds(pr_sys* s, int32_t* out, int64_t cap, int64_t* n);
 /* Copies the per-step counters of the steps run since the last load (at most
  * cap records) into host memory; *n receives their number.  Synchronises. */
 int pr_sys_stats(pr_sys* s, pr_stats* out, int64_t cap, int64_t* n);
+
+/* Checkpoint of a resident system into host memory: the configuration in
+ * particle-id order (x, y, z, type, state, adjacency), the bond log and the
+ * per-step counters, with the handle's n, B, L, rule and seed.  *bytes
+ * receives the size needed; buf == NULL only asks for it.  PR_ECAP when cap
+ * is smaller (nothing written) or when the bond log has overflowed its
+ * capacity (a checkpoint would be incomplete).  Synchronises. */
+int pr_sys_checkpoint(pr_sys* s, void* buf, int64_t cap, int64_t* bytes);
+
+/* Restores a checkpoint into a handle created with the same n, B, L, rule
+ * and seed (brick edge, sort period and log capacity may differ).  Runs
+ * continued from it give the bonds, counters and configuration of the
+ * uninterrupted run: the draws depend only on (step, ids) and the seed.
+ * PR_EINVAL for another system's or a malformed checkpoint, PR_ECAP if its
+ * bonds exceed the log capacity (in these cases the handle is unchanged);
+ * PR_EINVAL for a position outside [0, L) (the handle then holds no valid
+ * configuration).  Synchronises. */
+int pr_sys_restore(pr_sys* s, const void* buf, int64_t bytes);
 
 /* Dense-pass tuning of a handle: sort_period = steps between spatial re-sorts
  * of the particle storage (default 64; 0 = never sort).  Results never depend
@@ -301,6 +337,17 @@ int pr_server_submit(pr_server* s, const pr_replica_desc* r, uint32_t n_steps, d
  * not wait.  PR_ENOTFOUND for an unknown or released ticket. */
 int pr_server_wait(pr_server* s, uint64_t ticket, double timeout_s, int32_t* status,
                    int32_t* code, double* latency_s);
+
+/* pr_server_wait without waiting. */
+int pr_server_poll(pr_server* s, uint64_t ticket, int32_t* status, int32_t* code,
+                   double* latency_s);
+
+/* Cancels a request.  A queued one fails at once with code PR_ECANCELED; a
+ * running one is retired, without results, when its current round of steps
+ * ends (then status 3, code PR_ECANCELED).  PR_EBUSY if it has already
+ * finished (its results stand), PR_ENOTFOUND for an unknown ticket.
+ * Thread-safe. */
+int pr_server_cancel(pr_server* s, uint64_t ticket);
 
 /* Results of a finished request (host memory), as pr_sys_bonds, pr_sys_read
  * (on_device = 0) and pr_sys_stats; PR_EBUSY while it is not done. */

@@ -13,8 +13,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpolyreact.so")
 
-PR_OK, PR_EINVAL, PR_ERULE_AMBIGUOUS, PR_ECAP, PR_ENOMEM, PR_EHIP, PR_EBUSY, PR_ENOTFOUND = (
-    0, -1, -2, -3, -4, -5, -6, -7)
+(PR_OK, PR_EINVAL, PR_ERULE_AMBIGUOUS, PR_ECAP, PR_ENOMEM, PR_EHIP, PR_EBUSY, PR_ENOTFOUND,
+ PR_ECANCELED) = (0, -1, -2, -3, -4, -5, -6, -7, -8)
 STATS_FIELDS = ("a_elig", "t_elig", "in_rc", "drawn", "excluded", "accepted", "proposals", "bonds",
                 "adj_overflow")
 
@@ -85,6 +85,12 @@ def _load():
         "pr_sys_run": ([vp, u32, u32, f64], C.c_int),
         "pr_sys_run_timed": ([vp, u32, u32, f64, P(f32)], C.c_int),
         "pr_sys_read": ([vp, vp, vp, vp, vp, vp, i32], C.c_int),
+        "pr_sys_checkpoint": ([vp, vp, i64, P(i64)], C.c_int),
+        "pr_sys_restore": ([vp, vp, i64], C.c_int),
+        "pr_p_from_rate": ([f64, f64, f64, P(i32)], C.c_double),
+        "pr_draws": ([vp, i64, u64, vp, vp], C.c_int),
+        "pr_server_poll": ([vp, u64, P(i32), P(i32), P(f64)], C.c_int),
+        "pr_server_cancel": ([vp, u64], C.c_int),
         "pr_sys_bonds": ([vp, vp, i64, P(i64)], C.c_int),
         "pr_sys_stats": ([vp, P(Stats), i64, P(i64)], C.c_int),
         "pr_sys_set_sort_period": ([vp, i32], C.c_int),
@@ -128,7 +134,9 @@ def exported_symbols():
                         "pr_batch_read", "pr_batch_stats", "pr_footprint", "pr_server_create",
                         "pr_server_destroy", "pr_server_submit", "pr_server_wait",
                         "pr_server_bonds", "pr_server_read", "pr_server_stats",
-                        "pr_server_release", "pr_server_info_get")]
+                        "pr_server_release", "pr_server_info_get", "pr_sys_checkpoint",
+                        "pr_sys_restore", "pr_p_from_rate", "pr_draws", "pr_server_poll",
+                        "pr_server_cancel")]
 
 
 def _check(code):
@@ -246,12 +254,43 @@ class System:
         _check(lib.pr_sys_bonds(self._h, out.ctypes.data_as(C.c_void_p), total, C.byref(n)))
         return out[:total]
 
+    def checkpoint(self):
+        """The system's checkpoint (configuration, bond log, counters) as bytes."""
+        n = C.c_int64(0)
+        _check(lib.pr_sys_checkpoint(self._h, None, 0, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        _check(lib.pr_sys_checkpoint(self._h, buf, n.value, C.byref(n)))
+        return buf.raw
+
+    def restore(self, data):
+        _check(lib.pr_sys_restore(self._h, data, len(data)))
+
     def stats(self):
         n = C.c_int64(0)
         _check(lib.pr_sys_stats(self._h, None, 0, C.byref(n)))
         arr = (Stats * max(n.value, 1))()
         _check(lib.pr_sys_stats(self._h, arr, n.value, C.byref(n)))
         return [arr[k].as_dict() for k in range(n.value)]
+
+
+def p_from_rate(k, dt, theta):
+    """(p, warn): p = k dt Theta and whether it exceeds 0.1; ValueError on bad input."""
+    w = C.c_int32(0)
+    p = lib.pr_p_from_rate(float(k), float(dt), float(theta), C.byref(w))
+    if p < 0.0:
+        raise ValueError("k, dt and theta must be finite and >= 0")
+    return p, bool(w.value)
+
+
+def draws(ctr, key, stream=None):
+    """Device Philox4x32-10 words of counters ctr (int32/uint32 tensor n x 4 on the device)."""
+    import torch
+    assert ctr.is_cuda and ctr.dtype in (torch.int32,) and ctr.dim() == 2 and ctr.shape[1] == 4
+    ctr = ctr.contiguous()
+    out = torch.empty_like(ctr)
+    _check(lib.pr_draws(_ptr(ctr), ctr.shape[0], C.c_uint64(int(key)), _ptr(out),
+                        _stream(stream)))
+    return out
 
 
 def replica_desc(r):
@@ -373,6 +412,15 @@ class Server:
         _check(lib.pr_server_wait(self._h, C.c_uint64(ticket), float(timeout_s), C.byref(st),
                                   C.byref(code), C.byref(lat)))
         return st.value, code.value, lat.value
+
+    def poll(self, ticket):
+        st, code, lat = C.c_int32(0), C.c_int32(0), C.c_double(0)
+        _check(lib.pr_server_poll(self._h, C.c_uint64(ticket), C.byref(st), C.byref(code),
+                                  C.byref(lat)))
+        return st.value, code.value, lat.value
+
+    def cancel(self, ticket):
+        _check(lib.pr_server_cancel(self._h, C.c_uint64(ticket)))
 
     def bonds(self, ticket):
         n = C.c_int64(0)

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -36,8 +37,10 @@ hipError_t launch_step(const Dev& d, int k, hipStream_t s, hipEvent_t ev_sweep0,
 hipError_t launch_block_end(const Dev& d, int K, hipStream_t s);
 hipError_t launch_single_end(const Dev& d, hipStream_t s);
 hipError_t launch_sort(const Dev& d, hipStream_t s);
-hipError_t launch_gather_out(const Dev& d, float* ox, float* oy, float* oz, int32_t* ost,
-                             int32_t* oadj, hipStream_t s);
+hipError_t launch_gather_out(const Dev& d, float* ox, float* oy, float* oz, int32_t* otyp,
+                             int32_t* ost, int32_t* oadj, hipStream_t s);
+hipError_t launch_draws(const uint32_t* ctr, long long n, unsigned long long key, uint32_t* out,
+                        hipStream_t s);
 }  // namespace pr
 
 using namespace pr;
@@ -229,6 +232,23 @@ const char* pr_last_error(void) { return g_err.c_str(); }
 
 const char* pr_version(void) { return "polyreact 0.2 (gfx950)"; }
 
+double pr_p_from_rate(double k, double dt, double theta, int32_t* warn) {
+  if (warn) *warn = 0;
+  if (!(k >= 0.0) || !(dt >= 0.0) || !(theta >= 0.0) || !std::isfinite(k * dt * theta))
+    return -1.0;
+  const double p = k * dt * theta;
+  if (warn && p > 0.1) *warn = 1;
+  return p;
+}
+
+int pr_draws(const uint32_t* ctr, int64_t n, uint64_t key, uint32_t* out, void* stream) {
+  if (n < 0 || n > (int64_t)kMaxParticles) return fail(PR_EINVAL, "n=%lld", (long long)n);
+  if (n == 0) return PR_OK;
+  if (!ctr || !out) return fail(PR_EINVAL, "NULL array");
+  HIP_TRY(launch_draws(ctr, (long long)n, (unsigned long long)key, out, (hipStream_t)stream));
+  return PR_OK;
+}
+
 int pr_react_step(int32_t n, float L, const float* x, const float* y, const float* z,
                   const int32_t* type, int32_t* state, int32_t* adj, int32_t B,
                   const pr_rule* rule, uint64_t seed, uint32_t step, int32_t* bonds,
@@ -358,7 +378,7 @@ struct pr_sys {
   float g_jit = -1.0f;
   long long g_part = 0;
   float *rx = nullptr, *ry = nullptr, *rz = nullptr;  // id-order read buffers
-  int32_t *rst = nullptr, *radj = nullptr;
+  int32_t *rtyp = nullptr, *rst = nullptr, *radj = nullptr;
   Ctl* hctl = nullptr;
   bool own_hctl = true;  // false: the pinned word belongs to a server's pool
   ~pr_sys() {
@@ -749,14 +769,18 @@ int pr_sys_run_timed(pr_sys* s, uint32_t first_step, uint32_t n_steps, double si
   return run_impl(s, first_step, n_steps, sigma, ms);
 }
 
-int pr_sys_read(pr_sys* s, float* x, float* y, float* z, int32_t* state, int32_t* adj,
-                int32_t on_device) {
+namespace {
+
+// The configuration in particle-id order into host or device memory (any
+// pointer may be NULL); synchronises and reports a pending device error.
+int sys_read(pr_sys* s, float* x, float* y, float* z, int32_t* type, int32_t* state,
+             int32_t* adj, int32_t on_device) {
   int e = check_sys(s, false);
   if (e) return e;
   const Dev& d = s->d;
   const size_t n = (size_t)d.n;
   if (on_device) {
-    HIP_TRY(launch_gather_out(d, x, y, z, state, adj, s->stream));
+    HIP_TRY(launch_gather_out(d, x, y, z, type, state, adj, s->stream));
   } else {
     if (!s->rx) {
       if ((e = s->arena.alloc(&s->rx, n)) || (e = s->arena.alloc(&s->ry, n)) ||
@@ -764,18 +788,28 @@ int pr_sys_read(pr_sys* s, float* x, float* y, float* z, int32_t* state, int32_t
           (e = s->arena.alloc(&s->radj, n * d.B)))
         return e;
     }
+    if (type && !s->rtyp && (e = s->arena.alloc(&s->rtyp, n))) return e;
     HIP_TRY(launch_gather_out(d, x ? s->rx : nullptr, y ? s->ry : nullptr, z ? s->rz : nullptr,
-                              state ? s->rst : nullptr, adj ? s->radj : nullptr, s->stream));
+                              type ? s->rtyp : nullptr, state ? s->rst : nullptr,
+                              adj ? s->radj : nullptr, s->stream));
     const hipMemcpyKind k = hipMemcpyDeviceToHost;
     if (x) HIP_TRY(hipMemcpyAsync(x, s->rx, n * 4, k, s->stream));
     if (y) HIP_TRY(hipMemcpyAsync(y, s->ry, n * 4, k, s->stream));
     if (z) HIP_TRY(hipMemcpyAsync(z, s->rz, n * 4, k, s->stream));
+    if (type) HIP_TRY(hipMemcpyAsync(type, s->rtyp, n * 4, k, s->stream));
     if (state) HIP_TRY(hipMemcpyAsync(state, s->rst, n * 4, k, s->stream));
     if (adj) HIP_TRY(hipMemcpyAsync(adj, s->radj, n * 4 * d.B, k, s->stream));
   }
   if ((e = sync_ctl(s))) return e;
   if (s->hctl->err) return fail(s->hctl->err, "device error during the run");
   return PR_OK;
+}
+
+}  // namespace
+
+int pr_sys_read(pr_sys* s, float* x, float* y, float* z, int32_t* state, int32_t* adj,
+                int32_t on_device) {
+  return sys_read(s, x, y, z, nullptr, state, adj, on_device);
 }
 
 }  // extern "C"
@@ -866,6 +900,152 @@ int pr_sys_stats(pr_sys* s, pr_stats* out, int64_t cap, int64_t* n) {
   }
   *n = have;
   return PR_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Layout of a checkpoint: this header, then x, y, z, type, state (n each),
+// adj (n * B), the bond-log rows (3 int32 each) and the per-step counters.
+struct CkHeader {
+  char magic[8];
+  int32_t n, B;
+  float L;
+  int32_t exclude_bonded;
+  uint64_t seed;
+  int32_t type_a, a_min, a_max, d_a, type_t, t_min, t_max, d_t;
+  float rc;
+  int32_t pad;
+  double p;
+  int64_t rows, steps;
+};
+constexpr char kCkMagic[8] = {'P', 'R', 'C', 'K', 'P', 'T', '0', '1'};
+
+int64_t ck_bytes(const Dev& d, int64_t rows, int64_t steps) {
+  return (int64_t)sizeof(CkHeader) + (int64_t)d.n * (5 * 4 + 4 * (int64_t)d.B) + rows * 12 +
+         steps * (int64_t)sizeof(pr_stats);
+}
+
+bool same_rule(const CkHeader& h, const pr_sys* s) {
+  const pr_rule& r = s->rule;
+  return h.n == s->d.n && h.B == s->d.B && h.L == s->d.L && h.seed == s->d.seed &&
+         h.type_a == r.type_a && h.a_min == r.a_min && h.a_max == r.a_max && h.d_a == r.d_a &&
+         h.type_t == r.type_t && h.t_min == r.t_min && h.t_max == r.t_max && h.d_t == r.d_t &&
+         h.rc == r.rc && h.p == r.p && h.exclude_bonded == r.exclude_bonded;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pr_sys_checkpoint(pr_sys* s, void* buf, int64_t cap, int64_t* bytes) {
+  int e = check_sys(s, true);
+  if (e) return e;
+  if (!bytes) return fail(PR_EINVAL, "bytes is NULL");
+  if ((e = sync_ctl(s))) return e;
+  if (s->hctl->err) return fail(s->hctl->err, "device error during the run");
+  const int64_t rows = (int64_t)s->hctl->log_n;
+  if (rows > s->log_cap)
+    return fail(PR_ECAP, "bond log overflowed (%lld > %lld): no complete checkpoint",
+                (long long)rows, (long long)s->log_cap);
+  const int64_t steps = std::min<int64_t>((int64_t)s->hctl->stats_n0, s->part_cap);
+  const Dev& d = s->d;
+  const int64_t need = ck_bytes(d, rows, steps);
+  *bytes = need;
+  if (!buf) return PR_OK;
+  if (cap < need) return fail(PR_ECAP, "checkpoint needs %lld bytes", (long long)need);
+  CkHeader h{};
+  std::memcpy(h.magic, kCkMagic, 8);
+  const pr_rule& r = s->rule;
+  h.n = d.n;
+  h.B = d.B;
+  h.L = d.L;
+  h.exclude_bonded = r.exclude_bonded;
+  h.seed = d.seed;
+  h.type_a = r.type_a;
+  h.a_min = r.a_min;
+  h.a_max = r.a_max;
+  h.d_a = r.d_a;
+  h.type_t = r.type_t;
+  h.t_min = r.t_min;
+  h.t_max = r.t_max;
+  h.d_t = r.d_t;
+  h.rc = r.rc;
+  h.p = r.p;
+  h.rows = rows;
+  h.steps = steps;
+  char* q = (char*)buf;
+  std::memcpy(q, &h, sizeof h);
+  q += sizeof h;
+  const size_t n = (size_t)d.n;
+  float* x = (float*)q;
+  int32_t* typ = (int32_t*)(x + 3 * n);
+  int32_t* st = typ + n;
+  int32_t* adj = st + n;
+  int32_t* log = adj + n * d.B;
+  pr_stats* stats = (pr_stats*)(log + 3 * rows);
+  if ((e = sys_read(s, x, x + n, x + 2 * n, typ, st, adj, 0))) return e;
+  int64_t got = 0;
+  if ((e = sys_bonds(s, log, rows, &got, nullptr, 0))) return e;
+  if ((e = pr_sys_stats(s, stats, steps, &got))) return e;
+  return PR_OK;
+}
+
+int pr_sys_restore(pr_sys* s, const void* buf, int64_t bytes) {
+  int e = check_sys(s, false);
+  if (e) return e;
+  if (!buf || bytes < (int64_t)sizeof(CkHeader)) return fail(PR_EINVAL, "no checkpoint");
+  CkHeader h;
+  std::memcpy(&h, buf, sizeof h);
+  if (std::memcmp(h.magic, kCkMagic, 8) != 0) return fail(PR_EINVAL, "not a checkpoint");
+  if (!same_rule(h, s)) return fail(PR_EINVAL, "checkpoint of another system (n, B, L, rule, seed)");
+  if (h.rows < 0 || h.steps < 0 || bytes != ck_bytes(s->d, h.rows, h.steps))
+    return fail(PR_EINVAL, "malformed checkpoint");
+  if (h.rows > s->log_cap)
+    return fail(PR_ECAP, "checkpoint holds %lld bonds, log capacity %lld", (long long)h.rows,
+                (long long)s->log_cap);
+  const Dev& d0 = s->d;
+  const size_t n = (size_t)d0.n, row = (size_t)d0.ngroups * kPart;
+  const char* q = (const char*)buf + sizeof h;
+  const float* x = (const float*)q;
+  const int32_t* typ = (const int32_t*)(x + 3 * n);
+  const int32_t* st = typ + n;
+  const int32_t* adj = st + n;
+  const int32_t* log = adj + n * d0.B;
+  std::vector<int32_t> part((size_t)h.steps * row, 0);
+  for (int64_t k = 0; k < h.steps; ++k) {
+    pr_stats t;
+    std::memcpy(&t, (const char*)(log + 3 * h.rows) + k * sizeof(pr_stats), sizeof t);
+    // partial layout: a_elig, t_elig, in_rc, drawn, excluded, proposals, bonds, lost
+    const int64_t v[kPart] = {t.a_elig,   t.t_elig,    t.in_rc, t.drawn,
+                              t.excluded, t.proposals, t.bonds, t.adj_overflow};
+    for (int c = 0; c < kPart; ++c) {
+      int64_t left = v[c];
+      if (left < 0) return fail(PR_EINVAL, "malformed checkpoint (negative counter)");
+      for (int g = 0; g < d0.ngroups && left > 0; ++g) {
+        const int64_t put = std::min<int64_t>(left, INT32_MAX);
+        part[(size_t)k * row + (size_t)g * kPart + c] = (int32_t)put;
+        left -= put;
+      }
+      if (left > 0) return fail(PR_EINVAL, "counter too large for the counter log");
+    }
+  }
+  // the configuration (validated on the device), then the logs
+  if ((e = pr_sys_load(s, x, x + n, x + 2 * n, typ, st, adj, 0))) return e;
+  if ((e = grow_part(s, h.steps))) return e;
+  const Dev& d = s->d;
+  if (h.rows > 0)
+    HIP_TRY(hipMemcpyAsync(d.log, log, (size_t)h.rows * 12, hipMemcpyHostToDevice, s->stream));
+  if (h.steps > 0)
+    HIP_TRY(hipMemcpyAsync(d.part, part.data(), part.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, s->stream));
+  const uint32_t n0 = (uint32_t)h.steps;
+  const uint64_t ln = (uint64_t)h.rows;
+  HIP_TRY(hipMemcpyAsync(&d.ctl->stats_n0, &n0, sizeof n0, hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipMemcpyAsync(&d.ctl->log_n, &ln, sizeof ln, hipMemcpyHostToDevice, s->stream));
+  s->steps_since_load = h.steps;
+  return sync_ctl(s);
 }
 
 int pr_autotune(const pr_replica_desc* r, uint32_t n_steps, double sigma, int32_t copies,
@@ -1195,6 +1375,7 @@ struct SrvReq {
   Clock::time_point t_submit, t_done;
   int32_t status = 0;  // 0 queued, 1 running, 2 done, 3 failed
   int32_t code = 0;
+  std::atomic<bool> cancel{false};  // admitted and cancelled: retired at the round's end
   pr_sys* sys = nullptr;
   // results, host memory
   std::vector<int32_t> bonds;
@@ -1495,11 +1676,20 @@ void srv_loop(pr_server* S) {
       S->wait_s += std::chrono::duration<double>(Clock::now() - t0).count();
       in_flight = false;
       std::vector<SrvReq*> keep;
+      bool cancelled = false;
       for (SrvReq* r : S->active) {
-        if (e) srv_fail(S, r, e);
-        else if (r->done_steps >= r->n_steps) finished.push_back(r);
-        else keep.push_back(r);
+        if (e) {
+          srv_fail(S, r, e);
+        } else if (r->done_steps >= r->n_steps) {
+          finished.push_back(r);
+        } else if (r->cancel.load()) {
+          srv_fail(S, r, PR_ECANCELED);
+          cancelled = true;
+        } else {
+          keep.push_back(r);
+        }
       }
+      if (cancelled) S->cv_done.notify_all();
       std::lock_guard<std::mutex> lk(S->mu);
       if (keep.size() != S->active.size()) S->set_changed = true;
       S->active.swap(keep);
@@ -1674,6 +1864,35 @@ int pr_server_wait(pr_server* S, uint64_t ticket, double timeout_s, int32_t* sta
   if (code) *code = q->code;
   if (latency_s)
     *latency_s = q->status >= 2 ? std::chrono::duration<double>(q->t_done - q->t_submit).count() : -1.0;
+  return PR_OK;
+}
+
+int pr_server_poll(pr_server* S, uint64_t ticket, int32_t* status, int32_t* code,
+                   double* latency_s) {
+  return pr_server_wait(S, ticket, 0.0, status, code, latency_s);
+}
+
+int pr_server_cancel(pr_server* S, uint64_t ticket) {
+  if (!S) return fail(PR_EINVAL, "NULL server");
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    SrvReq* q = srv_find(S, ticket);
+    if (!q) return fail(PR_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+    if (q->status >= 2)
+      return fail(PR_EBUSY, "request %llu has already finished", (unsigned long long)ticket);
+    const auto it = std::find(S->queue.begin(), S->queue.end(), q);
+    if (it == S->queue.end()) {  // admitted: the worker retires it after its round
+      q->cancel.store(true);
+      return PR_OK;
+    }
+    S->queue.erase(it);
+    q->status = 3;
+    q->code = PR_ECANCELED;
+    q->t_done = Clock::now();
+    S->n_failed++;
+  }
+  S->cv_done.notify_all();
+  S->cv_work.notify_all();
   return PR_OK;
 }
 

@@ -1392,7 +1392,8 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter_b(const Dev* __restri
 
 // Storage order -> particle-id order (positions of the current parity).
 __global__ __launch_bounds__(kThreads) void k_gather_out(Dev d, float* ox, float* oy, float* oz,
-                                                         int32_t* ost, int32_t* oadj) {
+                                                         int32_t* otyp, int32_t* ost,
+                                                         int32_t* oadj) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= d.n) return;
   const Arr a = pick_set(d, d.ctl->set & 1u);
@@ -1401,9 +1402,20 @@ __global__ __launch_bounds__(kThreads) void k_gather_out(Dev d, float* ox, float
   if (ox) ox[id] = pick(a.x, par)[k];
   if (oy) oy[id] = pick(a.y, par)[k];
   if (oz) oz[id] = pick(a.z, par)[k];
+  if (otyp) otyp[id] = a.typ[k];
   if (ost) ost[id] = a.st[k];
   if (oadj)
     for (int b = 0; b < d.B; ++b) oadj[(size_t)id * d.B + b] = a.adj[(size_t)k * d.B + b];
+}
+
+// The generator's words for caller counters (4 uint32 per counter).
+__global__ __launch_bounds__(kThreads) void k_draws(const uint4* __restrict__ ctr, long long n,
+                                                    unsigned long long key, uint4* out) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint4 c = ctr[i];
+  const W4 w = philox(c.x, c.y, c.z, c.w, key);
+  out[i] = make_uint4(w.w0, w.w1, w.w2, w.w3);
 }
 
 // ---------------------------------------------------------------------------
@@ -1512,9 +1524,15 @@ hipError_t launch_sort_b(const BatchLaunch& b, hipStream_t s) {
   return launch_ctl_b(b, 2, 0u, s);
 }
 
-hipError_t launch_gather_out(const Dev& d, float* ox, float* oy, float* oz, int32_t* ost,
-                             int32_t* oadj, hipStream_t s) {
-  k_gather_out<<<blocks_for(d.n, kThreads), kThreads, 0, s>>>(d, ox, oy, oz, ost, oadj);
+hipError_t launch_gather_out(const Dev& d, float* ox, float* oy, float* oz, int32_t* otyp,
+                             int32_t* ost, int32_t* oadj, hipStream_t s) {
+  k_gather_out<<<blocks_for(d.n, kThreads), kThreads, 0, s>>>(d, ox, oy, oz, otyp, ost, oadj);
+  return hipGetLastError();
+}
+
+hipError_t launch_draws(const uint32_t* ctr, long long n, unsigned long long key, uint32_t* out,
+                        hipStream_t s) {
+  k_draws<<<blocks_for(n, kThreads), kThreads, 0, s>>>((const uint4*)ctr, n, key, (uint4*)out);
   return hipGetLastError();
 }
 

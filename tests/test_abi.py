@@ -97,3 +97,16 @@ def test_footprint_and_brick_validation():
     good = b.replica_desc(d)
     assert b.lib.pr_autotune(ctypes.byref(good), 64, 0.05, 0, None, ctypes.byref(best),
                              None) == b.PR_EINVAL
+
+
+def test_p_from_rate():
+    """p = k dt Theta (Eqs. (3)-(4)), flagged above 0.1; bad inputs refused (host only)."""
+    from paper_1409_7498_amd import binding as b
+    p, warn = b.p_from_rate(0.1, 0.005, 10)
+    assert p == 0.1 * 0.005 * 10 and not warn
+    p, warn = b.p_from_rate(2.0, 0.01, 10)
+    assert abs(p - 0.2) < 1e-15 and warn
+    assert b.p_from_rate(0.0, 0.005, 100) == (0.0, False)
+    for bad in ((-1.0, 0.005, 10), (1.0, float("nan"), 10), (1.0, 1.0, float("inf"))):
+        with pytest.raises(ValueError):
+            b.p_from_rate(*bad)

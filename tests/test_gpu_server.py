@@ -119,3 +119,45 @@ def test_admission_refuses_oversize_and_reports():
         srv.wait(12345)
     assert e.value.code == B.PR_ENOTFOUND
     srv.close()
+
+
+def test_cancel_queued_running_and_finished():
+    """One slot: the first request runs while the others queue.  Cancelling a
+    queued request fails it at once; cancelling the running one retires it at
+    the end of its round; a finished request cannot be cancelled; the rest
+    still equal their runs alone."""
+    from paper_1409_7498_amd import binding as B
+    reqs = _reqs(4, 31, nmin=20000, nmax=30000, steps_max=3)
+    srv = B.Server(1 << 34, 1)
+    long_req = dict(reqs[0][0])
+    t_long = srv.submit(long_req, 3000, 0.05)
+    others = [srv.submit(d, 40, 0.05) for d, _ in reqs[1:]]
+    srv.cancel(others[0])
+    st, code, _ = srv.poll(others[0])
+    assert (st, code) == (3, B.PR_ECANCELED)
+    t0 = time.time()
+    while srv.poll(t_long)[0] == 0 and time.time() - t0 < 60:
+        time.sleep(0.001)
+    assert srv.poll(t_long)[0] == 1
+    srv.cancel(t_long)
+    st, code, _ = srv.wait(t_long, 60.0)
+    assert (st, code) == (3, B.PR_ECANCELED)
+    with pytest.raises(B.PrError) as e:
+        srv.bonds(t_long)
+    assert e.value.code == B.PR_ECANCELED
+    for t in others[1:]:
+        assert srv.wait(t, 120.0)[0] == 2
+    with pytest.raises(B.PrError) as e:
+        srv.cancel(others[1])
+    assert e.value.code == B.PR_EBUSY
+    with pytest.raises(B.PrError) as e:
+        srv.cancel(12345678)
+    assert e.value.code == B.PR_ENOTFOUND
+    for (d, _), t in zip(reqs[2:], others[1:]):
+        want = _alone(B, d, 40, 0.05)
+        assert np.array_equal(srv.bonds(t), want[1])
+        assert srv.stats(t) == want[2]
+    info = srv.info()
+    say("cancel: done", info["done"], "failed", info["failed"], "used", info["used"])
+    assert info["failed"] == 2 and info["used"] == 0
+    srv.close()
