@@ -279,3 +279,40 @@ def test_workspace_box_changes(B):
     for N, seed in ((30000, 41), (2000, 42), (4000, 43), (30000, 44), (500, 45), (9000, 46)):
         cfg = gen(N, workload.box_for(N), "step", seed)
         compare_step(cfg, _rule("step", 1.0), seed, 2, "box N=%d" % N)
+
+
+def test_dense_brick_queue_overflow_and_deferral(B):
+    """One brick packed with four A's per cell (256 records: still staged),
+    the 543 T's in it with about 1000 partners in all (the oracle counts
+    them): one pass queues more pairs than the queue holds, so the surplus
+    T's are deferred with none of their pairs, and 15 T's with more than four
+    partners are deferred as well; the rest of the box has no A."""
+    N = 40000
+    cfg = gen(N, workload.box_for(N), "step", 91)
+    L = cfg["L"]
+    nc = int(np.floor(L / (2 * 1.12 * (1 + 1 / 1024))))
+    w = L / nc
+    rng = np.random.default_rng(91)
+    cfg["type"][:] = 0
+    cfg["state"][:] = 2
+    cells = [(cx, cy, cz) for cz in range(4, 8) for cy in range(4, 8) for cx in range(4, 8)]
+    A = rng.choice(N, 4 * len(cells), replace=False)
+    for q, (cx, cy, cz) in enumerate(np.repeat(np.array(cells), 4, axis=0)):
+        i = A[q]
+        cfg["type"][i], cfg["state"][i] = 1, 4
+        for v, c in (("x", cx), ("y", cy), ("z", cz)):
+            cfg[v][i] = np.float32((c + rng.uniform(0.05, 0.95)) * w)
+    _run_both(cfg, _rule("step", 1.0), 91, 1, 3, 0.05, 64)
+
+
+@pytest.mark.parametrize("frac", [0.12, 0.2])
+def test_a_rich_mixes_staged_and_unstaged_bricks(B, frac):
+    """About 250 A records per brick region at 12% A's: some workgroups stage
+    their region, the others scan every T in the global buckets, in one step."""
+    N = 40000
+    cfg = gen(N, workload.box_for(N), "step", 93)
+    rng = np.random.default_rng(93)
+    pick = rng.random(N) < frac
+    cfg["type"] = pick.astype(np.int32)
+    cfg["state"] = np.where(pick, 4, 2).astype(np.int32)
+    _run_both(cfg, _rule("step", 0.3), 93, 1, 6, 0.05, 3)
