@@ -839,7 +839,8 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
         *(float*)((char*)YW + bo) = cur.y;
         *(float*)((char*)ZW + bo) = cur.z;
       }
-      // in-range staged records of this T: up to four, one byte each
+      // in-range staged records of this T: nh counts them all, hits keeps the
+      // first four, one byte each (a T with more is deferred)
       int nh = 0;
       uint32_t hits = 0;
       bool defer = false;
@@ -870,8 +871,7 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
               for (int q = 0; q < tot; ++q) {
                 const int r = q + (q < p1 ? b0 : (q < p2 ? o1 : (q < p3 ? o2 : o3)));
                 if (dist2_plain(px, py, pz, s_rec[r]) < d.rc2) {
-                  over |= nh == 4;
-                  hits |= (uint32_t)r << (8 * (nh & 3));
+                  hits |= (uint32_t)r << ((8 * nh) & 31);
                   nh++;
                 }
               }
@@ -879,13 +879,12 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
               for (int q = 0; q < tot; ++q) {
                 const int r = q + (q < p1 ? b0 : (q < p2 ? o1 : (q < p3 ? o2 : o3)));
                 if (dist2(d, px, py, pz, s_rec[r]) < d.rc2) {
-                  over |= nh == 4;
-                  hits |= (uint32_t)r << (8 * (nh & 3));
+                  hits |= (uint32_t)r << ((8 * nh) & 31);
                   nh++;
                 }
               }
             }
-            defer = over;
+            defer = nh > 4;
           }
         }
       }
