@@ -292,6 +292,14 @@ int pr_footprint(const pr_replica_desc* r, uint32_t n_steps, int64_t* bytes);
 int pr_autotune(const pr_replica_desc* r, uint32_t n_steps, double sigma, int32_t copies,
                 void* stream, int32_t* best, float* us);
 
+/* pr_autotune with a cache file (host text, one line per tuned geometry: the
+ * coarse cells per side, copies and adjacency width, the choice and the
+ * times).  A hit returns the stored choice and times without running
+ * anything; a miss tunes and appends a line.  cache_path NULL: no cache.
+ * PR_EINVAL if the file cannot be appended to. */
+int pr_autotune_cached(const pr_replica_desc* r, uint32_t n_steps, double sigma, int32_t copies,
+                       void* stream, const char* cache_path, int32_t* best, float* us);
+
 /* ------------------------------------------------------------------------ */
 /* Serving: a request loop with continuous batching.  Requests (a replica   */
 /* description, a number of steps and the re-jitter sigma) queue in arrival */

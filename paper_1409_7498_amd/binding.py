@@ -104,6 +104,8 @@ def _load():
         "pr_batch_stats": ([vp, i32, P(Stats), i64, P(i64)], C.c_int),
         "pr_footprint": ([P(ReplicaDesc), u32, P(i64)], C.c_int),
         "pr_autotune": ([P(ReplicaDesc), u32, f64, i32, vp, P(i32), P(f32)], C.c_int),
+        "pr_autotune_cached": ([P(ReplicaDesc), u32, f64, i32, vp, C.c_char_p, P(i32), P(f32)],
+                               C.c_int),
         "pr_server_create": ([P(vp), i64, i32, vp], C.c_int),
         "pr_server_destroy": ([vp], None),
         "pr_server_submit": ([vp, P(ReplicaDesc), u32, f64, P(u64)], C.c_int),
@@ -136,7 +138,7 @@ def exported_symbols():
                         "pr_server_bonds", "pr_server_read", "pr_server_stats",
                         "pr_server_release", "pr_server_info_get", "pr_sys_checkpoint",
                         "pr_sys_restore", "pr_p_from_rate", "pr_draws", "pr_server_poll",
-                        "pr_server_cancel")]
+                        "pr_server_cancel", "pr_autotune_cached")]
 
 
 def _check(code):
@@ -303,15 +305,20 @@ def replica_desc(r):
                        int(r.get("brick", 0)))
 
 
-def autotune(r, n_steps=128, sigma=0.05, copies=1, stream=None):
+def autotune(r, n_steps=128, sigma=0.05, copies=1, stream=None, cache=None):
     """Times the replica at every distinct brick edge on the device (pr_autotune),
-    alone (copies = 1) or as one of `copies` identical replicas of a batch.
+    alone (copies = 1) or as one of `copies` identical replicas of a batch;
+    with `cache` (a file path) a stored result for the same geometry is reused.
     Returns (best edge, {edge: microseconds per replica-step})."""
     d = replica_desc(r)
     best = C.c_int32(0)
     us = (C.c_float * 4)()
-    _check(lib.pr_autotune(C.byref(d), int(n_steps), float(sigma), int(copies), _stream(stream),
-                           C.byref(best), us))
+    if cache is None:
+        _check(lib.pr_autotune(C.byref(d), int(n_steps), float(sigma), int(copies),
+                               _stream(stream), C.byref(best), us))
+    else:
+        _check(lib.pr_autotune_cached(C.byref(d), int(n_steps), float(sigma), int(copies),
+                                      _stream(stream), os.fsencode(cache), C.byref(best), us))
     return best.value, {b + 1: float(us[b]) for b in range(4) if us[b] >= 0.0}
 
 

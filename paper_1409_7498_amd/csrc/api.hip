@@ -1109,6 +1109,47 @@ int pr_autotune(const pr_replica_desc* r, uint32_t n_steps, double sigma, int32_
   return e;
 }
 
+int pr_autotune_cached(const pr_replica_desc* r, uint32_t n_steps, double sigma, int32_t copies,
+                       void* stream, const char* cache_path, int32_t* best, float* us) {
+  if (!cache_path) return pr_autotune(r, n_steps, sigma, copies, stream, best, us);
+  if (!r || !best) return fail(PR_EINVAL, "NULL argument");
+  if (copies < 1) return fail(PR_EINVAL, "copies=%d", copies);
+  int64_t bytes = 0;
+  int e = pr_footprint(r, n_steps + 64, &bytes);  // validates the description
+  if (e) return e;
+  Dev g{};
+  set_geometry(g, r->n, r->L, r->B, &r->rule, r->seed, kMaxBrick);
+  // one line per tuned geometry: "pr-tune 1 <nc> <copies> <B> <best> <us 1..kMaxBrick>"
+  static_assert(kMaxBrick == 4, "the cache line holds four times");
+  if (FILE* f = std::fopen(cache_path, "r")) {
+    char line[256];
+    while (std::fgets(line, sizeof line, f)) {
+      int ver = 0, nc = 0, cp = 0, bw = 0, b = 0;
+      float t[kMaxBrick] = {-1.0f, -1.0f, -1.0f, -1.0f};
+      if (std::sscanf(line, "pr-tune %d %d %d %d %d %f %f %f %f", &ver, &nc, &cp, &bw, &b, &t[0],
+                      &t[1], &t[2], &t[3]) == 5 + kMaxBrick &&
+          ver == 1 && nc == g.nc && cp == copies && bw == r->B && b >= 1 && b <= kMaxBrick) {
+        std::fclose(f);
+        *best = b;
+        if (us)
+          for (int q = 0; q < kMaxBrick; ++q) us[q] = t[q];
+        return PR_OK;
+      }
+    }
+    std::fclose(f);
+  }
+  float t[kMaxBrick];
+  if ((e = pr_autotune(r, n_steps, sigma, copies, stream, best, t))) return e;
+  if (us)
+    for (int q = 0; q < kMaxBrick; ++q) us[q] = t[q];
+  FILE* f = std::fopen(cache_path, "a");
+  if (!f) return fail(PR_EINVAL, "cannot append to the tuning cache %s", cache_path);
+  std::fprintf(f, "pr-tune 1 %d %d %d %d %.3f %.3f %.3f %.3f\n", g.nc, copies, r->B, *best, t[0],
+               t[1], t[2], t[3]);
+  std::fclose(f);
+  return PR_OK;
+}
+
 int pr_sys_set_graphs(pr_sys* s, int32_t on) {
   int e = check_sys(s, false);
   if (e) return e;

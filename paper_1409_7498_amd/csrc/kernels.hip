@@ -866,7 +866,6 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
             const int p3 = p2 + (int)s_off[l2 + 2] - b2;
             const int tot = p3 + (int)s_off[l3 + 2] - b3;
             const int o1 = b1 - p1, o2 = b2 - p2, o3 = b3 - p3;
-            bool over = false;
             if (fl & kFNowrap) {  // no difference can reach L/2 in this region
               for (int q = 0; q < tot; ++q) {
                 const int r = q + (q < p1 ? b0 : (q < p2 ? o1 : (q < p3 ? o2 : o3)));

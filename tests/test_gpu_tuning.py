@@ -3,6 +3,8 @@ brick^3 coarse cells and the sweep runs one workgroup per brick, but every
 result (bonds, states, adjacency, positions, counters) must be identical for
 every brick edge, alone and in a batch.  The autotuner times the distinct
 edges on the device and returns the fastest."""
+import time
+
 import numpy as np
 import pytest
 
@@ -87,3 +89,22 @@ def test_autotune_and_tuned_batch():
         _, ref = _run(B, d, 100, 0)
         _same((bt.read(r), bt.bonds(r), bt.stats(r)), ref, "replica %d brick %d" % (r, d["brick"]))
     bt.close()
+
+
+def test_autotune_cache(tmp_path):
+    """A miss tunes and appends one line; a hit for the same geometry returns
+    the stored choice and times without timing again; another geometry misses."""
+    from paper_1409_7498_amd import binding as B
+    cache = str(tmp_path / "tune.txt")
+    d = _desc(20000, "step", 0.02, workload.MASTER_SEED + 80)
+    best, us = B.autotune(d, 64, workload.SIGMA_JITTER, cache=cache)
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("pr-tune 1 ")
+    t0 = time.time()
+    best2, us2 = B.autotune(dict(d, seed=d["seed"] + 1), 64, workload.SIGMA_JITTER, cache=cache)
+    assert time.time() - t0 < 0.5
+    assert best2 == best and set(us2) == set(us)
+    assert all(abs(us2[b] - us[b]) < 1e-3 * max(1.0, us[b]) for b in us)
+    B.autotune(_desc(3000, "step", 0.02, workload.MASTER_SEED + 81), 64, workload.SIGMA_JITTER,
+               cache=cache)
+    assert len(open(cache).read().splitlines()) == 2
