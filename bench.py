@@ -12,6 +12,8 @@ bytes per launch (positions read and written, type and state) over its mean
 duration, measured with events stamped at each sweep's own start and end
 (hipExtLaunchKernel) on the system's stream, in a second, directly launched
 run of the next steps.
+``copy_gbs`` is the measured ceiling of a plain device copy (bytes read and
+written per second) and ``frac_of_copy`` the sweep's rate against it.
 ``traffic`` is the sweep's HBM traffic per launch from the profiler
 counters recorded under profiles/ (null when the kernel source changed
 since).  ``cpu_baseline`` times the CPU oracle on one full step of the same
@@ -267,6 +269,25 @@ def bench_serve(args):
     print(json.dumps(res), flush=True)
 
 
+def copy_bandwidth(mib=1024, reps=5):
+    """Measured device copy ceiling in GB/s (bytes read plus written per
+    second): the median of `reps` torch copies of `mib` MiB timed with events."""
+    import torch
+    src = torch.ones(mib << 18, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    times.sort()
+    return 2 * src.numel() * 4 / (times[len(times) // 2] * 1e-3) / 1e9
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -375,6 +396,9 @@ def main():
         "cpu_baseline": None,
     }
     sysm.close()
+    copy = copy_bandwidth()
+    out["roofline"]["copy_gbs"] = copy
+    out["roofline"]["frac_of_copy"] = achieved / copy
     if not args.no_cpu:
         log("timing the CPU oracle on one full step of the workload ...")
         out["cpu_baseline"] = cpu_baseline(cfg)

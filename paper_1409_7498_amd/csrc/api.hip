@@ -318,7 +318,6 @@ int pr_react_step(int32_t n, float L, const float* x, const float* y, const floa
   const Arr caller{{cx, cx}, {cy, cy}, {cz, cz}, const_cast<int32_t*>(type), state, adj, nullptr,
                    ws->role};
   d.set[0] = d.set[1] = caller;
-  d.slot_of = nullptr;
   d.bonds = bonds;
   d.bonds_cap = cap;
   d.log = ws->log;
@@ -531,7 +530,6 @@ int alloc_system(Arena& A, Dev& d, int32_t n, int32_t B, int64_t log_cap, hipStr
     if (!e) e = A.alloc(&a.role, n);
     if (!e) e = A.alloc(&a.adj, (size_t)n * B);
   }
-  if (!e) e = A.alloc(&d.slot_of, n);
   if (!e) e = A.alloc(&d.log, (size_t)log_cap * 3);
   if (!e) e = A.alloc(&d.bstart, (size_t)d.nbricks + 1);
   if (!e) e = A.alloc(&d.bcnt, (size_t)d.nbricks);

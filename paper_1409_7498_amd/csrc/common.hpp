@@ -71,7 +71,6 @@ enum Role : uint8_t { kRoleNone = 0, kRoleT = 1, kRoleA = 2 };
 // Everything a kernel needs, passed by value as the kernel argument.
 struct Dev {
   Arr set[2];           // storage sets (the sort writes the other one)
-  int32_t* slot_of;     // id -> slot (nullptr: identity)
   // A grid: per-cell counts by parity; bucket records (x, y, z, id), the
   // A's slot and (rows of width <= kAdjStage) its adjacency row; overflow
   // records and slots

@@ -262,7 +262,6 @@ __global__ __launch_bounds__(kThreads) void k_identity(Dev d) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= d.n) return;
   if (pick_set(d, 0).id) pick_set(d, 0).id[k] = k;
-  if (d.slot_of) d.slot_of[k] = k;
   d.tflag[k] = 0;
 }
 
@@ -1203,7 +1202,8 @@ __device__ __forceinline__ int sort_bin(const Dev& d, float x, float y, float z,
   return b * d.nd + (lz * e + ly) * e + lx;
 }
 
-// Ranks within sort bins.
+// Ranks within sort bins (one returning atomic per particle; the bins are
+// fine, so lanes rarely share one and there is little to aggregate).
 __device__ __forceinline__ void sort_count_body(const Dev& d, int k) {
   if (k >= d.n) return;
   const Arr a = pick_set(d, d.ctl->set & 1u);
@@ -1275,7 +1275,6 @@ __device__ __forceinline__ void sort_scatter_body(const Dev& d, int k) {
   o.role[ns] = a.role[k];
   const int id = a.id[k];
   o.id[ns] = id;
-  d.slot_of[id] = ns;
   for (int q = 0; q < d.B; ++q) o.adj[(size_t)ns * d.B + q] = a.adj[(size_t)k * d.B + q];
 }
 
