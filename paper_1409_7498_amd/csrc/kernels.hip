@@ -13,10 +13,10 @@
 //              queue so that the keyed Philox draws (step 2) run on full
 //              wavefronts; each retained pair lowers its A's key (w1, id_T) by
 //              a 64-bit atomicMin (steps 3-5) and joins the workgroup's list
-//   k_resolve  per workgroup, the listed pairs whose A chose their T; of those
-//              the smallest (w2, id_A) per T is bonded, states and adjacency
-//              updated (steps 6-9)
-// plus the counting sort of the storage by brick, the synthetic generator and
+//   k_resolve  per sweep workgroup (one wavefront each), the listed pairs
+//              whose A chose their T; of those the smallest (w2, id_A) per T
+//              is bonded, states and adjacency updated (steps 6-9)
+// plus the counting sort of the storage by brick and dual cell, the synthetic generator and
 // the helpers of the runtime.
 //
 // Arithmetic follows the contract of include/polyreact.h: FP32 min-image
@@ -1044,58 +1044,65 @@ __device__ __forceinline__ void make_bond(const Dev& d, const Arr& a, uint32_t p
   }
 }
 
-template <bool kBrick>
+// kWave: one wavefront per unit (four units per workgroup, unit = blockIdx.x
+// * 4 + wavefront); else the whole workgroup handles unit w.  Every barrier
+// is taken by the whole workgroup (mode is the same for all its units).
+template <bool kBrick, bool kWave>
 __device__ __forceinline__ void resolve_body(const Dev& d, int k, int w) {
-  __shared__ int s_nw, s_lost, s_prop, s_mode;
-  __shared__ unsigned long long s_key[kRetCap];
-  __shared__ int32_t s_sj[kRetCap];
-  const int tid = threadIdx.x;
+  constexpr int kG = kWave ? kThreads / 64 : 1;  // units per workgroup
+  constexpr int kL = kWave ? 64 : kThreads;      // lanes per unit
+  __shared__ int s_nw[kG], s_lost[kG], s_prop[kG];
+  __shared__ int s_mode;
+  __shared__ unsigned long long s_key[kG][kRetCap];
+  __shared__ int32_t s_sj[kG][kRetCap];
+  const int g = kWave ? (int)(threadIdx.x >> 6) : 0;
+  const int tid = kWave ? (int)__lane_id() : (int)threadIdx.x;
+  if (kWave) w = w * kG + g;
+  const bool live = !kWave || w < d.nwg_sweep;  // the last workgroup's spare wavefronts
   const Ctl* c = d.ctl;
   const StepInfo si = step_info(c, k);
   const uint32_t par = si.par, step = si.step;
   if (tid == 0) {
-    s_nw = 0;
-    s_lost = 0;
-    s_prop = 0;
-    s_mode = read_err(c) ? 0 : (c->ret_ovf[par] ? 2 : 1);
+    s_nw[g] = 0;
+    s_lost[g] = 0;
+    s_prop[g] = 0;
   }
+  if (threadIdx.x == 0) s_mode = read_err(c) ? 0 : (c->ret_ovf[par] ? 2 : 1);
   __syncthreads();
   const int mode = s_mode;
   const Arr a = pick_set(d, c->set & 1u);
-  const BondCtx bc{&s_nw, &s_lost};
+  const BondCtx bc{&s_nw[g], &s_lost[g]};
   if (mode == 1) {
-    const int ne = pick(d.wgo, par)[w * kWgOut + kOutRet];
-    if (ne > 0) {
-      bool chosen = false;
-      int4 e = make_int4(0, 0, 0, 0);
-      unsigned long long key = kEmpty;
-      if (tid < ne) {
-        e = pick(d.wge, par)[w * kRetCap + tid];
-        const uint32_t w2 = pick(d.wgk, par)[w * kRetCap + tid];
-        d.tflag[e.z] = 0;
-        chosen = (uint32_t)d.slotA[e.x] == (uint32_t)e.w;
-        if (chosen) {
-          d.slotA[e.x] = kEmpty;
-          key = ((unsigned long long)w2 << 32) | (uint32_t)e.x;
-          atomicAdd(&s_prop, 1);
-        }
-        s_key[tid] = key;
-        s_sj[tid] = e.z;
-      }
-      __syncthreads();
+    const int ne = live ? pick(d.wgo, par)[w * kWgOut + kOutRet] : 0;
+    bool chosen = false;
+    int4 e = make_int4(0, 0, 0, 0);
+    unsigned long long key = kEmpty;
+    if (tid < ne) {
+      e = pick(d.wge, par)[w * kRetCap + tid];
+      const uint32_t w2 = pick(d.wgk, par)[w * kRetCap + tid];
+      d.tflag[e.z] = 0;
+      chosen = (uint32_t)d.slotA[e.x] == (uint32_t)e.w;
       if (chosen) {
-        bool win = true;
-        for (int f = 0; f < ne; ++f)
-          if (s_sj[f] == e.z && s_key[f] < key) win = false;
-        if (win) make_bond(d, a, par, w, e.x, e.y, e.z, e.w, bc);
+        d.slotA[e.x] = kEmpty;
+        key = ((unsigned long long)w2 << 32) | (uint32_t)e.x;
+        atomicAdd(&s_prop[g], 1);
       }
+      s_key[g][tid] = key;
+      s_sj[g][tid] = e.z;
     }
-  } else if (mode == 2) {
+    __syncthreads();
+    if (chosen) {
+      bool win = true;
+      for (int f = 0; f < ne; ++f)
+        if (s_sj[g][f] == e.z && s_key[g][f] < key) win = false;
+      if (win) make_bond(d, a, par, w, e.x, e.y, e.z, e.w, bc);
+    }
+  } else if (mode == 2 && live) {
     const float *X = pick(a.x, par ^ 1u), *Y = pick(a.y, par ^ 1u), *Z = pick(a.z, par ^ 1u);
     const uint32_t novf = c->ovf_n[par];
     int s0, s1;
     range_of<kBrick>(d, w, s0, s1);
-    for (int base = s0; base < s1; base += kThreads) {
+    for (int base = s0; base < s1; base += kL) {
       const int slot = base + tid;
       if (slot < s1 && d.tflag[slot]) {
         d.tflag[slot] = 0;
@@ -1116,17 +1123,17 @@ __device__ __forceinline__ void resolve_body(const Dev& d, int k, int w) {
             best_sa = sa;
           }
         });
-        if (np) atomicAdd(&s_prop, np);
+        if (np) atomicAdd(&s_prop[g], np);
         if (best != kEmpty) make_bond(d, a, par, w, (int)(uint32_t)best, best_sa, slot, (int)idj, bc);
       }
     }
   }
   __syncthreads();
-  if (tid == 0) {
+  if (tid == 0 && live) {
     int32_t* out = pick(d.wgo, par) + w * kWgOut;
-    out[kOutProp] = s_prop;
-    out[kOutBonds] = s_nw;
-    out[kOutLost] = s_lost;
+    out[kOutProp] = s_prop[g];
+    out[kOutBonds] = s_nw[g];
+    out[kOutLost] = s_lost[g];
   }
 }
 
@@ -1295,7 +1302,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
 }
 template <bool kBrick>
 __global__ __launch_bounds__(kThreads) void k_resolve(Dev d, int k) {
-  resolve_body<kBrick>(d, k, blockIdx.x);
+  resolve_body<kBrick, true>(d, k, blockIdx.x);
 }
 __global__ __launch_bounds__(kThreads) void k_sort_count(Dev d) {
   sort_count_body(d, blockIdx.x * blockDim.x + threadIdx.x);
@@ -1340,7 +1347,7 @@ __global__ __launch_bounds__(kThreads) void k_resolve_b(const Dev* __restrict__ 
   const int4 m = uniform_map(map);
   const Dev& d = ds[m.x];
   if (k >= d.k_limit) return;
-  resolve_body<true>(d, k, m.y);
+  resolve_body<true, false>(d, k, m.y);
 }
 __global__ __launch_bounds__(kThreads) void k_close_b(const Dev* __restrict__ ds,
                                                       const int4* __restrict__ map, int k) {
@@ -1462,9 +1469,9 @@ hipError_t launch_step(const Dev& d, int k, hipStream_t s, hipEvent_t ev_sweep0,
       k_sweep<false><<<g, b, 0, s>>>(d, k);
   }
   if (d.sorted)
-    k_resolve<true><<<d.nwg_sweep, kThreads, 0, s>>>(d, k);
+    k_resolve<true><<<(d.nwg_sweep + 3) / 4, kThreads, 0, s>>>(d, k);
   else
-    k_resolve<false><<<d.nwg_sweep, kThreads, 0, s>>>(d, k);
+    k_resolve<false><<<(d.nwg_sweep + 3) / 4, kThreads, 0, s>>>(d, k);
   return hipGetLastError();
 }
 
