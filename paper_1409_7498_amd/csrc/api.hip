@@ -1200,7 +1200,7 @@ int check_batch(pr_batch* b, int32_t rep) {
 // Maps of grid blocks to (replica, local block, blocks of the replica) for
 // the sorted-storage kernels of the batch.
 int fill_maps(const std::vector<pr_sys*>& sys, Arena& arena, BatchLaunch& bl) {
-  std::vector<int4> prep0, prepk, sweep, close, part;
+  std::vector<int4> prep0, prepk, sweep, close, part, res;
   int n_sortl = 1;
   for (int r = 0; r < (int)sys.size(); ++r) {
     const Dev& d = sys[r]->d;
@@ -1209,21 +1209,23 @@ int fill_maps(const std::vector<pr_sys*>& sys, Arena& arena, BatchLaunch& bl) {
     for (int q = 0; q < d.ngroups + d.nwg_prep; ++q)
       prepk.push_back(make_int4(r, q, d.ngroups + d.nwg_prep, 0));
     for (int q = 0; q < d.nbricks; ++q) sweep.push_back(make_int4(r, q, d.nbricks, 0));
+    for (int q = 0; q < (d.nbricks + 3) / 4; ++q) res.push_back(make_int4(r, q, d.nbricks, 0));
     for (int q = 0; q < d.ngroups; ++q) close.push_back(make_int4(r, q, d.ngroups, 0));
     const int np = (d.n + kThreads - 1) / kThreads;
     for (int q = 0; q < np; ++q) part.push_back(make_int4(r, q, np, 0));
   }
-  int4 *m0, *mk, *ms, *mc, *mp;
+  int4 *m0, *mk, *ms, *mc, *mp, *mr;
   int e;
   if ((e = arena.alloc(&m0, prep0.size())) || (e = arena.alloc(&mk, prepk.size())) ||
       (e = arena.alloc(&ms, sweep.size())) || (e = arena.alloc(&mc, close.size())) ||
-      (e = arena.alloc(&mp, part.size())))
+      (e = arena.alloc(&mp, part.size())) || (e = arena.alloc(&mr, res.size())))
     return e;
   HIP_TRY(hipMemcpy(m0, prep0.data(), prep0.size() * sizeof(int4), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(mk, prepk.data(), prepk.size() * sizeof(int4), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(ms, sweep.data(), sweep.size() * sizeof(int4), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(mc, close.data(), close.size() * sizeof(int4), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(mp, part.data(), part.size() * sizeof(int4), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(mr, res.data(), res.size() * sizeof(int4), hipMemcpyHostToDevice));
   bl.prep0 = m0;
   bl.prepk = mk;
   bl.sweep = ms;
@@ -1235,6 +1237,8 @@ int fill_maps(const std::vector<pr_sys*>& sys, Arena& arena, BatchLaunch& bl) {
   bl.n_close = (int)close.size();
   bl.n_part = (int)part.size();
   bl.n_sortl = n_sortl;
+  bl.res = mr;
+  bl.n_res = (int)res.size();
   bl.nrep = (int)sys.size();
   return PR_OK;
 }

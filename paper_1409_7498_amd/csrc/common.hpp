@@ -132,6 +132,8 @@ struct BatchLaunch {
   const int4 *prep0, *prepk, *sweep, *close, *part;  // prep at k == 0 / k > 0, sweep and
   int n_prep0, n_prepk, n_sweep, n_close, n_part;     // resolve, closing, particle blocks
   int n_sortl;          // blocks of the per-brick sort scan of the largest replica
+  const int4* res;      // resolve: four bricks per block (one per wavefront)
+  int n_res;
 };
 
 }  // namespace pr

@@ -1048,7 +1048,7 @@ __device__ __forceinline__ void make_bond(const Dev& d, const Arr& a, uint32_t p
 // * 4 + wavefront); else the whole workgroup handles unit w.  Every barrier
 // is taken by the whole workgroup (mode is the same for all its units).
 template <bool kBrick, bool kWave>
-__device__ __forceinline__ void resolve_body(const Dev& d, int k, int w) {
+__device__ __forceinline__ void resolve_body(const Dev& d, int k, int w, int nunits) {
   constexpr int kG = kWave ? kThreads / 64 : 1;  // units per workgroup
   constexpr int kL = kWave ? 64 : kThreads;      // lanes per unit
   __shared__ int s_nw[kG], s_lost[kG], s_prop[kG];
@@ -1058,7 +1058,7 @@ __device__ __forceinline__ void resolve_body(const Dev& d, int k, int w) {
   const int g = kWave ? (int)(threadIdx.x >> 6) : 0;
   const int tid = kWave ? (int)__lane_id() : (int)threadIdx.x;
   if (kWave) w = w * kG + g;
-  const bool live = !kWave || w < d.nwg_sweep;  // the last workgroup's spare wavefronts
+  const bool live = !kWave || w < nunits;  // the last workgroup's spare wavefronts
   const Ctl* c = d.ctl;
   const StepInfo si = step_info(c, k);
   const uint32_t par = si.par, step = si.step;
@@ -1302,7 +1302,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
 }
 template <bool kBrick>
 __global__ __launch_bounds__(kThreads) void k_resolve(Dev d, int k) {
-  resolve_body<kBrick, true>(d, k, blockIdx.x);
+  resolve_body<kBrick, true>(d, k, blockIdx.x, d.nwg_sweep);
 }
 __global__ __launch_bounds__(kThreads) void k_sort_count(Dev d) {
   sort_count_body(d, blockIdx.x * blockDim.x + threadIdx.x);
@@ -1347,7 +1347,7 @@ __global__ __launch_bounds__(kThreads) void k_resolve_b(const Dev* __restrict__ 
   const int4 m = uniform_map(map);
   const Dev& d = ds[m.x];
   if (k >= d.k_limit) return;
-  resolve_body<true, false>(d, k, m.y);
+  resolve_body<true, true>(d, k, m.y, m.z);
 }
 __global__ __launch_bounds__(kThreads) void k_close_b(const Dev* __restrict__ ds,
                                                       const int4* __restrict__ map, int k) {
@@ -1511,7 +1511,7 @@ hipError_t launch_step_b(const BatchLaunch& b, int k, hipStream_t s) {
   else
     k_prep_b<<<b.n_prep0, kThreads, 0, s>>>(b.ds, b.prep0, k);
   k_sweep_b<<<b.n_sweep, kThreads, 0, s>>>(b.ds, b.sweep, k);
-  k_resolve_b<<<b.n_sweep, kThreads, 0, s>>>(b.ds, b.sweep, k);
+  k_resolve_b<<<b.n_res, kThreads, 0, s>>>(b.ds, b.res, k);
   return hipGetLastError();
 }
 
