@@ -827,6 +827,14 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
       const int slot = base + lt;
       uint32_t fl = flags0;
       asm volatile("" : "+s"(fl));
+      // wave priority by progress: the arbiter otherwise favours the oldest
+      // waves, so the workgroups dispatched first race ahead and the last
+      // ones end up running nearly alone on their compute units at the end
+      if (kBrick) {
+        if (u == 0) __builtin_amdgcn_s_setprio(3);
+        else if (u == 1) __builtin_amdgcn_s_setprio(2);
+        else __builtin_amdgcn_s_setprio(1);
+      }
       // the next particle's loads are in flight while this one is handled
       Part nxt = cur;
       if (u + 1 < kPer) nxt = load_part<kBrick>(a, X, Y, Z, slot + kThreads, s1);
