@@ -381,8 +381,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+u32",
         "data": "synthetic (jittered lattice, generated on device)",
-        "config": {"workload": "step growth N=1,048,576 L=105.6 rc=1.12 p=0.005, 5% crosslinkers; "
-                               "a step = re-jitter (sigma=0.05, fused) + reaction step",
+        "config": {"workload": "%s N=%s L=%g rc=%g p=%g, %s; a step = re-jitter (sigma=%g, "
+                               "fused) + reaction step"
+                               % ("step growth" if cfg.kind == "step" else "chain growth",
+                                  format(cfg.N, ","), cfg.L, cfg.rc, cfg.p,
+                                  "5% crosslinkers" if cfg.kind == "step" else "0.1% initiators",
+                                  cfg.sigma),
                    "steps_timed": K, "sort_period": sort_period},
         "step_roofline_frac": step_bytes / (step_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
         "prep_ms_direct": prep_ms,
