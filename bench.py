@@ -296,6 +296,8 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--sort-period", type=int, default=-1)
+    ap.add_argument("--brick", type=int, default=0,
+                    help="brick edge in coarse cells, 1..6 (0 = the library default, 4)")
     ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--requests", type=int, default=1000, help="c5: requests of the stream")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="c5: HBM admission budget")
@@ -332,7 +334,7 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     sysm = binding.System(cfg.N, cfg.L, cfg.B, cfg.rule(), cfg.seed,
-                          log_cap=cfg.N * 2, stream=stream)
+                          log_cap=cfg.N * 2, stream=stream, brick=args.brick)
     if args.sort_period >= 0:
         sysm.set_sort_period(args.sort_period)
     sort_period = 64 if args.sort_period < 0 else args.sort_period
@@ -387,7 +389,8 @@ def main():
                                   format(cfg.N, ","), cfg.L, cfg.rc, cfg.p,
                                   "5% crosslinkers" if cfg.kind == "step" else "0.1% initiators",
                                   cfg.sigma),
-                   "steps_timed": K, "sort_period": sort_period},
+                   "steps_timed": K, "sort_period": sort_period,
+                   "brick": sysm.geometry()[1]},
         "step_roofline_frac": step_bytes / (step_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
         "prep_ms_direct": prep_ms,
         "sweep_ms_direct": sweep_ms,

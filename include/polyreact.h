@@ -135,10 +135,12 @@ int pr_sys_create(pr_sys** out, int32_t n, float L, int32_t B, const pr_rule* ru
                   uint64_t seed, int64_t log_cap, void* stream);
 
 /* As pr_sys_create, with the brick edge chosen: the storage is sorted by
- * bricks of brick^3 coarse cells (brick in 1..4, 0 = 4; clamped to nc - 2
+ * bricks of brick^3 coarse cells (brick in 1..6, 0 = 4; clamped to nc - 2
  * for small boxes, nc = coarse cells per side) and the sweep runs one
- * workgroup per brick.  A tuning parameter only: every result is identical
- * for every brick.  PR_EINVAL for brick outside 0..4. */
+ * workgroup per brick.  Larger bricks mean fewer workgroups (each staging a
+ * larger region); they suit large systems with few A's.  A tuning parameter
+ * only: every result is identical for every brick.  PR_EINVAL for brick
+ * outside 0..6. */
 int pr_sys_create_ex(pr_sys** out, int32_t n, float L, int32_t B, const pr_rule* rule,
                      uint64_t seed, int64_t log_cap, void* stream, int32_t brick);
 
@@ -244,7 +246,7 @@ typedef struct pr_replica_desc {
   uint64_t gen_seed;  /* generator seed */
   double gen_sigma0;  /* lattice displacement of the generator */
   int64_t log_cap;    /* bond-log capacity in bonds (0 = n) */
-  int32_t brick;      /* brick edge in cells, 1..4 (0 = 4): see pr_sys_create_ex */
+  int32_t brick;      /* brick edge in cells, 1..6 (0 = 4): see pr_sys_create_ex */
 } pr_replica_desc;
 
 typedef struct pr_batch pr_batch;
@@ -279,14 +281,14 @@ int pr_batch_stats(pr_batch* b, int32_t rep, pr_stats* out, int64_t cap, int64_t
  * pr_sys_create. */
 int pr_footprint(const pr_replica_desc* r, uint32_t n_steps, int64_t* bytes);
 
-/* Autotuner of the brick edge: for every brick edge 1..4 that gives a
+/* Autotuner of the brick edge: for every brick edge 1..6 that gives a
  * distinct brick count, creates the replica with that edge -- copies = 1: one
  * system (pr_sys_create_ex); copies > 1: a batch of `copies` identical
  * replicas (pr_batch_create), the context of a replica in a full batch --
  * generates it, runs one untimed block of 64 steps (first sort, graph
  * capture) and times n_steps more steps (use a multiple of 64) with HIP
- * events on stream.  *best receives the fastest edge, us[0..3] (may be NULL)
- * the microseconds per replica-step of edges 1..4 (-1 where not timed).
+ * events on stream.  *best receives the fastest edge, us[0..5] (may be NULL)
+ * the microseconds per replica-step of edges 1..6 (-1 where not timed).
  * Allocates and frees one candidate at a time; synchronises stream.  Errors
  * as pr_sys_create_ex / pr_batch_create and the runs. */
 int pr_autotune(const pr_replica_desc* r, uint32_t n_steps, double sigma, int32_t copies,

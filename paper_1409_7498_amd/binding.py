@@ -186,7 +186,7 @@ class System:
     """Resident particle system (pr_sys_* entry points)."""
 
     def __init__(self, n, L, B, rule, seed, log_cap=0, stream=None, brick=0):
-        """brick: brick edge in coarse cells (1..4, 0 = 4), a tuning choice only."""
+        """brick: brick edge in coarse cells (1..6, 0 = 4), a tuning choice only."""
         self._h = C.c_void_p()
         r = rule if isinstance(rule, Rule) else Rule.make(rule)
         self.n, self.L, self.B = int(n), float(np.float32(L)), int(B)
@@ -312,14 +312,14 @@ def autotune(r, n_steps=128, sigma=0.05, copies=1, stream=None, cache=None):
     Returns (best edge, {edge: microseconds per replica-step})."""
     d = replica_desc(r)
     best = C.c_int32(0)
-    us = (C.c_float * 4)()
+    us = (C.c_float * 6)()
     if cache is None:
         _check(lib.pr_autotune(C.byref(d), int(n_steps), float(sigma), int(copies),
                                _stream(stream), C.byref(best), us))
     else:
         _check(lib.pr_autotune_cached(C.byref(d), int(n_steps), float(sigma), int(copies),
                                       _stream(stream), os.fsencode(cache), C.byref(best), us))
-    return best.value, {b + 1: float(us[b]) for b in range(4) if us[b] >= 0.0}
+    return best.value, {b + 1: float(us[b]) for b in range(6) if us[b] >= 0.0}
 
 
 def footprint(r, n_steps):

@@ -270,7 +270,7 @@ int pr_react_step(int32_t n, float L, const float* x, const float* y, const floa
   if ((int)g_ws.size() <= dev) g_ws.resize(dev + 1, nullptr);
   Workspace*& ws = g_ws[dev];
   Dev geo{};
-  set_geometry(geo, n, L, B, rule, seed, kMaxBrick);
+  set_geometry(geo, n, L, B, rule, seed, kDefaultBrick);
   if (!ws || ws->n < n || ws->ncell < geo.ncell) {
     delete ws;
     ws = new Workspace();
@@ -555,7 +555,7 @@ int pr_footprint(const pr_replica_desc* r, uint32_t n_steps, int64_t* bytes) {
   int e = validate_rule(&r->rule, r->L);
   if (e) return e;
   Dev d{};
-  set_geometry(d, r->n, r->L, r->B, &r->rule, r->seed, r->brick > 0 ? r->brick : kMaxBrick);
+  set_geometry(d, r->n, r->L, r->B, &r->rule, r->seed, r->brick > 0 ? r->brick : kDefaultBrick);
   Arena A;
   A.dry = true;
   const int64_t log_cap = r->log_cap > 0 ? r->log_cap : r->n;
@@ -603,7 +603,7 @@ int sys_create(pr_sys** out, int32_t n, float L, int32_t B, const pr_rule* rule,
     return fail(PR_EHIP, "hipGetDevice failed");
   }
   Dev& d = s->d;
-  set_geometry(d, n, L, B, rule, seed, brick > 0 ? brick : kMaxBrick);
+  set_geometry(d, n, L, B, rule, seed, brick > 0 ? brick : kDefaultBrick);
   s->log_cap = log_cap > 0 ? log_cap : n;
   e = alloc_system(s->arena, d, n, B, s->log_cap, s->stream);
   if (!e && !s->hctl && hipHostMalloc((void**)&s->hctl, sizeof(Ctl)) != hipSuccess)
@@ -1116,17 +1116,17 @@ int pr_autotune_cached(const pr_replica_desc* r, uint32_t n_steps, double sigma,
   int e = pr_footprint(r, n_steps + 64, &bytes);  // validates the description
   if (e) return e;
   Dev g{};
-  set_geometry(g, r->n, r->L, r->B, &r->rule, r->seed, kMaxBrick);
-  // one line per tuned geometry: "pr-tune 1 <nc> <copies> <B> <best> <us 1..kMaxBrick>"
-  static_assert(kMaxBrick == 4, "the cache line holds four times");
+  set_geometry(g, r->n, r->L, r->B, &r->rule, r->seed, kDefaultBrick);
+  // one line per tuned geometry: "pr-tune 2 <nc> <copies> <B> <best> <us 1..kMaxBrick>"
+  static_assert(kMaxBrick == 6, "the cache line holds six times");
   if (FILE* f = std::fopen(cache_path, "r")) {
     char line[256];
     while (std::fgets(line, sizeof line, f)) {
       int ver = 0, nc = 0, cp = 0, bw = 0, b = 0;
-      float t[kMaxBrick] = {-1.0f, -1.0f, -1.0f, -1.0f};
-      if (std::sscanf(line, "pr-tune %d %d %d %d %d %f %f %f %f", &ver, &nc, &cp, &bw, &b, &t[0],
-                      &t[1], &t[2], &t[3]) == 5 + kMaxBrick &&
-          ver == 1 && nc == g.nc && cp == copies && bw == r->B && b >= 1 && b <= kMaxBrick) {
+      float t[kMaxBrick] = {-1.0f, -1.0f, -1.0f, -1.0f, -1.0f, -1.0f};
+      if (std::sscanf(line, "pr-tune %d %d %d %d %d %f %f %f %f %f %f", &ver, &nc, &cp, &bw, &b,
+                      &t[0], &t[1], &t[2], &t[3], &t[4], &t[5]) == 5 + kMaxBrick &&
+          ver == 2 && nc == g.nc && cp == copies && bw == r->B && b >= 1 && b <= kMaxBrick) {
         std::fclose(f);
         *best = b;
         if (us)
@@ -1142,8 +1142,8 @@ int pr_autotune_cached(const pr_replica_desc* r, uint32_t n_steps, double sigma,
     for (int q = 0; q < kMaxBrick; ++q) us[q] = t[q];
   FILE* f = std::fopen(cache_path, "a");
   if (!f) return fail(PR_EINVAL, "cannot append to the tuning cache %s", cache_path);
-  std::fprintf(f, "pr-tune 1 %d %d %d %d %.3f %.3f %.3f %.3f\n", g.nc, copies, r->B, *best, t[0],
-               t[1], t[2], t[3]);
+  std::fprintf(f, "pr-tune 2 %d %d %d %d %.3f %.3f %.3f %.3f %.3f %.3f\n", g.nc, copies, r->B,
+               *best, t[0], t[1], t[2], t[3], t[4], t[5]);
   std::fclose(f);
   return PR_OK;
 }
@@ -1201,9 +1201,10 @@ int check_batch(pr_batch* b, int32_t rep) {
 // the sorted-storage kernels of the batch.
 int fill_maps(const std::vector<pr_sys*>& sys, Arena& arena, BatchLaunch& bl) {
   std::vector<int4> prep0, prepk, sweep, close, part, res;
-  int n_sortl = 1;
+  int n_sortl = 1, two = 0;
   for (int r = 0; r < (int)sys.size(); ++r) {
     const Dev& d = sys[r]->d;
+    if (d.bs > kOneCellBrick && d.nbricks > 1) two = 1;
     n_sortl = std::max(n_sortl, (d.nbricks + kThreads / 64 - 1) / (kThreads / 64));
     for (int q = 0; q < d.nwg_prep; ++q) prep0.push_back(make_int4(r, q, d.nwg_prep, 0));
     for (int q = 0; q < d.ngroups + d.nwg_prep; ++q)
@@ -1237,6 +1238,7 @@ int fill_maps(const std::vector<pr_sys*>& sys, Arena& arena, BatchLaunch& bl) {
   bl.n_close = (int)close.size();
   bl.n_part = (int)part.size();
   bl.n_sortl = n_sortl;
+  bl.two = two;
   bl.res = mr;
   bl.n_res = (int)res.size();
   bl.nrep = (int)sys.size();

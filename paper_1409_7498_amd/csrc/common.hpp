@@ -27,9 +27,16 @@ constexpr int kAdjStage = 4;        // adjacency rows up to this width travel wi
 // Spatially sorted storage: particles are kept ordered by "brick" (a block of
 // bs^3 coarse cells); one sweep workgroup owns a brick and stages the A
 // records of the brick plus one halo cell layer in LDS.
-constexpr int kMaxBrick = 4;
+constexpr int kMaxBrick = 6;
+constexpr int kDefaultBrick = 4;
 constexpr int kStageCells = (kMaxBrick + 2) * (kMaxBrick + 2) * (kMaxBrick + 2);
-static_assert(kStageCells <= kThreads, "the sweep stages one region cell per thread");
+static_assert(kStageCells <= 2 * kThreads, "the sweep stages two region cells per thread");
+// bricks up to this edge take the sweep variant with one region cell per thread
+constexpr int kOneCellBrick = 4;
+constexpr int kStageCells1 = (kOneCellBrick + 2) * (kOneCellBrick + 2) * (kOneCellBrick + 2);
+static_assert(kStageCells1 <= kThreads, "one region cell per thread");
+static_assert((kMaxBrick + 1) * (kMaxBrick + 1) * (kMaxBrick + 1) <= 6 * 64,
+              "the per-brick sort scan takes up to six bins per lane");
 constexpr int kStageRecs = 256;
 constexpr int kTPass = 768;         // particles a sweep workgroup holds per pass (3 per thread)
 constexpr int kQueue = 512;         // in-range pairs queued per pass
@@ -134,6 +141,7 @@ struct BatchLaunch {
   int n_sortl;          // blocks of the per-brick sort scan of the largest replica
   const int4* res;      // resolve: four bricks per block (one per wavefront)
   int n_res;
+  int two;              // some replica's brick edge exceeds kOneCellBrick
 };
 
 }  // namespace pr

@@ -717,17 +717,19 @@ __device__ __forceinline__ uint32_t lanes_below(unsigned long long b) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
 }
 
-template <bool kBrick>
+// kTwo: two region cells per thread while staging (brick edges above
+// kOneCellBrick); else one, with the smaller tables.
+template <bool kBrick, bool kTwo>
 __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) {
+  constexpr int kCells = kTwo ? kStageCells : kStageCells1;  // region cells at most
   constexpr int kPer = kBrick ? kTPass / kThreads : 1;
   constexpr int kTP = kPer * kThreads;
   constexpr uint32_t kQEmpty = 0xFFFFFFFFu;
   __shared__ float4 s_rec[kBrick ? kStageRecs : 1];
   __shared__ int4 s_radj[kBrick ? kStageRecs : 1];
   __shared__ int32_t s_rsa[kBrick ? kStageRecs : 1];
-  __shared__ uint32_t s_off[kBrick ? kStageCells + 1 : 1];
-  __shared__ int32_t s_cid[kBrick ? kStageCells : 1];
-  __shared__ uint8_t s_rcell[kBrick ? kStageRecs : 1];  // staged record -> region cell
+  __shared__ uint16_t s_off[kBrick ? kCells + 1 : 1];  // first record of a region cell
+  __shared__ uint16_t s_rcell[kBrick ? kStageRecs : 1];  // staged record -> region cell
   __shared__ uint32_t s_q[kBrick ? kQueue : 1];  // queued pair: local T | staged record << 16
   __shared__ int32_t s_tid[kBrick ? kTP : 1];    // ids of the pass's T's
   __shared__ uint16_t s_def[kTP];            // deferred T's (local index in the pass)
@@ -761,7 +763,17 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
   bool staged = false, nowrap = false;
   const int nc = d.nc;
   int ncs = 0;
-  uint32_t mine = 0;
+  uint32_t mine = 0, mine2 = 0, m_exy = 0, m_ex = 0;
+  // global cell of region cell cl (region cells in z, y, x order)
+  auto region_cell = [&](int cl) {
+    const int lz = div_small(cl, m_exy), rem = cl - lz * ex * ey;
+    const int ly = div_small(rem, m_ex), lx = rem - ly * ex;
+    int cx = bx + lx, cy = by + ly, cz = bz + lz;
+    cx -= cx >= nc ? nc : 0;
+    cy -= cy >= nc ? nc : 0;
+    cz -= cz >= nc ? nc : 0;
+    return (cz * nc + cy) * nc + cx;
+  };
   if (kBrick) {
     int bxc, byc;
     const int bzc = div_nb(d, div_nb(d, w, bxc), byc);
@@ -774,16 +786,14 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
     nowrap = d.nbricks > 1 && bx + ex <= nc && by + ey <= nc && bz + ez <= nc &&
              2 * ex + 1 <= nc && 2 * ey + 1 <= nc && 2 * ez + 1 <= nc;
     ncs = ex * ey * ez;
-    if (tid < ncs) {  // the record count of this thread's region cell, issued first
-      const int lz = div_small(tid, recip16((uint32_t)(ex * ey))), rem = tid - lz * ex * ey;
-      const int ly = div_small(rem, recip16((uint32_t)ex)), lx = rem - ly * ex;
-      int cx = bx + lx, cy = by + ly, cz = bz + lz;
-      cx -= cx >= nc ? nc : 0;
-      cy -= cy >= nc ? nc : 0;
-      cz -= cz >= nc ? nc : 0;
-      const int myc = (cz * nc + cy) * nc + cx;
-      s_cid[tid] = myc;
-      mine = pick(d.cnt, par)[myc];
+    m_exy = recip16((uint32_t)(ex * ey));
+    m_ex = recip16((uint32_t)ex);
+    // the record counts of this thread's region cells (2 tid and 2 tid + 1,
+    // or tid), issued first
+#pragma unroll
+    for (int h = 0; h < (kTwo ? 2 : 1); ++h) {
+      const int cl = kTwo ? 2 * tid + h : tid;
+      if (cl < ncs) (h ? mine2 : mine) = pick(d.cnt, par)[region_cell(cl)];
     }
   }
   // the first particle of the first pass, issued behind the record counts
@@ -791,19 +801,25 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
   Part cur = load_part<kBrick>(a, X, Y, Z, s0 + tid, s1);
   if (kBrick) {
     mine = mine < (uint32_t)kCellCap ? mine : (uint32_t)kCellCap;
+    mine2 = mine2 < (uint32_t)kCellCap ? mine2 : (uint32_t)kCellCap;
     uint32_t total = 0;
-    const uint32_t off = block_scan_excl(mine, s_wave, total);
-    if (tid < ncs) {
-      s_off[tid] = off;
-      for (uint32_t j = 0; j < mine && off + j < (uint32_t)kStageRecs; ++j)
-        s_rcell[off + j] = (uint8_t)tid;
+    const uint32_t off = block_scan_excl(mine + mine2, s_wave, total);
+#pragma unroll
+    for (int h = 0; h < (kTwo ? 2 : 1); ++h) {
+      const int cl = kTwo ? 2 * tid + h : tid;
+      const uint32_t o = h ? off + mine : off, m = h ? mine2 : mine;
+      if (cl < ncs) {
+        s_off[cl] = (uint16_t)o;
+        for (uint32_t j = 0; j < m && o + j < (uint32_t)kStageRecs; ++j)
+          s_rcell[o + j] = (uint16_t)cl;
+      }
     }
-    if (tid == 0) s_off[ncs] = total;
+    if (tid == 0) s_off[ncs] = (uint16_t)total;
     staged = total <= (uint32_t)kStageRecs && novf == 0;
     __syncthreads();
     if (staged && tid < (int)total) {
       const int lo = s_rcell[tid];  // the region cell of record tid
-      const size_t ri = (size_t)s_cid[lo] * kCellCap + (tid - (int)s_off[lo]);
+      const size_t ri = (size_t)region_cell(lo) * kCellCap + (tid - (int)s_off[lo]);
       s_rec[tid] = d.rec[ri];
       s_rsa[tid] = d.rsa[ri];
       if (d.adj_staged) s_radj[tid] = d.radj[ri];
@@ -1228,30 +1244,36 @@ __device__ __forceinline__ void sort_count_body(const Dev& d, int k) {
   d.rank[k] = (int32_t)atomicAdd(&d.dcnt[bin], 1u);
 }
 
-// Offsets of the bins within brick b (one wavefront, two bins per lane;
-// nd <= 125), the brick's total for the scan over bricks; the counts are
-// cleared for the next sort.
+// Offsets of the bins within brick b (one wavefront, up to six consecutive
+// bins per lane: nd = (bs + 1)^3 <= 343), the brick's total for the scan
+// over bricks; the counts are cleared for the next sort.
 __device__ __forceinline__ void sort_local_body(const Dev& d, int b) {
   if (b >= d.nbricks) return;
-  const int lane = __lane_id(), nd = d.nd;
+  constexpr int kPerLane = 6;
+  const int lane = __lane_id(), nd = d.nd, per = (nd + 63) / 64;
   uint32_t* c = d.dcnt + (size_t)b * nd;
   uint32_t* o = d.dloc + (size_t)b * nd;
-  const int j0 = 2 * lane, j1 = j0 + 1;
-  const uint32_t v0 = j0 < nd ? c[j0] : 0u, v1 = j1 < nd ? c[j1] : 0u;
-  uint32_t x = v0 + v1;
+  const int j0 = lane * per;
+  uint32_t v[kPerLane], sum = 0u;
+#pragma unroll
+  for (int q = 0; q < kPerLane; ++q) {
+    v[q] = q < per && j0 + q < nd ? c[j0 + q] : 0u;
+    sum += v[q];
+  }
+  uint32_t x = sum;
 #pragma unroll
   for (int q = 1; q < 64; q <<= 1) {
     const uint32_t y = __shfl_up(x, q);
     if (lane >= q) x += y;
   }
-  const uint32_t ex = x - v0 - v1;
-  if (j0 < nd) {
-    o[j0] = ex;
-    c[j0] = 0u;
-  }
-  if (j1 < nd) {
-    o[j1] = ex + v0;
-    c[j1] = 0u;
+  uint32_t run = x - sum;
+#pragma unroll
+  for (int q = 0; q < kPerLane; ++q) {
+    if (q < per && j0 + q < nd) {
+      o[j0 + q] = run;
+      c[j0 + q] = 0u;
+    }
+    run += v[q];
   }
   const uint32_t total = __shfl(x, 63);
   if (lane == 0) d.bcnt[b] = total;
@@ -1304,9 +1326,9 @@ __global__ __launch_bounds__(kThreads) void k_close(Dev d, int k) { close_body(d
 __global__ void k_advance(Ctl* c, int K) {
   if (threadIdx.x == 0 && blockIdx.x == 0) advance_ctl(c, K);
 }
-template <bool kBrick>
+template <bool kBrick, bool kTwo>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) void k_sweep(Dev d, int k) {
-  sweep_body<kBrick>(d, k, blockIdx.x, gridDim.x);
+  sweep_body<kBrick, kTwo>(d, k, blockIdx.x, gridDim.x);
 }
 template <bool kBrick>
 __global__ __launch_bounds__(kThreads) void k_resolve(Dev d, int k) {
@@ -1343,12 +1365,13 @@ __global__ __launch_bounds__(kThreads) void k_prep_b(const Dev* __restrict__ ds,
   if (k >= d.k_limit) return;
   prep_body(d, k, m.y);
 }
+template <bool kTwo>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) void k_sweep_b(
     const Dev* __restrict__ ds, const int4* __restrict__ map, int k) {
   const int4 m = uniform_map(map);
   const Dev& d = ds[m.x];
   if (k >= d.k_limit) return;
-  sweep_body<true>(d, k, m.y, m.z);
+  sweep_body<true, kTwo>(d, k, m.y, m.z);
 }
 __global__ __launch_bounds__(kThreads) void k_resolve_b(const Dev* __restrict__ ds,
                                                         const int4* __restrict__ map, int k) {
@@ -1465,16 +1488,21 @@ hipError_t launch_step(const Dev& d, int k, hipStream_t s, hipEvent_t ev_sweep0,
   const int prep_blocks = d.nwg_prep + (k > 0 ? d.ngroups : 0);
   k_prep<<<prep_blocks, kThreads, 0, s>>>(d, k);
   const dim3 g(d.nwg_sweep), b(kThreads);
-  if (d.sorted) {
+  if (d.sorted && d.bs > kOneCellBrick) {
     if (ev_sweep0)
-      hipExtLaunchKernelGGL(k_sweep<true>, g, b, 0, s, ev_sweep0, ev_sweep1, 0, d, k);
+      hipExtLaunchKernelGGL(k_sweep<true, true>, g, b, 0, s, ev_sweep0, ev_sweep1, 0, d, k);
     else
-      k_sweep<true><<<g, b, 0, s>>>(d, k);
+      k_sweep<true, true><<<g, b, 0, s>>>(d, k);
+  } else if (d.sorted) {
+    if (ev_sweep0)
+      hipExtLaunchKernelGGL(k_sweep<true, false>, g, b, 0, s, ev_sweep0, ev_sweep1, 0, d, k);
+    else
+      k_sweep<true, false><<<g, b, 0, s>>>(d, k);
   } else {
     if (ev_sweep0)
-      hipExtLaunchKernelGGL(k_sweep<false>, g, b, 0, s, ev_sweep0, ev_sweep1, 0, d, k);
+      hipExtLaunchKernelGGL(k_sweep<false, false>, g, b, 0, s, ev_sweep0, ev_sweep1, 0, d, k);
     else
-      k_sweep<false><<<g, b, 0, s>>>(d, k);
+      k_sweep<false, false><<<g, b, 0, s>>>(d, k);
   }
   if (d.sorted)
     k_resolve<true><<<(d.nwg_sweep + 3) / 4, kThreads, 0, s>>>(d, k);
@@ -1518,7 +1546,10 @@ hipError_t launch_step_b(const BatchLaunch& b, int k, hipStream_t s) {
     k_prep_b<<<b.n_prepk, kThreads, 0, s>>>(b.ds, b.prepk, k);
   else
     k_prep_b<<<b.n_prep0, kThreads, 0, s>>>(b.ds, b.prep0, k);
-  k_sweep_b<<<b.n_sweep, kThreads, 0, s>>>(b.ds, b.sweep, k);
+  if (b.two)
+    k_sweep_b<true><<<b.n_sweep, kThreads, 0, s>>>(b.ds, b.sweep, k);
+  else
+    k_sweep_b<false><<<b.n_sweep, kThreads, 0, s>>>(b.ds, b.sweep, k);
   k_resolve_b<<<b.n_res, kThreads, 0, s>>>(b.ds, b.res, k);
   return hipGetLastError();
 }

@@ -70,28 +70,28 @@ def test_host_validation_without_gpu():
 
 def test_footprint_and_brick_validation():
     """The footprint model runs on the host: smaller bricks mean more sweep
-    workgroups and so more per-workgroup scratch; a brick edge outside 0..4
+    workgroups and so more per-workgroup scratch; a brick edge outside 0..6
     and n above 2^30 are refused before any device call."""
     from paper_1409_7498_amd import binding as b
     from paper_1409_7498_amd import workload
     n = 50000
     d = dict(n=n, L=workload.box_for(n), B=4, rule=workload.rule_for("step", workload.RC, 0.01),
              seed=1, kind="step", gen_seed=2, sigma0=0.1, log_cap=n)
-    fp = {br: b.footprint(dict(d, brick=br), 100) for br in (0, 1, 2, 3, 4)}
+    fp = {br: b.footprint(dict(d, brick=br), 100) for br in range(7)}
     assert fp[0] == fp[4]
-    assert fp[1] > fp[2] > fp[3] > fp[4]
+    assert fp[1] > fp[2] > fp[3] > fp[4] > fp[5] > fp[6]
     assert b.footprint(d, 5000) > b.footprint(d, 100)
     with pytest.raises(b.PrError) as e:
-        b.footprint(dict(d, brick=5), 100)
+        b.footprint(dict(d, brick=7), 100)
     assert e.value.code == b.PR_EINVAL
     r = b.Rule.make(d["rule"])
     h = ctypes.c_void_p()
     assert b.lib.pr_sys_create_ex(ctypes.byref(h), n, ctypes.c_float(d["L"]), 4, ctypes.byref(r),
-                                  1, 0, None, 5) == b.PR_EINVAL
+                                  1, 0, None, 7) == b.PR_EINVAL
     assert b.lib.pr_sys_create_ex(ctypes.byref(h), (1 << 30) + 1, ctypes.c_float(d["L"]), 4,
                                   ctypes.byref(r), 1, 0, None, 0) == b.PR_EINVAL
     best = ctypes.c_int32(0)
-    bad = b.replica_desc(dict(d, brick=7))
+    bad = b.replica_desc(dict(d, brick=9))
     assert b.lib.pr_autotune(ctypes.byref(bad), 64, 0.05, 1, None, ctypes.byref(best),
                              None) == b.PR_EINVAL
     good = b.replica_desc(d)

@@ -45,14 +45,14 @@ def test_results_identical_for_every_brick(kind, p):
     ref_geo, ref = _run(B, d, steps, 4)
     say("brick 4", ref_geo, "bonds", len(ref[1]))
     assert len(ref[1]) > 0
-    seen = {ref_geo[2]}
-    for brick in (1, 2, 3):
+    seen = {ref_geo[:2]}
+    for brick in (1, 2, 3, 5, 6):
         geo, out = _run(B, d, steps, brick)
         say("brick", brick, geo)
         assert geo[1] == brick
-        seen.add(geo[2])
+        seen.add(geo[:2])
         _same(out, ref, "brick %d" % brick)
-    assert len(seen) == 4  # four distinct decompositions were compared
+    assert len(seen) == 6  # six decompositions (12 cells per side) were compared
 
 
 def test_small_box_clamps_brick():
@@ -99,7 +99,7 @@ def test_autotune_cache(tmp_path):
     d = _desc(20000, "step", 0.02, workload.MASTER_SEED + 80)
     best, us = B.autotune(d, 64, workload.SIGMA_JITTER, cache=cache)
     lines = open(cache).read().splitlines()
-    assert len(lines) == 1 and lines[0].startswith("pr-tune 1 ")
+    assert len(lines) == 1 and lines[0].startswith("pr-tune 2 ")
     t0 = time.time()
     best2, us2 = B.autotune(dict(d, seed=d["seed"] + 1), 64, workload.SIGMA_JITTER, cache=cache)
     assert time.time() - t0 < 0.5
