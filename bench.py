@@ -79,7 +79,7 @@ def cpu_baseline(cfg):
                       "steps 1-9) of the %d-particle workload: %.1f s wall" % (cfg.N, dt)}
 
 
-def tune_bricks(binding, descs, steps, sigma, target_wgs=4096, max_copies=256):
+def tune_bricks(binding, descs, steps, sigma, target_wgs=4096, max_copies=256, max_brick=6):
     """Brick edge per replica from the device autotuner, one tuning per class
     of equal coarse grids (the edges a box allows depend on its cells per
     side).  Each class is timed as one of enough identical replicas of a
@@ -98,6 +98,9 @@ def tune_bricks(binding, descs, steps, sigma, target_wgs=4096, max_copies=256):
         nb = -(-nc // bs) if nc > 2 else 1
         copies = int(min(max_copies, max(1, -(-target_wgs // nb ** 3))))
         best, us = binding.autotune(rep, steps, sigma, copies=copies)
+        allowed = {b: t for b, t in us.items() if b <= max_brick}
+        if allowed:
+            best = min(allowed, key=allowed.get)
         table[nc] = {"brick": best, "us_per_replica_step": {b: round(t, 3) for b, t in us.items()},
                      "replicas": len(ks), "copies": copies}
         for k in ks:
@@ -131,7 +134,7 @@ def bench_batch(args):
         return h.hexdigest()[:16]
 
     t0 = time.perf_counter()
-    tuned, table = tune_bricks(binding, descs, 64, workload.SIGMA_JITTER)
+    tuned, table = tune_bricks(binding, descs, 64, workload.SIGMA_JITTER, max_brick=args.max_brick)
     torch.cuda.synchronize()
     tune_s = time.perf_counter() - t0
     log("autotune: %.2f s, %s" % (tune_s, {nc: v["brick"] for nc, v in table.items()}))
@@ -299,6 +302,9 @@ def main():
     ap.add_argument("--brick", type=int, default=0,
                     help="brick edge in coarse cells, 1..6 (0 = the library default, 4)")
     ap.add_argument("--batch-steps", type=int, default=500)
+    ap.add_argument("--max-brick", type=int, default=4,
+                    help="c4: largest brick edge the tuned ensemble may use (edges 5-6 "
+                         "time faster per class but slow the mixed ensemble)")
     ap.add_argument("--requests", type=int, default=1000, help="c5: requests of the stream")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="c5: HBM admission budget")
     ap.add_argument("--slots", type=int, default=64, help="c5: replicas resident at once")
