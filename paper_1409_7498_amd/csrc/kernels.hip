@@ -41,6 +41,12 @@ struct W4 {
   uint32_t w0, w1, w2, w3;
 };
 
+// a ^ b ^ c in one instruction (gfx950's three-input bitwise op; 0x96 is the
+// truth table of the three-way exclusive or)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ W4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                      unsigned long long key) {
   uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
@@ -50,8 +56,8 @@ __device__ __forceinline__ W4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
     const unsigned long long p0 = 0xD2511F53ull * c0, p1 = 0xCD9E8D57ull * c2;
     const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
     const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
-    const uint32_t n0 = hi1 ^ c1 ^ k0;
-    const uint32_t n2 = hi0 ^ c3 ^ k1;
+    const uint32_t n0 = xor3(hi1, c1, k0);
+    const uint32_t n2 = xor3(hi0, c3, k1);
     c0 = n0;
     c1 = lo1;
     c2 = n2;
