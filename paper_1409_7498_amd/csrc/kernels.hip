@@ -93,9 +93,11 @@ __device__ __forceinline__ void ih12(uint32_t step, uint32_t id, uint32_t tag,
 __device__ __forceinline__ void ih4(uint32_t step, uint32_t id, uint32_t tag,
                                     unsigned long long key, int32_t S[3]) {
   const W4 a = philox(step, id, 0u, tag, key);
-  S[0] = (int32_t)byte_sum(a.w0, 0u) - 510;
-  S[1] = (int32_t)byte_sum(a.w1, 0u) - 510;
-  S[2] = (int32_t)byte_sum(a.w2, 0u) - 510;
+  // the -510 rides in the accumulator (32-bit wrap: the sum is in [0, 1020])
+  constexpr uint32_t kMinus510 = 0u - 510u;
+  S[0] = (int32_t)byte_sum(a.w0, kMinus510);
+  S[1] = (int32_t)byte_sum(a.w1, kMinus510);
+  S[2] = (int32_t)byte_sum(a.w2, kMinus510);
 }
 
 __device__ __forceinline__ float wrap_box(float v, float L) {
@@ -886,7 +888,7 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
           if ((uint32_t)lx0 < (uint32_t)(ex - 1) && (uint32_t)ly0 < (uint32_t)(ey - 1) &&
               (uint32_t)lz0 < (uint32_t)(ez - 1)) {
             // runs (dy, dz) = (0,0), (1,0), (0,1), (1,1): cells lx0 and lx0 + 1
-            const int l0 = (lz0 * ey + ly0) * ex + lx0;
+            const int l0 = (int)__umul24(__umul24(lz0, ey) + ly0, ex) + lx0;  // small operands
             const int l1 = l0 + ex, l2 = l0 + ex * ey, l3 = l2 + ex;
             const int b0 = (int)s_off[l0], b1 = (int)s_off[l1], b2 = (int)s_off[l2],
                       b3 = (int)s_off[l3];
