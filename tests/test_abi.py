@@ -110,3 +110,18 @@ def test_p_from_rate():
     for bad in ((-1.0, 0.005, 10), (1.0, float("nan"), 10), (1.0, 1.0, float("inf"))):
         with pytest.raises(ValueError):
             b.p_from_rate(*bad)
+
+
+def test_empty_step_without_gpu():
+    """n = 0: PR_OK, no bonds, all counters zero, before any device call."""
+    from paper_1409_7498_amd import binding as b
+    r = b.Rule.make(type_a=1, a_min=1, a_max=4, d_a=-1, type_t=0, t_min=1, t_max=2, d_t=-1,
+                    rc=1.12, exclude_bonded=1, p=0.5)
+    nb = ctypes.c_int32(7)
+    st = b.Stats()
+    st.in_rc = 99
+    code = b.lib.pr_react_step(0, ctypes.c_float(10.0), None, None, None, None, None, None, 4,
+                               ctypes.byref(r), 1, 1, None, 0, ctypes.byref(nb), ctypes.byref(st),
+                               None)
+    assert code == b.PR_OK and nb.value == 0
+    assert all(v == 0 for v in st.as_dict().values())

@@ -54,6 +54,21 @@ def test_hand_cases(B, case, p):
         compare_step(_cfg_from_sys(s), _rule("step", p), seed, 1 + seed, name)
 
 
+def test_empty_and_single_particle(B):
+    """No particles, and one lone A or T: no candidates, no bonds, the oracle agrees."""
+    import torch
+    z = torch.empty(0, dtype=torch.float32, device="cuda")
+    zi = torch.empty(0, dtype=torch.int32, device="cuda")
+    code, bonds, st = B.react_step(z, z, z, zi, zi, torch.empty((0, 4), dtype=torch.int32,
+                                                                 device="cuda"),
+                                   10.0, _rule("step", 1.0), 1, 1)
+    assert code == B.PR_OK and bonds.shape[0] == 0 and all(v == 0 for v in st.values())
+    for typ, state in ((1, 4), (0, 2)):
+        s = pins.mk(10.0, [(5, 5, 5)], [typ], [state])
+        g, st = compare_step(_cfg_from_sys(s), _rule("step", 1.0), 3, 1, "single")
+        assert len(g) == 0 and st["in_rc"] == 0
+
+
 def test_strict_cutoff(B):
     s = pins.mk(10.0, [(1, 1, 1), (2, 1, 1)], [1, 0], [4, 2])
     g, st = compare_step(_cfg_from_sys(s), _rule("step", 1.0, rc=1.0), 1, 1, "r2==rc2")
