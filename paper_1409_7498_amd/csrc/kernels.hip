@@ -529,6 +529,18 @@ __device__ __forceinline__ float dist2_plain(float xj, float yj, float zj, float
   return __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz));
 }
 
+// dist2 of two positions whose differences lie within (-L/2, L/2) in every
+// component but axis kAxis (there the minimum image is taken as in dist2):
+// the same value as dist2.
+template <int kAxis>
+__device__ __forceinline__ float dist2_axis(const Dev& d, float xj, float yj, float zj, float4 a) {
+  float dx = __fsub_rn(xj, a.x), dy = __fsub_rn(yj, a.y), dz = __fsub_rn(zj, a.z);
+  if (kAxis == 0) dx = min_image(dx, d.L, d.halfL);
+  if (kAxis == 1) dy = min_image(dy, d.L, d.halfL);
+  if (kAxis == 2) dz = min_image(dz, d.L, d.halfL);
+  return __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz));
+}
+
 __device__ __forceinline__ bool row_has(const int32_t* row, int B, int32_t v) {
   for (int b = 0; b < B; ++b)
     if (row[b] == v) return true;
@@ -768,7 +780,7 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
   int s0, s1;
   range_of<kBrick>(d, w, s0, s1);
   int bx = 0, ex = 0, by = 0, ey = 0, bz = 0, ez = 0;
-  bool staged = false, nowrap = false;
+  bool staged = false, nowrap = false, plain_x = false, plain_y = false, plain_z = false;
   const int nc = d.nc;
   int ncs = 0;
   uint32_t mine = 0, mine2 = 0, m_exy = 0, m_ex = 0;
@@ -791,8 +803,10 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
     // a region that does not wrap around the box and spans less than half of
     // it: a difference of two positions in it is below L/2 in magnitude, and
     // the minimum image leaves it unchanged
-    nowrap = d.nbricks > 1 && bx + ex <= nc && by + ey <= nc && bz + ez <= nc &&
-             2 * ex + 1 <= nc && 2 * ey + 1 <= nc && 2 * ez + 1 <= nc;
+    plain_x = d.nbricks > 1 && bx + ex <= nc && 2 * ex + 1 <= nc;
+    plain_y = d.nbricks > 1 && by + ey <= nc && 2 * ey + 1 <= nc;
+    plain_z = d.nbricks > 1 && bz + ez <= nc && 2 * ez + 1 <= nc;
+    nowrap = plain_x && plain_y && plain_z;
     ncs = ex * ey * ez;
     m_exy = recip16((uint32_t)(ex * ey));
     m_ex = recip16((uint32_t)ex);
@@ -838,10 +852,14 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
   // the workgroup-uniform switches of the pass loop, one scalar register
   // whose bits are tested where they are used (kept as separate booleans
   // they would each occupy a 64-bit lane mask)
+  // kFWrapX/Y/Z: only that axis of the region needs the minimum image
   constexpr uint32_t kFJit = 1u, kFMove = 2u, kFStaged = 4u, kFNowrap = 8u;
+  constexpr uint32_t kFWrapX = 16u, kFWrapY = 32u, kFWrapZ = 64u;
   const uint32_t flags0 = (uint32_t)__builtin_amdgcn_readfirstlane(
       (jit ? kFJit : 0u) | (d.jitter ? kFMove : 0u) | (staged ? kFStaged : 0u) |
-      (nowrap ? kFNowrap : 0u));
+      (nowrap ? kFNowrap : 0u) | (!plain_x && plain_y && plain_z ? kFWrapX : 0u) |
+      (plain_x && !plain_y && plain_z ? kFWrapY : 0u) |
+      (plain_x && plain_y && !plain_z ? kFWrapZ : 0u));
   SweepAcc n = {0, 0, 0, 0};
   for (int base = s0; base < s1 && !dead; base += kTP) {
     if (base != s0) cur = load_part<kBrick>(a, X, Y, Z, base + tid, s1);
@@ -897,22 +915,26 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
             const int p3 = p2 + (int)s_off[l2 + 2] - b2;
             const int tot = p3 + (int)s_off[l3 + 2] - b3;
             const int o1 = b1 - p1, o2 = b2 - p2, o3 = b3 - p3;
+            // the four runs, with the distance of the region's kind
+            auto scan = [&](auto dist) {
+              for (int q = 0; q < tot; ++q) {
+                const int r = q + (q < p1 ? b0 : (q < p2 ? o1 : (q < p3 ? o2 : o3)));
+                if (dist(s_rec[r]) < d.rc2) {
+                  hits |= (uint32_t)r << ((8 * nh) & 31);
+                  nh++;
+                }
+              }
+            };
             if (fl & kFNowrap) {  // no difference can reach L/2 in this region
-              for (int q = 0; q < tot; ++q) {
-                const int r = q + (q < p1 ? b0 : (q < p2 ? o1 : (q < p3 ? o2 : o3)));
-                if (dist2_plain(px, py, pz, s_rec[r]) < d.rc2) {
-                  hits |= (uint32_t)r << ((8 * nh) & 31);
-                  nh++;
-                }
-              }
+              scan([&](float4 a) { return dist2_plain(px, py, pz, a); });
+            } else if (fl & kFWrapX) {  // the region wraps (or spans half the box) in x only
+              scan([&](float4 a) { return dist2_axis<0>(d, px, py, pz, a); });
+            } else if (fl & kFWrapY) {
+              scan([&](float4 a) { return dist2_axis<1>(d, px, py, pz, a); });
+            } else if (fl & kFWrapZ) {
+              scan([&](float4 a) { return dist2_axis<2>(d, px, py, pz, a); });
             } else {
-              for (int q = 0; q < tot; ++q) {
-                const int r = q + (q < p1 ? b0 : (q < p2 ? o1 : (q < p3 ? o2 : o3)));
-                if (dist2(d, px, py, pz, s_rec[r]) < d.rc2) {
-                  hits |= (uint32_t)r << ((8 * nh) & 31);
-                  nh++;
-                }
-              }
+              scan([&](float4 a) { return dist2(d, px, py, pz, a); });
             }
             defer = nh > 4;
           }
