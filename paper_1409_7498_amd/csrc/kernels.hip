@@ -1098,6 +1098,59 @@ __device__ __forceinline__ void make_bond(const Dev& d, const Arr& a, uint32_t p
   }
 }
 
+// The operands of a bond read ahead of the decision, together with the A's
+// key: both states and types and (rows of width B <= kAdjStage) both
+// adjacency rows.  Every particle takes at most one bond per step, and only
+// that bond writes its state and row, so values read ahead are the ones a
+// bond made after the decision would read.
+struct BondOps {
+  int32_t sta, stt, tya, tyt;
+  int4 rowa, rowt;
+};
+
+__device__ __forceinline__ int4 load_row4(const int32_t* row, int B) {
+  int4 r = make_int4(0, 0, 0, 0);  // entries beyond B are not used
+  r.x = row[0];
+  if (B > 1) r.y = row[1];
+  if (B > 2) r.z = row[2];
+  if (B > 3) r.w = row[3];
+  return r;
+}
+
+// The slot adj_append would fill in a row read ahead (B when it is full).
+__device__ __forceinline__ int first_empty(int4 r, int B) {
+  if (r.x < 0) return 0;
+  if (B > 1 && r.y < 0) return 1;
+  if (B > 2 && r.z < 0) return 2;
+  if (B > 3 && r.w < 0) return 3;
+  return B;
+}
+
+// make_bond with its operands read ahead (rows of width B <= kAdjStage).
+__device__ __forceinline__ void make_bond_ahead(const Dev& d, const Arr& a, uint32_t par, int w,
+                                                int ida, int sa, int sj, int idj,
+                                                const BondOps& o, const BondCtx& b) {
+  const int32_t na = o.sta + d.rule.d_a, nt = o.stt + d.rule.d_t;
+  a.st[sa] = na;
+  a.st[sj] = nt;
+  a.role[sa] = role_of(d, o.tya, na);
+  a.role[sj] = role_of(d, o.tyt, nt);
+  int lost = 0;
+  const int fa = first_empty(o.rowa, d.B), ft = first_empty(o.rowt, d.B);
+  if (fa < d.B) a.adj[(size_t)sa * d.B + fa] = (int32_t)idj;
+  else lost++;
+  if (ft < d.B) a.adj[(size_t)sj * d.B + ft] = (int32_t)ida;
+  else lost++;
+  if (lost) atomicAdd(b.lost, lost);
+  const int p = atomicAdd(b.nw, 1);
+  if (p < kWinCap) {
+    pick(d.wgw, par)[w * kWinCap + p] = make_int2(ida, idj);
+  } else {
+    const uint32_t q = atomicAdd(&d.ctl->nwin_ovf[par], 1u);
+    pick(d.wov, par)[q] = make_int2(ida, idj);
+  }
+}
+
 // kWave: one wavefront per unit (four units per workgroup, unit = blockIdx.x
 // * 4 + wavefront); else the whole workgroup handles unit w.  Every barrier
 // is taken by the whole workgroup (mode is the same for all its units).
@@ -1127,15 +1180,35 @@ __device__ __forceinline__ void resolve_body(const Dev& d, int k, int w, int nun
   const Arr a = pick_set(d, c->set & 1u);
   const BondCtx bc{&s_nw[g], &s_lost[g]};
   if (mode == 1) {
-    const int ne = live ? pick(d.wgo, par)[w * kWgOut + kOutRet] : 0;
-    bool chosen = false;
+    // the list's length and its entries in one round trip (entries past the
+    // length are read but not used), then the A keys with the bonds'
+    // operands in a second one
+    int ne = 0;
     int4 e = make_int4(0, 0, 0, 0);
+    uint32_t w2 = 0;
+    if (live) {
+      ne = pick(d.wgo, par)[w * kWgOut + kOutRet];
+      if (tid < kRetCap) {
+        e = pick(d.wge, par)[w * kRetCap + tid];
+        w2 = pick(d.wgk, par)[w * kRetCap + tid];
+      }
+    }
+    const bool ahead = d.adj_staged != 0;
+    bool chosen = false;
     unsigned long long key = kEmpty;
+    BondOps ops{0, 0, 0, 0, make_int4(0, 0, 0, 0), make_int4(0, 0, 0, 0)};
     if (tid < ne) {
-      e = pick(d.wge, par)[w * kRetCap + tid];
-      const uint32_t w2 = pick(d.wgk, par)[w * kRetCap + tid];
+      const unsigned long long ka = d.slotA[e.x];
+      if (ahead) {
+        ops.sta = a.st[e.y];
+        ops.stt = a.st[e.z];
+        ops.tya = a.typ[e.y];
+        ops.tyt = a.typ[e.z];
+        ops.rowa = load_row4(a.adj + (size_t)e.y * d.B, d.B);
+        ops.rowt = load_row4(a.adj + (size_t)e.z * d.B, d.B);
+      }
       d.tflag[e.z] = 0;
-      chosen = (uint32_t)d.slotA[e.x] == (uint32_t)e.w;
+      chosen = (uint32_t)ka == (uint32_t)e.w;
       if (chosen) {
         d.slotA[e.x] = kEmpty;
         key = ((unsigned long long)w2 << 32) | (uint32_t)e.x;
@@ -1149,7 +1222,10 @@ __device__ __forceinline__ void resolve_body(const Dev& d, int k, int w, int nun
       bool win = true;
       for (int f = 0; f < ne; ++f)
         if (s_sj[g][f] == e.z && s_key[g][f] < key) win = false;
-      if (win) make_bond(d, a, par, w, e.x, e.y, e.z, e.w, bc);
+      if (win) {
+        if (ahead) make_bond_ahead(d, a, par, w, e.x, e.y, e.z, e.w, ops, bc);
+        else make_bond(d, a, par, w, e.x, e.y, e.z, e.w, bc);
+      }
     }
   } else if (mode == 2 && live) {
     const float *X = pick(a.x, par ^ 1u), *Y = pick(a.y, par ^ 1u), *Z = pick(a.z, par ^ 1u);
