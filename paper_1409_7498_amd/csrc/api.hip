@@ -127,7 +127,7 @@ void set_geometry(Dev& d, int32_t n, float L, int32_t B, const pr_rule* r, uint6
     d.nb = 1;
   }
   d.nbricks = d.nb * d.nb * d.nb;
-  d.nd = (d.bs + 1) * (d.bs + 1) * (d.bs + 1);
+  d.nd = (d.bs + 1) * (d.bs + 1) * (d.bs + 1) + 1;  // the brick's A's, then its dual cells
   d.nb_m = (uint32_t)((1ull << 32) / (unsigned long long)d.nb);  // nb >= 1; nb = 1 gives 0
   d.sorted = 0;
   // closing groups cover the larger of the two sweep grids (dense, bricks)

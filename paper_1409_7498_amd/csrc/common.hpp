@@ -35,7 +35,7 @@ static_assert(kStageCells <= 2 * kThreads, "the sweep stages two region cells pe
 constexpr int kOneCellBrick = 4;
 constexpr int kStageCells1 = (kOneCellBrick + 2) * (kOneCellBrick + 2) * (kOneCellBrick + 2);
 static_assert(kStageCells1 <= kThreads, "one region cell per thread");
-static_assert((kMaxBrick + 1) * (kMaxBrick + 1) * (kMaxBrick + 1) <= 6 * 64,
+static_assert((kMaxBrick + 1) * (kMaxBrick + 1) * (kMaxBrick + 1) + 1 <= 6 * 64,
               "the per-brick sort scan takes up to six bins per lane");
 constexpr int kStageRecs = 256;
 constexpr int kTPass = 768;         // particles a sweep workgroup holds per pass (3 per thread)
@@ -97,9 +97,9 @@ struct Dev {
   int2* wgw[2];         // staged bonds (id_A, id_T), kWinCap per workgroup, by parity
   int2* wov[2];         // staged bonds beyond kWinCap (capacity n/2 + 1 each)
   int32_t* abst[2];     // per prep workgroup: A's binned, by parity
-  // spatial sort: bricks, and within a brick its (bs + 1)^3 "dual cells"
-  // (nd bins per brick): per-bin counts, offsets within the brick, and the
-  // rank of every particle within its bin
+  // spatial sort: bricks, and within a brick its A's, then its (bs + 1)^3
+  // "dual cells" (nd bins per brick): per-bin counts, offsets within the
+  // brick, and the rank of every particle within its bin
   int32_t* bstart;      // nbricks + 1 slot offsets
   uint32_t* bcnt;
   uint32_t *dcnt, *dloc;
@@ -116,7 +116,7 @@ struct Dev {
   // geometry, rule, draws
   int32_t n, B, nc, ncell, nwg_sweep, nwg_prep, ngroups;
   int32_t bs, nb, nbricks, sorted;  // brick edge (cells), bricks per side, total, storage sorted
-  int32_t nd;                        // sort bins per brick, (bs + 1)^3
+  int32_t nd;                        // sort bins per brick, (bs + 1)^3 + 1
   uint32_t nb_m;                     // floor(2^32 / nb): brick coordinates by multiplication
   int32_t jitter;       // 1: resident system (positions ping-pong, re-jitter by jit_c)
                         // 0: caller's arrays, read only

@@ -1319,11 +1319,14 @@ __global__ __launch_bounds__(kFinThreads) void k_single_sort(Dev d) {
 // which also rebuilds the A list in brick order.  Results never depend on the
 // storage order; the sort only gives each sweep workgroup a compact region.
 // ---------------------------------------------------------------------------
-// The sort bin of a particle: its brick b and, within it, its dual cell
-// floor(u - 1/2) (u = position / cell width; bs + 1 values per dimension from
-// the brick's first cell - 1).  All T's of one dual cell have the same 2x2x2
-// partner block, so a wavefront of them scans runs of equal length.
-__device__ __forceinline__ int sort_bin(const Dev& d, float x, float y, float z, int& b) {
+// The sort bin of a particle: its brick b and, within it, bin 0 for an A
+// (the brick's few A's then share a handful of cache lines, which the binning
+// of every step reads), else 1 + its dual cell floor(u - 1/2) (u = position /
+// cell width; bs + 1 values per dimension from the brick's first cell - 1).
+// All T's of one dual cell have the same 2x2x2 partner block, so a wavefront
+// of them scans runs of equal length.
+__device__ __forceinline__ int sort_bin(const Dev& d, float x, float y, float z, uint8_t role,
+                                        int& b) {
   const float ux = __fmul_rn(x, d.inv_w), uy = __fmul_rn(y, d.inv_w), uz = __fmul_rn(z, d.inv_w);
   const int nc = d.nc, bs = d.bs, e = bs + 1;
   int bx = 0, by = 0, bz = 0;
@@ -1336,7 +1339,7 @@ __device__ __forceinline__ int sort_bin(const Dev& d, float x, float y, float z,
   const int lx = min(max((int)floorf(__fsub_rn(ux, 0.5f)) - (bx * bs - 1), 0), bs);
   const int ly = min(max((int)floorf(__fsub_rn(uy, 0.5f)) - (by * bs - 1), 0), bs);
   const int lz = min(max((int)floorf(__fsub_rn(uz, 0.5f)) - (bz * bs - 1), 0), bs);
-  return b * d.nd + (lz * e + ly) * e + lx;
+  return b * d.nd + (role == kRoleA ? 0 : 1 + (lz * e + ly) * e + lx);
 }
 
 // Ranks within sort bins (one returning atomic per particle; the bins are
@@ -1346,12 +1349,13 @@ __device__ __forceinline__ void sort_count_body(const Dev& d, int k) {
   const Arr a = pick_set(d, d.ctl->set & 1u);
   const uint32_t par = d.ctl->par0;
   int b;
-  const int bin = sort_bin(d, pick(a.x, par)[k], pick(a.y, par)[k], pick(a.z, par)[k], b);
+  const int bin =
+      sort_bin(d, pick(a.x, par)[k], pick(a.y, par)[k], pick(a.z, par)[k], a.role[k], b);
   d.rank[k] = (int32_t)atomicAdd(&d.dcnt[bin], 1u);
 }
 
 // Offsets of the bins within brick b (one wavefront, up to six consecutive
-// bins per lane: nd = (bs + 1)^3 <= 343), the brick's total for the scan
+// bins per lane: nd = (bs + 1)^3 + 1 <= 344), the brick's total for the scan
 // over bricks; the counts are cleared for the next sort.
 __device__ __forceinline__ void sort_local_body(const Dev& d, int b) {
   if (b >= d.nbricks) return;
@@ -1407,15 +1411,16 @@ __device__ __forceinline__ void sort_scatter_body(const Dev& d, int k) {
   const uint32_t s = d.ctl->set & 1u, par = d.ctl->par0;
   const Arr a = pick_set(d, s), o = pick_set(d, s ^ 1u);
   const float x = pick(a.x, par)[k], y = pick(a.y, par)[k], z = pick(a.z, par)[k];
+  const uint8_t role = a.role[k];
   int b;
-  const int bin = sort_bin(d, x, y, z, b);
+  const int bin = sort_bin(d, x, y, z, role, b);
   const int ns = d.bstart[b] + (int)d.dloc[bin] + d.rank[k];
   pick(o.x, par)[ns] = x;
   pick(o.y, par)[ns] = y;
   pick(o.z, par)[ns] = z;
   o.typ[ns] = a.typ[k];
   o.st[ns] = a.st[k];
-  o.role[ns] = a.role[k];
+  o.role[ns] = role;
   const int id = a.id[k];
   o.id[ns] = id;
   for (int q = 0; q < d.B; ++q) o.adj[(size_t)ns * d.B + q] = a.adj[(size_t)k * d.B + q];
