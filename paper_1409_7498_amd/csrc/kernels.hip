@@ -315,6 +315,7 @@ __global__ __launch_bounds__(kThreads) void k_generate(Dev d, int kind, unsigned
 // also takes the bonds beyond the staging windows and resets the step's
 // per-parity counters.
 // ---------------------------------------------------------------------------
+static_assert(kWinCap >= 2, "the closing reads two staged bonds ahead");
 __device__ void close_group(const Dev& d, uint32_t par, uint32_t step, uint32_t sidx, int g,
                             uint32_t* s_wave) {
   __shared__ int s_sum[kPart];
@@ -323,11 +324,18 @@ __device__ void close_group(const Dev& d, uint32_t par, uint32_t step, uint32_t 
   const int tid = threadIdx.x;
   if (tid < kPart) s_sum[tid] = 0;
   const int w = g * kGroup + tid;
+  const int2* staged = pick(d.wgw, par) + w * kWinCap;
   int o[kWgOut] = {0, 0, 0, 0, 0, 0, 0, 0};
+  // a workgroup stages 0.3 bonds per step on average: its first two are read
+  // with its counters, before their number is known (a window holds
+  // kWinCap >= 2), which saves a dependent round trip in the common case
+  int2 pre[2] = {make_int2(0, 0), make_int2(0, 0)};
   if (w < d.nwg_sweep) {
     const int32_t* src = pick(d.wgo, par) + w * kWgOut;
 #pragma unroll
     for (int q = 0; q < kWgOut; ++q) o[q] = src[q];
+    pre[0] = staged[0];
+    pre[1] = staged[1];
   }
   int a_elig = 0;  // the A-bin workgroup counts, strided over the groups
   for (int q = w; q < d.nwg_prep; q += d.ngroups * kGroup) a_elig += pick(d.abst, par)[q];
@@ -344,10 +352,9 @@ __device__ void close_group(const Dev& d, uint32_t par, uint32_t step, uint32_t 
   for (int q = 0; q < kPart; ++q) wave_add(&s_sum[q], v[q]);
   __syncthreads();
   const uint64_t row0 = s_row;
-  const int2* staged = pick(d.wgw, par) + w * kWinCap;
   for (uint32_t e = 0; e < nw; ++e) {
     const uint64_t row = row0 + off + e;
-    const int2 b = staged[e];
+    const int2 b = e < 2 ? pre[e] : staged[e];
     if ((int64_t)row < d.log_cap) {
       d.log[3 * row] = (int32_t)step;
       d.log[3 * row + 1] = b.x;
