@@ -1349,16 +1349,36 @@ __device__ __forceinline__ int sort_bin(const Dev& d, float x, float y, float z,
   return b * d.nd + (role == kRoleA ? 0 : 1 + (lz * e + ly) * e + lx);
 }
 
-// Ranks within sort bins (one returning atomic per particle; the bins are
-// fine, so lanes rarely share one and there is little to aggregate).
+// Ranks within sort bins.  The storage is in bin order from the previous
+// sort, so the 64 particles of a wavefront fall into few bins: the lowest lane
+// of each bin reserves the ranks of all its lanes with one returning atomic.
 __device__ __forceinline__ void sort_count_body(const Dev& d, int k) {
-  if (k >= d.n) return;
+  const bool valid = k < d.n;
   const Arr a = pick_set(d, d.ctl->set & 1u);
   const uint32_t par = d.ctl->par0;
-  int b;
-  const int bin =
-      sort_bin(d, pick(a.x, par)[k], pick(a.y, par)[k], pick(a.z, par)[k], a.role[k], b);
-  d.rank[k] = (int32_t)atomicAdd(&d.dcnt[bin], 1u);
+  int b, bin = -1;
+  if (valid)
+    bin = sort_bin(d, pick(a.x, par)[k], pick(a.y, par)[k], pick(a.z, par)[k], a.role[k], b);
+  // group the lanes by bin: each round takes the lowest ungrouped lane's bin
+  int leader = 0;
+  unsigned long long peers = 0ull;
+  unsigned long long todo = __ballot(valid);
+  while (todo) {
+    const int ld = (int)__builtin_ctzll(todo);
+    const int lb = __builtin_amdgcn_readlane(bin, ld);
+    const bool mine = valid && bin == lb;
+    const unsigned long long m = __ballot(mine);
+    if (mine) {
+      leader = ld;
+      peers = m;
+    }
+    todo &= ~m;
+  }
+  uint32_t r = 0u;
+  if (valid && __lane_id() == (unsigned)leader)
+    r = atomicAdd(&d.dcnt[bin], (uint32_t)__popcll(peers));
+  r = (uint32_t)__shfl((int)r, leader);
+  if (valid) d.rank[k] = (int32_t)(r + lanes_below(peers));
 }
 
 // Offsets of the bins within brick b (one wavefront, up to six consecutive
