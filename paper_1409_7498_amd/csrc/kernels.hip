@@ -16,8 +16,9 @@
 //   k_resolve  per sweep workgroup (one wavefront each), the listed pairs
 //              whose A chose their T; of those the smallest (w2, id_A) per T
 //              is bonded, states and adjacency updated (steps 6-9)
-// plus the counting sort of the storage by brick and dual cell, the synthetic generator and
-// the helpers of the runtime.
+// plus the counting sort of the storage by brick (within a brick its A's,
+// then the rest by dual cell), the synthetic generator and the helpers of the
+// runtime.
 //
 // Arithmetic follows the contract of include/polyreact.h: FP32 min-image
 // distance with explicitly rounded operations (no contraction), Philox4x32-10
@@ -1322,9 +1323,10 @@ __global__ __launch_bounds__(kFinThreads) void k_single_sort(Dev d) {
 }
 
 // ---------------------------------------------------------------------------
-// Spatial sort of the storage by brick (counting sort: count, scan, scatter),
-// which also rebuilds the A list in brick order.  Results never depend on the
-// storage order; the sort only gives each sweep workgroup a compact region.
+// Spatial sort of the storage by brick, within a brick its A's first and the
+// rest by dual cell (counting sort: count, per-brick scan, scan over bricks,
+// scatter).  Results never depend on the storage order; the sort only gives
+// each sweep workgroup a compact region and its wavefronts similar blocks.
 // ---------------------------------------------------------------------------
 // The sort bin of a particle: its brick b and, within it, bin 0 for an A
 // (the brick's few A's then share a handful of cache lines, which the binning
