@@ -1452,7 +1452,15 @@ __device__ __forceinline__ void sort_scatter_body(const Dev& d, int k) {
   o.role[ns] = role;
   const int id = a.id[k];
   o.id[ns] = id;
-  for (int q = 0; q < d.B; ++q) o.adj[(size_t)ns * d.B + q] = a.adj[(size_t)k * d.B + q];
+  // rows of width 4 or 2 move as one vector when both arrays are aligned
+  const bool vec = (((uintptr_t)a.adj | (uintptr_t)o.adj) & 15u) == 0u;
+  if (vec && d.B == 4) {
+    ((int4*)o.adj)[ns] = ((const int4*)a.adj)[k];
+  } else if (vec && d.B == 2) {
+    ((int2*)o.adj)[ns] = ((const int2*)a.adj)[k];
+  } else {
+    for (int q = 0; q < d.B; ++q) o.adj[(size_t)ns * d.B + q] = a.adj[(size_t)k * d.B + q];
+  }
 }
 
 // ---------------------------------------------------------------------------
