@@ -15,8 +15,8 @@ run of the next steps.
 ``copy_gbs`` is the measured ceiling of a plain device copy (bytes read and
 written per second) and ``frac_of_copy`` the sweep's rate against it.
 ``traffic`` is the sweep's HBM traffic per launch from the profiler
-counters recorded under profiles/ (null when the kernel source changed
-since).  ``cpu_baseline`` times the CPU oracle on one full step of the same
+counters recorded under profiles/ for the default workload (null when the
+kernel source changed since, and for any other workload or brick edge).  ``cpu_baseline`` times the CPU oracle on one full step of the same
 workload.
 
 Prints ONE JSON line.  ``--gpus N`` with N > 1 exits: this build runs on one GPU.
@@ -299,8 +299,10 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--sort-period", type=int, default=-1)
-    ap.add_argument("--brick", type=int, default=0,
-                    help="brick edge in coarse cells, 1..6 (0 = the library default, 4)")
+    ap.add_argument("--brick", default="0",
+                    help="brick edge in coarse cells, 1..6 (0 = the library default, 4), "
+                         "or 'auto': the device autotuner's choice for the workload "
+                         "(untimed set-up)")
     ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--max-brick", type=int, default=4,
                     help="c4: largest brick edge the tuned ensemble may use (edges 5-6 "
@@ -339,8 +341,17 @@ def main():
     cfg = workload.CONFIGS[args.config]
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    tuned = None
+    if args.brick == "auto":
+        desc = dict(n=cfg.N, L=cfg.L, B=cfg.B, rule=cfg.rule(), seed=cfg.seed, kind=cfg.kind,
+                    gen_seed=cfg.seed, sigma0=workload.SIGMA_LATTICE, log_cap=2 * cfg.N)
+        brick, us = binding.autotune(desc, 128, cfg.sigma, stream=stream)
+        tuned = {b: round(t, 3) for b, t in sorted(us.items())}
+        log("autotune: edge %d, us per step by edge %s" % (brick, tuned))
+    else:
+        brick = int(args.brick)
     sysm = binding.System(cfg.N, cfg.L, cfg.B, cfg.rule(), cfg.seed,
-                          log_cap=cfg.N * 2, stream=stream, brick=args.brick)
+                          log_cap=cfg.N * 2, stream=stream, brick=brick)
     if args.sort_period >= 0:
         sysm.set_sort_period(args.sort_period)
     sort_period = 64 if args.sort_period < 0 else args.sort_period
@@ -375,7 +386,9 @@ def main():
     sweep_bytes = SWEEP_B_PER_PARTICLE * cfg.N
     step_bytes = SWEEP_B_PER_PARTICLE * cfg.N + BOND_B * bonds
     achieved = sweep_bytes / (sweep_ms * 1e-3) / 1e9
-    traffic = recorded_traffic()
+    # the counters were taken on the default workload at the default edge
+    profiled = args.config == "c2" and sysm.geometry()[1] == 4 and sort_period == 64
+    traffic = recorded_traffic() if profiled else None
     out = {
         "metric": "reaction-step particles/s at 1M + % HBM roofline",
         "value": cfg.N / (step_ms * 1e-3),
@@ -396,7 +409,7 @@ def main():
                                   "5% crosslinkers" if cfg.kind == "step" else "0.1% initiators",
                                   cfg.sigma),
                    "steps_timed": K, "sort_period": sort_period,
-                   "brick": sysm.geometry()[1]},
+                   "brick": sysm.geometry()[1], "brick_autotune_us": tuned},
         "step_roofline_frac": step_bytes / (step_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
         "prep_ms_direct": prep_ms,
         "sweep_ms_direct": sweep_ms,
