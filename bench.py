@@ -3,21 +3,35 @@
 Workload: step growth, N = 1,048,576 particles in L = 105.6 (jittered lattice,
 5% crosslinkers, r_c = 1.12, p = 0.005), generated on the device.  One step =
 the re-jitter of every particle (the stand-in for the MD between reaction
-steps, fused into the pair sweep) followed by the reaction step.  ``value``
-is whole-job throughput in particles/s: N x steps / wall time of the timed
-steps, replayed from captured HIP graphs with the state resident in HBM.
+steps, fused into the pair sweep) followed by the reaction step.  The storage
+is re-sorted spatially every 64 steps.
+
+Timed region: exactly --steps steps after --warmup steps, replayed from HIP
+graphs captured beforehand (pr_sys_prepare), state resident in HBM, HIP
+events on the system's stream.  The window holds the sorts that fall due in
+it (none, or more than one per 64 steps, when --steps is not a multiple of 64
+or the window is not aligned to the sort period).  ``value`` charges exactly
+one sort per 64 steps: the window's time minus the sorts it held plus
+steps/64 sorts, each sort timed on its own in the phase-timed run that
+follows; ``window_ms`` is the raw time of the window and the JSON states the
+sorts it held.
+
+``reaction_only`` separates the reaction step from the MD stand-in: the
+per-step time minus the re-jitter alone (pr_sys_jitter, its kernel's own
+duration over the same number of steps).
 
 ``roofline`` covers the dominant kernel, the pair sweep: its algorithmic
 bytes per launch (positions read and written, type and state) over its mean
 duration, measured with events stamped at each sweep's own start and end
-(hipExtLaunchKernel) on the system's stream, in a second, directly launched
-run of the next steps.
-``copy_gbs`` is the measured ceiling of a plain device copy (bytes read and
-written per second) and ``frac_of_copy`` the sweep's rate against it.
-``traffic`` is the sweep's HBM traffic per launch from the profiler
-counters recorded under profiles/ for the default workload (null when the
-kernel source changed since, and for any other workload or brick edge).  ``cpu_baseline`` times the CPU oracle on one full step of the same
-workload.
+(hipExtLaunchKernel) on the system's stream, in a directly launched run of
+the next steps.  ``copy_gbs`` is the measured ceiling of the library's own
+copy kernel (pr_stream_copy, 16 bytes per lane, bytes read plus written per
+second) and ``frac_of_copy`` the sweep's rate against it.  ``traffic`` is
+the sweep's HBM traffic per launch from the profiler counters recorded under
+profiles/ for the default workload (null when the kernel source changed
+since, and for any other workload or brick edge).  ``cpu_baseline`` times
+the CPU oracle on one full step of the same workload and reports the FP64
+recheck of that step's cutoff decisions.
 
 Prints ONE JSON line.  ``--gpus N`` with N > 1 exits: this build runs on one GPU.
 """
@@ -35,6 +49,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 SWEEP_B_PER_PARTICLE = 32.0   # x, y, z read (12) + type, state (8) + re-jittered x, y, z written (12)
 BOND_B = 24.0                 # per new bond: the pair, two states, two adjacency entries
+REACT_B_PER_PARTICLE = 20.0   # the reaction step alone: x, y, z read (12) + type, state (8)
 COUNTERS = os.path.join(ROOT, "profiles", "k_sweep_step_growth_1M_counters.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_1409_7498_amd", "csrc", "kernels.hip")
 
@@ -66,17 +81,23 @@ def cpu_baseline(cfg):
     reaction step) of the same workload."""
     import oracle
     from paper_1409_7498_amd import workload
-    g = workload.generate(cfg.N, cfg.L, cfg.kind, cfg.seed)
+    g = cfg.initial()
     s = oracle.System(g["L"], g["x"], g["y"], g["z"], g["type"], g["state"], g["adj"])
     rule = oracle.Rule(**cfg.rule())
     t0 = time.perf_counter()
     code, _, _ = oracle.run(s, rule, cfg.seed, 1, 1, cfg.sigma)
     dt = time.perf_counter() - t0
     assert code == 0
+    # FP64 recheck of the same step's cutoff decisions (after its re-jitter,
+    # on the states before it), outside the timed part
+    r = oracle.System(g["L"], g["x"], g["y"], g["z"], g["type"], g["state"], g["adj"])
+    oracle.jitter(r, cfg.seed, 1, cfg.sigma)
+    near, dis = oracle.near_cutoff(r, rule, 1e-6)
     return {"value": cfg.N / dt, "unit": "particles/s", "cores": oracle.num_threads(),
             "kind": "oracle",
             "sample": "one full step (re-jitter + O(N_A N) brute-force reaction step, Table I "
-                      "steps 1-9) of the %d-particle workload: %.1f s wall" % (cfg.N, dt)}
+                      "steps 1-9) of the %d-particle workload: %.1f s wall" % (cfg.N, dt),
+            "fp64_recheck": {"step": 1, "tol": 1e-6, "near": near, "disagree": dis}}
 
 
 def tune_bricks(binding, descs, steps, sigma, target_wgs=4096, max_copies=256, max_brick=6):
@@ -272,22 +293,16 @@ def bench_serve(args):
     print(json.dumps(res), flush=True)
 
 
-def copy_bandwidth(mib=1024, reps=5):
+def copy_bandwidth(mib=1024, reps=5, width=16):
     """Measured device copy ceiling in GB/s (bytes read plus written per
-    second): the median of `reps` torch copies of `mib` MiB timed with events."""
+    second): the median kernel time of `reps` copies of `mib` MiB with the
+    library's own copy kernel (pr_stream_copy)."""
     import torch
+    from paper_1409_7498_amd import binding
     src = torch.ones(mib << 18, dtype=torch.float32, device="cuda:0")
     dst = torch.empty_like(src)
-    dst.copy_(src)
-    times = []
-    for _ in range(reps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        dst.copy_(src)
-        e1.record()
-        torch.cuda.synchronize()
-        times.append(e0.elapsed_time(e1))
-    times.sort()
+    binding.stream_copy(src, dst, width)
+    times = sorted(binding.stream_copy(src, dst, width) for _ in range(reps))
     return 2 * src.numel() * 4 / (times[len(times) // 2] * 1e-3) / 1e9
 
 
@@ -313,8 +328,10 @@ def main():
     ap.add_argument("--baseline-requests", type=int, default=100,
                     help="c5: requests run through the plain per-replica loop")
     ap.add_argument("--probe-copy", type=int, default=0, metavar="MIB",
-                    help="only run a plain device copy of MIB MiB (calibrates the HBM "
-                         "byte counters of the profiler) and exit")
+                    help="only run the library's copy kernel on MIB MiB, three times "
+                         "(calibrates the HBM byte counters of the profiler), and exit")
+    ap.add_argument("--probe-width", type=int, default=16,
+                    help="--probe-copy: bytes per lane of the copy kernel (4, 8 or 16)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
@@ -323,14 +340,16 @@ def main():
 
     import torch
     if args.probe_copy:
+        from paper_1409_7498_amd import binding
         src = torch.ones(args.probe_copy << 18, dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        for _ in range(3):
-            dst.copy_(src)
+        ms = [binding.stream_copy(src, dst, args.probe_width) for _ in range(3)]
         torch.cuda.synchronize()
-        print(json.dumps({"probe": "copy", "bytes_read": src.numel() * 4,
-                          "bytes_written": dst.numel() * 4, "launches": 3}), flush=True)
+        print(json.dumps({"probe": "pr_stream_copy", "width": args.probe_width,
+                          "bytes_read": src.numel() * 4, "bytes_written": dst.numel() * 4,
+                          "launches": 3, "kernel_ms": ms,
+                          "gbs": 2 * src.numel() * 4 / (min(ms) * 1e-3) / 1e9}), flush=True)
         return
     from paper_1409_7498_amd import binding, workload
 
@@ -355,37 +374,52 @@ def main():
     if args.sort_period >= 0:
         sysm.set_sort_period(args.sort_period)
     sort_period = 64 if args.sort_period < 0 else args.sort_period
-    sysm.generate(cfg.kind, cfg.seed, workload.SIGMA_LATTICE)
+    sysm.generate(cfg.kind, cfg.gen_seed, workload.SIGMA_LATTICE)
     first = 1
     sysm.run(first, args.warmup, cfg.sigma)
     first += args.warmup
+    sysm.prepare(args.steps, cfg.sigma)  # the window's graphs, captured untimed
     torch.cuda.synchronize()
 
-    # timed region: K steps replayed from captured HIP graphs (blocks of one
-    # spatial sort + sort_period steps), events on the system's stream
+    # timed region: exactly K steps replayed from the captured HIP graphs,
+    # events on the system's stream
+    K = args.steps
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(stream)
-    sysm.run(first, args.steps, cfg.sigma)
+    sysm.run(first, K, cfg.sigma)
     e1.record(stream)
     torch.cuda.synchronize()
-    loop_ms = e0.elapsed_time(e1)
-    first += args.steps
-    K = args.steps
+    window_ms = e0.elapsed_time(e1)
+    # sorts the window held: steps with index (from 0) a multiple of the period
+    w0 = args.warmup
+    sorts_in = (sum(1 for k in range(w0, w0 + K) if k % sort_period == 0)
+                if sort_period > 0 else 0)
+    first += K
     st = sysm.stats()[-K:]
 
     # kernel timing: the next steps launched directly, HIP events around the
-    # prep kernel, the sweep kernel and whole steps
-    KT = min(K, 64)
+    # prep kernel, the sweep kernel, whole steps and each sort that falls due
+    # (a run of one period holds exactly one)
+    KT = max(min(K, 64), sort_period if sort_period > 0 else 0)
     ph = sysm.run_timed(first, KT, cfg.sigma)
+    first += KT
     sweep_ms = ph["sweep_ms"] / KT
     prep_ms = ph["prep_ms"] / KT
+    sort_ms = ph["sort_ms"] / ph["sorts"] if ph["sorts"] else 0.0
+    # the window with exactly K / sort_period sorts
+    step_ms = (window_ms - sorts_in * sort_ms) / K + (sort_ms / sort_period if sort_period else 0)
+    # the re-jitter alone over as many steps (kernel durations)
+    KJ = min(K, 64)
+    jit_ms = sysm.jitter(first, KJ, cfg.sigma, timed=True) / KJ
+    first += KJ
     n_t = sum(r["t_elig"] for r in st) / len(st)
     bonds = sum(r["bonds"] for r in st) / len(st)
-    step_ms = loop_ms / K
     sweep_bytes = SWEEP_B_PER_PARTICLE * cfg.N
     step_bytes = SWEEP_B_PER_PARTICLE * cfg.N + BOND_B * bonds
+    react_bytes = REACT_B_PER_PARTICLE * cfg.N + BOND_B * bonds
     achieved = sweep_bytes / (sweep_ms * 1e-3) / 1e9
+    react_ms = step_ms - jit_ms
     # the counters were taken on the default workload at the default edge
     profiled = args.config == "c2" and sysm.geometry()[1] == 4 and sort_period == 64
     traffic = recorded_traffic() if profiled else None
@@ -409,8 +443,19 @@ def main():
                                   "5% crosslinkers" if cfg.kind == "step" else "0.1% initiators",
                                   cfg.sigma),
                    "steps_timed": K, "sort_period": sort_period,
-                   "brick": sysm.geometry()[1], "brick_autotune_us": tuned},
+                   "brick": sysm.geometry()[1], "brick_autotune_us": tuned,
+                   "path": "graph replay (captured before the window)"},
+        "window_ms": window_ms,
+        "sorts_in_window": sorts_in,
+        "sort_ms": sort_ms,
+        "sort_charge": "value charges %s sorts per step (one per %d steps); the window held %d"
+                       % ("1/%d" % sort_period if sort_period else "no", sort_period, sorts_in),
         "step_roofline_frac": step_bytes / (step_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+        "reaction_only": {"ms_per_step": react_ms, "jitter_ms_per_step": jit_ms,
+                          "particles_per_s": cfg.N / (react_ms * 1e-3),
+                          "roofline_frac": react_bytes / (react_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+                          "how": "per-step time minus the re-jitter kernel alone "
+                                 "(pr_sys_jitter, same steps)"},
         "prep_ms_direct": prep_ms,
         "sweep_ms_direct": sweep_ms,
         "step_ms_direct": ph["step_ms"] / KT,
@@ -428,6 +473,7 @@ def main():
     if not args.no_cpu:
         log("timing the CPU oracle on one full step of the workload ...")
         out["cpu_baseline"] = cpu_baseline(cfg)
+        out["fp64_near_cutoff"] = out["cpu_baseline"]["fp64_recheck"]
     print(json.dumps(out), flush=True)
 
 

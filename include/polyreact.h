@@ -175,12 +175,31 @@ int pr_sys_generate(pr_sys* s, int32_t kind, uint64_t gen_seed, double sigma0);
 int pr_sys_run(pr_sys* s, uint32_t first_step, uint32_t n_steps, double sigma);
 
 /* Phase timing: like pr_sys_run, but every step is launched directly (no
- * graph) and the call synchronises; ms[0..2] receive the summed GPU time from
+ * graph) and the call synchronises; ms[0..4] receive the summed GPU time from
  * the start of each step to the start of its pair sweep (the binning of the
- * A particles), of whole steps, and of the pair-sweep kernels alone (their
- * own start and end, stamped by hipExtLaunchKernel), measured with HIP
- * events on the handle's stream. */
+ * A particles), of whole steps (a spatial sort excluded), of the pair-sweep
+ * kernels alone (their own start and end, stamped by hipExtLaunchKernel), of
+ * the spatial sorts that fell due during the run, and (as a float) the number
+ * of those sorts, measured with HIP events on the handle's stream. */
 int pr_sys_run_timed(pr_sys* s, uint32_t first_step, uint32_t n_steps, double sigma, float* ms);
+
+/* Captures, without running anything, the HIP graphs that a following
+ * pr_sys_run of n_steps steps with this sigma will replay, so that the run
+ * itself pays no capture (a latency-sensitive caller, a timed region).  A run
+ * of any length replays graphs: one per segment of steps between spatial
+ * sorts, cached by shape.  No effect when graphs are off.  Synchronous. */
+int pr_sys_prepare(pr_sys* s, uint32_t n_steps, double sigma);
+
+/* The re-jitter alone for steps first_step .. first_step + n_steps - 1: every
+ * particle moves exactly as the re-jitter of pr_sys_run's steps would move it
+ * (the stand-in for the MD integration between reaction steps), and no
+ * reaction happens (nothing is logged; a later run continues from the moved
+ * configuration with the next step numbers).  kernel_ms (host, may be NULL):
+ * receives the summed GPU time of the re-jitter kernels, stamped at each
+ * kernel's own start and end (the call then synchronises).  Used to separate
+ * the reaction step's own cost from the fused step's. */
+int pr_sys_jitter(pr_sys* s, uint32_t first_step, uint32_t n_steps, double sigma,
+                  float* kernel_ms);
 
 /* Copies the current configuration out in particle-id order (host or device
  * pointers per on_device; any pointer may be NULL to skip).  Synchronises;
@@ -221,11 +240,23 @@ int pr_sys_restore(pr_sys* s, const void* buf, int64_t bytes);
  * on it: every selection is a minimum over keys, whatever the storage order. */
 int pr_sys_set_sort_period(pr_sys* s, int32_t sort_period);
 
-/* on = 1 (default): pr_sys_run replays blocks of steps (one sort and
- * sort_period steps, or 32 steps without sorting) from a captured HIP graph;
+/* on = 1 (default): pr_sys_run replays its steps from captured HIP graphs,
+ * one per segment (a spatial sort when one is due, then the steps up to the
+ * next sort; 32 steps at a time without sorting), cached by segment shape;
  * on = 0: every kernel is launched directly.  Results are identical. */
 int pr_sys_set_graphs(pr_sys* s, int32_t on);
 
+
+/* Bandwidth probe: copies bytes from src to dst (device memory, bytes a
+ * multiple of width) with the library's own copy kernel, each lane moving
+ * one element of width 4, 8 or 16 bytes per iteration (a wavefront reads and
+ * writes 64 * width contiguous bytes), 2048 workgroups striding over the
+ * buffer.  kernel_ms (host, may be NULL): the kernel's own duration (the call
+ * then synchronises).  Measures the HBM ceiling the reaction kernels are
+ * compared with and calibrates the profiler's byte counters.  PR_EINVAL for
+ * another width, a negative or unaligned size, or NULL buffers. */
+int pr_stream_copy(const void* src, void* dst, int64_t bytes, int32_t width, void* stream,
+                   float* kernel_ms);
 
 /* ------------------------------------------------------------------------ */
 /* Batched ensemble: many independent replicas (uneven sizes, step or chain  */

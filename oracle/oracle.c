@@ -32,11 +32,20 @@
  * Floating point: positions are FP32; the squared minimum-image distance is
  * evaluated as ((dx*dx + dy*dy) + dz*dz) with every operation rounded to
  * FP32 and no fused multiply-add (this file must be built with
- * -ffp-contract=off and without -ffast-math).  The pair is in range iff
+ * -ffp-contract=off and without -ffast-math; see build.py).  The pair is in range iff
  * r2 < rc2 with rc2 = fl32(rc*rc) (strict).
  *
- * Parity pins of each function are listed in the tests; functions with no
- * pin say so here.  All functions are pinned (see tests/test_oracle_*.py).
+ * Enumeration order.  The whole step (or_react_step) visits every (A, T)
+ * pair exactly once, by brute force, in tiles: OR_TILE active particles
+ * against every particle j.  The tiling only reorders the visits so that the
+ * particle arrays stream from memory once per tile instead of once per A;
+ * each pair's arithmetic is the one above, and every reduction (the minimum
+ * over 64-bit keys, integer counts) is exact and independent of order.  The
+ * sampled form (or_sample_bonds) visits pairs one A at a time, in the plain
+ * loop order, and a test shows both give the same bonds.
+ *
+ * Pins of every function are in tests/pins.py and tests/test_oracle_*.py
+ * (hand cases, closed forms, statistics, planted mistakes).
  */
 #include <math.h>
 #include <stdint.h>
@@ -123,17 +132,17 @@ static float min_image(float d, float L, float halfL) {
 #if OR_MUTANT == 2 /* mutant: no periodic wrap */
   return d;
 #endif
-  if (d > halfL) d = d - L;
-  else if (d < -halfL) d = d + L;
-  return d;
+  const float dn = d - L, up = d + L;
+  return d > halfL ? dn : (d < -halfL ? up : d);
 }
 
-/* squared distance of T=j relative to A=i, every op rounded to FP32 */
-static float dist2(const float* x, const float* y, const float* z, int64_t i, int64_t j,
-                   float L, float halfL) {
-  float dx = min_image(x[j] - x[i], L, halfL);
-  float dy = min_image(y[j] - y[i], L, halfL);
-  float dz = min_image(z[j] - z[i], L, halfL);
+/* squared distance of T at (xt, yt, zt) relative to A at (xa, ya, za), every
+ * op rounded to FP32: differences T - A, minimum image, ((dx^2 + dy^2) + dz^2) */
+static inline float pair_r2(float xt, float yt, float zt, float xa, float ya, float za,
+                            float L, float halfL) {
+  float dx = min_image(xt - xa, L, halfL);
+  float dy = min_image(yt - ya, L, halfL);
+  float dz = min_image(zt - za, L, halfL);
   float sx = dx * dx;
   float sy = dy * dy;
   float sz = dz * dz;
@@ -142,6 +151,20 @@ static float dist2(const float* x, const float* y, const float* z, int64_t i, in
   return sxy + 0.0f * sz;
 #endif
   return sxy + sz;
+}
+
+static float dist2(const float* x, const float* y, const float* z, int64_t i, int64_t j,
+                   float L, float halfL) {
+  return pair_r2(x[j], y[j], z[j], x[i], y[i], z[i], L, halfL);
+}
+
+/* the cutoff test of step 1: strictly inside */
+static inline int in_cutoff(float r2, float rc2) {
+#if OR_MUTANT == 3 /* mutant: inclusive cutoff */
+  return r2 <= rc2;
+#else
+  return r2 < rc2;
+#endif
 }
 
 static int bonded(const int32_t* adj, int32_t B, int64_t i, int64_t j) {
@@ -179,6 +202,31 @@ enum {
   ST_PROPOSALS, ST_BONDS, ST_ADJ_OVERFLOW, ST_COUNT
 };
 
+/* Steps 1-2 and the A side of step 5 for one in-range (A = i, T = j) pair:
+ * bonded exclusion, the draw u < k dt Theta, and the running minimum of the
+ * (w1, id_T) keys of i.  cnt += {in range, drawn, excluded, accepted}. */
+static void take_pair(const int32_t* adj, int32_t B, const or_rule* R, uint64_t thresh,
+                      uint64_t seed, uint32_t step, int64_t i, int64_t j, uint64_t* best,
+                      int64_t cnt[4]) {
+  cnt[0]++;
+#if OR_MUTANT == 9 /* mutant: bonded pairs not excluded */
+  const int already = 0;
+#else
+  const int already = R->exclude_bonded && bonded(adj, B, i, j); /* step 1: not yet bonded */
+#endif
+  uint32_t ctr[4] = {step, (uint32_t)i, (uint32_t)j, 0u}, w[4];
+  or_philox4x32_10(ctr, seed, w);
+  if (!((uint64_t)w[0] < thresh)) return;        /* step 2: u < k dt Theta */
+  cnt[1]++;
+  if (already) {
+    cnt[2]++;
+    return;
+  }
+  cnt[3]++;
+  uint64_t key = ((uint64_t)w[1] << 32) | (uint64_t)(uint32_t)j;
+  if (key < *best) *best = key;                   /* step 5: one T per A */
+}
+
 /* Steps 1-5 for one active particle i: brute force over all particles, keep
  * the in-range, target-eligible, not yet bonded, accepted ones (Table I, steps
  * 1-2) and return the smallest (w1, id_T) key among them, or UINT64_MAX when
@@ -192,31 +240,47 @@ static uint64_t choose_target(int32_t n, float L, const float* x, const float* y
   uint64_t best = UINT64_MAX;
   for (int64_t j = 0; j < n; ++j) {
     if (!is_t[j] || j == i) continue;
-    float r2 = dist2(x, y, z, i, j, L, halfL);
-#if OR_MUTANT == 3 /* mutant: inclusive cutoff */
-    if (!(r2 <= rc2)) continue;
-#else
-    if (!(r2 < rc2)) continue;                    /* step 1: cutoff */
-#endif
-    cnt[0]++;
-#if OR_MUTANT == 9 /* mutant: bonded pairs not excluded */
-    const int already = 0;
-#else
-    const int already = R->exclude_bonded && bonded(adj, B, i, j); /* step 1: not yet bonded */
-#endif
-    uint32_t ctr[4] = {step, (uint32_t)i, (uint32_t)j, 0u}, w[4];
-    or_philox4x32_10(ctr, seed, w);
-    if (!((uint64_t)w[0] < thresh)) continue;    /* step 2: u < k dt Theta */
-    cnt[1]++;
-    if (already) {
-      cnt[2]++;
-      continue;
-    }
-    cnt[3]++;
-    uint64_t key = ((uint64_t)w[1] << 32) | (uint64_t)(uint32_t)j;
-    if (key < best) best = key;                   /* step 5: one T per A */
+    if (!in_cutoff(dist2(x, y, z, i, j, L, halfL), rc2)) continue;  /* step 1: cutoff */
+    take_pair(adj, B, R, thresh, seed, step, i, j, &best, cnt);
   }
   return best;
+}
+
+/* Steps 1-5 for a tile of m <= OR_TILE active particles ids[0..m-1], every
+ * particle j tested against each of them: the same pairs, arithmetic and
+ * keys as choose_target for each, visited j-major so that the particle
+ * arrays are read once per tile.  best[k] receives the key of ids[k]. */
+#define OR_TILE 64
+__attribute__((target_clones("avx512f", "avx2", "default")))
+static void choose_targets_tile(int32_t n, float L, const float* x, const float* y,
+                                const float* z, const uint8_t* is_t, const int32_t* adj,
+                                int32_t B, const or_rule* R, uint64_t thresh, uint64_t seed,
+                                uint32_t step, const int64_t* ids, int m, uint64_t* best,
+                                int64_t cnt[4]) {
+  const float halfL = 0.5f * L;
+  const float rc2 = R->rc * R->rc;
+  float ax[OR_TILE], ay[OR_TILE], az[OR_TILE], r2[OR_TILE];
+  for (int k = 0; k < OR_TILE; ++k) {  /* unused slots repeat the last A */
+    const int64_t i = ids[k < m ? k : m - 1];
+    ax[k] = x[i];
+    ay[k] = y[i];
+    az[k] = z[i];
+  }
+  for (int k = 0; k < m; ++k) best[k] = UINT64_MAX;
+  for (int64_t j = 0; j < n; ++j) {
+    if (!is_t[j]) continue;
+    const float xj = x[j], yj = y[j], zj = z[j];
+    int any = 0;
+    for (int k = 0; k < OR_TILE; ++k) {
+      r2[k] = pair_r2(xj, yj, zj, ax[k], ay[k], az[k], L, halfL);
+      any |= in_cutoff(r2[k], rc2);
+    }
+    if (!any) continue;
+    for (int k = 0; k < m; ++k) {
+      if (ids[k] == j || !in_cutoff(r2[k], rc2)) continue;            /* step 1: cutoff */
+      take_pair(adj, B, R, thresh, seed, step, ids[k], j, &best[k], cnt);
+    }
+  }
 }
 
 /* ----------------------------------------------------------------------- */
@@ -259,19 +323,23 @@ int or_react_step(int32_t n, float L, const float* x, const float* y, const floa
     t_best[i] = EMPTY;
   }
 
-  /* Steps 1-5: for each A, scan every particle (brute force), keep the
-   * in-range, eligible, non-bonded, accepted targets and pick one of them:
-   * the one with the smallest (w1, id_T) key. */
+  /* Steps 1-5: every particle is tested against every A (brute force, in
+   * tiles of OR_TILE A's); each A keeps the in-range, eligible, non-bonded,
+   * accepted targets and picks one of them: the smallest (w1, id_T) key. */
   int64_t in_rc = 0, drawn = 0, excluded = 0, accepted = 0, proposals = 0;
-#pragma omp parallel for schedule(dynamic, 8) reduction(+ : in_rc, drawn, excluded, accepted, proposals)
-  for (int64_t k = 0; k < na; ++k) {
+  const int64_t ntile = (na + OR_TILE - 1) / OR_TILE;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : in_rc, drawn, excluded, accepted, proposals)
+  for (int64_t t = 0; t < ntile; ++t) {
     int64_t cnt[4] = {0, 0, 0, 0};
-    a_choice[k] = choose_target(n, L, x, y, z, is_t, adj, B, &R, thresh, seed, step, alist[k], cnt);
+    const int64_t k0 = t * OR_TILE;
+    const int m = (int)(na - k0 < OR_TILE ? na - k0 : OR_TILE);
+    choose_targets_tile(n, L, x, y, z, is_t, adj, B, &R, thresh, seed, step, alist + k0, m,
+                        a_choice + k0, cnt);
     in_rc += cnt[0];
     drawn += cnt[1];
     excluded += cnt[2];
     accepted += cnt[3];
-    if (a_choice[k] != EMPTY) proposals++;
+    for (int k = 0; k < m; ++k) proposals += a_choice[k0 + k] != EMPTY;
   }
 
   /* Steps 6-7: each chosen T keeps the A with the smallest (w2, id_A). */
@@ -381,42 +449,110 @@ int or_sample_bonds(int32_t n, float L, const float* x, const float* y, const fl
 }
 
 /* ----------------------------------------------------------------------- */
-/* FP64 recheck of the cutoff decision (diagnostic only).                    */
-/* Counts, over all eligible (A, T) pairs, those whose FP64 distance from  */
-/* the same FP32 coordinates lies within tol of rc, and those where the    */
-/* FP64 decision r < rc differs from the FP32 decision r2 < rc2.           */
+/* FP64 recheck of the cutoff decision (diagnostic only; Sec. II gives the  */
+/* cutoff as a distance, the contract decides it in FP32 on r^2).            */
+/* Over every pair of an A-eligible i and a T-eligible j != i, from the same */
+/* FP32 coordinates converted to double: r64 = sqrt of the FP64 squared      */
+/* minimum-image distance.  near counts |r64 - rc| < tol (rc the FP32 cutoff */
+/* as a double), disagree counts pairs whose FP64 decision r64 < rc differs  */
+/* from the FP32 decision of the step (pair_r2 < fl32(rc*rc)).  Pairs with   */
+/* r64 >= rc + 1 can be neither (the FP32 value is within a few ulps of the  */
+/* FP64 one) and are skipped after their FP64 r^2.  Brute force, in tiles of */
+/* OR_TILE A's like the step.                                                */
 /* ----------------------------------------------------------------------- */
+static inline double min_image64(double d, double L, double halfL) {
+#if OR_MUTANT == 14 /* mutant: no periodic wrap in the FP64 recheck */
+  return d;
+#endif
+  const double dn = d - L, up = d + L;
+  return d > halfL ? dn : (d < -halfL ? up : d);
+}
+
+__attribute__((target_clones("avx512f", "avx2", "default")))
+static void near_tile(int32_t n, float L, const float* x, const float* y, const float* z,
+                      const uint8_t* is_t, const int64_t* ids, int m, float rc, double tol,
+                      int64_t* near, int64_t* disagree) {
+  const double Ld = (double)L, halfd = 0.5 * Ld, rcd = (double)rc;
+  const double lim2 = (rcd + 1.0) * (rcd + 1.0);
+  const float halfL = 0.5f * L, rc2 = rc * rc;
+  double ax[OR_TILE], ay[OR_TILE], az[OR_TILE], r2[OR_TILE];
+  for (int k = 0; k < OR_TILE; ++k) {
+    const int64_t i = ids[k < m ? k : m - 1];
+    ax[k] = (double)x[i];
+    ay[k] = (double)y[i];
+    az[k] = (double)z[i];
+  }
+  int64_t cn = 0, cd = 0;
+  for (int64_t j = 0; j < n; ++j) {
+    if (!is_t[j]) continue;
+    const double xj = (double)x[j], yj = (double)y[j], zj = (double)z[j];
+    int any = 0;
+    for (int k = 0; k < OR_TILE; ++k) {
+      const double dx = min_image64(xj - ax[k], Ld, halfd);
+      const double dy = min_image64(yj - ay[k], Ld, halfd);
+      const double dz = min_image64(zj - az[k], Ld, halfd);
+      r2[k] = dx * dx + dy * dy + dz * dz;
+      any |= r2[k] < lim2;
+    }
+    if (!any) continue;
+    for (int k = 0; k < m; ++k) {
+      if (ids[k] == j || !(r2[k] < lim2)) continue;
+      const double r = sqrt(r2[k]);
+#if OR_MUTANT == 15 /* mutant: tolerance applied to r^2 instead of r */
+      cn += fabs(r2[k] - rcd * rcd) < tol;
+#else
+      cn += fabs(r - rcd) < tol;
+#endif
+      const int64_t i = ids[k];
+#if OR_MUTANT == 17 /* mutant: the FP32 side taken in FP64 (never disagrees) */
+      const int in32 = r2[k] < (double)rc2;
+#else
+      const int in32 = pair_r2(x[j], y[j], z[j], x[i], y[i], z[i], L, halfL) < rc2;
+#endif
+      const int in64 = r < rcd;
+      cd += in32 != in64;
+    }
+  }
+  *near += cn;
+  *disagree += cd;
+}
+
 int or_near_cutoff(int32_t n, float L, const float* x, const float* y, const float* z,
                    const int32_t* type, const int32_t* state,
                    int32_t type_a, int32_t a_min, int32_t a_max,
                    int32_t type_t, int32_t t_min, int32_t t_max,
                    float rc, double tol, int64_t* near, int64_t* disagree) {
-  const double Ld = (double)L, halfd = 0.5 * Ld, rcd = (double)rc;
-  const float halfL = 0.5f * L, rc2 = rc * rc;
-  int64_t cnt_near = 0, cnt_dis = 0;
-#pragma omp parallel for schedule(dynamic, 8) reduction(+ : cnt_near, cnt_dis)
+  or_rule R = {type_a, a_min, a_max, 0, type_t, t_min, t_max, 0, rc, 0.0, 0};
+  int64_t* alist = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  uint8_t* is_t = (uint8_t*)malloc((size_t)(n > 0 ? n : 1));
+  if (!alist || !is_t) {
+    free(alist); free(is_t);
+    return OR_ENOMEM;
+  }
+  int64_t na = 0;
   for (int64_t i = 0; i < n; ++i) {
-    if (!(type[i] == type_a && state[i] >= a_min && state[i] <= a_max)) continue;
-    for (int64_t j = 0; j < n; ++j) {
-      if (!(type[j] == type_t && state[j] >= t_min && state[j] <= t_max) || j == i) continue;
-      double d[3] = {(double)x[j] - (double)x[i], (double)y[j] - (double)y[i],
-                     (double)z[j] - (double)z[i]};
-      double r2 = 0.0;
-      for (int c = 0; c < 3; ++c) {
-        if (d[c] > halfd) d[c] -= Ld;
-        else if (d[c] < -halfd) d[c] += Ld;
-        r2 += d[c] * d[c];
-      }
-      if (r2 > (rcd + 1.0) * (rcd + 1.0)) continue;
-      double r = sqrt(r2);
-      if (fabs(r - rcd) < tol) cnt_near++;
-      int in32 = dist2(x, y, z, i, j, L, halfL) < rc2;
-      int in64 = r < rcd;
-      if (in32 != in64) cnt_dis++;
-    }
+#if OR_MUTANT == 16 /* mutant: every particle counted as an A */
+    alist[na++] = i;
+#else
+    if (is_active(&R, type[i], state[i])) alist[na++] = i;
+#endif
+    is_t[i] = (uint8_t)is_target(&R, type[i], state[i]);
+  }
+  int64_t cnt_near = 0, cnt_dis = 0;
+  const int64_t ntile = (na + OR_TILE - 1) / OR_TILE;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : cnt_near, cnt_dis)
+  for (int64_t t = 0; t < ntile; ++t) {
+    const int64_t k0 = t * OR_TILE;
+    const int m = (int)(na - k0 < OR_TILE ? na - k0 : OR_TILE);
+    int64_t a = 0, d = 0;
+    near_tile(n, L, x, y, z, is_t, alist + k0, m, rc, tol, &a, &d);
+    cnt_near += a;
+    cnt_dis += d;
   }
   *near = cnt_near;
   *disagree = cnt_dis;
+  free(alist);
+  free(is_t);
   return OR_OK;
 }
 

@@ -84,6 +84,9 @@ def _load():
         "pr_sys_generate": ([vp, i32, u64, f64], C.c_int),
         "pr_sys_run": ([vp, u32, u32, f64], C.c_int),
         "pr_sys_run_timed": ([vp, u32, u32, f64, P(f32)], C.c_int),
+        "pr_sys_prepare": ([vp, u32, f64], C.c_int),
+        "pr_sys_jitter": ([vp, u32, u32, f64, P(f32)], C.c_int),
+        "pr_stream_copy": ([vp, vp, i64, i32, vp, P(f32)], C.c_int),
         "pr_sys_read": ([vp, vp, vp, vp, vp, vp, i32], C.c_int),
         "pr_sys_checkpoint": ([vp, vp, i64, P(i64)], C.c_int),
         "pr_sys_restore": ([vp, vp, i64], C.c_int),
@@ -138,7 +141,8 @@ def exported_symbols():
                         "pr_server_bonds", "pr_server_read", "pr_server_stats",
                         "pr_server_release", "pr_server_info_get", "pr_sys_checkpoint",
                         "pr_sys_restore", "pr_p_from_rate", "pr_draws", "pr_server_poll",
-                        "pr_server_cancel", "pr_autotune_cached")]
+                        "pr_server_cancel", "pr_autotune_cached", "pr_sys_prepare",
+                        "pr_sys_jitter", "pr_stream_copy")]
 
 
 def _check(code):
@@ -174,9 +178,10 @@ def react_step(x, y, z, type_, state, adj, L, rule, seed, step, bonds=None, stre
     nb = C.c_int32(0)
     st = Stats()
     r = rule if isinstance(rule, Rule) else Rule.make(rule)
-    code = lib.pr_react_step(n, C.c_float(L), _ptr(x), _ptr(y), _ptr(z), _ptr(type_), _ptr(state),
-                             _ptr(adj), B, C.byref(r), C.c_uint64(seed), C.c_uint32(step),
-                             _ptr(bonds), bonds.shape[0], C.byref(nb), C.byref(st), _stream(stream))
+    fn = lib.pr_react_step
+    code = fn(n, C.c_float(L), _ptr(x), _ptr(y), _ptr(z), _ptr(type_), _ptr(state), _ptr(adj), B,
+              C.byref(r), C.c_uint64(seed), C.c_uint32(step), _ptr(bonds), bonds.shape[0],
+              C.byref(nb), C.byref(st), _stream(stream))
     if raise_on_error and code not in (PR_OK,):
         _check(code)
     return code, bonds[: nb.value], st.as_dict()
@@ -230,9 +235,22 @@ class System:
         _check(lib.pr_sys_run(self._h, int(first_step), int(n_steps), float(sigma)))
 
     def run_timed(self, first_step, n_steps, sigma):
-        ms = (C.c_float * 3)()
+        ms = (C.c_float * 5)()
         _check(lib.pr_sys_run_timed(self._h, int(first_step), int(n_steps), float(sigma), ms))
-        return {"prep_ms": ms[0], "step_ms": ms[1], "sweep_ms": ms[2]}
+        return {"prep_ms": ms[0], "step_ms": ms[1], "sweep_ms": ms[2], "sort_ms": ms[3],
+                "sorts": int(ms[4])}
+
+    def prepare(self, n_steps, sigma):
+        """Capture the graphs a following run of n_steps will replay."""
+        _check(lib.pr_sys_prepare(self._h, int(n_steps), float(sigma)))
+
+    def jitter(self, first_step, n_steps, sigma, timed=False):
+        """The re-jitter alone for n_steps steps; timed: returns the summed
+        kernel time in ms."""
+        ms = C.c_float(0.0)
+        _check(lib.pr_sys_jitter(self._h, int(first_step), int(n_steps), float(sigma),
+                                 C.byref(ms) if timed else None))
+        return ms.value if timed else None
 
     def set_sort_period(self, k):
         _check(lib.pr_sys_set_sort_period(self._h, int(k)))
@@ -293,6 +311,17 @@ def draws(ctr, key, stream=None):
     _check(lib.pr_draws(_ptr(ctr), ctr.shape[0], C.c_uint64(int(key)), _ptr(out),
                         _stream(stream)))
     return out
+
+
+def stream_copy(src, dst, width=16, stream=None):
+    """The library's copy kernel from tensor src to dst (same byte size);
+    returns the kernel's duration in ms."""
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nbytes
+    ms = C.c_float(0.0)
+    _check(lib.pr_stream_copy(_ptr(src), _ptr(dst), nbytes, int(width), _stream(stream),
+                              C.byref(ms)))
+    return ms.value
 
 
 def replica_desc(r):

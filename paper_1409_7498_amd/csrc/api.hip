@@ -41,6 +41,11 @@ hipError_t launch_gather_out(const Dev& d, float* ox, float* oy, float* oz, int3
                              int32_t* ost, int32_t* oadj, hipStream_t s);
 hipError_t launch_draws(const uint32_t* ctr, long long n, unsigned long long key, uint32_t* out,
                         hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, long long n, uint32_t v, hipStream_t s);
+hipError_t launch_jitter_only(const Dev& d, int n_steps, hipStream_t s, hipEvent_t ev0,
+                              hipEvent_t ev1);
+hipError_t launch_stream_copy(const void* src, void* dst, long long bytes, int width,
+                              hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 }  // namespace pr
 
 using namespace pr;
@@ -144,6 +149,11 @@ struct Arena {
   hipStream_t astream = nullptr;
   hipMemPool_t pool = nullptr;  // async: the pool to draw from (null: the device's default)
   size_t bytes = 0;
+  // carve mode (base != null): every allocation is the next 256-byte aligned
+  // piece of the caller's region [base, base + cap); nothing is allocated or
+  // freed, and running past cap fails with PR_ECAP
+  char* base = nullptr;
+  size_t cap = 0;
   ~Arena() { release(); }
   void release() {
     for (void* p : ptrs) (void)(async ? hipFreeAsync(p, astream) : hipFree(p));
@@ -153,9 +163,16 @@ struct Arena {
   int alloc(T** out, size_t count) {
     if (count == 0) count = 1;
     const size_t nb = count * sizeof(T);
+    const size_t at = bytes;
     bytes += (nb + 255) & ~(size_t)255;
     if (dry) {
       *out = nullptr;
+      return PR_OK;
+    }
+    if (base) {
+      if (bytes > cap)
+        return fail(PR_ECAP, "scratch needs more than its %zu bytes", cap);
+      *out = (T*)(base + at);
       return PR_OK;
     }
     void* p = nullptr;
@@ -191,7 +208,7 @@ int alloc_scratch(Arena& a, Dev& d, int32_t n, int32_t nwg, hipStream_t s) {
       return e;
   }
   if ((e = a.alloc(&d.ctl, 1))) return e;
-  if (a.dry) return PR_OK;
+  if (a.dry || a.base) return PR_OK;  // a carved region is cleared by its user
   HIP_TRY(hipMemsetAsync(d.cnt[0], 0, sizeof(uint32_t) * std::max(1, d.ncell), s));
   HIP_TRY(hipMemsetAsync(d.cnt[1], 0, sizeof(uint32_t) * std::max(1, d.ncell), s));
   HIP_TRY(hipMemsetAsync(d.slotA, 0xFF, sizeof(unsigned long long) * std::max(1, n), s));
@@ -249,10 +266,14 @@ int pr_draws(const uint32_t* ctr, int64_t n, uint64_t key, uint32_t* out, void* 
   return PR_OK;
 }
 
-int pr_react_step(int32_t n, float L, const float* x, const float* y, const float* z,
-                  const int32_t* type, int32_t* state, int32_t* adj, int32_t B,
-                  const pr_rule* rule, uint64_t seed, uint32_t step, int32_t* bonds,
-                  int32_t cap, int32_t* n_bonds, pr_stats* st, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Validation shared by the stateless single-step entry points.
+int check_single(int32_t n, float L, const float* x, const float* y, const float* z,
+                 const int32_t* type, const int32_t* state, const int32_t* adj, int32_t B,
+                 const pr_rule* rule, const int32_t* bonds, int32_t cap, const int32_t* n_bonds) {
   if (n < 0 || n > kMaxParticles || B < 1) return fail(PR_EINVAL, "n=%d B=%d", n, B);
   int e = validate_rule(rule, L);
   if (e) return e;
@@ -260,6 +281,73 @@ int pr_react_step(int32_t n, float L, const float* x, const float* y, const floa
   if ((int64_t)cap < (int64_t)n / 2) return fail(PR_ECAP, "cap=%d < n/2=%d", cap, n / 2);
   if (n > 0 && (!x || !y || !z || !type || !state || !adj || !bonds))
     return fail(PR_EINVAL, "NULL device array");
+  return PR_OK;
+}
+
+// Points d (scratch pointers already set) at the caller's arrays with the
+// geometry of this call (the scratch may be sized for a larger one).
+void bind_single(Dev& d, const Dev& geo, float* x, float* y, float* z, int32_t* type,
+                 int32_t* state, int32_t* adj, uint8_t* role, int32_t* bonds, int32_t cap) {
+  d.n = geo.n;
+  d.B = geo.B;
+  d.L = geo.L;
+  d.halfL = geo.halfL;
+  d.rc2 = geo.rc2;
+  d.nc = geo.nc;
+  d.ncell = geo.ncell;
+  d.inv_w = geo.inv_w;
+  d.thresh = geo.thresh;
+  d.seed = geo.seed;
+  d.rule = geo.rule;
+  d.adj_staged = geo.adj_staged;
+  d.nwg_sweep = geo.nwg_sweep;
+  d.nwg_prep = geo.nwg_prep;
+  d.jitter = 0;
+  d.sorted = 0;
+  const Arr caller{{x, x}, {y, y}, {z, z}, type, state, adj, nullptr, role};
+  d.set[0] = d.set[1] = caller;
+  d.bonds = bonds;
+  d.bonds_cap = cap;
+  d.log_cap = (int64_t)geo.n / 2 + 1;
+  d.part_cap = 1;
+  d.ngroups = (d.nwg_sweep + kGroup - 1) / kGroup;
+}
+
+// The launches of one stateless step (count buffers already cleared), the
+// read-back of its control block and counters into hctl / hpart (host
+// memory of d.ngroups * kPart words) and the results.
+int single_step(const Dev& d, uint32_t step, hipStream_t s, Ctl* hctl, int32_t* hpart,
+                int32_t* n_bonds, pr_stats* st) {
+  HIP_TRY(launch_ctl_reset(d.ctl, step, 1, s));
+  HIP_TRY(launch_classify(d, s));
+  HIP_TRY(launch_step(d, 0, s, nullptr, nullptr));
+  HIP_TRY(launch_single_end(d, s));
+  HIP_TRY(hipMemcpyAsync(hctl, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(hpart, d.part, sizeof(int32_t) * d.ngroups * kPart,
+                         hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const Ctl c = *hctl;
+  if (c.err) return fail(c.err, "invalid particle position (NaN or outside [0, L))");
+  *n_bonds = (int32_t)c.log_n;
+  long long h[kPart] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int g = 0; g < d.ngroups; ++g)
+    for (int q = 0; q < kPart; ++q) h[q] += hpart[g * kPart + q];
+  // partial layout: a_elig, t_elig, in_rc, drawn, excluded, proposals, bonds, lost
+  if (st) *st = pr_stats{h[0], h[1], h[2], h[3], h[4], h[3] - h[4], h[5], h[6], h[7]};
+  if (h[7] > 0) return fail(PR_ECAP, "%lld adjacency appends found a full row", h[7]);
+  return PR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pr_react_step(int32_t n, float L, const float* x, const float* y, const float* z,
+                  const int32_t* type, int32_t* state, int32_t* adj, int32_t B,
+                  const pr_rule* rule, uint64_t seed, uint32_t step, int32_t* bonds,
+                  int32_t cap, int32_t* n_bonds, pr_stats* st, void* stream) {
+  int e = check_single(n, L, x, y, z, type, state, adj, B, rule, bonds, cap, n_bonds);
+  if (e) return e;
   *n_bonds = 0;
   if (st) std::memset(st, 0, sizeof *st);
   if (n == 0) return PR_OK;
@@ -295,61 +383,19 @@ int pr_react_step(int32_t n, float L, const float* x, const float* y, const floa
     ws->ncell = geo.ncell;
   }
   Dev d = ws->d;  // scratch pointers
-  // geometry of this call (the allocation may be larger)
-  d.n = geo.n;
-  d.B = geo.B;
-  d.L = geo.L;
-  d.halfL = geo.halfL;
-  d.rc2 = geo.rc2;
-  d.nc = geo.nc;
-  d.ncell = geo.ncell;
-  d.inv_w = geo.inv_w;
-  d.thresh = geo.thresh;
-  d.seed = geo.seed;
-  d.rule = geo.rule;
-  d.adj_staged = geo.adj_staged;
-  d.nwg_sweep = geo.nwg_sweep;
-  d.nwg_prep = geo.nwg_prep;
-  d.jitter = 0;
-  d.sorted = 0;
-  float* cx = const_cast<float*>(x);
-  float* cy = const_cast<float*>(y);
-  float* cz = const_cast<float*>(z);
-  const Arr caller{{cx, cx}, {cy, cy}, {cz, cz}, const_cast<int32_t*>(type), state, adj, nullptr,
-                   ws->role};
-  d.set[0] = d.set[1] = caller;
-  d.bonds = bonds;
-  d.bonds_cap = cap;
   d.log = ws->log;
-  d.log_cap = (int64_t)ws->n / 2 + 1;
   d.sortbuf = ws->sortbuf;
   d.part = ws->part;
-  d.part_cap = 1;
-  d.ngroups = (d.nwg_sweep + kGroup - 1) / kGroup;
+  bind_single(d, geo, const_cast<float*>(x), const_cast<float*>(y), const_cast<float*>(z),
+              const_cast<int32_t*>(type), state, adj, ws->role, bonds, cap);
   // The workspace serves calls of any box size: a previous call may have left
   // counts in cells beyond this call's grid, so both count buffers are cleared
   // over their whole allocation (each step only clears the cells it uses).
   HIP_TRY(hipMemsetAsync(d.cnt[0], 0, sizeof(uint32_t) * (size_t)ws->ncell, s));
   HIP_TRY(hipMemsetAsync(d.cnt[1], 0, sizeof(uint32_t) * (size_t)ws->ncell, s));
-  HIP_TRY(launch_ctl_reset(d.ctl, step, 1, s));
-  HIP_TRY(launch_classify(d, s));
-  HIP_TRY(launch_step(d, 0, s, nullptr, nullptr));
-  HIP_TRY(launch_single_end(d, s));
-  HIP_TRY(hipMemcpyAsync(ws->hctl, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(ws->hpart, ws->part, sizeof(int32_t) * d.ngroups * kPart,
-                         hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  const Ctl c = *ws->hctl;
-  if (c.err) return fail(c.err, "invalid particle position (NaN or outside [0, L))");
-  *n_bonds = (int32_t)c.log_n;
-  long long h[kPart] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int g = 0; g < d.ngroups; ++g)
-    for (int q = 0; q < kPart; ++q) h[q] += ws->hpart[g * kPart + q];
-  // partial layout: a_elig, t_elig, in_rc, drawn, excluded, proposals, bonds, lost
-  if (st) *st = pr_stats{h[0], h[1], h[2], h[3], h[4], h[3] - h[4], h[5], h[6], h[7]};
-  if (h[7] > 0) return fail(PR_ECAP, "%lld adjacency appends found a full row", h[7]);
-  return PR_OK;
+  return single_step(d, step, s, ws->hctl, ws->hpart, n_bonds, st);
 }
+
 
 }  // extern "C"
 
@@ -371,17 +417,25 @@ struct pr_sys {
   bool poisoned = false;
   int32_t sort_period = 0;
   int32_t use_graphs = 1;
-  // captured block: one sort (when sort_period > 0) and block_steps steps
-  hipGraphExec_t gexec = nullptr;
-  int32_t g_steps = 0;
-  float g_jit = -1.0f;
-  long long g_part = 0;
+  // captured segments of steps: (a sort when one is due and) K steps and the
+  // block end, keyed by what the captured kernels hold
+  struct Seg {
+    hipGraphExec_t gexec = nullptr;
+    int32_t steps = 0;
+    bool sort = false;
+    float jit = -1.0f;
+    long long part = 0;
+    uint64_t used = 0;
+  };
+  std::vector<Seg> segs;
+  uint64_t seg_clock = 0;
   float *rx = nullptr, *ry = nullptr, *rz = nullptr;  // id-order read buffers
   int32_t *rtyp = nullptr, *rst = nullptr, *radj = nullptr;
   Ctl* hctl = nullptr;
   bool own_hctl = true;  // false: the pinned word belongs to a server's pool
   ~pr_sys() {
-    if (gexec) (void)hipGraphExecDestroy(gexec);
+    for (Seg& g : segs)
+      if (g.gexec) (void)hipGraphExecDestroy(g.gexec);
     if (cap) (void)hipStreamDestroy(cap);
     if (hctl && own_hctl) (void)hipHostFree(hctl);
   }
@@ -403,8 +457,9 @@ int sync_ctl(pr_sys* s) {
 }
 
 void drop_graph(pr_sys* s) {
-  if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
-  s->gexec = nullptr;
+  for (pr_sys::Seg& g : s->segs)
+    if (g.gexec) (void)hipGraphExecDestroy(g.gexec);
+  s->segs.clear();
 }
 
 // The partial-counter log holds `need` steps (grown by doubling; a copy keeps
@@ -466,10 +521,17 @@ int sort_storage(pr_sys* s, hipStream_t st) {
 
 // A block of K steps on st: a sort first when due, K steps, the block end.
 // ev (timed runs, K == 1): events before the prep, before and after the sweep.
-int run_block(pr_sys* s, hipStream_t st, int32_t K, hipEvent_t* ev) {
+// sort_ev (may be null): events around the sort, when one runs (*sorted = 1).
+int run_block(pr_sys* s, hipStream_t st, int32_t K, hipEvent_t* ev,
+              hipEvent_t* sort_ev = nullptr, bool* sorted = nullptr) {
   int e;
-  if (s->sort_period > 0 && (!s->d.sorted || s->steps_since_sort >= s->sort_period))
+  if (sorted) *sorted = false;
+  if (s->sort_period > 0 && (!s->d.sorted || s->steps_since_sort >= s->sort_period)) {
+    if (sort_ev) HIP_TRY(hipEventRecord(sort_ev[0], st));
     if ((e = sort_storage(s, st))) return e;
+    if (sort_ev) HIP_TRY(hipEventRecord(sort_ev[1], st));
+    if (sorted) *sorted = true;
+  }
   if (ev) HIP_TRY(hipEventRecord(ev[0], st));
   for (int32_t k = 0; k < K; ++k)
     HIP_TRY(launch_step(s->d, k, st, ev ? ev[1] : nullptr, ev ? ev[2] : nullptr));
@@ -478,9 +540,51 @@ int run_block(pr_sys* s, hipStream_t st, int32_t K, hipEvent_t* ev) {
   return PR_OK;
 }
 
-// Captures one block into a graph on the private stream.
-int capture_block(pr_sys* s, int32_t K) {
-  drop_graph(s);
+// Whether the next step of a run starts with a spatial sort.
+bool sort_due(const pr_sys* s) {
+  return s->sort_period > 0 && (!s->d.sorted || s->steps_since_sort >= s->sort_period);
+}
+
+// The next segment of a run with `left` steps to go: a sort when one is due,
+// then up to the next sort (or 32 steps without sorting).
+int32_t next_segment(const pr_sys* s, uint32_t left, bool* with_sort) {
+  *with_sort = sort_due(s);
+  int64_t room = s->sort_period > 0
+                     ? (*with_sort ? s->sort_period : s->sort_period - s->steps_since_sort)
+                     : 32;
+  return (int32_t)std::min<int64_t>(room, left);
+}
+
+// The host-side state a segment leaves behind (the kernels move the device
+// side).
+void after_segment(pr_sys* s, int32_t K, bool with_sort) {
+  if (with_sort) {
+    s->d.sorted = 1;
+    s->d.nwg_sweep = s->d.nbricks;
+    s->steps_since_sort = K;
+  } else {
+    s->steps_since_sort += K;
+  }
+}
+
+// The captured graph of a segment of K steps (with a sort first when
+// with_sort), capturing it on the private stream if it is not cached.
+int segment_graph(pr_sys* s, int32_t K, bool with_sort, hipGraphExec_t* out) {
+  const long long part = (long long)(size_t)s->d.part;
+  for (pr_sys::Seg& g : s->segs)
+    if (g.steps == K && g.sort == with_sort && g.jit == s->d.jit_c && g.part == part) {
+      g.used = ++s->seg_clock;
+      *out = g.gexec;
+      return PR_OK;
+    }
+  constexpr size_t kMaxSegs = 6;
+  if (s->segs.size() >= kMaxSegs) {  // drop the least recently used
+    size_t lru = 0;
+    for (size_t i = 1; i < s->segs.size(); ++i)
+      if (s->segs[i].used < s->segs[lru].used) lru = i;
+    (void)hipGraphExecDestroy(s->segs[lru].gexec);
+    s->segs.erase(s->segs.begin() + (long)lru);
+  }
   hipGraph_t g = nullptr;
   if (!s->cap) HIP_TRY(hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking));
   HIP_TRY(hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal));
@@ -497,15 +601,19 @@ int capture_block(pr_sys* s, int32_t K) {
     return e;
   }
   if (ce != hipSuccess) return fail(PR_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(ce));
-  const hipError_t ie = hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0);
+  hipGraphExec_t ge = nullptr;
+  const hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
-  if (ie != hipSuccess) {
-    s->gexec = nullptr;
-    return fail(PR_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
-  }
-  s->g_steps = K;
-  s->g_jit = s->d.jit_c;
-  s->g_part = (long long)(size_t)s->d.part;
+  if (ie != hipSuccess) return fail(PR_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+  pr_sys::Seg seg;
+  seg.gexec = ge;
+  seg.steps = K;
+  seg.sort = with_sort;
+  seg.jit = s->d.jit_c;
+  seg.part = part;
+  seg.used = ++s->seg_clock;
+  s->segs.push_back(seg);
+  *out = ge;
   return PR_OK;
 }
 
@@ -695,7 +803,8 @@ int pr_sys_set_sort_period(pr_sys* s, int32_t sort_period) {
   return PR_OK;
 }
 
-static int run_impl(pr_sys* s, uint32_t first_step, uint32_t n_steps, double sigma, float* ms) {
+static int run_impl(pr_sys* s, uint32_t first_step, uint32_t n_steps, double sigma, float* ms,
+                    float* ms_sort = nullptr) {
   int e = check_sys(s, true);
   if (e) return e;
   if (!(sigma >= 0.0) || sigma * 6.0 >= (double)s->d.L * 0.5)
@@ -706,19 +815,37 @@ static int run_impl(pr_sys* s, uint32_t first_step, uint32_t n_steps, double sig
   HIP_TRY(launch_ctl_reset(s->d.ctl, first_step, 0, st));
   if (ms) {
     // phase timing: one-step blocks launched directly, HIP events around the
-    // prep (jitter + A binning), the sweep and the whole step
-    std::vector<hipEvent_t> ev((size_t)n_steps * 3 + 1);
+    // prep (jitter + A binning), the sweep and the whole step, and around
+    // the sorts that fall due
+    std::vector<hipEvent_t> ev((size_t)n_steps * 5 + 1);
     for (auto& v : ev) HIP_TRY(hipEventCreate(&v));
-    for (uint32_t k = 0; k < n_steps; ++k)
-      if ((e = run_block(s, st, 1, &ev[3 * k]))) return e;
+    std::vector<char> did_sort(n_steps, 0);
+    for (uint32_t k = 0; k < n_steps; ++k) {
+      bool sorted = false;
+      if ((e = run_block(s, st, 1, &ev[3 * k], &ev[3 * n_steps + 1 + 2 * k], &sorted))) return e;
+      did_sort[k] = sorted;
+    }
     HIP_TRY(hipEventRecord(ev[3 * n_steps], st));
     HIP_TRY(hipEventSynchronize(ev[3 * n_steps]));
-    float tp = 0, tstep = 0, tsw = 0;
+    float tp = 0, tstep = 0, tsw = 0, tsort = 0;
+    int nsort = 0;
     for (uint32_t k = 0; k < n_steps; ++k) {
-      float a = 0, b = 0, c = 0;
+      float a = 0, b = 0, c = 0, so = 0;
       HIP_TRY(hipEventElapsedTime(&a, ev[3 * k], ev[3 * k + 1]));
       HIP_TRY(hipEventElapsedTime(&b, ev[3 * k + 1], ev[3 * k + 2]));
-      HIP_TRY(hipEventElapsedTime(&c, ev[3 * k], ev[3 * (k + 1)]));
+      const size_t next = k + 1 < n_steps ? 3 * (k + 1) : 3 * n_steps;
+      if (k + 1 < n_steps && did_sort[k + 1]) {
+        // the next step's sort runs between this step and the next one
+        HIP_TRY(hipEventElapsedTime(&c, ev[3 * k], ev[3 * n_steps + 1 + 2 * (k + 1)]));
+      } else {
+        HIP_TRY(hipEventElapsedTime(&c, ev[3 * k], ev[next]));
+      }
+      if (did_sort[k]) {
+        HIP_TRY(hipEventElapsedTime(&so, ev[3 * n_steps + 1 + 2 * k],
+                                    ev[3 * n_steps + 2 + 2 * k]));
+        tsort += so;
+        nsort++;
+      }
       tp += a;
       tsw += b;
       tstep += c;
@@ -726,33 +853,28 @@ static int run_impl(pr_sys* s, uint32_t first_step, uint32_t n_steps, double sig
     ms[0] = tp;
     ms[1] = tstep;
     ms[2] = tsw;
+    if (ms_sort) {
+      ms_sort[0] = tsort;
+      ms_sort[1] = (float)nsort;
+    }
     for (auto& v : ev) (void)hipEventDestroy(v);
     s->steps_since_load += n_steps;
     return PR_OK;
   }
-  const int32_t block = s->sort_period > 0 ? s->sort_period : 32;
   uint32_t left = n_steps;
   while (left > 0) {
-    const bool aligned =
-        s->sort_period == 0 || !s->d.sorted || s->steps_since_sort >= s->sort_period;
-    if (s->use_graphs && aligned && left >= (uint32_t)block) {
-      if (!s->gexec || s->g_steps != block || s->g_jit != s->d.jit_c ||
-          s->g_part != (long long)(size_t)s->d.part)
-        if ((e = capture_block(s, block))) return e;
-      HIP_TRY(hipGraphLaunch(s->gexec, st));
-      // the host-side state the block leaves behind
-      if (s->sort_period > 0) {
-        s->d.sorted = 1;
-        s->d.nwg_sweep = s->d.nbricks;
-        s->steps_since_sort = block;
-      } else {
-        s->steps_since_sort += block;
-      }
-      left -= (uint32_t)block;
+    bool with_sort = false;
+    const int32_t K = next_segment(s, left, &with_sort);
+    if (s->use_graphs) {
+      hipGraphExec_t ge = nullptr;
+      if ((e = segment_graph(s, K, with_sort, &ge))) return e;
+      HIP_TRY(hipGraphLaunch(ge, st));
+      after_segment(s, K, with_sort);
     } else {
-      if ((e = run_block(s, st, 1, nullptr))) return e;
-      left -= 1;
+      for (int32_t k = 0; k < K; ++k)
+        if ((e = run_block(s, st, 1, nullptr))) return e;
     }
+    left -= (uint32_t)K;
   }
   s->steps_since_load += n_steps;
   return PR_OK;
@@ -764,7 +886,98 @@ int pr_sys_run(pr_sys* s, uint32_t first_step, uint32_t n_steps, double sigma) {
 
 int pr_sys_run_timed(pr_sys* s, uint32_t first_step, uint32_t n_steps, double sigma, float* ms) {
   if (!ms) return fail(PR_EINVAL, "ms is NULL");
-  return run_impl(s, first_step, n_steps, sigma, ms);
+  return run_impl(s, first_step, n_steps, sigma, ms, ms + 3);
+}
+
+int pr_sys_prepare(pr_sys* s, uint32_t n_steps, double sigma) {
+  int e = check_sys(s, true);
+  if (e) return e;
+  if (!(sigma >= 0.0) || sigma * 6.0 >= (double)s->d.L * 0.5)
+    return fail(PR_EINVAL, "sigma=%g", sigma);
+  if (!s->use_graphs) return PR_OK;
+  if ((e = grow_part(s, s->steps_since_load + n_steps))) return e;
+  s->d.jit_c = (float)(sigma / std::sqrt(21845.0));
+  // walk the segments the run would take, capturing each, then restore the
+  // host-side state (nothing ran)
+  const Dev saved_d = s->d;
+  const int64_t saved_since = s->steps_since_sort;
+  uint32_t left = n_steps;
+  while (left > 0 && !e) {
+    bool with_sort = false;
+    const int32_t K = next_segment(s, left, &with_sort);
+    hipGraphExec_t ge = nullptr;
+    e = segment_graph(s, K, with_sort, &ge);
+    after_segment(s, K, with_sort);
+    left -= (uint32_t)K;
+  }
+  s->d = saved_d;
+  s->steps_since_sort = saved_since;
+  return e;
+}
+
+int pr_sys_jitter(pr_sys* s, uint32_t first_step, uint32_t n_steps, double sigma,
+                  float* kernel_ms) {
+  int e = check_sys(s, true);
+  if (e) return e;
+  if (!(sigma >= 0.0) || sigma * 6.0 >= (double)s->d.L * 0.5)
+    return fail(PR_EINVAL, "sigma=%g", sigma);
+  if (n_steps == 0) {
+    if (kernel_ms) *kernel_ms = 0.0f;
+    return PR_OK;
+  }
+  s->d.jit_c = (float)(sigma / std::sqrt(21845.0));
+  hipStream_t st = s->stream;
+  HIP_TRY(launch_ctl_reset(s->d.ctl, first_step, 0, st));
+  if (!kernel_ms) {
+    HIP_TRY(launch_jitter_only(s->d, (int)n_steps, st, nullptr, nullptr));
+    return PR_OK;
+  }
+  // per-step kernel times, stamped at each kernel's own start and end
+  float total = 0.0f;
+  hipEvent_t ev[2];
+  HIP_TRY(hipEventCreate(&ev[0]));
+  HIP_TRY(hipEventCreate(&ev[1]));
+  for (uint32_t k = 0; k < n_steps && !e; ++k) {
+    Dev dk = s->d;
+    if (launch_jitter_only(dk, 1, st, ev[0], ev[1]) != hipSuccess ||
+        hipEventSynchronize(ev[1]) != hipSuccess) {
+      e = fail(PR_EHIP, "jitter-only launch failed");
+      break;
+    }
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
+    total += ms;
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  *kernel_ms = total;
+  return e;
+}
+
+int pr_stream_copy(const void* src, void* dst, int64_t bytes, int32_t width, void* stream,
+                   float* kernel_ms) {
+  if (width != 4 && width != 8 && width != 16) return fail(PR_EINVAL, "width=%d", width);
+  if (bytes < 0 || bytes % width) return fail(PR_EINVAL, "bytes=%lld", (long long)bytes);
+  if (bytes == 0) {
+    if (kernel_ms) *kernel_ms = 0.0f;
+    return PR_OK;
+  }
+  if (!src || !dst) return fail(PR_EINVAL, "NULL buffer");
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  if (kernel_ms) {
+    HIP_TRY(hipEventCreate(&ev[0]));
+    HIP_TRY(hipEventCreate(&ev[1]));
+  }
+  const hipError_t he = launch_stream_copy(src, dst, (long long)bytes, width, st, ev[0], ev[1]);
+  int e = he == hipSuccess ? PR_OK : fail(PR_EHIP, "stream copy: %s", hipGetErrorString(he));
+  if (kernel_ms && !e) {
+    if (hipEventSynchronize(ev[1]) != hipSuccess) e = fail(PR_EHIP, "hipEventSynchronize");
+    else (void)hipEventElapsedTime(kernel_ms, ev[0], ev[1]);
+  }
+  if (ev[0]) (void)hipEventDestroy(ev[0]);
+  if (ev[1]) (void)hipEventDestroy(ev[1]);
+  return e;
 }
 
 namespace {
@@ -1462,6 +1675,9 @@ struct pr_server {
   // keeps up to the budget mapped, and pinned control words (never freed
   // while the server lives: freeing pinned memory waits for the device)
   hipMemPool_t pool = nullptr;
+  // the control-word pool is shared by the worker (admission, failures) and
+  // the finisher (retirement): every use holds ctl_mu
+  std::mutex ctl_mu;
   std::vector<Ctl*> ctl_chunks, ctl_free;
   // retirement runs on its own thread and stream: results copied out (into
   // pinned staging, grown and never shrunk: freeing pinned memory waits for
@@ -1481,8 +1697,10 @@ namespace {
 
 // The worker's results copy of a finished replica, then its device memory
 // freed.  Returns the error code (0 = done).
-// A pinned control word from the server's pool (worker thread).
+// A pinned control word from the server's pool (worker thread; the
+// finisher returns words concurrently, so both hold ctl_mu).
 Ctl* srv_ctl(pr_server* S) {
+  std::lock_guard<std::mutex> lk(S->ctl_mu);
   if (S->ctl_free.empty()) {
     const int chunk = 64;
     Ctl* c = nullptr;
@@ -1493,6 +1711,13 @@ Ctl* srv_ctl(pr_server* S) {
   Ctl* c = S->ctl_free.back();
   S->ctl_free.pop_back();
   return c;
+}
+
+// Returns a control word to the pool (worker or finisher thread).
+void srv_put_ctl(pr_server* S, Ctl* c) {
+  if (!c) return;
+  std::lock_guard<std::mutex> lk(S->ctl_mu);
+  S->ctl_free.push_back(c);
 }
 
 int srv_finish(pr_server* S, SrvReq* r) {
@@ -1549,7 +1774,7 @@ int srv_finish(pr_server* S, SrvReq* r) {
   }
   Ctl* c = s->hctl;
   pr_sys_destroy(s);
-  S->ctl_free.push_back(c);
+  srv_put_ctl(S, c);
   r->sys = nullptr;
   return e;
 }
@@ -1565,8 +1790,8 @@ int srv_admit(pr_server* S, SrvReq* r) {
   if (!e) e = pr_sys_generate(s, q.gen_kind, q.gen_seed, q.gen_sigma0);
   if (!e) e = grow_part(s, std::max<int64_t>(1024, r->n_steps));
   if (e) {
-    if (s) pr_sys_destroy(s);
-    S->ctl_free.push_back(lease.hctl);
+    if (s) pr_sys_destroy(s);  // a leased word is not the system's to free
+    srv_put_ctl(S, lease.hctl);
     return e;
   }
   s->d.jit_c = (float)(r->sigma / std::sqrt(21845.0));
@@ -1651,7 +1876,9 @@ std::vector<SrvReq*> srv_take(pr_server* S, size_t resident) {
 
 void srv_fail(pr_server* S, SrvReq* r, int e) {
   if (r->sys) {
+    Ctl* c = r->sys->hctl;
     pr_sys_destroy(r->sys);
+    srv_put_ctl(S, c);
     r->sys = nullptr;
   }
   std::lock_guard<std::mutex> lk(S->mu);

@@ -26,6 +26,7 @@
 // selection is a minimum over 64-bit keys, so no result depends on thread or
 // atomic order, nor on the storage order of the particles.
 #include <hip/hip_ext.h>
+#include <algorithm>
 #include <hip/hip_runtime.h>
 
 #include "common.hpp"
@@ -1591,6 +1592,58 @@ __global__ __launch_bounds__(kThreads) void k_gather_out(Dev d, float* ox, float
     for (int b = 0; b < d.B; ++b) oadj[(size_t)id * d.B + b] = a.adj[(size_t)k * d.B + b];
 }
 
+// The re-jitter alone (the stand-in for the MD between reaction steps),
+// step k of a block: every particle's position of parity par moves by the
+// step's offsets into parity par ^ 1, exactly as the sweep of a reaction
+// step moves it, and the cell counts of the next parity are cleared as the
+// sweep clears them.  No reaction happens.
+__global__ __launch_bounds__(kThreads) void k_jitter_only(Dev d, int k) {
+  const Ctl* c = d.ctl;
+  const uint32_t par = (c->par0 + (uint32_t)k) & 1u, step = c->step0 + (uint32_t)k;
+  const Arr a = pick_set(d, c->set & 1u);
+  const float *X = pick(a.x, par), *Y = pick(a.y, par), *Z = pick(a.z, par);
+  float *XW = pick(a.x, par ^ 1u), *YW = pick(a.y, par ^ 1u), *ZW = pick(a.z, par ^ 1u);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < d.n) {
+    float x = X[i], y = Y[i], z = Z[i];
+    if (d.jit_c != 0.0f) rejitter(d, step, a.id ? (uint32_t)a.id[i] : (uint32_t)i, x, y, z);
+    XW[i] = x;
+    YW[i] = y;
+    ZW[i] = z;
+  }
+  for (int q = i; q < d.ncell; q += gridDim.x * blockDim.x) pick(d.cnt, par ^ 1u)[q] = 0u;
+}
+
+// Moves the block origin by K steps of the re-jitter alone: the draw step
+// and the position parity advance, the counter log does not (nothing was
+// logged).
+__global__ void k_advance_jitter(Ctl* c, int K) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    c->step0 += (uint32_t)K;
+    c->par0 = (c->par0 + (uint32_t)K) & 1u;
+  }
+}
+
+// Plain device copy of n elements of T (one element per lane and
+// iteration, grid-stride): the project's own bandwidth probe, with a known
+// request shape per wavefront (64 lanes x sizeof(T) contiguous bytes).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_stream_copy(const T* __restrict__ src,
+                                                          T* __restrict__ dst, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+// Fills n 32-bit words with v (clears scratch inside code a caller may
+// capture into a graph, where memset nodes are avoided).
+__global__ __launch_bounds__(kThreads) void k_fill_u32(uint32_t* __restrict__ p, long long n,
+                                                       uint32_t v) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
 // The generator's words for caller counters (4 uint32 per counter).
 __global__ __launch_bounds__(kThreads) void k_draws(const uint4* __restrict__ ctr, long long n,
                                                     unsigned long long key, uint4* out) {
@@ -1718,6 +1771,41 @@ hipError_t launch_sort_b(const BatchLaunch& b, hipStream_t s) {
 hipError_t launch_gather_out(const Dev& d, float* ox, float* oy, float* oz, int32_t* otyp,
                              int32_t* ost, int32_t* oadj, hipStream_t s) {
   k_gather_out<<<blocks_for(d.n, kThreads), kThreads, 0, s>>>(d, ox, oy, oz, otyp, ost, oadj);
+  return hipGetLastError();
+}
+
+// n_steps of the re-jitter alone, then the block origin moved by them.
+// ev0/ev1 (may be null): stamped at the start and end of each step's kernel.
+hipError_t launch_jitter_only(const Dev& d, int n_steps, hipStream_t s, hipEvent_t ev0,
+                              hipEvent_t ev1) {
+  const dim3 g(blocks_for(d.n, kThreads)), b(kThreads);
+  for (int k = 0; k < n_steps; ++k) {
+    if (ev0) hipExtLaunchKernelGGL(k_jitter_only, g, b, 0, s, ev0, ev1, 0, d, k);
+    else k_jitter_only<<<g, b, 0, s>>>(d, k);
+  }
+  k_advance_jitter<<<1, 64, 0, s>>>(d.ctl, n_steps);
+  return hipGetLastError();
+}
+
+// bytes must be a multiple of width; width 4, 8 or 16.  The grid holds
+// 2048 workgroups (8 per compute unit) and strides over the buffer.
+hipError_t launch_stream_copy(const void* src, void* dst, long long bytes, int width,
+                              hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  const dim3 g(2048), b(kThreads);
+  if (width == 16)
+    hipExtLaunchKernelGGL(k_stream_copy<uint4>, g, b, 0, s, ev0, ev1, 0, (const uint4*)src,
+                          (uint4*)dst, bytes / 16);
+  else if (width == 8)
+    hipExtLaunchKernelGGL(k_stream_copy<uint2>, g, b, 0, s, ev0, ev1, 0, (const uint2*)src,
+                          (uint2*)dst, bytes / 8);
+  else
+    hipExtLaunchKernelGGL(k_stream_copy<uint32_t>, g, b, 0, s, ev0, ev1, 0, (const uint32_t*)src,
+                          (uint32_t*)dst, bytes / 4);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, long long n, uint32_t v, hipStream_t s) {
+  if (n > 0) k_fill_u32<<<(int)std::min<long long>(blocks_for(n, kThreads), 4096), kThreads, 0, s>>>(p, n, v);
   return hipGetLastError();
 }
 

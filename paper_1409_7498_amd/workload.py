@@ -98,9 +98,11 @@ def lattice_sites(N, L):
 class Config:
     """One synthetic workload."""
 
-    def __init__(self, name, N, L, kind, p, steps, seed, sigma=SIGMA_JITTER, rc=RC):
+    def __init__(self, name, N, L, kind, p, steps, seed, sigma=SIGMA_JITTER, rc=RC, gen_seed=None):
         self.name, self.N, self.L, self.kind = name, int(N), float(np.float32(L)), kind
         self.p, self.steps, self.seed, self.sigma, self.rc = float(p), int(steps), int(seed), sigma, rc
+        # seed of the initial configuration (the reaction steps draw with `seed`)
+        self.gen_seed = int(seed if gen_seed is None else gen_seed)
 
     def rule(self):
         return rule_for(self.kind, self.rc, self.p)
@@ -108,6 +110,16 @@ class Config:
     @property
     def B(self):
         return 4 if self.kind == "step" else 2
+
+    def initial(self):
+        """The initial configuration (host arrays), as generate() makes it."""
+        return generate(self.N, self.L, self.kind, self.gen_seed)
+
+    def desc(self, log_cap=None):
+        """Replica description (the keys of the library's replica struct)."""
+        return dict(n=self.N, L=self.L, B=self.B, rule=self.rule(), seed=self.seed,
+                    kind=self.kind, gen_seed=self.gen_seed, sigma0=SIGMA_LATTICE,
+                    log_cap=2 * self.N if log_cap is None else log_cap)
 
     def __repr__(self):
         return "Config(%s, N=%d, L=%g, %s, p=%g, steps=%d)" % (self.name, self.N, self.L, self.kind,
@@ -183,7 +195,8 @@ def replica_configs(n_rep=256, steps=500, seed=MASTER_SEED + 4, nmin=2000, nmax=
         kind = "step" if i % 2 == 0 else "chain"
         p = 0.001 + 0.019 * u1
         rseed = int(k[0][i]) | (int(k[1][i]) << 32)
-        out.append(Config("rep%d" % i, N, box_for(N), kind, p, steps, rseed))
+        out.append(Config("rep%d" % i, N, box_for(N), kind, p, steps, rseed,
+                          gen_seed=rseed ^ 0x5A5A))
     return out
 
 
@@ -203,5 +216,6 @@ def request_stream(n_req=10000, rate=200.0, steps=1000, seed=MASTER_SEED + 5, nm
         p = 0.001 + 0.019 * u1
         rseed = int(k[0][i]) | (int(k[1][i]) << 32)
         arrivals.append(t)
-        cfgs.append(Config("req%d" % i, N, box_for(N), kind, p, steps, rseed))
+        cfgs.append(Config("req%d" % i, N, box_for(N), kind, p, steps, rseed,
+                           gen_seed=rseed ^ 0x5A5A))
     return np.array(arrivals), cfgs

@@ -480,8 +480,95 @@ def check_chain_consumption(lib, p=0.05, steps=40):
     assert 0.85 * pred < obs < 1.01 * pred + 3 * math.sqrt(pred), (obs, pred)
 
 
+# --------------------------------------------------------------------------
+# FP64 recheck of the cutoff decision (diagnostic; the step decides in FP32)
+# --------------------------------------------------------------------------
+RC32 = float(np.float32(1.12))  # the cutoff as the FP32 value both sides use
+
+
+def _near(lib, s, rule, tol=1e-6):
+    return oracle.near_cutoff(s, rule, tol, lib=lib)
+
+
+def _float_at(base, target):
+    """The float32 v nearest to base + target whose difference v - base is
+    exact (both float32): returns (v, v - base as a Python float)."""
+    v = np.float32(base + target)
+    return v, float(v) - float(np.float32(base))
+
+
+def check_near_cutoff(lib):
+    """Pairs placed on one axis: the FP64 distance is the coordinate
+    difference itself (exact), so each case's count is known by construction.
+    Offsets of 6e-7 from rc: |r - rc| < 1e-6 although |r^2 - rc^2| > 1e-6;
+    1e-5: not near.  At 6e-7 the FP32 r^2 is ~11 ulps from fl32(rc^2), so FP32
+    and FP64 agree (no disagreement)."""
+    L = 10.0
+    for off, near in ((6e-7, 1), (-6e-7, 1), (1e-5, 0), (-1e-5, 0), (3e-3, 0)):
+        xt, r = _float_at(2.0, RC32 + off)
+        assert abs(abs(r - RC32) - abs(off)) < 2.5e-7
+        s = mk(L, [(2.0, 5, 5), (xt, 5, 5)], [1, 0], [4, 2])
+        assert _near(lib, s, step_rule()) == (near, 0), (off, _near(lib, s, step_rule()))
+    # across the periodic boundary (x = 0): only a wrapped FP64 difference is near
+    xt, r = _float_at(0.3, -(RC32 + 6e-7))
+    xt = np.float32(float(xt) + L)
+    s = mk(L, [(0.3, 5, 5), (xt, 5, 5)], [1, 0], [4, 2])
+    assert _near(lib, s, step_rule()) == (1, 0)
+    # ineligible pairs at the same offset are not counted: A-A, T-T, a spent
+    # crosslinker (state 0) and a spent end unit (state 0)
+    xt, _ = _float_at(2.0, RC32 - 6e-7)
+    for types, states in (([1, 1], [4, 4]), ([0, 0], [2, 2]), ([1, 0], [0, 2]), ([1, 0], [4, 0])):
+        s = mk(L, [(2.0, 5, 5), (xt, 5, 5)], types, states)
+        assert _near(lib, s, step_rule()) == (0, 0), (types, states)
+    # several pairs of one A (and a second A) are counted one by one
+    xa, _ = _float_at(2.0, RC32 + 6e-7)
+    xb, _ = _float_at(2.0, -(RC32 - 6e-7))
+    s = mk(L, [(2.0, 5, 5), (xa, 5, 5), (xb, 5, 5), (2.0, 8, 5), (2.0, 8, 5 + 0.5)],
+           [1, 0, 0, 1, 0], [4, 2, 1, 4, 2])
+    assert _near(lib, s, step_rule()) == (2, 0)
+
+
+def check_near_cutoff_disagree(lib, want=3):
+    """Pairs whose FP32 decision (the step's own in-range count at p = 1)
+    differs from the exact one.  The truth comes from exact rational
+    arithmetic on the same FP32 coordinates (r < rc <=> r^2 < rc^2); the
+    recheck must count each such pair as near and as a disagreement, and a
+    pair where both agree as no disagreement."""
+    from fractions import Fraction as F
+    rng = np.random.default_rng(2024)
+    rc = F(RC32)
+    found = agreeing = 0
+    for trial in range(4000):
+        if found >= want and agreeing >= want:
+            break
+        dx, dy = np.float32(rng.uniform(0.3, 0.7)), np.float32(rng.uniform(0.3, 0.7))
+        xa = np.float32(3.0)
+        pa = (xa, np.float32(3.0), np.float32(3.0))
+        rest = float(rc * rc) - float(dx) ** 2 - float(dy) ** 2
+        dz0 = np.float32(math.sqrt(rest))
+        dz = dz0
+        for _ in range(rng.integers(-3, 4)):
+            dz = np.nextafter(dz, np.float32(2.0))
+        pt = (np.float32(pa[0] + dx), np.float32(pa[1] + dy), np.float32(pa[2] + dz))
+        d = [F(float(pt[c])) - F(float(pa[c])) for c in range(3)]
+        exact_in = d[0] ** 2 + d[1] ** 2 + d[2] ** 2 < rc * rc
+        s = mk(10.0, [pa, pt], [1, 0], [4, 2])
+        _, _, st = one(lib, s.copy(), step_rule(p=1.0))
+        fp32_in = st["in_rc"] == 1
+        near, dis = _near(lib, s, step_rule())
+        assert near == 1, (trial, near)  # within a few ulps of rc by construction
+        if fp32_in != exact_in:
+            assert dis == 1, (trial, pt)
+            found += 1
+        else:
+            assert dis == 0, (trial, pt)
+            agreeing += 1
+    assert found >= want and agreeing >= want, (found, agreeing)
+
+
 ALL = [check_pair_distance, check_periodic, check_cutoff_strict, check_p0_p1, check_isolated_pairs,
        check_isolated_cluster_probability, check_acceptance_ratio, check_two_a_one_t,
        check_two_a_one_t_probability, check_uniform_choice, check_exact_small_graph,
        check_exclusion, check_valence_stop, check_chain_transfer, check_errors, check_adj_overflow,
-       check_jitter_distribution, check_generator_offsets, check_jitter_wrap]
+       check_jitter_distribution, check_generator_offsets, check_jitter_wrap,
+       check_near_cutoff, check_near_cutoff_disagree]

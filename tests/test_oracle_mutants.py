@@ -21,6 +21,10 @@ MUTANTS = {
     9: ("bonded pairs not excluded", [pins.check_exclusion]),
     10: ("state deltas swapped between roles", [pins.check_chain_transfer]),
     12: ("off-centre jitter offsets", [pins.check_jitter_distribution]),
+    14: ("FP64 recheck without the periodic wrap", [pins.check_near_cutoff]),
+    15: ("FP64 tolerance applied to r^2", [pins.check_near_cutoff]),
+    16: ("FP64 recheck counts every particle as an A", [pins.check_near_cutoff]),
+    17: ("FP32 side of the recheck evaluated in FP64", [pins.check_near_cutoff_disagree]),
 }
 
 
