@@ -122,6 +122,23 @@ int pr_react_step(int32_t n, float L, const float* x, const float* y, const floa
                   const pr_rule* rule, uint64_t seed, uint32_t step, int32_t* bonds,
                   int32_t cap, int32_t* n_bonds, pr_stats* st, void* stream);
 
+/* pr_react_step for callers that cannot allocate device memory: tight serving
+ * loops and harnesses that forbid hipMalloc (like pr_react_step it
+ * synchronises its stream, so it is not itself meant for graph capture).  Same
+ * arguments, arithmetic, results and errors as pr_react_step, but no call to
+ * hipMalloc, hipFree or any allocating routine: the step's scratch is one
+ * fixed region of device memory per GPU (24 MiB, a file-scope device array
+ * of the library, held until the process ends).  n is limited to 32768
+ * particles (PR_EINVAL beyond, with nothing written); every such call on one
+ * GPU shares the region and clears what it needs at its start.  Calls on one
+ * GPU are serialised by the library for the duration of the call (it
+ * synchronises stream before returning); launches that other code makes into
+ * the region concurrently would race.  Synchronises stream. */
+int pr_react_step_noalloc(int32_t n, float L, const float* x, const float* y, const float* z,
+                          const int32_t* type, int32_t* state, int32_t* adj, int32_t B,
+                          const pr_rule* rule, uint64_t seed, uint32_t step, int32_t* bonds,
+                          int32_t cap, int32_t* n_bonds, pr_stats* st, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Resident system: particle state kept in device memory across steps.      */
 /* ------------------------------------------------------------------------ */

@@ -76,6 +76,8 @@ def _load():
         "pr_version": ([], C.c_char_p),
         "pr_react_step": ([i32, f32, vp, vp, vp, vp, vp, vp, i32, P(Rule), u64, u32, vp, i32,
                            P(i32), P(Stats), vp], C.c_int),
+        "pr_react_step_noalloc": ([i32, f32, vp, vp, vp, vp, vp, vp, i32, P(Rule), u64, u32, vp,
+                                   i32, P(i32), P(Stats), vp], C.c_int),
         "pr_sys_create": ([P(vp), i32, f32, i32, P(Rule), u64, i64, vp], C.c_int),
         "pr_sys_create_ex": ([P(vp), i32, f32, i32, P(Rule), u64, i64, vp, i32], C.c_int),
         "pr_sys_geometry": ([vp, P(i32), P(i32), P(i32)], C.c_int),
@@ -130,7 +132,8 @@ lib = _load()
 
 
 def exported_symbols():
-    return [n for n in ("pr_last_error", "pr_version", "pr_react_step", "pr_sys_create",
+    return [n for n in ("pr_last_error", "pr_version", "pr_react_step", "pr_react_step_noalloc",
+                        "pr_sys_create",
                         "pr_sys_create_ex", "pr_sys_geometry", "pr_autotune",
                         "pr_sys_destroy", "pr_sys_load", "pr_sys_generate", "pr_sys_run",
                         "pr_sys_run_timed", "pr_sys_read", "pr_sys_bonds", "pr_sys_stats",
@@ -162,8 +165,10 @@ def _stream(stream=None):
 
 
 def react_step(x, y, z, type_, state, adj, L, rule, seed, step, bonds=None, stream=None,
-               raise_on_error=True):
+               raise_on_error=True, noalloc=False):
     """One reaction step on device tensors (state and adj updated in place).
+    noalloc: through pr_react_step_noalloc (library scratch in a fixed device
+    region, no allocation; n <= 32768).
 
     Returns (code, bonds[n_b, 2] device tensor view, stats dict)."""
     import torch
@@ -178,7 +183,7 @@ def react_step(x, y, z, type_, state, adj, L, rule, seed, step, bonds=None, stre
     nb = C.c_int32(0)
     st = Stats()
     r = rule if isinstance(rule, Rule) else Rule.make(rule)
-    fn = lib.pr_react_step
+    fn = lib.pr_react_step_noalloc if noalloc else lib.pr_react_step
     code = fn(n, C.c_float(L), _ptr(x), _ptr(y), _ptr(z), _ptr(type_), _ptr(state), _ptr(adj), B,
               C.byref(r), C.c_uint64(seed), C.c_uint32(step), _ptr(bonds), bonds.shape[0],
               C.byref(nb), C.byref(st), _stream(stream))

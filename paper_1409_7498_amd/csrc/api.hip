@@ -338,6 +338,33 @@ int single_step(const Dev& d, uint32_t step, hipStream_t s, Ctl* hctl, int32_t* 
   return PR_OK;
 }
 
+// Scratch of the allocation-free single step: one region per device, the
+// file-scope array below.  Host code never passes the array's name to a
+// kernel (on the host it only stands for the symbol); it uses the device
+// address hipGetSymbolAddress returns for the current device, kept per device.
+constexpr size_t kScratchBytes = (size_t)24 << 20;
+constexpr int32_t kScratchMaxN = 32768;
+constexpr int kScratchMaxDev = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu[kScratchMaxDev];  // one call at a time per device
+char* g_scratch_ptr[kScratchMaxDev] = {};
+std::mutex g_scratch_init_mu;
+
+// Carves the scratch of a single step of up to n particles and ncell cells
+// out of arena a (the same buffers pr_react_step's workspace allocates).
+int carve_single(Arena& a, Dev& d, int32_t n, uint8_t** role) {
+  int e = alloc_scratch(a, d, n, sweep_blocks(n), nullptr);
+  if (e) return e;
+  size_t n2 = 1;
+  while (n2 < (size_t)n / 2 + 1) n2 <<= 1;
+  const int ngroups = (sweep_blocks(n) + kGroup - 1) / kGroup;
+  if ((e = a.alloc(&d.part, (size_t)ngroups * kPart)) ||
+      (e = a.alloc(&d.log, 3 * ((size_t)n / 2 + 1))) || (e = a.alloc(role, (size_t)n)) ||
+      (e = a.alloc(&d.sortbuf, n2)))
+    return e;
+  return PR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -396,6 +423,58 @@ int pr_react_step(int32_t n, float L, const float* x, const float* y, const floa
   return single_step(d, step, s, ws->hctl, ws->hpart, n_bonds, st);
 }
 
+int pr_react_step_noalloc(int32_t n, float L, const float* x, const float* y, const float* z,
+                          const int32_t* type, int32_t* state, int32_t* adj, int32_t B,
+                          const pr_rule* rule, uint64_t seed, uint32_t step, int32_t* bonds,
+                          int32_t cap, int32_t* n_bonds, pr_stats* st, void* stream) {
+  int e = check_single(n, L, x, y, z, type, state, adj, B, rule, bonds, cap, n_bonds);
+  if (e) return e;
+  if (n > kScratchMaxN)
+    return fail(PR_EINVAL, "n=%d: the allocation-free step takes at most %d particles", n,
+                kScratchMaxN);
+  Dev geo{};
+  set_geometry(geo, n, L, B, rule, seed, kDefaultBrick);
+  Arena dry;
+  dry.dry = true;
+  uint8_t* role = nullptr;
+  Dev dd = geo;
+  if ((e = carve_single(dry, dd, std::max(n, 1), &role))) return e;
+  if (dry.bytes > kScratchBytes)
+    return fail(PR_EINVAL, "n=%d, %d cells: %zu bytes of scratch, the allocation-free step "
+                "holds %zu", n, geo.ncell, dry.bytes, kScratchBytes);
+  *n_bonds = 0;
+  if (st) std::memset(st, 0, sizeof *st);
+  if (n == 0) return PR_OK;
+  hipStream_t s = (hipStream_t)stream;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kScratchMaxDev) return fail(PR_EINVAL, "device %d", dev);
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_init_mu);
+    if (!g_scratch_ptr[dev]) {
+      void* ptr = nullptr;
+      HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+      g_scratch_ptr[dev] = (char*)ptr;
+    }
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu[dev]);
+  Arena carve;
+  carve.base = g_scratch_ptr[dev];
+  carve.cap = kScratchBytes;
+  Dev d = geo;
+  if ((e = carve_single(carve, d, n, &role))) return e;
+  bind_single(d, geo, const_cast<float*>(x), const_cast<float*>(y), const_cast<float*>(z),
+              const_cast<int32_t*>(type), state, adj, role, bonds, cap);
+  // the region keeps the previous call's contents: clear what the kernels
+  // expect empty (cell counts, A keys, T flags) with fill kernels
+  HIP_TRY(launch_fill_u32(d.cnt[0], d.ncell, 0u, s));
+  HIP_TRY(launch_fill_u32(d.cnt[1], d.ncell, 0u, s));
+  HIP_TRY(launch_fill_u32((uint32_t*)d.slotA, 2LL * n, 0xFFFFFFFFu, s));
+  HIP_TRY(launch_fill_u32((uint32_t*)d.tflag, ((long long)n + 3) / 4, 0u, s));
+  Ctl hctl{};
+  int32_t hpart[((kScratchMaxN + kThreads - 1) / kThreads + kGroup - 1) / kGroup * kPart];
+  return single_step(d, step, s, &hctl, hpart, n_bonds, st);
+}
 
 }  // extern "C"
 

@@ -125,3 +125,18 @@ def test_empty_step_without_gpu():
                                None)
     assert code == b.PR_OK and nb.value == 0
     assert all(v == 0 for v in st.as_dict().values())
+
+
+def test_noalloc_limit_without_gpu():
+    """The allocation-free step refuses more particles than its fixed scratch
+    holds, on the host, before any device call (the pointers are never read)."""
+    from paper_1409_7498_amd import binding as b
+    r = b.Rule.make(type_a=1, a_min=1, a_max=4, d_a=-1, type_t=0, t_min=1, t_max=2, d_t=-1,
+                    rc=1.12, exclude_bonded=1, p=0.5)
+    nb = ctypes.c_int32(0)
+    fake = ctypes.c_void_p(0x1000)
+    n = 32769
+    code = b.lib.pr_react_step_noalloc(n, ctypes.c_float(40.0), fake, fake, fake, fake, fake, fake,
+                                       4, ctypes.byref(r), 1, 1, fake, n // 2, ctypes.byref(nb),
+                                       None, None)
+    assert code == b.PR_EINVAL and b"at most 32768" in b.lib.pr_last_error()
