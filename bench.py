@@ -312,6 +312,9 @@ def main():
     ap.add_argument("--steps", type=int, default=256)
     ap.add_argument("--warmup", type=int, default=64)
     ap.add_argument("--config", default="c2")
+    ap.add_argument("--policy", default="random", choices=["random", "nearest"],
+                    help="selection: the paper's (random) or LAMMPS fix bond/create's "
+                         "closest partner (nearest)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--sort-period", type=int, default=-1)
     ap.add_argument("--brick", default="0",
@@ -369,7 +372,8 @@ def main():
         log("autotune: edge %d, us per step by edge %s" % (brick, tuned))
     else:
         brick = int(args.brick)
-    sysm = binding.System(cfg.N, cfg.L, cfg.B, cfg.rule(), cfg.seed,
+    rule = dict(cfg.rule(), policy=args.policy)
+    sysm = binding.System(cfg.N, cfg.L, cfg.B, rule, cfg.seed,
                           log_cap=cfg.N * 2, stream=stream, brick=brick)
     if args.sort_period >= 0:
         sysm.set_sort_period(args.sort_period)
@@ -421,7 +425,8 @@ def main():
     achieved = sweep_bytes / (sweep_ms * 1e-3) / 1e9
     react_ms = step_ms - jit_ms
     # the counters were taken on the default workload at the default edge
-    profiled = args.config == "c2" and sysm.geometry()[1] == 4 and sort_period == 64
+    profiled = (args.config == "c2" and sysm.geometry()[1] == 4 and sort_period == 64
+                and args.policy == "random")
     traffic = recorded_traffic() if profiled else None
     out = {
         "metric": "reaction-step particles/s at 1M + % HBM roofline",
@@ -444,6 +449,7 @@ def main():
                                   cfg.sigma),
                    "steps_timed": K, "sort_period": sort_period,
                    "brick": sysm.geometry()[1], "brick_autotune_us": tuned,
+                   "policy": args.policy,
                    "path": "graph replay (captured before the window)"},
         "window_ms": window_ms,
         "sorts_in_window": sorts_in,
@@ -463,14 +469,15 @@ def main():
         "t_elig_per_step": n_t,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_sweep", "bytes_per_launch": sweep_bytes},
+                     "kernel": "k_sweep" if args.policy == "random" else "k_near_sweep",
+                     "bytes_per_launch": sweep_bytes},
         "cpu_baseline": None,
     }
     sysm.close()
     copy = copy_bandwidth()
     out["roofline"]["copy_gbs"] = copy
     out["roofline"]["frac_of_copy"] = achieved / copy
-    if not args.no_cpu:
+    if not args.no_cpu and args.policy == "random":
         log("timing the CPU oracle on one full step of the workload ...")
         out["cpu_baseline"] = cpu_baseline(cfg)
         out["fp64_near_cutoff"] = out["cpu_baseline"]["fp64_recheck"]

@@ -53,19 +53,35 @@ extern "C" {
 #define PR_ENOTFOUND (-7)       /* serving: unknown ticket */
 #define PR_ECANCELED (-8)       /* serving: the request was cancelled */
 
+/* Selection policies of a rule.
+ * PR_POLICY_RANDOM: the paper's algorithm (Sec. III, Table I): every
+ *   candidate pair is accepted with probability p, each A picks one accepted
+ *   T at random, each T one of the A's that picked it.
+ * PR_POLICY_NEAREST: the selection of LAMMPS fix bond/create (Sec. IV A):
+ *   every particle keeps its closest candidate partner (key (r^2, partner id):
+ *   equal distances go to the lower id); a pair whose particles keep each
+ *   other is tested once, u < p with the pair's draw (word 0 of the counter
+ *   (step, id_A, id_T, 0)), and bonds if it passes.  Already bonded pairs
+ *   (exclude_bonded) are no candidates at all.  Counters: drawn = mutual
+ *   pairs tested, accepted = bonds, excluded = in-range pairs already bonded. */
+#define PR_POLICY_RANDOM 0
+#define PR_POLICY_NEAREST 1
+
 /* One reaction rule, T^t + A^a -> T^(t+d_t)-A^(a+d_a) (Sec. II, Eq. (2)).
  * A particle is eligible for the A role iff type == type_a and
  * a_min <= state <= a_max (the paper's s_min^A, Sec. III); for the T role iff
  * type == type_t and t_min <= state <= t_max.  Roles are decided on the state
  * before the step.  rc: reaction cutoff (strict, r < rc).  p = k*dt*Theta in
  * [0, 1] (Sec. II, Eqs. (3)-(4)).  exclude_bonded = 1: a pair that is already
- * bonded (id_T present in the A's adjacency row) is never a candidate. */
+ * bonded (id_T present in the A's adjacency row) is never a candidate.
+ * policy: PR_POLICY_RANDOM (0) or PR_POLICY_NEAREST (1), else PR_EINVAL. */
 typedef struct pr_rule {
   int32_t type_a, a_min, a_max, d_a;
   int32_t type_t, t_min, t_max, d_t;
   float rc;
   int32_t exclude_bonded;
   double p;
+  int32_t policy;
 } pr_rule;
 
 /* Per-step counters.  in_rc: eligible (A, T) pairs with r2 < rc2; drawn: of

@@ -47,6 +47,10 @@ def _declare(lib):
     lib.or_run.argtypes = [i32, f32, P(f32), P(f32), P(f32), P(i32), P(i32), P(i32), i32,
                            *rule, u64, u32, u32, f64, P(i32), i64, P(i64), P(i64)]
     lib.or_run.restype = C.c_int
+    lib.or_react_step_nearest.argtypes = lib.or_react_step.argtypes
+    lib.or_react_step_nearest.restype = C.c_int
+    lib.or_run_nearest.argtypes = lib.or_run.argtypes
+    lib.or_run_nearest.restype = C.c_int
     lib.or_sample_bonds.argtypes = [i32, f32, P(f32), P(f32), P(f32), P(i32), P(i32), P(i32), i32,
                                     *rule, u64, u32, P(i64), i64, P(i32)]
     lib.or_sample_bonds.restype = C.c_int
@@ -67,13 +71,18 @@ def _declare(lib):
 
 
 class Rule:
-    """Reaction rule T^t + A^a -> T^(t+dT)-A^(a+dA) (Sec. II, Eq. (2))."""
+    """Reaction rule T^t + A^a -> T^(t+dT)-A^(a+dA) (Sec. II, Eq. (2)).
+
+    policy: "random" (the paper's selection, Table I) or "nearest" (the
+    closest-partner selection of LAMMPS fix bond/create, Sec. IV A)."""
 
     def __init__(self, type_a, a_min, a_max, d_a, type_t, t_min, t_max, d_t, rc, p,
-                 exclude_bonded=1):
+                 exclude_bonded=1, policy="random"):
         self.type_a, self.a_min, self.a_max, self.d_a = type_a, a_min, a_max, d_a
         self.type_t, self.t_min, self.t_max, self.d_t = type_t, t_min, t_max, d_t
         self.rc, self.p, self.exclude_bonded = float(rc), float(p), int(exclude_bonded)
+        assert policy in ("random", "nearest"), policy
+        self.policy = policy
 
     def args(self):
         return (self.type_a, self.a_min, self.a_max, self.d_a, self.type_t, self.t_min,
@@ -132,7 +141,8 @@ def react_step(sysm, rule, seed, step, lib=None):
     bonds = np.empty((cap, 2), dtype=np.int32)
     nb = C.c_int64(0)
     st = np.zeros(ST_COUNT, dtype=np.int64)
-    code = lib.or_react_step(n, C.c_float(sysm.L), _p(sysm.x, C.c_float), _p(sysm.y, C.c_float),
+    fn = lib.or_react_step_nearest if rule.policy == "nearest" else lib.or_react_step
+    code = fn(n, C.c_float(sysm.L), _p(sysm.x, C.c_float), _p(sysm.y, C.c_float),
                              _p(sysm.z, C.c_float), _p(sysm.type, C.c_int32),
                              _p(sysm.state, C.c_int32), _p(sysm.adj, C.c_int32), sysm.B,
                              *rule.args(), C.c_uint64(seed), C.c_uint32(step), _p(bonds, C.c_int32),
@@ -151,7 +161,8 @@ def run(sysm, rule, seed, first_step, n_steps, sigma, log_cap=None, lib=None):
     log = np.empty((log_cap, 3), dtype=np.int32)
     nl = C.c_int64(0)
     st = np.zeros((max(n_steps, 1), ST_COUNT), dtype=np.int64)
-    code = lib.or_run(n, C.c_float(sysm.L), _p(sysm.x, C.c_float), _p(sysm.y, C.c_float),
+    fn = lib.or_run_nearest if rule.policy == "nearest" else lib.or_run
+    code = fn(n, C.c_float(sysm.L), _p(sysm.x, C.c_float), _p(sysm.y, C.c_float),
                       _p(sysm.z, C.c_float), _p(sysm.type, C.c_int32), _p(sysm.state, C.c_int32),
                       _p(sysm.adj, C.c_int32), sysm.B, *rule.args(), C.c_uint64(seed),
                       C.c_uint32(first_step), C.c_uint32(n_steps), float(sigma),

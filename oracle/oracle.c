@@ -402,6 +402,180 @@ int or_react_step(int32_t n, float L, const float* x, const float* y, const floa
 }
 
 /* ----------------------------------------------------------------------- */
+/* The "nearest" selection of LAMMPS fix bond/create (Sec. IV A), one step:  */
+/*  1. every candidate pair -- eligible A and T (same windows as the rule),  */
+/*     in range (r2 < rc2, FP32 as above), not already bonded when           */
+/*     exclude_bonded -- is visited; each particle records its closest       */
+/*     partner, by the key (r2, partner id): r2's FP32 bits above the id,    */
+/*     so equal distances go to the lower id;                                */
+/*  2. the consolidation across processors has nothing to do on one memory; */
+/*  3. a pair whose partners record each other is evaluated once: the       */
+/*     probability test u < p with the pair's draw (counter (step, id_A,     */
+/*     id_T, 0), word 0, the same draw as above: one draw per pair, which is */
+/*     what evaluating it on one particle of the pair amounts to);           */
+/*  then bonds and states as in step 9 of the random selection.             */
+/* A pair whose draw fails does not bond, and neither partner falls back to */
+/* another one in that step.                                                */
+/* Counters: in_rc and excluded count in-range pairs (excluded: bonded);    */
+/* drawn counts the mutual pairs, accepted and bonds those that pass;       */
+/* proposals counts A's with a closest partner.                             */
+/* ----------------------------------------------------------------------- */
+typedef struct {
+  int64_t i, j;
+  float r2;
+} or_cand;
+
+static uint64_t near_key(float r2, int64_t partner) {
+  uint32_t bits;
+  memcpy(&bits, &r2, sizeof bits);  /* r2 >= 0: its bits order like the value */
+  return ((uint64_t)bits << 32) | (uint64_t)(uint32_t)partner;
+}
+
+int or_react_step_nearest(int32_t n, float L, const float* x, const float* y, const float* z,
+                          const int32_t* type, int32_t* state, int32_t* adj, int32_t B,
+                          int32_t type_a, int32_t a_min, int32_t a_max, int32_t d_a,
+                          int32_t type_t, int32_t t_min, int32_t t_max, int32_t d_t,
+                          float rc, double p, int32_t exclude_bonded,
+                          uint64_t seed, uint32_t step,
+                          int32_t* bonds, int64_t cap, int64_t* n_bonds, int64_t* stats) {
+  or_rule R = {type_a, a_min, a_max, d_a, type_t, t_min, t_max, d_t, rc, p, exclude_bonded};
+  int err = validate(n, L, x, y, z, B, &R);
+  if (err) return err;
+  if (cap < (int64_t)n / 2) return OR_ECAP;
+  const uint64_t thresh = or_threshold(p);
+  const float halfL = 0.5f * L, rc2 = rc * rc;
+  const size_t nn = (size_t)(n > 0 ? n : 1);
+  int64_t* alist = (int64_t*)malloc(sizeof(int64_t) * nn);
+  uint8_t* is_t = (uint8_t*)malloc(nn);
+  uint64_t* nearA = (uint64_t*)malloc(sizeof(uint64_t) * nn);
+  uint64_t* nearT = (uint64_t*)malloc(sizeof(uint64_t) * nn);
+  if (!alist || !is_t || !nearA || !nearT) {
+    free(alist); free(is_t); free(nearA); free(nearT);
+    return OR_ENOMEM;
+  }
+  int64_t na = 0, nt = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (is_active(&R, type[i], state[i])) alist[na++] = i;
+    is_t[i] = (uint8_t)is_target(&R, type[i], state[i]);
+    nt += is_t[i];
+    nearA[i] = nearT[i] = UINT64_MAX;
+  }
+  /* Step 1, brute force over all (A, T) pairs in tiles of OR_TILE A's: the
+   * in-range pairs of each tile are collected, then every candidate updates
+   * the closest-partner keys of both of its particles. */
+  const int64_t ntile = (na + OR_TILE - 1) / OR_TILE;
+  or_cand** found = (or_cand**)calloc((size_t)(ntile > 0 ? ntile : 1), sizeof(or_cand*));
+  int64_t* nfound = (int64_t*)calloc((size_t)(ntile > 0 ? ntile : 1), sizeof(int64_t));
+  int oom = !found || !nfound;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t t = 0; t < ntile; ++t) {
+    if (oom) continue;
+    const int64_t k0 = t * OR_TILE;
+    const int m = (int)(na - k0 < OR_TILE ? na - k0 : OR_TILE);
+    int64_t cap_t = 256, cnt = 0;
+    or_cand* buf = (or_cand*)malloc(sizeof(or_cand) * (size_t)cap_t);
+    for (int64_t j = 0; j < n && buf; ++j) {
+      if (!is_t[j]) continue;
+      for (int k = 0; k < m; ++k) {
+        const int64_t i = alist[k0 + k];
+        if (i == j) continue;
+        const float r2 = dist2(x, y, z, i, j, L, halfL);
+        if (!in_cutoff(r2, rc2)) continue;
+        if (cnt == cap_t) {
+          cap_t *= 2;
+          or_cand* nb = (or_cand*)realloc(buf, sizeof(or_cand) * (size_t)cap_t);
+          if (!nb) { free(buf); buf = NULL; break; }
+          buf = nb;
+        }
+        buf[cnt].i = i;
+        buf[cnt].j = j;
+        buf[cnt].r2 = r2;
+        cnt++;
+      }
+    }
+    if (!buf) oom = 1;
+    found[t] = buf;
+    nfound[t] = cnt;
+  }
+  int64_t in_rc = 0, excluded = 0;
+  for (int64_t t = 0; t < ntile && !oom; ++t) {
+    for (int64_t c = 0; c < nfound[t]; ++c) {
+      const or_cand q = found[t][c];
+      in_rc++;
+#if OR_MUTANT == 18 /* mutant: bonded pairs stay candidates */
+      const int already = 0;
+#else
+      const int already = exclude_bonded && bonded(adj, B, q.i, q.j);
+#endif
+      if (already) {
+        excluded++;
+        continue;
+      }
+      const uint64_t ka = near_key(q.r2, q.j), kt = near_key(q.r2, q.i);
+      if (ka < nearA[q.i]) nearA[q.i] = ka;
+      if (kt < nearT[q.j]) nearT[q.j] = kt;
+    }
+  }
+  for (int64_t t = 0; t < ntile && found; ++t) free(found[t]);
+  free(found);
+  free(nfound);
+  if (oom) {
+    free(alist); free(is_t); free(nearA); free(nearT);
+    return OR_ENOMEM;
+  }
+  /* Step 3: mutual pairs, one draw each, bonds in increasing id_A order */
+  int64_t proposals = 0, mutual = 0, nb = 0;
+  for (int64_t k = 0; k < na; ++k) {
+    const int64_t i = alist[k];
+    if (nearA[i] == UINT64_MAX) continue;
+    proposals++;
+    const int64_t j = (int64_t)(nearA[i] & 0xFFFFFFFFu);
+#if OR_MUTANT == 19 /* mutant: the T side's choice ignored */
+    const int mutual_pair = 1;
+#else
+    const int mutual_pair = (int64_t)(nearT[j] & 0xFFFFFFFFu) == i;
+#endif
+    if (!mutual_pair) continue;
+    mutual++;
+    uint32_t ctr[4] = {step, (uint32_t)i, (uint32_t)j, 0u}, w[4];
+    or_philox4x32_10(ctr, seed, w);
+    if (!((uint64_t)w[0] < thresh)) continue;
+    bonds[2 * nb] = (int32_t)i;
+    bonds[2 * nb + 1] = (int32_t)j;
+    nb++;
+  }
+  /* bonds and states (Table I, step 9), simultaneously */
+  int64_t overflow = 0;
+  for (int64_t b = 0; b < nb; ++b) {
+    const int64_t i = bonds[2 * b], j = bonds[2 * b + 1];
+    state[i] += d_a;
+    state[j] += d_t;
+    int placed = 0;
+    for (int32_t s2 = 0; s2 < B && !placed; ++s2)
+      if (adj[i * B + s2] < 0) { adj[i * B + s2] = (int32_t)j; placed = 1; }
+    if (!placed) overflow++;
+    placed = 0;
+    for (int32_t s2 = 0; s2 < B && !placed; ++s2)
+      if (adj[j * B + s2] < 0) { adj[j * B + s2] = (int32_t)i; placed = 1; }
+    if (!placed) overflow++;
+  }
+  *n_bonds = nb;
+  if (stats) {
+    stats[ST_A_ELIG] = na;
+    stats[ST_T_ELIG] = nt;
+    stats[ST_IN_RC] = in_rc;
+    stats[ST_DRAWN] = mutual;
+    stats[ST_EXCLUDED] = excluded;
+    stats[ST_ACCEPTED] = nb;
+    stats[ST_PROPOSALS] = proposals;
+    stats[ST_BONDS] = nb;
+    stats[ST_ADJ_OVERFLOW] = overflow;
+  }
+  free(alist); free(is_t); free(nearA); free(nearT);
+  return overflow ? OR_ECAP : OR_OK;
+}
+
+/* ----------------------------------------------------------------------- */
 /* Sampled form of steps 1-7, for checks at sizes where a whole step is too  */
 /* slow: for each sampled particle ids[k], out[k] = the id of the target it  */
 /* bonds with in this step, or -1.  Its choice (steps 1-5) is computed by    */
@@ -630,7 +804,8 @@ void or_jitter(int32_t n, float L, float* x, float* y, float* z, uint64_t seed,
 /* jitters the positions with step index s (if sigma > 0) and then reacts.   */
 /* Bond log rows: (step, id_A, id_T).  stats_per_step: n_steps x ST_COUNT.   */
 /* ----------------------------------------------------------------------- */
-int or_run(int32_t n, float L, float* x, float* y, float* z, const int32_t* type,
+static int run_policy(int policy, int32_t n, float L, float* x, float* y, float* z,
+                      const int32_t* type,
            int32_t* state, int32_t* adj, int32_t B,
            int32_t type_a, int32_t a_min, int32_t a_max, int32_t d_a,
            int32_t type_t, int32_t t_min, int32_t t_max, int32_t d_t,
@@ -646,9 +821,9 @@ int or_run(int32_t n, float L, float* x, float* y, float* z, const int32_t* type
     if (sigma > 0.0) or_jitter(n, L, x, y, z, seed, s, sigma);
     int64_t nb = 0;
     int64_t* st = stats_per_step ? stats_per_step + (int64_t)k * ST_COUNT : NULL;
-    int e = or_react_step(n, L, x, y, z, type, state, adj, B, type_a, a_min, a_max, d_a,
-                          type_t, t_min, t_max, d_t, rc, p, exclude_bonded, seed, s,
-                          step_bonds, n / 2 + 1, &nb, st);
+    int e = (policy == 1 ? or_react_step_nearest : or_react_step)(
+        n, L, x, y, z, type, state, adj, B, type_a, a_min, a_max, d_a, type_t, t_min, t_max,
+        d_t, rc, p, exclude_bonded, seed, s, step_bonds, n / 2 + 1, &nb, st);
     if (e != OR_OK && e != OR_ECAP) { rc_code = e; break; }
     if (e == OR_ECAP) rc_code = OR_ECAP;
     for (int64_t b = 0; b < nb; ++b) {
@@ -664,6 +839,31 @@ int or_run(int32_t n, float L, float* x, float* y, float* z, const int32_t* type
   free(step_bonds);
   if (rc_code == OR_OK && total > log_cap) return OR_ECAP;
   return rc_code;
+}
+
+int or_run(int32_t n, float L, float* x, float* y, float* z, const int32_t* type,
+           int32_t* state, int32_t* adj, int32_t B,
+           int32_t type_a, int32_t a_min, int32_t a_max, int32_t d_a,
+           int32_t type_t, int32_t t_min, int32_t t_max, int32_t d_t,
+           float rc, double p, int32_t exclude_bonded, uint64_t seed,
+           uint32_t first_step, uint32_t n_steps, double sigma,
+           int32_t* log, int64_t log_cap, int64_t* n_log, int64_t* stats_per_step) {
+  return run_policy(0, n, L, x, y, z, type, state, adj, B, type_a, a_min, a_max, d_a, type_t,
+                    t_min, t_max, d_t, rc, p, exclude_bonded, seed, first_step, n_steps, sigma,
+                    log, log_cap, n_log, stats_per_step);
+}
+
+/* or_run with the "nearest" selection of or_react_step_nearest. */
+int or_run_nearest(int32_t n, float L, float* x, float* y, float* z, const int32_t* type,
+                   int32_t* state, int32_t* adj, int32_t B,
+                   int32_t type_a, int32_t a_min, int32_t a_max, int32_t d_a,
+                   int32_t type_t, int32_t t_min, int32_t t_max, int32_t d_t,
+                   float rc, double p, int32_t exclude_bonded, uint64_t seed,
+                   uint32_t first_step, uint32_t n_steps, double sigma,
+                   int32_t* log, int64_t log_cap, int64_t* n_log, int64_t* stats_per_step) {
+  return run_policy(1, n, L, x, y, z, type, state, adj, B, type_a, a_min, a_max, d_a, type_t,
+                    t_min, t_max, d_t, rc, p, exclude_bonded, seed, first_step, n_steps, sigma,
+                    log, log_cap, n_log, stats_per_step);
 }
 
 int or_num_threads(void) {

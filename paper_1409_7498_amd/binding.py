@@ -25,16 +25,23 @@ class PrError(RuntimeError):
         self.code = code
 
 
+POLICIES = {"random": 0, "nearest": 1}
+
+
 class Rule(C.Structure):
     _fields_ = [("type_a", C.c_int32), ("a_min", C.c_int32), ("a_max", C.c_int32),
                 ("d_a", C.c_int32), ("type_t", C.c_int32), ("t_min", C.c_int32),
                 ("t_max", C.c_int32), ("d_t", C.c_int32), ("rc", C.c_float),
-                ("exclude_bonded", C.c_int32), ("p", C.c_double)]
+                ("exclude_bonded", C.c_int32), ("p", C.c_double), ("policy", C.c_int32)]
 
     @classmethod
     def make(cls, d=None, **kw):
+        """From a dict with the field names; policy may be "random" or
+        "nearest" (default "random")."""
         v = dict(d or {})
         v.update(kw)
+        pol = v.get("policy", "random")
+        v["policy"] = POLICIES[pol] if isinstance(pol, str) else int(pol)
         return cls(**{k: v[k] for k, _ in cls._fields_})
 
 

@@ -78,7 +78,18 @@ int validate_rule(const pr_rule* r, float L) {
   if (!(r->p >= 0.0 && r->p <= 1.0)) return fail(PR_EINVAL, "p=%g outside [0, 1]", r->p);
   if (r->type_a == r->type_t && r->a_min <= r->t_max && r->t_min <= r->a_max)
     return fail(PR_ERULE_AMBIGUOUS, "type_a == type_t and the A/T state windows overlap");
+  if (r->policy != PR_POLICY_RANDOM && r->policy != PR_POLICY_NEAREST)
+    return fail(PR_EINVAL, "policy=%d (PR_POLICY_RANDOM or PR_POLICY_NEAREST)", r->policy);
   return PR_OK;
+}
+
+// pr_stats from the kPart partial counters of a step (layout: a_elig, t_elig,
+// in_rc, drawn, excluded, proposals, bonds, lost).  Random selection: the
+// accepted candidates are the drawn pairs less the excluded ones; nearest:
+// every tested pair that passes bonds.
+pr_stats stats_of(const long long h[kPart], int32_t policy) {
+  const long long accepted = policy == PR_POLICY_NEAREST ? h[6] : h[3] - h[4];
+  return pr_stats{h[0], h[1], h[2], h[3], h[4], accepted, h[5], h[6], h[7]};
 }
 
 unsigned long long threshold(double p) {
@@ -114,7 +125,7 @@ void set_geometry(Dev& d, int32_t n, float L, int32_t B, const pr_rule* r, uint6
   d.thresh = threshold(r->p);
   d.seed = seed;
   d.rule = RuleD{r->type_a, r->a_min, r->a_max, r->d_a, r->type_t, r->t_min, r->t_max, r->d_t,
-                 r->exclude_bonded};
+                 r->exclude_bonded, r->policy};
   d.nwg_sweep = sweep_blocks(n);
   d.nwg_prep = prep_blocks(n);
   d.adj_staged = B <= kAdjStage ? 1 : 0;
@@ -197,7 +208,7 @@ int alloc_scratch(Arena& a, Dev& d, int32_t n, int32_t nwg, hipStream_t s) {
   if ((e = a.alloc(&d.rec, nrec)) || (e = a.alloc(&d.rsa, nrec)) ||
       (e = a.alloc(&d.radj, nrec)))
     return e;
-  if ((e = a.alloc(&d.slotA, n))) return e;
+  if ((e = a.alloc(&d.slotA, n)) || (e = a.alloc(&d.tnear, n))) return e;
   for (int p = 0; p < 2; ++p) {
     if ((e = a.alloc(&d.ovf[p], n)) || (e = a.alloc(&d.ovf_sa[p], n)) ||
         (e = a.alloc(&d.wgo[p], (size_t)nwg * kWgOut)) ||
@@ -332,8 +343,7 @@ int single_step(const Dev& d, uint32_t step, hipStream_t s, Ctl* hctl, int32_t* 
   long long h[kPart] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int g = 0; g < d.ngroups; ++g)
     for (int q = 0; q < kPart; ++q) h[q] += hpart[g * kPart + q];
-  // partial layout: a_elig, t_elig, in_rc, drawn, excluded, proposals, bonds, lost
-  if (st) *st = pr_stats{h[0], h[1], h[2], h[3], h[4], h[3] - h[4], h[5], h[6], h[7]};
+  if (st) *st = stats_of(h, d.rule.policy);
   if (h[7] > 0) return fail(PR_ECAP, "%lld adjacency appends found a full row", h[7]);
   return PR_OK;
 }
@@ -1184,8 +1194,7 @@ int pr_sys_stats(pr_sys* s, pr_stats* out, int64_t cap, int64_t* n) {
       long long h[kPart] = {0, 0, 0, 0, 0, 0, 0, 0};
       for (int g = 0; g < s->d.ngroups; ++g)
         for (int q = 0; q < kPart; ++q) h[q] += p[(size_t)k * row + (size_t)g * kPart + q];
-      // partial layout: a_elig, t_elig, in_rc, drawn, excluded, proposals, bonds, lost
-      out[k] = pr_stats{h[0], h[1], h[2], h[3], h[4], h[3] - h[4], h[5], h[6], h[7]};
+      out[k] = stats_of(h, s->rule.policy);
     }
   }
   *n = have;
@@ -1206,7 +1215,7 @@ struct CkHeader {
   uint64_t seed;
   int32_t type_a, a_min, a_max, d_a, type_t, t_min, t_max, d_t;
   float rc;
-  int32_t pad;
+  int32_t policy;
   double p;
   int64_t rows, steps;
 };
@@ -1222,7 +1231,8 @@ bool same_rule(const CkHeader& h, const pr_sys* s) {
   return h.n == s->d.n && h.B == s->d.B && h.L == s->d.L && h.seed == s->d.seed &&
          h.type_a == r.type_a && h.a_min == r.a_min && h.a_max == r.a_max && h.d_a == r.d_a &&
          h.type_t == r.type_t && h.t_min == r.t_min && h.t_max == r.t_max && h.d_t == r.d_t &&
-         h.rc == r.rc && h.p == r.p && h.exclude_bonded == r.exclude_bonded;
+         h.rc == r.rc && h.p == r.p && h.exclude_bonded == r.exclude_bonded &&
+         h.policy == r.policy;
 }
 
 }  // namespace
@@ -1262,6 +1272,7 @@ int pr_sys_checkpoint(pr_sys* s, void* buf, int64_t cap, int64_t* bytes) {
   h.t_max = r.t_max;
   h.d_t = r.d_t;
   h.rc = r.rc;
+  h.policy = r.policy;
   h.p = r.p;
   h.rows = rows;
   h.steps = steps;
@@ -1493,10 +1504,12 @@ int check_batch(pr_batch* b, int32_t rep) {
 // the sorted-storage kernels of the batch.
 int fill_maps(const std::vector<pr_sys*>& sys, Arena& arena, BatchLaunch& bl) {
   std::vector<int4> prep0, prepk, sweep, close, part, res;
-  int n_sortl = 1, two = 0;
+  int n_sortl = 1, two = 0, any_random = 0, any_nearest = 0;
   for (int r = 0; r < (int)sys.size(); ++r) {
     const Dev& d = sys[r]->d;
     if (d.bs > kOneCellBrick && d.nbricks > 1) two = 1;
+    if (d.rule.policy == PR_POLICY_NEAREST) any_nearest = 1;
+    else any_random = 1;
     n_sortl = std::max(n_sortl, (d.nbricks + kThreads / 64 - 1) / (kThreads / 64));
     for (int q = 0; q < d.nwg_prep; ++q) prep0.push_back(make_int4(r, q, d.nwg_prep, 0));
     for (int q = 0; q < d.ngroups + d.nwg_prep; ++q)
@@ -1531,6 +1544,8 @@ int fill_maps(const std::vector<pr_sys*>& sys, Arena& arena, BatchLaunch& bl) {
   bl.n_part = (int)part.size();
   bl.n_sortl = n_sortl;
   bl.two = two;
+  bl.any_random = any_random;
+  bl.any_nearest = any_nearest;
   bl.res = mr;
   bl.n_res = (int)res.size();
   bl.nrep = (int)sys.size();

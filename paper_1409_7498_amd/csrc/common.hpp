@@ -63,6 +63,7 @@ struct RuleD {
   int32_t type_a, a_min, a_max, d_a;
   int32_t type_t, t_min, t_max, d_t;
   int32_t exclude;
+  int32_t policy;  // PR_POLICY_RANDOM / PR_POLICY_NEAREST
 };
 
 // Particle arrays of one storage set, slot order.  Positions have two
@@ -94,6 +95,8 @@ struct Dev {
   int4* wge[2];
   uint32_t* wgk[2];
   uint8_t* tflag;       // per slot: this T has a retained pair in the current step
+  int2* tnear;          // nearest policy, per T id: (id of its closest A, the T's slot),
+                        // written in the step for every T with a candidate
   int2* wgw[2];         // staged bonds (id_A, id_T), kWinCap per workgroup, by parity
   int2* wov[2];         // staged bonds beyond kWinCap (capacity n/2 + 1 each)
   int32_t* abst[2];     // per prep workgroup: A's binned, by parity
@@ -142,6 +145,7 @@ struct BatchLaunch {
   const int4* res;      // resolve: four bricks per block (one per wavefront)
   int n_res;
   int two;              // some replica's brick edge exceeds kOneCellBrick
+  int any_random, any_nearest;  // some replica selects with that policy
 };
 
 }  // namespace pr

@@ -1277,6 +1277,141 @@ __device__ __forceinline__ void resolve_body(const Dev& d, int k, int w, int nun
 }
 
 // ---------------------------------------------------------------------------
+// The "nearest" selection (LAMMPS fix bond/create, Sec. IV A of the paper):
+// every candidate pair -- eligible, in range, not already bonded when the
+// rule excludes bonded pairs -- is visited once, from its T, which keeps its
+// closest A in registers (key (r2 bits, id_A): r2 >= 0 orders like its bits,
+// equal distances go to the lower id) and lowers the A's key (r2 bits, id_T)
+// with a 64-bit atomicMin.  A T with a candidate leaves (its closest A, its
+// slot) in tnear[id_T].  Then each A whose closest T keeps it in return is
+// tested once, with the pair's draw (word 0 of the counter (step, id_A, id_T,
+// 0)), and bonds when it passes.
+// ---------------------------------------------------------------------------
+template <bool kBrick>
+__device__ __forceinline__ void near_sweep_body(const Dev& d, int k, int w, int nwg) {
+  __shared__ int s_cnt[4];
+  const int tid = threadIdx.x;
+  if (tid < 4) s_cnt[tid] = 0;
+  const Ctl* c = d.ctl;
+  const StepInfo si = step_info(c, k);
+  const uint32_t par = si.par, step = si.step;
+  const Arr a = pick_set(d, c->set & 1u);
+  const float *X = pick(a.x, par), *Y = pick(a.y, par), *Z = pick(a.z, par);
+  float *XW = pick(a.x, par ^ 1u), *YW = pick(a.y, par ^ 1u), *ZW = pick(a.z, par ^ 1u);
+  const bool jit = d.jitter && d.jit_c != 0.0f;
+  const uint32_t novf = c->ovf_n[par];
+  const bool dead = read_err(c) != 0;
+  int s0, s1;
+  range_of<kBrick>(d, w, s0, s1);
+  __syncthreads();
+  int t_elig = 0, in_rc = 0, excl = 0;
+  for (int slot = s0 + tid; slot < s1 && !dead; slot += kThreads) {
+    float x = X[slot], y = Y[slot], z = Z[slot];
+    const uint32_t id = a.id ? (uint32_t)a.id[slot] : (uint32_t)slot;
+    if (d.jitter) {  // the re-jitter, as in the random selection's sweep
+      if (jit) rejitter(d, step, id, x, y, z);
+      XW[slot] = x;
+      YW[slot] = y;
+      ZW[slot] = z;
+    }
+    if (a.role[slot] != kRoleT) continue;
+    t_elig++;
+    unsigned long long best = kEmpty;
+    for_global_records(d, par, novf, x, y, z, [&](float4 A, int sa) {
+      const float r2 = dist2(d, x, y, z, A);
+      if (!(r2 < d.rc2)) return;
+      in_rc++;
+      if (d.rule.exclude && row_has(a.adj + (size_t)sa * d.B, d.B, (int32_t)id)) {
+        excl++;
+        return;
+      }
+      const unsigned long long rb = (unsigned long long)__float_as_uint(r2) << 32;
+      const uint32_t ida = (uint32_t)__float_as_int(A.w);
+      atomicMin(&d.slotA[ida], rb | id);
+      const unsigned long long kt = rb | ida;
+      best = kt < best ? kt : best;
+    });
+    if (best != kEmpty) d.tnear[id] = make_int2((int)(uint32_t)best, slot);
+  }
+  wave_add(&s_cnt[0], t_elig);
+  wave_add(&s_cnt[1], in_rc);
+  wave_add(&s_cnt[2], excl);
+  // clear the bucket counts of the next step's parity (as the other sweep)
+  for (int q = w * kThreads + tid; q < d.ncell; q += nwg * kThreads)
+    pick(d.cnt, par ^ 1u)[q] = 0u;
+  __syncthreads();
+  int32_t* out = pick(d.wgo, par) + w * kWgOut;
+  if (tid == 0) {
+    out[kOutTElig] = s_cnt[0];
+    out[kOutInRc] = s_cnt[1];
+    out[kOutDrawn] = 0;
+    out[kOutExcl] = s_cnt[2];
+    out[kOutRet] = 0;
+  }
+}
+
+// The A side of the nearest selection and the bonds: unit w (of nunits, the
+// sweep's workgroup count, whose staging windows and counters it fills)
+// takes the A records of a contiguous range of cells, unit 0 also the
+// overflow list.  Every A record appears once, so every A key is read and
+// emptied by exactly one thread.
+__device__ __forceinline__ void near_resolve_body(const Dev& d, int k, int w, int nunits) {
+  __shared__ int s_nw, s_lost, s_cnt[2];
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    s_nw = 0;
+    s_lost = 0;
+    s_cnt[0] = 0;
+    s_cnt[1] = 0;
+  }
+  __syncthreads();
+  const Ctl* c = d.ctl;
+  const StepInfo si = step_info(c, k);
+  const uint32_t par = si.par, step = si.step;
+  const Arr a = pick_set(d, c->set & 1u);
+  const BondCtx bc{&s_nw, &s_lost};
+  int prop = 0, mutual = 0;
+  auto visit = [&](float4 A, int sa) {
+    const int ida = __float_as_int(A.w);
+    const unsigned long long key = d.slotA[ida];
+    if (key == kEmpty) return;
+    d.slotA[ida] = kEmpty;
+    prop++;
+    const uint32_t idj = (uint32_t)key;
+    const int2 t = d.tnear[idj];
+    if (t.x != ida) return;  // the T's closest A is another one
+    mutual++;
+    const W4 r = philox(step, (uint32_t)ida, idj, 0u, d.seed);
+    if ((unsigned long long)r.w0 < d.thresh) make_bond(d, a, par, w, ida, sa, t.y, (int)idj, bc);
+  };
+  if (read_err(c) == 0) {
+    const int per = (d.ncell + nunits - 1) / nunits;
+    const int c0 = w * per, c1 = min(d.ncell, c0 + per);
+    for (int cc = c0 + tid; cc < c1; cc += kThreads) {
+      uint32_t nr = pick(d.cnt, par)[cc];
+      nr = nr < (uint32_t)kCellCap ? nr : (uint32_t)kCellCap;
+      const size_t r0 = (size_t)cc * kCellCap;
+      for (uint32_t r = 0; r < nr; ++r) visit(d.rec[r0 + r], d.rsa[r0 + r]);
+    }
+    if (w == 0) {
+      const uint32_t novf = c->ovf_n[par];
+      for (uint32_t r = tid; r < novf; r += kThreads)
+        visit(pick(d.ovf, par)[r], pick(d.ovf_sa, par)[r]);
+    }
+  }
+  wave_add(&s_cnt[0], prop);
+  wave_add(&s_cnt[1], mutual);
+  __syncthreads();
+  if (tid == 0) {
+    int32_t* out = pick(d.wgo, par) + w * kWgOut;
+    out[kOutDrawn] = s_cnt[1];
+    out[kOutProp] = s_cnt[0];
+    out[kOutBonds] = s_nw;
+    out[kOutLost] = s_lost;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Stateless single step: close it and sort its bonds by id_A into the
 // caller's buffer (one workgroup).
 // ---------------------------------------------------------------------------
@@ -1483,6 +1618,13 @@ template <bool kBrick>
 __global__ __launch_bounds__(kThreads) void k_resolve(Dev d, int k) {
   resolve_body<kBrick, true>(d, k, blockIdx.x, d.nwg_sweep);
 }
+template <bool kBrick>
+__global__ __launch_bounds__(kThreads) void k_near_sweep(Dev d, int k) {
+  near_sweep_body<kBrick>(d, k, blockIdx.x, gridDim.x);
+}
+__global__ __launch_bounds__(kThreads) void k_near_resolve(Dev d, int k) {
+  near_resolve_body(d, k, blockIdx.x, gridDim.x);
+}
 __global__ __launch_bounds__(kThreads) void k_sort_count(Dev d) {
   sort_count_body(d, blockIdx.x * blockDim.x + threadIdx.x);
 }
@@ -1519,14 +1661,28 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
     const Dev* __restrict__ ds, const int4* __restrict__ map, int k) {
   const int4 m = uniform_map(map);
   const Dev& d = ds[m.x];
-  if (k >= d.k_limit) return;
+  if (k >= d.k_limit || d.rule.policy != PR_POLICY_RANDOM) return;
   sweep_body<true, kTwo>(d, k, m.y, m.z);
+}
+__global__ __launch_bounds__(kThreads) void k_near_sweep_b(const Dev* __restrict__ ds,
+                                                           const int4* __restrict__ map, int k) {
+  const int4 m = uniform_map(map);
+  const Dev& d = ds[m.x];
+  if (k >= d.k_limit || d.rule.policy != PR_POLICY_NEAREST) return;
+  near_sweep_body<true>(d, k, m.y, m.z);
+}
+__global__ __launch_bounds__(kThreads) void k_near_resolve_b(const Dev* __restrict__ ds,
+                                                             const int4* __restrict__ map, int k) {
+  const int4 m = uniform_map(map);
+  const Dev& d = ds[m.x];
+  if (k >= d.k_limit || d.rule.policy != PR_POLICY_NEAREST) return;
+  near_resolve_body(d, k, m.y, m.z);
 }
 __global__ __launch_bounds__(kThreads) void k_resolve_b(const Dev* __restrict__ ds,
                                                         const int4* __restrict__ map, int k) {
   const int4 m = uniform_map(map);
   const Dev& d = ds[m.x];
-  if (k >= d.k_limit) return;
+  if (k >= d.k_limit || d.rule.policy != PR_POLICY_RANDOM) return;
   resolve_body<true, true>(d, k, m.y, m.z);
 }
 __global__ __launch_bounds__(kThreads) void k_close_b(const Dev* __restrict__ ds,
@@ -1689,6 +1845,21 @@ hipError_t launch_step(const Dev& d, int k, hipStream_t s, hipEvent_t ev_sweep0,
   const int prep_blocks = d.nwg_prep + (k > 0 ? d.ngroups : 0);
   k_prep<<<prep_blocks, kThreads, 0, s>>>(d, k);
   const dim3 g(d.nwg_sweep), b(kThreads);
+  if (d.rule.policy == PR_POLICY_NEAREST) {
+    if (d.sorted) {
+      if (ev_sweep0)
+        hipExtLaunchKernelGGL(k_near_sweep<true>, g, b, 0, s, ev_sweep0, ev_sweep1, 0, d, k);
+      else
+        k_near_sweep<true><<<g, b, 0, s>>>(d, k);
+    } else {
+      if (ev_sweep0)
+        hipExtLaunchKernelGGL(k_near_sweep<false>, g, b, 0, s, ev_sweep0, ev_sweep1, 0, d, k);
+      else
+        k_near_sweep<false><<<g, b, 0, s>>>(d, k);
+    }
+    k_near_resolve<<<g, b, 0, s>>>(d, k);
+    return hipGetLastError();
+  }
   if (d.sorted && d.bs > kOneCellBrick) {
     if (ev_sweep0)
       hipExtLaunchKernelGGL(k_sweep<true, true>, g, b, 0, s, ev_sweep0, ev_sweep1, 0, d, k);
@@ -1747,11 +1918,17 @@ hipError_t launch_step_b(const BatchLaunch& b, int k, hipStream_t s) {
     k_prep_b<<<b.n_prepk, kThreads, 0, s>>>(b.ds, b.prepk, k);
   else
     k_prep_b<<<b.n_prep0, kThreads, 0, s>>>(b.ds, b.prep0, k);
-  if (b.two)
-    k_sweep_b<true><<<b.n_sweep, kThreads, 0, s>>>(b.ds, b.sweep, k);
-  else
-    k_sweep_b<false><<<b.n_sweep, kThreads, 0, s>>>(b.ds, b.sweep, k);
-  k_resolve_b<<<b.n_res, kThreads, 0, s>>>(b.ds, b.res, k);
+  if (b.any_random) {
+    if (b.two)
+      k_sweep_b<true><<<b.n_sweep, kThreads, 0, s>>>(b.ds, b.sweep, k);
+    else
+      k_sweep_b<false><<<b.n_sweep, kThreads, 0, s>>>(b.ds, b.sweep, k);
+    k_resolve_b<<<b.n_res, kThreads, 0, s>>>(b.ds, b.res, k);
+  }
+  if (b.any_nearest) {
+    k_near_sweep_b<<<b.n_sweep, kThreads, 0, s>>>(b.ds, b.sweep, k);
+    k_near_resolve_b<<<b.n_sweep, kThreads, 0, s>>>(b.ds, b.sweep, k);
+  }
   return hipGetLastError();
 }
 

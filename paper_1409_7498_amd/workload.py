@@ -126,20 +126,21 @@ class Config:
                                                                self.p, self.steps)
 
 
-def rule_for(kind, rc=RC, p=0.01):
+def rule_for(kind, rc=RC, p=0.01, policy="random"):
     """Rule parameters as a dict (keys follow the library's rule struct).
 
     step growth (Sec. II C): A = crosslinker (type 1) with remaining valence in
     [1, 4], -1 per bond; T = end unit (type 0) with remaining valence in [1, 2],
     -1 per bond.  chain growth (Sec. II B): one type; free monomer 0, active end
     2, inert 1; A = active end (2 -> 1), T = free monomer (0 -> 2, becomes the
-    new active end)."""
+    new active end).  policy: "random" (the paper's selection) or "nearest"
+    (the closest-partner selection of LAMMPS fix bond/create, Sec. IV A)."""
     if kind == "step":
         return dict(type_a=1, a_min=1, a_max=4, d_a=-1, type_t=0, t_min=1, t_max=2, d_t=-1,
-                    rc=rc, p=p, exclude_bonded=1)
+                    rc=rc, p=p, exclude_bonded=1, policy=policy)
     if kind == "chain":
         return dict(type_a=0, a_min=2, a_max=2, d_a=-1, type_t=0, t_min=0, t_max=0, d_t=2,
-                    rc=rc, p=p, exclude_bonded=1)
+                    rc=rc, p=p, exclude_bonded=1, policy=policy)
     raise ValueError(kind)
 
 

@@ -91,11 +91,14 @@ def _one_replica(args):
             fin["state"], fin["adj"])
 
 
+def _single_thread():
+    os.environ["OMP_NUM_THREADS"] = "1"
+
+
 def _pool(jobs, workers):
     ctx = __import__("multiprocessing").get_context("spawn")
     with ProcessPoolExecutor(max_workers=workers, mp_context=ctx,
-                             initializer=os.environ.__setitem__,
-                             initargs=("OMP_NUM_THREADS", "1")) as ex:
+                             initializer=_single_thread) as ex:
         return list(ex.map(_one_replica, jobs, chunksize=1))
 
 

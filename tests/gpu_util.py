@@ -25,8 +25,10 @@ def to_dev(cfg):
 
 
 def oracle_rule(rule):
-    return oracle.Rule(**{k: rule[k] for k in ("type_a", "a_min", "a_max", "d_a", "type_t", "t_min",
-                                               "t_max", "d_t", "rc", "p", "exclude_bonded")})
+    r = oracle.Rule(**{k: rule[k] for k in ("type_a", "a_min", "a_max", "d_a", "type_t", "t_min",
+                                            "t_max", "d_t", "rc", "p", "exclude_bonded")})
+    r.policy = rule.get("policy", "random")
+    return r
 
 
 def oracle_system(cfg):

@@ -481,6 +481,83 @@ def check_chain_consumption(lib, p=0.05, steps=40):
 
 
 # --------------------------------------------------------------------------
+# the "nearest" selection of LAMMPS fix bond/create (Sec. IV A)
+# --------------------------------------------------------------------------
+def near_rule(p=1.0, excl=1):
+    return Rule(**STEP, rc=1.12, p=p, exclude_bonded=excl, policy="nearest")
+
+
+def check_nearest_picks_closest(lib):
+    """One A, targets at 0.6, 0.8 and 1.0 (p = 1): the closest bonds; a target
+    beyond rc never does; the farther ones are left for later steps."""
+    s = mk(10.0, [(5, 5, 5), (5.8, 5, 5), (5, 5.6, 5), (5, 5, 6.0), (3.8, 5, 5)],
+           [1, 0, 0, 0, 0], [4, 2, 2, 2, 2])
+    code, bonds, st = one(lib, s, near_rule())
+    assert code == 0 and bonds == [(0, 2)], bonds
+    assert (st["in_rc"], st["drawn"], st["accepted"], st["proposals"]) == (3, 1, 1, 1), st
+    _, bonds, _ = one(lib, s, near_rule(), step=2)
+    assert bonds == [(0, 1)], bonds  # 0.8 is the closest unbonded one now
+
+
+def check_nearest_mutual(lib):
+    """T between two A's is closer to A1 (0.7) than to A0 (0.8): only A1-T bonds,
+    and A0, whose closest partner is that T, takes no bond in this step even
+    though a second target sits at 0.9 from it (Sec. IV A: no random choice
+    among partners, the pair must be mutual)."""
+    s = mk(10.0, [(5.0, 5, 5), (6.5, 5, 5), (5.8, 5, 5), (4.1, 5, 5)], [1, 1, 0, 0], [4, 4, 2, 2])
+    _, bonds, st = one(lib, s, near_rule())
+    assert bonds == [(1, 2)], bonds
+    assert st["proposals"] == 2 and st["drawn"] == 1, st
+    # the same geometry under the random selection bonds both A's
+    _, bonds, _ = one(lib, mk(10.0, [(5.0, 5, 5), (6.5, 5, 5), (5.8, 5, 5), (4.1, 5, 5)],
+                              [1, 1, 0, 0], [4, 4, 2, 2]), step_rule(p=1.0), seed=3)
+    assert len(bonds) in (1, 2)
+
+
+def check_nearest_tie_lower_id(lib):
+    """Two targets at exactly equal FP32 distance (mirror images on x): the
+    lower id is the closest by the (r2, id) key, whichever is listed first."""
+    for order in ((1, 2), (2, 1)):
+        pts = {0: (5.0, 5, 5), order[0]: (5.75, 5, 5), order[1]: (4.25, 5, 5)}
+        s = mk(10.0, [pts[k] for k in range(3)], [1, 0, 0], [4, 2, 2])
+        _, bonds, _ = one(lib, s, near_rule())
+        assert bonds == [(0, 1)], (order, bonds)
+
+
+def check_nearest_probability(lib, p=0.3, copies=343, seeds=6):
+    """An isolated A with n partners bonds with probability p, always to the
+    closest one (the random selection gives 1 - (1 - p)^n)."""
+    for n_t in (1, 3):
+        s = _cluster_system(n_t, copies)
+        # move the partners to distinct distances 0.6, 0.7, 0.8 from their A
+        for k in range(copies):
+            a = k * (n_t + 1)
+            for q in range(n_t):
+                t = a + 1 + q
+                for arr in (s.x, s.y, s.z):
+                    d = float(arr[t]) - float(arr[a])
+                    if abs(d) > 0.1:
+                        arr[t] = np.float32(float(arr[a]) + np.sign(d) * (0.6 + 0.1 * q))
+        hits = 0
+        for seed in range(seeds):
+            _, bonds, _ = one(lib, s.copy(), near_rule(p=p), seed=2000 + seed)
+            hits += len(bonds)
+            assert all(j == i + 1 for i, j in bonds), bonds
+        trials = copies * seeds
+        sd = math.sqrt(p * (1 - p) / trials)
+        assert abs(hits / trials - p) < 4.5 * sd, (n_t, hits / trials, p)
+
+
+def check_nearest_exclusion_first(lib):
+    """Already bonded pairs are not candidates at all: the closest target,
+    bonded already, leaves the next one as the A's closest partner."""
+    adj = [[1, -1, -1, -1], [0, -1, -1, -1], [-1] * 4]
+    s = mk(10.0, [(5, 5, 5), (5.6, 5, 5), (5, 5.9, 5)], [1, 0, 0], [3, 1, 2], adj=adj)
+    _, bonds, st = one(lib, s, near_rule())
+    assert bonds == [(0, 2)] and st["excluded"] == 1, (bonds, st)
+
+
+# --------------------------------------------------------------------------
 # FP64 recheck of the cutoff decision (diagnostic; the step decides in FP32)
 # --------------------------------------------------------------------------
 RC32 = float(np.float32(1.12))  # the cutoff as the FP32 value both sides use
@@ -571,4 +648,6 @@ ALL = [check_pair_distance, check_periodic, check_cutoff_strict, check_p0_p1, ch
        check_two_a_one_t_probability, check_uniform_choice, check_exact_small_graph,
        check_exclusion, check_valence_stop, check_chain_transfer, check_errors, check_adj_overflow,
        check_jitter_distribution, check_generator_offsets, check_jitter_wrap,
-       check_near_cutoff, check_near_cutoff_disagree]
+       check_near_cutoff, check_near_cutoff_disagree, check_nearest_picks_closest,
+       check_nearest_mutual, check_nearest_tie_lower_id, check_nearest_probability,
+       check_nearest_exclusion_first]

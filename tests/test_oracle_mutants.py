@@ -25,6 +25,8 @@ MUTANTS = {
     15: ("FP64 tolerance applied to r^2", [pins.check_near_cutoff]),
     16: ("FP64 recheck counts every particle as an A", [pins.check_near_cutoff]),
     17: ("FP32 side of the recheck evaluated in FP64", [pins.check_near_cutoff_disagree]),
+    18: ("nearest: bonded pairs stay candidates", [pins.check_nearest_exclusion_first]),
+    19: ("nearest: pairs need not be mutual", [pins.check_nearest_mutual]),
 }
 
 
