@@ -234,6 +234,26 @@ int pr_sys_prepare(pr_sys* s, uint32_t n_steps, double sigma);
 int pr_sys_jitter(pr_sys* s, uint32_t first_step, uint32_t n_steps, double sigma,
                   float* kernel_ms);
 
+/* Kinetics counters of the current configuration: the quantities the
+ * paper's rate equations are built from (Sec. II B-C), counted on the device
+ * so that they can be followed at any system size.
+ *   pop[s]   particles of type type_a in state s, s = 0 .. nstate-1 (the
+ *            populations [X_s] of Eq. (12); [M], [P*] of Eqs. (5)-(10) when
+ *            A and T share a type); other states are not counted;
+ *   pairs[s] summed over the A-eligible particles in state s: the T-eligible
+ *            particles within the cutoff (the step's own FP32 test) that are
+ *            not bonded to them when the rule excludes bonded pairs, so that
+ *            pairs[s] / pop[s] is <N_{X^s E^0}> of Eq. (13), or <N_{P* M}>
+ *            of the chain-growth rate k_c;
+ *   hist[b]  those pairs by distance: bin b holds e2[b] <= r2 < e2[b + 1],
+ *            e2[b] = fl32((rc b / nbins)^2) with the product in double, the
+ *            last bin ending at the cutoff (a pair distribution function up
+ *            to rc, whose integral is <N>).
+ * Host arrays of nstate (1..64) and nbins (0..256; hist may be NULL when 0)
+ * elements.  Nothing of the system changes.  Synchronises. */
+int pr_sys_kinetics(pr_sys* s, int32_t nstate, int64_t* pop, int64_t* pairs, int32_t nbins,
+                    int64_t* hist);
+
 /* Copies the current configuration out in particle-id order (host or device
  * pointers per on_device; any pointer may be NULL to skip).  Synchronises;
  * returns a pending device error, if any. */
@@ -338,6 +358,9 @@ int pr_batch_bonds(pr_batch* b, int32_t rep, int32_t* out, int64_t cap, int64_t*
 int pr_batch_read(pr_batch* b, int32_t rep, float* x, float* y, float* z, int32_t* state,
                   int32_t* adj, int32_t on_device);
 int pr_batch_stats(pr_batch* b, int32_t rep, pr_stats* out, int64_t cap, int64_t* n);
+/* pr_sys_kinetics of one replica. */
+int pr_batch_kinetics(pr_batch* b, int32_t rep, int32_t nstate, int64_t* pop, int64_t* pairs,
+                      int32_t nbins, int64_t* hist);
 
 
 /* Device bytes a resident system of this description allocates for a run of

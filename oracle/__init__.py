@@ -65,6 +65,12 @@ def _declare(lib):
     lib.or_jitter_scale.restype = C.c_float
     lib.or_jitter.argtypes = [i32, f32, P(f32), P(f32), P(f32), u64, u32, f64]
     lib.or_jitter.restype = None
+    lib.or_kinetics.argtypes = [i32, f32, P(f32), P(f32), P(f32), P(i32), P(i32), P(i32), i32,
+                                i32, i32, i32, i32, i32, i32, f32, i32, i32, P(i64), P(i64), i32,
+                                P(i64)]
+    lib.or_kinetics.restype = C.c_int
+    lib.or_kin_edge2.argtypes = [f32, i32, i32]
+    lib.or_kin_edge2.restype = C.c_float
     lib.or_num_threads.argtypes = []
     lib.or_num_threads.restype = C.c_int
     return lib
@@ -230,10 +236,32 @@ def near_cutoff(sysm, rule, tol=1e-6, lib=None):
     return near.value, dis.value
 
 
+def kinetics(sysm, rule, nstate=8, nbins=16, lib=None):
+    """Kinetics counters of the configuration: (pop[nstate], pairs[nstate],
+    hist[nbins]) as numpy int64 arrays (see or_kinetics)."""
+    lib = lib or load()
+    pop = np.zeros(nstate, np.int64)
+    pairs = np.zeros(nstate, np.int64)
+    hist = np.zeros(max(nbins, 1), np.int64)
+    code = lib.or_kinetics(sysm.n, C.c_float(sysm.L), _p(sysm.x, C.c_float), _p(sysm.y, C.c_float),
+                           _p(sysm.z, C.c_float), _p(sysm.type, C.c_int32),
+                           _p(sysm.state, C.c_int32), _p(sysm.adj, C.c_int32), sysm.B,
+                           rule.type_a, rule.a_min, rule.a_max, rule.type_t, rule.t_min,
+                           rule.t_max, C.c_float(rule.rc), rule.exclude_bonded, nstate,
+                           _p(pop, C.c_int64), _p(pairs, C.c_int64), nbins, _p(hist, C.c_int64))
+    assert code == 0, code
+    return pop, pairs, hist[:nbins]
+
+
+def kin_edge2(rc, b, nbins, lib=None):
+    return float((lib or load()).or_kin_edge2(C.c_float(rc), b, nbins))
+
+
 def num_threads(lib=None):
     return int((lib or load()).or_num_threads())
 
 
 __all__ = ["Rule", "System", "react_step", "run", "jitter", "philox", "threshold", "near_cutoff",
+           "kinetics", "kin_edge2",
            "sample_bonds",
            "ih12_offsets", "ih4_offsets", "jitter_scale", "ST_NAMES", "load", "num_threads"]

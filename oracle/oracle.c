@@ -731,6 +731,94 @@ int or_near_cutoff(int32_t n, float L, const float* x, const float* y, const flo
 }
 
 /* ----------------------------------------------------------------------- */
+/* Kinetics counters of a configuration (Sec. II B-C): the quantities the    */
+/* rate equations are built from.                                           */
+/*  pop[s]   particles of type type_a in state s, s = 0 .. nstate-1 (the    */
+/*           populations [X_s] of Eq. (12), [M], [P*] of Eqs. (5)-(10));    */
+/*  pairs[s] over the A-eligible particles in state s, the number of        */
+/*           T-eligible particles within the cutoff (FP32 r2 < fl32(rc^2),  */
+/*           the step's own test) that are not bonded to them when the rule */
+/*           excludes bonded pairs: pairs[s] / pop[s] is <N_{X^s E^0}>      */
+/*           (Eq. (13)) or <N_{P* M}> (k_c of Eq. (6));                     */
+/*  hist[b]  the same pairs by distance, b = 0 .. nbins-1: the pair is in   */
+/*           bin b iff e2[b] <= r2 < e2[b + 1] with e2[b] = fl32((rc b /    */
+/*           nbins)^2) evaluated in double (e2[nbins] is the cutoff rc2).   */
+/*           hist[b] / pop / (rho_T shell volume) is g(r), whose integral   */
+/*           up to rc gives <N>.                                            */
+/* Brute force over all (A, T) pairs in tiles of OR_TILE A's.               */
+/* ----------------------------------------------------------------------- */
+float or_kin_edge2(float rc, int32_t b, int32_t nbins) {
+  const double r = (double)rc * (double)b / (double)nbins;
+  return (float)(r * r);
+}
+
+int or_kinetics(int32_t n, float L, const float* x, const float* y, const float* z,
+                const int32_t* type, const int32_t* state, const int32_t* adj, int32_t B,
+                int32_t type_a, int32_t a_min, int32_t a_max,
+                int32_t type_t, int32_t t_min, int32_t t_max, float rc, int32_t exclude_bonded,
+                int32_t nstate, int64_t* pop, int64_t* pairs, int32_t nbins, int64_t* hist) {
+  or_rule R = {type_a, a_min, a_max, 0, type_t, t_min, t_max, 0, rc, 0.0, exclude_bonded};
+  if (nstate < 1 || nbins < 0) return OR_EINVAL;
+  for (int32_t q = 0; q < nstate; ++q) pop[q] = pairs[q] = 0;
+  for (int32_t b = 0; b < nbins; ++b) hist[b] = 0;
+  const size_t nn = (size_t)(n > 0 ? n : 1);
+  int64_t* alist = (int64_t*)malloc(sizeof(int64_t) * nn);
+  uint8_t* is_t = (uint8_t*)malloc(nn);
+  float* e2 = (float*)malloc(sizeof(float) * (size_t)(nbins + 1));
+  if (!alist || !is_t || !e2) {
+    free(alist); free(is_t); free(e2);
+    return OR_ENOMEM;
+  }
+  for (int32_t b = 0; b <= nbins; ++b) e2[b] = or_kin_edge2(rc, b, nbins);
+  int64_t na = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (type[i] == type_a && state[i] >= 0 && state[i] < nstate) pop[state[i]]++;
+    if (is_active(&R, type[i], state[i])) alist[na++] = i;
+    is_t[i] = (uint8_t)is_target(&R, type[i], state[i]);
+  }
+  const float halfL = 0.5f * L, rc2 = rc * rc;
+  const int64_t ntile = (na + OR_TILE - 1) / OR_TILE;
+#pragma omp parallel
+  {
+    int64_t* lp = (int64_t*)calloc((size_t)nstate, sizeof(int64_t));
+    int64_t* lh = (int64_t*)calloc((size_t)(nbins > 0 ? nbins : 1), sizeof(int64_t));
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t t = 0; t < ntile; ++t) {
+      const int64_t k0 = t * OR_TILE;
+      const int m = (int)(na - k0 < OR_TILE ? na - k0 : OR_TILE);
+      for (int64_t j = 0; j < n && lp && lh; ++j) {
+        if (!is_t[j]) continue;
+        for (int k = 0; k < m; ++k) {
+          const int64_t i = alist[k0 + k];
+          if (i == j) continue;
+          const float r2 = dist2(x, y, z, i, j, L, halfL);
+          if (!in_cutoff(r2, rc2)) continue;
+          if (exclude_bonded && bonded(adj, B, i, j)) continue;
+#if OR_MUTANT == 20 /* mutant: partners counted for the T's state */
+          const int32_t s = state[j];
+#else
+          const int32_t s = state[i];
+#endif
+          if (s >= 0 && s < nstate) lp[s]++;
+          int32_t b = 0;
+          while (b + 1 < nbins && !(r2 < e2[b + 1])) b++;
+          if (nbins > 0) lh[b]++;
+        }
+      }
+    }
+#pragma omp critical
+    {
+      for (int32_t q = 0; q < nstate && lp; ++q) pairs[q] += lp[q];
+      for (int32_t b = 0; b < nbins && lh; ++b) hist[b] += lh[b];
+    }
+    free(lp);
+    free(lh);
+  }
+  free(alist); free(is_t); free(e2);
+  return OR_OK;
+}
+
+/* ----------------------------------------------------------------------- */
 /* Integer Irwin-Hall(12) offsets of the synthetic initial configuration:    */
 /* per dimension S = (sum of 12 uniform bytes) - 1530 (mean 0, variance     */
 /* 65535); the bytes come from three Philox blocks with counter              */

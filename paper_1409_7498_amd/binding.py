@@ -96,6 +96,8 @@ def _load():
         "pr_sys_prepare": ([vp, u32, f64], C.c_int),
         "pr_sys_jitter": ([vp, u32, u32, f64, P(f32)], C.c_int),
         "pr_stream_copy": ([vp, vp, i64, i32, vp, P(f32)], C.c_int),
+        "pr_sys_kinetics": ([vp, i32, vp, vp, i32, vp], C.c_int),
+        "pr_batch_kinetics": ([vp, i32, i32, vp, vp, i32, vp], C.c_int),
         "pr_sys_read": ([vp, vp, vp, vp, vp, vp, i32], C.c_int),
         "pr_sys_checkpoint": ([vp, vp, i64, P(i64)], C.c_int),
         "pr_sys_restore": ([vp, vp, i64], C.c_int),
@@ -152,7 +154,8 @@ def exported_symbols():
                         "pr_server_release", "pr_server_info_get", "pr_sys_checkpoint",
                         "pr_sys_restore", "pr_p_from_rate", "pr_draws", "pr_server_poll",
                         "pr_server_cancel", "pr_autotune_cached", "pr_sys_prepare",
-                        "pr_sys_jitter", "pr_stream_copy")]
+                        "pr_sys_jitter", "pr_stream_copy", "pr_sys_kinetics",
+                        "pr_batch_kinetics")]
 
 
 def _check(code):
@@ -264,6 +267,11 @@ class System:
                                  C.byref(ms) if timed else None))
         return ms.value if timed else None
 
+    def kinetics(self, nstate=8, nbins=16):
+        """Kinetics counters of the current configuration: (pop, pairs, hist)
+        int64 arrays (see pr_sys_kinetics)."""
+        return _kinetics(lambda *a: lib.pr_sys_kinetics(self._h, *a), nstate, nbins)
+
     def set_sort_period(self, k):
         _check(lib.pr_sys_set_sort_period(self._h, int(k)))
 
@@ -303,6 +311,14 @@ class System:
         arr = (Stats * max(n.value, 1))()
         _check(lib.pr_sys_stats(self._h, arr, n.value, C.byref(n)))
         return [arr[k].as_dict() for k in range(n.value)]
+
+
+def _kinetics(call, nstate, nbins):
+    pop, pairs = np.zeros(nstate, np.int64), np.zeros(nstate, np.int64)
+    hist = np.zeros(max(nbins, 1), np.int64)
+    _check(call(int(nstate), pop.ctypes.data_as(C.c_void_p), pairs.ctypes.data_as(C.c_void_p),
+                int(nbins), hist.ctypes.data_as(C.c_void_p)))
+    return pop, pairs, hist[:nbins]
 
 
 def p_from_rate(k, dt, theta):
@@ -417,6 +433,9 @@ class Batch:
         _check(lib.pr_batch_bonds(self._h, int(rep), out.ctypes.data_as(C.c_void_p), total,
                                   C.byref(n)))
         return out[:total]
+
+    def kinetics(self, rep, nstate=8, nbins=16):
+        return _kinetics(lambda *a: lib.pr_batch_kinetics(self._h, int(rep), *a), nstate, nbins)
 
     def stats(self, rep):
         n = C.c_int64(0)

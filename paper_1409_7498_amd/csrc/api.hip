@@ -42,6 +42,9 @@ hipError_t launch_gather_out(const Dev& d, float* ox, float* oy, float* oz, int3
 hipError_t launch_draws(const uint32_t* ctr, long long n, unsigned long long key, uint32_t* out,
                         hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, long long n, uint32_t v, hipStream_t s);
+hipError_t launch_kinetics(const Dev& d, int nstate, int nbins, const float* e2,
+                           unsigned long long* pop, unsigned long long* pairs,
+                           unsigned long long* hist, hipStream_t s);
 hipError_t launch_jitter_only(const Dev& d, int n_steps, hipStream_t s, hipEvent_t ev0,
                               hipEvent_t ev1);
 hipError_t launch_stream_copy(const void* src, void* dst, long long bytes, int width,
@@ -522,6 +525,9 @@ struct pr_sys {
   int32_t *rtyp = nullptr, *rst = nullptr, *radj = nullptr;
   Ctl* hctl = nullptr;
   bool own_hctl = true;  // false: the pinned word belongs to a server's pool
+  // kinetics counters (allocated on first use): pop, pairs, hist, bin edges
+  unsigned long long* kin = nullptr;
+  float* kin_e2 = nullptr;
   ~pr_sys() {
     for (Seg& g : segs)
       if (g.gexec) (void)hipGraphExecDestroy(g.gexec);
@@ -1041,6 +1047,43 @@ int pr_sys_jitter(pr_sys* s, uint32_t first_step, uint32_t n_steps, double sigma
   (void)hipEventDestroy(ev[1]);
   *kernel_ms = total;
   return e;
+}
+
+int pr_sys_kinetics(pr_sys* s, int32_t nstate, int64_t* pop, int64_t* pairs, int32_t nbins,
+                    int64_t* hist) {
+  int e = check_sys(s, true);
+  if (e) return e;
+  if (nstate < 1 || nstate > kKinMaxState || nbins < 0 || nbins > kKinMaxBins)
+    return fail(PR_EINVAL, "nstate=%d (1..%d), nbins=%d (0..%d)", nstate, kKinMaxState, nbins,
+                kKinMaxBins);
+  if (!pop || !pairs || (nbins > 0 && !hist)) return fail(PR_EINVAL, "NULL output");
+  const size_t nk = 2 * kKinMaxState + kKinMaxBins;
+  if (!s->kin && ((e = s->arena.alloc(&s->kin, nk)) ||
+                  (e = s->arena.alloc(&s->kin_e2, (size_t)kKinMaxBins + 1))))
+    return e;
+  // bin edges: e2[b] = fl32((rc b / nbins)^2), the product taken in double
+  std::vector<float> e2((size_t)nbins + 1);
+  for (int b = 0; b <= nbins; ++b) {
+    const double r = (double)s->rule.rc * (double)b / (double)nbins;
+    e2[(size_t)b] = (float)(r * r);
+  }
+  hipStream_t st = s->stream;
+  unsigned long long *kp = s->kin, *kq = s->kin + kKinMaxState, *kh = s->kin + 2 * kKinMaxState;
+  HIP_TRY(hipMemcpyAsync(s->kin_e2, e2.data(), e2.size() * sizeof(float), hipMemcpyHostToDevice,
+                         st));
+  HIP_TRY(launch_fill_u32((uint32_t*)s->kin, 2 * (long long)nk, 0u, st));
+  HIP_TRY(launch_kinetics(s->d, nstate, nbins, s->kin_e2, kp, kq, kh, st));
+  std::vector<unsigned long long> h(nk);
+  HIP_TRY(hipMemcpyAsync(h.data(), s->kin, nk * sizeof(unsigned long long),
+                         hipMemcpyDeviceToHost, st));
+  if ((e = sync_ctl(s))) return e;
+  if (s->hctl->err) return fail(s->hctl->err, "device error during the run");
+  for (int q = 0; q < nstate; ++q) {
+    pop[q] = (int64_t)h[(size_t)q];
+    pairs[q] = (int64_t)h[(size_t)(kKinMaxState + q)];
+  }
+  for (int b = 0; b < nbins; ++b) hist[b] = (int64_t)h[(size_t)(2 * kKinMaxState + b)];
+  return PR_OK;
 }
 
 int pr_stream_copy(const void* src, void* dst, int64_t bytes, int32_t width, void* stream,
@@ -1707,6 +1750,12 @@ int pr_batch_read(pr_batch* b, int32_t rep, float* x, float* y, float* z, int32_
 int pr_batch_stats(pr_batch* b, int32_t rep, pr_stats* out, int64_t cap, int64_t* n) {
   int e = check_batch(b, rep);
   return e ? e : pr_sys_stats(b->sys[rep], out, cap, n);
+}
+
+int pr_batch_kinetics(pr_batch* b, int32_t rep, int32_t nstate, int64_t* pop, int64_t* pairs,
+                      int32_t nbins, int64_t* hist) {
+  int e = check_batch(b, rep);
+  return e ? e : pr_sys_kinetics(b->sys[rep], nstate, pop, pairs, nbins, hist);
 }
 
 }  // extern "C"

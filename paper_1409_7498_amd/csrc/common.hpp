@@ -41,6 +41,8 @@ constexpr int kStageRecs = 256;
 constexpr int kTPass = 768;         // particles a sweep workgroup holds per pass (3 per thread)
 constexpr int kQueue = 512;         // in-range pairs queued per pass
 constexpr int32_t kMaxParticles = 1 << 30;  // byte offsets of 4-byte fields fit in 32 bits
+constexpr int kKinMaxState = 64;    // kinetics counters: states per call
+constexpr int kKinMaxBins = 256;    // kinetics counters: distance bins per call
 
 enum WgOut { kOutTElig = 0, kOutInRc, kOutDrawn, kOutExcl, kOutRet, kOutProp, kOutBonds, kOutLost };
 

@@ -1412,6 +1412,78 @@ __device__ __forceinline__ void near_resolve_body(const Dev& d, int k, int w, in
 }
 
 // ---------------------------------------------------------------------------
+// Kinetics counters of the current configuration (the quantities of the
+// paper's rate equations, Sec. II B-C): populations of the A type by state,
+// and, per state of the A-eligible particles, their T-eligible partners
+// within the cutoff (not bonded to them when the rule excludes bonded pairs)
+// with a histogram of those pairs by distance.  The A records come from the
+// binning kernel run on the current positions (no re-jitter); each pair is
+// found once, from its T, as in the sweep.  Counts go to LDS, then one
+// global atomic per workgroup and counter.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_kin_pop(Dev d, int nstate,
+                                                      unsigned long long* __restrict__ pop) {
+  __shared__ uint32_t s_pop[kKinMaxState];
+  for (int q = threadIdx.x; q < nstate; q += blockDim.x) s_pop[q] = 0u;
+  __syncthreads();
+  const Arr a = pick_set(d, d.ctl->set & 1u);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.n; i += gridDim.x * blockDim.x) {
+    const int32_t st = a.st[i];
+    if (a.typ[i] == d.rule.type_a && st >= 0 && st < nstate) atomicAdd(&s_pop[st], 1u);
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < nstate; q += blockDim.x)
+    if (s_pop[q]) atomicAdd(&pop[q], (unsigned long long)s_pop[q]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_kin_pairs(Dev d, int nstate, int nbins,
+                                                        const float* __restrict__ e2,
+                                                        unsigned long long* __restrict__ pairs,
+                                                        unsigned long long* __restrict__ hist) {
+  __shared__ uint32_t s_pairs[kKinMaxState], s_hist[kKinMaxBins];
+  __shared__ float s_e2[kKinMaxBins + 1];
+  for (int q = threadIdx.x; q < nstate; q += blockDim.x) s_pairs[q] = 0u;
+  for (int q = threadIdx.x; q < nbins; q += blockDim.x) s_hist[q] = 0u;
+  for (int q = threadIdx.x; q <= nbins; q += blockDim.x) s_e2[q] = e2[q];
+  __syncthreads();
+  const Ctl* c = d.ctl;
+  const uint32_t par = c->par0;
+  const Arr a = pick_set(d, c->set & 1u);
+  const float *X = pick(a.x, par), *Y = pick(a.y, par), *Z = pick(a.z, par);
+  const uint32_t novf = c->ovf_n[par];
+  for (int slot = blockIdx.x * blockDim.x + threadIdx.x; slot < d.n;
+       slot += gridDim.x * blockDim.x) {
+    if (a.role[slot] != kRoleT) continue;
+    const float x = X[slot], y = Y[slot], z = Z[slot];
+    const int32_t id = a.id ? a.id[slot] : slot;
+    for_global_records(d, par, novf, x, y, z, [&](float4 A, int sa) {
+      const float r2 = dist2(d, x, y, z, A);
+      if (!(r2 < d.rc2)) return;
+      if (d.rule.exclude && row_has(a.adj + (size_t)sa * d.B, d.B, id)) return;
+      const int32_t st = a.st[sa];
+      if (st >= 0 && st < nstate) atomicAdd(&s_pairs[st], 1u);
+      int b = 0;
+      while (b + 1 < nbins && !(r2 < s_e2[b + 1])) ++b;
+      if (nbins > 0) atomicAdd(&s_hist[b], 1u);
+    });
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < nstate; q += blockDim.x)
+    if (s_pairs[q]) atomicAdd(&pairs[q], (unsigned long long)s_pairs[q]);
+  for (int q = threadIdx.x; q < nbins; q += blockDim.x)
+    if (s_hist[q]) atomicAdd(&hist[q], (unsigned long long)s_hist[q]);
+}
+
+// Leaves the A grid of the current parity as a step expects to find it
+// (no records, no overflow).
+__global__ __launch_bounds__(kThreads) void k_kin_reset(Dev d) {
+  const uint32_t par = d.ctl->par0;
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < d.ncell; q += gridDim.x * blockDim.x)
+    pick(d.cnt, par)[q] = 0u;
+  if (blockIdx.x == 0 && threadIdx.x == 0) d.ctl->ovf_n[par] = 0u;
+}
+
+// ---------------------------------------------------------------------------
 // Stateless single step: close it and sort its bonds by id_A into the
 // caller's buffer (one workgroup).
 // ---------------------------------------------------------------------------
@@ -1978,6 +2050,21 @@ hipError_t launch_stream_copy(const void* src, void* dst, long long bytes, int w
   else
     hipExtLaunchKernelGGL(k_stream_copy<uint32_t>, g, b, 0, s, ev0, ev1, 0, (const uint32_t*)src,
                           (uint32_t*)dst, bytes / 4);
+  return hipGetLastError();
+}
+
+// Kinetics counters (counters zeroed by the caller): populations, the A
+// binning of the current positions (a copy of d without re-jitter), pairs.
+hipError_t launch_kinetics(const Dev& d, int nstate, int nbins, const float* e2,
+                           unsigned long long* pop, unsigned long long* pairs,
+                           unsigned long long* hist, hipStream_t s) {
+  const int g = std::min(blocks_for(d.n, kThreads), 2048);
+  k_kin_pop<<<g, kThreads, 0, s>>>(d, nstate, pop);
+  Dev dn = d;
+  dn.jit_c = 0.0f;
+  k_prep<<<d.nwg_prep, kThreads, 0, s>>>(dn, 0);
+  k_kin_pairs<<<g, kThreads, 0, s>>>(dn, nstate, nbins, e2, pairs, hist);
+  k_kin_reset<<<std::min(blocks_for(d.ncell, kThreads), 1024), kThreads, 0, s>>>(dn);
   return hipGetLastError();
 }
 

@@ -558,6 +558,55 @@ def check_nearest_exclusion_first(lib):
 
 
 # --------------------------------------------------------------------------
+# kinetics counters: populations and partner counts of the rate equations
+# (Sec. II B-C: [X_s], <N_{X^s E^0}>, <N_{P* M}>, g(r))
+# --------------------------------------------------------------------------
+def check_kinetics_hand(lib):
+    """One eligible crosslinker (state 3) with end units at 0.5, 0.9, 1.05
+    (in range), 1.3 (out), a bonded one at 0.7 and a spent one (state 0) at
+    0.6; a spent crosslinker (state 0) elsewhere.  4 bins of width rc/4."""
+    pts = [(5, 5, 5), (5.5, 5, 5), (5, 5.9, 5), (5, 5, 6.05), (3.7, 5, 5), (5, 4.3, 5),
+           (5, 5, 4.4), (1, 1, 1)]
+    types = [1, 0, 0, 0, 0, 0, 0, 1]
+    states = [3, 2, 2, 1, 2, 1, 0, 0]
+    adj = [[-1] * 4 for _ in pts]
+    adj[0][0] = 5
+    adj[5][0] = 0
+    s = mk(10.0, pts, types, states, adj=adj)
+    pop, pairs, hist = oracle.kinetics(s, step_rule(), nstate=5, nbins=4, lib=lib)
+    assert pop.tolist() == [1, 0, 0, 1, 0], pop
+    assert pairs.tolist() == [0, 0, 0, 3, 0], pairs
+    assert hist.tolist() == [0, 1, 0, 2], hist
+    # without the exclusion the bonded partner at 0.7 counts too (bin 2)
+    pop, pairs, hist = oracle.kinetics(s, step_rule(excl=0), nstate=5, nbins=4, lib=lib)
+    assert pairs.tolist() == [0, 0, 0, 4, 0] and hist.tolist() == [0, 1, 1, 2], (pairs, hist)
+
+
+def check_kinetics_poisson(lib, n=60000, L=30.0, frac=0.05, nbins=8):
+    """Uniform random positions: the mean partner count of an A is
+    rho_T (4/3) pi rc^3 and bin b holds rho_T (4/3) pi (r_{b+1}^3 - r_b^3)
+    per A (g(r) = 1), chi^2 over the bins."""
+    rng = np.random.default_rng(77)
+    x, y, z = (rng.uniform(0, L, n).astype(np.float32) for _ in range(3))
+    typ = (rng.random(n) < frac).astype(np.int32)
+    st = np.where(typ == 1, 4, 2).astype(np.int32)
+    s = System(L, x, y, z, typ, st, np.full((n, 4), -1, np.int32))
+    pop, pairs, hist = oracle.kinetics(s, step_rule(), nstate=5, nbins=nbins, lib=lib)
+    na, nt = int((typ == 1).sum()), int((typ == 0).sum())
+    assert pop[4] == na and pop[:4].sum() == 0
+    rho = nt / L ** 3
+    rc = RC32
+    mean = rho * 4 / 3 * math.pi * rc ** 3
+    assert abs(pairs[4] / na - mean) < 5 * math.sqrt(mean / na), (pairs[4] / na, mean)
+    assert hist.sum() == pairs[4]
+    edges = np.array([math.sqrt(oracle.kin_edge2(1.12, b, nbins, lib=lib)) for b in range(nbins + 1)])
+    edges[-1] = rc
+    exp = na * rho * 4 / 3 * math.pi * np.diff(edges ** 3)
+    chi2 = float(((hist - exp) ** 2 / exp).sum())
+    assert chi2 < nbins - 1 + 6 * math.sqrt(2 * (nbins - 1)), (chi2, hist, exp)
+
+
+# --------------------------------------------------------------------------
 # FP64 recheck of the cutoff decision (diagnostic; the step decides in FP32)
 # --------------------------------------------------------------------------
 RC32 = float(np.float32(1.12))  # the cutoff as the FP32 value both sides use
@@ -650,4 +699,4 @@ ALL = [check_pair_distance, check_periodic, check_cutoff_strict, check_p0_p1, ch
        check_jitter_distribution, check_generator_offsets, check_jitter_wrap,
        check_near_cutoff, check_near_cutoff_disagree, check_nearest_picks_closest,
        check_nearest_mutual, check_nearest_tie_lower_id, check_nearest_probability,
-       check_nearest_exclusion_first]
+       check_nearest_exclusion_first, check_kinetics_hand, check_kinetics_poisson]

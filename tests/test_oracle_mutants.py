@@ -27,6 +27,7 @@ MUTANTS = {
     17: ("FP32 side of the recheck evaluated in FP64", [pins.check_near_cutoff_disagree]),
     18: ("nearest: bonded pairs stay candidates", [pins.check_nearest_exclusion_first]),
     19: ("nearest: pairs need not be mutual", [pins.check_nearest_mutual]),
+    20: ("kinetics: partners counted under the T's state", [pins.check_kinetics_hand]),
 }
 
 
