@@ -138,6 +138,26 @@ int pr_react_step(int32_t n, float L, const float* x, const float* y, const floa
                   const pr_rule* rule, uint64_t seed, uint32_t step, int32_t* bonds,
                   int32_t cap, int32_t* n_bonds, pr_stats* st, void* stream);
 
+/* Several concurrent rules in one step (1 <= nrules <= 4, each validated as
+ * for pr_react_step, all with PR_POLICY_RANDOM).  The paper proposes such
+ * concurrent reactions without a procedure (Sec. III B); the library
+ * generalises Table I: every rule contributes its candidates, each with its
+ * own draw (counter (step, id_A, id_T, tag), tag 0 for rule 0 and 0x100 + r
+ * for rule r); each particle, as an A, picks among its accepted candidates of
+ * all rules the smallest (w1, id_T) (the lower rule on a tie); each T keeps
+ * the smallest (w2, id_A) of the pairs that picked it; a particle that then
+ * wins both as the A of one pair and the T of another keeps the pair with
+ * the smaller (w3, partner id, rule), and a pair bonds only if both of its
+ * particles keep it.  Every particle still takes at most one new bond.  With
+ * one rule the result is pr_react_step's.  A particle may hold the A role of
+ * one rule and the T role of another.  bonds: 3 * cap int32 (id_A, id_T,
+ * rule) in increasing id_A order; the rest as pr_react_step. */
+int pr_react_step_multi(int32_t n, float L, const float* x, const float* y, const float* z,
+                        const int32_t* type, int32_t* state, int32_t* adj, int32_t B,
+                        const pr_rule* rules, int32_t nrules, uint64_t seed, uint32_t step,
+                        int32_t* bonds, int32_t cap, int32_t* n_bonds, pr_stats* st,
+                        void* stream);
+
 /* pr_react_step for callers that cannot allocate device memory: tight serving
  * loops and harnesses that forbid hipMalloc (like pr_react_step it
  * synchronises its stream, so it is not itself meant for graph capture).  Same
@@ -176,6 +196,14 @@ int pr_sys_create(pr_sys** out, int32_t n, float L, int32_t B, const pr_rule* ru
  * outside 0..6. */
 int pr_sys_create_ex(pr_sys** out, int32_t n, float L, int32_t B, const pr_rule* rule,
                      uint64_t seed, int64_t log_cap, void* stream, int32_t brick);
+
+/* A resident system with several concurrent rules (as pr_react_step_multi;
+ * the coarse grid is sized for the largest cutoff).  The bond log rows stay
+ * (step, id_A, id_T).  Checkpoints and kinetics counters take one rule
+ * (PR_EINVAL here); batches and the server take one rule per replica. */
+int pr_sys_create_multi(pr_sys** out, int32_t n, float L, int32_t B, const pr_rule* rules,
+                        int32_t nrules, uint64_t seed, int64_t log_cap, void* stream,
+                        int32_t brick);
 
 /* The handle's geometry: coarse cells per side, effective brick edge and
  * number of bricks (= sweep workgroups once sorted).  Any output may be NULL. */

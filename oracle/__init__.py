@@ -65,6 +65,16 @@ def _declare(lib):
     lib.or_jitter_scale.restype = C.c_float
     lib.or_jitter.argtypes = [i32, f32, P(f32), P(f32), P(f32), u64, u32, f64]
     lib.or_jitter.restype = None
+    lib.or_react_step_multi.argtypes = [i32, f32, P(f32), P(f32), P(f32), P(i32), P(i32), P(i32),
+                                        i32, P(i32), P(f32), P(f64), i32, u64, u32, P(i32), i64,
+                                        P(i64), P(i64)]
+    lib.or_react_step_multi.restype = C.c_int
+    lib.or_run_multi.argtypes = [i32, f32, P(f32), P(f32), P(f32), P(i32), P(i32), P(i32), i32,
+                                 P(i32), P(f32), P(f64), i32, u64, u32, u32, f64, P(i32), i64,
+                                 P(i64), P(i64)]
+    lib.or_run_multi.restype = C.c_int
+    lib.or_rule_tag.argtypes = [i32]
+    lib.or_rule_tag.restype = u32
     lib.or_kinetics.argtypes = [i32, f32, P(f32), P(f32), P(f32), P(i32), P(i32), P(i32), i32,
                                 i32, i32, i32, i32, i32, i32, f32, i32, i32, P(i64), P(i64), i32,
                                 P(i64)]
@@ -236,6 +246,53 @@ def near_cutoff(sysm, rule, tol=1e-6, lib=None):
     return near.value, dis.value
 
 
+def _rule_arrays(rules):
+    ri = np.zeros((len(rules), 10), np.int32)
+    for k, r in enumerate(rules):
+        ri[k, :9] = (r.type_a, r.a_min, r.a_max, r.d_a, r.type_t, r.t_min, r.t_max, r.d_t,
+                     r.exclude_bonded)
+    rc = np.array([r.rc for r in rules], np.float32)
+    p = np.array([r.p for r in rules], np.float64)
+    return ri, rc, p
+
+
+def react_step_multi(sysm, rules, seed, step, lib=None):
+    """One step with several concurrent rules, in place.  Returns (code,
+    bonds[n_b, 3] of (id_A, id_T, rule), stats dict)."""
+    lib = lib or load()
+    ri, rc, p = _rule_arrays(rules)
+    cap = sysm.n // 2 + 1
+    bonds = np.empty((cap, 3), np.int32)
+    nb = C.c_int64(0)
+    st = np.zeros(ST_COUNT, np.int64)
+    code = lib.or_react_step_multi(sysm.n, C.c_float(sysm.L), _p(sysm.x, C.c_float),
+                                   _p(sysm.y, C.c_float), _p(sysm.z, C.c_float),
+                                   _p(sysm.type, C.c_int32), _p(sysm.state, C.c_int32),
+                                   _p(sysm.adj, C.c_int32), sysm.B, _p(ri, C.c_int32),
+                                   _p(rc, C.c_float), _p(p, C.c_double), len(rules),
+                                   C.c_uint64(seed), C.c_uint32(step), _p(bonds, C.c_int32), cap,
+                                   C.byref(nb), _p(st, C.c_int64))
+    return code, bonds[: nb.value].copy(), dict(zip(ST_NAMES, st.tolist()))
+
+
+def run_multi(sysm, rules, seed, first_step, n_steps, sigma, log_cap=None, lib=None):
+    """Steps with several rules; log rows (step, id_A, id_T, rule)."""
+    lib = lib or load()
+    ri, rc, p = _rule_arrays(rules)
+    log_cap = log_cap or max(16, sysm.n * 4)
+    log = np.empty((log_cap, 4), np.int32)
+    nl = C.c_int64(0)
+    st = np.zeros((max(n_steps, 1), ST_COUNT), np.int64)
+    code = lib.or_run_multi(sysm.n, C.c_float(sysm.L), _p(sysm.x, C.c_float),
+                            _p(sysm.y, C.c_float), _p(sysm.z, C.c_float), _p(sysm.type, C.c_int32),
+                            _p(sysm.state, C.c_int32), _p(sysm.adj, C.c_int32), sysm.B,
+                            _p(ri, C.c_int32), _p(rc, C.c_float), _p(p, C.c_double), len(rules),
+                            C.c_uint64(seed), C.c_uint32(first_step), C.c_uint32(n_steps),
+                            float(sigma), _p(log, C.c_int32), log_cap, C.byref(nl),
+                            _p(st, C.c_int64))
+    return code, log[: min(nl.value, log_cap)].copy(), st[:n_steps]
+
+
 def kinetics(sysm, rule, nstate=8, nbins=16, lib=None):
     """Kinetics counters of the configuration: (pop[nstate], pairs[nstate],
     hist[nbins]) as numpy int64 arrays (see or_kinetics)."""
@@ -262,6 +319,6 @@ def num_threads(lib=None):
 
 
 __all__ = ["Rule", "System", "react_step", "run", "jitter", "philox", "threshold", "near_cutoff",
-           "kinetics", "kin_edge2",
+           "kinetics", "kin_edge2", "react_step_multi", "run_multi",
            "sample_bonds",
            "ih12_offsets", "ih4_offsets", "jitter_scale", "ST_NAMES", "load", "num_threads"]

@@ -576,6 +576,220 @@ int or_react_step_nearest(int32_t n, float L, const float* x, const float* y, co
 }
 
 /* ----------------------------------------------------------------------- */
+/* Several concurrent rules in one step (the extension Sec. III B and the    */
+/* conclusions propose; the paper gives no procedure, so this is the        */
+/* generalisation of Table I the library implements):                       */
+/*  1-2. every rule r contributes its candidates (A and T eligible under r, */
+/*       in range of r's cutoff, not bonded when r excludes bonded pairs),  */
+/*       each with its own draw: counter (step, id_A, id_T, tag(r)), tag 0  */
+/*       for rule 0 and 0x100 + r otherwise, accepted iff w0 < thresh(p_r); */
+/*  3-5. each particle, as an A, picks among all its accepted candidates    */
+/*       (any rule) the smallest (w1, id_T), the lower rule on a tie;       */
+/*  6-7. each T keeps, among the A's that picked it, the smallest (w2,      */
+/*       id_A) of the picked pairs;                                         */
+/*  8.   a particle can now hold two winning pairs (as the A of one rule    */
+/*       and the T of another): it keeps the one with the smaller (w3,      */
+/*       partner id, rule), and a pair is bonded only if both of its        */
+/*       particles keep it (losers wait for a later step, as in step 7);    */
+/*  9.   bonds in increasing id_A order, each with its rule's deltas.       */
+/* With one rule no particle can hold two roles (the windows of a rule do   */
+/* not overlap), step 8 never acts and the result is or_react_step's.       */
+/* rules: nrules records of 10 int32 (type_a, a_min, a_max, d_a, type_t,    */
+/* t_min, t_max, d_t, exclude_bonded, unused), rc[nrules], p[nrules].       */
+/* bonds: 3 * cap int32 (id_A, id_T, rule).  Counters summed over rules.    */
+/* ----------------------------------------------------------------------- */
+#define OR_MAX_RULES 4
+
+void or_jitter(int32_t n, float L, float* x, float* y, float* z, uint64_t seed, uint32_t step,
+               double sigma);
+
+uint32_t or_rule_tag(int32_t r) { return r == 0 ? 0u : 0x100u + (uint32_t)r; }
+
+typedef struct {
+  uint64_t key;  /* (w1, id_T) */
+  int32_t rule;
+} or_pick;
+
+static int pick_less(uint64_t k1, int32_t r1, uint64_t k2, int32_t r2) {
+  return k1 < k2 || (k1 == k2 && r1 < r2);
+}
+
+int or_react_step_multi(int32_t n, float L, const float* x, const float* y, const float* z,
+                        const int32_t* type, int32_t* state, int32_t* adj, int32_t B,
+                        const int32_t* rules, const float* rc, const double* p, int32_t nrules,
+                        uint64_t seed, uint32_t step,
+                        int32_t* bonds, int64_t cap, int64_t* n_bonds, int64_t* stats) {
+  if (nrules < 1 || nrules > OR_MAX_RULES) return OR_EINVAL;
+  or_rule R[OR_MAX_RULES];
+  uint64_t thresh[OR_MAX_RULES];
+  for (int32_t r = 0; r < nrules; ++r) {
+    const int32_t* q = rules + 10 * r;
+    or_rule rr = {q[0], q[1], q[2], q[3], q[4], q[5], q[6], q[7], rc[r], p[r], q[8]};
+    R[r] = rr;
+    int err = validate(n, L, x, y, z, B, &R[r]);
+    if (err) return err;
+    thresh[r] = or_threshold(p[r]);
+  }
+  if (cap < (int64_t)n / 2) return OR_ECAP;
+  const float halfL = 0.5f * L;
+  const size_t nn = (size_t)(n > 0 ? n : 1);
+  or_pick* pickA = (or_pick*)malloc(sizeof(or_pick) * nn);   /* steps 3-5, per A */
+  uint64_t* bestT = (uint64_t*)malloc(sizeof(uint64_t) * nn); /* steps 6-7, per T */
+  uint64_t* keep = (uint64_t*)malloc(sizeof(uint64_t) * nn);  /* step 8, per particle */
+  int32_t* keep_rule = (int32_t*)malloc(sizeof(int32_t) * nn);
+  if (!pickA || !bestT || !keep || !keep_rule) {
+    free(pickA); free(bestT); free(keep); free(keep_rule);
+    return OR_ENOMEM;
+  }
+  int64_t na = 0, nt = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    int a = 0, t = 0;
+    for (int32_t r = 0; r < nrules; ++r) {
+      a |= is_active(&R[r], type[i], state[i]);
+      t |= is_target(&R[r], type[i], state[i]);
+    }
+    na += a;
+    nt += t;
+    pickA[i].key = UINT64_MAX;
+    pickA[i].rule = -1;
+    bestT[i] = keep[i] = UINT64_MAX;
+    keep_rule[i] = -1;
+  }
+  /* steps 1-5: brute force over all pairs and rules */
+  int64_t in_rc = 0, drawn = 0, excluded = 0, accepted = 0, proposals = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : in_rc, drawn, excluded, accepted)
+  for (int64_t i = 0; i < n; ++i) {
+    for (int32_t r = 0; r < nrules; ++r) {
+      if (!is_active(&R[r], type[i], state[i])) continue;
+      const float rc2 = rc[r] * rc[r];
+      for (int64_t j = 0; j < n; ++j) {
+        if (j == i || !is_target(&R[r], type[j], state[j])) continue;
+        if (!in_cutoff(dist2(x, y, z, i, j, L, halfL), rc2)) continue;
+        in_rc++;
+        const int already = R[r].exclude_bonded && bonded(adj, B, i, j);
+        uint32_t ctr[4] = {step, (uint32_t)i, (uint32_t)j, or_rule_tag(r)}, w[4];
+        or_philox4x32_10(ctr, seed, w);
+        if (!((uint64_t)w[0] < thresh[r])) continue;
+        drawn++;
+        if (already) {
+          excluded++;
+          continue;
+        }
+        accepted++;
+        const uint64_t key = ((uint64_t)w[1] << 32) | (uint64_t)(uint32_t)j;
+        if (pick_less(key, r, pickA[i].key, pickA[i].rule)) {
+          pickA[i].key = key;
+          pickA[i].rule = r;
+        }
+      }
+    }
+  }
+  /* steps 6-7 */
+  for (int64_t i = 0; i < n; ++i) {
+    if (pickA[i].rule < 0) continue;
+    proposals++;
+    const int64_t j = (int64_t)(pickA[i].key & 0xFFFFFFFFu);
+    uint32_t ctr[4] = {step, (uint32_t)i, (uint32_t)j, or_rule_tag(pickA[i].rule)}, w[4];
+    or_philox4x32_10(ctr, seed, w);
+    const uint64_t key2 = ((uint64_t)w[2] << 32) | (uint64_t)(uint32_t)i;
+    if (key2 < bestT[j]) bestT[j] = key2;
+  }
+  /* step 8: every winning pair offers itself to both of its particles */
+  for (int64_t i = 0; i < n; ++i) {
+    if (pickA[i].rule < 0) continue;
+    const int64_t j = (int64_t)(pickA[i].key & 0xFFFFFFFFu);
+    if ((bestT[j] & 0xFFFFFFFFu) != (uint64_t)(uint32_t)i) continue;
+    const int32_t r = pickA[i].rule;
+    uint32_t ctr[4] = {step, (uint32_t)i, (uint32_t)j, or_rule_tag(r)}, w[4];
+    or_philox4x32_10(ctr, seed, w);
+    const uint64_t ki = ((uint64_t)w[3] << 32) | (uint64_t)(uint32_t)j;  /* at i */
+    const uint64_t kj = ((uint64_t)w[3] << 32) | (uint64_t)(uint32_t)i;  /* at j */
+    if (pick_less(ki, r, keep[i], keep_rule[i])) { keep[i] = ki; keep_rule[i] = r; }
+    if (pick_less(kj, r, keep[j], keep_rule[j])) { keep[j] = kj; keep_rule[j] = r; }
+  }
+  /* step 9 */
+  int64_t nb = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (pickA[i].rule < 0) continue;
+    const int64_t j = (int64_t)(pickA[i].key & 0xFFFFFFFFu);
+    if ((bestT[j] & 0xFFFFFFFFu) != (uint64_t)(uint32_t)i) continue;
+    const int32_t r = pickA[i].rule;
+#if OR_MUTANT != 21 /* mutant 21: no step 8 */
+    if (keep_rule[i] != r || (keep[i] & 0xFFFFFFFFu) != (uint64_t)(uint32_t)j) continue;
+    if (keep_rule[j] != r || (keep[j] & 0xFFFFFFFFu) != (uint64_t)(uint32_t)i) continue;
+#endif
+    bonds[3 * nb] = (int32_t)i;
+    bonds[3 * nb + 1] = (int32_t)j;
+    bonds[3 * nb + 2] = r;
+    nb++;
+  }
+  int64_t overflow = 0;
+  for (int64_t b = 0; b < nb; ++b) {
+    const int64_t i = bonds[3 * b], j = bonds[3 * b + 1];
+    const int32_t r = bonds[3 * b + 2];
+    state[i] += R[r].d_a;
+    state[j] += R[r].d_t;
+    int placed = 0;
+    for (int32_t s2 = 0; s2 < B && !placed; ++s2)
+      if (adj[i * B + s2] < 0) { adj[i * B + s2] = (int32_t)j; placed = 1; }
+    if (!placed) overflow++;
+    placed = 0;
+    for (int32_t s2 = 0; s2 < B && !placed; ++s2)
+      if (adj[j * B + s2] < 0) { adj[j * B + s2] = (int32_t)i; placed = 1; }
+    if (!placed) overflow++;
+  }
+  *n_bonds = nb;
+  if (stats) {
+    stats[ST_A_ELIG] = na;
+    stats[ST_T_ELIG] = nt;
+    stats[ST_IN_RC] = in_rc;
+    stats[ST_DRAWN] = drawn;
+    stats[ST_EXCLUDED] = excluded;
+    stats[ST_ACCEPTED] = accepted;
+    stats[ST_PROPOSALS] = proposals;
+    stats[ST_BONDS] = nb;
+    stats[ST_ADJ_OVERFLOW] = overflow;
+  }
+  free(pickA); free(bestT); free(keep); free(keep_rule);
+  return overflow ? OR_ECAP : OR_OK;
+}
+
+/* Steps first_step .. with several rules: each step re-jitters (sigma > 0)
+ * and runs or_react_step_multi.  Log rows: (step, id_A, id_T, rule). */
+int or_run_multi(int32_t n, float L, float* x, float* y, float* z, const int32_t* type,
+                 int32_t* state, int32_t* adj, int32_t B, const int32_t* rules, const float* rc,
+                 const double* p, int32_t nrules, uint64_t seed, uint32_t first_step,
+                 uint32_t n_steps, double sigma, int32_t* log, int64_t log_cap, int64_t* n_log,
+                 int64_t* stats_per_step) {
+  int32_t* sb = (int32_t*)malloc(sizeof(int32_t) * 3 * (size_t)(n / 2 + 1));
+  if (!sb) return OR_ENOMEM;
+  int64_t total = 0;
+  int code = OR_OK;
+  for (uint32_t k = 0; k < n_steps; ++k) {
+    const uint32_t st = first_step + k;
+    if (sigma > 0.0) or_jitter(n, L, x, y, z, seed, st, sigma);
+    int64_t nb = 0;
+    int e = or_react_step_multi(n, L, x, y, z, type, state, adj, B, rules, rc, p, nrules, seed,
+                                st, sb, n / 2 + 1, &nb,
+                                stats_per_step ? stats_per_step + (int64_t)k * ST_COUNT : NULL);
+    if (e != OR_OK && e != OR_ECAP) { code = e; break; }
+    if (e == OR_ECAP) code = OR_ECAP;
+    for (int64_t b = 0; b < nb; ++b, ++total) {
+      if (total < log_cap) {
+        log[4 * total] = (int32_t)st;
+        log[4 * total + 1] = sb[3 * b];
+        log[4 * total + 2] = sb[3 * b + 1];
+        log[4 * total + 3] = sb[3 * b + 2];
+      }
+    }
+  }
+  *n_log = total;
+  free(sb);
+  if (code == OR_OK && total > log_cap) return OR_ECAP;
+  return code;
+}
+
+/* ----------------------------------------------------------------------- */
 /* Sampled form of steps 1-7, for checks at sizes where a whole step is too  */
 /* slow: for each sampled particle ids[k], out[k] = the id of the target it  */
 /* bonds with in this step, or -1.  Its choice (steps 1-5) is computed by    */

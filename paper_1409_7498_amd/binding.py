@@ -97,6 +97,9 @@ def _load():
         "pr_sys_jitter": ([vp, u32, u32, f64, P(f32)], C.c_int),
         "pr_stream_copy": ([vp, vp, i64, i32, vp, P(f32)], C.c_int),
         "pr_sys_kinetics": ([vp, i32, vp, vp, i32, vp], C.c_int),
+        "pr_react_step_multi": ([i32, f32, vp, vp, vp, vp, vp, vp, i32, vp, i32, u64, u32, vp, i32,
+                                 P(i32), P(Stats), vp], C.c_int),
+        "pr_sys_create_multi": ([P(vp), i32, f32, i32, vp, i32, u64, i64, vp, i32], C.c_int),
         "pr_batch_kinetics": ([vp, i32, i32, vp, vp, i32, vp], C.c_int),
         "pr_sys_read": ([vp, vp, vp, vp, vp, vp, i32], C.c_int),
         "pr_sys_checkpoint": ([vp, vp, i64, P(i64)], C.c_int),
@@ -155,7 +158,7 @@ def exported_symbols():
                         "pr_sys_restore", "pr_p_from_rate", "pr_draws", "pr_server_poll",
                         "pr_server_cancel", "pr_autotune_cached", "pr_sys_prepare",
                         "pr_sys_jitter", "pr_stream_copy", "pr_sys_kinetics",
-                        "pr_batch_kinetics")]
+                        "pr_batch_kinetics", "pr_react_step_multi", "pr_sys_create_multi")]
 
 
 def _check(code):
@@ -202,14 +205,49 @@ def react_step(x, y, z, type_, state, adj, L, rule, seed, step, bonds=None, stre
     return code, bonds[: nb.value], st.as_dict()
 
 
+def _rules(rules):
+    arr = (Rule * len(rules))()
+    for k, r in enumerate(rules):
+        arr[k] = r if isinstance(r, Rule) else Rule.make(r)
+    return arr
+
+
+def react_step_multi(x, y, z, type_, state, adj, L, rules, seed, step, stream=None,
+                     raise_on_error=True):
+    """One step with several concurrent rules on device tensors.  Returns
+    (code, bonds[n_b, 3] of (id_A, id_T, rule) device tensor view, stats)."""
+    import torch
+    n = x.numel()
+    B = adj.shape[1] if adj.dim() == 2 else 1
+    cap = n // 2 + 1
+    bonds = torch.empty((cap, 3), dtype=torch.int32, device=x.device)
+    nb = C.c_int32(0)
+    st = Stats()
+    arr = _rules(rules)
+    code = lib.pr_react_step_multi(n, C.c_float(L), _ptr(x), _ptr(y), _ptr(z), _ptr(type_),
+                                   _ptr(state), _ptr(adj), B, arr, len(rules), C.c_uint64(seed),
+                                   C.c_uint32(step), _ptr(bonds), cap, C.byref(nb), C.byref(st),
+                                   _stream(stream))
+    if raise_on_error and code != PR_OK:
+        _check(code)
+    return code, bonds[: nb.value], st.as_dict()
+
+
 class System:
     """Resident particle system (pr_sys_* entry points)."""
 
     def __init__(self, n, L, B, rule, seed, log_cap=0, stream=None, brick=0):
-        """brick: brick edge in coarse cells (1..6, 0 = 4), a tuning choice only."""
+        """brick: brick edge in coarse cells (1..6, 0 = 4), a tuning choice only.
+        rule: one rule, or a list of several concurrent rules."""
         self._h = C.c_void_p()
-        r = rule if isinstance(rule, Rule) else Rule.make(rule)
         self.n, self.L, self.B = int(n), float(np.float32(L)), int(B)
+        if isinstance(rule, (list, tuple)):
+            arr = _rules(rule)
+            _check(lib.pr_sys_create_multi(C.byref(self._h), self.n, C.c_float(L), self.B, arr,
+                                           len(rule), C.c_uint64(seed), int(log_cap),
+                                           _stream(stream), int(brick)))
+            return
+        r = rule if isinstance(rule, Rule) else Rule.make(rule)
         _check(lib.pr_sys_create_ex(C.byref(self._h), self.n, C.c_float(L), self.B, C.byref(r),
                                     C.c_uint64(seed), int(log_cap), _stream(stream), int(brick)))
 

@@ -129,6 +129,8 @@ void set_geometry(Dev& d, int32_t n, float L, int32_t B, const pr_rule* r, uint6
   d.seed = seed;
   d.rule = RuleD{r->type_a, r->a_min, r->a_max, r->d_a, r->type_t, r->t_min, r->t_max, r->d_t,
                  r->exclude_bonded, r->policy};
+  d.nrules = 1;
+  d.mr[0] = RuleX{d.rule, d.rc2, 0u, d.thresh};
   d.nwg_sweep = sweep_blocks(n);
   d.nwg_prep = prep_blocks(n);
   d.adj_staged = B <= kAdjStage ? 1 : 0;
@@ -151,6 +153,42 @@ void set_geometry(Dev& d, int32_t n, float L, int32_t B, const pr_rule* r, uint6
   d.sorted = 0;
   // closing groups cover the larger of the two sweep grids (dense, bricks)
   d.ngroups = (std::max(d.nwg_sweep, d.nbricks) + kGroup - 1) / kGroup;
+}
+
+// Validation of a set of concurrent rules (each as validate_rule; several
+// rules use the random selection).
+int validate_rules(const pr_rule* rules, int32_t nrules, float L) {
+  if (!rules || nrules < 1 || nrules > kMaxRules)
+    return fail(PR_EINVAL, "nrules=%d (1..%d)", nrules, kMaxRules);
+  for (int32_t r = 0; r < nrules; ++r) {
+    int e = validate_rule(&rules[r], L);
+    if (e) return e;
+    if (nrules > 1 && rules[r].policy != PR_POLICY_RANDOM)
+      return fail(PR_EINVAL, "several rules use the random selection (rule %d)", r);
+  }
+  return PR_OK;
+}
+
+// Geometry of a system of nrules concurrent rules: the A grid is sized for
+// the largest cutoff; each rule keeps its own cutoff, threshold and tag.
+void set_geometry_rules(Dev& d, int32_t n, float L, int32_t B, const pr_rule* rules,
+                        int32_t nrules, uint64_t seed, int brick_pref) {
+  pr_rule big = rules[0];
+  for (int32_t r = 1; r < nrules; ++r) big.rc = std::max(big.rc, rules[r].rc);
+  set_geometry(d, n, L, B, &big, seed, brick_pref);
+  d.rule.d_a = rules[0].d_a;
+  if (nrules == 1) {
+    d.rc2 = rules[0].rc * rules[0].rc;
+    d.mr[0].rc2 = d.rc2;
+    return;
+  }
+  d.nrules = nrules;
+  for (int32_t r = 0; r < nrules; ++r) {
+    const pr_rule& q = rules[r];
+    d.mr[r] = RuleX{RuleD{q.type_a, q.a_min, q.a_max, q.d_a, q.type_t, q.t_min, q.t_max, q.d_t,
+                          q.exclude_bonded, q.policy},
+                    q.rc * q.rc, r == 0 ? 0u : 0x100u + (uint32_t)r, threshold(q.p)};
+  }
 }
 
 // Device allocations of one handle.  dry = true only adds up the bytes (the
@@ -222,6 +260,9 @@ int alloc_scratch(Arena& a, Dev& d, int32_t n, int32_t nwg, hipStream_t s) {
       return e;
   }
   if ((e = a.alloc(&d.ctl, 1))) return e;
+  if (d.nrules > 1 && ((e = a.alloc(&d.wfa, n)) || (e = a.alloc(&d.wft, n)) ||
+                       (e = a.alloc(&d.wina, n)) || (e = a.alloc(&d.wint, n))))
+    return e;
   if (a.dry || a.base) return PR_OK;  // a carved region is cleared by its user
   HIP_TRY(hipMemsetAsync(d.cnt[0], 0, sizeof(uint32_t) * std::max(1, d.ncell), s));
   HIP_TRY(hipMemsetAsync(d.cnt[1], 0, sizeof(uint32_t) * std::max(1, d.ncell), s));
@@ -243,6 +284,7 @@ struct Workspace {
   unsigned long long* sortbuf = nullptr;
   Ctl* hctl = nullptr;  // pinned host copies
   int32_t* hpart = nullptr;
+  bool multi = false;   // holds the arrays of several concurrent rules
   ~Workspace() {
     if (hctl) (void)hipHostFree(hctl);
     if (hpart) (void)hipHostFree(hpart);
@@ -313,6 +355,8 @@ void bind_single(Dev& d, const Dev& geo, float* x, float* y, float* z, int32_t* 
   d.thresh = geo.thresh;
   d.seed = geo.seed;
   d.rule = geo.rule;
+  d.nrules = geo.nrules;
+  for (int r = 0; r < kMaxRules; ++r) d.mr[r] = geo.mr[r];
   d.adj_staged = geo.adj_staged;
   d.nwg_sweep = geo.nwg_sweep;
   d.nwg_prep = geo.nwg_prep;
@@ -322,6 +366,7 @@ void bind_single(Dev& d, const Dev& geo, float* x, float* y, float* z, int32_t* 
   d.set[0] = d.set[1] = caller;
   d.bonds = bonds;
   d.bonds_cap = cap;
+  d.bonds_rule = 0;
   d.log_cap = (int64_t)geo.n / 2 + 1;
   d.part_cap = 1;
   d.ngroups = (d.nwg_sweep + kGroup - 1) / kGroup;
@@ -382,12 +427,20 @@ int carve_single(Arena& a, Dev& d, int32_t n, uint8_t** role) {
 
 extern "C" {
 
-int pr_react_step(int32_t n, float L, const float* x, const float* y, const float* z,
-                  const int32_t* type, int32_t* state, int32_t* adj, int32_t B,
-                  const pr_rule* rule, uint64_t seed, uint32_t step, int32_t* bonds,
-                  int32_t cap, int32_t* n_bonds, pr_stats* st, void* stream) {
-  int e = check_single(n, L, x, y, z, type, state, adj, B, rule, bonds, cap, n_bonds);
+}  // extern "C"
+
+namespace {
+
+// The stateless step with nrules concurrent rules (nrules == 1: the single
+// rule of pr_react_step) on the per-device workspace.
+int react_step_impl(int32_t n, float L, const float* x, const float* y, const float* z,
+                    const int32_t* type, int32_t* state, int32_t* adj, int32_t B,
+                    const pr_rule* rules, int32_t nrules, uint64_t seed, uint32_t step,
+                    int32_t* bonds, int32_t cap, int32_t* n_bonds, pr_stats* st, void* stream,
+                    bool triples) {
+  int e = validate_rules(rules, nrules, L);
   if (e) return e;
+  if ((e = check_single(n, L, x, y, z, type, state, adj, B, rules, bonds, cap, n_bonds))) return e;
   *n_bonds = 0;
   if (st) std::memset(st, 0, sizeof *st);
   if (n == 0) return PR_OK;
@@ -398,17 +451,20 @@ int pr_react_step(int32_t n, float L, const float* x, const float* y, const floa
   if ((int)g_ws.size() <= dev) g_ws.resize(dev + 1, nullptr);
   Workspace*& ws = g_ws[dev];
   Dev geo{};
-  set_geometry(geo, n, L, B, rule, seed, kDefaultBrick);
-  if (!ws || ws->n < n || ws->ncell < geo.ncell) {
+  set_geometry_rules(geo, n, L, B, rules, nrules, seed, kDefaultBrick);
+  if (!ws || ws->n < n || ws->ncell < geo.ncell || (nrules > 1 && !ws->multi)) {
+    const bool multi = nrules > 1 || (ws && ws->multi);
     delete ws;
     ws = new Workspace();
     ws->d = geo;
+    ws->d.nrules = multi ? 2 : 1;  // allocation of the several-rule arrays
     const int32_t n_alloc = std::max(n, 1024);
     if ((e = alloc_scratch(ws->arena, ws->d, n_alloc, sweep_blocks(n_alloc), s))) {
       delete ws;
       ws = nullptr;
       return e;
     }
+    ws->multi = multi;
     size_t n2 = 1;
     while (n2 < (size_t)n_alloc / 2 + 1) n2 <<= 1;
     ws->ngroups = (sweep_blocks(n_alloc) + kGroup - 1) / kGroup;
@@ -428,12 +484,34 @@ int pr_react_step(int32_t n, float L, const float* x, const float* y, const floa
   d.part = ws->part;
   bind_single(d, geo, const_cast<float*>(x), const_cast<float*>(y), const_cast<float*>(z),
               const_cast<int32_t*>(type), state, adj, ws->role, bonds, cap);
+  d.bonds_rule = triples ? 1 : 0;
   // The workspace serves calls of any box size: a previous call may have left
   // counts in cells beyond this call's grid, so both count buffers are cleared
   // over their whole allocation (each step only clears the cells it uses).
   HIP_TRY(hipMemsetAsync(d.cnt[0], 0, sizeof(uint32_t) * (size_t)ws->ncell, s));
   HIP_TRY(hipMemsetAsync(d.cnt[1], 0, sizeof(uint32_t) * (size_t)ws->ncell, s));
   return single_step(d, step, s, ws->hctl, ws->hpart, n_bonds, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+int pr_react_step(int32_t n, float L, const float* x, const float* y, const float* z,
+                  const int32_t* type, int32_t* state, int32_t* adj, int32_t B,
+                  const pr_rule* rule, uint64_t seed, uint32_t step, int32_t* bonds,
+                  int32_t cap, int32_t* n_bonds, pr_stats* st, void* stream) {
+  return react_step_impl(n, L, x, y, z, type, state, adj, B, rule, 1, seed, step, bonds, cap,
+                         n_bonds, st, stream, false);
+}
+
+int pr_react_step_multi(int32_t n, float L, const float* x, const float* y, const float* z,
+                        const int32_t* type, int32_t* state, int32_t* adj, int32_t B,
+                        const pr_rule* rules, int32_t nrules, uint64_t seed, uint32_t step,
+                        int32_t* bonds, int32_t cap, int32_t* n_bonds, pr_stats* st,
+                        void* stream) {
+  return react_step_impl(n, L, x, y, z, type, state, adj, B, rules, nrules, seed, step, bonds,
+                         cap, n_bonds, st, stream, true);
 }
 
 int pr_react_step_noalloc(int32_t n, float L, const float* x, const float* y, const float* z,
@@ -784,12 +862,13 @@ struct SysLease {
 };
 
 int sys_create(pr_sys** out, int32_t n, float L, int32_t B, const pr_rule* rule, uint64_t seed,
-               int64_t log_cap, void* stream, int32_t brick, const SysLease* lease) {
+               int64_t log_cap, void* stream, int32_t brick, const SysLease* lease,
+               int32_t nrules = 1) {
   if (!out) return fail(PR_EINVAL, "out is NULL");
   *out = nullptr;
   if (n < 1 || n > kMaxParticles || B < 1) return fail(PR_EINVAL, "n=%d B=%d", n, B);
   if (brick < 0 || brick > kMaxBrick) return fail(PR_EINVAL, "brick=%d", brick);
-  int e = validate_rule(rule, L);
+  int e = validate_rules(rule, nrules, L);
   if (e) return e;
   pr_sys* s = new pr_sys();
   s->stream = (hipStream_t)stream;
@@ -806,7 +885,7 @@ int sys_create(pr_sys** out, int32_t n, float L, int32_t B, const pr_rule* rule,
     return fail(PR_EHIP, "hipGetDevice failed");
   }
   Dev& d = s->d;
-  set_geometry(d, n, L, B, rule, seed, brick > 0 ? brick : kDefaultBrick);
+  set_geometry_rules(d, n, L, B, rule, nrules, seed, brick > 0 ? brick : kDefaultBrick);
   s->log_cap = log_cap > 0 ? log_cap : n;
   e = alloc_system(s->arena, d, n, B, s->log_cap, s->stream);
   if (!e && !s->hctl && hipHostMalloc((void**)&s->hctl, sizeof(Ctl)) != hipSuccess)
@@ -839,6 +918,12 @@ int pr_sys_create(pr_sys** out, int32_t n, float L, int32_t B, const pr_rule* ru
 int pr_sys_create_ex(pr_sys** out, int32_t n, float L, int32_t B, const pr_rule* rule,
                      uint64_t seed, int64_t log_cap, void* stream, int32_t brick) {
   return sys_create(out, n, L, B, rule, seed, log_cap, stream, brick, nullptr);
+}
+
+int pr_sys_create_multi(pr_sys** out, int32_t n, float L, int32_t B, const pr_rule* rules,
+                        int32_t nrules, uint64_t seed, int64_t log_cap, void* stream,
+                        int32_t brick) {
+  return sys_create(out, n, L, B, rules, seed, log_cap, stream, brick, nullptr, nrules);
 }
 
 int pr_sys_geometry(pr_sys* s, int32_t* nc, int32_t* brick, int32_t* nbricks) {
@@ -1057,6 +1142,7 @@ int pr_sys_kinetics(pr_sys* s, int32_t nstate, int64_t* pop, int64_t* pairs, int
     return fail(PR_EINVAL, "nstate=%d (1..%d), nbins=%d (0..%d)", nstate, kKinMaxState, nbins,
                 kKinMaxBins);
   if (!pop || !pairs || (nbins > 0 && !hist)) return fail(PR_EINVAL, "NULL output");
+  if (s->d.nrules > 1) return fail(PR_EINVAL, "kinetics counters take one rule");
   const size_t nk = 2 * kKinMaxState + kKinMaxBins;
   if (!s->kin && ((e = s->arena.alloc(&s->kin, nk)) ||
                   (e = s->arena.alloc(&s->kin_e2, (size_t)kKinMaxBins + 1))))
@@ -1203,6 +1289,8 @@ int sys_bonds(pr_sys* s, int32_t* out, int64_t cap, int64_t* n, void* pin, size_
         return u.step != v.step ? u.step < v.step : u.a < v.a;
       });
     }
+    if (s->d.nrules > 1)  // the rule of each bond rides in bits 30-31 of id_T
+      for (size_t i = 0; i < nr; ++i) rows[i].t &= 0x3FFFFFFF;
     std::memcpy(out, rows, (size_t)m * sizeof(Row));
   }
   *n = total;
@@ -1285,6 +1373,7 @@ extern "C" {
 int pr_sys_checkpoint(pr_sys* s, void* buf, int64_t cap, int64_t* bytes) {
   int e = check_sys(s, true);
   if (e) return e;
+  if (s->d.nrules > 1) return fail(PR_EINVAL, "checkpoints hold one rule");
   if (!bytes) return fail(PR_EINVAL, "bytes is NULL");
   if ((e = sync_ctl(s))) return e;
   if (s->hctl->err) return fail(s->hctl->err, "device error during the run");

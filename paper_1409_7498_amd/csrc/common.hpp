@@ -41,6 +41,7 @@ constexpr int kStageRecs = 256;
 constexpr int kTPass = 768;         // particles a sweep workgroup holds per pass (3 per thread)
 constexpr int kQueue = 512;         // in-range pairs queued per pass
 constexpr int32_t kMaxParticles = 1 << 30;  // byte offsets of 4-byte fields fit in 32 bits
+constexpr int kMaxRules = 4;        // concurrent rules of one system
 constexpr int kKinMaxState = 64;    // kinetics counters: states per call
 constexpr int kKinMaxBins = 256;    // kinetics counters: distance bins per call
 
@@ -68,6 +69,15 @@ struct RuleD {
   int32_t policy;  // PR_POLICY_RANDOM / PR_POLICY_NEAREST
 };
 
+// One of several concurrent rules: its windows and deltas, squared cutoff,
+// acceptance threshold and the draw tag (counter word 3).
+struct RuleX {
+  RuleD r;
+  float rc2;
+  uint32_t tag;
+  unsigned long long thresh;
+};
+
 // Particle arrays of one storage set, slot order.  Positions have two
 // buffers: a step reads parity p and writes the jittered positions to p ^ 1.
 struct Arr {
@@ -77,6 +87,9 @@ struct Arr {
 };
 
 enum Role : uint8_t { kRoleNone = 0, kRoleT = 1, kRoleA = 2 };
+// With several rules the role byte is a mask: bit r = T of rule r, bit 4 + r =
+// A of rule r.
+constexpr uint8_t kMaskT = 0x0F, kMaskA = 0xF0;
 
 // Everything a kernel needs, passed by value as the kernel argument.
 struct Dev {
@@ -112,6 +125,7 @@ struct Dev {
   // outputs
   int32_t* bonds;       // stateless step: (id_A, id_T) in id_A order
   int64_t bonds_cap;
+  int32_t bonds_rule;   // stateless step: rows (id_A, id_T, rule) instead
   int32_t* log;         // (step, id_A, id_T) rows
   int64_t log_cap;
   int32_t* part;        // per step and closing group: kPart partial counters
@@ -133,6 +147,12 @@ struct Dev {
   float L, halfL, rc2, inv_w, jit_c;
   unsigned long long thresh, seed;
   RuleD rule;
+  // several concurrent rules (nrules > 1; then rc2 is the largest cutoff's)
+  int32_t nrules;
+  RuleX mr[kMaxRules];
+  uint8_t *wfa, *wft;   // per slot: won as an A / as a T in this step (one writer each)
+  int4 *wina, *wint;    // per slot, the winning pair as A / as T:
+                        // (partner id, partner slot, rule, 0)
 };
 
 // A batch of independent systems stepped in lockstep: their Devs in device

@@ -128,7 +128,21 @@ __device__ __forceinline__ bool is_t(const Dev& d, int32_t t, int32_t s) {
 }
 
 __device__ __forceinline__ uint8_t role_of(const Dev& d, int32_t t, int32_t s) {
+  if (d.nrules > 1) {  // a mask over the rules: T bits 0-3, A bits 4-7
+    uint32_t m = 0;
+    for (int r = 0; r < d.nrules; ++r) {
+      const RuleD& q = d.mr[r].r;
+      if (in_window(t, s, q.type_t, q.t_min, q.t_max)) m |= 1u << r;
+      if (in_window(t, s, q.type_a, q.a_min, q.a_max)) m |= 16u << r;
+    }
+    return (uint8_t)m;
+  }
   return is_t(d, t, s) ? kRoleT : (is_a(d, t, s) ? kRoleA : kRoleNone);
+}
+
+// Whether a role byte makes its particle an A (of some rule).
+__device__ __forceinline__ bool role_is_a(uint32_t b, bool multi) {
+  return multi ? (b & kMaskA) != 0u : b == kRoleA;
 }
 
 __device__ __forceinline__ int cell1(float u, int nc) {
@@ -426,10 +440,11 @@ __device__ __forceinline__ void prep_body(const Dev& d, int k, int blk) {
       }
   }
   int na = 0;
+  const bool multi = d.nrules > 1;
 #pragma unroll
   for (int q = 0; q < kPrepRoles / 4; ++q)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) na += ((rw[q] >> (8 * e)) & 0xFFu) == kRoleA;
+    for (int e = 0; e < 4; ++e) na += role_is_a((rw[q] >> (8 * e)) & 0xFFu, multi);
   uint32_t incl = (uint32_t)na;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
@@ -442,7 +457,7 @@ __device__ __forceinline__ void prep_body(const Dev& d, int k, int blk) {
   for (int q = 0; q < kPrepRoles / 4; ++q)
 #pragma unroll
     for (int e = 0; e < 4; ++e)
-      if (((rw[q] >> (8 * e)) & 0xFFu) == kRoleA) s_list[wv][at++] = i0 + 4 * q + e;
+      if (role_is_a((rw[q] >> (8 * e)) & 0xFFu, multi)) s_list[wv][at++] = i0 + 4 * q + e;
   __syncthreads();
   for (int e = lane; e < wtot; e += 64) {
     const int i = s_list[wv][e];
@@ -1087,6 +1102,30 @@ struct BondCtx {
   int* lost;
 };
 
+// A bond (step 9): states, roles, adjacency rows, and the staged (id_A, id_T)
+// row for the log; tagged_t: id_T with the rule of a system of several rules
+// in bits 30-31 (plain id_T otherwise).
+__device__ __forceinline__ void make_bond_d(const Dev& d, const Arr& a, uint32_t par, int w,
+                                            int ida, int sa, int sj, int idj, int32_t da,
+                                            int32_t dt, int tagged_t, const BondCtx& b) {
+  const int32_t na = a.st[sa] + da, nt = a.st[sj] + dt;
+  a.st[sa] = na;
+  a.st[sj] = nt;
+  a.role[sa] = role_of(d, a.typ[sa], na);
+  a.role[sj] = role_of(d, a.typ[sj], nt);
+  int lost = 0;
+  if (!adj_append(a.adj + (size_t)sa * d.B, d.B, (int32_t)idj)) lost++;
+  if (!adj_append(a.adj + (size_t)sj * d.B, d.B, (int32_t)ida)) lost++;
+  if (lost) atomicAdd(b.lost, lost);
+  const int p = atomicAdd(b.nw, 1);
+  if (p < kWinCap) {
+    pick(d.wgw, par)[w * kWinCap + p] = make_int2(ida, tagged_t);
+  } else {
+    const uint32_t o = atomicAdd(&d.ctl->nwin_ovf[par], 1u);
+    pick(d.wov, par)[o] = make_int2(ida, tagged_t);
+  }
+}
+
 __device__ __forceinline__ void make_bond(const Dev& d, const Arr& a, uint32_t par, int w,
                                           int ida, int sa, int sj, int idj, const BondCtx& b) {
   const int32_t na = a.st[sa] + d.rule.d_a, nt = a.st[sj] + d.rule.d_t;
@@ -1412,6 +1451,245 @@ __device__ __forceinline__ void near_resolve_body(const Dev& d, int k, int w, in
 }
 
 // ---------------------------------------------------------------------------
+// Several concurrent rules (nrules > 1): Table I generalised over the rules.
+// Every rule contributes candidates with its own draw (counter word 3 = the
+// rule's tag); each A picks among its accepted candidates of all rules the
+// smallest (w1, id_T), the lower rule on a tie; each T keeps the smallest
+// (w2, id_A) of the pairs that picked it; a particle that wins both as an A
+// and as a T keeps the pair with the smaller (w3, partner id, rule) and a
+// pair is bonded only if both of its particles keep it.  Three kernels after
+// the binning: the sweep (draws, A-side picks by 64-bit atomicMin, T flags),
+// the T-side choice (re-enumerates the flagged T's candidates) and the final
+// choice with the bonds.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t rule_tag(const Dev& d, int r) {
+  uint32_t t = d.mr[0].tag;
+#pragma unroll
+  for (int q = 1; q < kMaxRules; ++q)
+    if (r == q) t = d.mr[q].tag;
+  return t;
+}
+
+__device__ __forceinline__ void rule_deltas(const Dev& d, int r, int32_t& da, int32_t& dt) {
+  da = d.mr[0].r.d_a;
+  dt = d.mr[0].r.d_t;
+#pragma unroll
+  for (int q = 1; q < kMaxRules; ++q)
+    if (r == q) {
+      da = d.mr[q].r.d_a;
+      dt = d.mr[q].r.d_t;
+    }
+}
+
+__device__ __forceinline__ bool key_less(unsigned long long k1, int r1, unsigned long long k2,
+                                         int r2) {
+  return k1 < k2 || (k1 == k2 && r1 < r2);
+}
+
+// Visits the rules r under which the pair (A record at slot sa, T of role
+// mask rt) is a candidate at squared distance r2, in increasing r:
+// f(r, draw words, excluded as bonded).
+template <typename F>
+__device__ __forceinline__ void multi_candidates(const Dev& d, const Arr& a, uint32_t step,
+                                                 uint32_t rt, int sa, int ida, uint32_t idj,
+                                                 float r2, F f) {
+  const uint32_t both = rt & ((uint32_t)a.role[sa] >> 4);
+  if (!both) return;
+  int bonded = -1;
+#pragma unroll
+  for (int r = 0; r < kMaxRules; ++r) {
+    if (r >= d.nrules || !((both >> r) & 1u) || !(r2 < d.mr[r].rc2)) continue;
+    if (bonded < 0) bonded = row_has(a.adj + (size_t)sa * d.B, d.B, (int32_t)idj) ? 1 : 0;
+    const W4 w = philox(step, (uint32_t)ida, idj, d.mr[r].tag, d.seed);
+    f(r, w, d.mr[r].r.exclude && bonded > 0, w.w0 < d.mr[r].thresh);
+  }
+}
+
+template <bool kBrick>
+__device__ __forceinline__ void multi_sweep_body(const Dev& d, int k, int w, int nwg) {
+  __shared__ int s_cnt[4];
+  const int tid = threadIdx.x;
+  if (tid < 4) s_cnt[tid] = 0;
+  const Ctl* c = d.ctl;
+  const StepInfo si = step_info(c, k);
+  const uint32_t par = si.par, step = si.step;
+  const Arr a = pick_set(d, c->set & 1u);
+  const float *X = pick(a.x, par), *Y = pick(a.y, par), *Z = pick(a.z, par);
+  float *XW = pick(a.x, par ^ 1u), *YW = pick(a.y, par ^ 1u), *ZW = pick(a.z, par ^ 1u);
+  const bool jit = d.jitter && d.jit_c != 0.0f;
+  const uint32_t novf = c->ovf_n[par];
+  const bool dead = read_err(c) != 0;
+  int s0, s1;
+  range_of<kBrick>(d, w, s0, s1);
+  __syncthreads();
+  int t_elig = 0, in_rc = 0, drawn = 0, excl = 0;
+  for (int slot = s0 + tid; slot < s1 && !dead; slot += kThreads) {
+    float x = X[slot], y = Y[slot], z = Z[slot];
+    const uint32_t id = a.id ? (uint32_t)a.id[slot] : (uint32_t)slot;
+    if (d.jitter) {
+      if (jit) rejitter(d, step, id, x, y, z);
+      XW[slot] = x;
+      YW[slot] = y;
+      ZW[slot] = z;
+    }
+    d.wfa[slot] = 0;
+    d.wft[slot] = 0;
+    const uint32_t rt = a.role[slot] & kMaskT;
+    if (!rt) continue;
+    t_elig++;
+    bool any = false;
+    for_global_records(d, par, novf, x, y, z, [&](float4 A, int sa) {
+      const int ida = __float_as_int(A.w);
+      if ((uint32_t)ida == id) return;
+      const float r2 = dist2(d, x, y, z, A);
+      if (!(r2 < d.rc2)) return;
+      multi_candidates(d, a, step, rt, sa, ida, id, r2, [&](int, W4 wd, bool ex, bool acc) {
+        in_rc++;
+        if (!acc) return;
+        drawn++;
+        if (ex) {
+          excl++;
+          return;
+        }
+        any = true;
+        atomicMin(&d.slotA[ida], ((unsigned long long)wd.w1 << 32) | id);
+      });
+    });
+    if (any) d.tflag[slot] = 1;
+  }
+  wave_add(&s_cnt[0], t_elig);
+  wave_add(&s_cnt[1], in_rc);
+  wave_add(&s_cnt[2], drawn);
+  wave_add(&s_cnt[3], excl);
+  for (int q = w * kThreads + tid; q < d.ncell; q += nwg * kThreads)
+    pick(d.cnt, par ^ 1u)[q] = 0u;
+  __syncthreads();
+  int32_t* out = pick(d.wgo, par) + w * kWgOut;
+  if (tid == 0) {
+    out[kOutTElig] = s_cnt[0];
+    out[kOutInRc] = s_cnt[1];
+    out[kOutDrawn] = s_cnt[2];
+    out[kOutExcl] = s_cnt[3];
+    out[kOutRet] = 0;
+  }
+}
+
+// The T side: every T with an accepted candidate finds the A's whose pick
+// names it (the lowest rule whose accepted candidate gives the A's key) and
+// keeps the smallest (w2, id_A); the pair is recorded at both slots.
+template <bool kBrick>
+__device__ __forceinline__ void multi_resolve_body(const Dev& d, int k, int w) {
+  __shared__ int s_prop;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_prop = 0;
+  __syncthreads();
+  const Ctl* c = d.ctl;
+  const StepInfo si = step_info(c, k);
+  const uint32_t par = si.par, step = si.step;
+  const Arr a = pick_set(d, c->set & 1u);
+  const float *X = pick(a.x, par ^ 1u), *Y = pick(a.y, par ^ 1u), *Z = pick(a.z, par ^ 1u);
+  const uint32_t novf = c->ovf_n[par];
+  int s0, s1;
+  range_of<kBrick>(d, w, s0, s1);
+  int prop = 0;
+  for (int slot = s0 + tid; slot < s1; slot += kThreads) {
+    if (d.tflag[slot] != 1) continue;
+    d.tflag[slot] = 0;
+    const float x = X[slot], y = Y[slot], z = Z[slot];
+    const uint32_t id = a.id ? (uint32_t)a.id[slot] : (uint32_t)slot;
+    const uint32_t rt = a.role[slot] & kMaskT;
+    unsigned long long best = kEmpty;
+    int best_sa = 0, best_r = 0;
+    for_global_records(d, par, novf, x, y, z, [&](float4 A, int sa) {
+      const int ida = __float_as_int(A.w);
+      if ((uint32_t)ida == id) return;
+      const float r2 = dist2(d, x, y, z, A);
+      if (!(r2 < d.rc2)) return;
+      const unsigned long long key = d.slotA[ida];
+      if (key == kEmpty || (uint32_t)key != id) return;  // the A picked another T
+      int got = -1;
+      W4 wg{0, 0, 0, 0};
+      multi_candidates(d, a, step, rt, sa, ida, id, r2, [&](int r, W4 wd, bool ex, bool acc) {
+        if (got < 0 && acc && !ex && wd.w1 == (uint32_t)(key >> 32)) {
+          got = r;
+          wg = wd;
+        }
+      });
+      if (got < 0) return;
+      d.slotA[ida] = kEmpty;  // only this T's thread reads the key that names it
+      prop++;
+      const unsigned long long k2 = ((unsigned long long)wg.w2 << 32) | (uint32_t)ida;
+      if (k2 < best) {
+        best = k2;
+        best_sa = sa;
+        best_r = got;
+      }
+    });
+    if (best != kEmpty) {
+      const int ida = (int)(uint32_t)best;
+      d.wint[slot] = make_int4(ida, best_sa, best_r, 0);
+      d.wina[best_sa] = make_int4((int)id, slot, best_r, 0);
+      d.wft[slot] = 1;
+      d.wfa[best_sa] = 1;  // one writer: the A picked one T
+    }
+  }
+  atomicAdd(&s_prop, prop);
+  __syncthreads();
+  if (tid == 0) pick(d.wgo, par)[w * kWgOut + kOutProp] = s_prop;
+}
+
+// Step 8 and the bonds, from the T of every winning pair.
+template <bool kBrick>
+__device__ __forceinline__ void multi_final_body(const Dev& d, int k, int w) {
+  __shared__ int s_nw, s_lost;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    s_nw = 0;
+    s_lost = 0;
+  }
+  __syncthreads();
+  const Ctl* c = d.ctl;
+  const StepInfo si = step_info(c, k);
+  const uint32_t par = si.par, step = si.step;
+  const Arr a = pick_set(d, c->set & 1u);
+  const BondCtx bc{&s_nw, &s_lost};
+  int s0, s1;
+  range_of<kBrick>(d, w, s0, s1);
+  for (int slot = s0 + tid; slot < s1; slot += kThreads) {
+    if (!d.wft[slot]) continue;
+    const uint32_t id = a.id ? (uint32_t)a.id[slot] : (uint32_t)slot;
+    const int4 t = d.wint[slot];
+    const int ida = t.x, sa = t.y, r = t.z;
+    const W4 wd = philox(step, (uint32_t)ida, id, rule_tag(d, r), d.seed);
+    bool keep = true;
+    if (d.wfa[slot]) {  // this T also won as the A of another pair
+      const int4 o = d.wina[slot];
+      const W4 wo = philox(step, id, (uint32_t)o.x, rule_tag(d, o.z), d.seed);
+      keep = key_less(((unsigned long long)wd.w3 << 32) | (uint32_t)ida, r,
+                      ((unsigned long long)wo.w3 << 32) | (uint32_t)o.x, o.z);
+    }
+    if (keep && d.wft[sa]) {  // the A also won as the T of another pair
+      const int4 o = d.wint[sa];
+      const W4 wo = philox(step, (uint32_t)o.x, (uint32_t)ida, rule_tag(d, o.z), d.seed);
+      keep = key_less(((unsigned long long)wd.w3 << 32) | id, r,
+                      ((unsigned long long)wo.w3 << 32) | (uint32_t)o.x, o.z);
+    }
+    if (keep) {
+      int32_t da, dt;
+      rule_deltas(d, r, da, dt);
+      make_bond_d(d, a, par, w, ida, sa, slot, (int)id, da, dt, (int)(id | ((uint32_t)r << 30)),
+                  bc);
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int32_t* out = pick(d.wgo, par) + w * kWgOut;
+    out[kOutBonds] = s_nw;
+    out[kOutLost] = s_lost;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Kinetics counters of the current configuration (the quantities of the
 // paper's rate equations, Sec. II B-C): populations of the A type by state,
 // and, per state of the A-eligible particles, their T-eligible partners
@@ -1525,8 +1803,15 @@ __global__ __launch_bounds__(kFinThreads) void k_single_sort(Dev d) {
   __syncthreads();
   if (m > 1) bitonic_sort(buf, n2);
   for (int t = threadIdx.x; t < m && t < d.bonds_cap; t += blockDim.x) {
-    d.bonds[2 * t] = (int32_t)(buf[t] >> 32);
-    d.bonds[2 * t + 1] = (int32_t)(uint32_t)buf[t];
+    if (d.bonds_rule) {  // (id_A, id_T, rule): the rule rides in bits 30-31 of id_T
+      const uint32_t tt = (uint32_t)buf[t];
+      d.bonds[3 * t] = (int32_t)(buf[t] >> 32);
+      d.bonds[3 * t + 1] = (int32_t)(d.nrules > 1 ? tt & 0x3FFFFFFFu : tt);
+      d.bonds[3 * t + 2] = (int32_t)(d.nrules > 1 ? tt >> 30 : 0u);
+    } else {
+      d.bonds[2 * t] = (int32_t)(buf[t] >> 32);
+      d.bonds[2 * t + 1] = (int32_t)(uint32_t)buf[t];
+    }
   }
 }
 
@@ -1556,7 +1841,7 @@ __device__ __forceinline__ int sort_bin(const Dev& d, float x, float y, float z,
   const int lx = min(max((int)floorf(__fsub_rn(ux, 0.5f)) - (bx * bs - 1), 0), bs);
   const int ly = min(max((int)floorf(__fsub_rn(uy, 0.5f)) - (by * bs - 1), 0), bs);
   const int lz = min(max((int)floorf(__fsub_rn(uz, 0.5f)) - (bz * bs - 1), 0), bs);
-  return b * d.nd + (role == kRoleA ? 0 : 1 + (lz * e + ly) * e + lx);
+  return b * d.nd + (role_is_a(role, d.nrules > 1) ? 0 : 1 + (lz * e + ly) * e + lx);
 }
 
 // Ranks within sort bins.  The storage is in bin order from the previous
@@ -1696,6 +1981,18 @@ __global__ __launch_bounds__(kThreads) void k_near_sweep(Dev d, int k) {
 }
 __global__ __launch_bounds__(kThreads) void k_near_resolve(Dev d, int k) {
   near_resolve_body(d, k, blockIdx.x, gridDim.x);
+}
+template <bool kBrick>
+__global__ __launch_bounds__(kThreads) void k_multi_sweep(Dev d, int k) {
+  multi_sweep_body<kBrick>(d, k, blockIdx.x, gridDim.x);
+}
+template <bool kBrick>
+__global__ __launch_bounds__(kThreads) void k_multi_resolve(Dev d, int k) {
+  multi_resolve_body<kBrick>(d, k, blockIdx.x);
+}
+template <bool kBrick>
+__global__ __launch_bounds__(kThreads) void k_multi_final(Dev d, int k) {
+  multi_final_body<kBrick>(d, k, blockIdx.x);
 }
 __global__ __launch_bounds__(kThreads) void k_sort_count(Dev d) {
   sort_count_body(d, blockIdx.x * blockDim.x + threadIdx.x);
@@ -1917,6 +2214,24 @@ hipError_t launch_step(const Dev& d, int k, hipStream_t s, hipEvent_t ev_sweep0,
   const int prep_blocks = d.nwg_prep + (k > 0 ? d.ngroups : 0);
   k_prep<<<prep_blocks, kThreads, 0, s>>>(d, k);
   const dim3 g(d.nwg_sweep), b(kThreads);
+  if (d.nrules > 1) {
+    if (d.sorted) {
+      if (ev_sweep0)
+        hipExtLaunchKernelGGL(k_multi_sweep<true>, g, b, 0, s, ev_sweep0, ev_sweep1, 0, d, k);
+      else
+        k_multi_sweep<true><<<g, b, 0, s>>>(d, k);
+      k_multi_resolve<true><<<g, b, 0, s>>>(d, k);
+      k_multi_final<true><<<g, b, 0, s>>>(d, k);
+    } else {
+      if (ev_sweep0)
+        hipExtLaunchKernelGGL(k_multi_sweep<false>, g, b, 0, s, ev_sweep0, ev_sweep1, 0, d, k);
+      else
+        k_multi_sweep<false><<<g, b, 0, s>>>(d, k);
+      k_multi_resolve<false><<<g, b, 0, s>>>(d, k);
+      k_multi_final<false><<<g, b, 0, s>>>(d, k);
+    }
+    return hipGetLastError();
+  }
   if (d.rule.policy == PR_POLICY_NEAREST) {
     if (d.sorted) {
       if (ev_sweep0)

@@ -607,6 +607,82 @@ def check_kinetics_poisson(lib, n=60000, L=30.0, frac=0.05, nbins=8):
 
 
 # --------------------------------------------------------------------------
+# several concurrent rules in one step (the extension of Sec. III B)
+# --------------------------------------------------------------------------
+def check_multi_one_rule_is_single(lib):
+    """With one rule the multi-rule step is the single-rule step, bit for bit."""
+    for kind, p, seed in (("step", 0.3, 41), ("chain", 0.8, 42), ("step", 1.0, 43)):
+        g = workload.generate(4000, 16.75, kind, seed)
+        if kind == "chain":
+            g["state"][np.random.default_rng(seed).choice(4000, 300, replace=False)] = 2
+        s = System(g["L"], g["x"], g["y"], g["z"], g["type"], g["state"], g["adj"])
+        r = Rule(**{k: v for k, v in workload.rule_for(kind, 1.12, p).items() if k != "policy"})
+        s1, s2 = s.copy(), s.copy()
+        c1, b1, st1 = oracle.react_step(s1, r, seed, 5, lib=lib)
+        c2, b2, st2 = oracle.react_step_multi(s2, [r], seed, 5, lib=lib)
+        assert c1 == c2 == 0 and np.array_equal(b1, b2[:, :2]) and np.all(b2[:, 2] == 0)
+        assert st1 == st2 and np.array_equal(s1.state, s2.state) and np.array_equal(s1.adj, s2.adj)
+        assert len(b1) > 0
+
+
+def _two_rule_system(copies=343, spacing=3.5):
+    """Isolated crosslinkers (type 1), each with one type-0 end at 0.7 (rule
+    0) and one type-2 end at 0.8 (rule 1) on the other side."""
+    m = int(math.ceil(copies ** (1 / 3)))
+    pts, types, states = [], [], []
+    for k in range(copies):
+        c = np.array([(k % m) + 0.5, ((k // m) % m) + 0.5, (k // (m * m)) + 0.5]) * spacing
+        pts += [tuple(c), tuple(c + [0.7, 0, 0]), tuple(c - [0.8, 0, 0])]
+        types += [1, 0, 2]
+        states += [4, 2, 2]
+    return mk(spacing * m, pts, types, states)
+
+
+def _rule01(p0, p1):
+    r0 = Rule(**STEP, rc=1.12, p=p0, exclude_bonded=1)
+    r1 = Rule(type_a=1, a_min=1, a_max=4, d_a=-1, type_t=2, t_min=1, t_max=2, d_t=-1, rc=1.12,
+              p=p1, exclude_bonded=1)
+    return r0, r1
+
+
+def check_multi_two_rates(lib, p0=0.2, p1=0.5, seeds=8):
+    """One crosslinker with a partner under each of two rules: it bonds with
+    probability 1 - (1 - p0)(1 - p1), by rule 0 with probability
+    p0 (1 - p1) + p0 p1 / 2 (both accepted: a uniform choice)."""
+    s = _two_rule_system()
+    n_rule = [0, 0]
+    trials = 0
+    for seed in range(seeds):
+        _, b, _ = oracle.react_step_multi(s.copy(), list(_rule01(p0, p1)), 500 + seed, 3, lib=lib)
+        for i, j, r in b.tolist():
+            assert (r == 0 and j == i + 1) or (r == 1 and j == i + 2), (i, j, r)
+            n_rule[r] += 1
+        trials += s.n // 3
+    for obs, q in ((sum(n_rule), 1 - (1 - p0) * (1 - p1)), (n_rule[0], p0 * (1 - p1) + p0 * p1 / 2)):
+        sd = math.sqrt(q * (1 - q) / trials)
+        assert abs(obs / trials - q) < 4.5 * sd, (obs / trials, q)
+
+
+def check_multi_cross_role(lib, seeds=600):
+    """A particle that is the T of rule 0 (an end unit, state 2) and the A of
+    rule 1 (ends in state 2 bond type-2 units): with a crosslinker and a
+    type-2 unit next to it (p = 1) it wins as both; step 8 keeps one of its
+    two pairs, each with frequency 1/2, so exactly one bond forms."""
+    r0 = Rule(**STEP, rc=1.12, p=1.0, exclude_bonded=1)
+    r1 = Rule(type_a=0, a_min=2, a_max=2, d_a=-1, type_t=2, t_min=0, t_max=0, d_t=1, rc=1.12, p=1.0,
+              exclude_bonded=1)
+    s = mk(10.0, [(5.0, 5, 5), (5.8, 5, 5), (6.6, 5, 5)], [1, 0, 2], [4, 2, 0])
+    first = 0
+    for seed in range(seeds):
+        _, b, st = oracle.react_step_multi(s.copy(), [r0, r1], seed, 1, lib=lib)
+        assert len(b) == 1, b
+        first += b[0].tolist() == [0, 1, 0]
+        assert b[0].tolist() in ([0, 1, 0], [1, 2, 1]), b
+    sd = math.sqrt(0.25 / seeds)
+    assert abs(first / seeds - 0.5) < 4.5 * sd, first
+
+
+# --------------------------------------------------------------------------
 # FP64 recheck of the cutoff decision (diagnostic; the step decides in FP32)
 # --------------------------------------------------------------------------
 RC32 = float(np.float32(1.12))  # the cutoff as the FP32 value both sides use
@@ -699,4 +775,5 @@ ALL = [check_pair_distance, check_periodic, check_cutoff_strict, check_p0_p1, ch
        check_jitter_distribution, check_generator_offsets, check_jitter_wrap,
        check_near_cutoff, check_near_cutoff_disagree, check_nearest_picks_closest,
        check_nearest_mutual, check_nearest_tie_lower_id, check_nearest_probability,
-       check_nearest_exclusion_first, check_kinetics_hand, check_kinetics_poisson]
+       check_nearest_exclusion_first, check_kinetics_hand, check_kinetics_poisson,
+       check_multi_one_rule_is_single, check_multi_two_rates, check_multi_cross_role]
