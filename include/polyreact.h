@@ -251,6 +251,34 @@ int pr_sys_run_timed(pr_sys* s, uint32_t first_step, uint32_t n_steps, double si
  * sorts, cached by shape.  No effect when graphs are off.  Synchronous. */
 int pr_sys_prepare(pr_sys* s, uint32_t n_steps, double sigma);
 
+/* Bonded-force coupling: instead of the re-jitter, every reaction step of
+ * pr_sys_run is preceded by theta steps of velocity-Verlet MD (time step dt,
+ * unit masses) under the mirror Lennard-Jones bond potential of every bond in
+ * the adjacency table (Sec. II D, Eq. (mirror LJ)):
+ *   V_b(r) = 4 eps ((sig / (2 sc - r))^12 - (sig / (2 sc - r))^6 + 1/4) for
+ *   sc < r < 2 sc, sc = 2^(1/6) sig, and 0 below sc,
+ * and no other force.  Bonds are made at r < rc <= sc, where V_b vanishes,
+ * so a reaction step adds no energy (the paper's thermoneutral bonding).
+ * FP32 arithmetic in a fixed order (forces in adjacency-row order; per MD
+ * step v += (dt/2) F, x = wrap(x + dt v), F = F(x), v += (dt/2) F).
+ * Velocities are (re)initialised at temperature temp: per component an
+ * Irwin-Hall(4) offset of the bytes of word d of the Philox block (0, id,
+ * 0, 6) under vseed, times fl32(sqrt(temp / 21845)).  pr_sys_run then needs
+ * sigma = 0.  theta = 0 switches back to the re-jitter.  A bond stretched to
+ * 2 sc or beyond is reported as PR_EINVAL by the next synchronising call.
+ * Call after pr_sys_load / pr_sys_generate.  Synchronises. */
+int pr_sys_set_md(pr_sys* s, int32_t theta, double dt, double sig, double eps, double temp,
+                  uint64_t vseed);
+
+/* The bonded-force kernel's FP32 square root (correctly rounded, as IEEE
+ * sqrt) on n device values, each positive and normal (others: unspecified).
+ * in, out: device arrays (may be equal); 0 <= n <= 2^30.  Asynchronous. */
+int pr_sqrt_rn(const float* in, float* out, int64_t n, void* stream);
+
+/* Velocities in particle-id order (host arrays of n floats; PR_EINVAL when
+ * pr_sys_set_md was never called).  Synchronises. */
+int pr_sys_read_velocities(pr_sys* s, float* vx, float* vy, float* vz);
+
 /* The re-jitter alone for steps first_step .. first_step + n_steps - 1: every
  * particle moves exactly as the re-jitter of pr_sys_run's steps would move it
  * (the stand-in for the MD integration between reaction steps), and no

@@ -75,6 +75,18 @@ def _declare(lib):
     lib.or_run_multi.restype = C.c_int
     lib.or_rule_tag.argtypes = [i32]
     lib.or_rule_tag.restype = u32
+    lib.or_md_block.argtypes = [i32, f32, P(f32), P(f32), P(f32), P(f32), P(f32), P(f32), P(i32),
+                                i32, f64, f64, f64, i32]
+    lib.or_md_block.restype = C.c_int
+    lib.or_md_energy.argtypes = [i32, f32, P(f32), P(f32), P(f32), P(f32), P(f32), P(f32), P(i32),
+                                 i32, f64, f64]
+    lib.or_md_energy.restype = C.c_double
+    lib.or_md_velocities.argtypes = [i32, P(f32), P(f32), P(f32), u64, f64]
+    lib.or_md_velocities.restype = None
+    lib.or_run_md.argtypes = [i32, f32, P(f32), P(f32), P(f32), P(f32), P(f32), P(f32), P(i32),
+                              P(i32), P(i32), i32, *rule, u64, u32, u32, f64, f64, f64, i32,
+                              P(i32), i64, P(i64), P(i64)]
+    lib.or_run_md.restype = C.c_int
     lib.or_kinetics.argtypes = [i32, f32, P(f32), P(f32), P(f32), P(i32), P(i32), P(i32), i32,
                                 i32, i32, i32, i32, i32, i32, f32, i32, i32, P(i64), P(i64), i32,
                                 P(i64)]
@@ -293,6 +305,52 @@ def run_multi(sysm, rules, seed, first_step, n_steps, sigma, log_cap=None, lib=N
     return code, log[: min(nl.value, log_cap)].copy(), st[:n_steps]
 
 
+class MD:
+    """Velocities of a System for the bonded-force coupling (FP32 arrays)."""
+
+    def __init__(self, n, seed=None, temp=1.0, lib=None):
+        self.vx = np.zeros(n, np.float32)
+        self.vy = np.zeros(n, np.float32)
+        self.vz = np.zeros(n, np.float32)
+        if seed is not None:
+            (lib or load()).or_md_velocities(n, _p(self.vx, C.c_float), _p(self.vy, C.c_float),
+                                             _p(self.vz, C.c_float), C.c_uint64(seed), float(temp))
+
+    def _v(self):
+        return _p(self.vx, C.c_float), _p(self.vy, C.c_float), _p(self.vz, C.c_float)
+
+
+def md_block(sysm, md, theta, dt=0.0025, sig=1.0, eps=1.0, lib=None):
+    lib = lib or load()
+    return lib.or_md_block(sysm.n, C.c_float(sysm.L), _p(sysm.x, C.c_float), _p(sysm.y, C.c_float),
+                           _p(sysm.z, C.c_float), *md._v(), _p(sysm.adj, C.c_int32), sysm.B,
+                           float(dt), float(sig), float(eps), int(theta))
+
+
+def md_energy(sysm, md, sig=1.0, eps=1.0, lib=None):
+    lib = lib or load()
+    return lib.or_md_energy(sysm.n, C.c_float(sysm.L), _p(sysm.x, C.c_float),
+                            _p(sysm.y, C.c_float), _p(sysm.z, C.c_float), *md._v(),
+                            _p(sysm.adj, C.c_int32), sysm.B, float(sig), float(eps))
+
+
+def run_md(sysm, md, rule, seed, first_step, n_steps, theta, dt=0.0025, sig=1.0, eps=1.0,
+           log_cap=None, lib=None):
+    """Reaction steps with theta MD steps before each; (code, log, stats)."""
+    lib = lib or load()
+    log_cap = log_cap or max(16, sysm.n * 4)
+    log = np.empty((log_cap, 3), np.int32)
+    nl = C.c_int64(0)
+    st = np.zeros((max(n_steps, 1), ST_COUNT), np.int64)
+    code = lib.or_run_md(sysm.n, C.c_float(sysm.L), _p(sysm.x, C.c_float), _p(sysm.y, C.c_float),
+                         _p(sysm.z, C.c_float), *md._v(), _p(sysm.type, C.c_int32),
+                         _p(sysm.state, C.c_int32), _p(sysm.adj, C.c_int32), sysm.B,
+                         *rule.args(), C.c_uint64(seed), C.c_uint32(first_step),
+                         C.c_uint32(n_steps), float(dt), float(sig), float(eps), int(theta),
+                         _p(log, C.c_int32), log_cap, C.byref(nl), _p(st, C.c_int64))
+    return code, log[: min(nl.value, log_cap)].copy(), st[:n_steps]
+
+
 def kinetics(sysm, rule, nstate=8, nbins=16, lib=None):
     """Kinetics counters of the configuration: (pop[nstate], pairs[nstate],
     hist[nbins]) as numpy int64 arrays (see or_kinetics)."""
@@ -319,6 +377,7 @@ def num_threads(lib=None):
 
 
 __all__ = ["Rule", "System", "react_step", "run", "jitter", "philox", "threshold", "near_cutoff",
-           "kinetics", "kin_edge2", "react_step_multi", "run_multi",
+           "kinetics", "kin_edge2", "react_step_multi", "run_multi", "MD", "md_block",
+           "md_energy", "run_md",
            "sample_bonds",
            "ih12_offsets", "ih4_offsets", "jitter_scale", "ST_NAMES", "load", "num_threads"]

@@ -600,6 +600,9 @@ int or_react_step_nearest(int32_t n, float L, const float* x, const float* y, co
 /* ----------------------------------------------------------------------- */
 #define OR_MAX_RULES 4
 
+static float wrap_box(float v, float L);
+void or_ih4_offsets(uint32_t step, uint32_t id, uint32_t tag, uint64_t seed, int32_t S[3]);
+
 void or_jitter(int32_t n, float L, float* x, float* y, float* z, uint64_t seed, uint32_t step,
                double sigma);
 
@@ -1030,6 +1033,192 @@ int or_kinetics(int32_t n, float L, const float* x, const float* y, const float*
   }
   free(alist); free(is_t); free(e2);
   return OR_OK;
+}
+
+/* ----------------------------------------------------------------------- */
+/* Bonded-force coupling: velocity-Verlet MD with the mirror Lennard-Jones   */
+/* bond potential (Sec. II D, Eq. (mirror LJ); Ref. Akkermans et al.):       */
+/*   V_b(r) = 4 eps ((sig/(2 sc - r))^12 - (sig/(2 sc - r))^6 + 1/4)         */
+/*   for sc < r < 2 sc, 0 otherwise (sc = 2^(1/6) sig, the LJ cutoff),       */
+/* over every bond of the adjacency table; unit masses; no other force (the  */
+/* minimal loop that moves particles between reaction steps instead of the  */
+/* re-jitter).  Bonds are made at r < rc = 1.12 < sc, where V_b and its      */
+/* force vanish: bonding adds no energy (the paper's thermoneutral          */
+/* reaction), and the total energy is conserved by the integrator.          */
+/* FP32 contract (identical on the device): for the bond (i, j) at i,       */
+/*   d = min_image(x_j - x_i) per component, r2 = (dx dx + dy dy) + dz dz;  */
+/*   if r2 > sc^2 (FP32 of the double product):                             */
+/*     r = sqrt(r2), s = 2sc - r, q = sig / s, q2 = q q, q6 = (q2 q2) q2,   */
+/*     q12 = q6 q6, c = ((24 eps) ((q12 + q12) - q6) / s) / r,              */
+/*     F_i += c d (component-wise, bonds in adjacency-row order);           */
+/*   r >= 2 sc (a bond torn apart) is an error.                             */
+/* One MD step: v += h F; x = wrap(x + dt v); F = F(x); v += h F, with     */
+/* h = fl32(dt / 2), each particle's forces taken from the positions of the */
+/* same instant.                                                            */
+/* ----------------------------------------------------------------------- */
+typedef struct {
+  float dt, h, sc, sc2, two_sc, sig, e24;
+} or_md;
+
+static or_md md_params(double dt, double sig, double eps) {
+  or_md m;
+  m.dt = (float)dt;
+  m.h = (float)(0.5 * dt);
+  m.sc = (float)(pow(2.0, 1.0 / 6.0) * sig);
+  m.sc2 = (float)((double)m.sc * (double)m.sc);
+  m.two_sc = (float)(2.0 * (double)m.sc);
+  m.sig = (float)sig;
+  m.e24 = (float)(24.0 * eps);
+  return m;
+}
+
+/* forces on every particle from its bonds (rows of adj, -1 = empty) */
+static int md_forces(int32_t n, float L, const float* x, const float* y, const float* z,
+                     const int32_t* adj, int32_t B, const or_md* m, float* fx, float* fy,
+                     float* fz) {
+  const float halfL = 0.5f * L;
+  int torn = 0;
+#pragma omp parallel for schedule(static) reduction(| : torn)
+  for (int64_t i = 0; i < n; ++i) {
+    float ax = 0.0f, ay = 0.0f, az = 0.0f;
+    for (int32_t b = 0; b < B; ++b) {
+      const int32_t j = adj[i * B + b];
+      if (j < 0) continue;
+      const float dx = min_image(x[j] - x[i], L, halfL);
+      const float dy = min_image(y[j] - y[i], L, halfL);
+      const float dz = min_image(z[j] - z[i], L, halfL);
+      const float r2 = (dx * dx + dy * dy) + dz * dz;
+      if (!(r2 > m->sc2)) continue;                 /* V_b = 0 up to sc */
+      const float r = sqrtf(r2);
+      const float sgap = m->two_sc - r;
+      if (!(sgap > 0.0f)) { torn = 1; continue; }
+      const float q = m->sig / sgap;
+      const float q2 = q * q;
+      const float q6 = (q2 * q2) * q2;
+      const float q12 = q6 * q6;
+#if OR_MUTANT == 22 /* mutant: repulsive sign */
+      const float c = -((m->e24 * ((q12 + q12) - q6)) / sgap) / r;
+#else
+      const float c = ((m->e24 * ((q12 + q12) - q6)) / sgap) / r;
+#endif
+      ax = ax + c * dx;
+      ay = ay + c * dy;
+      az = az + c * dz;
+    }
+    fx[i] = ax;
+    fy[i] = ay;
+    fz[i] = az;
+  }
+  return torn ? OR_EINVAL : OR_OK;
+}
+
+/* theta MD steps (velocity Verlet) in place. */
+int or_md_block(int32_t n, float L, float* x, float* y, float* z, float* vx, float* vy,
+                float* vz, const int32_t* adj, int32_t B, double dt, double sig, double eps,
+                int32_t theta) {
+  const or_md m = md_params(dt, sig, eps);
+  const size_t nn = (size_t)(n > 0 ? n : 1);
+  float* f = (float*)malloc(sizeof(float) * 3 * nn);
+  if (!f) return OR_ENOMEM;
+  float *fx = f, *fy = f + nn, *fz = f + 2 * nn;
+  int e = md_forces(n, L, x, y, z, adj, B, &m, fx, fy, fz);
+  for (int32_t k = 0; k < theta && !e; ++k) {
+    for (int64_t i = 0; i < n; ++i) {
+      vx[i] = vx[i] + m.h * fx[i];
+      vy[i] = vy[i] + m.h * fy[i];
+      vz[i] = vz[i] + m.h * fz[i];
+      x[i] = wrap_box(x[i] + m.dt * vx[i], L);
+      y[i] = wrap_box(y[i] + m.dt * vy[i], L);
+      z[i] = wrap_box(z[i] + m.dt * vz[i], L);
+    }
+    e = md_forces(n, L, x, y, z, adj, B, &m, fx, fy, fz);
+    for (int64_t i = 0; i < n; ++i) {
+      vx[i] = vx[i] + m.h * fx[i];
+      vy[i] = vy[i] + m.h * fy[i];
+      vz[i] = vz[i] + m.h * fz[i];
+    }
+  }
+  free(f);
+  return e;
+}
+
+/* Total energy in FP64 from the FP32 state: sum v^2 / 2 + sum over bonds
+ * (each once) of V_b(r). */
+double or_md_energy(int32_t n, float L, const float* x, const float* y, const float* z,
+                    const float* vx, const float* vy, const float* vz, const int32_t* adj,
+                    int32_t B, double sig, double eps) {
+  const double sc = pow(2.0, 1.0 / 6.0) * sig, Ld = L, hl = 0.5 * Ld;
+  double e = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    e += 0.5 * ((double)vx[i] * vx[i] + (double)vy[i] * vy[i] + (double)vz[i] * vz[i]);
+    for (int32_t b = 0; b < B; ++b) {
+      const int32_t j = adj[i * B + b];
+      if (j <= i) continue;
+      double d[3] = {(double)x[j] - x[i], (double)y[j] - y[i], (double)z[j] - z[i]};
+      double r2 = 0.0;
+      for (int c = 0; c < 3; ++c) {
+        if (d[c] > hl) d[c] -= Ld;
+        else if (d[c] < -hl) d[c] += Ld;
+        r2 += d[c] * d[c];
+      }
+      const double r = sqrt(r2);
+      if (r <= sc) continue;
+      const double q = sig / (2.0 * sc - r), q6 = pow(q, 6.0);
+      e += 4.0 * eps * (q6 * q6 - q6 + 0.25);
+    }
+  }
+  return e;
+}
+
+/* Initial velocities at temperature temp (unit mass): per component an
+ * Irwin-Hall(4) offset of the bytes of word d of the Philox block (0, id, 0,
+ * 6) times fl32(sqrt(temp / 21845)) (unit variance per offset). */
+void or_md_velocities(int32_t n, float* vx, float* vy, float* vz, uint64_t seed, double temp) {
+  const float c = (float)sqrt(temp / 21845.0);
+  for (int64_t i = 0; i < n; ++i) {
+    int32_t S[3];
+    or_ih4_offsets(0u, (uint32_t)i, 6u, seed, S);
+    vx[i] = (float)S[0] * c;
+    vy[i] = (float)S[1] * c;
+    vz[i] = (float)S[2] * c;
+  }
+}
+
+/* Reaction steps with the MD in between: step s runs theta MD steps and
+ * then the reaction step s (random selection).  Log rows (step, id_A, id_T). */
+int or_run_md(int32_t n, float L, float* x, float* y, float* z, float* vx, float* vy, float* vz,
+              const int32_t* type, int32_t* state, int32_t* adj, int32_t B,
+              int32_t type_a, int32_t a_min, int32_t a_max, int32_t d_a,
+              int32_t type_t, int32_t t_min, int32_t t_max, int32_t d_t,
+              float rc, double p, int32_t exclude_bonded, uint64_t seed,
+              uint32_t first_step, uint32_t n_steps, double dt, double sig, double eps,
+              int32_t theta, int32_t* log, int64_t log_cap, int64_t* n_log,
+              int64_t* stats_per_step) {
+  int32_t* sb = (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)(n / 2 + 1));
+  if (!sb) return OR_ENOMEM;
+  int64_t total = 0;
+  int code = OR_OK;
+  for (uint32_t k = 0; k < n_steps; ++k) {
+    const uint32_t st = first_step + k;
+    int e = or_md_block(n, L, x, y, z, vx, vy, vz, adj, B, dt, sig, eps, theta);
+    if (e) { code = e; break; }
+    int64_t nb = 0;
+    e = or_react_step(n, L, x, y, z, type, state, adj, B, type_a, a_min, a_max, d_a, type_t,
+                      t_min, t_max, d_t, rc, p, exclude_bonded, seed, st, sb, n / 2 + 1, &nb,
+                      stats_per_step ? stats_per_step + (int64_t)k * ST_COUNT : NULL);
+    if (e != OR_OK && e != OR_ECAP) { code = e; break; }
+    if (e == OR_ECAP) code = OR_ECAP;
+    for (int64_t b = 0; b < nb; ++b, ++total)
+      if (total < log_cap) {
+        log[3 * total] = (int32_t)st;
+        log[3 * total + 1] = sb[2 * b];
+        log[3 * total + 2] = sb[2 * b + 1];
+      }
+  }
+  *n_log = total;
+  free(sb);
+  if (code == OR_OK && total > log_cap) return OR_ECAP;
+  return code;
 }
 
 /* ----------------------------------------------------------------------- */

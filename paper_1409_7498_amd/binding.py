@@ -97,6 +97,9 @@ def _load():
         "pr_sys_jitter": ([vp, u32, u32, f64, P(f32)], C.c_int),
         "pr_stream_copy": ([vp, vp, i64, i32, vp, P(f32)], C.c_int),
         "pr_sys_kinetics": ([vp, i32, vp, vp, i32, vp], C.c_int),
+        "pr_sys_set_md": ([vp, i32, f64, f64, f64, f64, u64], C.c_int),
+        "pr_sys_read_velocities": ([vp, vp, vp, vp], C.c_int),
+        "pr_sqrt_rn": ([vp, vp, i64, vp], C.c_int),
         "pr_react_step_multi": ([i32, f32, vp, vp, vp, vp, vp, vp, i32, vp, i32, u64, u32, vp, i32,
                                  P(i32), P(Stats), vp], C.c_int),
         "pr_sys_create_multi": ([P(vp), i32, f32, i32, vp, i32, u64, i64, vp, i32], C.c_int),
@@ -158,7 +161,8 @@ def exported_symbols():
                         "pr_sys_restore", "pr_p_from_rate", "pr_draws", "pr_server_poll",
                         "pr_server_cancel", "pr_autotune_cached", "pr_sys_prepare",
                         "pr_sys_jitter", "pr_stream_copy", "pr_sys_kinetics",
-                        "pr_batch_kinetics", "pr_react_step_multi", "pr_sys_create_multi")]
+                        "pr_batch_kinetics", "pr_react_step_multi", "pr_sys_create_multi",
+                        "pr_sys_set_md", "pr_sys_read_velocities", "pr_sqrt_rn")]
 
 
 def _check(code):
@@ -310,6 +314,17 @@ class System:
         int64 arrays (see pr_sys_kinetics)."""
         return _kinetics(lambda *a: lib.pr_sys_kinetics(self._h, *a), nstate, nbins)
 
+    def set_md(self, theta, dt=0.0025, sig=1.0, eps=1.0, temp=1.0, vseed=0):
+        """Velocity-Verlet MD with the mirror-LJ bond force, theta steps
+        before each reaction step (theta = 0: back to the re-jitter)."""
+        _check(lib.pr_sys_set_md(self._h, int(theta), float(dt), float(sig), float(eps),
+                                 float(temp), C.c_uint64(vseed)))
+
+    def velocities(self):
+        v = [np.empty(self.n, np.float32) for _ in range(3)]
+        _check(lib.pr_sys_read_velocities(self._h, *[a.ctypes.data_as(C.c_void_p) for a in v]))
+        return v
+
     def set_sort_period(self, k):
         _check(lib.pr_sys_set_sort_period(self._h, int(k)))
 
@@ -376,6 +391,13 @@ def draws(ctr, key, stream=None):
     out = torch.empty_like(ctr)
     _check(lib.pr_draws(_ptr(ctr), ctr.shape[0], C.c_uint64(int(key)), _ptr(out),
                         _stream(stream)))
+    return out
+
+
+def sqrt_rn(t, stream=None):
+    """The bonded-force kernel's square root of a float32 device tensor."""
+    out = t.new_empty(t.shape)
+    _check(lib.pr_sqrt_rn(_ptr(t), _ptr(out), t.numel(), _stream(stream)))
     return out
 
 

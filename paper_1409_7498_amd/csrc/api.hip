@@ -42,6 +42,9 @@ hipError_t launch_gather_out(const Dev& d, float* ox, float* oy, float* oz, int3
 hipError_t launch_draws(const uint32_t* ctr, long long n, unsigned long long key, uint32_t* out,
                         hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, long long n, uint32_t v, hipStream_t s);
+hipError_t launch_md_init(const Dev& d, unsigned long long vseed, float cv, hipStream_t s);
+hipError_t launch_sqrt_rn(const float* in, float* out, long long n, hipStream_t s);
+hipError_t launch_gather_v(const Dev& d, float* ox, float* oy, float* oz, hipStream_t s);
 hipError_t launch_kinetics(const Dev& d, int nstate, int nbins, const float* e2,
                            unsigned long long* pop, unsigned long long* pairs,
                            unsigned long long* hist, hipStream_t s);
@@ -989,6 +992,8 @@ static int run_impl(pr_sys* s, uint32_t first_step, uint32_t n_steps, double sig
   if (e) return e;
   if (!(sigma >= 0.0) || sigma * 6.0 >= (double)s->d.L * 0.5)
     return fail(PR_EINVAL, "sigma=%g", sigma);
+  if (s->d.md_theta > 0 && sigma != 0.0)
+    return fail(PR_EINVAL, "the MD of pr_sys_set_md moves the particles: sigma must be 0");
   if ((e = grow_part(s, s->steps_since_load + n_steps))) return e;
   s->d.jit_c = (float)(sigma / std::sqrt(21845.0));  // unit-variance offsets
   hipStream_t st = s->stream;
@@ -1095,6 +1100,67 @@ int pr_sys_prepare(pr_sys* s, uint32_t n_steps, double sigma) {
   return e;
 }
 
+int pr_sys_set_md(pr_sys* s, int32_t theta, double dt, double sig, double eps, double temp,
+                  uint64_t vseed) {
+  int e = check_sys(s, true);
+  if (e) return e;
+  if (theta < 0 || theta > 100000) return fail(PR_EINVAL, "theta=%d", theta);
+  drop_graph(s);
+  Dev& d = s->d;
+  if (theta == 0) {
+    d.md_theta = 0;
+    return PR_OK;
+  }
+  if (!(dt > 0.0) || !(sig > 0.0) || !(eps >= 0.0) || !(temp >= 0.0) ||
+      !(2.0 * std::pow(2.0, 1.0 / 6.0) * sig < 0.5 * (double)d.L))
+    return fail(PR_EINVAL, "dt=%g sig=%g eps=%g temp=%g", dt, sig, eps, temp);
+  const size_t n = (size_t)d.n;
+  if (!d.slot_of) {
+    for (int q = 0; q < 2 && !e; ++q) {
+      Arr& a = d.set[q];
+      if (!e) e = s->arena.alloc(&a.vx, n);
+      if (!e) e = s->arena.alloc(&a.vy, n);
+      if (!e) e = s->arena.alloc(&a.vz, n);
+    }
+    if (!e) e = s->arena.alloc(&d.slot_of, n);
+    if (e) {
+      for (int q = 0; q < 2; ++q) d.set[q].vx = d.set[q].vy = d.set[q].vz = nullptr;
+      d.slot_of = nullptr;
+      return e;
+    }
+  }
+  // the oracle's parameters, rounded to FP32 from double
+  const double sc = std::pow(2.0, 1.0 / 6.0) * sig;
+  d.md_theta = theta;
+  d.md_dt = (float)dt;
+  d.md_h = (float)(0.5 * dt);
+  const float scf = (float)sc;
+  d.md_sc2 = (float)((double)scf * (double)scf);
+  d.md_two_sc = (float)(2.0 * (double)scf);
+  d.md_sig = (float)sig;
+  d.md_e24 = (float)(24.0 * eps);
+  const float cv = (float)std::sqrt(temp / 21845.0);
+  HIP_TRY(launch_md_init(d, (unsigned long long)vseed, cv, s->stream));
+  return sync_ctl(s);
+}
+
+int pr_sys_read_velocities(pr_sys* s, float* vx, float* vy, float* vz) {
+  int e = check_sys(s, true);
+  if (e) return e;
+  if (!s->d.slot_of) return fail(PR_EINVAL, "no velocities: pr_sys_set_md was not called");
+  if (!vx || !vy || !vz) return fail(PR_EINVAL, "NULL output");
+  const size_t n = (size_t)s->d.n;
+  float* buf = nullptr;
+  if ((e = s->arena.alloc(&buf, 3 * n))) return e;  // kept in the arena until destroy
+  HIP_TRY(launch_gather_v(s->d, buf, buf + n, buf + 2 * n, s->stream));
+  HIP_TRY(hipMemcpyAsync(vx, buf, n * 4, hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipMemcpyAsync(vy, buf + n, n * 4, hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipMemcpyAsync(vz, buf + 2 * n, n * 4, hipMemcpyDeviceToHost, s->stream));
+  if ((e = sync_ctl(s))) return e;
+  if (s->hctl->err) return fail(s->hctl->err, "device error during the run");
+  return PR_OK;
+}
+
 int pr_sys_jitter(pr_sys* s, uint32_t first_step, uint32_t n_steps, double sigma,
                   float* kernel_ms) {
   int e = check_sys(s, true);
@@ -1169,6 +1235,13 @@ int pr_sys_kinetics(pr_sys* s, int32_t nstate, int64_t* pop, int64_t* pairs, int
     pairs[q] = (int64_t)h[(size_t)(kKinMaxState + q)];
   }
   for (int b = 0; b < nbins; ++b) hist[b] = (int64_t)h[(size_t)(2 * kKinMaxState + b)];
+  return PR_OK;
+}
+
+int pr_sqrt_rn(const float* in, float* out, int64_t n, void* stream) {
+  if (n < 0 || n > (int64_t)kMaxParticles) return fail(PR_EINVAL, "n=%lld", (long long)n);
+  if (n > 0 && (!in || !out)) return fail(PR_EINVAL, "NULL array");
+  HIP_TRY(launch_sqrt_rn(in, out, (long long)n, (hipStream_t)stream));
   return PR_OK;
 }
 
@@ -1374,6 +1447,7 @@ int pr_sys_checkpoint(pr_sys* s, void* buf, int64_t cap, int64_t* bytes) {
   int e = check_sys(s, true);
   if (e) return e;
   if (s->d.nrules > 1) return fail(PR_EINVAL, "checkpoints hold one rule");
+  if (s->d.md_theta > 0) return fail(PR_EINVAL, "checkpoints hold no velocities");
   if (!bytes) return fail(PR_EINVAL, "bytes is NULL");
   if ((e = sync_ctl(s))) return e;
   if (s->hctl->err) return fail(s->hctl->err, "device error during the run");

@@ -84,6 +84,7 @@ struct Arr {
   float *x[2], *y[2], *z[2];
   int32_t *typ, *st, *adj, *id;  // id == nullptr: slot == id
   uint8_t* role;                 // kRoleT / kRoleA / 0 from (type, state) and the rule
+  float *vx, *vy, *vz;           // velocities (bonded-force coupling only; else null)
 };
 
 enum Role : uint8_t { kRoleNone = 0, kRoleT = 1, kRoleA = 2 };
@@ -151,6 +152,12 @@ struct Dev {
   int32_t nrules;
   RuleX mr[kMaxRules];
   uint8_t *wfa, *wft;   // per slot: won as an A / as a T in this step (one writer each)
+  // bonded-force coupling (md_theta > 0): md_theta velocity-Verlet steps with
+  // the mirror-LJ bond force before each reaction step, instead of the
+  // re-jitter; slot_of maps ids to slots of the current storage set
+  int32_t md_theta;
+  float md_dt, md_h, md_sc2, md_two_sc, md_sig, md_e24;
+  int32_t* slot_of;
   int4 *wina, *wint;    // per slot, the winning pair as A / as T:
                         // (partner id, partner slot, rule, 0)
 };

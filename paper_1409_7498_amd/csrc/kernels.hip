@@ -102,6 +102,23 @@ __device__ __forceinline__ void ih4(uint32_t step, uint32_t id, uint32_t tag,
   S[2] = (int32_t)byte_sum(a.w2, kMinus510);
 }
 
+// Correctly rounded FP32 square root of a positive normal x: the hardware
+// estimate (within one ulp) is moved one ulp down or up when x lies beyond
+// the midpoint to that neighbour; the residuals x - s_dn * s and x - s_up * s
+// are each rounded once by the fused multiply-add, and their signs decide
+// exactly (s_dn * s and s_up * s are the midpoints' squares up to a term below
+// the rounding of x).
+__device__ __forceinline__ float sqrt_rn(float x) {
+  float s = __builtin_amdgcn_sqrtf(x);
+  const float s_dn = __uint_as_float(__float_as_uint(s) - 1u);
+  const float s_up = __uint_as_float(__float_as_uint(s) + 1u);
+  const float v_dn = __builtin_fmaf(-s_dn, s, x);
+  const float v_up = __builtin_fmaf(-s_up, s, x);
+  s = v_dn <= 0.0f ? s_dn : s;
+  s = v_up > 0.0f ? s_up : s;
+  return s;
+}
+
 __device__ __forceinline__ float wrap_box(float v, float L) {
   if (v < 0.0f) v = __fadd_rn(v, L);
   if (v >= L) v = __fsub_rn(v, L);
@@ -190,6 +207,9 @@ __device__ __forceinline__ Arr pick_set(const Dev& d, uint32_t s) {
   r.adj = pick({u.adj, v.adj}, s);
   r.id = pick({u.id, v.id}, s);
   r.role = pick({u.role, v.role}, s);
+  r.vx = pick({u.vx, v.vx}, s);
+  r.vy = pick({u.vy, v.vy}, s);
+  r.vz = pick({u.vz, v.vz}, s);
   return r;
 }
 
@@ -286,6 +306,7 @@ __global__ __launch_bounds__(kThreads) void k_identity(Dev d) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= d.n) return;
   if (pick_set(d, 0).id) pick_set(d, 0).id[k] = k;
+  if (d.slot_of) d.slot_of[k] = k;
   d.tflag[k] = 0;
 }
 
@@ -1690,6 +1711,113 @@ __device__ __forceinline__ void multi_final_body(const Dev& d, int k, int w) {
 }
 
 // ---------------------------------------------------------------------------
+// Bonded-force coupling: velocity Verlet with the mirror-LJ bond force over
+// the adjacency table (Sec. II D, Eq. (mirror LJ)), md_theta steps before each
+// reaction step.  Kernel m = 0 .. theta of reaction step k of a block: the
+// forces at the positions of parity (par0 + k + m) (partners found through
+// slot_of); m = 0 kicks half a step and drifts, 0 < m < theta completes the
+// previous step's second half kick, kicks and drifts, m = theta completes
+// the last one.  Drifted positions go to the other parity; for odd theta the
+// last kernel copies the positions over once more, so that every MD block
+// flips the buffers an even number of times and the reaction step finds them
+// in the parity its step number gives.  Every operation is FP32, rounded on
+// its own, in the order the oracle uses.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_md(Dev d, int k, int m) {
+  const Ctl* c = d.ctl;
+  const uint32_t par = (c->par0 + (uint32_t)k + (uint32_t)m) & 1u;
+  const Arr a = pick_set(d, c->set & 1u);
+  const float *X = pick(a.x, par), *Y = pick(a.y, par), *Z = pick(a.z, par);
+  float *XW = pick(a.x, par ^ 1u), *YW = pick(a.y, par ^ 1u), *ZW = pick(a.z, par ^ 1u);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.n || read_err(c)) return;
+  const float xi = X[i], yi = Y[i], zi = Z[i];
+  float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+  bool torn = false;
+  const int32_t* row = a.adj + (size_t)i * d.B;
+  for (int b = 0; b < d.B; ++b) {
+    const int32_t j = row[b];
+    if (j < 0) continue;
+    const int sj = d.slot_of[j];
+    const float dx = min_image(__fsub_rn(X[sj], xi), d.L, d.halfL);
+    const float dy = min_image(__fsub_rn(Y[sj], yi), d.L, d.halfL);
+    const float dz = min_image(__fsub_rn(Z[sj], zi), d.L, d.halfL);
+    const float r2 = __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz));
+    if (!(r2 > d.md_sc2)) continue;  // no force up to sigma_c
+    const float r = sqrt_rn(r2);
+    const float sgap = __fsub_rn(d.md_two_sc, r);
+    if (!(sgap > 0.0f)) {
+      torn = true;
+      continue;
+    }
+    const float q = __fdiv_rn(d.md_sig, sgap);
+    const float q2 = __fmul_rn(q, q);
+    const float q6 = __fmul_rn(__fmul_rn(q2, q2), q2);
+    const float q12 = __fmul_rn(q6, q6);
+    const float cf =
+        __fdiv_rn(__fdiv_rn(__fmul_rn(d.md_e24, __fsub_rn(__fadd_rn(q12, q12), q6)), sgap), r);
+    fx = __fadd_rn(fx, __fmul_rn(cf, dx));
+    fy = __fadd_rn(fy, __fmul_rn(cf, dy));
+    fz = __fadd_rn(fz, __fmul_rn(cf, dz));
+  }
+  if (torn) set_err(d.ctl, PR_EINVAL);
+  float vx = a.vx[i], vy = a.vy[i], vz = a.vz[i];
+  const float h = d.md_h;
+  if (m > 0) {  // the second half kick of the previous MD step
+    vx = __fadd_rn(vx, __fmul_rn(h, fx));
+    vy = __fadd_rn(vy, __fmul_rn(h, fy));
+    vz = __fadd_rn(vz, __fmul_rn(h, fz));
+  }
+  if (m < d.md_theta) {  // the first half kick and the drift of MD step m
+    vx = __fadd_rn(vx, __fmul_rn(h, fx));
+    vy = __fadd_rn(vy, __fmul_rn(h, fy));
+    vz = __fadd_rn(vz, __fmul_rn(h, fz));
+    XW[i] = wrap_box(__fadd_rn(xi, __fmul_rn(d.md_dt, vx)), d.L);
+    YW[i] = wrap_box(__fadd_rn(yi, __fmul_rn(d.md_dt, vy)), d.L);
+    ZW[i] = wrap_box(__fadd_rn(zi, __fmul_rn(d.md_dt, vz)), d.L);
+  } else if (d.md_theta & 1) {  // odd theta: one more flip of the buffers
+    XW[i] = xi;
+    YW[i] = yi;
+    ZW[i] = zi;
+  }
+  a.vx[i] = vx;
+  a.vy[i] = vy;
+  a.vz[i] = vz;
+}
+
+// Initial velocities: per component the Irwin-Hall(4) offset of the bytes of
+// word d of the Philox block (0, id, 0, 6) times cv = fl32(sqrt(T / 21845)).
+__global__ __launch_bounds__(kThreads) void k_md_init(Dev d, unsigned long long vseed, float cv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
+  const Arr a = pick_set(d, d.ctl->set & 1u);
+  int32_t S[3];
+  ih4(0u, a.id ? (uint32_t)a.id[i] : (uint32_t)i, 6u, vseed, S);
+  a.vx[i] = __fmul_rn((float)S[0], cv);
+  a.vy[i] = __fmul_rn((float)S[1], cv);
+  a.vz[i] = __fmul_rn((float)S[2], cv);
+}
+
+// The id -> slot map of the current storage set.
+__global__ __launch_bounds__(kThreads) void k_slot_of(Dev d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
+  const Arr a = pick_set(d, d.ctl->set & 1u);
+  d.slot_of[a.id ? a.id[i] : i] = i;
+}
+
+// Velocities in particle-id order.
+__global__ __launch_bounds__(kThreads) void k_gather_v(Dev d, float* ox, float* oy, float* oz) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
+  const Arr a = pick_set(d, d.ctl->set & 1u);
+  const int id = a.id ? a.id[i] : i;
+  ox[id] = a.vx[i];
+  oy[id] = a.vy[i];
+  oz[id] = a.vz[i];
+}
+
+// ---------------------------------------------------------------------------
 // Kinetics counters of the current configuration (the quantities of the
 // paper's rate equations, Sec. II B-C): populations of the A type by state,
 // and, per state of the A-eligible particles, their T-eligible partners
@@ -1945,6 +2073,12 @@ __device__ __forceinline__ void sort_scatter_body(const Dev& d, int k) {
   o.role[ns] = role;
   const int id = a.id[k];
   o.id[ns] = id;
+  if (a.vx) {
+    o.vx[ns] = a.vx[k];
+    o.vy[ns] = a.vy[k];
+    o.vz[ns] = a.vz[k];
+  }
+  if (d.slot_of) d.slot_of[id] = ns;
   // rows of width 4 or 2 move as one vector when both arrays are aligned
   const bool vec = (((uintptr_t)a.adj | (uintptr_t)o.adj) & 15u) == 0u;
   if (vec && d.B == 4) {
@@ -2169,6 +2303,13 @@ __global__ __launch_bounds__(kThreads) void k_fill_u32(uint32_t* __restrict__ p,
     p[i] = v;
 }
 
+// The bonded-force kernel's square root on caller data (n values > 0, normal).
+__global__ __launch_bounds__(kThreads) void k_sqrt_rn(const float* __restrict__ in,
+                                                      float* __restrict__ out, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = sqrt_rn(in[i]);
+}
+
 // The generator's words for caller counters (4 uint32 per counter).
 __global__ __launch_bounds__(kThreads) void k_draws(const uint4* __restrict__ ctr, long long n,
                                                     unsigned long long key, uint4* out) {
@@ -2211,6 +2352,8 @@ hipError_t launch_generate(const Dev& d, int kind, unsigned long long gseed, flo
 // which stamps the two events at the kernel's own start and end.
 hipError_t launch_step(const Dev& d, int k, hipStream_t s, hipEvent_t ev_sweep0,
                        hipEvent_t ev_sweep1) {
+  for (int m = 0; d.md_theta > 0 && m <= d.md_theta; ++m)
+    k_md<<<blocks_for(d.n, kThreads), kThreads, 0, s>>>(d, k, m);
   const int prep_blocks = d.nwg_prep + (k > 0 ? d.ngroups : 0);
   k_prep<<<prep_blocks, kThreads, 0, s>>>(d, k);
   const dim3 g(d.nwg_sweep), b(kThreads);
@@ -2380,6 +2523,24 @@ hipError_t launch_kinetics(const Dev& d, int nstate, int nbins, const float* e2,
   k_prep<<<d.nwg_prep, kThreads, 0, s>>>(dn, 0);
   k_kin_pairs<<<g, kThreads, 0, s>>>(dn, nstate, nbins, e2, pairs, hist);
   k_kin_reset<<<std::min(blocks_for(d.ncell, kThreads), 1024), kThreads, 0, s>>>(dn);
+  return hipGetLastError();
+}
+
+hipError_t launch_md_init(const Dev& d, unsigned long long vseed, float cv, hipStream_t s) {
+  if (d.n > 0) {
+    k_slot_of<<<blocks_for(d.n, kThreads), kThreads, 0, s>>>(d);
+    if (cv >= 0.0f) k_md_init<<<blocks_for(d.n, kThreads), kThreads, 0, s>>>(d, vseed, cv);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_v(const Dev& d, float* ox, float* oy, float* oz, hipStream_t s) {
+  if (d.n > 0) k_gather_v<<<blocks_for(d.n, kThreads), kThreads, 0, s>>>(d, ox, oy, oz);
+  return hipGetLastError();
+}
+
+hipError_t launch_sqrt_rn(const float* in, float* out, long long n, hipStream_t s) {
+  if (n > 0) k_sqrt_rn<<<blocks_for(n, kThreads), kThreads, 0, s>>>(in, out, n);
   return hipGetLastError();
 }
 

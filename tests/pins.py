@@ -683,6 +683,104 @@ def check_multi_cross_role(lib, seeds=600):
 
 
 # --------------------------------------------------------------------------
+# bonded-force coupling: velocity Verlet with the mirror-LJ bond potential
+# (Sec. II D, Eq. (mirror LJ))
+# --------------------------------------------------------------------------
+SC = 2.0 ** (1.0 / 6.0)
+
+
+def _mirror_lj(r):
+    """The paper's bond potential, eps = sig = 1 (zero up to sc, Eq. mirror LJ)."""
+    if r <= SC:
+        return 0.0
+    q = 1.0 / (2 * SC - r)
+    return 4.0 * (q ** 12 - q ** 6 + 0.25)
+
+
+def _pair(r0, L=10.0, vel=0.0):
+    s = mk(L, [(4.0, 5, 5), (4.0 + r0, 5, 5)], [0, 0], [0, 0], B=2, adj=[[1, -1], [0, -1]])
+    md = oracle.MD(2)
+    md.vx[:] = [-vel, vel]
+    return s, md
+
+
+def check_md_no_force_inside_sc(lib):
+    """A bond shorter than sc exerts no force: a pair at rest stays put."""
+    s, md = _pair(1.0)
+    x0 = s.x.copy()
+    assert oracle.md_block(s, md, 200, lib=lib) == 0
+    assert np.array_equal(s.x, x0) and not md.vx.any()
+
+
+def check_md_two_body(lib):
+    """A bonded pair at r0 = 1.13 flying apart (each particle at speed 3): the
+    relative distance obeys r'' = -2 V_b'(r) (unit masses) until it falls back
+    inside sc (t = 0.1; there is no other force).  Reference: an independent
+    FP64 ODE solution with the derivative of the paper's V_b taken by central
+    differences; velocity Verlet at dt = 0.0005 agrees to O(dt^2)."""
+    from scipy.integrate import solve_ivp
+    r0, v = 1.13, 3.0
+
+    def dV(r, h=1e-6):
+        return (_mirror_lj(r + h) - _mirror_lj(r - h)) / (2 * h)
+
+    ref = solve_ivp(lambda t, y: [y[1], -2.0 * dV(y[0])], (0, 0.1), [r0, 2 * v], rtol=1e-11,
+                    atol=1e-12, dense_output=True, max_step=0.0005)
+    s, md = _pair(r0, vel=v)
+    t = 0.0
+    for chunk in (40, 40, 40, 40, 30):  # t = 0.02, 0.04, 0.06, 0.08, 0.095
+        assert oracle.md_block(s, md, chunk, dt=0.0005, lib=lib) == 0
+        t += chunk * 0.0005
+        r = float(s.x[1]) - float(s.x[0])
+        assert abs(r - ref.sol(t)[0]) < 2e-4, (t, r, ref.sol(t)[0])
+        assert abs(float(s.x[0]) + float(s.x[1]) - (8.0 + r0)) < 1e-4  # centre of mass at rest
+    assert ref.sol(0.05)[0] > 1.3  # the excursion reached well into the bond's range
+
+
+def check_md_energy_conservation(lib, pairs=60):
+    """Bonded pairs stretched into the attractive range, random velocities:
+    the total energy (kinetic + bonds) is conserved by the integrator."""
+    rng = np.random.default_rng(9)
+    pts, adj = [], []
+    for k in range(pairs):
+        c = rng.uniform(2, 18, 3)
+        u = rng.normal(size=3)
+        u /= np.linalg.norm(u)
+        r = rng.uniform(1.13, 1.25)
+        pts += [tuple(c), tuple(c + r * u)]
+        adj += [[2 * k + 1, -1], [2 * k, -1]]
+    s = mk(20.0, pts, [0] * (2 * pairs), [0] * (2 * pairs), B=2, adj=adj)
+    md = oracle.MD(s.n, seed=77, temp=0.5, lib=lib)
+    e0 = oracle.md_energy(s, md, lib=lib)
+    for _ in range(8):
+        assert oracle.md_block(s, md, 500, lib=lib) == 0
+        e = oracle.md_energy(s, md, lib=lib)
+        assert abs(e - e0) < 2e-3 * abs(e0), (e, e0)
+
+
+def check_md_thermoneutral_run(lib):
+    """Reaction steps between MD blocks: bonds form at r < rc < sc, where the
+    mirror-LJ potential and its force vanish, so a reaction step changes no
+    energy and the run conserves the total energy while bonds form
+    (the paper's thermoneutral bonding, Sec. II)."""
+    g = workload.generate(4000, 16.75, "step", 17)
+    s = System(g["L"], g["x"], g["y"], g["z"], g["type"], g["state"], g["adj"])
+    md = oracle.MD(s.n, seed=5, temp=1.0, lib=lib)
+    e0 = oracle.md_energy(s, md, lib=lib)
+    rule = step_rule(p=0.05)
+    total = 0
+    for step in range(1, 31):
+        assert oracle.md_block(s, md, 25, lib=lib) == 0
+        e_before = oracle.md_energy(s, md, lib=lib)
+        code, bonds, _ = one(lib, s, rule, seed=17, step=step)
+        assert code == 0
+        total += len(bonds)
+        assert oracle.md_energy(s, md, lib=lib) == e_before, "a reaction step changed the energy"
+    assert total > 100
+    assert abs(oracle.md_energy(s, md, lib=lib) - e0) < 1e-3 * abs(e0)
+
+
+# --------------------------------------------------------------------------
 # FP64 recheck of the cutoff decision (diagnostic; the step decides in FP32)
 # --------------------------------------------------------------------------
 RC32 = float(np.float32(1.12))  # the cutoff as the FP32 value both sides use
@@ -776,4 +874,6 @@ ALL = [check_pair_distance, check_periodic, check_cutoff_strict, check_p0_p1, ch
        check_near_cutoff, check_near_cutoff_disagree, check_nearest_picks_closest,
        check_nearest_mutual, check_nearest_tie_lower_id, check_nearest_probability,
        check_nearest_exclusion_first, check_kinetics_hand, check_kinetics_poisson,
-       check_multi_one_rule_is_single, check_multi_two_rates, check_multi_cross_role]
+       check_multi_one_rule_is_single, check_multi_two_rates, check_multi_cross_role,
+       check_md_no_force_inside_sc, check_md_two_body, check_md_energy_conservation,
+       check_md_thermoneutral_run]

@@ -29,6 +29,7 @@ MUTANTS = {
     19: ("nearest: pairs need not be mutual", [pins.check_nearest_mutual]),
     20: ("kinetics: partners counted under the T's state", [pins.check_kinetics_hand]),
     21: ("several rules: no cross-role selection (step 8)", [pins.check_multi_cross_role]),
+    22: ("mirror-LJ force with the wrong sign", [pins.check_md_two_body]),
 }
 
 
