@@ -20,7 +20,7 @@ constexpr int kSortLds = 4096;      // bonds of a stateless step sorted in LDS u
 constexpr int kStatsPerStep = 9;    // pr_stats fields
 constexpr int kGroup = 256;         // sweep workgroups closed by one closing workgroup
 constexpr int kPart = 8;            // partial counters per closing workgroup and step
-constexpr int kWgOut = 8;           // per sweep workgroup counters (see WgOut)
+constexpr int kWgOut = 9;           // per sweep workgroup counters (see WgOut)
 constexpr int kRetCap = 32;         // retained pairs a sweep workgroup hands to the resolve
 constexpr int kWinCap = 16;         // bonds a resolve workgroup stages in place
 constexpr int kAdjStage = 4;        // adjacency rows up to this width travel with A records
@@ -45,7 +45,15 @@ constexpr int kMaxRules = 4;        // concurrent rules of one system
 constexpr int kKinMaxState = 64;    // kinetics counters: states per call
 constexpr int kKinMaxBins = 256;    // kinetics counters: distance bins per call
 
-enum WgOut { kOutTElig = 0, kOutInRc, kOutDrawn, kOutExcl, kOutRet, kOutProp, kOutBonds, kOutLost };
+enum WgOut { kOutTElig = 0, kOutInRc, kOutDrawn, kOutExcl, kOutRet, kOutProp, kOutBonds, kOutLost,
+             kOutAElig };
+// Brick lists (sorted storage): A records of the next step are written by each
+// A's own sweep workgroup, by brick, without atomics.  kXCap: A's beyond a
+// brick's sort-time A's (chain growth: new active ends) a brick lists.
+constexpr int kXCap = 32;
+// Record flags in the id word of a brick-list record: not an A in that step /
+// outside its home brick's region (then on the stray list, not the brick's).
+constexpr uint32_t kRecDead = 0x80000000u, kRecStray = 0x40000000u, kRecId = 0x3FFFFFFFu;
 
 // Device control block.  Steps are launched in blocks of K steps; the kernels
 // of step k of a block use step0 + k and parity (par0 + k) & 1, so a captured
@@ -152,6 +160,17 @@ struct Dev {
   int32_t nrules;
   RuleX mr[kMaxRules];
   uint8_t *wfa, *wft;   // per slot: won as an A / as a T in this step (one writer each)
+  // brick lists (bricklist = 1: sorted storage, one rule, random selection,
+  // no MD, brick edge >= 2): the A records of a step by slot, (x, y, z, id |
+  // flags), for parity p; sort-time A's per brick (the first bna[b] slots of
+  // brick b); further A's of brick b by parity (count xcnt, slots xlist); A's
+  // outside their brick's region on the stray list of (step mod 3)
+  int32_t bricklist;
+  float4* arec[2];
+  int32_t* bna;
+  int32_t *xcnt[2], *xlist[2];
+  uint32_t* scnt;       // 3 counts
+  int32_t* sslot[3];
   // bonded-force coupling (md_theta > 0): md_theta velocity-Verlet steps with
   // the mirror-LJ bond force before each reaction step, instead of the
   // re-jitter; slot_of maps ids to slots of the current storage set

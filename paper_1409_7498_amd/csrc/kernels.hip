@@ -51,7 +51,9 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
 
 __device__ __forceinline__ W4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                      unsigned long long key) {
-  uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
+  // the key (the seed) is uniform in every caller
+  uint32_t k0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)key);
+  uint32_t k1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(key >> 32));
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     // one 32x32 -> 64-bit product each (a single v_mad_u64_u32)
@@ -195,6 +197,8 @@ __device__ __forceinline__ T* pick(T* const (&v)[2], uint32_t p) {
 // Storage set s, member by member (a select of the whole aggregate would be
 // built in scratch memory).
 __device__ __forceinline__ Arr pick_set(const Dev& d, uint32_t s) {
+  // s is uniform: a scalar select keeps the pointers in scalar registers
+  s = (uint32_t)__builtin_amdgcn_readfirstlane((int)s);
   const Arr &u = d.set[0], &v = d.set[1];
   Arr r;
   for (int q = 0; q < 2; ++q) {
@@ -219,7 +223,10 @@ struct StepInfo {
 };
 
 __device__ __forceinline__ StepInfo step_info(const Ctl* c, int k) {
-  return StepInfo{c->step0 + (uint32_t)k, (c->par0 + (uint32_t)k) & 1u};
+  // uniform over the launch (scalar registers, scalar selects of buffers)
+  const uint32_t s0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)c->step0);
+  const uint32_t p0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)c->par0);
+  return StepInfo{s0 + (uint32_t)k, (p0 + (uint32_t)k) & 1u};
 }
 
 // Exclusive prefix sum over the workgroup (wave64 shuffles, then wave
@@ -362,7 +369,7 @@ __device__ void close_group(const Dev& d, uint32_t par, uint32_t step, uint32_t 
   if (tid < kPart) s_sum[tid] = 0;
   const int w = g * kGroup + tid;
   const int2* staged = pick(d.wgw, par) + w * kWinCap;
-  int o[kWgOut] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int o[kWgOut] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   // a workgroup stages 0.3 bonds per step on average: its first two are read
   // with its counters, before their number is known (a window holds
   // kWinCap >= 2), which saves a dependent round trip in the common case
@@ -374,8 +381,11 @@ __device__ void close_group(const Dev& d, uint32_t par, uint32_t step, uint32_t 
     pre[0] = staged[0];
     pre[1] = staged[1];
   }
-  int a_elig = 0;  // the A-bin workgroup counts, strided over the groups
-  for (int q = w; q < d.nwg_prep; q += d.ngroups * kGroup) a_elig += pick(d.abst, par)[q];
+  // the A's of the step: counted by the sweep workgroups (brick lists), else
+  // by the binning workgroups (strided over the groups)
+  int a_elig = d.bricklist ? o[kOutAElig] : 0;
+  for (int q = w; !d.bricklist && q < d.nwg_prep; q += d.ngroups * kGroup)
+    a_elig += pick(d.abst, par)[q];
   const uint32_t nw = (uint32_t)min(o[kOutBonds], kWinCap);
   uint32_t tot = 0;
   const uint32_t off = block_scan_excl(nw, s_wave, tot);
@@ -656,6 +666,147 @@ __device__ __forceinline__ int local_of(int c, int base, int nc) {
   return l < 0 ? l + nc : l;
 }
 
+// ---------------------------------------------------------------------------
+// Brick lists (sorted storage).  The A's of step k are the records arec[p][slot]
+// (x, y, z, id | flags) of: the first bna[b] slots of every brick b (its A's
+// at the last sort), the slots xlist[p][b] of A's that appeared in brick b
+// since (chain growth), and the stray list of (step mod 3).  An A is "home"
+// while its cell lies in the region of its brick (the brick's cells plus one
+// cell layer); else its record carries kRecStray and it is on the stray list
+// instead.  With brick edges of at least two cells, every A within the cutoff
+// of a point lies on the lists of the (at most 27 distinct) bricks around the
+// point's brick, or on the stray list.
+// ---------------------------------------------------------------------------
+// The brick coordinates (bx, by, bz) of brick index b.
+__device__ __forceinline__ void brick_xyz(const Dev& d, int b, int& bx, int& by, int& bz) {
+  bz = div_nb(d, div_nb(d, b, bx), by);
+}
+
+// Neighbour t (0 .. 26) of brick (bx, by, bz): false when, with fewer than
+// three bricks per side, the offset repeats a brick another t already names.
+__device__ __forceinline__ bool brick_neighbour(const Dev& d, int bx, int by, int bz, int t,
+                                                int& nbr) {
+  const int o[3] = {t % 3 - 1, (t / 3) % 3 - 1, t / 9 - 1};
+  const int c[3] = {bx, by, bz};
+  int q[3];
+  for (int e = 0; e < 3; ++e) {
+    if (d.nb == 1 && o[e] != 0) return false;
+    if (d.nb == 2 && o[e] < 0) return false;
+    int v = c[e] + o[e];
+    v = v < 0 ? v + d.nb : (v >= d.nb ? v - d.nb : v);
+    q[e] = v;
+  }
+  nbr = (q[2] * d.nb + q[1]) * d.nb + q[0];
+  return true;
+}
+
+// Whether a position's cell lies in the region (cells base + [0, ext) per
+// dimension, modulo nc) of a brick.
+__device__ __forceinline__ bool in_region(const Dev& d, float x, float y, float z, int bx0,
+                                          int ex, int by0, int ey, int bz0, int ez, int& cl) {
+  const int nc = d.nc;
+  int lx = cell1(__fmul_rn(x, d.inv_w), nc) - bx0;
+  int ly = cell1(__fmul_rn(y, d.inv_w), nc) - by0;
+  int lz = cell1(__fmul_rn(z, d.inv_w), nc) - bz0;
+  lx += lx < 0 ? nc : 0;
+  ly += ly < 0 ? nc : 0;
+  lz += lz < 0 ? nc : 0;
+  cl = (lz * ey + ly) * ex + lx;
+  return lx < ex && ly < ey && lz < ez;
+}
+
+// The stray list that holds the A's of reaction step `step`.
+__device__ __forceinline__ uint32_t stray_list(uint32_t step) { return step % 3u; }
+
+// Visits, with the lanes of one wavefront, every A record of step parity par
+// that can lie within the cutoff of (x, y, z) (the same point in every lane):
+// the lists of the bricks around the point's brick and the stray list q,
+// flattened into one index range of which this lane takes first, first +
+// stride, ... (kB records in flight per lane).  f(record with the plain id
+// in w, the A's slot).  Every lane of the wavefront must call it.
+template <int kB, typename F>
+__device__ __forceinline__ void wave_brick_records(const Dev& d, uint32_t par, uint32_t q, float x,
+                                                   float y, float z, int first, int stride, F f) {
+  const int lane = __lane_id(), nc = d.nc;
+  const int cx = cell1(__fmul_rn(x, d.inv_w), nc), cy = cell1(__fmul_rn(y, d.inv_w), nc),
+            cz = cell1(__fmul_rn(z, d.inv_w), nc);
+  const int bx = d.nbricks > 1 ? cx / d.bs : 0, by = d.nbricks > 1 ? cy / d.bs : 0,
+            bz = d.nbricks > 1 ? cz / d.bs : 0;
+  // lane t < 27: neighbour brick t (start, sort-time A's, index); lane 27: the
+  // stray list; their record counts, prefix-summed over the lanes
+  int b = 0, st = 0, na = 0, cnt = 0;
+  if (lane < 27) {
+    if (brick_neighbour(d, bx, by, bz, lane, b)) {
+      st = d.bstart[b];
+      na = d.bna[b];
+      cnt = na + min(pick(d.xcnt, par)[b], kXCap);
+    }
+  } else if (lane == 27) {
+    cnt = (int)min(d.scnt[q], (uint32_t)d.n);
+  }
+  int incl = cnt;
+#pragma unroll
+  for (int o = 1; o < 32; o <<= 1) {
+    const int v = __shfl_up(incl, o);
+    if (lane >= o) incl += v;
+  }
+  const int pre = incl - cnt;
+  const int tot = __shfl(incl, 27);
+  const float4* rec = pick(d.arec, par);
+  const int32_t* xl = pick(d.xlist, par);
+  const int32_t* sl = d.sslot[q];
+  for (int i0 = first; __shfl(i0, 0) < tot; i0 += kB * stride) {
+    float4 r[kB];
+    int slot[kB], src[kB];
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      const int i = i0 + u * stride;
+      // the source of flat index i: the last t in [0, 27] with pre[t] <= i
+      int t = 0;
+#pragma unroll
+      for (int h = 16; h > 0; h >>= 1) {
+        const int m = t + h;
+        const int pm = __shfl(pre, m < 28 ? m : 27);
+        if (m < 28 && pm <= i) t = m;
+      }
+      const int j = i - __shfl(pre, t);
+      const int tst = __shfl(st, t), tna = __shfl(na, t), tb = __shfl(b, t);
+      src[u] = t;
+      slot[u] = -1;
+      if (i < tot) {
+        slot[u] = t == 27 ? sl[j] : (j < tna ? tst + j : xl[tb * kXCap + (j - tna)]);
+        r[u] = rec[slot[u]];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      if (slot[u] < 0) continue;
+      const uint32_t w = __float_as_uint(r[u].w);
+      // home lists take home records, the stray list its stray ones
+      if ((w & kRecDead) || ((w & kRecStray) != 0) != (src[u] == 27)) continue;
+      r[u].w = __uint_as_float(w & kRecId);
+      f(r[u], slot[u]);
+    }
+  }
+}
+
+// Writes the record of A (slot, id) for the step `step` at position (x, y,
+// z): stray when outside the region of its home brick (given), then listed
+// on the stray list of that step (a returning atomic; strays are rare).
+__device__ __forceinline__ void put_record(const Dev& d, uint32_t par, uint32_t step, int slot,
+                                           uint32_t id, float x, float y, float z, int bx0, int ex,
+                                           int by0, int ey, int bz0, int ez, bool unlisted) {
+  int cl;
+  const bool home =
+      !unlisted && (d.nbricks == 1 || in_region(d, x, y, z, bx0, ex, by0, ey, bz0, ez, cl));
+  pick(d.arec, par)[slot] = make_float4(x, y, z, __uint_as_float(id | (home ? 0u : kRecStray)));
+  if (!home) {
+    const uint32_t q = stray_list(step);
+    const uint32_t p = atomicAdd(&d.scnt[q], 1u);
+    if (p < (uint32_t)d.n) d.sslot[q][p] = slot;
+  }
+}
+
 // Slot range of sweep/resolve workgroup w.
 template <bool kBrick>
 __device__ __forceinline__ void range_of(const Dev& d, int w, int& s0, int& s1) {
@@ -674,7 +825,7 @@ __device__ __forceinline__ void range_of(const Dev& d, int w, int& s0, int& s1) 
 // workgroup's list.  arow: the A's adjacency row staged with its record
 // (nullptr: the row is read from the particle arrays).
 struct SweepAcc {
-  int t_elig, in_rc, drawn, excl;
+  int t_elig, in_rc, drawn, excl, a_elig;
 };
 
 struct RetList {
@@ -784,8 +935,10 @@ __device__ __forceinline__ uint32_t lanes_below(unsigned long long b) {
 
 // kTwo: two region cells per thread while staging (brick edges above
 // kOneCellBrick); else one, with the smaller tables.
-template <bool kBrick, bool kTwo>
+// kBL: brick lists instead of the A grid (sorted storage of one system).
+template <bool kBrick, bool kTwo, bool kBL = false>
 __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) {
+  static_assert(!kBL || kBrick, "brick lists need sorted storage");
   constexpr int kCells = kTwo ? kStageCells : kStageCells1;  // region cells at most
   constexpr int kPer = kBrick ? kTPass / kThreads : 1;
   constexpr int kTP = kPer * kThreads;
@@ -801,10 +954,20 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
   __shared__ int4 s_ent[kRetCap];
   __shared__ uint32_t s_ew2[kRetCap];
   __shared__ uint32_t s_wave[kThreads / 64 + 1];
-  __shared__ int s_cnt[4];
+  __shared__ int s_cnt[5];
   __shared__ int s_qn, s_ndef, s_ne, s_dead;
+  // brick lists: the distinct neighbour bricks (start, sort-time A's, further
+  // A's, index), per region cell counts, kept records, this brick's new list
+  __shared__ int s_nbs[kBL ? 27 : 1], s_nbn[kBL ? 27 : 1], s_nbx[kBL ? 27 : 1],
+      s_nbb[kBL ? 27 : 1];
+  __shared__ uint32_t s_ccnt[kBL ? kCells : 1];
+  __shared__ int s_kept, s_ns, s_xn, s_na;
+  __shared__ int32_t s_xl[kBL ? kXCap : 1];
+  // brick lists: the A's of the brick at their positions of this step (slot
+  // in w), in the staging array the pass loop leaves idle
+  float4* const s_apos = (float4*)s_radj;
   const int tid = threadIdx.x;
-  if (tid < 4) s_cnt[tid] = 0;
+  if (tid < 5) s_cnt[tid] = 0;
   if (tid == 0) {
     s_qn = 0;
     s_ndef = 0;
@@ -855,18 +1018,119 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
     ncs = ex * ey * ez;
     m_exy = recip16((uint32_t)(ex * ey));
     m_ex = recip16((uint32_t)ex);
-    // the record counts of this thread's region cells (2 tid and 2 tid + 1,
-    // or tid), issued first
+    if (kBL) {
+      // the lists of the neighbour bricks, the stray count; cleared counts
+      if (tid < 27) {
+        int b = 0;
+        const bool ok = brick_neighbour(d, bxc, byc, bzc, tid, b);
+        s_nbb[tid] = ok ? b : -1;
+        s_nbs[tid] = ok ? d.bstart[b] : 0;
+        s_nbn[tid] = ok ? d.bna[b] : 0;
+        s_nbx[tid] = ok ? min(pick(d.xcnt, par)[b], kXCap) : 0;
+      }
+      if (tid == 0) {
+        s_kept = 0;
+        s_xn = 0;
+        s_na = 0;
+        s_ns = (int)min(d.scnt[stray_list(step)], (uint32_t)d.n);
+        // the stray list two steps ahead is free: the next step's sweep fills it
+        if (w == 0) d.scnt[stray_list(step + 2u)] = 0u;
+      }
 #pragma unroll
-    for (int h = 0; h < (kTwo ? 2 : 1); ++h) {
-      const int cl = kTwo ? 2 * tid + h : tid;
-      if (cl < ncs) (h ? mine2 : mine) = pick(d.cnt, par)[region_cell(cl)];
+      for (int h = 0; h < (kTwo ? 2 : 1); ++h) {
+        const int cl = kTwo ? 2 * tid + h : tid;
+        if (cl < kCells) s_ccnt[cl] = 0u;
+      }
+    } else {
+      // the record counts of this thread's region cells (2 tid and 2 tid + 1,
+      // or tid), issued first
+#pragma unroll
+      for (int h = 0; h < (kTwo ? 2 : 1); ++h) {
+        const int cl = kTwo ? 2 * tid + h : tid;
+        if (cl < ncs) (h ? mine2 : mine) = pick(d.cnt, par)[region_cell(cl)];
+      }
     }
   }
   // the first particle of the first pass, issued behind the record counts
   // (memory operations complete in issue order)
   Part cur = load_part<kBrick>(a, X, Y, Z, s0 + tid, s1);
-  if (kBrick) {
+  int a_end = s0;  // brick lists: the end of this brick's sort-time A's
+  if (kBL) {
+    __syncthreads();
+    a_end = s0 + s_nbn[13];  // neighbour 13 is the brick itself
+    // kept records and their region cells go to arrays that are idle during
+    // staging (s_radj, s_tid, s_def)
+    float4* t_rec = (float4*)s_radj;
+    int32_t* t_sa = s_tid;
+    uint16_t* t_cl = s_def;
+    // sources: threads 0-215 take the 27 bricks (eight each), 216-255 the
+    // stray list; each loads up to kB records before it filters any
+    constexpr int kB = 4;
+    const int src = tid < 216 ? tid >> 3 : 27;
+    const int lane = tid < 216 ? (tid & 7) : tid - 216;
+    const int stride = tid < 216 ? 8 : 40;
+    const int nn = src < 27 ? s_nbn[src] : 0;
+    const int nsrc = src < 27 ? nn + s_nbx[src] : s_ns;
+    const float4* R = pick(d.arec, par);
+    const uint32_t q = stray_list(step);
+    for (int i0 = lane; i0 < nsrc; i0 += stride * kB) {
+      float4 r[kB];
+      int sl[kB];
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        const int i = i0 + u * stride;
+        sl[u] = -1;
+        if (i < nsrc) {
+          sl[u] = src < 27 ? (i < nn ? s_nbs[src] + i
+                                     : pick(d.xlist, par)[s_nbb[src] * kXCap + (i - nn)])
+                           : d.sslot[q][i];
+          r[u] = R[sl[u]];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        if (sl[u] < 0) continue;
+        const uint32_t fw = __float_as_uint(r[u].w);
+        // home lists take home records; the stray list its (stray) records
+        if ((fw & kRecDead) || ((fw & kRecStray) != 0) != (src == 27)) continue;
+        int cl;
+        if (!in_region(d, r[u].x, r[u].y, r[u].z, bx, ex, by, ey, bz, ez, cl)) continue;
+        const int kk = atomicAdd(&s_kept, 1);
+        if (kk < kStageRecs) {
+          t_rec[kk] = make_float4(r[u].x, r[u].y, r[u].z, __uint_as_float(fw & kRecId));
+          t_sa[kk] = sl[u];
+          t_cl[kk] = (uint16_t)cl;
+          atomicAdd(&s_ccnt[cl], 1u);
+        }
+      }
+    }
+    __syncthreads();
+    const uint32_t total = (uint32_t)s_kept;
+    staged = total <= (uint32_t)kStageRecs;
+#pragma unroll
+    for (int h = 0; h < (kTwo ? 2 : 1); ++h) {
+      const int cl = kTwo ? 2 * tid + h : tid;
+      if (cl < ncs) (h ? mine2 : mine) = s_ccnt[cl];
+    }
+    uint32_t tot = 0;
+    const uint32_t off = block_scan_excl(mine + mine2, s_wave, tot);
+#pragma unroll
+    for (int h = 0; h < (kTwo ? 2 : 1); ++h) {
+      const int cl = kTwo ? 2 * tid + h : tid;
+      if (cl < ncs) {
+        const uint32_t o = h ? off + mine : off;
+        s_off[cl] = (uint16_t)o;
+        s_ccnt[cl] = o;  // insert position
+      }
+    }
+    if (tid == 0) s_off[ncs] = (uint16_t)min(total, (uint32_t)kStageRecs);
+    __syncthreads();
+    if (staged && tid < (int)total) {
+      const uint32_t pos = atomicAdd(&s_ccnt[t_cl[tid]], 1u);
+      s_rec[pos] = t_rec[tid];
+      s_rsa[pos] = t_sa[tid];
+    }
+  } else if (kBrick) {
     mine = mine < (uint32_t)kCellCap ? mine : (uint32_t)kCellCap;
     mine2 = mine2 < (uint32_t)kCellCap ? mine2 : (uint32_t)kCellCap;
     uint32_t total = 0;
@@ -905,7 +1169,7 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
       (nowrap ? kFNowrap : 0u) | (!plain_x && plain_y && plain_z ? kFWrapX : 0u) |
       (plain_x && !plain_y && plain_z ? kFWrapY : 0u) |
       (plain_x && plain_y && !plain_z ? kFWrapZ : 0u));
-  SweepAcc n = {0, 0, 0, 0};
+  SweepAcc n = {0, 0, 0, 0, 0};
   for (int base = s0; base < s1 && !dead; base += kTP) {
     if (base != s0) cur = load_part<kBrick>(a, X, Y, Z, base + tid, s1);
 #pragma unroll 1
@@ -932,6 +1196,11 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
         *(float*)((char*)XW + bo) = cur.x;
         *(float*)((char*)YW + bo) = cur.y;
         *(float*)((char*)ZW + bo) = cur.z;
+      }
+      if (kBL && slot < s1 && cur.role == kRoleA) {  // kept for the next step's record
+        n.a_elig++;
+        const int p = atomicAdd(&s_na, 1);
+        if (p < kStageRecs) s_apos[p] = make_float4(cur.x, cur.y, cur.z, __int_as_float(slot));
       }
       // in-range staged records of this T: nh counts them all, hits keeps the
       // first four, one byte each (a T with more is deferred)
@@ -1026,13 +1295,28 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
         if (q == kQEmpty) continue;
         const uint32_t lt = q & 0xFFFFu, r = q >> 16;
         retain(d, a, step, __float_as_int(s_rec[r].w), s_rsa[r], (uint32_t)s_tid[lt],
-               base + (int)lt, d.adj_staged ? &s_radj[r] : nullptr, n, rl);
+               base + (int)lt, d.adj_staged && !kBL ? &s_radj[r] : nullptr, n, rl);
       }
     }
-    // the deferred T's, in the global buckets (cells 0-7 of the block, then
-    // the overflow list), re-jittered again from the previous positions
+    // the deferred T's, re-jittered again from the previous positions; with
+    // brick lists one T at a time, its candidate records spread over the
+    // workgroup's lanes
     const int ndef = s_ndef;
-    for (int e = tid; e < ndef; e += kThreads) {
+    for (int e = 0; kBL && e < ndef; ++e) {
+      const int slot = base + (int)s_def[e];
+      float px = X[slot], py = Y[slot], pz = Z[slot];
+      const uint32_t idj = (uint32_t)a.id[slot];
+      if (jit) rejitter(d, step, idj, px, py, pz);
+      wave_brick_records<1>(d, par, stray_list(step), px, py, pz, tid, kThreads,
+                         [&](float4 A, int sa) {
+                           if (!(dist2(d, px, py, pz, A) < d.rc2)) return;
+                           n.in_rc++;
+                           retain(d, a, step, __float_as_int(A.w), sa, idj, slot, nullptr, n, rl);
+                         });
+    }
+    // else one T per thread in the global buckets (cells 0-7 of the block,
+    // then the overflow list)
+    for (int e = tid; !kBL && e < ndef; e += kThreads) {
       const int slot = base + (int)s_def[e];
       float px = X[slot], py = Y[slot], pz = Z[slot];
       const uint32_t idj = a.id ? (uint32_t)a.id[slot] : (uint32_t)slot;
@@ -1076,15 +1360,61 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
     }
     __syncthreads();
   }
+  if (kBL && !dead) {
+    // the brick's A records of the next step (re-jittered once more), the
+    // further A's listed with the brick; with more A's than the array holds,
+    // every A of the brick from its previous position instead
+    const int na = s_na;
+    const bool all = na > kStageRecs;
+    const int cnt = all ? s1 - s0 : na;
+    for (int e = tid; e < cnt; e += kThreads) {
+      int slot;
+      float x, y, z;
+      if (all) {
+        slot = s0 + e;
+        if (a.role[slot] != kRoleA) continue;
+        x = X[slot];
+        y = Y[slot];
+        z = Z[slot];
+      } else {
+        const float4 q = s_apos[e];
+        slot = __float_as_int(q.w);
+        x = q.x;
+        y = q.y;
+        z = q.z;
+      }
+      const uint32_t id = (uint32_t)a.id[slot];
+      if (all && jit) rejitter(d, step, id, x, y, z);
+      if (jit) rejitter(d, step + 1u, id, x, y, z);
+      bool unlisted = false;
+      if (slot >= a_end) {
+        const int p = atomicAdd(&s_xn, 1);
+        if (p < kXCap) s_xl[p] = slot;
+        unlisted = p >= kXCap;
+      }
+      put_record(d, par ^ 1u, step + 1u, slot, id, x, y, z, bx, ex, by, ey, bz, ez, unlisted);
+    }
+    // sort-time A's no longer active
+    for (int slot = s0 + tid; slot < a_end; slot += kThreads)
+      if (a.role[slot] != kRoleA)
+        ((uint32_t*)pick(d.arec, par ^ 1u))[4 * (size_t)slot + 3] = kRecDead;
+  }
   // clear the bucket counts of the next step's parity (no workgroup of this
-  // step reads them)
+  // step reads them; with brick lists too, so that the buckets are clear
+  // whenever a step without them follows)
   for (int q = w * kThreads + tid; q < d.ncell; q += nwg * kThreads)
     pick(d.cnt, par ^ 1u)[q] = 0u;
   wave_add(&s_cnt[kOutTElig], n.t_elig);
   wave_add(&s_cnt[kOutInRc], n.in_rc);
   wave_add(&s_cnt[kOutDrawn], n.drawn);
   wave_add(&s_cnt[kOutExcl], n.excl);
+  if (kBL) wave_add(&s_cnt[4], n.a_elig);
   __syncthreads();
+  if (kBL) {  // this brick's further A's of the next step
+    const int nx = min(s_xn, kXCap);
+    if (tid < nx) pick(d.xlist, par ^ 1u)[w * kXCap + tid] = s_xl[tid];
+    if (tid == 0) pick(d.xcnt, par ^ 1u)[w] = nx;
+  }
   const int ne = s_ne;
   const int nk = ne < kRetCap ? ne : kRetCap;
   if (tid < nk) {
@@ -1095,6 +1425,7 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
   if (tid < 4) out[tid] = s_cnt[tid];
   if (tid == 0) {
     out[kOutRet] = nk;
+    if (kBL) out[kOutAElig] = s_cnt[4];
     if (ne > kRetCap) atomicAdd(&d.ctl->ret_ovf[par], (uint32_t)(ne - kRetCap));
   }
 }
@@ -1121,7 +1452,33 @@ __device__ __forceinline__ bool adj_append(int32_t* row, int B, int32_t v) {
 struct BondCtx {
   int* nw;
   int* lost;
+  uint32_t step;
 };
+
+// Brick lists after a bond of step `step` whose T has slot sj in brick w:
+// the A's record of the next step is dropped when the bond ends its A role,
+// and a T that takes the A role (chain growth) gets a record, listed with
+// its brick or, beyond kXCap further A's, on the stray list.
+__device__ void bl_after_bond(const Dev& d, const Arr& a, uint32_t par, uint32_t step, int w,
+                              int sa, int sj, uint32_t idj, uint8_t ra, uint8_t rt) {
+  if (ra != kRoleA) ((uint32_t*)pick(d.arec, par ^ 1u))[4 * (size_t)sa + 3] = kRecDead;
+  if (rt != kRoleA) return;
+  float x = pick(a.x, par ^ 1u)[sj], y = pick(a.y, par ^ 1u)[sj], z = pick(a.z, par ^ 1u)[sj];
+  if (d.jitter && d.jit_c != 0.0f) rejitter(d, step + 1u, idj, x, y, z);
+  int bxc, byc;
+  const int bzc = div_nb(d, div_nb(d, w, bxc), byc);
+  int bx, ex, by, ey, bz, ez;
+  region_dim(d, bxc, bx, ex);
+  region_dim(d, byc, by, ey);
+  region_dim(d, bzc, bz, ez);
+  bool unlisted = false;
+  if (sj >= d.bstart[w] + d.bna[w]) {
+    const int p = atomicAdd(&pick(d.xcnt, par ^ 1u)[w], 1);
+    if (p < kXCap) pick(d.xlist, par ^ 1u)[w * kXCap + p] = sj;
+    unlisted = p >= kXCap;
+  }
+  put_record(d, par ^ 1u, step + 1u, sj, idj, x, y, z, bx, ex, by, ey, bz, ez, unlisted);
+}
 
 // A bond (step 9): states, roles, adjacency rows, and the staged (id_A, id_T)
 // row for the log; tagged_t: id_T with the rule of a system of several rules
@@ -1152,8 +1509,10 @@ __device__ __forceinline__ void make_bond(const Dev& d, const Arr& a, uint32_t p
   const int32_t na = a.st[sa] + d.rule.d_a, nt = a.st[sj] + d.rule.d_t;
   a.st[sa] = na;
   a.st[sj] = nt;
-  a.role[sa] = role_of(d, a.typ[sa], na);
-  a.role[sj] = role_of(d, a.typ[sj], nt);
+  const uint8_t ra = role_of(d, a.typ[sa], na), rt = role_of(d, a.typ[sj], nt);
+  a.role[sa] = ra;
+  a.role[sj] = rt;
+  if (d.bricklist) bl_after_bond(d, a, par, b.step, w, sa, sj, (uint32_t)idj, ra, rt);
   int lost = 0;
   if (!adj_append(a.adj + (size_t)sa * d.B, d.B, (int32_t)idj)) lost++;
   if (!adj_append(a.adj + (size_t)sj * d.B, d.B, (int32_t)ida)) lost++;
@@ -1202,8 +1561,10 @@ __device__ __forceinline__ void make_bond_ahead(const Dev& d, const Arr& a, uint
   const int32_t na = o.sta + d.rule.d_a, nt = o.stt + d.rule.d_t;
   a.st[sa] = na;
   a.st[sj] = nt;
-  a.role[sa] = role_of(d, o.tya, na);
-  a.role[sj] = role_of(d, o.tyt, nt);
+  const uint8_t ra = role_of(d, o.tya, na), rt = role_of(d, o.tyt, nt);
+  a.role[sa] = ra;
+  a.role[sj] = rt;
+  if (d.bricklist) bl_after_bond(d, a, par, b.step, w, sa, sj, (uint32_t)idj, ra, rt);
   int lost = 0;
   const int fa = first_empty(o.rowa, d.B), ft = first_empty(o.rowt, d.B);
   if (fa < d.B) a.adj[(size_t)sa * d.B + fa] = (int32_t)idj;
@@ -1247,7 +1608,7 @@ __device__ __forceinline__ void resolve_body(const Dev& d, int k, int w, int nun
   __syncthreads();
   const int mode = s_mode;
   const Arr a = pick_set(d, c->set & 1u);
-  const BondCtx bc{&s_nw[g], &s_lost[g]};
+  const BondCtx bc{&s_nw[g], &s_lost[g], step};
   if (mode == 1) {
     // the list's length and its entries in one round trip (entries past the
     // length are read but not used), then the A keys with the bonds'
@@ -1294,6 +1655,55 @@ __device__ __forceinline__ void resolve_body(const Dev& d, int k, int w, int nun
       if (win) {
         if (ahead) make_bond_ahead(d, a, par, w, e.x, e.y, e.z, e.w, ops, bc);
         else make_bond(d, a, par, w, e.x, e.y, e.z, e.w, bc);
+      }
+    }
+  } else if (mode == 2 && live && kBrick && d.bricklist) {
+    // brick lists: the flagged T's of each wavefront one at a time, the
+    // candidate records spread over its lanes
+    const float *X = pick(a.x, par ^ 1u), *Y = pick(a.y, par ^ 1u), *Z = pick(a.z, par ^ 1u);
+    int s0, s1;
+    range_of<kBrick>(d, w, s0, s1);
+    const int lane = __lane_id();
+    for (int base = s0; base < s1; base += kL) {
+      const int slot = base + tid;
+      unsigned long long m = __ballot(slot < s1 && d.tflag[slot] != 0);
+      while (m) {
+        const int ld = (int)__builtin_ctzll(m);
+        m &= m - 1ull;
+        const int sj = __builtin_amdgcn_readlane(slot, ld);
+        const float xj = X[sj], yj = Y[sj], zj = Z[sj];
+        const uint32_t idj = (uint32_t)a.id[sj];
+        unsigned long long best = kEmpty;
+        int best_sa = 0, np = 0;
+        wave_brick_records<4>(d, par, stray_list(step), xj, yj, zj, lane, 64, [&](float4 A, int sa) {
+          if (!(dist2(d, xj, yj, zj, A) < d.rc2)) return;
+          const int ida = __float_as_int(A.w);
+          if ((uint32_t)d.slotA[ida] != idj) return;  // not retained, or the A chose another T
+          const W4 r = philox(step, (uint32_t)ida, idj, 0u, d.seed);
+          d.slotA[ida] = kEmpty;
+          np++;
+          const unsigned long long bid = ((unsigned long long)r.w2 << 32) | (uint32_t)ida;
+          if (bid < best) {
+            best = bid;
+            best_sa = sa;
+          }
+        });
+        // the smallest (w2, id_A) over the lanes, with its A's slot
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+          const unsigned long long ob = __shfl_xor(best, o);
+          const int os = __shfl_xor(best_sa, o);
+          if (ob < best) {
+            best = ob;
+            best_sa = os;
+          }
+        }
+        np = wave_sum(np);
+        if (lane == 0) {
+          d.tflag[sj] = 0;
+          if (np) atomicAdd(&s_prop[g], np);
+          if (best != kEmpty) make_bond(d, a, par, w, (int)(uint32_t)best, best_sa, sj, (int)idj, bc);
+        }
       }
     }
   } else if (mode == 2 && live) {
@@ -2036,7 +2446,14 @@ __device__ __forceinline__ void sort_local_body(const Dev& d, int b) {
     run += v[q];
   }
   const uint32_t total = __shfl(x, 63);
-  if (lane == 0) d.bcnt[b] = total;
+  if (lane == 0) {
+    d.bcnt[b] = total;
+    if (d.bricklist) {  // the brick's A's (bin 0), no further ones yet
+      d.bna[b] = (int32_t)v[0];
+      d.xcnt[0][b] = 0;
+      d.xcnt[1][b] = 0;
+    }
+  }
 }
 
 __device__ __forceinline__ void sort_scan_body(const Dev& d) {
@@ -2053,7 +2470,14 @@ __device__ __forceinline__ void sort_scan_body(const Dev& d) {
     }
     carry += total;
   }
-  if (threadIdx.x == 0) d.bstart[d.nbricks] = (int32_t)carry;
+  if (threadIdx.x == 0) {
+    d.bstart[d.nbricks] = (int32_t)carry;
+    if (d.bricklist) {  // stray lists of the first two steps after the sort
+      const uint32_t s0 = d.ctl->step0;
+      d.scnt[stray_list(s0)] = 0u;
+      d.scnt[stray_list(s0 + 1u)] = 0u;
+    }
+  }
 }
 
 __device__ __forceinline__ void sort_scatter_body(const Dev& d, int k) {
@@ -2079,6 +2503,17 @@ __device__ __forceinline__ void sort_scatter_body(const Dev& d, int k) {
     o.vz[ns] = a.vz[k];
   }
   if (d.slot_of) d.slot_of[id] = ns;
+  if (d.bricklist && role == kRoleA) {  // the A's record of the block's first step
+    float rx = x, ry = y, rz = z;
+    if (d.jitter && d.jit_c != 0.0f) rejitter(d, d.ctl->step0, (uint32_t)id, rx, ry, rz);
+    int bxc, byc;
+    const int bzc = div_nb(d, div_nb(d, b, bxc), byc);
+    int bx, ex, by, ey, bz, ez;
+    region_dim(d, bxc, bx, ex);
+    region_dim(d, byc, by, ey);
+    region_dim(d, bzc, bz, ez);
+    put_record(d, par, d.ctl->step0, ns, (uint32_t)id, rx, ry, rz, bx, ex, by, ey, bz, ez, false);
+  }
   // rows of width 4 or 2 move as one vector when both arrays are aligned
   const bool vec = (((uintptr_t)a.adj | (uintptr_t)o.adj) & 15u) == 0u;
   if (vec && d.B == 4) {
@@ -2101,13 +2536,25 @@ __global__ __launch_bounds__(kThreads) void k_close(Dev d, int k) { close_body(d
 __global__ void k_advance(Ctl* c, int K) {
   if (threadIdx.x == 0 && blockIdx.x == 0) advance_ctl(c, K);
 }
-template <bool kBrick, bool kTwo>
+template <bool kBrick, bool kTwo, bool kBL>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) void k_sweep(Dev d, int k) {
-  sweep_body<kBrick, kTwo>(d, k, blockIdx.x, gridDim.x);
+  sweep_body<kBrick, kTwo, kBL>(d, k, blockIdx.x, gridDim.x);
 }
+// With brick lists there is no prep kernel: the closing groups of step k - 1
+// lead the resolve of step k.
 template <bool kBrick>
 __global__ __launch_bounds__(kThreads) void k_resolve(Dev d, int k) {
-  resolve_body<kBrick, true>(d, k, blockIdx.x, d.nwg_sweep);
+  int b = blockIdx.x;
+  if (kBrick && d.bricklist && k > 0) {
+    if (b < d.ngroups) {
+      __shared__ uint32_t s_wave[kThreads / 64 + 1];
+      const StepInfo si = step_info(d.ctl, k);
+      close_group(d, si.par ^ 1u, si.step - 1u, d.ctl->stats_n0 + (uint32_t)k - 1u, b, s_wave);
+      return;
+    }
+    b -= d.ngroups;
+  }
+  resolve_body<kBrick, true>(d, k, b, d.nwg_sweep);
 }
 template <bool kBrick>
 __global__ __launch_bounds__(kThreads) void k_near_sweep(Dev d, int k) {
@@ -2354,6 +2801,23 @@ hipError_t launch_step(const Dev& d, int k, hipStream_t s, hipEvent_t ev_sweep0,
                        hipEvent_t ev_sweep1) {
   for (int m = 0; d.md_theta > 0 && m <= d.md_theta; ++m)
     k_md<<<blocks_for(d.n, kThreads), kThreads, 0, s>>>(d, k, m);
+  if (d.bricklist) {  // two kernels: sweep, then the closing of step k - 1 with the resolve
+    const dim3 g(d.nwg_sweep), b(kThreads);
+    if (d.bs > kOneCellBrick) {
+      if (ev_sweep0)
+        hipExtLaunchKernelGGL(k_sweep<true, true, true>, g, b, 0, s, ev_sweep0, ev_sweep1, 0, d, k);
+      else
+        k_sweep<true, true, true><<<g, b, 0, s>>>(d, k);
+    } else {
+      if (ev_sweep0)
+        hipExtLaunchKernelGGL(k_sweep<true, false, true>, g, b, 0, s, ev_sweep0, ev_sweep1, 0, d,
+                              k);
+      else
+        k_sweep<true, false, true><<<g, b, 0, s>>>(d, k);
+    }
+    k_resolve<true><<<(d.nwg_sweep + 3) / 4 + (k > 0 ? d.ngroups : 0), kThreads, 0, s>>>(d, k);
+    return hipGetLastError();
+  }
   const int prep_blocks = d.nwg_prep + (k > 0 ? d.ngroups : 0);
   k_prep<<<prep_blocks, kThreads, 0, s>>>(d, k);
   const dim3 g(d.nwg_sweep), b(kThreads);
@@ -2392,19 +2856,19 @@ hipError_t launch_step(const Dev& d, int k, hipStream_t s, hipEvent_t ev_sweep0,
   }
   if (d.sorted && d.bs > kOneCellBrick) {
     if (ev_sweep0)
-      hipExtLaunchKernelGGL(k_sweep<true, true>, g, b, 0, s, ev_sweep0, ev_sweep1, 0, d, k);
+      hipExtLaunchKernelGGL(k_sweep<true, true, false>, g, b, 0, s, ev_sweep0, ev_sweep1, 0, d, k);
     else
-      k_sweep<true, true><<<g, b, 0, s>>>(d, k);
+      k_sweep<true, true, false><<<g, b, 0, s>>>(d, k);
   } else if (d.sorted) {
     if (ev_sweep0)
-      hipExtLaunchKernelGGL(k_sweep<true, false>, g, b, 0, s, ev_sweep0, ev_sweep1, 0, d, k);
+      hipExtLaunchKernelGGL(k_sweep<true, false, false>, g, b, 0, s, ev_sweep0, ev_sweep1, 0, d, k);
     else
-      k_sweep<true, false><<<g, b, 0, s>>>(d, k);
+      k_sweep<true, false, false><<<g, b, 0, s>>>(d, k);
   } else {
     if (ev_sweep0)
-      hipExtLaunchKernelGGL(k_sweep<false, false>, g, b, 0, s, ev_sweep0, ev_sweep1, 0, d, k);
+      hipExtLaunchKernelGGL(k_sweep<false, false, false>, g, b, 0, s, ev_sweep0, ev_sweep1, 0, d, k);
     else
-      k_sweep<false, false><<<g, b, 0, s>>>(d, k);
+      k_sweep<false, false, false><<<g, b, 0, s>>>(d, k);
   }
   if (d.sorted)
     k_resolve<true><<<(d.nwg_sweep + 3) / 4, kThreads, 0, s>>>(d, k);
