@@ -317,8 +317,8 @@ def main():
                          "closest partner (nearest)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--sort-period", type=int, default=-1)
-    ap.add_argument("--bricklist", type=int, default=1, choices=[0, 1],
-                    help="carry the A's forward in brick lists (1) or bin them every step (0)")
+    ap.add_argument("--fused-binning", type=int, default=1, choices=[0, 1],
+                    help="the sweep bins the next step's A's (1) or a kernel bins them (0)")
     ap.add_argument("--brick", default="0",
                     help="brick edge in coarse cells, 1..6 (0 = the library default, 4), "
                          "or 'auto': the device autotuner's choice for the workload "
@@ -379,7 +379,7 @@ def main():
                           log_cap=cfg.N * 2, stream=stream, brick=brick)
     if args.sort_period >= 0:
         sysm.set_sort_period(args.sort_period)
-    sysm.set_bricklist(bool(args.bricklist))
+    sysm.set_fused_binning(bool(args.fused_binning))
     sort_period = 64 if args.sort_period < 0 else args.sort_period
     sysm.generate(cfg.kind, cfg.gen_seed, workload.SIGMA_LATTICE)
     first = 1
@@ -452,7 +452,7 @@ def main():
                                   cfg.sigma),
                    "steps_timed": K, "sort_period": sort_period,
                    "brick": sysm.geometry()[1], "brick_autotune_us": tuned,
-                   "policy": args.policy, "brick_lists": sysm.bricklist(),
+                   "policy": args.policy, "fused_binning": sysm.fused_binning(),
                    "path": "graph replay (captured before the window)"},
         "window_ms": window_ms,
         "sorts_in_window": sorts_in,

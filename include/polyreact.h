@@ -355,23 +355,23 @@ int pr_sys_set_sort_period(pr_sys* s, int32_t sort_period);
  * on = 0: every kernel is launched directly.  Results are identical. */
 int pr_sys_set_graphs(pr_sys* s, int32_t on);
 
-/* Brick lists (step 1 of Table I, the candidate search, on sorted storage):
- * enable = 1 (default) lets a sorted handle with one rule, the random
- * selection and no MD keep its A's in per-brick lists that each step's sweep
- * carries forward to the next step, instead of re-binning every A into the
- * cell grid before every sweep (one kernel fewer per step).  The lists are
- * allocated on the first run that can use them (44 bytes per particle) and
- * set up by the spatial sort; they hold the A's of one reaction step, so a
- * run that does not continue the previous one (another first_step or sigma,
- * after pr_sys_jitter or pr_sys_set_md) sorts first.  A handle whose brick
- * edge leaves a last brick of one cell with four or more bricks per side
- * bins as before.  enable = 0: always bin.  Results are identical.  PR_EINVAL
- * for enable outside {0, 1}. */
-int pr_sys_set_bricklist(pr_sys* s, int32_t enable);
+/* Fused binning (Table I step 1, the candidate search): enable = 1 (default)
+ * lets a handle on sorted storage with one rule, the random selection and no
+ * MD skip the binning kernel: each step's sweep bins the A's of the next step
+ * (at their positions re-jittered once more) into cell buckets of its own,
+ * and the resolve drops or adds the A's whose roles its bonds change, so a
+ * step is two kernels.  The buckets are allocated on the first run that can
+ * use them (about 2 x 160 bytes per cell and 40 per particle) and filled by
+ * the spatial sort; they hold the A's of one reaction step, so a run that
+ * does not continue the previous one (another first_step or sigma, after
+ * pr_sys_jitter or pr_sys_set_md) sorts first.  enable = 0: the binning
+ * kernel runs before every sweep.  Results are identical.  PR_EINVAL for
+ * enable outside {0, 1}. */
+int pr_sys_set_fused_binning(pr_sys* s, int32_t enable);
 
-/* *active = 1 when the handle's next step runs on brick lists (as the last
- * run left it), else 0. */
-int pr_sys_bricklist(pr_sys* s, int32_t* active);
+/* *active = 1 when the handle's next step uses fused binning (as the last run
+ * left it), else 0. */
+int pr_sys_fused_binning(pr_sys* s, int32_t* active);
 
 
 /* Bandwidth probe: copies bytes from src to dst (device memory, bytes a

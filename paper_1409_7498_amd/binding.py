@@ -115,8 +115,8 @@ def _load():
         "pr_sys_stats": ([vp, P(Stats), i64, P(i64)], C.c_int),
         "pr_sys_set_sort_period": ([vp, i32], C.c_int),
         "pr_sys_set_graphs": ([vp, i32], C.c_int),
-        "pr_sys_set_bricklist": ([vp, i32], C.c_int),
-        "pr_sys_bricklist": ([vp, C.POINTER(i32)], C.c_int),
+        "pr_sys_set_fused_binning": ([vp, i32], C.c_int),
+        "pr_sys_fused_binning": ([vp, C.POINTER(i32)], C.c_int),
         "pr_batch_create": ([P(vp), P(ReplicaDesc), i32, vp], C.c_int),
         "pr_batch_destroy": ([vp], None),
         "pr_batch_run": ([vp, u32, u32, f64], C.c_int),
@@ -154,8 +154,8 @@ def exported_symbols():
                         "pr_sys_create_ex", "pr_sys_geometry", "pr_autotune",
                         "pr_sys_destroy", "pr_sys_load", "pr_sys_generate", "pr_sys_run",
                         "pr_sys_run_timed", "pr_sys_read", "pr_sys_bonds", "pr_sys_stats",
-                        "pr_sys_set_sort_period", "pr_sys_set_graphs", "pr_sys_set_bricklist",
-                        "pr_sys_bricklist", "pr_batch_create",
+                        "pr_sys_set_sort_period", "pr_sys_set_graphs", "pr_sys_set_fused_binning",
+                        "pr_sys_fused_binning", "pr_batch_create",
                         "pr_batch_destroy", "pr_batch_run", "pr_batch_run_loop", "pr_batch_bonds",
                         "pr_batch_read", "pr_batch_stats", "pr_footprint", "pr_server_create",
                         "pr_server_destroy", "pr_server_submit", "pr_server_wait",
@@ -334,12 +334,12 @@ class System:
     def set_graphs(self, on):
         _check(lib.pr_sys_set_graphs(self._h, 1 if on else 0))
 
-    def set_bricklist(self, on):
-        _check(lib.pr_sys_set_bricklist(self._h, 1 if on else 0))
+    def set_fused_binning(self, on):
+        _check(lib.pr_sys_set_fused_binning(self._h, 1 if on else 0))
 
-    def bricklist(self):
+    def fused_binning(self):
         v = C.c_int32(0)
-        _check(lib.pr_sys_bricklist(self._h, C.byref(v)))
+        _check(lib.pr_sys_fused_binning(self._h, C.byref(v)))
         return bool(v.value)
 
     def read(self):

@@ -590,9 +590,10 @@ struct pr_sys {
   bool poisoned = false;
   int32_t sort_period = 0;
   int32_t use_graphs = 1;
-  // brick lists: allowed (pr_sys_set_bricklist), and the step and jitter
-  // scale the device records were last written for (rec_ok: they exist)
-  int32_t allow_bl = 1;
+  // fused binning: allowed (pr_sys_set_fused_binning), and the step and
+  // jitter scale the device's next-step A records were written for (rec_ok:
+  // they exist)
+  int32_t allow_fuse = 1;
   bool rec_ok = false;
   uint32_t rec_step = 0;
   float rec_jit = 0.0f;
@@ -604,7 +605,7 @@ struct pr_sys {
     bool sort = false;
     float jit = -1.0f;
     long long part = 0;
-    int32_t bl = 0;
+    int32_t fuse = 0;
     uint64_t used = 0;
   };
   std::vector<Seg> segs;
@@ -667,61 +668,55 @@ int grow_part(pr_sys* s, int64_t need) {
 // Unsorted storage until the first sort: sweep workgroups take consecutive slots.
 void set_dense(pr_sys* s) {
   s->d.sorted = 0;
-  s->d.bricklist = 0;
+  s->d.fuse = 0;
   s->d.nwg_sweep = sweep_blocks(s->d.n);
   s->rec_ok = false;
 }
 
-// Whether the sorted storage of a system can keep its A's in brick lists:
-// one rule with the random selection, no MD, the lists allocated, and every
-// home A within the cutoff of a point on the lists of the bricks around the
-// point's brick.  That holds with at most three bricks per side (all of them
-// are neighbours) and with edges of at least two cells when the last brick
-// of a side also has two or more.
-bool bl_eligible(const pr_sys* s) {
+// Whether the sweeps of a sorted system can bin the next step's A's
+// themselves: one rule with the random selection, no MD (the MD moves the
+// particles between steps), the buckets allocated.
+bool fuse_eligible(const pr_sys* s) {
   const Dev& d = s->d;
-  if (!s->allow_bl || d.nrules != 1 || d.rule.policy != PR_POLICY_RANDOM || d.md_theta > 0 ||
-      !d.arec[0])
-    return false;
-  if (d.nb <= 3) return true;
-  const int tail = d.nc % d.bs;
-  return d.bs >= 2 && (tail == 0 || tail >= 2);
+  return s->allow_fuse && d.nrules == 1 && d.rule.policy == PR_POLICY_RANDOM && d.md_theta == 0 &&
+         d.fcnt[0] != nullptr;
 }
 
-// The brick-list buffers, allocated on the first run that can use them.
-int alloc_bricklist(pr_sys* s) {
+// The fused-binning buckets, allocated on the first run that can use them.
+int alloc_fused(pr_sys* s) {
   Dev& d = s->d;
-  if (d.arec[0] || !s->allow_bl || d.nrules != 1 || d.rule.policy != PR_POLICY_RANDOM) return PR_OK;
+  if (d.fcnt[0] || !s->allow_fuse || d.nrules != 1 || d.rule.policy != PR_POLICY_RANDOM)
+    return PR_OK;
   Dev t = d;
-  const size_t n = (size_t)d.n, nb = (size_t)d.nbricks;
-  int e = s->arena.alloc(&t.arec[0], n);
-  if (!e) e = s->arena.alloc(&t.arec[1], n);
-  if (!e) e = s->arena.alloc(&t.bna, nb);
+  const size_t n = (size_t)d.n, nrec = (size_t)d.ncell * kCellCap;
+  int e = 0;
+  for (int q = 0; q < 3 && !e; ++q) e = s->arena.alloc(&t.fcnt[q], (size_t)d.ncell);
   for (int p = 0; p < 2 && !e; ++p) {
-    if (!e) e = s->arena.alloc(&t.xcnt[p], nb);
-    if (!e) e = s->arena.alloc(&t.xlist[p], nb * kXCap);
+    if (!e) e = s->arena.alloc(&t.frec[p], nrec);
+    if (!e) e = s->arena.alloc(&t.fsa[p], nrec);
+    if (!e) e = s->arena.alloc(&t.fovf[p], n);
+    if (!e) e = s->arena.alloc(&t.fovf_sa[p], n);
   }
-  if (!e) e = s->arena.alloc(&t.scnt, 3);
-  for (int q = 0; q < 3 && !e; ++q) e = s->arena.alloc(&t.sslot[q], n);
+  if (!e) e = s->arena.alloc(&t.apos, n);
   if (e) return e;  // what was allocated stays in the arena until destroy
-  d.arec[0] = t.arec[0];
-  d.arec[1] = t.arec[1];
-  d.bna = t.bna;
+  for (int q = 0; q < 3; ++q) d.fcnt[q] = t.fcnt[q];
   for (int p = 0; p < 2; ++p) {
-    d.xcnt[p] = t.xcnt[p];
-    d.xlist[p] = t.xlist[p];
+    d.frec[p] = t.frec[p];
+    d.fsa[p] = t.fsa[p];
+    d.fovf[p] = t.fovf[p];
+    d.fovf_sa[p] = t.fovf_sa[p];
   }
-  d.scnt = t.scnt;
-  for (int q = 0; q < 3; ++q) d.sslot[q] = t.sslot[q];
+  d.apos = t.apos;
   drop_graph(s);
   return PR_OK;
 }
 
-// A run from step first_step with jitter scale jit: the device records of
-// the brick lists hold the A's of one step only, so a run that does not
-// continue the last one sorts (and rewrites them) first.
-void bl_check_run(pr_sys* s, uint32_t first_step) {
-  if (!s->d.sorted || !s->d.bricklist) return;
+// A run from step first_step with jitter scale jit: with fused binning the
+// device holds the A records of one step only (binned at their re-jittered
+// positions), so a run that does not continue the last one sorts (and bins
+// them again) first.
+void fuse_check_run(pr_sys* s, uint32_t first_step) {
+  if (!s->d.sorted || !s->d.fuse) return;
   if (s->rec_ok && s->rec_step == first_step && s->rec_jit == s->d.jit_c) return;
   if (s->sort_period > 0)
     s->steps_since_sort = s->sort_period;
@@ -730,8 +725,8 @@ void bl_check_run(pr_sys* s, uint32_t first_step) {
   s->rec_ok = false;
 }
 
-void bl_after_run(pr_sys* s, uint32_t first_step, uint32_t n_steps) {
-  s->rec_ok = s->d.sorted && s->d.bricklist;
+void fuse_after_run(pr_sys* s, uint32_t first_step, uint32_t n_steps) {
+  s->rec_ok = s->d.sorted && s->d.fuse;
   s->rec_step = first_step + n_steps;
   s->rec_jit = s->d.jit_c;
 }
@@ -761,7 +756,7 @@ int after_load(pr_sys* s) {
 // Counting sort of the storage by brick (writes the other storage set);
 // afterwards the sweep runs per brick.
 int sort_storage(pr_sys* s, hipStream_t st) {
-  s->d.bricklist = bl_eligible(s) ? 1 : 0;
+  s->d.fuse = fuse_eligible(s) ? 1 : 0;
   HIP_TRY(launch_sort(s->d, st));
   s->d.sorted = 1;
   s->d.nwg_sweep = s->d.nbricks;
@@ -809,7 +804,7 @@ int32_t next_segment(const pr_sys* s, uint32_t left, bool* with_sort) {
 // side).
 void after_segment(pr_sys* s, int32_t K, bool with_sort) {
   if (with_sort) {
-    s->d.bricklist = bl_eligible(s) ? 1 : 0;
+    s->d.fuse = fuse_eligible(s) ? 1 : 0;
     s->d.sorted = 1;
     s->d.nwg_sweep = s->d.nbricks;
     s->steps_since_sort = K;
@@ -824,7 +819,7 @@ int segment_graph(pr_sys* s, int32_t K, bool with_sort, hipGraphExec_t* out) {
   const long long part = (long long)(size_t)s->d.part;
   for (pr_sys::Seg& g : s->segs)
     if (g.steps == K && g.sort == with_sort && g.jit == s->d.jit_c && g.part == part &&
-        g.bl == s->d.bricklist) {
+        g.fuse == s->d.fuse) {
       g.used = ++s->seg_clock;
       *out = g.gexec;
       return PR_OK;
@@ -863,7 +858,7 @@ int segment_graph(pr_sys* s, int32_t K, bool with_sort, hipGraphExec_t* out) {
   seg.sort = with_sort;
   seg.jit = s->d.jit_c;
   seg.part = part;
-  seg.bl = s->d.bricklist;
+  seg.fuse = s->d.fuse;
   seg.used = ++s->seg_clock;
   s->segs.push_back(seg);
   *out = ge;
@@ -1063,13 +1058,13 @@ int pr_sys_set_sort_period(pr_sys* s, int32_t sort_period) {
   return PR_OK;
 }
 
-int pr_sys_set_bricklist(pr_sys* s, int32_t enable) {
+int pr_sys_set_fused_binning(pr_sys* s, int32_t enable) {
   int e = check_sys(s, false);
   if (e) return e;
   if (enable != 0 && enable != 1) return fail(PR_EINVAL, "enable=%d (0 or 1)", enable);
-  s->allow_bl = enable;
+  s->allow_fuse = enable;
   drop_graph(s);
-  // the next run sorts first, and takes up (or leaves) the lists there
+  // the next run sorts first, and takes up (or leaves) fused binning there
   if (s->d.sorted && s->sort_period > 0)
     s->steps_since_sort = s->sort_period;
   else
@@ -1078,11 +1073,11 @@ int pr_sys_set_bricklist(pr_sys* s, int32_t enable) {
   return PR_OK;
 }
 
-int pr_sys_bricklist(pr_sys* s, int32_t* active) {
+int pr_sys_fused_binning(pr_sys* s, int32_t* active) {
   int e = check_sys(s, false);
   if (e) return e;
   if (!active) return fail(PR_EINVAL, "active is NULL");
-  *active = s->d.sorted && s->d.bricklist ? 1 : 0;
+  *active = s->d.sorted && s->d.fuse ? 1 : 0;
   return PR_OK;
 }
 
@@ -1095,9 +1090,9 @@ static int run_impl(pr_sys* s, uint32_t first_step, uint32_t n_steps, double sig
   if (s->d.md_theta > 0 && sigma != 0.0)
     return fail(PR_EINVAL, "the MD of pr_sys_set_md moves the particles: sigma must be 0");
   if ((e = grow_part(s, s->steps_since_load + n_steps))) return e;
-  if ((e = alloc_bricklist(s))) return e;
+  if ((e = alloc_fused(s))) return e;
   s->d.jit_c = (float)(sigma / std::sqrt(21845.0));  // unit-variance offsets
-  bl_check_run(s, first_step);
+  fuse_check_run(s, first_step);
   hipStream_t st = s->stream;
   HIP_TRY(launch_ctl_reset(s->d.ctl, first_step, 0, st));
   if (ms) {
@@ -1146,7 +1141,7 @@ static int run_impl(pr_sys* s, uint32_t first_step, uint32_t n_steps, double sig
     }
     for (auto& v : ev) (void)hipEventDestroy(v);
     s->steps_since_load += n_steps;
-    bl_after_run(s, first_step, n_steps);
+    fuse_after_run(s, first_step, n_steps);
     return PR_OK;
   }
   uint32_t left = n_steps;
@@ -1165,7 +1160,7 @@ static int run_impl(pr_sys* s, uint32_t first_step, uint32_t n_steps, double sig
     left -= (uint32_t)K;
   }
   s->steps_since_load += n_steps;
-  bl_after_run(s, first_step, n_steps);
+  fuse_after_run(s, first_step, n_steps);
   return PR_OK;
 }
 
@@ -1185,7 +1180,7 @@ int pr_sys_prepare(pr_sys* s, uint32_t n_steps, double sigma) {
     return fail(PR_EINVAL, "sigma=%g", sigma);
   if (!s->use_graphs) return PR_OK;
   if ((e = grow_part(s, s->steps_since_load + n_steps))) return e;
-  if ((e = alloc_bricklist(s))) return e;
+  if ((e = alloc_fused(s))) return e;
   s->d.jit_c = (float)(sigma / std::sqrt(21845.0));
   // walk the segments the run would take, capturing each, then restore the
   // host-side state (nothing ran)
@@ -1211,8 +1206,8 @@ int pr_sys_set_md(pr_sys* s, int32_t theta, double dt, double sig, double eps, d
   if (e) return e;
   if (theta < 0 || theta > 100000) return fail(PR_EINVAL, "theta=%d", theta);
   drop_graph(s);
-  // the next run sorts first: brick lists (the MD moves the particles
-  // between reaction steps) are set up or dropped there
+  // the next run sorts first: fused binning (the MD moves the particles
+  // between reaction steps) is taken up or left there
   if (s->d.sorted && s->sort_period > 0)
     s->steps_since_sort = s->sort_period;
   else
@@ -1284,7 +1279,7 @@ int pr_sys_jitter(pr_sys* s, uint32_t first_step, uint32_t n_steps, double sigma
     return PR_OK;
   }
   s->d.jit_c = (float)(sigma / std::sqrt(21845.0));
-  s->rec_ok = false;  // the particles move: brick-list records are rewritten by a sort
+  s->rec_ok = false;  // the particles move: the next run bins again (after a sort)
   hipStream_t st = s->stream;
   HIP_TRY(launch_ctl_reset(s->d.ctl, first_step, 0, st));
   if (!kernel_ms) {
@@ -1967,7 +1962,7 @@ int pr_batch_run(pr_batch* b, uint32_t first_step, uint32_t n_steps, double sigm
     if ((e = grow_part(s, s->steps_since_load + n_steps))) return e;
     s->d.jit_c = (float)(sigma / std::sqrt(21845.0));
     s->d.sorted = 1;
-    s->d.bricklist = 0;  // the batched kernels bin the A's every step
+    s->d.fuse = 0;  // the batched kernels bin the A's every step
     s->rec_ok = false;
     s->d.nwg_sweep = s->d.nbricks;
     b->hds[r] = s->d;
@@ -2247,7 +2242,7 @@ int srv_launch_round(pr_server* S) {
     pr_sys* s = r->sys;
     const int32_t kl = (int32_t)std::min<uint32_t>((uint32_t)Kmax, r->n_steps - r->done_steps);
     s->d.sorted = 1;
-    s->d.bricklist = 0;  // the batched kernels bin the A's every step
+    s->d.fuse = 0;  // the batched kernels bin the A's every step
     s->rec_ok = false;
     s->d.nwg_sweep = s->d.nbricks;
     S->hds[i] = s->d;

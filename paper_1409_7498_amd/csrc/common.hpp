@@ -47,13 +47,6 @@ constexpr int kKinMaxBins = 256;    // kinetics counters: distance bins per call
 
 enum WgOut { kOutTElig = 0, kOutInRc, kOutDrawn, kOutExcl, kOutRet, kOutProp, kOutBonds, kOutLost,
              kOutAElig };
-// Brick lists (sorted storage): A records of the next step are written by each
-// A's own sweep workgroup, by brick, without atomics.  kXCap: A's beyond a
-// brick's sort-time A's (chain growth: new active ends) a brick lists.
-constexpr int kXCap = 32;
-// Record flags in the id word of a brick-list record: not an A in that step /
-// outside its home brick's region (then on the stray list, not the brick's).
-constexpr uint32_t kRecDead = 0x80000000u, kRecStray = 0x40000000u, kRecId = 0x3FFFFFFFu;
 
 // Device control block.  Steps are launched in blocks of K steps; the kernels
 // of step k of a block use step0 + k and parity (par0 + k) & 1, so a captured
@@ -68,6 +61,7 @@ struct Ctl {
   uint32_t nwin_ovf[2];   // bonds beyond kWinCap, by parity
   uint32_t stats_n0;   // counter-log index of the block's first step
   uint64_t log_n;      // rows appended to the bond log (may exceed capacity)
+  uint32_t fovf_n[3];  // fused binning: A records beyond their bucket, by step mod 3
 };
 
 struct RuleD {
@@ -160,17 +154,19 @@ struct Dev {
   int32_t nrules;
   RuleX mr[kMaxRules];
   uint8_t *wfa, *wft;   // per slot: won as an A / as a T in this step (one writer each)
-  // brick lists (bricklist = 1: sorted storage, one rule, random selection,
-  // no MD, brick edge >= 2): the A records of a step by slot, (x, y, z, id |
-  // flags), for parity p; sort-time A's per brick (the first bna[b] slots of
-  // brick b); further A's of brick b by parity (count xcnt, slots xlist); A's
-  // outside their brick's region on the stray list of (step mod 3)
-  int32_t bricklist;
-  float4* arec[2];
-  int32_t* bna;
-  int32_t *xcnt[2], *xlist[2];
-  uint32_t* scnt;       // 3 counts
-  int32_t* sslot[3];
+  // fused binning (fuse = 1: sorted storage, one rule, random selection, no
+  // MD): the sweep of step k bins the A records of step k + 1 itself, so no
+  // binning kernel runs.  Counts by step mod 3 (read in step k, filled for
+  // k + 1, cleared for k + 2), bucket records and overflow by step parity;
+  // apos[slot]: where the A's record of the next step went (bucket index, or
+  // -1 - overflow index), for the resolve to drop it if the A's role ends
+  int32_t fuse;
+  uint32_t* fcnt[3];
+  float4* frec[2];
+  int32_t* fsa[2];
+  float4* fovf[2];
+  int32_t* fovf_sa[2];
+  int32_t* apos;
   // bonded-force coupling (md_theta > 0): md_theta velocity-Verlet steps with
   // the mirror-LJ bond force before each reaction step, instead of the
   // re-jitter; slot_of maps ids to slots of the current storage set

@@ -229,6 +229,9 @@ __device__ __forceinline__ StepInfo step_info(const Ctl* c, int k) {
   return StepInfo{s0 + (uint32_t)k, (p0 + (uint32_t)k) & 1u};
 }
 
+// Buffers kept by step mod 3 (fused binning).
+__device__ __forceinline__ uint32_t mod3(uint32_t step) { return step % 3u; }
+
 // Exclusive prefix sum over the workgroup (wave64 shuffles, then wave
 // totals in LDS).  Every thread of the block must call it.
 __device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t* s_wave,
@@ -381,10 +384,10 @@ __device__ void close_group(const Dev& d, uint32_t par, uint32_t step, uint32_t 
     pre[0] = staged[0];
     pre[1] = staged[1];
   }
-  // the A's of the step: counted by the sweep workgroups (brick lists), else
+  // the A's of the step: counted by the sweep workgroups (fused binning), else
   // by the binning workgroups (strided over the groups)
-  int a_elig = d.bricklist ? o[kOutAElig] : 0;
-  for (int q = w; !d.bricklist && q < d.nwg_prep; q += d.ngroups * kGroup)
+  int a_elig = d.fuse ? o[kOutAElig] : 0;
+  for (int q = w; !d.fuse && q < d.nwg_prep; q += d.ngroups * kGroup)
     a_elig += pick(d.abst, par)[q];
   const uint32_t nw = (uint32_t)min(o[kOutBonds], kWinCap);
   uint32_t tot = 0;
@@ -602,11 +605,35 @@ __device__ __forceinline__ bool row_has(const int32_t* row, int B, int32_t v) {
   return false;
 }
 
+// The A records of a step: per-cell counts and bucket records with the A's
+// slots, then the overflow list.
+struct Buckets {
+  const uint32_t* cnt;
+  const float4* rec;
+  const int32_t* sa;
+  const float4* ovf;
+  const int32_t* osa;
+  uint32_t novf;
+};
+
+// Those of step `step` (parity par): filled by the binning kernel (kF =
+// false), or with fused binning by the previous step's sweep.
+template <bool kF>
+__device__ __forceinline__ Buckets step_buckets(const Dev& d, uint32_t par, uint32_t step) {
+  if (kF) {
+    const uint32_t q = mod3(step);
+    return Buckets{d.fcnt[q], pick(d.frec, par), pick(d.fsa, par), pick(d.fovf, par),
+                   pick(d.fovf_sa, par), d.ctl->fovf_n[q]};
+  }
+  return Buckets{pick(d.cnt, par), d.rec, d.rsa, pick(d.ovf, par), pick(d.ovf_sa, par),
+                 d.ctl->ovf_n[par]};
+}
+
 // Visits the A records (record, slot of the A) of the 2x2x2 cell block around
-// (x, y, z) in the global buckets, then the overflow list.
+// (x, y, z) in the buckets, then the overflow list.
 template <typename F>
-__device__ __forceinline__ void for_global_records(const Dev& d, uint32_t par, uint32_t novf,
-                                                   float x, float y, float z, F f) {
+__device__ __forceinline__ void for_global_records(const Dev& d, const Buckets& bk, float x,
+                                                   float y, float z, F f) {
   const int nc = d.nc;
   int cx0, cx1, cy0, cy1, cz0, cz1;
   lo_hi(x, d.inv_w, nc, cx0, cx1);
@@ -618,14 +645,12 @@ __device__ __forceinline__ void for_global_records(const Dev& d, uint32_t par, u
     const int ia = q >> 2, ib = (q >> 1) & 1, ie = q & 1;
     if (ia >= m || ib >= m || ie >= m) continue;
     const int c = ((ia ? cz1 : cz0) * nc + (ib ? cy1 : cy0)) * nc + (ie ? cx1 : cx0);
-    uint32_t nr = pick(d.cnt, par)[c];
+    uint32_t nr = bk.cnt[c];
     nr = nr < (uint32_t)kCellCap ? nr : (uint32_t)kCellCap;
     const size_t r0 = (size_t)c * kCellCap;
-    for (uint32_t r = 0; r < nr; ++r) f(d.rec[r0 + r], d.rsa[r0 + r]);
+    for (uint32_t r = 0; r < nr; ++r) f(bk.rec[r0 + r], bk.sa[r0 + r]);
   }
-  const float4* ovf = pick(d.ovf, par);
-  const int32_t* osa = pick(d.ovf_sa, par);
-  for (uint32_t r = 0; r < novf; ++r) f(ovf[r], osa[r]);
+  for (uint32_t r = 0; r < bk.novf; ++r) f(bk.ovf[r], bk.osa[r]);
 }
 
 // Staged region of a brick along one dimension: the brick's cells plus one
@@ -667,144 +692,38 @@ __device__ __forceinline__ int local_of(int c, int base, int nc) {
 }
 
 // ---------------------------------------------------------------------------
-// Brick lists (sorted storage).  The A's of step k are the records arec[p][slot]
-// (x, y, z, id | flags) of: the first bna[b] slots of every brick b (its A's
-// at the last sort), the slots xlist[p][b] of A's that appeared in brick b
-// since (chain growth), and the stray list of (step mod 3).  An A is "home"
-// while its cell lies in the region of its brick (the brick's cells plus one
-// cell layer); else its record carries kRecStray and it is on the stray list
-// instead.  With brick edges of at least two cells, every A within the cutoff
-// of a point lies on the lists of the (at most 27 distinct) bricks around the
-// point's brick, or on the stray list.
+// Fused binning.  The sweep of step k writes the A records of step k + 1 into
+// cell buckets of their own (counts by step mod 3, records by step parity):
+// each A's own sweep workgroup re-jitters it once more and appends it to the
+// bucket of its cell.  The resolve of step k then drops the record of an A
+// whose bond ends its A role (its x becomes NaN: no distance test with it
+// passes) and appends a T that takes the A role.
 // ---------------------------------------------------------------------------
-// The brick coordinates (bx, by, bz) of brick index b.
-__device__ __forceinline__ void brick_xyz(const Dev& d, int b, int& bx, int& by, int& bz) {
-  bz = div_nb(d, div_nb(d, b, bx), by);
-}
-
-// Neighbour t (0 .. 26) of brick (bx, by, bz): false when, with fewer than
-// three bricks per side, the offset repeats a brick another t already names.
-__device__ __forceinline__ bool brick_neighbour(const Dev& d, int bx, int by, int bz, int t,
-                                                int& nbr) {
-  const int o[3] = {t % 3 - 1, (t / 3) % 3 - 1, t / 9 - 1};
-  const int c[3] = {bx, by, bz};
-  int q[3];
-  for (int e = 0; e < 3; ++e) {
-    if (d.nb == 1 && o[e] != 0) return false;
-    if (d.nb == 2 && o[e] < 0) return false;
-    int v = c[e] + o[e];
-    v = v < 0 ? v + d.nb : (v >= d.nb ? v - d.nb : v);
-    q[e] = v;
-  }
-  nbr = (q[2] * d.nb + q[1]) * d.nb + q[0];
-  return true;
-}
-
-// Whether a position's cell lies in the region (cells base + [0, ext) per
-// dimension, modulo nc) of a brick.
-__device__ __forceinline__ bool in_region(const Dev& d, float x, float y, float z, int bx0,
-                                          int ex, int by0, int ey, int bz0, int ez, int& cl) {
-  const int nc = d.nc;
-  int lx = cell1(__fmul_rn(x, d.inv_w), nc) - bx0;
-  int ly = cell1(__fmul_rn(y, d.inv_w), nc) - by0;
-  int lz = cell1(__fmul_rn(z, d.inv_w), nc) - bz0;
-  lx += lx < 0 ? nc : 0;
-  ly += ly < 0 ? nc : 0;
-  lz += lz < 0 ? nc : 0;
-  cl = (lz * ey + ly) * ex + lx;
-  return lx < ex && ly < ey && lz < ez;
-}
-
-// The stray list that holds the A's of reaction step `step`.
-__device__ __forceinline__ uint32_t stray_list(uint32_t step) { return step % 3u; }
-
-// Visits, with the lanes of one wavefront, every A record of step parity par
-// that can lie within the cutoff of (x, y, z) (the same point in every lane):
-// the lists of the bricks around the point's brick and the stray list q,
-// flattened into one index range of which this lane takes first, first +
-// stride, ... (kB records in flight per lane).  f(record with the plain id
-// in w, the A's slot).  Every lane of the wavefront must call it.
-template <int kB, typename F>
-__device__ __forceinline__ void wave_brick_records(const Dev& d, uint32_t par, uint32_t q, float x,
-                                                   float y, float z, int first, int stride, F f) {
-  const int lane = __lane_id(), nc = d.nc;
-  const int cx = cell1(__fmul_rn(x, d.inv_w), nc), cy = cell1(__fmul_rn(y, d.inv_w), nc),
-            cz = cell1(__fmul_rn(z, d.inv_w), nc);
-  const int bx = d.nbricks > 1 ? cx / d.bs : 0, by = d.nbricks > 1 ? cy / d.bs : 0,
-            bz = d.nbricks > 1 ? cz / d.bs : 0;
-  // lane t < 27: neighbour brick t (start, sort-time A's, index); lane 27: the
-  // stray list; their record counts, prefix-summed over the lanes
-  int b = 0, st = 0, na = 0, cnt = 0;
-  if (lane < 27) {
-    if (brick_neighbour(d, bx, by, bz, lane, b)) {
-      st = d.bstart[b];
-      na = d.bna[b];
-      cnt = na + min(pick(d.xcnt, par)[b], kXCap);
-    }
-  } else if (lane == 27) {
-    cnt = (int)min(d.scnt[q], (uint32_t)d.n);
-  }
-  int incl = cnt;
-#pragma unroll
-  for (int o = 1; o < 32; o <<= 1) {
-    const int v = __shfl_up(incl, o);
-    if (lane >= o) incl += v;
-  }
-  const int pre = incl - cnt;
-  const int tot = __shfl(incl, 27);
-  const float4* rec = pick(d.arec, par);
-  const int32_t* xl = pick(d.xlist, par);
-  const int32_t* sl = d.sslot[q];
-  for (int i0 = first; __shfl(i0, 0) < tot; i0 += kB * stride) {
-    float4 r[kB];
-    int slot[kB], src[kB];
-#pragma unroll
-    for (int u = 0; u < kB; ++u) {
-      const int i = i0 + u * stride;
-      // the source of flat index i: the last t in [0, 27] with pre[t] <= i
-      int t = 0;
-#pragma unroll
-      for (int h = 16; h > 0; h >>= 1) {
-        const int m = t + h;
-        const int pm = __shfl(pre, m < 28 ? m : 27);
-        if (m < 28 && pm <= i) t = m;
-      }
-      const int j = i - __shfl(pre, t);
-      const int tst = __shfl(st, t), tna = __shfl(na, t), tb = __shfl(b, t);
-      src[u] = t;
-      slot[u] = -1;
-      if (i < tot) {
-        slot[u] = t == 27 ? sl[j] : (j < tna ? tst + j : xl[tb * kXCap + (j - tna)]);
-        r[u] = rec[slot[u]];
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < kB; ++u) {
-      if (slot[u] < 0) continue;
-      const uint32_t w = __float_as_uint(r[u].w);
-      // home lists take home records, the stray list its stray ones
-      if ((w & kRecDead) || ((w & kRecStray) != 0) != (src[u] == 27)) continue;
-      r[u].w = __uint_as_float(w & kRecId);
-      f(r[u], slot[u]);
-    }
+// Appends the record of A (slot, id) at (x, y, z) to the buckets of step
+// `step` (parity par) and notes where it went.
+__device__ __forceinline__ void fuse_bin(const Dev& d, uint32_t par, uint32_t step, int slot,
+                                         uint32_t id, float x, float y, float z) {
+  const int c = cell_of(d, x, y, z);
+  const uint32_t r = atomicAdd(&d.fcnt[mod3(step)][c], 1u);
+  const float4 rec = make_float4(x, y, z, __uint_as_float(id));
+  if (r < (uint32_t)kCellCap) {
+    const int q = c * kCellCap + (int)r;
+    pick(d.frec, par)[q] = rec;
+    pick(d.fsa, par)[q] = slot;
+    d.apos[slot] = q;
+  } else {
+    const uint32_t o = atomicAdd(&d.ctl->fovf_n[mod3(step)], 1u);
+    pick(d.fovf, par)[o] = rec;
+    pick(d.fovf_sa, par)[o] = slot;
+    d.apos[slot] = -1 - (int)o;
   }
 }
 
-// Writes the record of A (slot, id) for the step `step` at position (x, y,
-// z): stray when outside the region of its home brick (given), then listed
-// on the stray list of that step (a returning atomic; strays are rare).
-__device__ __forceinline__ void put_record(const Dev& d, uint32_t par, uint32_t step, int slot,
-                                           uint32_t id, float x, float y, float z, int bx0, int ex,
-                                           int by0, int ey, int bz0, int ez, bool unlisted) {
-  int cl;
-  const bool home =
-      !unlisted && (d.nbricks == 1 || in_region(d, x, y, z, bx0, ex, by0, ey, bz0, ez, cl));
-  pick(d.arec, par)[slot] = make_float4(x, y, z, __uint_as_float(id | (home ? 0u : kRecStray)));
-  if (!home) {
-    const uint32_t q = stray_list(step);
-    const uint32_t p = atomicAdd(&d.scnt[q], 1u);
-    if (p < (uint32_t)d.n) d.sslot[q][p] = slot;
-  }
+// Drops the record of the next step (parity par) of the A in `slot`.
+__device__ __forceinline__ void fuse_drop(const Dev& d, uint32_t par, int slot) {
+  const int q = d.apos[slot];
+  float* x = q >= 0 ? &pick(d.frec, par)[q].x : &pick(d.fovf, par)[-1 - q].x;
+  *x = __int_as_float(0x7FC00000);  // quiet NaN
 }
 
 // Slot range of sweep/resolve workgroup w.
@@ -935,10 +854,10 @@ __device__ __forceinline__ uint32_t lanes_below(unsigned long long b) {
 
 // kTwo: two region cells per thread while staging (brick edges above
 // kOneCellBrick); else one, with the smaller tables.
-// kBL: brick lists instead of the A grid (sorted storage of one system).
-template <bool kBrick, bool kTwo, bool kBL = false>
+// kF: fused binning (the sweep bins the next step's A records; sorted storage).
+template <bool kBrick, bool kTwo, bool kF = false>
 __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) {
-  static_assert(!kBL || kBrick, "brick lists need sorted storage");
+  static_assert(!kF || kBrick, "fused binning runs on sorted storage");
   constexpr int kCells = kTwo ? kStageCells : kStageCells1;  // region cells at most
   constexpr int kPer = kBrick ? kTPass / kThreads : 1;
   constexpr int kTP = kPer * kThreads;
@@ -955,16 +874,10 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
   __shared__ uint32_t s_ew2[kRetCap];
   __shared__ uint32_t s_wave[kThreads / 64 + 1];
   __shared__ int s_cnt[5];
-  __shared__ int s_qn, s_ndef, s_ne, s_dead;
-  // brick lists: the distinct neighbour bricks (start, sort-time A's, further
-  // A's, index), per region cell counts, kept records, this brick's new list
-  __shared__ int s_nbs[kBL ? 27 : 1], s_nbn[kBL ? 27 : 1], s_nbx[kBL ? 27 : 1],
-      s_nbb[kBL ? 27 : 1];
-  __shared__ uint32_t s_ccnt[kBL ? kCells : 1];
-  __shared__ int s_kept, s_ns, s_xn, s_na;
-  __shared__ int32_t s_xl[kBL ? kXCap : 1];
-  // brick lists: the A's of the brick at their positions of this step (slot
-  // in w), in the staging array the pass loop leaves idle
+  __shared__ int s_qn, s_ndef, s_ne, s_dead, s_na;
+  // fused binning: the A's of the brick at their positions of this step
+  // (slot in w), in the staging array the pass loop then leaves idle (the
+  // records carry no adjacency rows)
   float4* const s_apos = (float4*)s_radj;
   const int tid = threadIdx.x;
   if (tid < 5) s_cnt[tid] = 0;
@@ -972,6 +885,7 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
     s_qn = 0;
     s_ndef = 0;
     s_ne = 0;
+    s_na = 0;
     s_dead = read_err(d.ctl) != 0;
   }
   const Ctl* c = d.ctl;
@@ -983,7 +897,7 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
   const float *X = pick(a.x, par), *Y = pick(a.y, par), *Z = pick(a.z, par);
   float *XW = pick(a.x, par ^ 1u), *YW = pick(a.y, par ^ 1u), *ZW = pick(a.z, par ^ 1u);
   const bool jit = d.jitter && d.jit_c != 0.0f;
-  const uint32_t novf = c->ovf_n[par];
+  const Buckets bk = step_buckets<kF>(d, par, step);
   const RetList rl{&s_ne, s_ent, s_ew2};
   int s0, s1;
   range_of<kBrick>(d, w, s0, s1);
@@ -1018,119 +932,18 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
     ncs = ex * ey * ez;
     m_exy = recip16((uint32_t)(ex * ey));
     m_ex = recip16((uint32_t)ex);
-    if (kBL) {
-      // the lists of the neighbour bricks, the stray count; cleared counts
-      if (tid < 27) {
-        int b = 0;
-        const bool ok = brick_neighbour(d, bxc, byc, bzc, tid, b);
-        s_nbb[tid] = ok ? b : -1;
-        s_nbs[tid] = ok ? d.bstart[b] : 0;
-        s_nbn[tid] = ok ? d.bna[b] : 0;
-        s_nbx[tid] = ok ? min(pick(d.xcnt, par)[b], kXCap) : 0;
-      }
-      if (tid == 0) {
-        s_kept = 0;
-        s_xn = 0;
-        s_na = 0;
-        s_ns = (int)min(d.scnt[stray_list(step)], (uint32_t)d.n);
-        // the stray list two steps ahead is free: the next step's sweep fills it
-        if (w == 0) d.scnt[stray_list(step + 2u)] = 0u;
-      }
+    // the record counts of this thread's region cells (2 tid and 2 tid + 1,
+    // or tid), issued first
 #pragma unroll
-      for (int h = 0; h < (kTwo ? 2 : 1); ++h) {
-        const int cl = kTwo ? 2 * tid + h : tid;
-        if (cl < kCells) s_ccnt[cl] = 0u;
-      }
-    } else {
-      // the record counts of this thread's region cells (2 tid and 2 tid + 1,
-      // or tid), issued first
-#pragma unroll
-      for (int h = 0; h < (kTwo ? 2 : 1); ++h) {
-        const int cl = kTwo ? 2 * tid + h : tid;
-        if (cl < ncs) (h ? mine2 : mine) = pick(d.cnt, par)[region_cell(cl)];
-      }
+    for (int h = 0; h < (kTwo ? 2 : 1); ++h) {
+      const int cl = kTwo ? 2 * tid + h : tid;
+      if (cl < ncs) (h ? mine2 : mine) = bk.cnt[region_cell(cl)];
     }
   }
   // the first particle of the first pass, issued behind the record counts
   // (memory operations complete in issue order)
   Part cur = load_part<kBrick>(a, X, Y, Z, s0 + tid, s1);
-  int a_end = s0;  // brick lists: the end of this brick's sort-time A's
-  if (kBL) {
-    __syncthreads();
-    a_end = s0 + s_nbn[13];  // neighbour 13 is the brick itself
-    // kept records and their region cells go to arrays that are idle during
-    // staging (s_radj, s_tid, s_def)
-    float4* t_rec = (float4*)s_radj;
-    int32_t* t_sa = s_tid;
-    uint16_t* t_cl = s_def;
-    // sources: threads 0-215 take the 27 bricks (eight each), 216-255 the
-    // stray list; each loads up to kB records before it filters any
-    constexpr int kB = 4;
-    const int src = tid < 216 ? tid >> 3 : 27;
-    const int lane = tid < 216 ? (tid & 7) : tid - 216;
-    const int stride = tid < 216 ? 8 : 40;
-    const int nn = src < 27 ? s_nbn[src] : 0;
-    const int nsrc = src < 27 ? nn + s_nbx[src] : s_ns;
-    const float4* R = pick(d.arec, par);
-    const uint32_t q = stray_list(step);
-    for (int i0 = lane; i0 < nsrc; i0 += stride * kB) {
-      float4 r[kB];
-      int sl[kB];
-#pragma unroll
-      for (int u = 0; u < kB; ++u) {
-        const int i = i0 + u * stride;
-        sl[u] = -1;
-        if (i < nsrc) {
-          sl[u] = src < 27 ? (i < nn ? s_nbs[src] + i
-                                     : pick(d.xlist, par)[s_nbb[src] * kXCap + (i - nn)])
-                           : d.sslot[q][i];
-          r[u] = R[sl[u]];
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < kB; ++u) {
-        if (sl[u] < 0) continue;
-        const uint32_t fw = __float_as_uint(r[u].w);
-        // home lists take home records; the stray list its (stray) records
-        if ((fw & kRecDead) || ((fw & kRecStray) != 0) != (src == 27)) continue;
-        int cl;
-        if (!in_region(d, r[u].x, r[u].y, r[u].z, bx, ex, by, ey, bz, ez, cl)) continue;
-        const int kk = atomicAdd(&s_kept, 1);
-        if (kk < kStageRecs) {
-          t_rec[kk] = make_float4(r[u].x, r[u].y, r[u].z, __uint_as_float(fw & kRecId));
-          t_sa[kk] = sl[u];
-          t_cl[kk] = (uint16_t)cl;
-          atomicAdd(&s_ccnt[cl], 1u);
-        }
-      }
-    }
-    __syncthreads();
-    const uint32_t total = (uint32_t)s_kept;
-    staged = total <= (uint32_t)kStageRecs;
-#pragma unroll
-    for (int h = 0; h < (kTwo ? 2 : 1); ++h) {
-      const int cl = kTwo ? 2 * tid + h : tid;
-      if (cl < ncs) (h ? mine2 : mine) = s_ccnt[cl];
-    }
-    uint32_t tot = 0;
-    const uint32_t off = block_scan_excl(mine + mine2, s_wave, tot);
-#pragma unroll
-    for (int h = 0; h < (kTwo ? 2 : 1); ++h) {
-      const int cl = kTwo ? 2 * tid + h : tid;
-      if (cl < ncs) {
-        const uint32_t o = h ? off + mine : off;
-        s_off[cl] = (uint16_t)o;
-        s_ccnt[cl] = o;  // insert position
-      }
-    }
-    if (tid == 0) s_off[ncs] = (uint16_t)min(total, (uint32_t)kStageRecs);
-    __syncthreads();
-    if (staged && tid < (int)total) {
-      const uint32_t pos = atomicAdd(&s_ccnt[t_cl[tid]], 1u);
-      s_rec[pos] = t_rec[tid];
-      s_rsa[pos] = t_sa[tid];
-    }
-  } else if (kBrick) {
+  if (kBrick) {
     mine = mine < (uint32_t)kCellCap ? mine : (uint32_t)kCellCap;
     mine2 = mine2 < (uint32_t)kCellCap ? mine2 : (uint32_t)kCellCap;
     uint32_t total = 0;
@@ -1146,14 +959,14 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
       }
     }
     if (tid == 0) s_off[ncs] = (uint16_t)total;
-    staged = total <= (uint32_t)kStageRecs && novf == 0;
+    staged = total <= (uint32_t)kStageRecs && bk.novf == 0;
     __syncthreads();
     if (staged && tid < (int)total) {
       const int lo = s_rcell[tid];  // the region cell of record tid
       const size_t ri = (size_t)region_cell(lo) * kCellCap + (tid - (int)s_off[lo]);
-      s_rec[tid] = d.rec[ri];
-      s_rsa[tid] = d.rsa[ri];
-      if (d.adj_staged) s_radj[tid] = d.radj[ri];
+      s_rec[tid] = bk.rec[ri];
+      s_rsa[tid] = bk.sa[ri];
+      if (!kF && d.adj_staged) s_radj[tid] = d.radj[ri];
     }
   }
   __syncthreads();
@@ -1197,7 +1010,7 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
         *(float*)((char*)YW + bo) = cur.y;
         *(float*)((char*)ZW + bo) = cur.z;
       }
-      if (kBL && slot < s1 && cur.role == kRoleA) {  // kept for the next step's record
+      if (kF && slot < s1 && cur.role == kRoleA) {  // kept for the next step's record
         n.a_elig++;
         const int p = atomicAdd(&s_na, 1);
         if (p < kStageRecs) s_apos[p] = make_float4(cur.x, cur.y, cur.z, __int_as_float(slot));
@@ -1295,28 +1108,13 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
         if (q == kQEmpty) continue;
         const uint32_t lt = q & 0xFFFFu, r = q >> 16;
         retain(d, a, step, __float_as_int(s_rec[r].w), s_rsa[r], (uint32_t)s_tid[lt],
-               base + (int)lt, d.adj_staged && !kBL ? &s_radj[r] : nullptr, n, rl);
+               base + (int)lt, d.adj_staged && !kF ? &s_radj[r] : nullptr, n, rl);
       }
     }
-    // the deferred T's, re-jittered again from the previous positions; with
-    // brick lists one T at a time, its candidate records spread over the
-    // workgroup's lanes
+    // the deferred T's, in the buckets (cells 0-7 of the block, then the
+    // overflow list), re-jittered again from the previous positions
     const int ndef = s_ndef;
-    for (int e = 0; kBL && e < ndef; ++e) {
-      const int slot = base + (int)s_def[e];
-      float px = X[slot], py = Y[slot], pz = Z[slot];
-      const uint32_t idj = (uint32_t)a.id[slot];
-      if (jit) rejitter(d, step, idj, px, py, pz);
-      wave_brick_records<1>(d, par, stray_list(step), px, py, pz, tid, kThreads,
-                         [&](float4 A, int sa) {
-                           if (!(dist2(d, px, py, pz, A) < d.rc2)) return;
-                           n.in_rc++;
-                           retain(d, a, step, __float_as_int(A.w), sa, idj, slot, nullptr, n, rl);
-                         });
-    }
-    // else one T per thread in the global buckets (cells 0-7 of the block,
-    // then the overflow list)
-    for (int e = tid; !kBL && e < ndef; e += kThreads) {
+    for (int e = tid; e < ndef; e += kThreads) {
       const int slot = base + (int)s_def[e];
       float px = X[slot], py = Y[slot], pz = Z[slot];
       const uint32_t idj = a.id ? (uint32_t)a.id[slot] : (uint32_t)slot;
@@ -1326,8 +1124,6 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
       lo_hi(py, d.inv_w, nc, cy0, cy1);
       lo_hi(pz, d.inv_w, nc, cz0, cz1);
       const int m = nc > 1 ? 2 : 1;
-      const float4* ovf = pick(d.ovf, par);
-      const int32_t* osa = pick(d.ovf_sa, par);
       for (int q = 0; q < 9; ++q) {
         const float4* rp;
         const int32_t* sp;
@@ -1336,14 +1132,14 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
           const int ia = q >> 2, ib = (q >> 1) & 1, ie = q & 1;
           if (ia >= m || ib >= m || ie >= m) continue;
           const int cc = ((ia ? cz1 : cz0) * nc + (ib ? cy1 : cy0)) * nc + (ie ? cx1 : cx0);
-          nr = pick(d.cnt, par)[cc];
+          nr = bk.cnt[cc];
           nr = nr < (uint32_t)kCellCap ? nr : (uint32_t)kCellCap;
-          rp = d.rec + (size_t)cc * kCellCap;
-          sp = d.rsa + (size_t)cc * kCellCap;
+          rp = bk.rec + (size_t)cc * kCellCap;
+          sp = bk.sa + (size_t)cc * kCellCap;
         } else {
-          nr = novf;
-          rp = ovf;
-          sp = osa;
+          nr = bk.novf;
+          rp = bk.ovf;
+          sp = bk.osa;
         }
         for (uint32_t r = 0; r < nr; ++r) {
           const float4 A = rp[r];
@@ -1360,10 +1156,10 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
     }
     __syncthreads();
   }
-  if (kBL && !dead) {
-    // the brick's A records of the next step (re-jittered once more), the
-    // further A's listed with the brick; with more A's than the array holds,
-    // every A of the brick from its previous position instead
+  if (kF && !dead) {
+    // the brick's A records of the next step (re-jittered once more) into the
+    // buckets of that step; with more A's than the array holds, every A of
+    // the brick from its previous position instead
     const int na = s_na;
     const bool all = na > kStageRecs;
     const int cnt = all ? s1 - s0 : na;
@@ -1386,35 +1182,24 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
       const uint32_t id = (uint32_t)a.id[slot];
       if (all && jit) rejitter(d, step, id, x, y, z);
       if (jit) rejitter(d, step + 1u, id, x, y, z);
-      bool unlisted = false;
-      if (slot >= a_end) {
-        const int p = atomicAdd(&s_xn, 1);
-        if (p < kXCap) s_xl[p] = slot;
-        unlisted = p >= kXCap;
-      }
-      put_record(d, par ^ 1u, step + 1u, slot, id, x, y, z, bx, ex, by, ey, bz, ez, unlisted);
+      fuse_bin(d, par ^ 1u, step + 1u, slot, id, x, y, z);
     }
-    // sort-time A's no longer active
-    for (int slot = s0 + tid; slot < a_end; slot += kThreads)
-      if (a.role[slot] != kRoleA)
-        ((uint32_t*)pick(d.arec, par ^ 1u))[4 * (size_t)slot + 3] = kRecDead;
+    // the counts two steps ahead (last read in the previous step) are cleared
+    // for the next step's sweep
+    for (int q = w * kThreads + tid; q < d.ncell; q += nwg * kThreads) d.fcnt[mod3(step + 2u)][q] = 0u;
+    if (w == 0 && tid == 0) d.ctl->fovf_n[mod3(step + 2u)] = 0u;
   }
   // clear the bucket counts of the next step's parity (no workgroup of this
-  // step reads them; with brick lists too, so that the buckets are clear
-  // whenever a step without them follows)
+  // step reads them; with fused binning too, so that they are clear whenever
+  // a step with the binning kernel follows)
   for (int q = w * kThreads + tid; q < d.ncell; q += nwg * kThreads)
     pick(d.cnt, par ^ 1u)[q] = 0u;
   wave_add(&s_cnt[kOutTElig], n.t_elig);
   wave_add(&s_cnt[kOutInRc], n.in_rc);
   wave_add(&s_cnt[kOutDrawn], n.drawn);
   wave_add(&s_cnt[kOutExcl], n.excl);
-  if (kBL) wave_add(&s_cnt[4], n.a_elig);
+  if (kF) wave_add(&s_cnt[4], n.a_elig);
   __syncthreads();
-  if (kBL) {  // this brick's further A's of the next step
-    const int nx = min(s_xn, kXCap);
-    if (tid < nx) pick(d.xlist, par ^ 1u)[w * kXCap + tid] = s_xl[tid];
-    if (tid == 0) pick(d.xcnt, par ^ 1u)[w] = nx;
-  }
   const int ne = s_ne;
   const int nk = ne < kRetCap ? ne : kRetCap;
   if (tid < nk) {
@@ -1425,7 +1210,7 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
   if (tid < 4) out[tid] = s_cnt[tid];
   if (tid == 0) {
     out[kOutRet] = nk;
-    if (kBL) out[kOutAElig] = s_cnt[4];
+    if (kF) out[kOutAElig] = s_cnt[4];
     if (ne > kRetCap) atomicAdd(&d.ctl->ret_ovf[par], (uint32_t)(ne - kRetCap));
   }
 }
@@ -1455,29 +1240,16 @@ struct BondCtx {
   uint32_t step;
 };
 
-// Brick lists after a bond of step `step` whose T has slot sj in brick w:
-// the A's record of the next step is dropped when the bond ends its A role,
-// and a T that takes the A role (chain growth) gets a record, listed with
-// its brick or, beyond kXCap further A's, on the stray list.
-__device__ void bl_after_bond(const Dev& d, const Arr& a, uint32_t par, uint32_t step, int w,
-                              int sa, int sj, uint32_t idj, uint8_t ra, uint8_t rt) {
-  if (ra != kRoleA) ((uint32_t*)pick(d.arec, par ^ 1u))[4 * (size_t)sa + 3] = kRecDead;
+// Fused binning after a bond of step `step`: the A's record of the next step
+// is dropped when the bond ends its A role, and a T that takes the A role
+// (chain growth) is binned for the next step at its re-jittered position.
+__device__ void fuse_after_bond(const Dev& d, const Arr& a, uint32_t par, uint32_t step, int sa,
+                                int sj, uint32_t idj, uint8_t ra, uint8_t rt) {
+  if (ra != kRoleA) fuse_drop(d, par ^ 1u, sa);
   if (rt != kRoleA) return;
   float x = pick(a.x, par ^ 1u)[sj], y = pick(a.y, par ^ 1u)[sj], z = pick(a.z, par ^ 1u)[sj];
   if (d.jitter && d.jit_c != 0.0f) rejitter(d, step + 1u, idj, x, y, z);
-  int bxc, byc;
-  const int bzc = div_nb(d, div_nb(d, w, bxc), byc);
-  int bx, ex, by, ey, bz, ez;
-  region_dim(d, bxc, bx, ex);
-  region_dim(d, byc, by, ey);
-  region_dim(d, bzc, bz, ez);
-  bool unlisted = false;
-  if (sj >= d.bstart[w] + d.bna[w]) {
-    const int p = atomicAdd(&pick(d.xcnt, par ^ 1u)[w], 1);
-    if (p < kXCap) pick(d.xlist, par ^ 1u)[w * kXCap + p] = sj;
-    unlisted = p >= kXCap;
-  }
-  put_record(d, par ^ 1u, step + 1u, sj, idj, x, y, z, bx, ex, by, ey, bz, ez, unlisted);
+  fuse_bin(d, par ^ 1u, step + 1u, sj, idj, x, y, z);
 }
 
 // A bond (step 9): states, roles, adjacency rows, and the staged (id_A, id_T)
@@ -1512,7 +1284,7 @@ __device__ __forceinline__ void make_bond(const Dev& d, const Arr& a, uint32_t p
   const uint8_t ra = role_of(d, a.typ[sa], na), rt = role_of(d, a.typ[sj], nt);
   a.role[sa] = ra;
   a.role[sj] = rt;
-  if (d.bricklist) bl_after_bond(d, a, par, b.step, w, sa, sj, (uint32_t)idj, ra, rt);
+  if (d.fuse) fuse_after_bond(d, a, par, b.step, sa, sj, (uint32_t)idj, ra, rt);
   int lost = 0;
   if (!adj_append(a.adj + (size_t)sa * d.B, d.B, (int32_t)idj)) lost++;
   if (!adj_append(a.adj + (size_t)sj * d.B, d.B, (int32_t)ida)) lost++;
@@ -1564,7 +1336,7 @@ __device__ __forceinline__ void make_bond_ahead(const Dev& d, const Arr& a, uint
   const uint8_t ra = role_of(d, o.tya, na), rt = role_of(d, o.tyt, nt);
   a.role[sa] = ra;
   a.role[sj] = rt;
-  if (d.bricklist) bl_after_bond(d, a, par, b.step, w, sa, sj, (uint32_t)idj, ra, rt);
+  if (d.fuse) fuse_after_bond(d, a, par, b.step, sa, sj, (uint32_t)idj, ra, rt);
   int lost = 0;
   const int fa = first_empty(o.rowa, d.B), ft = first_empty(o.rowt, d.B);
   if (fa < d.B) a.adj[(size_t)sa * d.B + fa] = (int32_t)idj;
@@ -1657,58 +1429,9 @@ __device__ __forceinline__ void resolve_body(const Dev& d, int k, int w, int nun
         else make_bond(d, a, par, w, e.x, e.y, e.z, e.w, bc);
       }
     }
-  } else if (mode == 2 && live && kBrick && d.bricklist) {
-    // brick lists: the flagged T's of each wavefront one at a time, the
-    // candidate records spread over its lanes
-    const float *X = pick(a.x, par ^ 1u), *Y = pick(a.y, par ^ 1u), *Z = pick(a.z, par ^ 1u);
-    int s0, s1;
-    range_of<kBrick>(d, w, s0, s1);
-    const int lane = __lane_id();
-    for (int base = s0; base < s1; base += kL) {
-      const int slot = base + tid;
-      unsigned long long m = __ballot(slot < s1 && d.tflag[slot] != 0);
-      while (m) {
-        const int ld = (int)__builtin_ctzll(m);
-        m &= m - 1ull;
-        const int sj = __builtin_amdgcn_readlane(slot, ld);
-        const float xj = X[sj], yj = Y[sj], zj = Z[sj];
-        const uint32_t idj = (uint32_t)a.id[sj];
-        unsigned long long best = kEmpty;
-        int best_sa = 0, np = 0;
-        wave_brick_records<4>(d, par, stray_list(step), xj, yj, zj, lane, 64, [&](float4 A, int sa) {
-          if (!(dist2(d, xj, yj, zj, A) < d.rc2)) return;
-          const int ida = __float_as_int(A.w);
-          if ((uint32_t)d.slotA[ida] != idj) return;  // not retained, or the A chose another T
-          const W4 r = philox(step, (uint32_t)ida, idj, 0u, d.seed);
-          d.slotA[ida] = kEmpty;
-          np++;
-          const unsigned long long bid = ((unsigned long long)r.w2 << 32) | (uint32_t)ida;
-          if (bid < best) {
-            best = bid;
-            best_sa = sa;
-          }
-        });
-        // the smallest (w2, id_A) over the lanes, with its A's slot
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-          const unsigned long long ob = __shfl_xor(best, o);
-          const int os = __shfl_xor(best_sa, o);
-          if (ob < best) {
-            best = ob;
-            best_sa = os;
-          }
-        }
-        np = wave_sum(np);
-        if (lane == 0) {
-          d.tflag[sj] = 0;
-          if (np) atomicAdd(&s_prop[g], np);
-          if (best != kEmpty) make_bond(d, a, par, w, (int)(uint32_t)best, best_sa, sj, (int)idj, bc);
-        }
-      }
-    }
   } else if (mode == 2 && live) {
     const float *X = pick(a.x, par ^ 1u), *Y = pick(a.y, par ^ 1u), *Z = pick(a.z, par ^ 1u);
-    const uint32_t novf = c->ovf_n[par];
+    const Buckets bk = d.fuse ? step_buckets<true>(d, par, step) : step_buckets<false>(d, par, step);
     int s0, s1;
     range_of<kBrick>(d, w, s0, s1);
     for (int base = s0; base < s1; base += kL) {
@@ -1719,7 +1442,7 @@ __device__ __forceinline__ void resolve_body(const Dev& d, int k, int w, int nun
         const uint32_t idj = a.id ? (uint32_t)a.id[slot] : (uint32_t)slot;
         unsigned long long best = kEmpty;
         int best_sa = 0, np = 0;
-        for_global_records(d, par, novf, xj, yj, zj, [&](float4 A, int sa) {
+        for_global_records(d, bk, xj, yj, zj, [&](float4 A, int sa) {
           if (!(dist2(d, xj, yj, zj, A) < d.rc2)) return;
           const int ida = __float_as_int(A.w);
           if ((uint32_t)d.slotA[ida] != idj) return;  // not retained, or the A chose another T
@@ -1769,7 +1492,7 @@ __device__ __forceinline__ void near_sweep_body(const Dev& d, int k, int w, int 
   const float *X = pick(a.x, par), *Y = pick(a.y, par), *Z = pick(a.z, par);
   float *XW = pick(a.x, par ^ 1u), *YW = pick(a.y, par ^ 1u), *ZW = pick(a.z, par ^ 1u);
   const bool jit = d.jitter && d.jit_c != 0.0f;
-  const uint32_t novf = c->ovf_n[par];
+  const Buckets bk = step_buckets<false>(d, par, step);
   const bool dead = read_err(c) != 0;
   int s0, s1;
   range_of<kBrick>(d, w, s0, s1);
@@ -1787,7 +1510,7 @@ __device__ __forceinline__ void near_sweep_body(const Dev& d, int k, int w, int 
     if (a.role[slot] != kRoleT) continue;
     t_elig++;
     unsigned long long best = kEmpty;
-    for_global_records(d, par, novf, x, y, z, [&](float4 A, int sa) {
+    for_global_records(d, bk, x, y, z, [&](float4 A, int sa) {
       const float r2 = dist2(d, x, y, z, A);
       if (!(r2 < d.rc2)) return;
       in_rc++;
@@ -1948,7 +1671,7 @@ __device__ __forceinline__ void multi_sweep_body(const Dev& d, int k, int w, int
   const float *X = pick(a.x, par), *Y = pick(a.y, par), *Z = pick(a.z, par);
   float *XW = pick(a.x, par ^ 1u), *YW = pick(a.y, par ^ 1u), *ZW = pick(a.z, par ^ 1u);
   const bool jit = d.jitter && d.jit_c != 0.0f;
-  const uint32_t novf = c->ovf_n[par];
+  const Buckets bk = step_buckets<false>(d, par, step);
   const bool dead = read_err(c) != 0;
   int s0, s1;
   range_of<kBrick>(d, w, s0, s1);
@@ -1969,7 +1692,7 @@ __device__ __forceinline__ void multi_sweep_body(const Dev& d, int k, int w, int
     if (!rt) continue;
     t_elig++;
     bool any = false;
-    for_global_records(d, par, novf, x, y, z, [&](float4 A, int sa) {
+    for_global_records(d, bk, x, y, z, [&](float4 A, int sa) {
       const int ida = __float_as_int(A.w);
       if ((uint32_t)ida == id) return;
       const float r2 = dist2(d, x, y, z, A);
@@ -2019,7 +1742,7 @@ __device__ __forceinline__ void multi_resolve_body(const Dev& d, int k, int w) {
   const uint32_t par = si.par, step = si.step;
   const Arr a = pick_set(d, c->set & 1u);
   const float *X = pick(a.x, par ^ 1u), *Y = pick(a.y, par ^ 1u), *Z = pick(a.z, par ^ 1u);
-  const uint32_t novf = c->ovf_n[par];
+  const Buckets bk = step_buckets<false>(d, par, step);
   int s0, s1;
   range_of<kBrick>(d, w, s0, s1);
   int prop = 0;
@@ -2031,7 +1754,7 @@ __device__ __forceinline__ void multi_resolve_body(const Dev& d, int k, int w) {
     const uint32_t rt = a.role[slot] & kMaskT;
     unsigned long long best = kEmpty;
     int best_sa = 0, best_r = 0;
-    for_global_records(d, par, novf, x, y, z, [&](float4 A, int sa) {
+    for_global_records(d, bk, x, y, z, [&](float4 A, int sa) {
       const int ida = __float_as_int(A.w);
       if ((uint32_t)ida == id) return;
       const float r2 = dist2(d, x, y, z, A);
@@ -2266,13 +1989,14 @@ __global__ __launch_bounds__(kThreads) void k_kin_pairs(Dev d, int nstate, int n
   const uint32_t par = c->par0;
   const Arr a = pick_set(d, c->set & 1u);
   const float *X = pick(a.x, par), *Y = pick(a.y, par), *Z = pick(a.z, par);
-  const uint32_t novf = c->ovf_n[par];
+  const Buckets bk{pick(d.cnt, par), d.rec, d.rsa, pick(d.ovf, par), pick(d.ovf_sa, par),
+                   c->ovf_n[par]};
   for (int slot = blockIdx.x * blockDim.x + threadIdx.x; slot < d.n;
        slot += gridDim.x * blockDim.x) {
     if (a.role[slot] != kRoleT) continue;
     const float x = X[slot], y = Y[slot], z = Z[slot];
     const int32_t id = a.id ? a.id[slot] : slot;
-    for_global_records(d, par, novf, x, y, z, [&](float4 A, int sa) {
+    for_global_records(d, bk, x, y, z, [&](float4 A, int sa) {
       const float r2 = dist2(d, x, y, z, A);
       if (!(r2 < d.rc2)) return;
       if (d.rule.exclude && row_has(a.adj + (size_t)sa * d.B, d.B, id)) return;
@@ -2446,14 +2170,7 @@ __device__ __forceinline__ void sort_local_body(const Dev& d, int b) {
     run += v[q];
   }
   const uint32_t total = __shfl(x, 63);
-  if (lane == 0) {
-    d.bcnt[b] = total;
-    if (d.bricklist) {  // the brick's A's (bin 0), no further ones yet
-      d.bna[b] = (int32_t)v[0];
-      d.xcnt[0][b] = 0;
-      d.xcnt[1][b] = 0;
-    }
-  }
+  if (lane == 0) d.bcnt[b] = total;
 }
 
 __device__ __forceinline__ void sort_scan_body(const Dev& d) {
@@ -2472,10 +2189,10 @@ __device__ __forceinline__ void sort_scan_body(const Dev& d) {
   }
   if (threadIdx.x == 0) {
     d.bstart[d.nbricks] = (int32_t)carry;
-    if (d.bricklist) {  // stray lists of the first two steps after the sort
+    if (d.fuse) {  // overflow of the first two steps after the sort
       const uint32_t s0 = d.ctl->step0;
-      d.scnt[stray_list(s0)] = 0u;
-      d.scnt[stray_list(s0 + 1u)] = 0u;
+      d.ctl->fovf_n[mod3(s0)] = 0u;
+      d.ctl->fovf_n[mod3(s0 + 1u)] = 0u;
     }
   }
 }
@@ -2503,16 +2220,10 @@ __device__ __forceinline__ void sort_scatter_body(const Dev& d, int k) {
     o.vz[ns] = a.vz[k];
   }
   if (d.slot_of) d.slot_of[id] = ns;
-  if (d.bricklist && role == kRoleA) {  // the A's record of the block's first step
+  if (d.fuse && role == kRoleA) {  // the A's record of the block's first step
     float rx = x, ry = y, rz = z;
     if (d.jitter && d.jit_c != 0.0f) rejitter(d, d.ctl->step0, (uint32_t)id, rx, ry, rz);
-    int bxc, byc;
-    const int bzc = div_nb(d, div_nb(d, b, bxc), byc);
-    int bx, ex, by, ey, bz, ez;
-    region_dim(d, bxc, bx, ex);
-    region_dim(d, byc, by, ey);
-    region_dim(d, bzc, bz, ez);
-    put_record(d, par, d.ctl->step0, ns, (uint32_t)id, rx, ry, rz, bx, ex, by, ey, bz, ez, false);
+    fuse_bin(d, par, d.ctl->step0, ns, (uint32_t)id, rx, ry, rz);
   }
   // rows of width 4 or 2 move as one vector when both arrays are aligned
   const bool vec = (((uintptr_t)a.adj | (uintptr_t)o.adj) & 15u) == 0u;
@@ -2536,16 +2247,16 @@ __global__ __launch_bounds__(kThreads) void k_close(Dev d, int k) { close_body(d
 __global__ void k_advance(Ctl* c, int K) {
   if (threadIdx.x == 0 && blockIdx.x == 0) advance_ctl(c, K);
 }
-template <bool kBrick, bool kTwo, bool kBL>
+template <bool kBrick, bool kTwo, bool kF>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) void k_sweep(Dev d, int k) {
-  sweep_body<kBrick, kTwo, kBL>(d, k, blockIdx.x, gridDim.x);
+  sweep_body<kBrick, kTwo, kF>(d, k, blockIdx.x, gridDim.x);
 }
-// With brick lists there is no prep kernel: the closing groups of step k - 1
-// lead the resolve of step k.
+// With fused binning there is no prep kernel: the closing groups of step
+// k - 1 lead the resolve of step k.
 template <bool kBrick>
 __global__ __launch_bounds__(kThreads) void k_resolve(Dev d, int k) {
   int b = blockIdx.x;
-  if (kBrick && d.bricklist && k > 0) {
+  if (kBrick && d.fuse && k > 0) {
     if (b < d.ngroups) {
       __shared__ uint32_t s_wave[kThreads / 64 + 1];
       const StepInfo si = step_info(d.ctl, k);
@@ -2576,7 +2287,15 @@ __global__ __launch_bounds__(kThreads) void k_multi_final(Dev d, int k) {
   multi_final_body<kBrick>(d, k, blockIdx.x);
 }
 __global__ __launch_bounds__(kThreads) void k_sort_count(Dev d) {
-  sort_count_body(d, blockIdx.x * blockDim.x + threadIdx.x);
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  sort_count_body(d, k);
+  if (d.fuse) {  // fused binning: the scatter bins the first step after the sort
+    const uint32_t s0 = d.ctl->step0;
+    for (int q = k; q < d.ncell; q += gridDim.x * blockDim.x) {
+      d.fcnt[mod3(s0)][q] = 0u;
+      d.fcnt[mod3(s0 + 1u)][q] = 0u;
+    }
+  }
 }
 __global__ __launch_bounds__(kThreads) void k_sort_local(Dev d) {
   sort_local_body(d, blockIdx.x * (kThreads / 64) + (int)(threadIdx.x / 64));
@@ -2801,7 +2520,7 @@ hipError_t launch_step(const Dev& d, int k, hipStream_t s, hipEvent_t ev_sweep0,
                        hipEvent_t ev_sweep1) {
   for (int m = 0; d.md_theta > 0 && m <= d.md_theta; ++m)
     k_md<<<blocks_for(d.n, kThreads), kThreads, 0, s>>>(d, k, m);
-  if (d.bricklist) {  // two kernels: sweep, then the closing of step k - 1 with the resolve
+  if (d.fuse) {  // two kernels: sweep, then the closing of step k - 1 with the resolve
     const dim3 g(d.nwg_sweep), b(kThreads);
     if (d.bs > kOneCellBrick) {
       if (ev_sweep0)
@@ -2984,6 +2703,7 @@ hipError_t launch_kinetics(const Dev& d, int nstate, int nbins, const float* e2,
   k_kin_pop<<<g, kThreads, 0, s>>>(d, nstate, pop);
   Dev dn = d;
   dn.jit_c = 0.0f;
+  dn.fuse = 0;  // binned into the plain buckets here, whatever the steps use
   k_prep<<<d.nwg_prep, kThreads, 0, s>>>(dn, 0);
   k_kin_pairs<<<g, kThreads, 0, s>>>(dn, nstate, nbins, e2, pairs, hist);
   k_kin_reset<<<std::min(blocks_for(d.ncell, kThreads), 1024), kThreads, 0, s>>>(dn);
