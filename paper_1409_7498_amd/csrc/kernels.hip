@@ -2247,9 +2247,22 @@ __global__ __launch_bounds__(kThreads) void k_close(Dev d, int k) { close_body(d
 __global__ void k_advance(Ctl* c, int K) {
   if (threadIdx.x == 0 && blockIdx.x == 0) advance_ctl(c, K);
 }
+// The brick of sweep workgroup g.  Workgroups are dispatched to the eight
+// XCDs in turn (g mod 8), each XCD with an L2 of its own; XCD x takes the
+// contiguous run of bricks x * q + min(x, r) .. (q or q + 1 of them, q =
+// nbricks / 8, r = nbricks mod 8), a slab of neighbouring bricks, so that
+// the A records a brick's neighbours stage again are in the same L2.
+__device__ __forceinline__ int xcd_brick(int g, int nbricks) {
+  constexpr int kXcd = 8;
+  const int q = nbricks / kXcd, r = nbricks - q * kXcd;
+  const int x = g % kXcd, i = g / kXcd;
+  return x * q + min(x, r) + i;
+}
+
 template <bool kBrick, bool kTwo, bool kF>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) void k_sweep(Dev d, int k) {
-  sweep_body<kBrick, kTwo, kF>(d, k, blockIdx.x, gridDim.x);
+  const int w = kBrick ? xcd_brick(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  sweep_body<kBrick, kTwo, kF>(d, k, w, gridDim.x);
 }
 // With fused binning there is no prep kernel: the closing groups of step
 // k - 1 lead the resolve of step k.
