@@ -405,8 +405,9 @@ def main():
     first += K
     st = sysm.stats()[-K:]
 
-    # kernel timing: the next steps launched directly, HIP events around the
-    # prep kernel, the sweep kernel, whole steps and each sort that falls due
+    # kernel timing: the next steps launched directly, HIP events from each
+    # step's start to its sweep (the binning kernel, when the sweep does not
+    # bin), around the sweep kernel, whole steps and each sort that falls due
     # (a run of one period holds exactly one)
     KT = max(min(K, 64), sort_period if sort_period > 0 else 0)
     ph = sysm.run_timed(first, KT, cfg.sigma)
@@ -465,7 +466,7 @@ def main():
                           "roofline_frac": react_bytes / (react_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
                           "how": "per-step time minus the re-jitter kernel alone "
                                  "(pr_sys_jitter, same steps)"},
-        "prep_ms_direct": prep_ms,
+        "before_sweep_ms_direct": prep_ms,
         "sweep_ms_direct": sweep_ms,
         "step_ms_direct": ph["step_ms"] / KT,
         "bonds_per_step": bonds,
