@@ -874,18 +874,13 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
   __shared__ uint32_t s_ew2[kRetCap];
   __shared__ uint32_t s_wave[kThreads / 64 + 1];
   __shared__ int s_cnt[5];
-  __shared__ int s_qn, s_ndef, s_ne, s_dead, s_na;
-  // fused binning: the A's of the brick at their positions of this step
-  // (slot in w), in the staging array the pass loop then leaves idle (the
-  // records carry no adjacency rows)
-  float4* const s_apos = (float4*)s_radj;
+  __shared__ int s_qn, s_ndef, s_ne, s_dead;
   const int tid = threadIdx.x;
   if (tid < 5) s_cnt[tid] = 0;
   if (tid == 0) {
     s_qn = 0;
     s_ndef = 0;
     s_ne = 0;
-    s_na = 0;
     s_dead = read_err(d.ctl) != 0;
   }
   const Ctl* c = d.ctl;
@@ -1010,10 +1005,14 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
         *(float*)((char*)YW + bo) = cur.y;
         *(float*)((char*)ZW + bo) = cur.z;
       }
-      if (kF && slot < s1 && cur.role == kRoleA) {  // kept for the next step's record
+      if (kF && slot < s1 && cur.role == kRoleA) {
+        // fused binning: the A's record of the next step, re-jittered once
+        // more (its bucket's returning atomic completes behind the rest of
+        // the pass)
         n.a_elig++;
-        const int p = atomicAdd(&s_na, 1);
-        if (p < kStageRecs) s_apos[p] = make_float4(cur.x, cur.y, cur.z, __int_as_float(slot));
+        float nx = cur.x, ny = cur.y, nz = cur.z;
+        if (fl & kFJit) rejitter(d, step + 1u, idj, nx, ny, nz);
+        fuse_bin(d, par ^ 1u, step + 1u, slot, idj, nx, ny, nz);
       }
       // in-range staged records of this T: nh counts them all, hits keeps the
       // first four, one byte each (a T with more is deferred)
@@ -1157,35 +1156,8 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
     __syncthreads();
   }
   if (kF && !dead) {
-    // the brick's A records of the next step (re-jittered once more) into the
-    // buckets of that step; with more A's than the array holds, every A of
-    // the brick from its previous position instead
-    const int na = s_na;
-    const bool all = na > kStageRecs;
-    const int cnt = all ? s1 - s0 : na;
-    for (int e = tid; e < cnt; e += kThreads) {
-      int slot;
-      float x, y, z;
-      if (all) {
-        slot = s0 + e;
-        if (a.role[slot] != kRoleA) continue;
-        x = X[slot];
-        y = Y[slot];
-        z = Z[slot];
-      } else {
-        const float4 q = s_apos[e];
-        slot = __float_as_int(q.w);
-        x = q.x;
-        y = q.y;
-        z = q.z;
-      }
-      const uint32_t id = (uint32_t)a.id[slot];
-      if (all && jit) rejitter(d, step, id, x, y, z);
-      if (jit) rejitter(d, step + 1u, id, x, y, z);
-      fuse_bin(d, par ^ 1u, step + 1u, slot, id, x, y, z);
-    }
-    // the counts two steps ahead (last read in the previous step) are cleared
-    // for the next step's sweep
+    // fused binning: the counts two steps ahead (last read in the previous
+    // step) are cleared for the next step's sweep
     for (int q = w * kThreads + tid; q < d.ncell; q += nwg * kThreads) d.fcnt[mod3(step + 2u)][q] = 0u;
     if (w == 0 && tid == 0) d.ctl->fovf_n[mod3(step + 2u)] = 0u;
   }
