@@ -1860,6 +1860,7 @@ int fill_maps(const std::vector<pr_sys*>& sys, Arena& arena, BatchLaunch& bl) {
   bl.two = two;
   bl.any_random = any_random;
   bl.any_nearest = any_nearest;
+  bl.fuse = 0;  // set by the batch when every replica has its fused buckets
   bl.res = mr;
   bl.n_res = (int)res.size();
   bl.nrep = (int)sys.size();
@@ -1926,6 +1927,18 @@ int pr_batch_create(pr_batch** out, const pr_replica_desc* reps, int32_t n_rep, 
     }
   }
   if (!e) e = fill_maps(b->sys, b->arena, b->bl);
+  // fused binning when every replica can take it (one rule, the random
+  // selection): no binning kernel in the batch's steps
+  if (!e && !b->bl.any_nearest) {
+    bool all = true;
+    for (pr_sys* s : b->sys) {
+      if (alloc_fused(s) != PR_OK || !s->d.fcnt[0]) {
+        all = false;
+        break;
+      }
+    }
+    b->bl.fuse = all ? 1 : 0;
+  }
   if (!e) e = b->arena.alloc(&b->ds, (size_t)n_rep);
   if (e) {
     delete b;
@@ -1962,7 +1975,7 @@ int pr_batch_run(pr_batch* b, uint32_t first_step, uint32_t n_steps, double sigm
     if ((e = grow_part(s, s->steps_since_load + n_steps))) return e;
     s->d.jit_c = (float)(sigma / std::sqrt(21845.0));
     s->d.sorted = 1;
-    s->d.fuse = 0;  // the batched kernels bin the A's every step
+    s->d.fuse = b->bl.fuse;  // the batch's sweeps bin the next step's A's, or k_prep_b does
     s->rec_ok = false;
     s->d.nwg_sweep = s->d.nbricks;
     b->hds[r] = s->d;

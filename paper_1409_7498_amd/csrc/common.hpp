@@ -190,6 +190,7 @@ struct BatchLaunch {
   int n_res;
   int two;              // some replica's brick edge exceeds kOneCellBrick
   int any_random, any_nearest;  // some replica selects with that policy
+  int fuse;             // every replica bins its next step's A's in its sweep
 };
 
 }  // namespace pr

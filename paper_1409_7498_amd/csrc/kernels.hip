@@ -2310,13 +2310,13 @@ __global__ __launch_bounds__(kThreads) void k_prep_b(const Dev* __restrict__ ds,
   if (k >= d.k_limit) return;
   prep_body(d, k, m.y);
 }
-template <bool kTwo>
+template <bool kTwo, bool kF>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) void k_sweep_b(
     const Dev* __restrict__ ds, const int4* __restrict__ map, int k) {
   const int4 m = uniform_map(map);
   const Dev& d = ds[m.x];
   if (k >= d.k_limit || d.rule.policy != PR_POLICY_RANDOM) return;
-  sweep_body<true, kTwo>(d, k, m.y, m.z);
+  sweep_body<true, kTwo, kF>(d, k, m.y, m.z);
 }
 __global__ __launch_bounds__(kThreads) void k_near_sweep_b(const Dev* __restrict__ ds,
                                                            const int4* __restrict__ map, int k) {
@@ -2332,12 +2332,26 @@ __global__ __launch_bounds__(kThreads) void k_near_resolve_b(const Dev* __restri
   if (k >= d.k_limit || d.rule.policy != PR_POLICY_NEAREST) return;
   near_resolve_body(d, k, m.y, m.z);
 }
+// With fused binning the first ncl workgroups close step k - 1 of each
+// replica (closing map), the rest resolve step k (resolve map).
 __global__ __launch_bounds__(kThreads) void k_resolve_b(const Dev* __restrict__ ds,
-                                                        const int4* __restrict__ map, int k) {
-  const int4 m = uniform_map(map);
-  const Dev& d = ds[m.x];
+                                                        const int4* __restrict__ map,
+                                                        const int4* __restrict__ cmap, int ncl,
+                                                        int k) {
+  if ((int)blockIdx.x < ncl) {
+    const int4 m = uniform_map(cmap);
+    const Dev& d = ds[m.x];
+    if (k >= d.k_limit) return;  // the block end closes the replica's last step
+    __shared__ uint32_t s_wave[kThreads / 64 + 1];
+    const StepInfo si = step_info(d.ctl, k);
+    close_group(d, si.par ^ 1u, si.step - 1u, d.ctl->stats_n0 + (uint32_t)k - 1u, m.y, s_wave);
+    return;
+  }
+  const int4 m = map[__builtin_amdgcn_readfirstlane((int)blockIdx.x - ncl)];
+  const Dev& d = ds[__builtin_amdgcn_readfirstlane(m.x)];
   if (k >= d.k_limit || d.rule.policy != PR_POLICY_RANDOM) return;
-  resolve_body<true, true>(d, k, m.y, m.z);
+  resolve_body<true, true>(d, k, __builtin_amdgcn_readfirstlane(m.y),
+                           __builtin_amdgcn_readfirstlane(m.z));
 }
 __global__ __launch_bounds__(kThreads) void k_close_b(const Dev* __restrict__ ds,
                                                       const int4* __restrict__ map, int k) {
@@ -2366,6 +2380,13 @@ __global__ __launch_bounds__(kThreads) void k_sort_count_b(const Dev* __restrict
   const int4 m = uniform_map(map);
   const Dev& d = ds[m.x];
   sort_count_body(d, m.y * kThreads + threadIdx.x);
+  if (d.fuse) {  // fused binning: the scatter bins the block's first step
+    const uint32_t s0 = d.ctl->step0;
+    for (int q = m.y * kThreads + threadIdx.x; q < d.ncell; q += m.z * kThreads) {
+      d.fcnt[mod3(s0)][q] = 0u;
+      d.fcnt[mod3(s0 + 1u)][q] = 0u;
+    }
+  }
 }
 // ngrp blocks per replica (the brick groups of the largest one)
 __global__ __launch_bounds__(kThreads) void k_sort_local_b(const Dev* __restrict__ ds, int ngrp) {
@@ -2612,16 +2633,25 @@ hipError_t launch_ctl_b(const BatchLaunch& b, int op, uint32_t arg, hipStream_t 
 }
 
 hipError_t launch_step_b(const BatchLaunch& b, int k, hipStream_t s) {
+  if (b.fuse) {  // every replica random and fused: sweep, then closing + resolve
+    if (b.two)
+      k_sweep_b<true, true><<<b.n_sweep, kThreads, 0, s>>>(b.ds, b.sweep, k);
+    else
+      k_sweep_b<false, true><<<b.n_sweep, kThreads, 0, s>>>(b.ds, b.sweep, k);
+    const int ncl = k > 0 ? b.n_close : 0;
+    k_resolve_b<<<ncl + b.n_res, kThreads, 0, s>>>(b.ds, b.res, b.close, ncl, k);
+    return hipGetLastError();
+  }
   if (k > 0)
     k_prep_b<<<b.n_prepk, kThreads, 0, s>>>(b.ds, b.prepk, k);
   else
     k_prep_b<<<b.n_prep0, kThreads, 0, s>>>(b.ds, b.prep0, k);
   if (b.any_random) {
     if (b.two)
-      k_sweep_b<true><<<b.n_sweep, kThreads, 0, s>>>(b.ds, b.sweep, k);
+      k_sweep_b<true, false><<<b.n_sweep, kThreads, 0, s>>>(b.ds, b.sweep, k);
     else
-      k_sweep_b<false><<<b.n_sweep, kThreads, 0, s>>>(b.ds, b.sweep, k);
-    k_resolve_b<<<b.n_res, kThreads, 0, s>>>(b.ds, b.res, k);
+      k_sweep_b<false, false><<<b.n_sweep, kThreads, 0, s>>>(b.ds, b.sweep, k);
+    k_resolve_b<<<b.n_res, kThreads, 0, s>>>(b.ds, b.res, b.close, 0, k);
   }
   if (b.any_nearest) {
     k_near_sweep_b<<<b.n_sweep, kThreads, 0, s>>>(b.ds, b.sweep, k);
