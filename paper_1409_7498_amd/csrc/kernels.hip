@@ -789,15 +789,15 @@ __device__ __forceinline__ void retain(const Dev& d, const Arr& a, uint32_t step
 // of the brick and its halo (positions, ids, slots, adjacency rows) staged in
 // LDS, one record per thread, and the brick's particles handled kTPass at a
 // time.  A T whose 2x2x2 cell block lies in the staged region scans it as four
-// runs of two x-adjacent cells (contiguous in LDS) and keeps up to three
-// in-range pairs in registers; the wavefront then reserves queue slots for all
+// runs of two x-adjacent cells (contiguous in LDS) and keeps up to four
+// in-range pairs in registers (one byte each); the wavefront then reserves queue slots for all
 // of them at once (ballot and mbcnt over the per-lane counts) and the queue is
 // drawn on full wavefronts after the pass.  Every other T is deferred to a
-// list and scanned again, after the queue, in the global buckets: T's with
-// more than three in-range pairs or whose pairs find the queue full,
-// particles that drifted out of the staged region since the last sort,
-// bricks whose region holds more than kStageRecs records, steps with bucket
-// overflow, and all T's of kBrick = false (kThreads consecutive slots per
+// list and scanned again after the queue: T's with more in-range pairs than
+// the registers hold, or whose pairs find the queue full, in the staged
+// records; in the global buckets particles that drifted out of the staged
+// region since the last sort, bricks whose region holds more than kStageRecs
+// records, steps with bucket overflow, and all T's of kBrick = false (kThreads consecutive slots per
 // workgroup).  A deferred T enters the queue with none of its pairs, so every
 // pair is drawn exactly once.
 // ---------------------------------------------------------------------------
@@ -836,18 +836,6 @@ __device__ __forceinline__ void rejitter(const Dev& d, uint32_t step, uint32_t i
   z = wrap_box(__fadd_rn(z, __fmul_rn((float)S[2], d.jit_c)), d.L);
 }
 
-// An in-range pair (local T, staged record r) into the three register slots;
-// false when they are full (the T is then deferred).
-__device__ __forceinline__ bool hold_hit(int r, int lt, int& nh, uint32_t& h0, uint32_t& h1,
-                                         uint32_t& h2) {
-  if (nh == 3) return false;
-  h2 = h1;
-  h1 = h0;
-  h0 = (uint32_t)lt | ((uint32_t)r << 16);
-  nh++;
-  return true;
-}
-
 __device__ __forceinline__ uint32_t lanes_below(unsigned long long b) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
 }
@@ -883,6 +871,10 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
     s_ne = 0;
     s_dead = read_err(d.ctl) != 0;
   }
+  // staging at the top wave priority: the workgroups dispatched last stage
+  // while the compute units already run the pass loops of the others, and
+  // below those waves' priority their staging waits for issue slots
+  if (kBrick) __builtin_amdgcn_s_setprio(3);
   const Ctl* c = d.ctl;
   const StepInfo si = step_info(c, k);
   const uint32_t par = si.par, step = si.step;
@@ -1110,14 +1102,36 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
                base + (int)lt, d.adj_staged && !kF ? &s_radj[r] : nullptr, n, rl);
       }
     }
-    // the deferred T's, in the buckets (cells 0-7 of the block, then the
-    // overflow list), re-jittered again from the previous positions
+    // the deferred T's, re-jittered again from the previous positions: in the
+    // staged records when the block lies in a staged region (T's with more
+    // pairs than the registers hold, or whose pairs found the queue full),
+    // else in the buckets (cells 0-7 of the block, then the overflow list)
     const int ndef = s_ndef;
     for (int e = tid; e < ndef; e += kThreads) {
       const int slot = base + (int)s_def[e];
       float px = X[slot], py = Y[slot], pz = Z[slot];
       const uint32_t idj = a.id ? (uint32_t)a.id[slot] : (uint32_t)slot;
       if (jit) rejitter(d, step, idj, px, py, pz);
+      if (kBrick && staged) {
+        const int lx0 = local_lo(px, d.inv_w, bx, nc), ly0 = local_lo(py, d.inv_w, by, nc),
+                  lz0 = local_lo(pz, d.inv_w, bz, nc);
+        if ((uint32_t)lx0 < (uint32_t)(ex - 1) && (uint32_t)ly0 < (uint32_t)(ey - 1) &&
+            (uint32_t)lz0 < (uint32_t)(ez - 1)) {
+          const int l0 = (lz0 * ey + ly0) * ex + lx0;
+#pragma unroll 1
+          for (int run = 0; run < 4; ++run) {
+            const int lr = l0 + ((run & 1) ? ex : 0) + ((run & 2) ? ex * ey : 0);
+            const int r1 = (int)s_off[lr + 2];
+            for (int r = (int)s_off[lr]; r < r1; ++r) {
+              if (!(dist2(d, px, py, pz, s_rec[r]) < d.rc2)) continue;
+              n.in_rc++;
+              retain(d, a, step, __float_as_int(s_rec[r].w), s_rsa[r], idj, slot,
+                     d.adj_staged && !kF ? &s_radj[r] : nullptr, n, rl);
+            }
+          }
+          continue;
+        }
+      }
       int cx0, cx1, cy0, cy1, cz0, cz1;
       lo_hi(px, d.inv_w, nc, cx0, cx1);
       lo_hi(py, d.inv_w, nc, cy0, cy1);
