@@ -719,11 +719,14 @@ __device__ __forceinline__ void fuse_bin(const Dev& d, uint32_t par, uint32_t st
   }
 }
 
-// Drops the record of the next step (parity par) of the A in `slot`.
-__device__ __forceinline__ void fuse_drop(const Dev& d, uint32_t par, int slot) {
-  const int q = d.apos[slot];
+// Drops the record of the next step (parity par) at q (a bucket record, or
+// overflow entry -1 - q), or that of the A in `slot`.
+__device__ __forceinline__ void fuse_drop_at(const Dev& d, uint32_t par, int q) {
   float* x = q >= 0 ? &pick(d.frec, par)[q].x : &pick(d.fovf, par)[-1 - q].x;
   *x = __int_as_float(0x7FC00000);  // quiet NaN
+}
+__device__ __forceinline__ void fuse_drop(const Dev& d, uint32_t par, int slot) {
+  fuse_drop_at(d, par, d.apos[slot]);
 }
 
 // Slot range of sweep/resolve workgroup w.
@@ -1287,11 +1290,17 @@ __device__ __forceinline__ void make_bond(const Dev& d, const Arr& a, uint32_t p
 // The operands of a bond read ahead of the decision, together with the A's
 // key: both states and types and (rows of width B <= kAdjStage) both
 // adjacency rows.  Every particle takes at most one bond per step, and only
-// that bond writes its state and row, so values read ahead are the ones a
-// bond made after the decision would read.
+// that bond writes its state and row (and, with fused binning, the bucket
+// position of an A's record or a T's binned record; positions are final after
+// the sweep), so values read ahead are the ones a bond made after the
+// decision would read.
 struct BondOps {
   int32_t sta, stt, tya, tyt;
   int4 rowa, rowt;
+  // fused binning: where the A's next-step record is, and the T's position
+  // of this step (binned if the bond gives the T the A role)
+  int32_t apa;
+  float tx, ty, tz;
 };
 
 __device__ __forceinline__ int4 load_row4(const int32_t* row, int B) {
@@ -1322,7 +1331,14 @@ __device__ __forceinline__ void make_bond_ahead(const Dev& d, const Arr& a, uint
   const uint8_t ra = role_of(d, o.tya, na), rt = role_of(d, o.tyt, nt);
   a.role[sa] = ra;
   a.role[sj] = rt;
-  if (d.fuse) fuse_after_bond(d, a, par, b.step, sa, sj, (uint32_t)idj, ra, rt);
+  if (d.fuse) {  // fuse_after_bond with the operands read ahead
+    if (ra != kRoleA) fuse_drop_at(d, par ^ 1u, o.apa);
+    if (rt == kRoleA) {
+      float x = o.tx, y = o.ty, z = o.tz;
+      if (d.jitter && d.jit_c != 0.0f) rejitter(d, b.step + 1u, (uint32_t)idj, x, y, z);
+      fuse_bin(d, par ^ 1u, b.step + 1u, sj, (uint32_t)idj, x, y, z);
+    }
+  }
   int lost = 0;
   const int fa = first_empty(o.rowa, d.B), ft = first_empty(o.rowt, d.B);
   if (fa < d.B) a.adj[(size_t)sa * d.B + fa] = (int32_t)idj;
@@ -1384,7 +1400,7 @@ __device__ __forceinline__ void resolve_body(const Dev& d, int k, int w, int nun
     const bool ahead = d.adj_staged != 0;
     bool chosen = false;
     unsigned long long key = kEmpty;
-    BondOps ops{0, 0, 0, 0, make_int4(0, 0, 0, 0), make_int4(0, 0, 0, 0)};
+    BondOps ops{0, 0, 0, 0, make_int4(0, 0, 0, 0), make_int4(0, 0, 0, 0), 0, 0.0f, 0.0f, 0.0f};
     if (tid < ne) {
       const unsigned long long ka = d.slotA[e.x];
       if (ahead) {
@@ -1394,6 +1410,12 @@ __device__ __forceinline__ void resolve_body(const Dev& d, int k, int w, int nun
         ops.tyt = a.typ[e.z];
         ops.rowa = load_row4(a.adj + (size_t)e.y * d.B, d.B);
         ops.rowt = load_row4(a.adj + (size_t)e.z * d.B, d.B);
+        if (d.fuse) {
+          ops.apa = d.apos[e.y];
+          ops.tx = pick(a.x, par ^ 1u)[e.z];
+          ops.ty = pick(a.y, par ^ 1u)[e.z];
+          ops.tz = pick(a.z, par ^ 1u)[e.z];
+        }
       }
       d.tflag[e.z] = 0;
       chosen = (uint32_t)ka == (uint32_t)e.w;
