@@ -167,6 +167,11 @@ struct Dev {
   float4* fovf[2];
   int32_t* fovf_sa[2];
   int32_t* apos;
+  // a resident system's sweep stores the re-jittered positions
+  // non-temporally: set when one parity's positions (12 bytes per particle)
+  // take at most half of the L2s, where they would otherwise still sit,
+  // dirty, when the kernel ends and delay the next kernel's start
+  int32_t nt_pos;
   // bonded-force coupling (md_theta > 0): md_theta velocity-Verlet steps with
   // the mirror-LJ bond force before each reaction step, instead of the
   // re-jitter; slot_of maps ids to slots of the current storage set

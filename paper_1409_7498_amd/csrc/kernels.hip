@@ -846,7 +846,8 @@ __device__ __forceinline__ uint32_t lanes_below(unsigned long long b) {
 // kTwo: two region cells per thread while staging (brick edges above
 // kOneCellBrick); else one, with the smaller tables.
 // kF: fused binning (the sweep bins the next step's A records; sorted storage).
-template <bool kBrick, bool kTwo, bool kF = false>
+// kNt: the re-jittered positions stored non-temporally (Dev::nt_pos).
+template <bool kBrick, bool kTwo, bool kF = false, bool kNt = false>
 __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) {
   static_assert(!kF || kBrick, "fused binning runs on sorted storage");
   constexpr int kCells = kTwo ? kStageCells : kStageCells1;  // region cells at most
@@ -996,9 +997,15 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
       if (slot < s1 && (fl & kFMove)) {  // the re-jitter (stand-in for the MD between steps)
         if (fl & kFJit) rejitter(d, step, idj, cur.x, cur.y, cur.z);
         const uint32_t bo = (uint32_t)slot * 4u;  // 32-bit byte offsets: scalar-base stores
-        *(float*)((char*)XW + bo) = cur.x;
-        *(float*)((char*)YW + bo) = cur.y;
-        *(float*)((char*)ZW + bo) = cur.z;
+        if (kNt) {
+          __builtin_nontemporal_store(cur.x, (float*)((char*)XW + bo));
+          __builtin_nontemporal_store(cur.y, (float*)((char*)YW + bo));
+          __builtin_nontemporal_store(cur.z, (float*)((char*)ZW + bo));
+        } else {
+          *(float*)((char*)XW + bo) = cur.x;
+          *(float*)((char*)YW + bo) = cur.y;
+          *(float*)((char*)ZW + bo) = cur.z;
+        }
       }
       if (kF && slot < s1 && cur.role == kRoleA) {
         // fused binning: the A's record of the next step, re-jittered once
@@ -2267,10 +2274,10 @@ __device__ __forceinline__ int xcd_brick(int g, int nbricks) {
   return x * q + min(x, r) + i;
 }
 
-template <bool kBrick, bool kTwo, bool kF>
+template <bool kBrick, bool kTwo, bool kF, bool kNt = false>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) void k_sweep(Dev d, int k) {
   const int w = kBrick ? xcd_brick(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-  sweep_body<kBrick, kTwo, kF>(d, k, w, gridDim.x);
+  sweep_body<kBrick, kTwo, kF, kNt>(d, k, w, gridDim.x);
 }
 // With fused binning there is no prep kernel: the closing groups of step
 // k - 1 lead the resolve of step k.
@@ -2464,6 +2471,7 @@ __global__ __launch_bounds__(kThreads) void k_gather_out(Dev d, float* ox, float
 // step's offsets into parity par ^ 1, exactly as the sweep of a reaction
 // step moves it, and the cell counts of the next parity are cleared as the
 // sweep clears them.  No reaction happens.
+template <bool kNt>
 __global__ __launch_bounds__(kThreads) void k_jitter_only(Dev d, int k) {
   const Ctl* c = d.ctl;
   const uint32_t par = (c->par0 + (uint32_t)k) & 1u, step = c->step0 + (uint32_t)k;
@@ -2474,9 +2482,15 @@ __global__ __launch_bounds__(kThreads) void k_jitter_only(Dev d, int k) {
   if (i < d.n) {
     float x = X[i], y = Y[i], z = Z[i];
     if (d.jit_c != 0.0f) rejitter(d, step, a.id ? (uint32_t)a.id[i] : (uint32_t)i, x, y, z);
-    XW[i] = x;
-    YW[i] = y;
-    ZW[i] = z;
+    if (kNt) {  // the sweep's store policy
+      __builtin_nontemporal_store(x, &XW[i]);
+      __builtin_nontemporal_store(y, &YW[i]);
+      __builtin_nontemporal_store(z, &ZW[i]);
+    } else {
+      XW[i] = x;
+      YW[i] = y;
+      ZW[i] = z;
+    }
   }
   for (int q = i; q < d.ncell; q += gridDim.x * blockDim.x) pick(d.cnt, par ^ 1u)[q] = 0u;
 }
@@ -2564,18 +2578,13 @@ hipError_t launch_step(const Dev& d, int k, hipStream_t s, hipEvent_t ev_sweep0,
     k_md<<<blocks_for(d.n, kThreads), kThreads, 0, s>>>(d, k, m);
   if (d.fuse) {  // two kernels: sweep, then the closing of step k - 1 with the resolve
     const dim3 g(d.nwg_sweep), b(kThreads);
-    if (d.bs > kOneCellBrick) {
-      if (ev_sweep0)
-        hipExtLaunchKernelGGL(k_sweep<true, true, true>, g, b, 0, s, ev_sweep0, ev_sweep1, 0, d, k);
-      else
-        k_sweep<true, true, true><<<g, b, 0, s>>>(d, k);
-    } else {
-      if (ev_sweep0)
-        hipExtLaunchKernelGGL(k_sweep<true, false, true>, g, b, 0, s, ev_sweep0, ev_sweep1, 0, d,
-                              k);
-      else
-        k_sweep<true, false, true><<<g, b, 0, s>>>(d, k);
-    }
+    // (edges above kOneCellBrick stage two region cells per thread)
+    auto kern = d.bs > kOneCellBrick ? (d.nt_pos ? k_sweep<true, true, true, true>
+                                                 : k_sweep<true, true, true, false>)
+                                     : (d.nt_pos ? k_sweep<true, false, true, true>
+                                                 : k_sweep<true, false, true, false>);
+    if (ev_sweep0) hipExtLaunchKernelGGL(kern, g, b, 0, s, ev_sweep0, ev_sweep1, 0, d, k);
+    else kern<<<g, b, 0, s>>>(d, k);
     k_resolve<true><<<(d.nwg_sweep + 3) / 4 + (k > 0 ? d.ngroups : 0), kThreads, 0, s>>>(d, k);
     return hipGetLastError();
   }
@@ -2721,8 +2730,9 @@ hipError_t launch_jitter_only(const Dev& d, int n_steps, hipStream_t s, hipEvent
                               hipEvent_t ev1) {
   const dim3 g(blocks_for(d.n, kThreads)), b(kThreads);
   for (int k = 0; k < n_steps; ++k) {
-    if (ev0) hipExtLaunchKernelGGL(k_jitter_only, g, b, 0, s, ev0, ev1, 0, d, k);
-    else k_jitter_only<<<g, b, 0, s>>>(d, k);
+    auto kern = d.nt_pos ? k_jitter_only<true> : k_jitter_only<false>;
+    if (ev0) hipExtLaunchKernelGGL(kern, g, b, 0, s, ev0, ev1, 0, d, k);
+    else kern<<<g, b, 0, s>>>(d, k);
   }
   k_advance_jitter<<<1, 64, 0, s>>>(d.ctl, n_steps);
   return hipGetLastError();
