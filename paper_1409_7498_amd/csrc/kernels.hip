@@ -793,16 +793,17 @@ __device__ __forceinline__ void retain(const Dev& d, const Arr& a, uint32_t step
 // LDS, one record per thread, and the brick's particles handled kTPass at a
 // time.  A T whose 2x2x2 cell block lies in the staged region scans it as four
 // runs of two x-adjacent cells (contiguous in LDS) and keeps up to four
-// in-range pairs in registers (one byte each); the wavefront then reserves queue slots for all
-// of them at once (ballot and mbcnt over the per-lane counts) and the queue is
-// drawn on full wavefronts after the pass.  Every other T is deferred to a
-// list and scanned again after the queue: T's with more in-range pairs than
-// the registers hold, or whose pairs find the queue full, in the staged
-// records; in the global buckets particles that drifted out of the staged
-// region since the last sort, bricks whose region holds more than kStageRecs
-// records, steps with bucket overflow, and all T's of kBrick = false (kThreads consecutive slots per
-// workgroup).  A deferred T enters the queue with none of its pairs, so every
-// pair is drawn exactly once.
+// in-range pairs in registers (one byte each); the wavefront then reserves
+// queue slots for all of them at once (ballot and mbcnt over the per-lane
+// counts) and the queue is drawn on full wavefronts after the pass.  Every
+// other T is deferred to a list and scanned again after the queue: T's with
+// more in-range pairs than the registers hold, or whose pairs find the queue
+// full, in the staged records; in the global buckets particles that drifted
+// out of the staged region since the last sort, bricks whose region holds
+// more than kStageRecs records, steps with bucket overflow, and all T's of
+// kBrick = false (kThreads consecutive slots per workgroup).  A deferred T
+// enters the queue with none of its pairs, so every pair is drawn exactly
+// once.
 // ---------------------------------------------------------------------------
 // One particle of a sweep pass, loaded with coalesced SoA reads.
 struct Part {
