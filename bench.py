@@ -51,7 +51,8 @@ SWEEP_B_PER_PARTICLE = 32.0   # x, y, z read (12) + type, state (8) + re-jittere
 BOND_B = 24.0                 # per new bond: the pair, two states, two adjacency entries
 REACT_B_PER_PARTICLE = 20.0   # the reaction step alone: x, y, z read (12) + type, state (8)
 COUNTERS = os.path.join(ROOT, "profiles", "k_sweep_step_growth_1M_counters.md")
-KERNEL_SRC = os.path.join(ROOT, "paper_1409_7498_amd", "csrc", "kernels.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1409_7498_amd", "csrc", f)
+               for f in ("kernels.hip", "common.hpp")]
 
 
 def log(*a):
@@ -59,8 +60,18 @@ def log(*a):
 
 
 def kernel_digest():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """SHA-256 (16 hex digits) of the kernels' code: kernels.hip and common.hpp
+    with line comments, trailing blanks and empty lines removed, so that an
+    edit of a comment keeps a counter summary valid and an edit of code does
+    not."""
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path) as f:
+            for line in f:
+                code = re.sub(r"(^|\s)//.*$", "", line.rstrip("\n")).rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
+    return h.hexdigest()[:16]
 
 
 def recorded_traffic():
@@ -69,7 +80,7 @@ def recorded_traffic():
     if not os.path.exists(COUNTERS):
         return None
     text = open(COUNTERS).read()
-    m_d = re.search(r"kernels\.hip digest:\s*([0-9a-f]+)", text)
+    m_d = re.search(r"kernel code digest:\s*([0-9a-f]+)", text)
     m_t = re.search(r"traffic bytes per launch:\s*([0-9.eE+]+)", text)
     if not (m_d and m_t) or m_d.group(1) != kernel_digest():
         return None
