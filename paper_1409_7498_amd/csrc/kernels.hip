@@ -2275,26 +2275,28 @@ __device__ __forceinline__ int xcd_brick(int g, int nbricks) {
   return x * q + min(x, r) + i;
 }
 
+// With fused binning there is no prep kernel: the closing groups of step
+// k - 1 trail the sweep of step k (workgroups nwg_sweep and up when k > 0).
+// Nothing the sweep reads or writes is theirs (the counters, staged bonds and
+// overflow words of step k - 1's parity, the log), and they are dispatched
+// with the sweep's workgroups, so their chain of round trips (with the
+// returning atomic that reserves log rows) runs beside the sweep instead of
+// lengthening the resolve.
 template <bool kBrick, bool kTwo, bool kF, bool kNt = false>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) void k_sweep(Dev d, int k) {
-  const int w = kBrick ? xcd_brick(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-  sweep_body<kBrick, kTwo, kF, kNt>(d, k, w, gridDim.x);
+  if (kF && (int)blockIdx.x >= d.nwg_sweep) {
+    __shared__ uint32_t s_wave[kThreads / 64 + 1];
+    const StepInfo si = step_info(d.ctl, k);
+    close_group(d, si.par ^ 1u, si.step - 1u, d.ctl->stats_n0 + (uint32_t)k - 1u,
+                (int)blockIdx.x - d.nwg_sweep, s_wave);
+    return;
+  }
+  const int w = kBrick ? xcd_brick(blockIdx.x, d.nwg_sweep) : (int)blockIdx.x;
+  sweep_body<kBrick, kTwo, kF, kNt>(d, k, w, d.nwg_sweep);
 }
-// With fused binning there is no prep kernel: the closing groups of step
-// k - 1 lead the resolve of step k.
 template <bool kBrick>
 __global__ __launch_bounds__(kThreads) void k_resolve(Dev d, int k) {
-  int b = blockIdx.x;
-  if (kBrick && d.fuse && k > 0) {
-    if (b < d.ngroups) {
-      __shared__ uint32_t s_wave[kThreads / 64 + 1];
-      const StepInfo si = step_info(d.ctl, k);
-      close_group(d, si.par ^ 1u, si.step - 1u, d.ctl->stats_n0 + (uint32_t)k - 1u, b, s_wave);
-      return;
-    }
-    b -= d.ngroups;
-  }
-  resolve_body<kBrick, true>(d, k, b, d.nwg_sweep);
+  resolve_body<kBrick, true>(d, k, blockIdx.x, d.nwg_sweep);
 }
 template <bool kBrick>
 __global__ __launch_bounds__(kThreads) void k_near_sweep(Dev d, int k) {
@@ -2355,8 +2357,21 @@ __global__ __launch_bounds__(kThreads) void k_prep_b(const Dev* __restrict__ ds,
   prep_body(d, k, m.y);
 }
 template <bool kTwo, bool kF>
+// With fused binning, workgroups nsw and up close step k - 1 of each replica
+// (closing map cmap), as the trailing workgroups of k_sweep do.
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) void k_sweep_b(
-    const Dev* __restrict__ ds, const int4* __restrict__ map, int k) {
+    const Dev* __restrict__ ds, const int4* __restrict__ map, int nsw,
+    const int4* __restrict__ cmap, int k) {
+  if (kF && (int)blockIdx.x >= nsw) {
+    const int4 c = cmap[__builtin_amdgcn_readfirstlane((int)blockIdx.x - nsw)];
+    const Dev& d = ds[__builtin_amdgcn_readfirstlane(c.x)];
+    if (k >= d.k_limit) return;  // the block end closes the replica's last step
+    __shared__ uint32_t s_wave[kThreads / 64 + 1];
+    const StepInfo si = step_info(d.ctl, k);
+    close_group(d, si.par ^ 1u, si.step - 1u, d.ctl->stats_n0 + (uint32_t)k - 1u,
+                __builtin_amdgcn_readfirstlane(c.y), s_wave);
+    return;
+  }
   const int4 m = uniform_map(map);
   const Dev& d = ds[m.x];
   if (k >= d.k_limit || d.rule.policy != PR_POLICY_RANDOM) return;
@@ -2376,26 +2391,12 @@ __global__ __launch_bounds__(kThreads) void k_near_resolve_b(const Dev* __restri
   if (k >= d.k_limit || d.rule.policy != PR_POLICY_NEAREST) return;
   near_resolve_body(d, k, m.y, m.z);
 }
-// With fused binning the first ncl workgroups close step k - 1 of each
-// replica (closing map), the rest resolve step k (resolve map).
 __global__ __launch_bounds__(kThreads) void k_resolve_b(const Dev* __restrict__ ds,
-                                                        const int4* __restrict__ map,
-                                                        const int4* __restrict__ cmap, int ncl,
-                                                        int k) {
-  if ((int)blockIdx.x < ncl) {
-    const int4 m = uniform_map(cmap);
-    const Dev& d = ds[m.x];
-    if (k >= d.k_limit) return;  // the block end closes the replica's last step
-    __shared__ uint32_t s_wave[kThreads / 64 + 1];
-    const StepInfo si = step_info(d.ctl, k);
-    close_group(d, si.par ^ 1u, si.step - 1u, d.ctl->stats_n0 + (uint32_t)k - 1u, m.y, s_wave);
-    return;
-  }
-  const int4 m = map[__builtin_amdgcn_readfirstlane((int)blockIdx.x - ncl)];
-  const Dev& d = ds[__builtin_amdgcn_readfirstlane(m.x)];
+                                                        const int4* __restrict__ map, int k) {
+  const int4 m = uniform_map(map);
+  const Dev& d = ds[m.x];
   if (k >= d.k_limit || d.rule.policy != PR_POLICY_RANDOM) return;
-  resolve_body<true, true>(d, k, __builtin_amdgcn_readfirstlane(m.y),
-                           __builtin_amdgcn_readfirstlane(m.z));
+  resolve_body<true, true>(d, k, m.y, m.z);
 }
 __global__ __launch_bounds__(kThreads) void k_close_b(const Dev* __restrict__ ds,
                                                       const int4* __restrict__ map, int k) {
@@ -2577,16 +2578,17 @@ hipError_t launch_step(const Dev& d, int k, hipStream_t s, hipEvent_t ev_sweep0,
                        hipEvent_t ev_sweep1) {
   for (int m = 0; d.md_theta > 0 && m <= d.md_theta; ++m)
     k_md<<<blocks_for(d.n, kThreads), kThreads, 0, s>>>(d, k, m);
-  if (d.fuse) {  // two kernels: sweep, then the closing of step k - 1 with the resolve
-    const dim3 g(d.nwg_sweep), b(kThreads);
-    // (edges above kOneCellBrick stage two region cells per thread)
+  if (d.fuse) {  // two kernels: the sweep (with the closing of step k - 1), the resolve
+    // the sweep, with the closing of step k - 1 in trailing workgroups (edges
+    // above kOneCellBrick stage two region cells per thread)
+    const dim3 g(d.nwg_sweep + (k > 0 ? d.ngroups : 0)), b(kThreads);
     auto kern = d.bs > kOneCellBrick ? (d.nt_pos ? k_sweep<true, true, true, true>
                                                  : k_sweep<true, true, true, false>)
                                      : (d.nt_pos ? k_sweep<true, false, true, true>
                                                  : k_sweep<true, false, true, false>);
     if (ev_sweep0) hipExtLaunchKernelGGL(kern, g, b, 0, s, ev_sweep0, ev_sweep1, 0, d, k);
     else kern<<<g, b, 0, s>>>(d, k);
-    k_resolve<true><<<(d.nwg_sweep + 3) / 4 + (k > 0 ? d.ngroups : 0), kThreads, 0, s>>>(d, k);
+    k_resolve<true><<<(d.nwg_sweep + 3) / 4, kThreads, 0, s>>>(d, k);
     return hipGetLastError();
   }
   const int prep_blocks = d.nwg_prep + (k > 0 ? d.ngroups : 0);
@@ -2679,13 +2681,15 @@ hipError_t launch_ctl_b(const BatchLaunch& b, int op, uint32_t arg, hipStream_t 
 }
 
 hipError_t launch_step_b(const BatchLaunch& b, int k, hipStream_t s) {
-  if (b.fuse) {  // every replica random and fused: sweep, then closing + resolve
-    if (b.two)
-      k_sweep_b<true, true><<<b.n_sweep, kThreads, 0, s>>>(b.ds, b.sweep, k);
-    else
-      k_sweep_b<false, true><<<b.n_sweep, kThreads, 0, s>>>(b.ds, b.sweep, k);
+  if (b.fuse) {  // every replica random and fused: sweep with the closing, then resolve
     const int ncl = k > 0 ? b.n_close : 0;
-    k_resolve_b<<<ncl + b.n_res, kThreads, 0, s>>>(b.ds, b.res, b.close, ncl, k);
+    if (b.two)
+      k_sweep_b<true, true><<<b.n_sweep + ncl, kThreads, 0, s>>>(b.ds, b.sweep, b.n_sweep,
+                                                                  b.close, k);
+    else
+      k_sweep_b<false, true><<<b.n_sweep + ncl, kThreads, 0, s>>>(b.ds, b.sweep, b.n_sweep,
+                                                                   b.close, k);
+    k_resolve_b<<<b.n_res, kThreads, 0, s>>>(b.ds, b.res, k);
     return hipGetLastError();
   }
   if (k > 0)
@@ -2694,10 +2698,11 @@ hipError_t launch_step_b(const BatchLaunch& b, int k, hipStream_t s) {
     k_prep_b<<<b.n_prep0, kThreads, 0, s>>>(b.ds, b.prep0, k);
   if (b.any_random) {
     if (b.two)
-      k_sweep_b<true, false><<<b.n_sweep, kThreads, 0, s>>>(b.ds, b.sweep, k);
+      k_sweep_b<true, false><<<b.n_sweep, kThreads, 0, s>>>(b.ds, b.sweep, b.n_sweep, b.close, k);
     else
-      k_sweep_b<false, false><<<b.n_sweep, kThreads, 0, s>>>(b.ds, b.sweep, k);
-    k_resolve_b<<<b.n_res, kThreads, 0, s>>>(b.ds, b.res, b.close, 0, k);
+      k_sweep_b<false, false><<<b.n_sweep, kThreads, 0, s>>>(b.ds, b.sweep, b.n_sweep, b.close,
+                                                             k);
+    k_resolve_b<<<b.n_res, kThreads, 0, s>>>(b.ds, b.res, k);
   }
   if (b.any_nearest) {
     k_near_sweep_b<<<b.n_sweep, kThreads, 0, s>>>(b.ds, b.sweep, k);
