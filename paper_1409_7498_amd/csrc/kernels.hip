@@ -1387,24 +1387,24 @@ __device__ __forceinline__ void resolve_body(const Dev& d, int k, int w, int nun
     s_prop[g] = 0;
   }
   if (threadIdx.x == 0) s_mode = read_err(c) ? 0 : (c->ret_ovf[par] ? 2 : 1);
+  // the list's length and its entries in one round trip, issued before the
+  // mode is known (read but not used in the other modes, as are entries past
+  // the length), then the A keys with the bonds' operands in a second one
+  int ne = 0;
+  int4 e = make_int4(0, 0, 0, 0);
+  uint32_t w2 = 0;
+  if (live) {
+    ne = pick(d.wgo, par)[w * kWgOut + kOutRet];
+    if (tid < kRetCap) {
+      e = pick(d.wge, par)[w * kRetCap + tid];
+      w2 = pick(d.wgk, par)[w * kRetCap + tid];
+    }
+  }
   __syncthreads();
   const int mode = s_mode;
   const Arr a = pick_set(d, c->set & 1u);
   const BondCtx bc{&s_nw[g], &s_lost[g], step};
   if (mode == 1) {
-    // the list's length and its entries in one round trip (entries past the
-    // length are read but not used), then the A keys with the bonds'
-    // operands in a second one
-    int ne = 0;
-    int4 e = make_int4(0, 0, 0, 0);
-    uint32_t w2 = 0;
-    if (live) {
-      ne = pick(d.wgo, par)[w * kWgOut + kOutRet];
-      if (tid < kRetCap) {
-        e = pick(d.wge, par)[w * kRetCap + tid];
-        w2 = pick(d.wgk, par)[w * kRetCap + tid];
-      }
-    }
     const bool ahead = d.adj_staged != 0;
     bool chosen = false;
     unsigned long long key = kEmpty;
