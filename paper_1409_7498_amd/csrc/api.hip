@@ -618,6 +618,7 @@ struct pr_sys {
     float jit = -1.0f;
     long long part = 0;
     int32_t fuse = 0;
+    uint32_t kpar0 = 0;  // parity origin the segment was captured at
     uint64_t used = 0;
   };
   std::vector<Seg> segs;
@@ -752,6 +753,7 @@ int after_load(pr_sys* s) {
   HIP_TRY(hipMemsetAsync(s->d.cnt[0], 0, sizeof(uint32_t) * (size_t)s->d.ncell, st));
   HIP_TRY(hipMemsetAsync(s->d.cnt[1], 0, sizeof(uint32_t) * (size_t)s->d.ncell, st));
   HIP_TRY(launch_ctl_reset(s->d.ctl, 0, 1, st));
+  s->d.kpar0 = 0;
   HIP_TRY(launch_identity(s->d, st));
   HIP_TRY(launch_classify(s->d, st));
   int e = sync_ctl(s);
@@ -794,6 +796,7 @@ int run_block(pr_sys* s, hipStream_t st, int32_t K, hipEvent_t* ev,
     HIP_TRY(launch_step(s->d, k, st, ev ? ev[1] : nullptr, ev ? ev[2] : nullptr));
   HIP_TRY(launch_block_end(s->d, K, st));
   s->steps_since_sort += K;
+  s->d.kpar0 = (s->d.kpar0 + (uint32_t)K) & 1u;
   return PR_OK;
 }
 
@@ -823,6 +826,7 @@ void after_segment(pr_sys* s, int32_t K, bool with_sort) {
   } else {
     s->steps_since_sort += K;
   }
+  s->d.kpar0 = (s->d.kpar0 + (uint32_t)K) & 1u;
 }
 
 // The captured graph of a segment of K steps (with a sort first when
@@ -831,7 +835,7 @@ int segment_graph(pr_sys* s, int32_t K, bool with_sort, hipGraphExec_t* out) {
   const long long part = (long long)(size_t)s->d.part;
   for (pr_sys::Seg& g : s->segs)
     if (g.steps == K && g.sort == with_sort && g.jit == s->d.jit_c && g.part == part &&
-        g.fuse == s->d.fuse) {
+        g.fuse == s->d.fuse && g.kpar0 == s->d.kpar0) {
       g.used = ++s->seg_clock;
       *out = g.gexec;
       return PR_OK;
@@ -871,6 +875,7 @@ int segment_graph(pr_sys* s, int32_t K, bool with_sort, hipGraphExec_t* out) {
   seg.jit = s->d.jit_c;
   seg.part = part;
   seg.fuse = s->d.fuse;
+  seg.kpar0 = s->d.kpar0;
   seg.used = ++s->seg_clock;
   s->segs.push_back(seg);
   *out = ge;
@@ -1296,6 +1301,7 @@ int pr_sys_jitter(pr_sys* s, uint32_t first_step, uint32_t n_steps, double sigma
   HIP_TRY(launch_ctl_reset(s->d.ctl, first_step, 0, st));
   if (!kernel_ms) {
     HIP_TRY(launch_jitter_only(s->d, (int)n_steps, st, nullptr, nullptr));
+    s->d.kpar0 = (s->d.kpar0 + n_steps) & 1u;
     return PR_OK;
   }
   // per-step kernel times, stamped at each kernel's own start and end
@@ -1310,6 +1316,7 @@ int pr_sys_jitter(pr_sys* s, uint32_t first_step, uint32_t n_steps, double sigma
       e = fail(PR_EHIP, "jitter-only launch failed");
       break;
     }
+    s->d.kpar0 = (s->d.kpar0 + 1u) & 1u;
     float ms = 0.0f;
     (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
     total += ms;
@@ -2016,6 +2023,7 @@ int pr_batch_run(pr_batch* b, uint32_t first_step, uint32_t n_steps, double sigm
     drop_graph(s);
     s->steps_since_sort = n_steps % (uint32_t)K == 0 ? K : (int32_t)(n_steps % (uint32_t)K);
     s->steps_since_load += n_steps;
+    s->d.kpar0 = (s->d.kpar0 + n_steps) & 1u;  // the batch advanced the parity origin
   }
   return PR_OK;
 }
@@ -2298,6 +2306,7 @@ int srv_end_round(pr_server* S) {
     drop_graph(r->sys);
     r->sys->steps_since_sort = (int64_t)r->round_steps;
     r->sys->steps_since_load += r->round_steps;
+    r->sys->d.kpar0 = (r->sys->d.kpar0 + r->round_steps) & 1u;
   }
   return PR_OK;
 }

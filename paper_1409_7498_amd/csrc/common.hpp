@@ -161,6 +161,10 @@ struct Dev {
   // apos[slot]: where the A's record of the next step went (bucket index, or
   // -1 - overflow index), for the resolve to drop it if the A's role ends
   int32_t fuse;
+  // resident systems: the control block's parity origin (par0) as the host
+  // keeps it, so that the resolve addresses its lists without reading the
+  // control block first
+  uint32_t kpar0;
   uint32_t* fcnt[3];
   float4* frec[2];
   int32_t* fsa[2];

@@ -1366,7 +1366,9 @@ __device__ __forceinline__ void make_bond_ahead(const Dev& d, const Arr& a, uint
 // kWave: one wavefront per unit (four units per workgroup, unit = blockIdx.x
 // * 4 + wavefront); else the whole workgroup handles unit w.  Every barrier
 // is taken by the whole workgroup (mode is the same for all its units).
-template <bool kBrick, bool kWave>
+// kHostPar: the step's parity from Dev::kpar0 (resident systems), else from
+// the control block.
+template <bool kBrick, bool kWave, bool kHostPar = false>
 __device__ __forceinline__ void resolve_body(const Dev& d, int k, int w, int nunits) {
   constexpr int kG = kWave ? kThreads / 64 : 1;  // units per workgroup
   constexpr int kL = kWave ? 64 : kThreads;      // lanes per unit
@@ -1380,7 +1382,7 @@ __device__ __forceinline__ void resolve_body(const Dev& d, int k, int w, int nun
   const bool live = !kWave || w < nunits;  // the last workgroup's spare wavefronts
   const Ctl* c = d.ctl;
   const StepInfo si = step_info(c, k);
-  const uint32_t par = si.par, step = si.step;
+  const uint32_t par = kHostPar ? (d.kpar0 + (uint32_t)k) & 1u : si.par, step = si.step;
   if (tid == 0) {
     s_nw[g] = 0;
     s_lost[g] = 0;
@@ -2296,7 +2298,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
 }
 template <bool kBrick>
 __global__ __launch_bounds__(kThreads) void k_resolve(Dev d, int k) {
-  resolve_body<kBrick, true>(d, k, blockIdx.x, d.nwg_sweep);
+  resolve_body<kBrick, true, true>(d, k, blockIdx.x, d.nwg_sweep);
 }
 template <bool kBrick>
 __global__ __launch_bounds__(kThreads) void k_near_sweep(Dev d, int k) {
