@@ -209,6 +209,43 @@ def test_c1_full_run(B, sort_period, graphs):
     assert len(log) > 200
 
 
+@pytest.mark.parametrize("timed", [False, True])
+@pytest.mark.parametrize("sort_period,graphs", [(64, True), (3, True), (0, False)])
+def test_jitter_only_between_runs(B, timed, sort_period, graphs):
+    """Reaction runs with re-jitter-only steps between them (an odd number,
+    so the position parity the next run starts at flips): the same as the
+    oracle taking the same steps, reaction and re-jitter alike."""
+    from paper_1409_7498_amd import binding
+    c = workload.CONFIGS["c1"]
+    cfg = gen(c.N, c.L, c.kind, c.seed)
+    rule = c.rule()
+    s = binding.System(c.N, cfg["L"], cfg["adj"].shape[1], rule, c.seed, log_cap=8 * c.N)
+    s.set_sort_period(sort_period)
+    s.set_graphs(graphs)
+    s.load(cfg)
+    s.run(1, 7, c.sigma)
+    s.jitter(8, 3, c.sigma, timed=timed)
+    s.run(11, 9, c.sigma)
+    s.jitter(20, 1, c.sigma, timed=timed)
+    s.run(21, 4, c.sigma)
+    out, log = s.read(), s.bonds()
+    s.close()
+    o = oracle_system(cfg)
+    orule = oracle_rule(rule)
+    logs = []
+    for first, n, jit in ((1, 7, (8, 9, 10)), (11, 9, (20,)), (21, 4, ())):
+        code, olog, _ = oracle.run(o, orule, c.seed, first, n, c.sigma)
+        assert code == 0
+        logs.append(olog)
+        for step in jit:
+            oracle.jitter(o, c.seed, step, c.sigma)
+    olog = np.concatenate(logs)
+    assert len(olog) > 20
+    assert np.array_equal(log, olog), (len(log), len(olog))
+    for k in ("x", "y", "z", "state", "adj"):
+        assert np.array_equal(out[k], getattr(o, k)), k
+
+
 @pytest.mark.parametrize("sort_period", [1000, 5])
 def test_a_list_growth_and_compaction(B, sort_period):
     """Chain growth with half the particles active and p = 1: the A list gains
