@@ -859,7 +859,6 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
   __shared__ int4 s_radj[kBrick ? kStageRecs : 1];
   __shared__ int32_t s_rsa[kBrick ? kStageRecs : 1];
   __shared__ uint16_t s_off[kBrick ? kCells + 1 : 1];  // first record of a region cell
-  __shared__ uint16_t s_rcell[kBrick ? kStageRecs : 1];  // staged record -> region cell
   __shared__ uint32_t s_q[kBrick ? kQueue : 1];  // queued pair: local T | staged record << 16
   __shared__ int32_t s_tid[kBrick ? kTP : 1];    // ids of the pass's T's
   __shared__ uint16_t s_def[kTP];            // deferred T's (local index in the pass)
@@ -898,6 +897,7 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
   const int nc = d.nc;
   int ncs = 0;
   uint32_t mine = 0, mine2 = 0, m_exy = 0, m_ex = 0;
+  int gc = 0, gc2 = 0;  // global cells of this thread's region cells
   // global cell of region cell cl (region cells in z, y, x order)
   auto region_cell = [&](int cl) {
     const int lz = div_small(cl, m_exy), rem = cl - lz * ex * ey;
@@ -929,7 +929,11 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
 #pragma unroll
     for (int h = 0; h < (kTwo ? 2 : 1); ++h) {
       const int cl = kTwo ? 2 * tid + h : tid;
-      if (cl < ncs) (h ? mine2 : mine) = bk.cnt[region_cell(cl)];
+      if (cl < ncs) {
+        const int gcl = region_cell(cl);
+        (h ? gc2 : gc) = gcl;
+        (h ? mine2 : mine) = bk.cnt[gcl];
+      }
     }
   }
   // the first particle of the first pass, issued behind the record counts
@@ -940,26 +944,41 @@ __device__ __forceinline__ void sweep_body(const Dev& d, int k, int w, int nwg) 
     mine2 = mine2 < (uint32_t)kCellCap ? mine2 : (uint32_t)kCellCap;
     uint32_t total = 0;
     const uint32_t off = block_scan_excl(mine + mine2, s_wave, total);
+    staged = total <= (uint32_t)kStageRecs && bk.novf == 0;
+    // each thread stages the records of its own region cells: the first
+    // kFirst of a cell loaded together, the rare rest one after another
+    constexpr int kFirst = kTwo ? 2 : 4;
 #pragma unroll
     for (int h = 0; h < (kTwo ? 2 : 1); ++h) {
       const int cl = kTwo ? 2 * tid + h : tid;
       const uint32_t o = h ? off + mine : off, m = h ? mine2 : mine;
       if (cl < ncs) {
         s_off[cl] = (uint16_t)o;
-        for (uint32_t j = 0; j < m && o + j < (uint32_t)kStageRecs; ++j)
-          s_rcell[o + j] = (uint16_t)cl;
+        if (staged) {
+          const size_t r0 = (size_t)(h ? gc2 : gc) * kCellCap;
+          // the first records in registers (named, so that none of them
+          // lives in scratch), loaded together, then written to LDS
+          float4 rv0 = make_float4(0.f, 0.f, 0.f, 0.f), rv1 = rv0, rv2 = rv0, rv3 = rv0;
+          int32_t sv0 = 0, sv1 = 0, sv2 = 0, sv3 = 0;
+          if (m > 0u) { rv0 = bk.rec[r0]; sv0 = bk.sa[r0]; }
+          if (m > 1u) { rv1 = bk.rec[r0 + 1]; sv1 = bk.sa[r0 + 1]; }
+          if (kFirst > 2 && m > 2u) { rv2 = bk.rec[r0 + 2]; sv2 = bk.sa[r0 + 2]; }
+          if (kFirst > 3 && m > 3u) { rv3 = bk.rec[r0 + 3]; sv3 = bk.sa[r0 + 3]; }
+          if (m > 0u) { s_rec[o] = rv0; s_rsa[o] = sv0; }
+          if (m > 1u) { s_rec[o + 1] = rv1; s_rsa[o + 1] = sv1; }
+          if (kFirst > 2 && m > 2u) { s_rec[o + 2] = rv2; s_rsa[o + 2] = sv2; }
+          if (kFirst > 3 && m > 3u) { s_rec[o + 3] = rv3; s_rsa[o + 3] = sv3; }
+          if (!kF && d.adj_staged)
+            for (uint32_t j = 0; j < m && j < (uint32_t)kFirst; ++j) s_radj[o + j] = d.radj[r0 + j];
+          for (uint32_t j = kFirst; j < m; ++j) {
+            s_rec[o + j] = bk.rec[r0 + j];
+            s_rsa[o + j] = bk.sa[r0 + j];
+            if (!kF && d.adj_staged) s_radj[o + j] = d.radj[r0 + j];
+          }
+        }
       }
     }
     if (tid == 0) s_off[ncs] = (uint16_t)total;
-    staged = total <= (uint32_t)kStageRecs && bk.novf == 0;
-    __syncthreads();
-    if (staged && tid < (int)total) {
-      const int lo = s_rcell[tid];  // the region cell of record tid
-      const size_t ri = (size_t)region_cell(lo) * kCellCap + (tid - (int)s_off[lo]);
-      s_rec[tid] = bk.rec[ri];
-      s_rsa[tid] = bk.sa[ri];
-      if (!kF && d.adj_staged) s_radj[tid] = d.radj[ri];
-    }
   }
   __syncthreads();
   const bool dead = s_dead != 0;
