@@ -790,8 +790,8 @@ __device__ __forceinline__ void retain(const Dev& d, const Arr& a, uint32_t step
 // the other position buffer; T's test the step's A records at their new
 // positions.  kBrick = sorted storage: one workgroup per brick, the A records
 // of the brick and its halo (positions, ids, slots, adjacency rows) staged in
-// LDS, one record per thread, and the brick's particles handled kTPass at a
-// time.  A T whose 2x2x2 cell block lies in the staged region scans it as four
+// LDS, each region cell's by the thread that read its count, and the brick's
+// particles handled kTPass at a time.  A T whose 2x2x2 cell block lies in the staged region scans it as four
 // runs of two x-adjacent cells (contiguous in LDS) and keeps up to four
 // in-range pairs in registers (one byte each); the wavefront then reserves
 // queue slots for all of them at once (ballot and mbcnt over the per-lane
