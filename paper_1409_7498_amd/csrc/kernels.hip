@@ -232,48 +232,45 @@ __device__ __forceinline__ StepInfo step_info(const Ctl* c, int k) {
 // Buffers kept by step mod 3 (fused binning).
 __device__ __forceinline__ uint32_t mod3(uint32_t step) { return step % 3u; }
 
-// Exclusive prefix sum over the workgroup (wave64 shuffles, then wave
-// totals in LDS).  Every thread of the block must call it.
+// Inclusive prefix sum over the wavefront with DPP: shifts by 1, 2, 4 and 8
+// lanes within each row of 16, then the row broadcasts of lanes 15 and 31
+// (lanes without a source add 0).  Every lane of the wavefront must be
+// active.
+__device__ __forceinline__ uint32_t wave_scan_incl(uint32_t x) {
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false);  // row_shr:1
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false);  // row_shr:2
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false);  // row_shr:4
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false);  // row_shr:8
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);  // row_bcast:15
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);  // row_bcast:31
+  return x;
+}
+
+// Exclusive prefix sum over the workgroup (wavefront scans, then the
+// wavefront totals through LDS, read by every thread).  Every thread of the
+// block must call it, with every lane active.
 __device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t* s_wave,
                                                     uint32_t& total) {
   const int lane = __lane_id(), w = threadIdx.x / 64, nw = blockDim.x / 64;
-  uint32_t x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(x, o);
-    if (lane >= o) x += y;
-  }
+  const uint32_t x = wave_scan_incl(v);
   if (lane == 63) s_wave[w] = x;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t acc = 0;
-    for (int i = 0; i < nw; ++i) {
-      const uint32_t t = s_wave[i];
-      s_wave[i] = acc;
-      acc += t;
-    }
-    s_wave[nw] = acc;
+  uint32_t below = 0, all = 0;
+  for (int i = 0; i < nw; ++i) {
+    const uint32_t t = s_wave[i];
+    below += i < w ? t : 0u;
+    all += t;
   }
-  __syncthreads();
-  total = s_wave[nw];
-  const uint32_t r = s_wave[w] + x - v;
-  __syncthreads();
-  return r;
-}
-
-// Sum over the wavefront (every lane of the wave must call it); the result
-// is valid in every lane.
-__device__ __forceinline__ int wave_sum(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+  total = all;
+  __syncthreads();  // s_wave is free for the next call
+  return below + x - v;
 }
 
 // Adds v of every lane to *dst with one LDS atomic per wavefront (every lane
-// of the wave must call it).
+// of the wave must call it, with every lane active).
 __device__ __forceinline__ void wave_add(int* dst, int v) {
-  const int t = wave_sum(v);
-  if (__lane_id() == 0 && t) atomicAdd(dst, t);
+  const int t = (int)wave_scan_incl((uint32_t)v);  // lane 63: the wavefront's sum
+  if (__lane_id() == 63 && t) atomicAdd(dst, t);
 }
 
 // ---------------------------------------------------------------------------
