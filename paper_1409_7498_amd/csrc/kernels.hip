@@ -476,13 +476,8 @@ __device__ __forceinline__ void prep_body(const Dev& d, int k, int blk) {
   for (int q = 0; q < kPrepRoles / 4; ++q)
 #pragma unroll
     for (int e = 0; e < 4; ++e) na += role_is_a((rw[q] >> (8 * e)) & 0xFFu, multi);
-  uint32_t incl = (uint32_t)na;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(incl, o);
-    if (lane >= o) incl += y;
-  }
-  const int wtot = (int)__shfl(incl, 63);
+  const uint32_t incl = wave_scan_incl((uint32_t)na);
+  const int wtot = __builtin_amdgcn_readlane((int)incl, 63);
   int at = (int)incl - na;
 #pragma unroll
   for (int q = 0; q < kPrepRoles / 4; ++q)
@@ -2188,12 +2183,7 @@ __device__ __forceinline__ void sort_local_body(const Dev& d, int b) {
     v[q] = q < per && j0 + q < nd ? c[j0 + q] : 0u;
     sum += v[q];
   }
-  uint32_t x = sum;
-#pragma unroll
-  for (int q = 1; q < 64; q <<= 1) {
-    const uint32_t y = __shfl_up(x, q);
-    if (lane >= q) x += y;
-  }
+  const uint32_t x = wave_scan_incl(sum);
   uint32_t run = x - sum;
 #pragma unroll
   for (int q = 0; q < kPerLane; ++q) {
@@ -2203,7 +2193,7 @@ __device__ __forceinline__ void sort_local_body(const Dev& d, int b) {
     }
     run += v[q];
   }
-  const uint32_t total = __shfl(x, 63);
+  const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
   if (lane == 0) d.bcnt[b] = total;
 }
 
