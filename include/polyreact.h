@@ -317,9 +317,12 @@ int pr_sys_read(pr_sys* s, float* x, float* y, float* z, int32_t* state, int32_t
                 int32_t on_device);
 
 /* Copies the bond log out: up to cap rows of (step, id_A, id_T) int32 into
- * host memory, ordered by step and, within a step, by id_A; *n receives the
- * total logged (PR_ECAP if it exceeded the log capacity; rows beyond it were
- * dropped).  Synchronises. */
+ * host memory, ordered by step and, within a step, by id_A (Table I, step 9);
+ * *n receives the total logged (PR_ECAP if it exceeded the log capacity; rows
+ * beyond it were dropped).  The order is made on the device, in place: the
+ * log in HBM stays in that order and later steps append after it.  Takes
+ * temporary device memory (about 24 bytes per logged row) from the stream's
+ * memory pool.  Synchronises. */
 int pr_sys_bonds(pr_sys* s, int32_t* out, int64_t cap, int64_t* n);
 
 /* Copies the per-step counters of the steps run since the last load (at most

@@ -37,6 +37,7 @@ hipError_t launch_step(const Dev& d, int k, hipStream_t s, hipEvent_t ev_sweep0,
 hipError_t launch_block_end(const Dev& d, int K, hipStream_t s);
 hipError_t launch_single_end(const Dev& d, hipStream_t s);
 hipError_t launch_sort(const Dev& d, hipStream_t s);
+hipError_t log_order(int32_t* log, int64_t n, hipStream_t s);
 hipError_t launch_gather_out(const Dev& d, float* ox, float* oy, float* oz, int32_t* otyp,
                              int32_t* ost, int32_t* oadj, hipStream_t s);
 hipError_t launch_draws(const uint32_t* ctr, long long n, unsigned long long key, uint32_t* out,
@@ -1456,41 +1457,25 @@ int sys_bonds(pr_sys* s, int32_t* out, int64_t cap, int64_t* n, void* pin, size_
   const int64_t have = std::min<int64_t>(total, s->log_cap);
   const int64_t m = std::min<int64_t>(have, cap);
   if (m > 0) {
-    // rows of one step were appended in workgroup order: order them by
-    // (step, id_A) -- steps are already in order, id_A is unique in a step
+    // the rows of one step were appended in workgroup order: the device
+    // orders the log in place by (step, id_A) (log_order), then it is copied
     struct Row {
       int32_t step, a, t;
     };
+    HIP_TRY(log_order(s->d.log, have, s->stream));
     std::vector<Row> vrows;
     Row* rows = nullptr;
-    if (pin && pin_bytes >= (size_t)have * sizeof(Row)) {
+    if (pin && pin_bytes >= (size_t)m * sizeof(Row)) {
       rows = (Row*)pin;
     } else {
-      vrows.resize((size_t)have);
+      vrows.resize((size_t)m);
       rows = vrows.data();
     }
-    HIP_TRY(hipMemcpyAsync(rows, s->d.log, (size_t)have * sizeof(Row), hipMemcpyDeviceToHost,
+    HIP_TRY(hipMemcpyAsync(rows, s->d.log, (size_t)m * sizeof(Row), hipMemcpyDeviceToHost,
                            s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
-    // the rows of one step are appended together, steps in order: sorting
-    // each step's run by id_A is enough (else everything is sorted)
-    const size_t nr = (size_t)have;
-    bool runs = true;
-    for (size_t i = 1; i < nr && runs; ++i) runs = rows[i - 1].step <= rows[i].step;
-    if (runs) {
-      for (size_t i = 0; i < nr;) {
-        size_t j = i + 1;
-        while (j < nr && rows[j].step == rows[i].step) ++j;
-        std::sort(rows + i, rows + j, [](const Row& u, const Row& v) { return u.a < v.a; });
-        i = j;
-      }
-    } else {
-      std::sort(rows, rows + nr, [](const Row& u, const Row& v) {
-        return u.step != v.step ? u.step < v.step : u.a < v.a;
-      });
-    }
     if (s->d.nrules > 1)  // the rule of each bond rides in bits 30-31 of id_T
-      for (size_t i = 0; i < nr; ++i) rows[i].t &= 0x3FFFFFFF;
+      for (size_t i = 0; i < (size_t)m; ++i) rows[i].t &= 0x3FFFFFFF;
     std::memcpy(out, rows, (size_t)m * sizeof(Row));
   }
   *n = total;

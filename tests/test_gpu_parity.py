@@ -246,6 +246,39 @@ def test_jitter_only_between_runs(B, timed, sort_period, graphs):
         assert np.array_equal(out[k], getattr(o, k)), k
 
 
+def test_log_ordered_in_place_between_runs(B):
+    """Each read orders the bond log on the device, in place (Table I step 9:
+    a step's bonds by id_A).  Reads between runs, whole and truncated, must
+    leave the rows appended later intact: every read equals the oracle's log
+    so far, and a truncated read is its prefix."""
+    import ctypes as C
+    c = workload.CONFIGS["c1"]
+    cfg = gen(c.N, c.L, c.kind, c.seed)
+    rule = _rule("step", 0.2)
+    s = B.System(c.N, c.L, 4, rule, c.seed, log_cap=8 * c.N)
+    s.load(cfg)
+    o = oracle_system(cfg)
+    orule = oracle_rule(rule)
+    logs, first = [], 1
+    for n in (5, 1, 9, 3):
+        s.run(first, n, c.sigma)
+        code, olog, _ = oracle.run(o, orule, c.seed, first, n, c.sigma)
+        assert code == 0
+        logs.append(olog)
+        first += n
+        want = np.concatenate(logs)
+        half = len(want) // 2
+        part = np.empty((max(half, 1), 3), np.int32)
+        got_n = C.c_int64(0)
+        assert B.lib.pr_sys_bonds(s._h, part.ctypes.data_as(C.c_void_p), half,
+                                  C.byref(got_n)) == 0
+        assert got_n.value == len(want)
+        assert np.array_equal(part[:half], want[:half])
+        assert np.array_equal(s.bonds(), want), (first, len(want))
+    assert len(want) > 50
+    s.close()
+
+
 @pytest.mark.parametrize("sort_period", [1000, 5])
 def test_a_list_growth_and_compaction(B, sort_period):
     """Chain growth with half the particles active and p = 1: the A list gains
