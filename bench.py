@@ -304,6 +304,128 @@ def bench_serve(args):
     print(json.dumps(res), flush=True)
 
 
+ROW_N = 1 << 20
+KIN_B_PER_PARTICLE = 25.0  # type, state (8) + role (1) + x, y, z (12) + id (4)
+
+
+def md_bytes(B):
+    """Algorithmic bytes of one MD step per particle: positions and velocities
+    read and written (48) and the adjacency row read (4 B)."""
+    return 48.0 + 4.0 * B
+
+
+def bench_row(args):
+    """Measurement of the rows beyond the paper's step, each on a 1,048,576-
+    particle system generated like the default workload:
+      f2  two concurrent rules (chain initiation and propagation: initiators of
+          type 1 and active ends of type 0 both bond free monomers), steps
+          replayed from graphs as the default path;
+      f3  the kinetics counters (pr_sys_kinetics: populations, partner counts,
+          distance histogram) of the default workload after the warm-up steps,
+          wall time per call (a synchronising read-out);
+      f4  the bonded-force coupling: theta velocity-Verlet MD steps under the
+          mirror-LJ bond force before each reaction step of the default
+          workload (MD in place of the re-jitter).
+    The "nearest" policy (f1) is the default path with --policy nearest."""
+    import numpy as np
+    import torch
+    from paper_1409_7498_amd import binding, workload
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    K, W = args.steps, args.warmup
+    cfg = workload.CONFIGS["c2"]
+    out = {"n_gpus": 1, "steps": K, "warmup": W, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32+u32", "cpu_baseline": None}
+
+    def timed_run(s, first, sigma):
+        s.prepare(K, sigma)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        s.run(first, K, sigma)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        st = s.stats()[-K:]
+        return e0.elapsed_time(e1) / K, sum(r["bonds"] for r in st) / K
+
+    if args.row == "f2":
+        N = ROW_N
+        L = workload.box_for(N)
+        g = workload.generate(N, L, "chain", cfg.seed)
+        init = np.random.default_rng(cfg.seed).choice(N, N // 200, replace=False)
+        g["type"][init] = 1
+        g["state"][init] = 2
+        r = lambda ta: dict(type_a=ta, a_min=2, a_max=2, d_a=-1, type_t=0, t_min=0, t_max=0,
+                            d_t=2, rc=workload.RC, p=0.02, exclude_bonded=1, policy="random")
+        rules = [r(1), r(0)]
+        s = binding.System(N, L, 2, rules, cfg.seed, log_cap=2 * N, stream=stream)
+        s.load(g)
+        s.run(1, W, cfg.sigma)
+        ms, bonds = timed_run(s, 1 + W, cfg.sigma)
+        s.close()
+        out.update({"metric": "reaction-step particles/s, two concurrent rules",
+                    "value": N / (ms * 1e-3), "unit": "particles/s", "ms_per_step": ms,
+                    "bonds_per_step": bonds,
+                    "data": "synthetic (jittered lattice, 0.5% initiators of type 1)",
+                    "config": {"workload": "chain initiation + propagation, N=%d L=%g rc=%g "
+                                           "p=0.02 each; a step = re-jitter (sigma=%g) + "
+                                           "reaction step over both rules" % (N, L, workload.RC,
+                                                                               cfg.sigma),
+                               "row": "f2", "path": "graph replay (binning kernel, sweep, "
+                                                    "resolve, final kernels per step)"}})
+    elif args.row == "f3":
+        s = binding.System(cfg.N, cfg.L, cfg.B, cfg.rule(), cfg.seed, log_cap=2 * cfg.N,
+                           stream=stream)
+        s.generate(cfg.kind, cfg.gen_seed, workload.SIGMA_LATTICE)
+        s.run(1, W, cfg.sigma)
+        s.kinetics(8, 16)
+        torch.cuda.synchronize()
+        reps = max(K // 16, 5)
+        t = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            pop, pairs, hist = s.kinetics(8, 16)
+            t.append(time.perf_counter() - t0)
+        s.close()
+        us = sorted(t)[len(t) // 2] * 1e6
+        gbs = KIN_B_PER_PARTICLE * cfg.N / (us * 1e-6) / 1e9
+        out.update({"metric": "kinetics counters: particles/s per read-out",
+                    "value": cfg.N / (us * 1e-6), "unit": "particles/s", "ms_per_step": None,
+                    "us_per_call": us, "calls": reps, "pop": pop.tolist(),
+                    "pairs": pairs.tolist(), "hist_total": int(hist.sum()),
+                    "data": "synthetic (jittered lattice, generated on device)",
+                    "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
+                                 "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                                 "kernel": "pr_sys_kinetics (wall time of the call)",
+                                 "bytes_per_launch": KIN_B_PER_PARTICLE * cfg.N},
+                    "config": {"workload": "step growth N=%d after %d steps; 8 states, 16 "
+                                           "distance bins" % (cfg.N, W), "row": "f3",
+                               "path": "median wall time of one call (binning, two kernels, "
+                                       "copy to host)"}})
+    elif args.row == "f4":
+        theta = args.md_theta
+        s = binding.System(cfg.N, cfg.L, cfg.B, cfg.rule(), cfg.seed, log_cap=2 * cfg.N,
+                           stream=stream)
+        s.generate(cfg.kind, cfg.gen_seed, workload.SIGMA_LATTICE)
+        s.set_md(theta, 0.0025, 1.0, 1.0, 1.0, 7)
+        s.run(1, W, 0.0)
+        ms, bonds = timed_run(s, 1 + W, 0.0)
+        s.close()
+        out.update({"metric": "reaction steps with bonded MD: particles/s",
+                    "value": cfg.N / (ms * 1e-3), "unit": "particles/s", "ms_per_step": ms,
+                    "md_steps_per_reaction_step": theta, "bonds_per_step": bonds,
+                    "md_bytes_per_particle_step": md_bytes(cfg.B),
+                    "data": "synthetic (jittered lattice, generated on device)",
+                    "config": {"workload": "step growth N=%d L=%g rc=%g p=%g; a step = %d "
+                                           "velocity-Verlet steps (dt=0.0025, mirror-LJ bonds, "
+                                           "sigma=eps=1, T=1) + reaction step"
+                                           % (cfg.N, cfg.L, cfg.rc, cfg.p, theta),
+                               "row": "f4", "path": "graph replay"}})
+    else:
+        raise SystemExit("--row: f2, f3 or f4 (f1 is --policy nearest)")
+    print(json.dumps(out), flush=True)
+
+
 def copy_bandwidth(mib=1024, reps=5, width=16):
     """Measured device copy ceiling in GB/s (bytes read plus written per
     second): the median kernel time of `reps` copies of `mib` MiB with the
@@ -323,6 +445,9 @@ def main():
     ap.add_argument("--steps", type=int, default=256)
     ap.add_argument("--warmup", type=int, default=64)
     ap.add_argument("--config", default="c2")
+    ap.add_argument("--row", default=None, choices=["f2", "f3", "f4"],
+                    help="measure a row beyond the paper's step (bench_row)")
+    ap.add_argument("--md-theta", type=int, default=10, help="f4: MD steps per reaction step")
     ap.add_argument("--policy", default="random", choices=["random", "nearest"],
                     help="selection: the paper's (random) or LAMMPS fix bond/create's "
                          "closest partner (nearest)")
@@ -369,6 +494,8 @@ def main():
         return
     from paper_1409_7498_amd import binding, workload
 
+    if args.row:
+        return bench_row(args)
     if args.config == "c4":
         return bench_batch(args)
     if args.config == "c5":

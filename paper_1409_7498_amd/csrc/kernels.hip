@@ -1572,6 +1572,208 @@ __device__ __forceinline__ void near_sweep_body(const Dev& d, int k, int w, int 
   }
 }
 
+// near_sweep_body on sorted storage with the brick's A records staged in LDS
+// (brick edges up to kOneCellBrick: one region cell per thread), as the
+// random selection's sweep stages them: each T scans the four runs of its
+// 2x2x2 block in LDS and tests the exclusion against the staged adjacency
+// row.  A T whose block leaves the staged region, and every T of a brick
+// whose region holds more than kStageRecs records or of a step with bucket
+// overflow, scans the global buckets as near_sweep_body does.  The same
+// pairs get the same keys, so the outcome is that of near_sweep_body.
+__device__ __forceinline__ void near_sweep_staged_body(const Dev& d, int k, int w, int nwg) {
+  __shared__ float4 s_rec[kStageRecs];
+  __shared__ int4 s_radj[kStageRecs];
+  __shared__ int32_t s_rsa[kStageRecs];
+  __shared__ uint16_t s_off[kStageCells1 + 1];
+  __shared__ uint32_t s_wave[kThreads / 64 + 1];
+  __shared__ int s_cnt[4];
+  const int tid = threadIdx.x;
+  if (tid < 4) s_cnt[tid] = 0;
+  const Ctl* c = d.ctl;
+  const StepInfo si = step_info(c, k);
+  const uint32_t par = si.par, step = si.step;
+  const Arr a = pick_set(d, c->set & 1u);
+  const float *X = pick(a.x, par), *Y = pick(a.y, par), *Z = pick(a.z, par);
+  float *XW = pick(a.x, par ^ 1u), *YW = pick(a.y, par ^ 1u), *ZW = pick(a.z, par ^ 1u);
+  const bool jit = d.jitter && d.jit_c != 0.0f;
+  const Buckets bk = step_buckets<false>(d, par, step);
+  const bool dead = read_err(c) != 0;
+  int s0, s1;
+  range_of<true>(d, w, s0, s1);
+  // the staged region: the brick's cells and one halo cell per side
+  const int nc = d.nc;
+  int bxc, byc, bx, ex, by, ey, bz, ez;
+  const int bzc = div_nb(d, div_nb(d, w, bxc), byc);
+  region_dim(d, bxc, bx, ex);
+  region_dim(d, byc, by, ey);
+  region_dim(d, bzc, bz, ez);
+  const int ncs = ex * ey * ez;
+  // a region that does not wrap around the box and spans less than half of
+  // it: the minimum image leaves every difference in it unchanged
+  const bool nowrap = d.nbricks > 1 && bx + ex <= nc && 2 * ex + 1 <= nc && by + ey <= nc &&
+                      2 * ey + 1 <= nc && bz + ez <= nc && 2 * ez + 1 <= nc;
+  uint32_t mine = 0;
+  int gc = 0;
+  if (tid < ncs) {
+    const int lz = div_small(tid, recip16((uint32_t)(ex * ey))), rem = tid - lz * ex * ey;
+    const int ly = div_small(rem, recip16((uint32_t)ex)), lx = rem - ly * ex;
+    int cx = bx + lx, cy = by + ly, cz = bz + lz;
+    cx -= cx >= nc ? nc : 0;
+    cy -= cy >= nc ? nc : 0;
+    cz -= cz >= nc ? nc : 0;
+    gc = (cz * nc + cy) * nc + cx;
+    mine = bk.cnt[gc];
+    mine = mine < (uint32_t)kCellCap ? mine : (uint32_t)kCellCap;
+  }
+  uint32_t total = 0;
+  const uint32_t off = block_scan_excl(mine, s_wave, total);
+  const bool staged = total <= (uint32_t)kStageRecs && bk.novf == 0;
+  if (tid < ncs) {
+    s_off[tid] = (uint16_t)off;
+    if (staged) {
+      const size_t r0 = (size_t)gc * kCellCap;
+      // the first two records loaded together, the rare rest one by one
+      float4 rv0 = make_float4(0.f, 0.f, 0.f, 0.f), rv1 = rv0;
+      int32_t sv0 = 0, sv1 = 0;
+      int4 av0 = make_int4(-1, -1, -1, -1), av1 = av0;
+      if (mine > 0u) {
+        rv0 = bk.rec[r0];
+        sv0 = bk.sa[r0];
+        if (d.adj_staged) av0 = d.radj[r0];
+      }
+      if (mine > 1u) {
+        rv1 = bk.rec[r0 + 1];
+        sv1 = bk.sa[r0 + 1];
+        if (d.adj_staged) av1 = d.radj[r0 + 1];
+      }
+      if (mine > 0u) {
+        s_rec[off] = rv0;
+        s_rsa[off] = sv0;
+        s_radj[off] = av0;
+      }
+      if (mine > 1u) {
+        s_rec[off + 1] = rv1;
+        s_rsa[off + 1] = sv1;
+        s_radj[off + 1] = av1;
+      }
+      for (uint32_t j = 2; j < mine; ++j) {
+        s_rec[off + j] = bk.rec[r0 + j];
+        s_rsa[off + j] = bk.sa[r0 + j];
+        if (d.adj_staged) s_radj[off + j] = d.radj[r0 + j];
+      }
+    }
+  }
+  if (tid == 0) s_off[ncs] = (uint16_t)total;
+  __syncthreads();
+  int t_elig = 0, in_rc = 0, excl = 0;
+  // one particle per thread and pass; the next pass's particle is loaded
+  // while this one is handled
+  float nx = 0.f, ny = 0.f, nz = 0.f;
+  int32_t nid = 0;
+  uint8_t nrole = kRoleNone;
+  if (s0 + tid < s1) {
+    nx = X[s0 + tid];
+    ny = Y[s0 + tid];
+    nz = Z[s0 + tid];
+    nid = a.id[s0 + tid];
+    nrole = a.role[s0 + tid];
+  }
+  for (int slot = s0 + tid; slot < s1 && !dead; slot += kThreads) {
+    float x = nx, y = ny, z = nz;
+    const uint32_t id = (uint32_t)nid;
+    const uint8_t role = nrole;
+    if (slot + kThreads < s1) {
+      nx = X[slot + kThreads];
+      ny = Y[slot + kThreads];
+      nz = Z[slot + kThreads];
+      nid = a.id[slot + kThreads];
+      nrole = a.role[slot + kThreads];
+    }
+    if (d.jitter) {  // the re-jitter, as in the random selection's sweep
+      if (jit) rejitter(d, step, id, x, y, z);
+      XW[slot] = x;
+      YW[slot] = y;
+      ZW[slot] = z;
+    }
+    if (role != kRoleT) continue;
+    t_elig++;
+    unsigned long long best = kEmpty;
+    // one candidate: the A's key lowered to (r2 bits, id_T), the T's own
+    // closest kept as (r2 bits, id_A)
+    auto visit = [&](float4 A, float r2, bool excluded) {
+      in_rc++;
+      if (excluded) {
+        excl++;
+        return;
+      }
+      const unsigned long long rb = (unsigned long long)__float_as_uint(r2) << 32;
+      const uint32_t ida = (uint32_t)__float_as_int(A.w);
+      atomicMin(&d.slotA[ida], rb | id);
+      const unsigned long long kt = rb | ida;
+      best = kt < best ? kt : best;
+    };
+    bool done = false;
+    if (staged) {
+      const int lx0 = local_lo(x, d.inv_w, bx, nc), ly0 = local_lo(y, d.inv_w, by, nc),
+                lz0 = local_lo(z, d.inv_w, bz, nc);
+      if ((uint32_t)lx0 < (uint32_t)(ex - 1) && (uint32_t)ly0 < (uint32_t)(ey - 1) &&
+          (uint32_t)lz0 < (uint32_t)(ez - 1)) {
+        const int l0 = (lz0 * ey + ly0) * ex + lx0;
+        auto scan = [&](auto dist) {
+          for (int run = 0; run < 4; ++run) {
+            const int lr = l0 + ((run & 1) ? ex : 0) + ((run & 2) ? ex * ey : 0);
+            const int r1 = (int)s_off[lr + 2];
+            for (int r = (int)s_off[lr]; r < r1; ++r) {
+              const float4 A = s_rec[r];
+              const float r2 = dist(A);
+              if (!(r2 < d.rc2)) continue;
+              bool ex_b = false;
+              if (d.rule.exclude) {
+                if (d.adj_staged) {
+                  const int4 q = s_radj[r];
+                  const int v = (int)id;
+                  ex_b = q.x == v || q.y == v || q.z == v || q.w == v;
+                } else {
+                  ex_b = row_has(a.adj + (size_t)s_rsa[r] * d.B, d.B, (int32_t)id);
+                }
+              }
+              visit(A, r2, ex_b);
+            }
+          }
+        };
+        if (nowrap)
+          scan([&](float4 A) { return dist2_plain(x, y, z, A); });
+        else
+          scan([&](float4 A) { return dist2(d, x, y, z, A); });
+        done = true;
+      }
+    }
+    if (!done) {
+      for_global_records(d, bk, x, y, z, [&](float4 A, int sa) {
+        const float r2 = dist2(d, x, y, z, A);
+        if (!(r2 < d.rc2)) return;
+        visit(A, r2, d.rule.exclude && row_has(a.adj + (size_t)sa * d.B, d.B, (int32_t)id));
+      });
+    }
+    if (best != kEmpty) d.tnear[id] = make_int2((int)(uint32_t)best, slot);
+  }
+  wave_add(&s_cnt[0], t_elig);
+  wave_add(&s_cnt[1], in_rc);
+  wave_add(&s_cnt[2], excl);
+  // clear the bucket counts of the next step's parity (as the other sweep)
+  for (int q = w * kThreads + tid; q < d.ncell; q += nwg * kThreads)
+    pick(d.cnt, par ^ 1u)[q] = 0u;
+  __syncthreads();
+  int32_t* out = pick(d.wgo, par) + w * kWgOut;
+  if (tid == 0) {
+    out[kOutTElig] = s_cnt[0];
+    out[kOutInRc] = s_cnt[1];
+    out[kOutDrawn] = 0;
+    out[kOutExcl] = s_cnt[2];
+    out[kOutRet] = 0;
+  }
+}
+
 // The A side of the nearest selection and the bonds: unit w (of nunits, the
 // sweep's workgroup count, whose staging windows and counters it fills)
 // takes the A records of a contiguous range of cells, unit 0 also the
@@ -2308,7 +2510,10 @@ __global__ __launch_bounds__(kThreads) void k_resolve(Dev d, int k) {
 }
 template <bool kBrick>
 __global__ __launch_bounds__(kThreads) void k_near_sweep(Dev d, int k) {
-  near_sweep_body<kBrick>(d, k, blockIdx.x, gridDim.x);
+  if (kBrick && d.bs <= kOneCellBrick)
+    near_sweep_staged_body(d, k, xcd_brick(blockIdx.x, gridDim.x), gridDim.x);
+  else
+    near_sweep_body<kBrick>(d, k, blockIdx.x, gridDim.x);
 }
 __global__ __launch_bounds__(kThreads) void k_near_resolve(Dev d, int k) {
   near_resolve_body(d, k, blockIdx.x, gridDim.x);

@@ -72,6 +72,33 @@ def test_run_equals_oracle(N, kind, p, steps):
     say("identical:", len(log), "bonds")
 
 
+@pytest.mark.parametrize("frac,B,sort_period", [(0.3, 4, 64), (0.3, 6, 64), (0.05, 6, 5)])
+def test_resident_a_rich_and_wide_rows(frac, B, sort_period):
+    """Resident runs on sorted storage (the staged sweep): uniformly random
+    positions with many A's (regions over the staging capacity and crowded
+    cells: the global-bucket paths) and adjacency rows wider than four (the
+    exclusion read from the particle arrays), against the oracle."""
+    from paper_1409_7498_amd import binding as Bn
+    N, L, seed, steps = 30000, 33.0, 90 + B, 24
+    cfg = random_cfg(N, L, "step", seed, frac=frac)
+    cfg["adj"] = np.full((N, B), -1, np.int32)
+    rule = _rule("step", 0.4)
+    say("nearest resident", "frac=%g B=%d sort=%d" % (frac, B, sort_period))
+    s = Bn.System(N, cfg["L"], B, rule, seed, log_cap=4 * N)
+    s.set_sort_period(sort_period)
+    s.load(cfg)
+    s.run(1, steps, 0.05)
+    out, log = s.read(), s.bonds()
+    s.close()
+    o = oracle_system(cfg)
+    code, olog, _ = oracle.run(o, oracle_rule(rule), seed, 1, steps, 0.05)
+    assert code == 0
+    assert len(olog) > 100
+    assert np.array_equal(log, olog), (len(log), len(olog))
+    for k in ("x", "y", "z", "state", "adj"):
+        assert np.array_equal(out[k], getattr(o, k)), k
+
+
 def test_sort_period_invariance():
     c = workload.Config("nearsort", 262144, workload.box_for(262144), "step", 0.05, 70,
                         workload.MASTER_SEED + 70)
