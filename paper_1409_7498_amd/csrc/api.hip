@@ -1337,7 +1337,8 @@ int pr_sys_kinetics(pr_sys* s, int32_t nstate, int64_t* pop, int64_t* pairs, int
                 kKinMaxBins);
   if (!pop || !pairs || (nbins > 0 && !hist)) return fail(PR_EINVAL, "NULL output");
   if (s->d.nrules > 1) return fail(PR_EINVAL, "kinetics counters take one rule");
-  const size_t nk = 2 * kKinMaxState + kKinMaxBins;
+  // kKinSlices slices of counters (the kernels spread their sums over them)
+  const size_t nk = (size_t)kKinStride * kKinSlices;
   if (!s->kin && ((e = s->arena.alloc(&s->kin, nk)) ||
                   (e = s->arena.alloc(&s->kin_e2, (size_t)kKinMaxBins + 1))))
     return e;
@@ -1353,8 +1354,8 @@ int pr_sys_kinetics(pr_sys* s, int32_t nstate, int64_t* pop, int64_t* pairs, int
                          st));
   HIP_TRY(launch_fill_u32((uint32_t*)s->kin, 2 * (long long)nk, 0u, st));
   HIP_TRY(launch_kinetics(s->d, nstate, nbins, s->kin_e2, kp, kq, kh, st));
-  std::vector<unsigned long long> h(nk);
-  HIP_TRY(hipMemcpyAsync(h.data(), s->kin, nk * sizeof(unsigned long long),
+  std::vector<unsigned long long> h(kKinStride);  // the first slice holds the sums
+  HIP_TRY(hipMemcpyAsync(h.data(), s->kin, (size_t)kKinStride * sizeof(unsigned long long),
                          hipMemcpyDeviceToHost, st));
   if ((e = sync_ctl(s))) return e;
   if (s->hctl->err) return fail(s->hctl->err, "device error during the run");

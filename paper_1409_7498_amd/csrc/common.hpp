@@ -44,6 +44,8 @@ constexpr int32_t kMaxParticles = 1 << 30;  // byte offsets of 4-byte fields fit
 constexpr int kMaxRules = 4;        // concurrent rules of one system
 constexpr int kKinMaxState = 64;    // kinetics counters: states per call
 constexpr int kKinMaxBins = 256;    // kinetics counters: distance bins per call
+constexpr int kKinStride = 2 * kKinMaxState + kKinMaxBins;  // one slice of kinetics counters
+constexpr int kKinSlices = 64;      // slices the kinetics workgroups spread their sums over
 
 enum WgOut { kOutTElig = 0, kOutInRc, kOutDrawn, kOutExcl, kOutRet, kOutProp, kOutBonds, kOutLost,
              kOutAElig };

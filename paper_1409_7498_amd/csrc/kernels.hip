@@ -1572,14 +1572,156 @@ __device__ __forceinline__ void near_sweep_body(const Dev& d, int k, int w, int 
   }
 }
 
-// near_sweep_body on sorted storage with the brick's A records staged in LDS
-// (brick edges up to kOneCellBrick: one region cell per thread), as the
-// random selection's sweep stages them: each T scans the four runs of its
-// 2x2x2 block in LDS and tests the exclusion against the staged adjacency
-// row.  A T whose block leaves the staged region, and every T of a brick
-// whose region holds more than kStageRecs records or of a step with bucket
-// overflow, scans the global buckets as near_sweep_body does.  The same
-// pairs get the same keys, so the outcome is that of near_sweep_body.
+// The brick of sweep workgroup g.  Workgroups are dispatched to the eight
+// XCDs in turn (g mod 8), each XCD with an L2 of its own; XCD x takes the
+// contiguous run of bricks x * q + min(x, r) .. (q or q + 1 of them, q =
+// nbricks / 8, r = nbricks mod 8), a slab of neighbouring bricks, so that
+// the A records a brick's neighbours stage again are in the same L2.
+__device__ __forceinline__ int xcd_brick(int g, int nbricks) {
+  constexpr int kXcd = 8;
+  const int q = nbricks / kXcd, r = nbricks - q * kXcd;
+  const int x = g % kXcd, i = g / kXcd;
+  return x * q + min(x, r) + i;
+}
+
+// The A records of a brick's region staged in LDS (sorted storage, brick
+// edges up to kOneCellBrick: one region cell per thread), as the random
+// selection's sweep stages them, for the kernels that visit every in-range
+// (A, T) pair of a T: the nearest selection's sweep and the kinetics
+// counters.  A T whose 2x2x2 block leaves the staged region, and every T of
+// a brick whose region holds more than kStageRecs records or of a step with
+// bucket overflow, scans the global buckets instead; either way a T visits
+// the same pairs.
+struct StagedRegion {
+  float4* rec;    // records (x, y, z, id_A)
+  int4* radj;     // the A's adjacency rows (rows of width <= kAdjStage)
+  int32_t* rsa;   // the A's slots
+  uint16_t* off;  // first record of each region cell (one more entry: the total)
+  int bx, ex, by, ey, bz, ez;
+  bool staged, nowrap;
+};
+
+__device__ __forceinline__ void stage_region(const Dev& d, const Buckets& bk, int w,
+                                             StagedRegion& g, uint32_t* s_wave) {
+  const int tid = threadIdx.x, nc = d.nc;
+  int bxc, byc;
+  const int bzc = div_nb(d, div_nb(d, w, bxc), byc);
+  region_dim(d, bxc, g.bx, g.ex);
+  region_dim(d, byc, g.by, g.ey);
+  region_dim(d, bzc, g.bz, g.ez);
+  const int ex = g.ex, ey = g.ey, ncs = ex * ey * g.ez;
+  // a region that does not wrap around the box and spans less than half of
+  // it: the minimum image leaves every difference in it unchanged
+  g.nowrap = d.nbricks > 1 && g.bx + ex <= nc && 2 * ex + 1 <= nc && g.by + ey <= nc &&
+             2 * ey + 1 <= nc && g.bz + g.ez <= nc && 2 * g.ez + 1 <= nc;
+  uint32_t mine = 0;
+  int gc = 0;
+  if (tid < ncs) {
+    const int lz = div_small(tid, recip16((uint32_t)(ex * ey))), rem = tid - lz * ex * ey;
+    const int ly = div_small(rem, recip16((uint32_t)ex)), lx = rem - ly * ex;
+    int cx = g.bx + lx, cy = g.by + ly, cz = g.bz + lz;
+    cx -= cx >= nc ? nc : 0;
+    cy -= cy >= nc ? nc : 0;
+    cz -= cz >= nc ? nc : 0;
+    gc = (cz * nc + cy) * nc + cx;
+    mine = bk.cnt[gc];
+    mine = mine < (uint32_t)kCellCap ? mine : (uint32_t)kCellCap;
+  }
+  uint32_t total = 0;
+  const uint32_t off = block_scan_excl(mine, s_wave, total);
+  g.staged = total <= (uint32_t)kStageRecs && bk.novf == 0;
+  if (tid < ncs) {
+    g.off[tid] = (uint16_t)off;
+    if (g.staged) {
+      const size_t r0 = (size_t)gc * kCellCap;
+      // the first two records loaded together, the rare rest one by one
+      float4 rv0 = make_float4(0.f, 0.f, 0.f, 0.f), rv1 = rv0;
+      int32_t sv0 = 0, sv1 = 0;
+      int4 av0 = make_int4(-1, -1, -1, -1), av1 = av0;
+      if (mine > 0u) {
+        rv0 = bk.rec[r0];
+        sv0 = bk.sa[r0];
+        if (d.adj_staged) av0 = d.radj[r0];
+      }
+      if (mine > 1u) {
+        rv1 = bk.rec[r0 + 1];
+        sv1 = bk.sa[r0 + 1];
+        if (d.adj_staged) av1 = d.radj[r0 + 1];
+      }
+      if (mine > 0u) {
+        g.rec[off] = rv0;
+        g.rsa[off] = sv0;
+        g.radj[off] = av0;
+      }
+      if (mine > 1u) {
+        g.rec[off + 1] = rv1;
+        g.rsa[off + 1] = sv1;
+        g.radj[off + 1] = av1;
+      }
+      for (uint32_t j = 2; j < mine; ++j) {
+        g.rec[off + j] = bk.rec[r0 + j];
+        g.rsa[off + j] = bk.sa[r0 + j];
+        if (d.adj_staged) g.radj[off + j] = d.radj[r0 + j];
+      }
+    }
+  }
+  if (tid == 0) g.off[ncs] = (uint16_t)total;
+  __syncthreads();
+}
+
+// Every in-range pair of the T (id_T) at (x, y, z): f(record, r2, excluded,
+// slot_A, staged index or -1), the exclusion tested on the A's staged row (or its row in the
+// particle arrays) when the rule excludes bonded pairs.  The staged records
+// when the T's block lies in the staged region, else the global buckets.
+template <typename F>
+__device__ __forceinline__ void visit_pairs(const Dev& d, const Arr& a, const Buckets& bk,
+                                            const StagedRegion& g, float x, float y, float z,
+                                            uint32_t id, F f) {
+  const int nc = d.nc;
+  if (g.staged) {
+    const int lx0 = local_lo(x, d.inv_w, g.bx, nc), ly0 = local_lo(y, d.inv_w, g.by, nc),
+              lz0 = local_lo(z, d.inv_w, g.bz, nc);
+    if ((uint32_t)lx0 < (uint32_t)(g.ex - 1) && (uint32_t)ly0 < (uint32_t)(g.ey - 1) &&
+        (uint32_t)lz0 < (uint32_t)(g.ez - 1)) {
+      const int l0 = (lz0 * g.ey + ly0) * g.ex + lx0;
+      auto scan = [&](auto dist) {
+        for (int run = 0; run < 4; ++run) {
+          const int lr = l0 + ((run & 1) ? g.ex : 0) + ((run & 2) ? g.ex * g.ey : 0);
+          const int r1 = (int)g.off[lr + 2];
+          for (int r = (int)g.off[lr]; r < r1; ++r) {
+            const float4 A = g.rec[r];
+            const float r2 = dist(A);
+            if (!(r2 < d.rc2)) continue;
+            bool ex_b = false;
+            if (d.rule.exclude) {
+              if (d.adj_staged) {
+                const int4 q = g.radj[r];
+                const int v = (int)id;
+                ex_b = q.x == v || q.y == v || q.z == v || q.w == v;
+              } else {
+                ex_b = row_has(a.adj + (size_t)g.rsa[r] * d.B, d.B, (int32_t)id);
+              }
+            }
+            f(A, r2, ex_b, g.rsa[r], r);
+          }
+        }
+      };
+      if (g.nowrap)
+        scan([&](float4 A) { return dist2_plain(x, y, z, A); });
+      else
+        scan([&](float4 A) { return dist2(d, x, y, z, A); });
+      return;
+    }
+  }
+  for_global_records(d, bk, x, y, z, [&](float4 A, int sa) {
+    const float r2 = dist2(d, x, y, z, A);
+    if (!(r2 < d.rc2)) return;
+    f(A, r2, d.rule.exclude && row_has(a.adj + (size_t)sa * d.B, d.B, (int32_t)id), sa, -1);
+  });
+}
+
+// near_sweep_body on sorted storage with the region staged (StagedRegion):
+// the same pairs get the same keys, so the outcome is that of near_sweep_body.
 __device__ __forceinline__ void near_sweep_staged_body(const Dev& d, int k, int w, int nwg) {
   __shared__ float4 s_rec[kStageRecs];
   __shared__ int4 s_radj[kStageRecs];
@@ -1600,71 +1742,12 @@ __device__ __forceinline__ void near_sweep_staged_body(const Dev& d, int k, int 
   const bool dead = read_err(c) != 0;
   int s0, s1;
   range_of<true>(d, w, s0, s1);
-  // the staged region: the brick's cells and one halo cell per side
-  const int nc = d.nc;
-  int bxc, byc, bx, ex, by, ey, bz, ez;
-  const int bzc = div_nb(d, div_nb(d, w, bxc), byc);
-  region_dim(d, bxc, bx, ex);
-  region_dim(d, byc, by, ey);
-  region_dim(d, bzc, bz, ez);
-  const int ncs = ex * ey * ez;
-  // a region that does not wrap around the box and spans less than half of
-  // it: the minimum image leaves every difference in it unchanged
-  const bool nowrap = d.nbricks > 1 && bx + ex <= nc && 2 * ex + 1 <= nc && by + ey <= nc &&
-                      2 * ey + 1 <= nc && bz + ez <= nc && 2 * ez + 1 <= nc;
-  uint32_t mine = 0;
-  int gc = 0;
-  if (tid < ncs) {
-    const int lz = div_small(tid, recip16((uint32_t)(ex * ey))), rem = tid - lz * ex * ey;
-    const int ly = div_small(rem, recip16((uint32_t)ex)), lx = rem - ly * ex;
-    int cx = bx + lx, cy = by + ly, cz = bz + lz;
-    cx -= cx >= nc ? nc : 0;
-    cy -= cy >= nc ? nc : 0;
-    cz -= cz >= nc ? nc : 0;
-    gc = (cz * nc + cy) * nc + cx;
-    mine = bk.cnt[gc];
-    mine = mine < (uint32_t)kCellCap ? mine : (uint32_t)kCellCap;
-  }
-  uint32_t total = 0;
-  const uint32_t off = block_scan_excl(mine, s_wave, total);
-  const bool staged = total <= (uint32_t)kStageRecs && bk.novf == 0;
-  if (tid < ncs) {
-    s_off[tid] = (uint16_t)off;
-    if (staged) {
-      const size_t r0 = (size_t)gc * kCellCap;
-      // the first two records loaded together, the rare rest one by one
-      float4 rv0 = make_float4(0.f, 0.f, 0.f, 0.f), rv1 = rv0;
-      int32_t sv0 = 0, sv1 = 0;
-      int4 av0 = make_int4(-1, -1, -1, -1), av1 = av0;
-      if (mine > 0u) {
-        rv0 = bk.rec[r0];
-        sv0 = bk.sa[r0];
-        if (d.adj_staged) av0 = d.radj[r0];
-      }
-      if (mine > 1u) {
-        rv1 = bk.rec[r0 + 1];
-        sv1 = bk.sa[r0 + 1];
-        if (d.adj_staged) av1 = d.radj[r0 + 1];
-      }
-      if (mine > 0u) {
-        s_rec[off] = rv0;
-        s_rsa[off] = sv0;
-        s_radj[off] = av0;
-      }
-      if (mine > 1u) {
-        s_rec[off + 1] = rv1;
-        s_rsa[off + 1] = sv1;
-        s_radj[off + 1] = av1;
-      }
-      for (uint32_t j = 2; j < mine; ++j) {
-        s_rec[off + j] = bk.rec[r0 + j];
-        s_rsa[off + j] = bk.sa[r0 + j];
-        if (d.adj_staged) s_radj[off + j] = d.radj[r0 + j];
-      }
-    }
-  }
-  if (tid == 0) s_off[ncs] = (uint16_t)total;
-  __syncthreads();
+  StagedRegion g;
+  g.rec = s_rec;
+  g.radj = s_radj;
+  g.rsa = s_rsa;
+  g.off = s_off;
+  stage_region(d, bk, w, g, s_wave);
   int t_elig = 0, in_rc = 0, excl = 0;
   // one particle per thread and pass; the next pass's particle is loaded
   // while this one is handled
@@ -1697,10 +1780,10 @@ __device__ __forceinline__ void near_sweep_staged_body(const Dev& d, int k, int 
     }
     if (role != kRoleT) continue;
     t_elig++;
+    // each candidate lowers the A's key to (r2 bits, id_T); the T keeps its
+    // own closest as (r2 bits, id_A)
     unsigned long long best = kEmpty;
-    // one candidate: the A's key lowered to (r2 bits, id_T), the T's own
-    // closest kept as (r2 bits, id_A)
-    auto visit = [&](float4 A, float r2, bool excluded) {
+    visit_pairs(d, a, bk, g, x, y, z, id, [&](float4 A, float r2, bool excluded, int, int) {
       in_rc++;
       if (excluded) {
         excl++;
@@ -1711,50 +1794,7 @@ __device__ __forceinline__ void near_sweep_staged_body(const Dev& d, int k, int 
       atomicMin(&d.slotA[ida], rb | id);
       const unsigned long long kt = rb | ida;
       best = kt < best ? kt : best;
-    };
-    bool done = false;
-    if (staged) {
-      const int lx0 = local_lo(x, d.inv_w, bx, nc), ly0 = local_lo(y, d.inv_w, by, nc),
-                lz0 = local_lo(z, d.inv_w, bz, nc);
-      if ((uint32_t)lx0 < (uint32_t)(ex - 1) && (uint32_t)ly0 < (uint32_t)(ey - 1) &&
-          (uint32_t)lz0 < (uint32_t)(ez - 1)) {
-        const int l0 = (lz0 * ey + ly0) * ex + lx0;
-        auto scan = [&](auto dist) {
-          for (int run = 0; run < 4; ++run) {
-            const int lr = l0 + ((run & 1) ? ex : 0) + ((run & 2) ? ex * ey : 0);
-            const int r1 = (int)s_off[lr + 2];
-            for (int r = (int)s_off[lr]; r < r1; ++r) {
-              const float4 A = s_rec[r];
-              const float r2 = dist(A);
-              if (!(r2 < d.rc2)) continue;
-              bool ex_b = false;
-              if (d.rule.exclude) {
-                if (d.adj_staged) {
-                  const int4 q = s_radj[r];
-                  const int v = (int)id;
-                  ex_b = q.x == v || q.y == v || q.z == v || q.w == v;
-                } else {
-                  ex_b = row_has(a.adj + (size_t)s_rsa[r] * d.B, d.B, (int32_t)id);
-                }
-              }
-              visit(A, r2, ex_b);
-            }
-          }
-        };
-        if (nowrap)
-          scan([&](float4 A) { return dist2_plain(x, y, z, A); });
-        else
-          scan([&](float4 A) { return dist2(d, x, y, z, A); });
-        done = true;
-      }
-    }
-    if (!done) {
-      for_global_records(d, bk, x, y, z, [&](float4 A, int sa) {
-        const float r2 = dist2(d, x, y, z, A);
-        if (!(r2 < d.rc2)) return;
-        visit(A, r2, d.rule.exclude && row_has(a.adj + (size_t)sa * d.B, d.B, (int32_t)id));
-      });
-    }
+    });
     if (best != kEmpty) d.tnear[id] = make_int2((int)(uint32_t)best, slot);
   }
   wave_add(&s_cnt[0], t_elig);
@@ -2191,6 +2231,17 @@ __global__ __launch_bounds__(kThreads) void k_gather_v(Dev d, float* ox, float* 
 // found once, from its T, as in the sweep.  Counts go to LDS, then one
 // global atomic per workgroup and counter.
 // ---------------------------------------------------------------------------
+// The distance bin of an in-range pair: the b with e2[b] <= r2 < e2[b + 1]
+// (the last bin ends at the cutoff), found from a guess by the uniform bin
+// width in r and moved by the exact edges, so that no pair walks every bin.
+__device__ __forceinline__ int kin_bin(float r2, const float* e2, int nbins, float scale) {
+  int b = (int)(__fsqrt_rn(r2) * scale);
+  b = b < 0 ? 0 : (b > nbins - 1 ? nbins - 1 : b);
+  while (b > 0 && r2 < e2[b]) --b;
+  while (b + 1 < nbins && !(r2 < e2[b + 1])) ++b;
+  return b;
+}
+
 __global__ __launch_bounds__(kThreads) void k_kin_pop(Dev d, int nstate,
                                                       unsigned long long* __restrict__ pop) {
   __shared__ uint32_t s_pop[kKinMaxState];
@@ -2202,8 +2253,9 @@ __global__ __launch_bounds__(kThreads) void k_kin_pop(Dev d, int nstate,
     if (a.typ[i] == d.rule.type_a && st >= 0 && st < nstate) atomicAdd(&s_pop[st], 1u);
   }
   __syncthreads();
+  const size_t so = (size_t)(blockIdx.x % kKinSlices) * kKinStride;
   for (int q = threadIdx.x; q < nstate; q += blockDim.x)
-    if (s_pop[q]) atomicAdd(&pop[q], (unsigned long long)s_pop[q]);
+    if (s_pop[q]) atomicAdd(&pop[so + q], (unsigned long long)s_pop[q]);
 }
 
 __global__ __launch_bounds__(kThreads) void k_kin_pairs(Dev d, int nstate, int nbins,
@@ -2216,6 +2268,7 @@ __global__ __launch_bounds__(kThreads) void k_kin_pairs(Dev d, int nstate, int n
   for (int q = threadIdx.x; q < nbins; q += blockDim.x) s_hist[q] = 0u;
   for (int q = threadIdx.x; q <= nbins; q += blockDim.x) s_e2[q] = e2[q];
   __syncthreads();
+  const float scale = nbins > 0 ? (float)nbins / __fsqrt_rn(d.rc2) : 0.0f;
   const Ctl* c = d.ctl;
   const uint32_t par = c->par0;
   const Arr a = pick_set(d, c->set & 1u);
@@ -2233,16 +2286,87 @@ __global__ __launch_bounds__(kThreads) void k_kin_pairs(Dev d, int nstate, int n
       if (d.rule.exclude && row_has(a.adj + (size_t)sa * d.B, d.B, id)) return;
       const int32_t st = a.st[sa];
       if (st >= 0 && st < nstate) atomicAdd(&s_pairs[st], 1u);
-      int b = 0;
-      while (b + 1 < nbins && !(r2 < s_e2[b + 1])) ++b;
-      if (nbins > 0) atomicAdd(&s_hist[b], 1u);
+      if (nbins > 0) atomicAdd(&s_hist[kin_bin(r2, s_e2, nbins, scale)], 1u);
     });
   }
   __syncthreads();
+  // the workgroup's sums go to its slice (kKinSlices of them, summed on the
+  // host): few workgroups share an address
+  const size_t so = (size_t)(blockIdx.x % kKinSlices) * kKinStride;
   for (int q = threadIdx.x; q < nstate; q += blockDim.x)
-    if (s_pairs[q]) atomicAdd(&pairs[q], (unsigned long long)s_pairs[q]);
+    if (s_pairs[q]) atomicAdd(&pairs[so + q], (unsigned long long)s_pairs[q]);
   for (int q = threadIdx.x; q < nbins; q += blockDim.x)
-    if (s_hist[q]) atomicAdd(&hist[q], (unsigned long long)s_hist[q]);
+    if (s_hist[q]) atomicAdd(&hist[so + q], (unsigned long long)s_hist[q]);
+}
+
+// k_kin_pairs on sorted storage (brick edges up to kOneCellBrick), one
+// workgroup per brick with its region's A records staged (StagedRegion): the
+// same pairs, the same counts.
+__global__ __launch_bounds__(kThreads) void k_kin_pairs_staged(Dev d, int nstate, int nbins,
+                                                               const float* __restrict__ e2,
+                                                               unsigned long long* __restrict__ pairs,
+                                                               unsigned long long* __restrict__ hist) {
+  __shared__ float4 s_rec[kStageRecs];
+  __shared__ int4 s_radj[kStageRecs];
+  __shared__ int32_t s_rsa[kStageRecs];
+  __shared__ uint16_t s_off[kStageCells1 + 1];
+  __shared__ uint32_t s_wave[kThreads / 64 + 1];
+  __shared__ int32_t s_ast[kStageRecs];
+  __shared__ uint32_t s_pairs[kKinMaxState], s_hist[kKinMaxBins];
+  __shared__ float s_e2[kKinMaxBins + 1];
+  for (int q = threadIdx.x; q < nstate; q += blockDim.x) s_pairs[q] = 0u;
+  for (int q = threadIdx.x; q < nbins; q += blockDim.x) s_hist[q] = 0u;
+  for (int q = threadIdx.x; q <= nbins; q += blockDim.x) s_e2[q] = e2[q];
+  const float scale = nbins > 0 ? (float)nbins / __fsqrt_rn(d.rc2) : 0.0f;
+  const Ctl* c = d.ctl;
+  const uint32_t par = c->par0;
+  const Arr a = pick_set(d, c->set & 1u);
+  const float *X = pick(a.x, par), *Y = pick(a.y, par), *Z = pick(a.z, par);
+  const Buckets bk{pick(d.cnt, par), d.rec, d.rsa, pick(d.ovf, par), pick(d.ovf_sa, par),
+                   c->ovf_n[par]};
+  const int w = xcd_brick(blockIdx.x, gridDim.x);
+  int s0, s1;
+  range_of<true>(d, w, s0, s1);
+  StagedRegion g;
+  g.rec = s_rec;
+  g.radj = s_radj;
+  g.rsa = s_rsa;
+  g.off = s_off;
+  stage_region(d, bk, w, g, s_wave);  // ends with a barrier (the tables above too)
+  // the staged A's states, so that no pair waits for a global load
+  if (g.staged) {
+    const int nrec = (int)s_off[g.ex * g.ey * g.ez];
+    for (int r = threadIdx.x; r < nrec; r += kThreads) s_ast[r] = a.st[s_rsa[r]];
+    __syncthreads();
+  }
+  for (int slot = s0 + threadIdx.x; slot < s1; slot += kThreads) {
+    if (a.role[slot] != kRoleT) continue;
+    const float x = X[slot], y = Y[slot], z = Z[slot];
+    visit_pairs(d, a, bk, g, x, y, z, (uint32_t)a.id[slot],
+                [&](float4, float r2, bool excluded, int sa, int r) {
+                  if (excluded) return;
+                  const int32_t st = r >= 0 ? s_ast[r] : a.st[sa];
+                  if (st >= 0 && st < nstate) atomicAdd(&s_pairs[st], 1u);
+                  if (nbins > 0) atomicAdd(&s_hist[kin_bin(r2, s_e2, nbins, scale)], 1u);
+                });
+  }
+  __syncthreads();
+  // the workgroup's sums go to its slice (kKinSlices of them, summed on the
+  // host): few workgroups share an address
+  const size_t so = (size_t)(blockIdx.x % kKinSlices) * kKinStride;
+  for (int q = threadIdx.x; q < nstate; q += blockDim.x)
+    if (s_pairs[q]) atomicAdd(&pairs[so + q], (unsigned long long)s_pairs[q]);
+  for (int q = threadIdx.x; q < nbins; q += blockDim.x)
+    if (s_hist[q]) atomicAdd(&hist[so + q], (unsigned long long)s_hist[q]);
+}
+
+// Sums the kKinSlices slices of the kinetics counters into the first.
+__global__ void k_kin_sum(unsigned long long* kin) {
+  for (int q = threadIdx.x; q < kKinStride; q += blockDim.x) {
+    unsigned long long v = 0;
+    for (int j = 1; j < kKinSlices; ++j) v += kin[(size_t)j * kKinStride + q];
+    kin[q] += v;
+  }
 }
 
 // Leaves the A grid of the current parity as a step expects to find it
@@ -2472,17 +2596,6 @@ __global__ __launch_bounds__(kThreads) void k_prep(Dev d, int k) { prep_body(d, 
 __global__ __launch_bounds__(kThreads) void k_close(Dev d, int k) { close_body(d, k, blockIdx.x); }
 __global__ void k_advance(Ctl* c, int K) {
   if (threadIdx.x == 0 && blockIdx.x == 0) advance_ctl(c, K);
-}
-// The brick of sweep workgroup g.  Workgroups are dispatched to the eight
-// XCDs in turn (g mod 8), each XCD with an L2 of its own; XCD x takes the
-// contiguous run of bricks x * q + min(x, r) .. (q or q + 1 of them, q =
-// nbricks / 8, r = nbricks mod 8), a slab of neighbouring bricks, so that
-// the A records a brick's neighbours stage again are in the same L2.
-__device__ __forceinline__ int xcd_brick(int g, int nbricks) {
-  constexpr int kXcd = 8;
-  const int q = nbricks / kXcd, r = nbricks - q * kXcd;
-  const int x = g % kXcd, i = g / kXcd;
-  return x * q + min(x, r) + i;
 }
 
 // With fused binning there is no prep kernel: the closing groups of step
@@ -2985,8 +3098,12 @@ hipError_t launch_kinetics(const Dev& d, int nstate, int nbins, const float* e2,
   dn.jit_c = 0.0f;
   dn.fuse = 0;  // binned into the plain buckets here, whatever the steps use
   k_prep<<<d.nwg_prep, kThreads, 0, s>>>(dn, 0);
-  k_kin_pairs<<<g, kThreads, 0, s>>>(dn, nstate, nbins, e2, pairs, hist);
+  if (d.sorted && d.bs <= kOneCellBrick)
+    k_kin_pairs_staged<<<d.nwg_sweep, kThreads, 0, s>>>(dn, nstate, nbins, e2, pairs, hist);
+  else
+    k_kin_pairs<<<g, kThreads, 0, s>>>(dn, nstate, nbins, e2, pairs, hist);
   k_kin_reset<<<std::min(blocks_for(d.ncell, kThreads), 1024), kThreads, 0, s>>>(dn);
+  k_kin_sum<<<1, kThreads, 0, s>>>(pop);  // pop is the first slice's start
   return hipGetLastError();
 }
 
