@@ -1673,7 +1673,7 @@ __device__ __forceinline__ void stage_region(const Dev& d, const Buckets& bk, in
 // slot_A, staged index or -1), the exclusion tested on the A's staged row (or its row in the
 // particle arrays) when the rule excludes bonded pairs.  The staged records
 // when the T's block lies in the staged region, else the global buckets.
-template <typename F>
+template <bool kExcl = true, typename F>
 __device__ __forceinline__ void visit_pairs(const Dev& d, const Arr& a, const Buckets& bk,
                                             const StagedRegion& g, float x, float y, float z,
                                             uint32_t id, F f) {
@@ -1693,7 +1693,7 @@ __device__ __forceinline__ void visit_pairs(const Dev& d, const Arr& a, const Bu
             const float r2 = dist(A);
             if (!(r2 < d.rc2)) continue;
             bool ex_b = false;
-            if (d.rule.exclude) {
+            if (kExcl && d.rule.exclude) {
               if (d.adj_staged) {
                 const int4 q = g.radj[r];
                 const int v = (int)id;
@@ -1716,7 +1716,8 @@ __device__ __forceinline__ void visit_pairs(const Dev& d, const Arr& a, const Bu
   for_global_records(d, bk, x, y, z, [&](float4 A, int sa) {
     const float r2 = dist2(d, x, y, z, A);
     if (!(r2 < d.rc2)) return;
-    f(A, r2, d.rule.exclude && row_has(a.adj + (size_t)sa * d.B, d.B, (int32_t)id), sa, -1);
+    f(A, r2, kExcl && d.rule.exclude && row_has(a.adj + (size_t)sa * d.B, d.B, (int32_t)id), sa,
+      -1);
   });
 }
 
@@ -1917,14 +1918,23 @@ __device__ __forceinline__ bool key_less(unsigned long long k1, int r1, unsigned
 template <typename F>
 __device__ __forceinline__ void multi_candidates(const Dev& d, const Arr& a, uint32_t step,
                                                  uint32_t rt, int sa, int ida, uint32_t idj,
-                                                 float r2, F f) {
-  const uint32_t both = rt & ((uint32_t)a.role[sa] >> 4);
+                                                 float r2, F f, int arole = -1,
+                                                 const int4* arow = nullptr) {
+  const uint32_t both = rt & ((uint32_t)(arole >= 0 ? arole : a.role[sa]) >> 4);
   if (!both) return;
   int bonded = -1;
 #pragma unroll
   for (int r = 0; r < kMaxRules; ++r) {
     if (r >= d.nrules || !((both >> r) & 1u) || !(r2 < d.mr[r].rc2)) continue;
-    if (bonded < 0) bonded = row_has(a.adj + (size_t)sa * d.B, d.B, (int32_t)idj) ? 1 : 0;
+    if (bonded < 0) {
+      if (arow) {
+        const int4 q = *arow;
+        const int v = (int)idj;
+        bonded = q.x == v || q.y == v || q.z == v || q.w == v;
+      } else {
+        bonded = row_has(a.adj + (size_t)sa * d.B, d.B, (int32_t)idj) ? 1 : 0;
+      }
+    }
     const W4 w = philox(step, (uint32_t)ida, idj, d.mr[r].tag, d.seed);
     f(r, w, d.mr[r].r.exclude && bonded > 0, w.w0 < d.mr[r].thresh);
   }
@@ -1979,6 +1989,92 @@ __device__ __forceinline__ void multi_sweep_body(const Dev& d, int k, int w, int
         any = true;
         atomicMin(&d.slotA[ida], ((unsigned long long)wd.w1 << 32) | id);
       });
+    });
+    if (any) d.tflag[slot] = 1;
+  }
+  wave_add(&s_cnt[0], t_elig);
+  wave_add(&s_cnt[1], in_rc);
+  wave_add(&s_cnt[2], drawn);
+  wave_add(&s_cnt[3], excl);
+  for (int q = w * kThreads + tid; q < d.ncell; q += nwg * kThreads)
+    pick(d.cnt, par ^ 1u)[q] = 0u;
+  __syncthreads();
+  int32_t* out = pick(d.wgo, par) + w * kWgOut;
+  if (tid == 0) {
+    out[kOutTElig] = s_cnt[0];
+    out[kOutInRc] = s_cnt[1];
+    out[kOutDrawn] = s_cnt[2];
+    out[kOutExcl] = s_cnt[3];
+    out[kOutRet] = 0;
+  }
+}
+
+// multi_sweep_body on sorted storage with the region staged (StagedRegion,
+// with the A's role bytes): the same candidates, draws and keys.
+__device__ __forceinline__ void multi_sweep_staged_body(const Dev& d, int k, int w, int nwg) {
+  __shared__ float4 s_rec[kStageRecs];
+  __shared__ int4 s_radj[kStageRecs];
+  __shared__ int32_t s_rsa[kStageRecs];
+  __shared__ uint8_t s_arole[kStageRecs];
+  __shared__ uint16_t s_off[kStageCells1 + 1];
+  __shared__ uint32_t s_wave[kThreads / 64 + 1];
+  __shared__ int s_cnt[4];
+  const int tid = threadIdx.x;
+  if (tid < 4) s_cnt[tid] = 0;
+  const Ctl* c = d.ctl;
+  const StepInfo si = step_info(c, k);
+  const uint32_t par = si.par, step = si.step;
+  const Arr a = pick_set(d, c->set & 1u);
+  const float *X = pick(a.x, par), *Y = pick(a.y, par), *Z = pick(a.z, par);
+  float *XW = pick(a.x, par ^ 1u), *YW = pick(a.y, par ^ 1u), *ZW = pick(a.z, par ^ 1u);
+  const bool jit = d.jitter && d.jit_c != 0.0f;
+  const Buckets bk = step_buckets<false>(d, par, step);
+  const bool dead = read_err(c) != 0;
+  int s0, s1;
+  range_of<true>(d, w, s0, s1);
+  StagedRegion g;
+  g.rec = s_rec;
+  g.radj = s_radj;
+  g.rsa = s_rsa;
+  g.off = s_off;
+  stage_region(d, bk, w, g, s_wave);
+  // the staged A's role bytes (the roles of the step: nothing changes them
+  // before the resolve)
+  if (g.staged) {
+    const int nrec = (int)s_off[g.ex * g.ey * g.ez];
+    for (int r = tid; r < nrec; r += kThreads) s_arole[r] = a.role[s_rsa[r]];
+    __syncthreads();
+  }
+  int t_elig = 0, in_rc = 0, drawn = 0, excl = 0;
+  for (int slot = s0 + tid; slot < s1 && !dead; slot += kThreads) {
+    float x = X[slot], y = Y[slot], z = Z[slot];
+    const uint32_t id = (uint32_t)a.id[slot];
+    const uint32_t rt = a.role[slot] & kMaskT;
+    if (d.jitter) {
+      if (jit) rejitter(d, step, id, x, y, z);
+      XW[slot] = x;
+      YW[slot] = y;
+      ZW[slot] = z;
+    }
+    d.wfa[slot] = 0;
+    d.wft[slot] = 0;
+    if (!rt) continue;
+    t_elig++;
+    bool any = false;
+    visit_pairs<false>(d, a, bk, g, x, y, z, id, [&](float4 A, float r2, bool, int sa, int r) {
+      const int ida = __float_as_int(A.w);
+      if ((uint32_t)ida == id) return;
+      multi_candidates(d, a, step, rt, sa, ida, id, r2, [&](int, W4 wd, bool ex, bool acc) {
+        in_rc++;
+        if (!acc) return;
+        drawn++;
+        if (ex) {
+          excl++;
+          return;
+        }
+        any = true;
+        atomicMin(&d.slotA[ida], ((unsigned long long)wd.w1 << 32) | id);
+      }, r >= 0 ? (int)s_arole[r] : -1, r >= 0 && d.adj_staged ? &s_radj[r] : nullptr);
     });
     if (any) d.tflag[slot] = 1;
   }
@@ -2633,7 +2729,10 @@ __global__ __launch_bounds__(kThreads) void k_near_resolve(Dev d, int k) {
 }
 template <bool kBrick>
 __global__ __launch_bounds__(kThreads) void k_multi_sweep(Dev d, int k) {
-  multi_sweep_body<kBrick>(d, k, blockIdx.x, gridDim.x);
+  if (kBrick && d.bs <= kOneCellBrick)
+    multi_sweep_staged_body(d, k, xcd_brick(blockIdx.x, gridDim.x), gridDim.x);
+  else
+    multi_sweep_body<kBrick>(d, k, blockIdx.x, gridDim.x);
 }
 template <bool kBrick>
 __global__ __launch_bounds__(kThreads) void k_multi_resolve(Dev d, int k) {
