@@ -2807,7 +2807,10 @@ __global__ __launch_bounds__(kThreads) void k_near_sweep_b(const Dev* __restrict
   const int4 m = uniform_map(map);
   const Dev& d = ds[m.x];
   if (k >= d.k_limit || d.rule.policy != PR_POLICY_NEAREST) return;
-  near_sweep_body<true>(d, k, m.y, m.z);
+  if (d.bs <= kOneCellBrick)
+    near_sweep_staged_body(d, k, m.y, m.z);
+  else
+    near_sweep_body<true>(d, k, m.y, m.z);
 }
 __global__ __launch_bounds__(kThreads) void k_near_resolve_b(const Dev* __restrict__ ds,
                                                              const int4* __restrict__ map, int k) {
