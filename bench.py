@@ -33,6 +33,11 @@ since, and for any other workload or brick edge).  ``cpu_baseline`` times
 the CPU oracle on one full step of the same workload and reports the FP64
 recheck of that step's cutoff decisions.
 
+``--config c1|c3`` time the other single-system workloads, ``--config c4`` the
+batched ensemble and ``--config c5`` the served stream (bench_batch, bench_serve);
+``--policy nearest`` the LAMMPS selection on the default workload and ``--row
+f2|f3|f4`` the other rows beyond the paper's step (bench_row).
+
 Prints ONE JSON line.  ``--gpus N`` with N > 1 exits: this build runs on one GPU.
 """
 import argparse
