@@ -1587,8 +1587,9 @@ __device__ __forceinline__ int xcd_brick(int g, int nbricks) {
 // The A records of a brick's region staged in LDS (sorted storage, brick
 // edges up to kOneCellBrick: one region cell per thread), as the random
 // selection's sweep stages them, for the kernels that visit every in-range
-// (A, T) pair of a T: the nearest selection's sweep and the kinetics
-// counters.  A T whose 2x2x2 block leaves the staged region, and every T of
+// (A, T) pair of a T: the sweeps of the nearest selection and of several
+// rules, and the kinetics counters.  A T whose 2x2x2 block leaves the staged
+// region, and every T of
 // a brick whose region holds more than kStageRecs records or of a step with
 // bucket overflow, scans the global buckets instead; either way a T visits
 // the same pairs.
